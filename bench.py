@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the hydrodynamics step on one MI355X.
+
+Workload: the 3D spherical (phi, r, theta) adiabatic disk, 1536 x 512 x 128
+active zones, FP64, orbital advection on, time step computed on the device
+every step (the whole hot path: boundary fill, bulk velocity, CFL reduction,
+source step, transport with integer shift and PPA residual, velocities).
+Inputs are seeded and synthetic and already resident in HBM when the timed
+region starts.
+
+Prints one JSON line: cell-updates/s, ms/step, the roofline of the dominant
+kernel (algorithmic bytes per launch over its average duration from HIP
+events recorded on the launch stream during the timed steps) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per full hydro step + HBM GB/s; FP32/batched vs FP64 at error"
+HBM_PEAK_GBS = 8000.0
+NGH = 3
+
+
+def words_per_unit(p):
+    """Algorithmic FP64 words moved per zone by each kernel (each input read
+    once, each output written once), and the zones one launch processes."""
+    d3 = p["nz"] > 1
+    adi = p["eos"] == "adi"
+    nT = 5 + (2 if d3 else 0) + (1 if adi else 0)
+    nvel = 3 if d3 else 2
+    act = p["nx"] * p["ny"] * p["nz"]
+    ghost_all = p["nx"] * (p["ny"] + 2 * NGH) * ((p["nz"] + 2 * NGH) if d3 else 1)
+    y_rows = p["nx"] * p["ny"] * ((p["nz"] + 4) if d3 else 1)
+    return {
+        # name: (words per zone, zones per launch)
+        "ring_v0": (1, act),
+        "cfl": (2 + nvel, act),                       # rho, cs|e, velocities
+        "source_7a": (3 + nvel + nvel, act),          # rho, cs|e, pot, v -> v'
+        "source_7b": (1 + nvel + nvel + (2 if adi else 0), act),
+        "source_7c": ((nvel + 2) if adi else 0, act),
+        "momenta_12a": (1 + nvel + (1 if adi else 0) + nT, ghost_all),
+        "sweep_y": (2 * nT + 1, y_rows),
+        "sweep_z": ((2 * nT + 1) if d3 else 0, act),
+        "ring_x": (2 * nT + 1, act),
+        "velocities_12d": (nT + nvel + 1 + (1 if adi else 0), act),
+    }
+
+
+def compulsory_bytes(p):
+    """Read every state and static field once, write the state once, plus the
+    time-step pass the global dt forces (velocities and sound speed again)."""
+    d3 = p["nz"] > 1
+    adi = p["eos"] == "adi"
+    nvel = 3 if d3 else 2
+    state = 1 + nvel + (1 if adi else 0)
+    static = 1 + (0 if adi else 1)  # pot, cs
+    cfl = nvel + 2
+    return 8 * (state + static + state + cfl)
+
+
+def sample_problem(prob, ny_s, nz_s):
+    """Rings [j0, j0+ny_s) x [k0, k0+nz_s) of a problem, whole X, with the
+    real neighbouring zones as caller-fixed ghosts on cut sides."""
+    from paper_1602_02359_amd import workloads as W
+    p = prob.params
+    sub = dict(p)
+    bc = list(p["bc"])
+    ja, jb = NGH, NGH + ny_s
+    if jb != NGH + p["ny"]:
+        bc[1] = "fixed"
+    sub["ny"] = ny_s
+    sub["ymin"] = p["ymin"][ja - NGH:jb + NGH + 1].copy()
+    if p["nz"] > 1:
+        mid = NGH + p["nz"] // 2 - nz_s // 2
+        ka, kb = mid, mid + nz_s
+        bc[2] = "fixed"
+        bc[3] = "fixed"
+        sub["nz"] = nz_s
+        sub["zmin"] = p["zmin"][ka - NGH:kb + NGH + 1].copy()
+        ks = slice(ka - NGH, kb + NGH)
+    else:
+        ks = slice(0, 1)
+    sub["bc"] = tuple(bc)
+    js = slice(ja - NGH, jb + NGH)
+    f = {k: (None if v is None else v[ks, js, :].copy()) for k, v in prob.fields.items()}
+    return W.Problem(prob.name + "_sample", sub, f, 1)
+
+
+def cpu_baseline(prob, target_s=12.0):
+    from oracle import oracle as O
+    p = prob.params
+    nz_s = 8 if p["nz"] > 1 else 1
+    ny_s = 16
+    s = sample_problem(prob, ny_s, nz_s)
+    f = s.copy_fields()
+    t0 = time.perf_counter()
+    O.step(s.params, f)
+    t_cal = time.perf_counter() - t0
+    rate = s.active_cells / t_cal
+    # scale the sample to about target_s of work, within the workload
+    want = rate * target_s
+    if p["nz"] > 1:
+        nz_s = max(4, min(p["nz"], int(want / (p["nx"] * p["ny"]))))
+        ny_s = p["ny"] if nz_s * p["nx"] * p["ny"] <= want else max(4, int(want / (p["nx"] * nz_s)))
+    else:
+        ny_s = max(4, min(p["ny"], int(want / p["nx"])))
+    s = sample_problem(prob, ny_s, nz_s)
+    f = s.copy_fields()
+    t0 = time.perf_counter()
+    O.step(s.params, f)
+    el = time.perf_counter() - t0
+    return {
+        "value": s.active_cells / el,
+        "unit": "cell-updates/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": "one full step (CFL included) of %d x %d x %d zones of the same workload (rings cut "
+                  "from the mesh, neighbours as fixed ghosts), %.1f s" % (p["nx"], s.params["ny"], s.params["nz"], el),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="sph3d", choices=["sph3d", "cyl3d_planet", "disk2d"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
+              "(the multi-GPU slab decomposition is a design, not a measured path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    from paper_1602_02359_amd import workloads as W
+
+    prob = W.make(args.config)
+    p = prob.params
+    print("workload %s %dx%dx%d, building state" % (args.config, p["nx"], p["ny"], p["nz"]), file=sys.stderr,
+          flush=True)
+    solver = F.Solver(p)
+    solver.upload(prob.fields)
+    for _ in range(args.warmup):
+        solver.fargo_step(0.0)
+    solver.fargo_check()
+    torch.cuda.synchronize()
+    solver.fargo_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.fargo_step(0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    timings = solver.fargo_timings()
+    solver.fargo_profile_enable(False)
+    solver.fargo_check()
+    dt_last = solver.fargo_get_dt()
+    cells = prob.active_cells
+    value = cells * args.steps / el
+    ms = 1e3 * el / args.steps
+    print("timed %d steps: %.3f ms/step, %.3e cell-updates/s, dt %.6g" % (args.steps, ms, value, dt_last),
+          file=sys.stderr, flush=True)
+
+    wpu = words_per_unit(p)
+    kern = {}
+    for name, (cnt, tot) in timings.items():
+        avg = tot / cnt
+        entry = {"launches": cnt, "avg_ms": avg}
+        if name in wpu and wpu[name][0] > 0:
+            b = 8.0 * wpu[name][0] * wpu[name][1]
+            entry["alg_bytes"] = b
+            entry["GBs"] = b / (avg * 1e-3) / 1e9
+        kern[name] = entry
+        print("  %-16s %6d launches  %9.4f ms avg  %s" % (name, cnt, avg,
+              ("%.0f GB/s" % entry["GBs"]) if "GBs" in entry else ""), file=sys.stderr)
+    dom = max((k for k in kern if "alg_bytes" in kern[k]), key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    achieved = kern[dom]["GBs"]
+    step_alg = sum(8.0 * w * n for (w, n) in wpu.values())
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "alg_bytes_per_launch": kern[dom]["alg_bytes"], "avg_launch_ms": kern[dom]["avg_ms"]}
+    del solver
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(prob)
+        print("  oracle %.3e cell-updates/s on %d threads" % (cpu["value"], cpu["cores"]), file=sys.stderr)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %s %dx%dx%d (phi, r, %s), %s, orbital advection %s, FP64, dt on device" % (
+                args.config, p["geometry"], p["nx"], p["ny"], p["nz"], "theta" if p["geometry"] == "sph" else "z",
+                "adiabatic" if p["eos"] == "adi" else "isothermal", "on" if p["fargo"] else "off"),
+            "active_cells": cells,
+            "parallelism": "single GPU",
+        },
+        "hbm": {
+            "step_alg_bytes_per_cell": step_alg / cells,
+            "step_alg_GBs": value * step_alg / cells / 1e9,
+            "compulsory_bytes_per_cell": compulsory_bytes(p),
+            "effective_GBs": value * compulsory_bytes(p) / 1e9,
+        },
+        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kern.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

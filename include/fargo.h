@@ -1,0 +1,200 @@
+/*
+ * fargo.h - C ABI of libfargo, an MI355X (gfx950) implementation of the
+ * hydrodynamics step of the FARGO3D method (Benitez-Llambay & Masset 2016,
+ * ApJS 223, 11; arXiv:1602.02359).
+ *
+ * One call of fargo_step performs one full update of the paper's flow chart
+ * (Sect. 3, Fig. "flowchart") restricted to hydrodynamics with a static
+ * potential: boundary fill (box 2), bulk azimuthal velocity (box 3), pressure
+ * (box 4), time step (box 6, Eq. cfl2 and Eq. 38), source step (boxes 7a-7c,
+ * Sect. 3.3), boundary fill (box 9) and transport (box 12, Sect. 3.4-3.5:
+ * left/right momenta, van Leer upwind sweeps in Y, Z and X, orbital advection
+ * by integer circular shift and PPA fractional residual, velocities from
+ * momenta).
+ *
+ * Mesh and storage (Sect. 2.2-2.3, Tab. "corresp", Sect. 4.1):
+ *   X = azimuth (periodic, uniform, no ghosts), Y = radius, Z = z or colatitude.
+ *   Every field is a device array [nz_g][ny_g][pitch] of double, X fastest,
+ *   with ny_g = ny + 6, nz_g = nz + 6 (3D) or 1 (2D, nz == 1) and pitch from
+ *   fargo_layout (a multiple of 64 elements, >= nx; columns nx..pitch-1 are
+ *   padding, never read or written).  Three ghost layers in Y and Z.
+ *   vx[k][j][i] sits on the lower X face of zone i, vy[k][j][i] on the face at
+ *   ymin[j], vz[k][j][i] on the face at zmin[k]; rho, e, cs and pot are zone
+ *   centred.
+ *
+ * Conventions.
+ *   - Every call returns an int status (FARGO_OK = 0, negative on error); no
+ *     exception crosses the ABI and nothing aborts.
+ *   - All device work is enqueued on the caller's HIP stream (`stream`, a
+ *     hipStream_t passed as void*; NULL means the default stream) and is
+ *     stream-ordered.  fargo_step never synchronises the host.
+ *   - Ownership: the caller owns the state arrays, the optional workspace and
+ *     the stream; the library never frees caller memory.  The library owns the
+ *     context and, when no workspace is given, one device allocation made in
+ *     fargo_init and released in fargo_destroy.
+ *   - A context is not thread safe and its calls must not overlap in time on
+ *     different streams; separate contexts are independent.
+ *   - Asynchronous problems found on the device (non-finite or non-positive
+ *     density, bad time step) set an error word in the context; it is reported
+ *     by the next fargo_check, and by fargo_cfl_dt when it reads dt back.
+ */
+#ifndef FARGO_H
+#define FARGO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FARGO_ABI_VERSION 1
+#define FARGO_NGH 3
+
+/* status codes */
+#define FARGO_OK 0
+#define FARGO_EINVAL (-1)      /* invalid argument or parameter */
+#define FARGO_ENOMEM (-2)      /* device or host allocation failed, or workspace too small */
+#define FARGO_EHIP (-3)        /* a HIP runtime call failed */
+#define FARGO_ENONFINITE (-4)  /* non-finite or non-positive state seen on the device */
+#define FARGO_ECFL (-5)        /* the time step came out non-positive or non-finite */
+#define FARGO_EUNSUPPORTED (-6)
+
+/* geometry (Tab. "corresp") */
+#define FARGO_CARTESIAN 0
+#define FARGO_CYLINDRICAL 1
+#define FARGO_SPHERICAL 2
+/* equation of state: Eq. eos1 (static c_s field) or Eq. eos2 */
+#define FARGO_ISOTHERMAL 0
+#define FARGO_ADIABATIC 1
+/* boundary kinds, per side (ymin, ymax, zmin, zmax).  PERIODIC must be set on
+   both sides of a direction (Cartesian Y, Cartesian or cylindrical Z);
+   REFLECT mirrors scalars and tangential velocities and makes the normal
+   velocity antisymmetric with a zero boundary face; OUTFLOW copies the edge
+   zone and the first interior face; FIXED leaves the caller's ghost values
+   (and the boundary face) untouched. */
+#define FARGO_BC_PERIODIC 0
+#define FARGO_BC_REFLECT 1
+#define FARGO_BC_OUTFLOW 2
+#define FARGO_BC_FIXED 3
+/* bulk azimuthal velocity of each ring (box 3): Eq. 37 or the azimuthal mean */
+#define FARGO_V0_MINMAX 0
+#define FARGO_V0_MEAN 1
+/* storage precision of the evolved state */
+#define FARGO_FP64 0
+
+typedef struct {
+  int32_t abi_version;     /* FARGO_ABI_VERSION */
+  int32_t geometry;        /* FARGO_CARTESIAN / _CYLINDRICAL / _SPHERICAL */
+  int32_t nx, ny, nz;      /* active zones; nx >= 1, ny >= 3, nz == 1 (2D) or >= 3;
+                              spherical needs nz >= 3 */
+  double xmin, xmax;       /* azimuthal (X) extent; dx = (xmax - xmin)/nx */
+  const double *ymin;      /* host, ny + 7 increasing face coordinates (ghosts included);
+                              copied at fargo_init */
+  const double *zmin;      /* host, nz + 7 face coordinates (3D) or 2 (2D); copied */
+  int32_t eos;             /* FARGO_ISOTHERMAL or FARGO_ADIABATIC */
+  double gamma;            /* ratio of specific heats (adiabatic), > 1 */
+  double omega;            /* constant rotation rate of the frame */
+  double courant;          /* Courant number C of Eq. cfl2 (paper: 0.44) */
+  double cvnr;             /* artificial-viscosity constant: q = cvnr^2 rho dv^2 for dv < 0 */
+  double shear_c0;         /* C0 of Eq. 38; <= 0 switches the shear limit off */
+  int32_t fargo;           /* 1: orbital advection (Sect. 3.5.1), 0: plain transport */
+  int32_t v0_mode;         /* FARGO_V0_MINMAX or FARGO_V0_MEAN */
+  int32_t bc[4];           /* boundary kind of the ymin, ymax, zmin, zmax sides */
+  int32_t precision;       /* FARGO_FP64 */
+} fargo_params;
+
+/* Device pointers to the state, each laid out as described above.  rho, vx,
+   vy are always required; vz in 3D only (NULL in 2D); e (volumic internal
+   energy) for FARGO_ADIABATIC, cs (isothermal sound speed, static) for
+   FARGO_ISOTHERMAL; pot (static potential, ghosts included) always. */
+typedef struct {
+  double *rho, *vx, *vy, *vz, *e;
+  const double *cs, *pot;
+} fargo_state;
+
+typedef struct fargo_ctx fargo_ctx;
+
+/* Version of this ABI (FARGO_ABI_VERSION). */
+int fargo_abi_version(void);
+
+/* Static description of a status code; never NULL. */
+const char *fargo_strerror(int status);
+
+/* Array layout for the given parameters: pitch (elements per X row), ny_g,
+   nz_g.  Any output may be NULL.  Validates the parameters (FARGO_EINVAL). */
+int fargo_layout(const fargo_params *params, int32_t *pitch, int32_t *ny_g, int32_t *nz_g);
+
+/* Bytes of device workspace fargo_init needs for these parameters. */
+int fargo_workspace_bytes(const fargo_params *params, size_t *bytes);
+
+/* Create a context on the current HIP device.  `workspace` is a device buffer
+   of at least fargo_workspace_bytes bytes, owned by the caller and kept alive
+   until fargo_destroy; NULL makes the library allocate it (hipMalloc).
+   Computes the geometric coefficients of Appendix A (Tab. "geom", Eqs. 70-71)
+   on the host in FP64 and uploads them (synchronously).  *out is set on
+   success only. */
+int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, fargo_ctx **out);
+
+/* Release the context (synchronises the device first).  NULL is a no-op. */
+void fargo_destroy(fargo_ctx *ctx);
+
+/* Boxes 2, 3, 4 and 6: fill the state's ghost layers (box 2; only ghosts and
+   boundary faces are written), compute each ring's bulk velocity and the time
+   step of Eq. cfl2 (items 1-3, with the residual velocity and the shear limit
+   of Eq. 38 under orbital advection), minimised over active zones.  The step
+   stays on the device for the next fargo_step(dt <= 0); if dt_host is not
+   NULL the call waits for the stream and copies it back, returning
+   FARGO_ENONFINITE / FARGO_ECFL if the device flagged a problem. */
+int fargo_cfl_dt(fargo_ctx *ctx, fargo_state *state, double *dt_host, void *stream);
+
+/* One full update of the state, in place.  dt > 0 imposes the time step; dt
+   <= 0 computes it on the device (box 6) without any host synchronisation.
+   Ghost layers are refilled at boxes 2 and 9; after the call they hold the
+   values of box 9 (the next call refills them). */
+int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream);
+
+/* Eq. 32 on one field: every active ring (j, k) is circularly permuted in
+   place, Q_i <- Q_{(i - N) mod nx}, with N = nshift[(k - k0)*ny + (j - j0)]
+   read from a device array of ny*nz int32 (k0 = 3 in 3D, 0 in 2D).  Ghost
+   rows are not touched.  Bit-exact (a pure permutation). */
+int fargo_shift(fargo_ctx *ctx, double *field, const int32_t *nshift, void *stream);
+
+/* Box 3 and the split of Eq. 29 for a given dt, on active rings: v0 (Eq. 37
+   or mean), N = nearest integer to D = (v0 dt)/dX with ties away from zero,
+   xi = D - N.  Outputs are device arrays of ny*nz elements indexed as in
+   fargo_shift.  dX is the azimuthal zone length at the v_phi face centre
+   (dx, r dphi or r sin(theta) dphi). */
+int fargo_ring_split(fargo_ctx *ctx, const double *vx, double dt, double *v0, int32_t *nshift, double *xi,
+                     void *stream);
+
+/* Conserved sums over active zones (waits for the stream): out[0] = mass
+   sum(rho V); out[1..3] = X, Y, Z momenta sum(rho m(<v>) V) with <v> the mean
+   of the two faces (Eq. 19) and m the factor of Tab. "momenta" (X: r(v + r
+   Omega) or R(v + R Omega); Z: r v_theta in spherical geometry); out[4] =
+   sum(e V) (0 if isothermal).  Double-double accumulation in a fixed order
+   (deterministic).  Upper faces in periodic directions are read through the
+   wrap.  `out` is host memory. */
+int fargo_conserved_sums(fargo_ctx *ctx, const fargo_state *state, double out[5], void *stream);
+
+/* Copy the time step last computed or imposed on the device into *dt_host
+   (waits for the stream). */
+int fargo_get_dt(fargo_ctx *ctx, double *dt_host, void *stream);
+
+/* Wait for the device and report (then clear) the asynchronous error word. */
+int fargo_check(fargo_ctx *ctx);
+
+/* Per-kernel timing with HIP events on the caller's stream.  While enabled,
+   every kernel launch of the library is bracketed by events.
+   fargo_profile_enable waits for the device and resets the accumulators;
+   fargo_timings (which waits for the stream) returns, for up to `cap` kernel
+   kinds, their names (static strings), launch counts and total milliseconds
+   since the last fargo_profile_enable, and the number of kinds returned. */
+int fargo_profile_enable(fargo_ctx *ctx, int on);
+int fargo_timings(fargo_ctx *ctx, const char **names, int64_t *counts, double *total_ms, int cap, int *n_out,
+                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FARGO_H */

@@ -34,6 +34,7 @@
  * centres at arithmetic midpoints; azimuthal length X = r sin(theta) dphi.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1136,3 +1137,6 @@ void orc_ppa_ring(int n, int nq, double *rho, double **Q, double xi, double dX, 
 }
 
 void orc_split_shift(double v0, double dt, double dX, int32_t *N, double *xi) { split_shift(v0, dt, dX, N, xi); }
+
+/* Threads the oracle's parallel loops use. */
+int orc_num_threads(void) { return omp_get_max_threads(); }

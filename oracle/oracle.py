@@ -70,6 +70,7 @@ def lib():
         L.orc_ppa_ring.restype = None
         L.orc_split_shift.argtypes = [C.c_double, C.c_double, C.c_double, ip, dp]
         L.orc_split_shift.restype = None
+        L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -197,3 +198,7 @@ def split_shift(v0: float, dt: float, dX: float):
     xi = C.c_double(0.0)
     lib().orc_split_shift(float(v0), float(dt), float(dX), C.byref(N), C.byref(xi))
     return N.value, xi.value
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()

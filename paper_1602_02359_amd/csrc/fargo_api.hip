@@ -1,0 +1,577 @@
+// Host side of the C ABI declared in include/fargo.h: parameter checks, the
+// FP64 geometric tables of Appendix A, workspace layout and the sequence of
+// kernels of one full update (Sect. 3, Fig. "flowchart").
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fargo_internal.h"
+
+using namespace fargo;
+
+namespace fargo {
+
+const char *kernel_names[K_COUNT] = {
+    "set_dt", "reset", "bc_faces", "bc_ghosts", "ring_v0", "cfl", "dt_final", "split",
+    "source_7a", "source_7b", "source_7c", "momenta_12a", "sweep_y", "sweep_z", "ring_x", "velocities_12d",
+    "shift", "sums", "sums_final"};
+
+struct Prof {
+  bool on = false;
+  struct Pending {
+    int kid;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t cur_a = nullptr;
+  double total_ms[K_COUNT] = {};
+  int64_t count[K_COUNT] = {};
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~Prof() {
+    for (auto &p : pending) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+void prof_begin(Launch &L, int kid) {
+  (void)kid;
+  if (!L.prof || !L.prof->on) return;
+  L.prof->cur_a = L.prof->get();
+  if (L.prof->cur_a) (void)hipEventRecord(L.prof->cur_a, L.s);
+}
+
+void prof_end(Launch &L, int kid) {
+  if (!L.prof || !L.prof->on || !L.prof->cur_a) return;
+  hipEvent_t b = L.prof->get();
+  if (!b) return;
+  (void)hipEventRecord(b, L.s);
+  L.prof->pending.push_back({kid, L.prof->cur_a, b});
+  L.prof->cur_a = nullptr;
+}
+
+} // namespace fargo
+
+struct fargo_ctx {
+  int dev = 0;
+  fargo_params p{};
+  Mesh m{};
+  std::vector<double> ymin, zmin;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  // carved workspace
+  DevWords w{};
+  double *v0 = nullptr, *xi = nullptr;
+  int32_t *nshift = nullptr;
+  double *partial = nullptr, *sums_out = nullptr;
+  double *v1[3] = {nullptr, nullptr, nullptr};
+  TSet TA{}, TB{};
+  Prof prof;
+};
+
+namespace {
+
+int check_params(const fargo_params *p) {
+  if (!p) return FARGO_EINVAL;
+  if (p->abi_version != FARGO_ABI_VERSION) return FARGO_EINVAL;
+  if (p->nx < 1 || p->ny < 3) return FARGO_EINVAL;
+  if (p->nz != 1 && p->nz < 3) return FARGO_EINVAL;
+  if (p->geometry < 0 || p->geometry > 2) return FARGO_EINVAL;
+  if (p->geometry == FARGO_SPHERICAL && p->nz < 3) return FARGO_EINVAL;
+  if (!p->ymin || !p->zmin || !(p->xmax > p->xmin)) return FARGO_EINVAL;
+  if (p->eos != FARGO_ISOTHERMAL && p->eos != FARGO_ADIABATIC) return FARGO_EINVAL;
+  if (p->eos == FARGO_ADIABATIC && !(p->gamma > 1.0)) return FARGO_EINVAL;
+  if (p->v0_mode != FARGO_V0_MINMAX && p->v0_mode != FARGO_V0_MEAN) return FARGO_EINVAL;
+  if (!(p->courant > 0.0) || !(p->cvnr >= 0.0)) return FARGO_EINVAL;
+  for (int s = 0; s < 4; s++)
+    if (p->bc[s] < 0 || p->bc[s] > 3) return FARGO_EINVAL;
+  if ((p->bc[0] == FARGO_BC_PERIODIC) != (p->bc[1] == FARGO_BC_PERIODIC)) return FARGO_EINVAL;
+  if (p->nz > 1 && (p->bc[2] == FARGO_BC_PERIODIC) != (p->bc[3] == FARGO_BC_PERIODIC)) return FARGO_EINVAL;
+  if (p->geometry != FARGO_CARTESIAN && p->bc[0] == FARGO_BC_PERIODIC) return FARGO_EINVAL;
+  if (p->geometry == FARGO_SPHERICAL && p->bc[2] == FARGO_BC_PERIODIC) return FARGO_EINVAL;
+  if (p->precision != FARGO_FP64) return FARGO_EUNSUPPORTED;
+  if (p->nx > 2048) return FARGO_EUNSUPPORTED; // ring kernel keeps a ring per workgroup in 64 KB of LDS
+  int nyg = p->ny + 2 * NGH, nzg = p->nz > 1 ? p->nz + 2 * NGH : 1;
+  for (int j = 0; j < nyg; j++)
+    if (!(p->ymin[j + 1] > p->ymin[j]) || !std::isfinite(p->ymin[j + 1])) return FARGO_EINVAL;
+  for (int k = 0; k < nzg; k++)
+    if (!(p->zmin[k + 1] > p->zmin[k]) || !std::isfinite(p->zmin[k + 1])) return FARGO_EINVAL;
+  if (p->geometry != FARGO_CARTESIAN && !(p->ymin[0] > 0.0)) return FARGO_EINVAL;
+  if (p->geometry == FARGO_SPHERICAL && !(p->zmin[0] > 0.0 && p->zmin[nzg] < M_PI)) return FARGO_EINVAL;
+  return FARGO_OK;
+}
+
+void dims(const fargo_params *p, int &pitch, int &nyg, int &nzg) {
+  pitch = (p->nx + 63) / 64 * 64;
+  nyg = p->ny + 2 * NGH;
+  nzg = p->nz > 1 ? p->nz + 2 * NGH : 1;
+}
+
+int ntransported(const fargo_params *p) { return 5 + (p->nz > 1 ? 2 : 0) + (p->eos == FARGO_ADIABATIC ? 1 : 0); }
+
+inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+// host tables, in the order of GeoTables
+struct HostGeo {
+  std::vector<double> ymin, ymed, zmin, zmed, sinz, Ly, hy, sxj, syj, szj, invVj, sxk, syk, szk, dxlen;
+};
+
+#pragma clang fp contract(off)
+void make_geo(const fargo_params *p, HostGeo &G) {
+  int pitch, nyg, nzg;
+  dims(p, pitch, nyg, nzg);
+  double dx = (p->xmax - p->xmin) / p->nx;
+  G.ymin.assign(p->ymin, p->ymin + nyg + 1);
+  G.zmin.assign(p->zmin, p->zmin + nzg + 1);
+  G.ymed.resize(nyg);
+  G.zmed.resize(nzg);
+  G.sinz.resize(nzg);
+  G.Ly.resize(nyg);
+  G.hy.resize(nyg);
+  for (int j = 0; j < nyg; j++) {
+    G.ymed[j] = 0.5 * (G.ymin[j] + G.ymin[j + 1]);
+    G.Ly[j] = G.ymin[j + 1] - G.ymin[j];
+  }
+  for (int j = 0; j < nyg; j++) G.hy[j] = j > 0 ? G.ymed[j] - G.ymed[j - 1] : G.Ly[0];
+  for (int k = 0; k < nzg; k++) {
+    G.zmed[k] = 0.5 * (G.zmin[k] + G.zmin[k + 1]);
+    G.sinz[k] = std::sin(G.zmed[k]);
+  }
+  G.sxj.resize(nyg);
+  G.szj.resize(nyg);
+  G.invVj.resize(nyg);
+  G.syj.resize(nyg + 1);
+  for (int j = 0; j <= nyg; j++) {
+    double a = G.ymin[j];
+    if (j < nyg) {
+      double b = G.ymin[j + 1];
+      if (p->geometry == FARGO_CARTESIAN) {
+        G.sxj[j] = b - a;
+        G.szj[j] = dx * (b - a);
+        G.invVj[j] = 1.0 / (b - a);
+      } else if (p->geometry == FARGO_CYLINDRICAL) {
+        G.sxj[j] = b - a;
+        G.szj[j] = 0.5 * dx * (b * b - a * a);
+        G.invVj[j] = 2.0 / ((b * b - a * a) * dx);
+      } else {
+        G.sxj[j] = 0.5 * (b * b - a * a);
+        G.szj[j] = 0.5 * dx * (b * b - a * a);
+        G.invVj[j] = 3.0 / ((b * b * b - a * a * a) * dx);
+      }
+    }
+    G.syj[j] = p->geometry == FARGO_CARTESIAN ? 1.0 : (p->geometry == FARGO_CYLINDRICAL ? a * dx : a * a * dx);
+  }
+  G.sxk.resize(nzg);
+  G.syk.resize(nzg);
+  G.szk.resize(nzg + 1);
+  for (int k = 0; k <= nzg; k++) {
+    double a = G.zmin[k];
+    if (k < nzg) {
+      double b = G.zmin[k + 1];
+      G.sxk[k] = b - a;
+      if (p->geometry == FARGO_CARTESIAN) G.syk[k] = dx * (b - a);
+      else if (p->geometry == FARGO_CYLINDRICAL) G.syk[k] = b - a;
+      else G.syk[k] = std::cos(a) - std::cos(b);
+    }
+    G.szk[k] = p->geometry == FARGO_SPHERICAL ? std::sin(a) : 1.0;
+  }
+  G.dxlen.resize((size_t)nzg * nyg);
+  for (int k = 0; k < nzg; k++)
+    for (int j = 0; j < nyg; j++) {
+      double v;
+      if (p->geometry == FARGO_CARTESIAN) v = dx;
+      else if (p->geometry == FARGO_CYLINDRICAL) v = G.ymed[j] * dx;
+      else v = G.ymed[j] * G.sinz[k] * dx;
+      G.dxlen[(size_t)k * nyg + j] = v;
+    }
+}
+
+size_t geo_doubles(int nyg, int nzg) {
+  return (size_t)(nyg + 1) + nyg + (nzg + 1) + nzg + nzg + nyg + nyg + nyg + (nyg + 1) + nyg + nyg + nzg + nzg +
+         (nzg + 1) + (size_t)nzg * nyg;
+}
+
+struct Layout {
+  size_t geo, words, v0, xi, nshift, partial, sums, v1, T, total;
+};
+
+Layout layout(const fargo_params *p) {
+  int pitch, nyg, nzg;
+  dims(p, pitch, nyg, nzg);
+  size_t nc = (size_t)pitch * nyg * nzg;
+  size_t nring = (size_t)p->ny * p->nz;
+  Layout L{};
+  size_t o = 0;
+  L.geo = o;
+  o += al(geo_doubles(nyg, nzg) * 8);
+  L.words = o;
+  o += 256;
+  L.v0 = o;
+  o += al(nring * 8);
+  L.xi = o;
+  o += al(nring * 8);
+  L.nshift = o;
+  o += al(nring * 4);
+  L.partial = o;
+  o += al(nring * 10 * 8);
+  L.sums = o;
+  o += 256;
+  L.v1 = o;
+  o += al(nc * 8) * (p->nz > 1 ? 3 : 2);
+  L.T = o;
+  o += al(nc * 8) * 2 * ntransported(p);
+  L.total = o;
+  return L;
+}
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? FARGO_OK : FARGO_EHIP; }
+
+// Pointers the configuration does not use are dropped, so that no kernel
+// touches a field (or a transport buffer) that does not exist.
+StateP state_of(const fargo_ctx *c, const fargo_state *s) {
+  StateP S;
+  S.rho = s->rho;
+  S.vx = s->vx;
+  S.vy = s->vy;
+  S.vz = c->m.d3 ? s->vz : nullptr;
+  S.e = c->p.eos == FARGO_ADIABATIC ? s->e : nullptr;
+  S.cs = c->p.eos == FARGO_ISOTHERMAL ? s->cs : nullptr;
+  S.pot = s->pot;
+  return S;
+}
+
+int check_state(const fargo_ctx *c, const fargo_state *s) {
+  if (!s || !s->rho || !s->vx || !s->vy || !s->pot) return FARGO_EINVAL;
+  if (c->m.d3 && !s->vz) return FARGO_EINVAL;
+  if (c->p.eos == FARGO_ISOTHERMAL && !s->cs) return FARGO_EINVAL;
+  if (c->p.eos == FARGO_ADIABATIC && !s->e) return FARGO_EINVAL;
+  return FARGO_OK;
+}
+
+// boxes 2, 3, 4, 6 (+ split when orbital advection is on)
+void timestep_phase(fargo_ctx *c, Launch &L, const StateP &S, double dt) {
+  const Mesh &m = c->m;
+  launch_reset(L, c->w);
+  if (dt > 0.0) launch_set_dt(L, c->w, dt);
+  launch_bc(L, m, S.rho, S.e, S.vx, S.vy, S.vz);
+  launch_ring_v0(L, m, S.vx, c->v0);
+  launch_cfl(L, m, S, c->v0, c->w);
+  launch_dt_final(L, m, c->w, dt > 0.0);
+}
+
+} // namespace
+
+extern "C" {
+
+int fargo_abi_version(void) { return FARGO_ABI_VERSION; }
+
+const char *fargo_strerror(int status) {
+  switch (status) {
+  case FARGO_OK: return "ok";
+  case FARGO_EINVAL: return "invalid argument";
+  case FARGO_ENOMEM: return "out of memory or workspace too small";
+  case FARGO_EHIP: return "HIP runtime error";
+  case FARGO_ENONFINITE: return "non-finite or non-positive state";
+  case FARGO_ECFL: return "invalid time step";
+  case FARGO_EUNSUPPORTED: return "unsupported configuration";
+  default: return "unknown status";
+  }
+}
+
+int fargo_layout(const fargo_params *params, int32_t *pitch, int32_t *ny_g, int32_t *nz_g) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  int a, b, c;
+  dims(params, a, b, c);
+  if (pitch) *pitch = a;
+  if (ny_g) *ny_g = b;
+  if (nz_g) *nz_g = c;
+  return FARGO_OK;
+}
+
+int fargo_workspace_bytes(const fargo_params *params, size_t *bytes) {
+  int rc = check_params(params);
+  if (rc) return rc;
+  if (!bytes) return FARGO_EINVAL;
+  *bytes = layout(params).total;
+  return FARGO_OK;
+}
+
+int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, fargo_ctx **out) {
+  if (!out) return FARGO_EINVAL;
+  int rc = check_params(params);
+  if (rc) return rc;
+  fargo_ctx *c = new (std::nothrow) fargo_ctx();
+  if (!c) return FARGO_ENOMEM;
+  if (hipGetDevice(&c->dev) != hipSuccess) {
+    delete c;
+    return FARGO_EHIP;
+  }
+  c->p = *params;
+  int pitch, nyg, nzg;
+  dims(params, pitch, nyg, nzg);
+  c->ymin.assign(params->ymin, params->ymin + nyg + 1);
+  c->zmin.assign(params->zmin, params->zmin + nzg + 1);
+  c->p.ymin = c->ymin.data();
+  c->p.zmin = c->zmin.data();
+  Layout Lo = layout(params);
+  if (workspace) {
+    if (ws_bytes < Lo.total || ((uintptr_t)workspace & 255)) {
+      delete c;
+      return ws_bytes < Lo.total ? FARGO_ENOMEM : FARGO_EINVAL;
+    }
+    c->ws = workspace;
+  } else {
+    if (hipMalloc(&c->ws, Lo.total) != hipSuccess) {
+      delete c;
+      return FARGO_ENOMEM;
+    }
+    c->own_ws = true;
+  }
+  c->ws_bytes = Lo.total;
+  char *base = (char *)c->ws;
+  // geometry
+  HostGeo G;
+  make_geo(&c->p, G);
+  std::vector<double> buf;
+  buf.reserve(geo_doubles(nyg, nzg));
+  std::vector<size_t> off;
+  for (const std::vector<double> *v : {&G.ymin, &G.ymed, &G.zmin, &G.zmed, &G.sinz, &G.Ly, &G.hy, &G.sxj, &G.syj,
+                                       &G.szj, &G.invVj, &G.sxk, &G.syk, &G.szk, &G.dxlen}) {
+    off.push_back(buf.size());
+    buf.insert(buf.end(), v->begin(), v->end());
+  }
+  double *gd = (double *)(base + Lo.geo);
+  if (hipMemcpy(gd, buf.data(), buf.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    fargo_destroy(c);
+    return FARGO_EHIP;
+  }
+  Mesh &m = c->m;
+  m.nx = params->nx;
+  m.ny = params->ny;
+  m.nz = params->nz;
+  m.pitch = pitch;
+  m.nyg = nyg;
+  m.nzg = nzg;
+  m.j0 = NGH;
+  m.jn = NGH + params->ny;
+  m.d3 = params->nz > 1;
+  m.k0 = m.d3 ? NGH : 0;
+  m.kn = m.d3 ? NGH + params->nz : 1;
+  m.geo = params->geometry;
+  m.eos = params->eos;
+  m.fargo = params->fargo ? 1 : 0;
+  m.v0_mean = params->v0_mode == FARGO_V0_MEAN;
+  for (int s = 0; s < 4; s++) m.bc[s] = params->bc[s];
+  m.nring = params->ny * params->nz;
+  m.dx = (params->xmax - params->xmin) / params->nx;
+  m.gamma = params->gamma;
+  m.omega = params->omega;
+  m.courant = params->courant;
+  m.cvnr = params->cvnr;
+  m.shear_c0 = params->shear_c0;
+  const double **tbl[] = {&m.g.ymin, &m.g.ymed, &m.g.zmin, &m.g.zmed, &m.g.sinz, &m.g.Ly, &m.g.hy, &m.g.sxj,
+                          &m.g.syj, &m.g.szj, &m.g.invVj, &m.g.sxk, &m.g.syk, &m.g.szk, &m.g.dxlen};
+  for (size_t t = 0; t < off.size(); t++) *tbl[t] = gd + off[t];
+  // words and per-ring arrays
+  char *wd = base + Lo.words;
+  c->w.dt = (double *)wd;
+  c->w.min_cell = (unsigned long long *)(wd + 8);
+  c->w.max_shear = (unsigned long long *)(wd + 16);
+  c->w.err = (int *)(wd + 24);
+  if (hipMemset(wd, 0, 256) != hipSuccess) {
+    fargo_destroy(c);
+    return FARGO_EHIP;
+  }
+  c->v0 = (double *)(base + Lo.v0);
+  c->xi = (double *)(base + Lo.xi);
+  c->nshift = (int32_t *)(base + Lo.nshift);
+  c->partial = (double *)(base + Lo.partial);
+  c->sums_out = (double *)(base + Lo.sums);
+  size_t nc = (size_t)pitch * nyg * nzg;
+  size_t fb = al(nc * 8);
+  c->v1[0] = (double *)(base + Lo.v1);
+  c->v1[1] = (double *)(base + Lo.v1 + fb);
+  c->v1[2] = m.d3 ? (double *)(base + Lo.v1 + 2 * fb) : nullptr;
+  int nT = ntransported(params);
+  int slot = 0;
+  for (int t = 0; t < T_MAX; t++) {
+    bool need = t <= T_PYP || (m.d3 && (t == T_PZM || t == T_PZP)) || (t == T_E && params->eos == FARGO_ADIABATIC);
+    c->TA.a[t] = c->TB.a[t] = nullptr;
+    if (!need) continue;
+    c->TA.a[t] = (double *)(base + Lo.T + (size_t)slot * fb);
+    c->TB.a[t] = (double *)(base + Lo.T + (size_t)(nT + slot) * fb);
+    slot++;
+    if (t != T_RHO) {
+      c->TA.q[c->TA.nq++] = c->TA.a[t];
+      c->TB.q[c->TB.nq++] = c->TB.a[t];
+    }
+  }
+  *out = c;
+  return FARGO_OK;
+}
+
+void fargo_destroy(fargo_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  if (ctx->own_ws && ctx->ws) (void)hipFree(ctx->ws);
+  delete ctx;
+}
+
+int fargo_cfl_dt(fargo_ctx *ctx, fargo_state *state, double *dt_host, void *stream) {
+  if (!ctx) return FARGO_EINVAL;
+  int rc = check_state(ctx, state);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Launch L{s, &ctx->prof};
+  StateP S = state_of(ctx, state);
+  timestep_phase(ctx, L, S, 0.0);
+  if (hipGetLastError() != hipSuccess) return FARGO_EHIP;
+  if (!dt_host) return FARGO_OK;
+  double dt = 0.0;
+  int err = 0;
+  if (hipMemcpyAsync(&dt, ctx->w.dt, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return FARGO_EHIP;
+  if (hipMemcpyAsync(&err, ctx->w.err, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return FARGO_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return FARGO_EHIP;
+  *dt_host = dt;
+  if (err & 1) return FARGO_ENONFINITE;
+  if (err & 2) return FARGO_ECFL;
+  return FARGO_OK;
+}
+
+int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream) {
+  if (!ctx) return FARGO_EINVAL;
+  int rc = check_state(ctx, state);
+  if (rc) return rc;
+  if (!(dt <= 0.0) && !std::isfinite(dt)) return FARGO_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Launch L{s, &ctx->prof};
+  const Mesh &m = ctx->m;
+  StateP S = state_of(ctx, state);
+  timestep_phase(ctx, L, S, dt > 0.0 ? dt : 0.0);                   // boxes 2, 3, 4, 6
+  if (m.fargo) launch_split(L, m, ctx->v0, ctx->w.dt, 0.0, ctx->nshift, ctx->xi);
+  launch_source(L, m, S, ctx->w.dt, ctx->v1[0], ctx->v1[1], ctx->v1[2]); // box 7
+  launch_bc(L, m, S.rho, S.e, S.vx, S.vy, S.vz);                    // box 9
+  launch_momenta(L, m, S, ctx->TA);                                  // box 12a
+  launch_sweep_y(L, m, S.vy, ctx->TA, ctx->TB, ctx->w.dt);          // box 12b/c
+  const TSet *cur = &ctx->TB;
+  if (m.d3) {
+    launch_sweep_z(L, m, S.vz, ctx->TB, ctx->TA, ctx->w.dt);
+    cur = &ctx->TA;
+  }
+  launch_ring_x(L, m, S.vx, *cur, ctx->v0, ctx->nshift, ctx->xi, ctx->w.dt);
+  launch_vel(L, m, S, *cur);                                         // box 12d
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+int fargo_shift(fargo_ctx *ctx, double *field, const int32_t *nshift, void *stream) {
+  if (!ctx || !field || !nshift) return FARGO_EINVAL;
+  if (ctx->m.nx > 8192) return FARGO_EUNSUPPORTED;
+  Launch L{(hipStream_t)stream, &ctx->prof};
+  launch_shift(L, ctx->m, field, nshift);
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+int fargo_ring_split(fargo_ctx *ctx, const double *vx, double dt, double *v0, int32_t *nshift, double *xi,
+                     void *stream) {
+  if (!ctx || !vx || !v0 || !nshift || !xi || !(dt > 0.0) || !std::isfinite(dt)) return FARGO_EINVAL;
+  Launch L{(hipStream_t)stream, &ctx->prof};
+  launch_ring_v0(L, ctx->m, vx, v0);
+  launch_split(L, ctx->m, v0, nullptr, dt, nshift, xi);
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+int fargo_conserved_sums(fargo_ctx *ctx, const fargo_state *state, double out[5], void *stream) {
+  if (!ctx || !out) return FARGO_EINVAL;
+  int rc = check_state(ctx, state);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Launch L{s, &ctx->prof};
+  StateP S = state_of(ctx, state);
+  launch_sums(L, ctx->m, S, ctx->partial, ctx->sums_out);
+  if (hipGetLastError() != hipSuccess) return FARGO_EHIP;
+  if (hipMemcpyAsync(out, ctx->sums_out, 5 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return FARGO_EHIP;
+  return hip_ok(hipStreamSynchronize(s));
+}
+
+int fargo_get_dt(fargo_ctx *ctx, double *dt_host, void *stream) {
+  if (!ctx || !dt_host) return FARGO_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(dt_host, ctx->w.dt, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return FARGO_EHIP;
+  return hip_ok(hipStreamSynchronize(s));
+}
+
+int fargo_check(fargo_ctx *ctx) {
+  if (!ctx) return FARGO_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return FARGO_EHIP;
+  int err = 0;
+  if (hipMemcpy(&err, ctx->w.err, 4, hipMemcpyDeviceToHost) != hipSuccess) return FARGO_EHIP;
+  int zero = 0;
+  if (hipMemcpy(ctx->w.err, &zero, 4, hipMemcpyHostToDevice) != hipSuccess) return FARGO_EHIP;
+  if (err & 1) return FARGO_ENONFINITE;
+  if (err & 2) return FARGO_ECFL;
+  return FARGO_OK;
+}
+
+int fargo_profile_enable(fargo_ctx *ctx, int on) {
+  if (!ctx) return FARGO_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return FARGO_EHIP;
+  Prof &P = ctx->prof;
+  for (auto &pd : P.pending) {
+    P.pool.push_back(pd.a);
+    P.pool.push_back(pd.b);
+  }
+  P.pending.clear();
+  for (int k = 0; k < K_COUNT; k++) {
+    P.total_ms[k] = 0.0;
+    P.count[k] = 0;
+  }
+  P.on = on != 0;
+  return FARGO_OK;
+}
+
+int fargo_timings(fargo_ctx *ctx, const char **names, int64_t *counts, double *total_ms, int cap, int *n_out,
+                  void *stream) {
+  if (!ctx) return FARGO_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return FARGO_EHIP;
+  Prof &P = ctx->prof;
+  for (auto &pd : P.pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pd.a, pd.b) == hipSuccess) {
+      P.total_ms[pd.kid] += ms;
+      P.count[pd.kid] += 1;
+    }
+    P.pool.push_back(pd.a);
+    P.pool.push_back(pd.b);
+  }
+  P.pending.clear();
+  int n = 0;
+  for (int k = 0; k < K_COUNT && n < cap; k++) {
+    if (names) names[n] = kernel_names[k];
+    if (counts) counts[n] = P.count[k];
+    if (total_ms) total_ms[n] = P.total_ms[k];
+    n++;
+  }
+  if (n_out) *n_out = n;
+  return FARGO_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,124 @@
+// Stand-alone circular shift of rings (Eq. 32) and conserved sums (mass,
+// momenta of Tab. "momenta" with the zone momentum of Eq. 19, internal
+// energy) with double-double accumulation in a fixed order.
+#include "fargo_internal.h"
+
+namespace fargo {
+
+namespace {
+
+// Eq. 32 in place: one workgroup per active ring, the ring staged in LDS.
+__global__ __launch_bounds__(256) void k_shift(Mesh m, double *__restrict__ f, const int32_t *__restrict__ N) {
+  extern __shared__ double ring[];
+  int r = blockIdx.x;
+  int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
+  double *row = f + m.idx(0, j, k);
+  int n = m.nx;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ring[i] = row[i];
+  __syncthreads();
+  int s = N[r] % n;
+  if (s < 0) s += n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int src = i - s;
+    if (src < 0) src += n;
+    row[i] = ring[src];
+  }
+}
+
+// double-double accumulation (error-free two-sum), contraction off
+struct DD {
+  double hi, lo;
+};
+__device__ inline DD dd_add(DD a, double b) {
+#pragma clang fp contract(off)
+  double s = a.hi + b;
+  double bp = s - a.hi;
+  double err = (a.hi - (s - bp)) + (b - bp);
+  return DD{s, a.lo + err};
+}
+__device__ inline DD dd_add(DD a, DD b) {
+#pragma clang fp contract(off)
+  DD s = dd_add(a, b.hi);
+  s.lo += b.lo;
+  double hi = s.hi + s.lo;
+  double lo = s.lo - (hi - s.hi);
+  return DD{hi, lo};
+}
+__device__ inline DD shfl_dd(DD v, int o) { return DD{__shfl_xor(v.hi, o, 64), __shfl_xor(v.lo, o, 64)}; }
+
+__device__ inline DD block_sum(DD v, DD *lds) {
+  for (int o = 32; o > 0; o >>= 1) v = dd_add(v, shfl_dd(v, o));
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  DD out{0.0, 0.0};
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) out = dd_add(out, lds[w]);
+  __syncthreads();
+  return out;
+}
+
+// One workgroup per active ring: partial[r*10 + 2q + {0,1}] = (hi, lo) of sum q.
+__global__ __launch_bounds__(256) void k_sums(Mesh m, StateP s, double *__restrict__ partial) {
+#pragma clang fp contract(off)
+  __shared__ DD lds[4];
+  int r = blockIdx.x;
+  int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
+  int jp = m.jabove(j), kp = m.d3 ? m.kabove(k) : k;
+  double V = m.Vol(j, k);
+  DD acc[5];
+  for (int q = 0; q < 5; q++) acc[q] = DD{0.0, 0.0};
+  for (int i = threadIdx.x; i < m.nx; i += blockDim.x) {
+    int ip = i + 1 == m.nx ? 0 : i + 1;
+    size_t c = m.idx(i, j, k);
+    double rho = s.rho[c];
+    double t0 = rho * V;
+    double t1 = rho * 0.5 * (m.mx(j, k, s.vx[c]) + m.mx(j, k, s.vx[m.idx(ip, j, k)])) * V;
+    double t2 = rho * 0.5 * (s.vy[c] + s.vy[m.idx(i, jp, k)]) * V;
+    double t3 = m.d3 ? rho * 0.5 * (m.mz(j, s.vz[c]) + m.mz(j, s.vz[m.idx(i, j, kp)])) * V : 0.0;
+    double t4 = s.e ? s.e[c] * V : 0.0;
+    acc[0] = dd_add(acc[0], t0);
+    acc[1] = dd_add(acc[1], t1);
+    acc[2] = dd_add(acc[2], t2);
+    acc[3] = dd_add(acc[3], t3);
+    acc[4] = dd_add(acc[4], t4);
+  }
+  for (int q = 0; q < 5; q++) {
+    DD v = block_sum(acc[q], lds);
+    if (threadIdx.x == 0) {
+      partial[(size_t)r * 10 + 2 * q] = v.hi;
+      partial[(size_t)r * 10 + 2 * q + 1] = v.lo;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sums_final(int nring, const double *__restrict__ partial,
+                                                    double *__restrict__ out) {
+  __shared__ DD lds[4];
+  for (int q = 0; q < 5; q++) {
+    DD acc{0.0, 0.0};
+    for (int r = threadIdx.x; r < nring; r += blockDim.x)
+      acc = dd_add(acc, DD{partial[(size_t)r * 10 + 2 * q], partial[(size_t)r * 10 + 2 * q + 1]});
+    DD v = block_sum(acc, lds);
+    if (threadIdx.x == 0) out[q] = v.hi + v.lo;
+  }
+}
+
+} // namespace
+
+void launch_shift(Launch &L, const Mesh &m, double *field, const int32_t *N) {
+  prof_begin(L, K_SHIFT);
+  k_shift<<<m.nring, 256, (size_t)m.nx * sizeof(double), L.s>>>(m, field, N);
+  prof_end(L, K_SHIFT);
+}
+
+void launch_sums(Launch &L, const Mesh &m, const StateP &s, double *partial, double *out) {
+  prof_begin(L, K_SUMS);
+  k_sums<<<m.nring, 256, 0, L.s>>>(m, s, partial);
+  prof_end(L, K_SUMS);
+  prof_begin(L, K_SUMS_FINAL);
+  k_sums_final<<<1, 256, 0, L.s>>>(m.nring, partial, out);
+  prof_end(L, K_SUMS_FINAL);
+}
+
+} // namespace fargo

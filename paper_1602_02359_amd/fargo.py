@@ -1,0 +1,236 @@
+"""Thin Python binding of libfargo (the C ABI of include/fargo.h).
+
+Argument marshalling only: every step of the hydrodynamics path runs in the
+library's HIP kernels.  PyTorch supplies device memory (the state tensors and
+the workspace) and the stream.  There is no CPU fallback: if libfargo.so has
+not been built, importing this module raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+import torch  # loads the HIP runtime that libfargo binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfargo.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libfargo.so is not built (run __graft_entry__.build() or "
+                      "python paper_1602_02359_amd/csrc/build.py)")
+
+ABI_VERSION = 1
+NGH = 3
+GEOMETRY = {"cart": 0, "cyl": 1, "sph": 2}
+EOS = {"iso": 0, "adi": 1}
+BC = {"periodic": 0, "reflect": 1, "outflow": 2, "fixed": 3}
+V0_MODE = {"minmax": 0, "mean": 1}
+FIELDS = ("rho", "vx", "vy", "vz", "e", "cs", "pot")
+
+
+class fargo_params(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("geometry", C.c_int32),
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("xmin", C.c_double), ("xmax", C.c_double),
+        ("ymin", C.POINTER(C.c_double)), ("zmin", C.POINTER(C.c_double)),
+        ("eos", C.c_int32), ("gamma", C.c_double),
+        ("omega", C.c_double), ("courant", C.c_double), ("cvnr", C.c_double), ("shear_c0", C.c_double),
+        ("fargo", C.c_int32), ("v0_mode", C.c_int32),
+        ("bc", C.c_int32 * 4), ("precision", C.c_int32),
+    ]
+
+
+class fargo_state(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in FIELDS]
+
+
+_lib = C.CDLL(LIB_PATH)
+_P = C.POINTER(fargo_params)
+_S = C.POINTER(fargo_state)
+_lib.fargo_abi_version.restype = C.c_int
+_lib.fargo_strerror.restype = C.c_char_p
+_lib.fargo_strerror.argtypes = [C.c_int]
+_lib.fargo_layout.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+_lib.fargo_workspace_bytes.argtypes = [_P, C.POINTER(C.c_size_t)]
+_lib.fargo_init.argtypes = [_P, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]
+_lib.fargo_destroy.argtypes = [C.c_void_p]
+_lib.fargo_destroy.restype = None
+_lib.fargo_cfl_dt.argtypes = [C.c_void_p, _S, C.POINTER(C.c_double), C.c_void_p]
+_lib.fargo_step.argtypes = [C.c_void_p, _S, C.c_double, C.c_void_p]
+_lib.fargo_shift.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.fargo_ring_split.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.fargo_conserved_sums.argtypes = [C.c_void_p, _S, C.POINTER(C.c_double), C.c_void_p]
+_lib.fargo_get_dt.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
+_lib.fargo_check.argtypes = [C.c_void_p]
+_lib.fargo_profile_enable.argtypes = [C.c_void_p, C.c_int]
+_lib.fargo_timings.argtypes = [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                               C.c_int, C.POINTER(C.c_int), C.c_void_p]
+
+EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_workspace_bytes", "fargo_init",
+            "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
+            "fargo_conserved_sums", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings")
+
+
+class FargoError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__("%s: %s (%d)" % (what, _lib.fargo_strerror(code).decode(), code))
+        self.code = code
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise FargoError(rc, what)
+
+
+def fargo_abi_version() -> int:
+    return _lib.fargo_abi_version()
+
+
+def make_params(p: Dict):
+    """ctypes fargo_params from a parameter dict; returns (struct, keepalive)."""
+    ymin = np.ascontiguousarray(p["ymin"], dtype=np.float64)
+    zmin = np.ascontiguousarray(p["zmin"], dtype=np.float64)
+    s = fargo_params()
+    s.abi_version = ABI_VERSION
+    s.geometry = GEOMETRY[p["geometry"]]
+    s.nx, s.ny, s.nz = int(p["nx"]), int(p["ny"]), int(p["nz"])
+    s.xmin, s.xmax = float(p["xmin"]), float(p["xmax"])
+    s.ymin = ymin.ctypes.data_as(C.POINTER(C.c_double))
+    s.zmin = zmin.ctypes.data_as(C.POINTER(C.c_double))
+    s.eos = EOS[p["eos"]]
+    s.gamma = float(p["gamma"])
+    s.omega, s.courant, s.cvnr, s.shear_c0 = float(p["omega"]), float(p["courant"]), float(p["cvnr"]), float(p["shear_c0"])
+    s.fargo = int(bool(p["fargo"]))
+    s.v0_mode = V0_MODE[p.get("v0_mode", "minmax")]
+    for i, b in enumerate(p["bc"]):
+        s.bc[i] = BC[b]
+    s.precision = 0
+    return s, (ymin, zmin)
+
+
+def fargo_layout(p: Dict):
+    ps, keep = make_params(p)
+    pitch, nyg, nzg = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib.fargo_layout(C.byref(ps), C.byref(pitch), C.byref(nyg), C.byref(nzg)), "fargo_layout")
+    return pitch.value, nyg.value, nzg.value
+
+
+def fargo_workspace_bytes(p: Dict) -> int:
+    ps, keep = make_params(p)
+    n = C.c_size_t()
+    _check(_lib.fargo_workspace_bytes(C.byref(ps), C.byref(n)), "fargo_workspace_bytes")
+    return n.value
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Solver:
+    """Owns a fargo context, its workspace and the device state tensors
+    (padded layout [nz_g, ny_g, pitch], float64)."""
+
+    def __init__(self, params: Dict, device: str = "cuda", workspace: bool = True):
+        self.params = dict(params)
+        self.device = torch.device(device)
+        self.pitch, self.nyg, self.nzg = fargo_layout(params)
+        self.shape = (self.nzg, self.nyg, self.pitch)
+        self._ps, self._keep = make_params(params)
+        nbytes = fargo_workspace_bytes(params)
+        self._ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            if workspace:
+                self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+                _check(_lib.fargo_init(C.byref(self._ps), C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                       C.byref(self._ctx)), "fargo_init")
+            else:
+                self.workspace = None
+                _check(_lib.fargo_init(C.byref(self._ps), None, 0, C.byref(self._ctx)), "fargo_init")
+        self.state: Dict[str, Optional[torch.Tensor]] = {}
+        self._st = fargo_state()
+
+    def __del__(self):
+        ctx = getattr(self, "_ctx", None)
+        if ctx is not None and ctx.value:
+            _lib.fargo_destroy(ctx)
+            self._ctx = None
+
+    # -- state -------------------------------------------------------------
+    def upload(self, fields: Dict[str, Optional[np.ndarray]]):
+        """Copy host arrays (nz_g, ny_g, nx) into padded device tensors."""
+        nx = self.params["nx"]
+        self.state = {}
+        for n in FIELDS:
+            a = fields.get(n)
+            if a is None:
+                self.state[n] = None
+                continue
+            t = torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+            t[:, :, :nx] = torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
+            self.state[n] = t
+        self._bind()
+
+    def _bind(self):
+        for n in FIELDS:
+            t = self.state.get(n)
+            setattr(self._st, n, C.c_void_p(t.data_ptr()) if t is not None else None)
+
+    def download(self) -> Dict[str, Optional[np.ndarray]]:
+        nx = self.params["nx"]
+        torch.cuda.synchronize(self.device)
+        return {n: (None if t is None else t[:, :, :nx].cpu().numpy().copy()) for n, t in self.state.items()}
+
+    # -- C ABI calls -------------------------------------------------------
+    def fargo_step(self, dt: float = 0.0, stream=None):
+        _check(_lib.fargo_step(self._ctx, C.byref(self._st), float(dt), _stream(stream)), "fargo_step")
+
+    def fargo_cfl_dt(self, stream=None) -> float:
+        out = C.c_double()
+        _check(_lib.fargo_cfl_dt(self._ctx, C.byref(self._st), C.byref(out), _stream(stream)), "fargo_cfl_dt")
+        return out.value
+
+    def fargo_get_dt(self, stream=None) -> float:
+        out = C.c_double()
+        _check(_lib.fargo_get_dt(self._ctx, C.byref(out), _stream(stream)), "fargo_get_dt")
+        return out.value
+
+    def fargo_shift(self, field: torch.Tensor, nshift: torch.Tensor, stream=None):
+        assert field.dtype == torch.float64 and tuple(field.shape) == self.shape and field.is_contiguous()
+        assert nshift.dtype == torch.int32 and nshift.numel() == self.params["ny"] * self.params["nz"]
+        _check(_lib.fargo_shift(self._ctx, C.c_void_p(field.data_ptr()), C.c_void_p(nshift.data_ptr()),
+                                _stream(stream)), "fargo_shift")
+
+    def fargo_ring_split(self, vx: torch.Tensor, dt: float, stream=None):
+        nr = self.params["ny"] * self.params["nz"]
+        v0 = torch.empty(nr, dtype=torch.float64, device=self.device)
+        N = torch.empty(nr, dtype=torch.int32, device=self.device)
+        xi = torch.empty(nr, dtype=torch.float64, device=self.device)
+        _check(_lib.fargo_ring_split(self._ctx, C.c_void_p(vx.data_ptr()), float(dt), C.c_void_p(v0.data_ptr()),
+                                     C.c_void_p(N.data_ptr()), C.c_void_p(xi.data_ptr()), _stream(stream)),
+               "fargo_ring_split")
+        return v0, N, xi
+
+    def fargo_conserved_sums(self, stream=None) -> np.ndarray:
+        out = (C.c_double * 5)()
+        _check(_lib.fargo_conserved_sums(self._ctx, C.byref(self._st), out, _stream(stream)), "fargo_conserved_sums")
+        return np.array(list(out))
+
+    def fargo_check(self):
+        _check(_lib.fargo_check(self._ctx), "fargo_check")
+
+    def fargo_profile_enable(self, on: bool = True):
+        _check(_lib.fargo_profile_enable(self._ctx, int(on)), "fargo_profile_enable")
+
+    def fargo_timings(self, stream=None) -> Dict[str, tuple]:
+        cap = 64
+        names = (C.c_char_p * cap)()
+        counts = (C.c_int64 * cap)()
+        tot = (C.c_double * cap)()
+        n = C.c_int()
+        _check(_lib.fargo_timings(self._ctx, names, counts, tot, cap, C.byref(n), _stream(stream)), "fargo_timings")
+        return {names[i].decode(): (counts[i], tot[i]) for i in range(n.value) if counts[i] > 0}

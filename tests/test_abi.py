@@ -1,0 +1,49 @@
+"""CPU checks of the C ABI boundary: the shared library loads and exports every
+function that include/fargo.h declares; parameter validation and layout
+queries answer without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1602_02359_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fargo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fargo_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    from paper_1602_02359_amd import fargo as F
+    lib = ctypes.CDLL(F.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(F.EXPORTED) == set(names)
+
+
+def test_layout_and_validation_without_gpu():
+    from paper_1602_02359_amd import fargo as F
+    pr = W.disk3d_sph()
+    assert F.fargo_layout(pr.params) == (1536, 518, 134)
+    pr = W.disk2d_cyl()
+    assert F.fargo_layout(pr.params) == (384, 134, 1)
+    pr = W.random_problem("cart", nx=70, ny=5, nz=4)
+    assert F.fargo_layout(pr.params) == (128, 11, 10)
+    assert F.fargo_abi_version() == 1
+    for bad in (dict(ny=2), dict(nz=2), dict(geometry="cyl", bc=("periodic",) * 4), dict(eos="adi", gamma=1.0)):
+        with pytest.raises(F.FargoError) as e:
+            F.fargo_layout(dict(pr.params, **bad))
+        assert e.value.code == -1
+    with pytest.raises(F.FargoError) as e:
+        F.fargo_layout(dict(pr.params, nx=4096))
+    assert e.value.code == -6
+    wsb = F.fargo_workspace_bytes(W.disk3d_sph().params)
+    assert wsb > 16 * 1536 * 518 * 134 * 8

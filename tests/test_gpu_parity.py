@@ -1,0 +1,283 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: integer work (shift amounts, circular shifts) and the time step are
+bit-exact; floating-point state is within 1e-12 normwise (velocities
+normalised by the largest speed) after one step, as the target states.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1602_02359_amd import workloads as W
+from gpu_common import NG, errors, gpu_solver, sub_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    yield "disk2d_small", lambda: W.disk2d_cyl(nx=200, ny=37, noise=1e-2)
+    yield "disk2d_rot", lambda: W.disk2d_cyl(nx=130, ny=21, noise=3e-2, omega=1.0)
+    yield "disk2d_nofargo", lambda: W.disk2d_cyl(nx=96, ny=17, noise=1e-2, fargo=False)
+    yield "sph3d_small", lambda: W.disk3d_sph(nx=136, ny=19, nz=11, noise=1e-2)
+    yield "cyl3d_planet_small", lambda: W.disk3d_cyl_planet(nx=150, ny=23, nz=9, noise=1e-2)
+    yield "cart_random_reflect", lambda: W.random_problem("cart", nx=70, ny=9, nz=7, eos="adi", seed=1)
+    yield "cart_random_periodic", lambda: W.random_problem("cart", nx=33, ny=8, nz=6, eos="iso", seed=2,
+                                                          bc=("periodic",) * 4)
+    yield "cart_random_outflow", lambda: W.random_problem("cart", nx=65, ny=7, nz=5, eos="adi", seed=3,
+                                                         bc=("outflow", "reflect", "outflow", "outflow"))
+    yield "cyl_random_fargo", lambda: W.random_problem("cyl", nx=300, ny=6, nz=5, eos="iso", seed=4, fargo=True,
+                                                      omega=0.5, bc=("fixed", "outflow", "periodic", "periodic"))
+    yield "sph_random_fargo", lambda: W.random_problem("sph", nx=257, ny=5, nz=4, eos="adi", seed=5, fargo=True,
+                                                      omega=-0.3, bc=("reflect", "fixed", "fixed", "reflect"))
+    yield "cyl2d_random_mean", lambda: _with(W.random_problem("cyl", nx=64, ny=12, nz=1, eos="adi", seed=6,
+                                                              fargo=True), v0_mode="mean")
+    yield "sod_y_nx1", lambda: W.sod("y", n=64)
+    yield "sod_z", lambda: W.sod("z", n=40)
+    yield "ring_2048", lambda: W.random_problem("cyl", nx=2048, ny=4, nz=1, eos="iso", seed=7, fargo=True)
+
+
+def _with(prob, **kw):
+    prob.params.update(kw)
+    return prob
+
+
+CASES = dict(_cases())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_one_step_matches_oracle(name):
+    prob = CASES[name]()
+    _say("case", name, prob.shape)
+    ref = prob.copy_fields()
+    dt_ref = O.step(prob.params, ref)
+    s = gpu_solver(prob)
+    s.fargo_step(0.0)
+    s.fargo_check()
+    dt_gpu = s.fargo_get_dt()
+    got = s.download()
+    assert dt_gpu == dt_ref, (dt_gpu, dt_ref)
+    err = errors(prob, got, ref)
+    _say(name, "dt", dt_gpu, "errors", err)
+    for k, e in err.items():
+        assert e <= TOL, (k, e)
+
+
+@pytest.mark.parametrize("name", ["disk2d_small", "sph3d_small", "cart_random_periodic", "sph_random_fargo"])
+def test_several_steps_match_oracle(name):
+    """Five steps, each side with its own time step."""
+    prob = CASES[name]()
+    _say("case", name, prob.shape)
+    ref = prob.copy_fields()
+    s = gpu_solver(prob)
+    for n in range(5):
+        dt_ref = O.step(prob.params, ref)
+        s.fargo_step(0.0)
+        assert s.fargo_get_dt() == dt_ref
+    s.fargo_check()
+    err = errors(prob, s.download(), ref)
+    _say(name, err)
+    for k, e in err.items():
+        assert e <= 10 * TOL, (k, e)
+
+
+def test_imposed_dt_and_cfl_readback():
+    prob = CASES["sph3d_small"]()
+    ref = prob.copy_fields()
+    dt_ref = O.cfl_dt(prob.params, ref)
+    s = gpu_solver(prob)
+    assert s.fargo_cfl_dt() == dt_ref
+    got0 = s.download()
+    for k in ("rho", "vx", "vy", "vz", "e"):  # box 2 on both sides
+        assert np.array_equal(got0[k], ref[k]), k
+    dt = 0.7 * dt_ref
+    O.step(prob.params, ref, dt)
+    s.fargo_step(dt)
+    assert s.fargo_get_dt() == dt
+    err = errors(prob, s.download(), ref)
+    for k, e in err.items():
+        assert e <= TOL, (k, e)
+
+
+@pytest.mark.parametrize("name", ["disk2d_small", "sph3d_small", "cyl_random_fargo", "cyl2d_random_mean"])
+def test_ring_split_bit_exact(name):
+    """v0, N and xi of Eq. 29 are bit-exact."""
+    import torch
+    prob = CASES[name]()
+    s = gpu_solver(prob)
+    for dt in (0.013, 0.0371, 1e-3):
+        v0, N, xi = O.ring_split(prob.params, prob.fields["vx"], dt)
+        g0, gN, gxi = s.fargo_ring_split(s.state["vx"], dt)
+        torch.cuda.synchronize()
+        assert np.array_equal(g0.cpu().numpy(), v0.ravel())
+        assert np.array_equal(gN.cpu().numpy(), N.ravel())
+        assert np.array_equal(gxi.cpu().numpy(), xi.ravel())
+
+
+def test_split_ties_and_signs():
+    """Nearest-integer ties (D = k + 1/2) go away from zero on both sides."""
+    import torch
+    p = W.default_params(geometry="cart", nx=16, ny=3, nz=1, xmin=0.0, xmax=16.0,
+                         ymin=W.uniform_faces(0.0, 3.0, 3), zmin=np.array([0.0, 1.0]), fargo=True)
+    pr = W._blank(p)
+    vals = [2.5, -2.5, 0.5]
+    for j, v in enumerate(vals):
+        pr.fields["vx"][0, NG + j, :] = v
+    s = gpu_solver(pr)
+    v0, N, xi = s.fargo_ring_split(s.state["vx"], 1.0)
+    torch.cuda.synchronize()
+    assert N.cpu().tolist() == [3, -3, 1]
+    assert xi.cpu().tolist() == [-0.5, 0.5, -0.5]
+    ov0, oN, oxi = O.ring_split(p, pr.fields["vx"], 1.0)
+    assert oN.ravel().tolist() == [3, -3, 1]
+
+
+@pytest.mark.parametrize("nx", [1, 7, 64, 200, 2048])
+def test_shift_bit_exact(nx):
+    """Eq. 32 as a pure permutation, equal to the oracle's, ghosts untouched."""
+    import torch
+    prob = W.random_problem("cart", nx=nx, ny=5, nz=4, seed=8)
+    s = gpu_solver(prob)
+    rng = np.random.default_rng(nx)
+    N = rng.integers(-3 * nx, 3 * nx + 1, size=(4, 5)).astype(np.int32)
+    f = s.state["rho"]
+    s.fargo_shift(f, torch.from_numpy(N.ravel()).to(f.device))
+    got = f[:, :, :nx].cpu().numpy()
+    ref = prob.fields["rho"].copy()
+    O.shift(prob.params, ref, N)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name", ["disk2d_small", "sph3d_small", "cart_random_periodic", "cyl_random_fargo"])
+def test_conserved_sums(name):
+    prob = CASES[name]()
+    ref = prob.copy_fields()
+    O.cfl_dt(prob.params, ref)
+    s = gpu_solver(prob)
+    s.fargo_cfl_dt()
+    g = s.fargo_conserved_sums()
+    o, a = O.sums(prob.params, ref)
+    for q in range(5):
+        assert abs(g[q] - o[q]) <= 1e-14 * max(a[q], 1e-300), (q, g[q], o[q])
+
+
+def test_deterministic():
+    prob = CASES["sph3d_small"]()
+    outs = []
+    for _ in range(2):
+        s = gpu_solver(prob)
+        for _ in range(3):
+            s.fargo_step(0.0)
+        outs.append(s.download())
+    for k in outs[0]:
+        if outs[0][k] is not None:
+            assert np.array_equal(outs[0][k], outs[1][k]), k
+
+
+def test_errors_reported():
+    from paper_1602_02359_amd import fargo as F
+    prob = W.random_problem("cart", nx=16, ny=5, nz=4, seed=9)
+    bad = dict(prob.params, ny=2)
+    with pytest.raises(F.FargoError) as e:
+        F.Solver(bad)
+    assert e.value.code == -1
+    f = prob.copy_fields()
+    f["rho"][NG + 1, NG + 1, 3] = np.nan
+    s = gpu_solver(W.Problem("nan", prob.params, f))
+    s.fargo_step(0.0)
+    with pytest.raises(F.FargoError) as e:
+        s.fargo_check()
+    assert e.value.code == -4
+    # error word cleared after the report
+    s2 = gpu_solver(prob)
+    s2.fargo_step(0.0)
+    s2.fargo_check()
+
+
+# ---------------------------------------------------------------------------
+# Full-size configurations, in the launch configuration the benchmark times:
+# time step bit-exact over the whole mesh, state checked on sampled sub-blocks
+# that the oracle recomputes with the real neighbouring data as ghosts.
+# ---------------------------------------------------------------------------
+
+MARGIN = 6
+
+
+def _blocks(p):
+    ny, nz = p["ny"], p["nz"]
+    w = 10
+    ys = [(NG, NG + w + MARGIN), (NG + ny // 2 - w // 2 - MARGIN, NG + ny // 2 + w // 2 + MARGIN),
+          (NG + ny - w - MARGIN, NG + ny)]
+    if nz == 1:
+        return [(y, None) for y in ys]
+    zs = [(NG, NG + w + MARGIN), (NG + nz // 2 - w // 2 - MARGIN, NG + nz // 2 + w // 2 + MARGIN),
+          (NG + nz - w - MARGIN, NG + nz)]
+    return [(ys[0], zs[1]), (ys[1], zs[0]), (ys[1], zs[1]), (ys[2], zs[2])]
+
+
+def _inner(p, sub_p, jr, kr):
+    """Slices of the sub-block result (and of the full arrays) that are exact."""
+    ja, jb = jr
+    lo = 0 if ja == NG else MARGIN
+    hi = 0 if jb == NG + p["ny"] else MARGIN
+    sj = slice(NG + lo, NG + sub_p["ny"] - hi)
+    fj = slice(ja + lo, jb - hi)
+    if p["nz"] == 1:
+        return (slice(0, 1), sj), (slice(0, 1), fj)
+    ka, kb = kr
+    lo = 0 if ka == NG else MARGIN
+    hi = 0 if kb == NG + p["nz"] else MARGIN
+    return (slice(NG + lo, NG + sub_p["nz"] - hi), sj), (slice(ka + lo, kb - hi), fj)
+
+
+@pytest.mark.parametrize("cfg", ["sph3d", "cyl3d_planet", "disk2d"])
+def test_full_size_sampled(cfg):
+    import torch
+    prob = W.make(cfg)
+    p = prob.params
+    _say("full-size", cfg, prob.shape, "cells", prob.active_cells)
+    f0 = prob.fields
+    full = {k: (None if v is None else v.copy()) for k, v in f0.items()}
+    dt_ref = O.cfl_dt(p, full)  # fills the ghosts of `full` (box 2)
+    s = gpu_solver(prob)
+    s.fargo_step(0.0)
+    s.fargo_check()
+    dt = s.fargo_get_dt()
+    assert dt == dt_ref, (dt, dt_ref)
+    got = s.download()
+    del s
+    torch.cuda.empty_cache()
+    vmax = max(np.abs(full[k]).max() for k in ("vx", "vy", "vz") if full.get(k) is not None)
+    worst = {}
+    for jr, kr in _blocks(p):
+        sub = sub_problem(prob, full, jr, kr)
+        ref = sub.copy_fields()
+        O.step(sub.params, ref, dt)
+        (sk, sj), (fk, fj) = _inner(p, sub.params, jr, kr)
+        for k in ("rho", "e", "vx", "vy", "vz"):
+            if ref.get(k) is None:
+                continue
+            a = got[k][fk, fj, :]
+            b = ref[k][sk, sj, :]
+            den = vmax if k.startswith("v") else np.abs(full[k]).max()
+            e = float(np.abs(a - b).max() / den)
+            worst[k] = max(worst.get(k, 0.0), e)
+    _say(cfg, "dt", dt, "sampled errors", worst)
+    for k, e in worst.items():
+        assert e <= TOL, (k, e)
