@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="sph3d", choices=["sph3d", "cyl3d_planet", "disk2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain device copy of 2 GiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
@@ -143,6 +145,14 @@ def main():
     from paper_1602_02359_amd import fargo as F
     from paper_1602_02359_amd import workloads as W
 
+    if args.copy_probe:
+        src = torch.ones(2 ** 28, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8), file=sys.stderr)
+        del src, dst
+        torch.cuda.empty_cache()
     prob = W.make(args.config)
     p = prob.params
     print("workload %s %dx%dx%d, building state" % (args.config, p["nx"], p["ny"], p["nz"]), file=sys.stderr,

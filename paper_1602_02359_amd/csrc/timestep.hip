@@ -21,8 +21,9 @@ __global__ void k_reset(DevWords w) {
 
 __global__ void k_set_dt(DevWords w, double dt) { *w.dt = dt; }
 
+// `id` is the identity of `op` (pads the lanes past the number of waves).
 template <typename T, typename Op>
-__device__ inline T block_reduce(T v, Op op, T *lds) {
+__device__ inline T block_reduce(T v, Op op, T id, T *lds) {
   // 64-lane wave reduction then across the (at most 16) waves of the block
   for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
   int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -30,7 +31,7 @@ __device__ inline T block_reduce(T v, Op op, T *lds) {
   __syncthreads();
   int nw = (blockDim.x + 63) >> 6;
   if (wid == 0) {
-    v = lane < nw ? lds[lane] : lds[0];
+    v = lane < nw ? lds[lane] : id;
     for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
   }
   return v; // valid in thread 0
@@ -54,13 +55,13 @@ __global__ __launch_bounds__(256) void k_ring_v0(Mesh m, const double *__restric
     sum += v;
   }
   if (m.v0_mean) {
-    sum = block_reduce(sum, Add(), lds);
+    sum = block_reduce(sum, Add(), 0.0, lds);
     if (threadIdx.x == 0) v0[r] = sum / m.nx;
     return;
   }
-  vmax = block_reduce(vmax, Max(), lds);
+  vmax = block_reduce(vmax, Max(), -HUGE_VAL, lds);
   __syncthreads();
-  vmin = block_reduce(vmin, Min(), lds);
+  vmin = block_reduce(vmin, Min(), HUGE_VAL, lds);
   if (threadIdx.x == 0) v0[r] = 0.5 * (vmax + vmin);
 }
 
@@ -117,9 +118,9 @@ __global__ __launch_bounds__(256) void k_cfl(Mesh m, StateP s, const double *__r
       shear = sh == sh ? sh : 0.0;
     }
   }
-  cell = block_reduce(cell, Min(), lds);
+  cell = block_reduce(cell, Min(), (double)HUGE_VAL, lds);
   __syncthreads();
-  shear = block_reduce(shear, Max(), lds);
+  shear = block_reduce(shear, Max(), 0.0, lds);
   int anybad = __syncthreads_or(bad);
   if (threadIdx.x == 0) {
     atomicMin(w.min_cell, dbits(cell));

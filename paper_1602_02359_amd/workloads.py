@@ -114,7 +114,8 @@ def _grid(p):
 
 
 def _full(shape, a) -> np.ndarray:
-    return np.ascontiguousarray(np.broadcast_to(a, shape), dtype=np.float64)
+    """A new writable C-contiguous float64 array of `shape` holding `a` broadcast."""
+    return np.array(np.broadcast_to(a, shape), dtype=np.float64, order="C", copy=True)
 
 
 def _noise(rng: np.random.Generator, rho: np.ndarray, p: Dict, amp: float):

@@ -72,7 +72,11 @@ def test_one_step_matches_oracle(name):
     s.fargo_check()
     dt_gpu = s.fargo_get_dt()
     got = s.download()
-    assert dt_gpu == dt_ref, (dt_gpu, dt_ref)
+    if prob.params.get("v0_mode") == "mean":
+        # the azimuthal mean is a sum: its rounding depends on the order
+        assert abs(dt_gpu / dt_ref - 1.0) < 1e-14, (dt_gpu, dt_ref)
+    else:
+        assert dt_gpu == dt_ref, (dt_gpu, dt_ref)
     err = errors(prob, got, ref)
     _say(name, "dt", dt_gpu, "errors", err)
     for k, e in err.items():
@@ -89,7 +93,12 @@ def test_several_steps_match_oracle(name):
     for n in range(5):
         dt_ref = O.step(prob.params, ref)
         s.fargo_step(0.0)
-        assert s.fargo_get_dt() == dt_ref
+        dt = s.fargo_get_dt()
+        if n == 0:
+            assert dt == dt_ref
+        else:
+            # the states now differ by rounding, and so may the time steps
+            assert abs(dt / dt_ref - 1.0) < 1e-12, (n, dt, dt_ref)
     s.fargo_check()
     err = errors(prob, s.download(), ref)
     _say(name, err)
@@ -125,6 +134,12 @@ def test_ring_split_bit_exact(name):
         v0, N, xi = O.ring_split(prob.params, prob.fields["vx"], dt)
         g0, gN, gxi = s.fargo_ring_split(s.state["vx"], dt)
         torch.cuda.synchronize()
+        if prob.params.get("v0_mode") == "mean":
+            # summation order differs: v0 within rounding, N exact away from ties
+            assert np.allclose(g0.cpu().numpy(), v0.ravel(), rtol=1e-14, atol=1e-15)
+            assert np.array_equal(gN.cpu().numpy(), N.ravel())
+            assert np.allclose(gxi.cpu().numpy(), xi.ravel(), rtol=0, atol=1e-12)
+            continue
         assert np.array_equal(g0.cpu().numpy(), v0.ravel())
         assert np.array_equal(gN.cpu().numpy(), N.ravel())
         assert np.array_equal(gxi.cpu().numpy(), xi.ravel())
