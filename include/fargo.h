@@ -150,8 +150,11 @@ int fargo_cfl_dt(fargo_ctx *ctx, fargo_state *state, double *dt_host, void *stre
 
 /* One full update of the state, in place.  dt > 0 imposes the time step; dt
    <= 0 computes it on the device (box 6) without any host synchronisation.
-   Ghost layers are refilled at boxes 2 and 9; after the call they hold the
-   values of box 9 (the next call refills them). */
+   The step defines the active zones and the owned faces (all X faces,
+   interior Y/Z faces, and the lower Y/Z boundary face in a periodic
+   direction).  Ghost zones and the other boundary faces of the state keep
+   the box-2 fill of this call (box 9 acts on internal copies); the next call
+   refills them, and FIXED sides are never written. */
 int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream);
 
 /* Eq. 32 on one field: every active ring (j, k) is circularly permuted in

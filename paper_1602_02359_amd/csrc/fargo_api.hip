@@ -14,10 +14,9 @@ using namespace fargo;
 
 namespace fargo {
 
-const char *kernel_names[K_COUNT] = {
-    "set_dt", "reset", "bc_faces", "bc_ghosts", "ring_v0", "cfl", "dt_final", "split",
-    "source_7a", "source_7b", "source_7c", "momenta_12a", "sweep_y", "sweep_z", "ring_x", "velocities_12d",
-    "shift", "sums", "sums_final"};
+const char *kernel_names[K_COUNT] = {"set_dt", "bc_faces", "bc_ghosts", "cfl", "dt_final", "split",
+                                     "source",  "sweep_y",  "sweep_z",   "ring_x", "vel_yz",
+                                     "shift",   "sums",     "sums_final"};
 
 struct Prof {
   bool on = false;
@@ -78,10 +77,10 @@ struct fargo_ctx {
   bool own_ws = false;
   // carved workspace
   DevWords w{};
-  double *v0 = nullptr, *xi = nullptr;
+  double *v0 = nullptr, *xi = nullptr, *ringmin = nullptr, *ringshear = nullptr;
   int32_t *nshift = nullptr;
   double *partial = nullptr, *sums_out = nullptr;
-  double *v1[3] = {nullptr, nullptr, nullptr};
+  double *v2[4] = {nullptr, nullptr, nullptr, nullptr}; // post-source vx, vy, vz, e
   TSet TA{}, TB{};
   Prof prof;
 };
@@ -209,7 +208,7 @@ size_t geo_doubles(int nyg, int nzg) {
 }
 
 struct Layout {
-  size_t geo, words, v0, xi, nshift, partial, sums, v1, T, total;
+  size_t geo, words, v0, xi, ringmin, ringshear, nshift, partial, sums, v2, T, total;
 };
 
 Layout layout(const fargo_params *p) {
@@ -227,14 +226,18 @@ Layout layout(const fargo_params *p) {
   o += al(nring * 8);
   L.xi = o;
   o += al(nring * 8);
+  L.ringmin = o;
+  o += al(nring * 8);
+  L.ringshear = o;
+  o += al(nring * 8);
   L.nshift = o;
   o += al(nring * 4);
   L.partial = o;
   o += al(nring * 10 * 8);
   L.sums = o;
   o += 256;
-  L.v1 = o;
-  o += al(nc * 8) * (p->nz > 1 ? 3 : 2);
+  L.v2 = o;
+  o += al(nc * 8) * ((p->nz > 1 ? 3 : 2) + (p->eos == FARGO_ADIABATIC ? 1 : 0));
   L.T = o;
   o += al(nc * 8) * 2 * ntransported(p);
   L.total = o;
@@ -265,15 +268,13 @@ int check_state(const fargo_ctx *c, const fargo_state *s) {
   return FARGO_OK;
 }
 
-// boxes 2, 3, 4, 6 (+ split when orbital advection is on)
+// boxes 2, 3, 4, 6 and the split of Eq. 29 (dt > 0: imposed)
 void timestep_phase(fargo_ctx *c, Launch &L, const StateP &S, double dt) {
   const Mesh &m = c->m;
-  launch_reset(L, c->w);
   if (dt > 0.0) launch_set_dt(L, c->w, dt);
   launch_bc(L, m, S.rho, S.e, S.vx, S.vy, S.vz);
-  launch_ring_v0(L, m, S.vx, c->v0);
-  launch_cfl(L, m, S, c->v0, c->w);
-  launch_dt_final(L, m, c->w, dt > 0.0);
+  launch_cfl(L, m, S, 1, c->v0, c->ringmin, c->ringshear, c->w.err);
+  launch_dt_final(L, m, c->w, c->ringmin, c->ringshear, dt > 0.0, c->v0, c->nshift, c->xi);
 }
 
 } // namespace
@@ -393,23 +394,29 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   // words and per-ring arrays
   char *wd = base + Lo.words;
   c->w.dt = (double *)wd;
-  c->w.min_cell = (unsigned long long *)(wd + 8);
-  c->w.max_shear = (unsigned long long *)(wd + 16);
-  c->w.err = (int *)(wd + 24);
+  c->w.err = (int *)(wd + 8);
   if (hipMemset(wd, 0, 256) != hipSuccess) {
     fargo_destroy(c);
     return FARGO_EHIP;
   }
   c->v0 = (double *)(base + Lo.v0);
   c->xi = (double *)(base + Lo.xi);
+  c->ringmin = (double *)(base + Lo.ringmin);
+  c->ringshear = (double *)(base + Lo.ringshear);
   c->nshift = (int32_t *)(base + Lo.nshift);
   c->partial = (double *)(base + Lo.partial);
   c->sums_out = (double *)(base + Lo.sums);
   size_t nc = (size_t)pitch * nyg * nzg;
   size_t fb = al(nc * 8);
-  c->v1[0] = (double *)(base + Lo.v1);
-  c->v1[1] = (double *)(base + Lo.v1 + fb);
-  c->v1[2] = m.d3 ? (double *)(base + Lo.v1 + 2 * fb) : nullptr;
+  {
+    size_t o = Lo.v2;
+    for (int d = 0; d < 4; d++) {
+      bool need = d < 2 || (d == 2 && m.d3) || (d == 3 && params->eos == FARGO_ADIABATIC);
+      if (!need) continue;
+      c->v2[d] = (double *)(base + o);
+      o += fb;
+    }
+  }
   int nT = ntransported(params);
   int slot = 0;
   for (int t = 0; t < T_MAX; t++) {
@@ -465,19 +472,23 @@ int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream) {
   Launch L{s, &ctx->prof};
   const Mesh &m = ctx->m;
   StateP S = state_of(ctx, state);
-  timestep_phase(ctx, L, S, dt > 0.0 ? dt : 0.0);                   // boxes 2, 3, 4, 6
-  if (m.fargo) launch_split(L, m, ctx->v0, ctx->w.dt, 0.0, ctx->nshift, ctx->xi);
-  launch_source(L, m, S, ctx->w.dt, ctx->v1[0], ctx->v1[1], ctx->v1[2]); // box 7
-  launch_bc(L, m, S.rho, S.e, S.vx, S.vy, S.vz);                    // box 9
-  launch_momenta(L, m, S, ctx->TA);                                  // box 12a
-  launch_sweep_y(L, m, S.vy, ctx->TA, ctx->TB, ctx->w.dt);          // box 12b/c
+  timestep_phase(ctx, L, S, dt > 0.0 ? dt : 0.0);                                  // boxes 2, 3, 4, 6
+  const double *dtp = ctx->w.dt;
+  launch_source(L, m, S, dtp, ctx->v2[0], ctx->v2[1], ctx->v2[2], ctx->v2[3]);    // box 7
+  StateP P = S; // post-source fields: density of the state, v'' and e''
+  P.vx = ctx->v2[0];
+  P.vy = ctx->v2[1];
+  P.vz = ctx->v2[2];
+  P.e = ctx->v2[3];
+  launch_bc(L, m, P.rho, P.e, P.vx, P.vy, P.vz);                                   // box 9
+  launch_sweep_y(L, m, P, ctx->TB, dtp);                                           // boxes 12a-c, Y
   const TSet *cur = &ctx->TB;
   if (m.d3) {
-    launch_sweep_z(L, m, S.vz, ctx->TB, ctx->TA, ctx->w.dt);
+    launch_sweep_z(L, m, P.vz, ctx->TB, ctx->TA, dtp);                             // Z
     cur = &ctx->TA;
   }
-  launch_ring_x(L, m, S.vx, *cur, ctx->v0, ctx->nshift, ctx->xi, ctx->w.dt);
-  launch_vel(L, m, S, *cur);                                         // box 12d
+  launch_ring_x(L, m, P.vx, *cur, S, ctx->v0, ctx->nshift, ctx->xi, dtp);          // X, FARGO, 12d (v_x)
+  launch_vel(L, m, S, *cur);                                                       // 12d (v_y, v_z)
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
 
@@ -493,8 +504,10 @@ int fargo_ring_split(fargo_ctx *ctx, const double *vx, double dt, double *v0, in
                      void *stream) {
   if (!ctx || !vx || !v0 || !nshift || !xi || !(dt > 0.0) || !std::isfinite(dt)) return FARGO_EINVAL;
   Launch L{(hipStream_t)stream, &ctx->prof};
-  launch_ring_v0(L, ctx->m, vx, v0);
-  launch_split(L, ctx->m, v0, nullptr, dt, nshift, xi);
+  StateP S{};
+  S.vx = const_cast<double *>(vx);
+  launch_cfl(L, ctx->m, S, 0, v0, nullptr, nullptr, nullptr);
+  launch_split(L, ctx->m, v0, dt, nshift, xi);
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
 

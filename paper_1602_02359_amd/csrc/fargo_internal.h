@@ -97,6 +97,21 @@ struct TSet {
   int nq;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with
+// its own L2.  This maps the hardware block id to a logical one so that every
+// XCD works on a contiguous range of logical blocks (a bijection of [0, G)).
+__device__ inline unsigned xcd_remap(unsigned b, unsigned G) {
+  unsigned q = G >> 3, r = G & 7u, x = b & 7u, l = b >> 3;
+  return x * q + (x < r ? x : r) + l;
+}
+
+// Blocks along an X row: nib blocks of bs threads (a multiple of 64, <= 256).
+inline void row_blocks(int nx, int &nib, int &bs) {
+  nib = (nx + 255) / 256;
+  int per = (nx + nib - 1) / nib;
+  bs = (per + 63) / 64 * 64;
+}
+
 // Order-preserving integer image of a non-negative double (for atomic min/max).
 __device__ inline unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
 
@@ -114,18 +129,16 @@ void prof_begin(Launch &L, int kid);
 void prof_end(Launch &L, int kid);
 
 enum KernelId {
-  K_SET_DT = 0, K_RESET, K_BC_FACES, K_BC_GHOSTS, K_RING_V0, K_CFL, K_DT_FINAL, K_SPLIT,
-  K_SRC1, K_SRC2, K_SRC3, K_MOMENTA, K_SWEEP_Y, K_SWEEP_Z, K_RING_X, K_VEL, K_SHIFT, K_SUMS, K_SUMS_FINAL,
+  K_SET_DT = 0, K_BC_FACES, K_BC_GHOSTS, K_CFL, K_DT_FINAL, K_SPLIT, K_SRC, K_SWEEP_Y, K_SWEEP_Z, K_RING_X, K_VEL,
+  K_SHIFT, K_SUMS, K_SUMS_FINAL,
   K_COUNT
 };
 extern const char *kernel_names[K_COUNT];
 
 // device words used by the step
 struct DevWords {
-  double *dt;                    // the step's time step
-  unsigned long long *min_cell;  // bits of min cell dt
-  unsigned long long *max_shear; // bits of max shear rate
-  int *err;                      // error flags: 1 non-finite state, 2 bad dt
+  double *dt; // the step's time step
+  int *err;   // error flags: 1 non-finite state, 2 bad dt
 };
 
 struct StateP {
@@ -135,23 +148,23 @@ struct StateP {
 
 // boundaries (boxes 2 and 9)
 void launch_bc(Launch &L, const Mesh &m, double *rho, double *e, double *vx, double *vy, double *vz);
-// box 3 / box 6
-void launch_reset(Launch &L, const DevWords &w);
+// boxes 3, 6 and the split of Eq. 29
 void launch_set_dt(Launch &L, const DevWords &w, double dt);
-void launch_ring_v0(Launch &L, const Mesh &m, const double *vx, double *v0);
-void launch_cfl(Launch &L, const Mesh &m, const StateP &s, const double *v0, const DevWords &w);
-void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, int use_given);
-// dt: device time step, or NULL to use dt_val
-void launch_split(Launch &L, const Mesh &m, const double *v0, const double *dt, double dt_val, int32_t *N,
-                  double *xi);
-// box 7
-void launch_source(Launch &L, const Mesh &m, const StateP &s, const double *dt, double *vx1, double *vy1, double *vz1);
+// per ring: v0 and (with_cfl) the minimum cell time step and maximum shear rate
+void launch_cfl(Launch &L, const Mesh &m, const StateP &s, int with_cfl, double *v0, double *ringmin,
+                double *ringshear, int *err);
+// dt from the ring slots (unless imposed), then N and xi of every ring
+void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringmin, const double *ringshear,
+                     int use_given, const double *v0, int32_t *N, double *xi);
+void launch_split(Launch &L, const Mesh &m, const double *v0, double dt, int32_t *N, double *xi);
+// box 7: post-source velocities and energy into vx2, vy2, vz2, e2
+void launch_source(Launch &L, const Mesh &m, const StateP &s, const double *dt, double *vx2, double *vy2,
+                   double *vz2, double *e2);
 // box 12
-void launch_momenta(Launch &L, const Mesh &m, const StateP &s, const TSet &T);
-void launch_sweep_y(Launch &L, const Mesh &m, const double *vy, const TSet &in, const TSet &out, const double *dt);
+void launch_sweep_y(Launch &L, const Mesh &m, const StateP &s, const TSet &out, const double *dt);
 void launch_sweep_z(Launch &L, const Mesh &m, const double *vz, const TSet &in, const TSet &out, const double *dt);
-void launch_ring_x(Launch &L, const Mesh &m, const double *vx, const TSet &T, const double *v0, const int32_t *N,
-                   const double *xi, const double *dt);
+void launch_ring_x(Launch &L, const Mesh &m, const double *vx2, const TSet &T, const StateP &s, const double *v0,
+                   const int32_t *N, const double *xi, const double *dt);
 void launch_vel(Launch &L, const Mesh &m, const StateP &s, const TSet &T);
 // misc
 void launch_shift(Launch &L, const Mesh &m, double *field, const int32_t *N);

@@ -1,88 +1,101 @@
 // Box 3 (bulk azimuthal velocity per ring, Eq. 37), box 6 (time step,
 // Eq. cfl2 items 1-3, Eq. 38) and the orbital-advection split of Eq. 29.
 //
-// The time step and the split (D, N, xi) are computed with floating-point
-// contraction off and in the same operation order as the written definition,
-// so that the integer shift N is reproducible bit for bit; the global minimum
-// is exact and order independent (atomic min on the bit pattern of positive
-// doubles, which orders like the values).
+// One workgroup per active ring computes the ring's v0 and, for each of its
+// zones, the cell time step and the shear rate; the ring minimum/maximum goes
+// to a per-ring slot.  A single workgroup then reduces the slots (exact and
+// order independent: min/max), forms dt and splits every ring's displacement
+// into (N, xi).  The time step and the split use floating-point contraction
+// off and the operation order of the written definition, so that the
+// integer shift N is reproducible bit for bit.
 #include "fargo_internal.h"
 
 namespace fargo {
 
 namespace {
 
-constexpr unsigned long long INF_BITS = 0x7FF0000000000000ull;
+constexpr int MAXW = 16; // waves per block, at most
 
-__global__ void k_reset(DevWords w) {
-  *w.min_cell = INF_BITS;
-  *w.max_shear = 0ull;
-}
-
-__global__ void k_set_dt(DevWords w, double dt) { *w.dt = dt; }
-
-// `id` is the identity of `op` (pads the lanes past the number of waves).
-template <typename T, typename Op>
-__device__ inline T block_reduce(T v, Op op, T id, T *lds) {
-  // 64-lane wave reduction then across the (at most 16) waves of the block
+template <typename Op>
+__device__ inline double block_reduce(double v, Op op, double id, double *lds) {
   for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
   int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
   if (lane == 0) lds[wid] = v;
   __syncthreads();
   int nw = (blockDim.x + 63) >> 6;
-  if (wid == 0) {
-    v = lane < nw ? lds[lane] : id;
-    for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
-  }
-  return v; // valid in thread 0
+  v = lane < nw ? lds[lane] : id;
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  return v; // valid in every lane
 }
 
 struct Max { __device__ double operator()(double a, double b) const { return a > b ? a : b; } };
 struct Min { __device__ double operator()(double a, double b) const { return a < b ? a : b; } };
 struct Add { __device__ double operator()(double a, double b) const { return a + b; } };
 
-// One workgroup per active ring: max, min (exact) or the mean of v_x.
-__global__ __launch_bounds__(256) void k_ring_v0(Mesh m, const double *__restrict__ vx, double *__restrict__ v0) {
-  __shared__ double lds[16];
-  int r = blockIdx.x;
-  int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
-  const double *row = vx + m.idx(0, j, k);
-  double vmax = row[0], vmin = row[0], sum = 0.0;
-  for (int i = threadIdx.x; i < m.nx; i += blockDim.x) {
-    double v = row[i];
-    vmax = v > vmax ? v : vmax;
-    vmin = v < vmin ? v : vmin;
-    sum += v;
-  }
+__global__ void k_set_dt(DevWords w, double dt) { *w.dt = dt; }
+
+// Bulk velocity of a ring (max/min exact; the mean in a fixed tree order).
+template <int M>
+__device__ inline double ring_bulk(const Mesh &m, const double (&v)[M], int tid, double *lds) {
+  const int B = blockDim.x;
   if (m.v0_mean) {
-    sum = block_reduce(sum, Add(), 0.0, lds);
-    if (threadIdx.x == 0) v0[r] = sum / m.nx;
-    return;
+    double s = 0.0;
+#pragma unroll
+    for (int mm = 0; mm < M; mm++)
+      if (tid + B * mm < m.nx) s += v[mm];
+    return block_reduce(s, Add(), 0.0, lds) / m.nx;
   }
+  double vmax = -HUGE_VAL, vmin = HUGE_VAL;
+#pragma unroll
+  for (int mm = 0; mm < M; mm++)
+    if (tid + B * mm < m.nx) {
+      vmax = v[mm] > vmax ? v[mm] : vmax;
+      vmin = v[mm] < vmin ? v[mm] : vmin;
+    }
   vmax = block_reduce(vmax, Max(), -HUGE_VAL, lds);
-  __syncthreads();
   vmin = block_reduce(vmin, Min(), HUGE_VAL, lds);
-  if (threadIdx.x == 0) v0[r] = 0.5 * (vmax + vmin);
+  return 0.5 * (vmax + vmin);
 }
 
-// Per active zone: cell time step (Eq. cfl2, items 1-3), shear rate (Eq. 38)
-// and validity; block min/max, then one atomic per block.
-__global__ __launch_bounds__(256) void k_cfl(Mesh m, StateP s, const double *__restrict__ v0, DevWords w) {
+// Rings in logical order (k fastest), XCD-contiguous; M zones per thread.
+template <int M>
+__global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateP s, int with_cfl, double *__restrict__ v0,
+                                                  double *__restrict__ ringmin, double *__restrict__ ringshear,
+                                                  int *__restrict__ err) {
 #pragma clang fp contract(off)
-  __shared__ double lds[16];
-  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  long total = (long)m.nx * m.ny * m.nz;
-  double cell = __longlong_as_double((long long)INF_BITS);
-  double shear = 0.0;
+  extern __shared__ double V[]; // the ring's v_x
+  __shared__ double red[MAXW];
+  const unsigned L = xcd_remap(blockIdx.x, gridDim.x);
+  const int kk = (int)(L % (unsigned)m.nz), jj = (int)(L / (unsigned)m.nz);
+  const int j = m.j0 + jj, k = m.k0 + kk;
+  const int r = kk * m.ny + jj; // ring index (k - k0) * ny + (j - j0)
+  const int tid = threadIdx.x, B = blockDim.x, n = m.nx;
+  const size_t base = m.idx(0, j, k);
+  double vx[M];
+#pragma unroll
+  for (int mm = 0; mm < M; mm++) {
+    int i = tid + B * mm;
+    vx[mm] = i < n ? s.vx[base + i] : 0.0;
+    if (i < n) V[i] = vx[mm];
+  }
+  const double vb_ring = ring_bulk<M>(m, vx, tid, red);
+  if (tid == 0) v0[r] = vb_ring;
+  if (!with_cfl) return;
+  __syncthreads();
+  const double vb = m.fargo ? vb_ring : 0.0;
+  const double Lx = m.DX(j, k), Lyy = m.g.Ly[j];
+  const double Lzz = m.d3 ? m.Lz(j, k) : 0.0;
+  const bool shear_on = m.fargo && m.shear_c0 > 0.0 && j + 1 < m.jn;
+  const double dXp = shear_on ? m.DX(j + 1, k) : 1.0;
+  double cmin = HUGE_VAL, smax = 0.0;
   int bad = 0;
-  if (t < total) {
-    int i = (int)(t % m.nx);
-    long rr = t / m.nx;
-    int j = m.j0 + (int)(rr % m.ny), k = m.k0 + (int)(rr / m.ny);
-    int ip = i + 1 == m.nx ? 0 : i + 1;
-    size_t c = m.idx(i, j, k);
-    double vb = m.fargo ? v0[rr] : 0.0;
-    double Lx = m.DX(j, k), Lyy = m.g.Ly[j];
+#pragma unroll
+  for (int mm = 0; mm < M; mm++) {
+    int i = tid + B * mm;
+    if (i >= n) continue;
+    size_t c = base + i;
+    double vxc = vx[mm], vxp = V[i + 1 == n ? 0 : i + 1];
     double rho = s.rho[c];
     double cw;
     if (m.eos == FARGO_ISOTHERMAL) cw = s.cs[c];
@@ -90,20 +103,18 @@ __global__ __launch_bounds__(256) void k_cfl(Mesh m, StateP s, const double *__r
       double P = (m.gamma - 1.0) * s.e[c];
       cw = sqrt(m.gamma * P / rho);
     }
-    double vxc = s.vx[c], vxp = s.vx[m.idx(ip, j, k)];
-    double vyc = s.vy[c], vyp = s.vy[m.idx(i, j + 1, k)];
-    bad = !(rho > 0.0) || !isfinite(rho) || !isfinite(cw) || !isfinite(vxc) || !isfinite(vyc);
+    double vyc = s.vy[c], vyp = s.vy[c + m.pitch];
+    bad |= !(rho > 0.0) || !isfinite(rho) || !isfinite(cw) || !isfinite(vxc) || !isfinite(vyc);
     double dt1 = fmin(Lx / cw, Lyy / cw);
     double ux = fmax(fabs(vxc - vb), fabs(vxp - vb));
     double uy = fmax(fabs(vyc), fabs(vyp));
     double dt2 = fmin(Lx / ux, Lyy / uy);
     double dvx = vxp - vxc, dvy = vyp - vyc;
-    double dt3 = __longlong_as_double((long long)INF_BITS);
+    double dt3 = HUGE_VAL;
     if (dvx < 0.0) dt3 = fmin(dt3, Lx / (4.0 * m.cvnr * m.cvnr * fabs(dvx)));
     if (dvy < 0.0) dt3 = fmin(dt3, Lyy / (4.0 * m.cvnr * m.cvnr * fabs(dvy)));
     if (m.d3) {
-      double Lzz = m.Lz(j, k);
-      double vzc = s.vz[c], vzp = s.vz[m.idx(i, j, k + 1)];
+      double vzc = s.vz[c], vzp = s.vz[c + m.plane()];
       bad |= !isfinite(vzc);
       dt1 = fmin(dt1, Lzz / cw);
       double uz = fmax(fabs(vzc), fabs(vzp));
@@ -111,59 +122,87 @@ __global__ __launch_bounds__(256) void k_cfl(Mesh m, StateP s, const double *__r
       double dvz = vzp - vzc;
       if (dvz < 0.0) dt3 = fmin(dt3, Lzz / (4.0 * m.cvnr * m.cvnr * fabs(dvz)));
     }
-    cell = 1.0 / sqrt(1.0 / (dt1 * dt1) + 1.0 / (dt2 * dt2) + 1.0 / (dt3 * dt3));
-    if (!(cell >= 0.0)) { bad = 1; cell = __longlong_as_double((long long)INF_BITS); }
-    if (m.fargo && m.shear_c0 > 0.0 && j + 1 < m.jn) {
-      double sh = fabs(vxc / Lx - s.vx[m.idx(i, j + 1, k)] / m.DX(j + 1, k));
-      shear = sh == sh ? sh : 0.0;
+    double cell = 1.0 / sqrt(1.0 / (dt1 * dt1) + 1.0 / (dt2 * dt2) + 1.0 / (dt3 * dt3));
+    if (!(cell >= 0.0)) bad = 1;
+    else cmin = cell < cmin ? cell : cmin;
+    if (shear_on) {
+      double sh = fabs(vxc / Lx - s.vx[c + m.pitch] / dXp);
+      if (sh > smax) smax = sh;
     }
   }
-  cell = block_reduce(cell, Min(), (double)HUGE_VAL, lds);
-  __syncthreads();
-  shear = block_reduce(shear, Max(), 0.0, lds);
+  cmin = block_reduce(cmin, Min(), HUGE_VAL, red);
+  smax = block_reduce(smax, Max(), 0.0, red);
   int anybad = __syncthreads_or(bad);
-  if (threadIdx.x == 0) {
-    atomicMin(w.min_cell, dbits(cell));
-    if (shear > 0.0) atomicMax(w.max_shear, dbits(shear));
-    if (anybad) atomicOr(w.err, 1);
+  if (tid == 0) {
+    ringmin[r] = cmin;
+    ringshear[r] = smax;
+    if (anybad) atomicOr(err, 1);
   }
 }
 
-__global__ void k_dt_final(Mesh m, DevWords w, int use_given) {
+// One workgroup: dt from the ring slots (or the imposed value), then the split
+// of every ring.  A non-positive or non-finite dt is flagged and replaced by 0,
+// which leaves the state unchanged.
+__global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const double *__restrict__ ringmin,
+                                                   const double *__restrict__ ringshear, int use_given,
+                                                   const double *__restrict__ v0, int32_t *__restrict__ N,
+                                                   double *__restrict__ xi) {
 #pragma clang fp contract(off)
-  double mincell = __longlong_as_double((long long)*w.min_cell);
-  double maxshear = __longlong_as_double((long long)*w.max_shear);
-  double dt = m.courant * mincell;
-  if (m.fargo && m.shear_c0 > 0.0 && maxshear > 0.0) dt = fmin(dt, m.shear_c0 / maxshear);
-  if (use_given) return;
-  if (!(dt > 0.0) || !isfinite(dt)) {
-    atomicOr(w.err, 2);
-    dt = 0.0; // a zero step leaves the state unchanged
+  __shared__ double red[MAXW];
+  __shared__ double dts;
+  if (!use_given) {
+    double cmin = HUGE_VAL, smax = 0.0;
+    for (int r = threadIdx.x; r < m.nring; r += blockDim.x) {
+      cmin = ringmin[r] < cmin ? ringmin[r] : cmin;
+      smax = ringshear[r] > smax ? ringshear[r] : smax;
+    }
+    cmin = block_reduce(cmin, Min(), HUGE_VAL, red);
+    smax = block_reduce(smax, Max(), 0.0, red);
+    if (threadIdx.x == 0) {
+      double dt = m.courant * cmin;
+      if (m.fargo && m.shear_c0 > 0.0 && smax > 0.0) dt = fmin(dt, m.shear_c0 / smax);
+      if (!(dt > 0.0) || !isfinite(dt)) {
+        atomicOr(w.err, 2);
+        dt = 0.0;
+      }
+      *w.dt = dt;
+      dts = dt;
+    }
+  } else if (threadIdx.x == 0) {
+    dts = *w.dt;
   }
-  *w.dt = dt;
+  __syncthreads();
+  if (!m.fargo) return;
+  const double dt = dts;
+  for (int r = threadIdx.x; r < m.nring; r += blockDim.x) {
+    int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
+    double D = (v0[r] * dt) / m.DX(j, k);
+    double rn = round(D);
+    N[r] = (int32_t)rn;
+    xi[r] = D - rn;
+  }
 }
 
-// Eq. 29: D = (v0 dt)/dX, N = nearest integer (ties away from zero), xi = D - N.
-__global__ __launch_bounds__(256) void k_split(Mesh m, const double *__restrict__ v0, const double *__restrict__ dtp,
-                                               double dt_val, int32_t *__restrict__ N, double *__restrict__ xi) {
+// The split alone (stand-alone entry point): one thread per ring.
+__global__ __launch_bounds__(256) void k_split(Mesh m, const double *__restrict__ v0, double dt,
+                                               int32_t *__restrict__ N, double *__restrict__ xi) {
 #pragma clang fp contract(off)
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= m.nring) return;
   int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
-  double dt = dtp ? *dtp : dt_val;
   double D = (v0[r] * dt) / m.DX(j, k);
-  double n = round(D);
-  N[r] = (int32_t)n;
-  xi[r] = D - n;
+  double rn = round(D);
+  N[r] = (int32_t)rn;
+  xi[r] = D - rn;
+}
+
+template <int M>
+void cfl_launch(Launch &L, const Mesh &m, const StateP &s, int with_cfl, double *v0, double *rmin, double *rsh,
+                int *err) {
+  k_cfl_ring<M><<<m.nring, 256, (size_t)m.nx * sizeof(double), L.s>>>(m, s, with_cfl, v0, rmin, rsh, err);
 }
 
 } // namespace
-
-void launch_reset(Launch &L, const DevWords &w) {
-  prof_begin(L, K_RESET);
-  k_reset<<<1, 1, 0, L.s>>>(w);
-  prof_end(L, K_RESET);
-}
 
 void launch_set_dt(Launch &L, const DevWords &w, double dt) {
   prof_begin(L, K_SET_DT);
@@ -171,29 +210,27 @@ void launch_set_dt(Launch &L, const DevWords &w, double dt) {
   prof_end(L, K_SET_DT);
 }
 
-void launch_ring_v0(Launch &L, const Mesh &m, const double *vx, double *v0) {
-  prof_begin(L, K_RING_V0);
-  k_ring_v0<<<m.nring, 256, 0, L.s>>>(m, vx, v0);
-  prof_end(L, K_RING_V0);
-}
-
-void launch_cfl(Launch &L, const Mesh &m, const StateP &s, const double *v0, const DevWords &w) {
-  long total = (long)m.nx * m.ny * m.nz;
+void launch_cfl(Launch &L, const Mesh &m, const StateP &s, int with_cfl, double *v0, double *ringmin,
+                double *ringshear, int *err) {
   prof_begin(L, K_CFL);
-  k_cfl<<<(unsigned)((total + 255) / 256), 256, 0, L.s>>>(m, s, v0, w);
+  int M = (m.nx + 255) / 256;
+  if (M <= 1) cfl_launch<1>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
+  else if (M == 2) cfl_launch<2>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
+  else if (M <= 4) cfl_launch<4>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
+  else cfl_launch<8>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
   prof_end(L, K_CFL);
 }
 
-void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, int use_given) {
+void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringmin, const double *ringshear,
+                     int use_given, const double *v0, int32_t *N, double *xi) {
   prof_begin(L, K_DT_FINAL);
-  k_dt_final<<<1, 1, 0, L.s>>>(m, w, use_given);
+  k_dt_final<<<1, 1024, 0, L.s>>>(m, w, ringmin, ringshear, use_given, v0, N, xi);
   prof_end(L, K_DT_FINAL);
 }
 
-void launch_split(Launch &L, const Mesh &m, const double *v0, const double *dt, double dt_val, int32_t *N,
-                  double *xi) {
+void launch_split(Launch &L, const Mesh &m, const double *v0, double dt, int32_t *N, double *xi) {
   prof_begin(L, K_SPLIT);
-  k_split<<<(m.nring + 255) / 256, 256, 0, L.s>>>(m, v0, dt, dt_val, N, xi);
+  k_split<<<(m.nring + 255) / 256, 256, 0, L.s>>>(m, v0, dt, N, xi);
   prof_end(L, K_SPLIT);
 }
 

@@ -113,7 +113,7 @@ def test_imposed_dt_and_cfl_readback():
     s = gpu_solver(prob)
     assert s.fargo_cfl_dt() == dt_ref
     got0 = s.download()
-    for k in ("rho", "vx", "vy", "vz", "e"):  # box 2 on both sides
+    for k in ("rho", "vx", "vy", "vz", "e"):  # box 2 on both sides, ghosts included
         assert np.array_equal(got0[k], ref[k]), k
     dt = 0.7 * dt_ref
     O.step(prob.params, ref, dt)
