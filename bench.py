@@ -11,7 +11,10 @@ region starts.
 Prints one JSON line: cell-updates/s, ms/step, the roofline of the dominant
 kernel (algorithmic bytes per launch over its average duration from HIP
 events recorded on the launch stream during the timed steps) and the CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  The FP32-bulk
+variant (FP32 state, FP64 time step, ring split and sums) is then timed on
+the same workload and reported with its normwise error against the FP64 run
+after the same number of steps from the same initial state.
 """
 import argparse
 import json
@@ -29,27 +32,24 @@ NGH = 3
 
 
 def words_per_unit(p):
-    """Algorithmic FP64 words moved per zone by each kernel (each input read
-    once, each output written once), and the zones one launch processes."""
+    """Algorithmic words (8 bytes in FP64, 4 in FP32 bulk) moved per zone by
+    each kernel of the step (each input read once, each output written once),
+    and the zones one launch processes."""
     d3 = p["nz"] > 1
-    adi = p["eos"] == "adi"
-    nT = 5 + (2 if d3 else 0) + (1 if adi else 0)
+    adi = 1 if p["eos"] == "adi" else 0
+    nT = 5 + (2 if d3 else 0) + adi
     nvel = 3 if d3 else 2
     act = p["nx"] * p["ny"] * p["nz"]
-    ghost_all = p["nx"] * (p["ny"] + 2 * NGH) * ((p["nz"] + 2 * NGH) if d3 else 1)
+    whole = p["nx"] * (p["ny"] + 2 * NGH) * ((p["nz"] + 2 * NGH) if d3 else 1)
     y_rows = p["nx"] * p["ny"] * ((p["nz"] + 4) if d3 else 1)
     return {
         # name: (words per zone, zones per launch)
-        "ring_v0": (1, act),
-        "cfl": (2 + nvel, act),                       # rho, cs|e, velocities
-        "source_7a": (3 + nvel + nvel, act),          # rho, cs|e, pot, v -> v'
-        "source_7b": (1 + nvel + nvel + (2 if adi else 0), act),
-        "source_7c": ((nvel + 2) if adi else 0, act),
-        "momenta_12a": (1 + nvel + (1 if adi else 0) + nT, ghost_all),
-        "sweep_y": (2 * nT + 1, y_rows),
-        "sweep_z": ((2 * nT + 1) if d3 else 0, act),
-        "ring_x": (2 * nT + 1, act),
-        "velocities_12d": (nT + nvel + 1 + (1 if adi else 0), act),
+        "cfl": (2 + nvel, act),                              # rho, cs|e, velocities
+        "source": ((3 + nvel) + (nvel + adi), whole),        # rho, cs|e, pot, v -> v'', e''
+        "sweep_y": ((1 + nvel + adi) + nT, y_rows),          # rho, v'', e'' -> T (momenta formed on the fly)
+        "sweep_z": ((2 * nT + 1) if d3 else 0, act),         # T, v_z -> T
+        "ring_x": ((nT + 1) + (2 + adi + 2 + (2 if d3 else 0)), act),  # T, v_x -> rho, v_x, e, Pi_y, Pi_z
+        "vel_yz": ((1 + 2 + (2 if d3 else 0)) + (nvel - 1), act),      # rho, Pi_y, Pi_z -> v_y, v_z
     }
 
 
@@ -133,6 +133,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="sph3d", choices=["sph3d", "cyl3d_planet", "disk2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variant", action="store_true", help="skip the FP32-bulk variant")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 GiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -155,49 +156,94 @@ def main():
         torch.cuda.empty_cache()
     prob = W.make(args.config)
     p = prob.params
-    print("workload %s %dx%dx%d, building state" % (args.config, p["nx"], p["ny"], p["nz"]), file=sys.stderr,
-          flush=True)
-    solver = F.Solver(p)
-    solver.upload(prob.fields)
-    for _ in range(args.warmup):
-        solver.fargo_step(0.0)
-    solver.fargo_check()
-    torch.cuda.synchronize()
-    solver.fargo_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        solver.fargo_step(0.0)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    timings = solver.fargo_timings()
-    solver.fargo_profile_enable(False)
-    solver.fargo_check()
-    dt_last = solver.fargo_get_dt()
-    cells = prob.active_cells
-    value = cells * args.steps / el
-    ms = 1e3 * el / args.steps
-    print("timed %d steps: %.3f ms/step, %.3e cell-updates/s, dt %.6g" % (args.steps, ms, value, dt_last),
-          file=sys.stderr, flush=True)
-
     wpu = words_per_unit(p)
-    kern = {}
-    for name, (cnt, tot) in timings.items():
-        avg = tot / cnt
-        entry = {"launches": cnt, "avg_ms": avg}
-        if name in wpu and wpu[name][0] > 0:
-            b = 8.0 * wpu[name][0] * wpu[name][1]
-            entry["alg_bytes"] = b
-            entry["GBs"] = b / (avg * 1e-3) / 1e9
-        kern[name] = entry
-        print("  %-16s %6d launches  %9.4f ms avg  %s" % (name, cnt, avg,
-              ("%.0f GB/s" % entry["GBs"]) if "GBs" in entry else ""), file=sys.stderr)
-    dom = max((k for k in kern if "alg_bytes" in kern[k]), key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    cells = prob.active_cells
+
+    def run(precision):
+        """Warm up, then time args.steps steps with per-kernel HIP events on
+        the launch stream; returns the solver (state kept) and the figures."""
+        print("workload %s %dx%dx%d %s, building state" % (args.config, p["nx"], p["ny"], p["nz"], precision),
+              file=sys.stderr, flush=True)
+        solver = F.Solver(dict(p, precision=precision))
+        solver.upload(prob.fields)
+        for _ in range(args.warmup):
+            solver.fargo_step(0.0)
+        solver.fargo_check()
+        torch.cuda.synchronize()
+        solver.fargo_profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            solver.fargo_step(0.0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        timings = solver.fargo_timings()
+        solver.fargo_profile_enable(False)
+        solver.fargo_check()
+        dt_last = solver.fargo_get_dt()
+        value = cells * args.steps / el
+        ms = 1e3 * el / args.steps
+        print("timed %d steps: %.3f ms/step, %.3e cell-updates/s, dt %.6g" % (args.steps, ms, value, dt_last),
+              file=sys.stderr, flush=True)
+        wb = 4.0 if precision == "fp32" else 8.0
+        kern = {}
+        for name, (cnt, tot) in timings.items():
+            avg = tot / cnt
+            entry = {"launches": cnt, "avg_ms": avg}
+            if name in wpu and wpu[name][0] > 0:
+                b = wb * wpu[name][0] * wpu[name][1]
+                entry["alg_bytes"] = b
+                entry["GBs"] = b / (avg * 1e-3) / 1e9
+            kern[name] = entry
+            print("  %-16s %6d launches  %9.4f ms avg  %s" % (name, cnt, avg,
+                  ("%.0f GB/s" % entry["GBs"]) if "GBs" in entry else ""), file=sys.stderr)
+        dom = max((k for k in kern if "alg_bytes" in kern[k]),
+                  key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+        step_alg = sum(wb * w * n for (w, n) in wpu.values())
+        return solver, {"value": value, "ms": ms, "kern": kern, "dom": dom, "step_alg": step_alg}
+
+    solver, r64 = run("fp64")
+    value, ms, kern, dom, step_alg = r64["value"], r64["ms"], r64["kern"], r64["dom"], r64["step_alg"]
     achieved = kern[dom]["GBs"]
-    step_alg = sum(8.0 * w * n for (w, n) in wpu.values())
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "alg_bytes_per_launch": kern[dom]["alg_bytes"], "avg_launch_ms": kern[dom]["avg_ms"]}
+
+    variants = {}
+    if not args.no_variant:
+        s32, r32 = run("fp32")
+        # normwise error of the FP32-bulk state against the FP64 state after
+        # the same warmup + timed steps (velocities scaled by the largest speed)
+        nx = p["nx"]
+        d3 = p["nz"] > 1
+        ks = slice(NGH, NGH + p["nz"]) if d3 else slice(0, 1)
+        js = slice(NGH, NGH + p["ny"])
+        vnames = ("vx", "vy", "vz") if d3 else ("vx", "vy")
+        vmax = max(float(solver.state[k][ks, js, :nx].abs().max()) for k in vnames)
+        err = {}
+        for k in ("rho", "e") + vnames:
+            if solver.state.get(k) is None:
+                continue
+            a = s32.state[k][ks, js, :nx].double()
+            b = solver.state[k][ks, js, :nx]
+            den = vmax if k.startswith("v") else float(b.abs().max())
+            err[k] = float((a - b).abs().max()) / den
+            del a
+        dk = r32["dom"]
+        variants["fp32_bulk"] = {
+            "value": r32["value"], "unit": "cell-updates/s", "ms_per_step": r32["ms"],
+            "speedup_vs_fp64": r32["value"] / value,
+            "error_vs_fp64": {k: float("%.3g" % v) for k, v in err.items()},
+            "steps_compared": args.warmup + args.steps,
+            "step_alg_bytes_per_cell": r32["step_alg"] / cells,
+            "dominant_kernel": {"kernel": dk, "avg_ms": r32["kern"][dk]["avg_ms"],
+                                "GBs": round(r32["kern"][dk]["GBs"], 1)},
+            "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                        for k, v in r32["kern"].items()},
+        }
+        print("  fp32 bulk: %.3e cell-updates/s (x%.2f), error vs fp64 %s" % (
+            r32["value"], r32["value"] / value, variants["fp32_bulk"]["error_vs_fp64"]), file=sys.stderr)
+        del s32
     del solver
     torch.cuda.empty_cache()
 
@@ -237,6 +283,7 @@ def main():
                     for k, v in kern.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "variants": variants,
     }
     print(json.dumps(out), flush=True)
 

@@ -14,7 +14,8 @@
  *
  * Mesh and storage (Sect. 2.2-2.3, Tab. "corresp", Sect. 4.1):
  *   X = azimuth (periodic, uniform, no ghosts), Y = radius, Z = z or colatitude.
- *   Every field is a device array [nz_g][ny_g][pitch] of double, X fastest,
+ *   Every field is a device array [nz_g][ny_g][pitch] of the state element
+ *   type (double, or float with FARGO_FP32_BULK; see `precision`), X fastest,
  *   with ny_g = ny + 6, nz_g = nz + 6 (3D) or 1 (2D, nz == 1) and pitch from
  *   fargo_layout (a multiple of 64 elements, >= nx; columns nx..pitch-1 are
  *   padding, never read or written).  Three ghost layers in Y and Z.
@@ -80,8 +81,16 @@ extern "C" {
 /* bulk azimuthal velocity of each ring (box 3): Eq. 37 or the azimuthal mean */
 #define FARGO_V0_MINMAX 0
 #define FARGO_V0_MEAN 1
-/* storage precision of the evolved state */
+/* precision of the evolved state (Sect. 6 discusses single vs double):
+   FARGO_FP64: every field is double and all arithmetic is FP64.
+   FARGO_FP32_BULK: every field (rho, v, e, cs, pot) is float and the bulk
+   arithmetic of boxes 2, 7, 9 and 12 is FP32; the steps whose accuracy needs
+   it stay FP64: the time step (box 6, from the stored values), each ring's
+   bulk velocity v0 and the split of Eq. 29 into N and xi, and the conserved
+   sums.  The geometric coefficients are FP64 tables rounded to FP32 where
+   they enter bulk arithmetic. */
 #define FARGO_FP64 0
+#define FARGO_FP32_BULK 1
 
 typedef struct {
   int32_t abi_version;     /* FARGO_ABI_VERSION */
@@ -101,16 +110,18 @@ typedef struct {
   int32_t fargo;           /* 1: orbital advection (Sect. 3.5.1), 0: plain transport */
   int32_t v0_mode;         /* FARGO_V0_MINMAX or FARGO_V0_MEAN */
   int32_t bc[4];           /* boundary kind of the ymin, ymax, zmin, zmax sides */
-  int32_t precision;       /* FARGO_FP64 */
+  int32_t precision;       /* FARGO_FP64 or FARGO_FP32_BULK */
 } fargo_params;
 
-/* Device pointers to the state, each laid out as described above.  rho, vx,
+/* Device pointers to the state, each laid out as described above, with
+   elements of type double (FARGO_FP64) or float (FARGO_FP32_BULK).  rho, vx,
    vy are always required; vz in 3D only (NULL in 2D); e (volumic internal
    energy) for FARGO_ADIABATIC, cs (isothermal sound speed, static) for
-   FARGO_ISOTHERMAL; pot (static potential, ghosts included) always. */
+   FARGO_ISOTHERMAL; pot (static potential, ghosts included) always.
+   Arrays must be aligned to their element size. */
 typedef struct {
-  double *rho, *vx, *vy, *vz, *e;
-  const double *cs, *pot;
+  void *rho, *vx, *vy, *vz, *e;
+  const void *cs, *pot;
 } fargo_state;
 
 typedef struct fargo_ctx fargo_ctx;
@@ -159,16 +170,18 @@ int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream);
 
 /* Eq. 32 on one field: every active ring (j, k) is circularly permuted in
    place, Q_i <- Q_{(i - N) mod nx}, with N = nshift[(k - k0)*ny + (j - j0)]
-   read from a device array of ny*nz int32 (k0 = 3 in 3D, 0 in 2D).  Ghost
-   rows are not touched.  Bit-exact (a pure permutation). */
-int fargo_shift(fargo_ctx *ctx, double *field, const int32_t *nshift, void *stream);
+   read from a device array of ny*nz int32 (k0 = 3 in 3D, 0 in 2D).  The
+   field has the state element type of the context.  Ghost rows are not
+   touched.  Bit-exact (a pure permutation). */
+int fargo_shift(fargo_ctx *ctx, void *field, const int32_t *nshift, void *stream);
 
 /* Box 3 and the split of Eq. 29 for a given dt, on active rings: v0 (Eq. 37
    or mean), N = nearest integer to D = (v0 dt)/dX with ties away from zero,
-   xi = D - N.  Outputs are device arrays of ny*nz elements indexed as in
+   xi = D - N, all in FP64 (vx has the state element type and is read
+   exactly).  Outputs are device arrays of ny*nz elements indexed as in
    fargo_shift.  dX is the azimuthal zone length at the v_phi face centre
    (dx, r dphi or r sin(theta) dphi). */
-int fargo_ring_split(fargo_ctx *ctx, const double *vx, double dt, double *v0, int32_t *nshift, double *xi,
+int fargo_ring_split(fargo_ctx *ctx, const void *vx, double dt, double *v0, int32_t *nshift, double *xi,
                      void *stream);
 
 /* Conserved sums over active zones (waits for the stream): out[0] = mass

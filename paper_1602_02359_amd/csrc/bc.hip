@@ -14,8 +14,9 @@ namespace fargo {
 
 namespace {
 
+template <typename R>
 struct Cen {
-  double *p[4];
+  R *p[4];
   int n;
 };
 
@@ -23,21 +24,23 @@ __device__ inline size_t at(const Mesh &m, int dir, int i, int a, int b) {
   return dir == 1 ? m.idx(i, a, b) : m.idx(i, b, a);
 }
 
-__global__ __launch_bounds__(256) void k_bc_faces(Mesh m, int dir, int side, int kind, double *vn) {
+template <typename R>
+__global__ __launch_bounds__(256) void k_bc_faces(Mesh m, int dir, int side, int kind, R *vn) {
   int lo = dir == 1 ? m.j0 : m.k0, hi = dir == 1 ? m.jn : m.kn;
   int nb = dir == 1 ? m.nzg : m.nyg;
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long)m.nx * nb) return;
   int i = (int)(t % m.nx), b = (int)(t / m.nx);
   int bf = side == 0 ? lo : hi;
-  double v;
-  if (kind == FARGO_BC_REFLECT) v = 0.0;
+  R v;
+  if (kind == FARGO_BC_REFLECT) v = R(0);
   else if (kind == FARGO_BC_OUTFLOW) v = vn[at(m, dir, i, side == 0 ? lo + 1 : hi - 1, b)];
   else v = vn[at(m, dir, i, lo, b)]; // periodic image of the lower boundary face (side 1 only)
   vn[at(m, dir, i, bf, b)] = v;
 }
 
-__global__ __launch_bounds__(256) void k_bc_ghosts(Mesh m, int dir, int side, int kind, Cen cen, double *vn) {
+template <typename R>
+__global__ __launch_bounds__(256) void k_bc_ghosts(Mesh m, int dir, int side, int kind, Cen<R> cen, R *vn) {
   int lo = dir == 1 ? m.j0 : m.k0, hi = dir == 1 ? m.jn : m.kn;
   int nb = dir == 1 ? m.nzg : m.nyg;
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -46,18 +49,18 @@ __global__ __launch_bounds__(256) void k_bc_ghosts(Mesh m, int dir, int side, in
   long r = t / m.nx;
   int b = (int)(r % nb), g = (int)(r / nb);
   int dst, src, fdst = -1, fsrc = -1;
-  double sgn = 1.0;
+  R sgn = R(1);
   if (side == 0) {
     dst = lo - 1 - g;
     fdst = lo - 1 - g;
     if (kind == FARGO_BC_PERIODIC) { src = hi - 1 - g; fsrc = hi - 1 - g; }
-    else if (kind == FARGO_BC_REFLECT) { src = lo + g; fsrc = lo + 1 + g; sgn = -1.0; }
+    else if (kind == FARGO_BC_REFLECT) { src = lo + g; fsrc = lo + 1 + g; sgn = R(-1); }
     else { src = lo; fsrc = lo; }
   } else {
     dst = hi + g;
     if (g < NGH - 1) fdst = hi + 1 + g;
     if (kind == FARGO_BC_PERIODIC) { src = lo + g; fsrc = lo + 1 + g; }
-    else if (kind == FARGO_BC_REFLECT) { src = hi - 1 - g; fsrc = hi - 1 - g; sgn = -1.0; }
+    else if (kind == FARGO_BC_REFLECT) { src = hi - 1 - g; fsrc = hi - 1 - g; sgn = R(-1); }
     else { src = hi - 1; fsrc = hi; }
   }
   size_t d = at(m, dir, i, dst, b), s = at(m, dir, i, src, b);
@@ -65,7 +68,8 @@ __global__ __launch_bounds__(256) void k_bc_ghosts(Mesh m, int dir, int side, in
   if (fdst >= 0) vn[at(m, dir, i, fdst, b)] = sgn * vn[at(m, dir, i, fsrc, b)];
 }
 
-void one_dir(Launch &L, const Mesh &m, int dir, const Cen &cen, double *vn) {
+template <typename R>
+void one_dir(Launch &L, const Mesh &m, int dir, const Cen<R> &cen, R *vn) {
   int nb = dir == 1 ? m.nzg : m.nyg;
   int k0 = dir == 1 ? 0 : 2;
   long nf = (long)m.nx * nb;
@@ -74,7 +78,7 @@ void one_dir(Launch &L, const Mesh &m, int dir, const Cen &cen, double *vn) {
     if (kind == FARGO_BC_FIXED) continue;
     if (kind == FARGO_BC_PERIODIC && side == 0) continue; // the lower face is owned by the step
     prof_begin(L, K_BC_FACES);
-    k_bc_faces<<<(unsigned)((nf + 255) / 256), 256, 0, L.s>>>(m, dir, side, kind, vn);
+    k_bc_faces<R><<<(unsigned)((nf + 255) / 256), 256, 0, L.s>>>(m, dir, side, kind, vn);
     prof_end(L, K_BC_FACES);
   }
   long ng = nf * NGH;
@@ -82,27 +86,31 @@ void one_dir(Launch &L, const Mesh &m, int dir, const Cen &cen, double *vn) {
     int kind = m.bc[k0 + side];
     if (kind == FARGO_BC_FIXED) continue;
     prof_begin(L, K_BC_GHOSTS);
-    k_bc_ghosts<<<(unsigned)((ng + 255) / 256), 256, 0, L.s>>>(m, dir, side, kind, cen, vn);
+    k_bc_ghosts<R><<<(unsigned)((ng + 255) / 256), 256, 0, L.s>>>(m, dir, side, kind, cen, vn);
     prof_end(L, K_BC_GHOSTS);
   }
 }
 
 } // namespace
 
-void launch_bc(Launch &L, const Mesh &m, double *rho, double *e, double *vx, double *vy, double *vz) {
-  Cen cy{};
+template <typename R>
+void launch_bc(Launch &L, const Mesh &m, R *rho, R *e, R *vx, R *vy, R *vz) {
+  Cen<R> cy{};
   cy.p[cy.n++] = rho;
   if (e) cy.p[cy.n++] = e;
   cy.p[cy.n++] = vx;
   if (m.d3) cy.p[cy.n++] = vz;
   one_dir(L, m, 1, cy, vy);
   if (!m.d3) return;
-  Cen cz{};
+  Cen<R> cz{};
   cz.p[cz.n++] = rho;
   if (e) cz.p[cz.n++] = e;
   cz.p[cz.n++] = vx;
   cz.p[cz.n++] = vy;
   one_dir(L, m, 2, cz, vz);
 }
+
+template void launch_bc<double>(Launch &, const Mesh &, double *, double *, double *, double *, double *);
+template void launch_bc<float>(Launch &, const Mesh &, float *, float *, float *, float *, float *);
 
 } // namespace fargo

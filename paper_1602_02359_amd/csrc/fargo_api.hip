@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/fargo.h: parameter checks, the
 // FP64 geometric tables of Appendix A, workspace layout and the sequence of
-// kernels of one full update (Sect. 3, Fig. "flowchart").
+// kernels of one full update (Sect. 3, Fig. "flowchart"), instantiated for
+// the FP64 state and for the FP32-bulk state.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -80,8 +81,12 @@ struct fargo_ctx {
   double *v0 = nullptr, *xi = nullptr, *ringmin = nullptr, *ringshear = nullptr;
   int32_t *nshift = nullptr;
   double *partial = nullptr, *sums_out = nullptr;
-  double *v2[4] = {nullptr, nullptr, nullptr, nullptr}; // post-source vx, vy, vz, e
-  TSet TA{}, TB{};
+  size_t esize = 8;                                    // bytes per state element
+  void *v2[4] = {nullptr, nullptr, nullptr, nullptr}; // post-source vx, vy, vz, e
+  // transport buffers (box 12): slot t of set A / B, and the packed order of
+  // the non-density quantities
+  void *TA[T_MAX] = {}, *TB[T_MAX] = {};
+  int tq[T_MAX] = {}, nq = 0;
   Prof prof;
 };
 
@@ -105,8 +110,14 @@ int check_params(const fargo_params *p) {
   if (p->nz > 1 && (p->bc[2] == FARGO_BC_PERIODIC) != (p->bc[3] == FARGO_BC_PERIODIC)) return FARGO_EINVAL;
   if (p->geometry != FARGO_CARTESIAN && p->bc[0] == FARGO_BC_PERIODIC) return FARGO_EINVAL;
   if (p->geometry == FARGO_SPHERICAL && p->bc[2] == FARGO_BC_PERIODIC) return FARGO_EINVAL;
-  if (p->precision != FARGO_FP64) return FARGO_EUNSUPPORTED;
+  if (p->precision != FARGO_FP64 && p->precision != FARGO_FP32_BULK) return FARGO_EINVAL;
   if (p->nx > 2048) return FARGO_EUNSUPPORTED; // ring kernel keeps a ring per workgroup in 64 KB of LDS
+  {
+    // kernels address fields with 32-bit element offsets
+    size_t pitch = (size_t)(p->nx + 63) / 64 * 64;
+    size_t cells = pitch * (size_t)(p->ny + 2 * NGH) * (size_t)(p->nz > 1 ? p->nz + 2 * NGH : 1);
+    if (cells >= ((size_t)1 << 31)) return FARGO_EUNSUPPORTED;
+  }
   int nyg = p->ny + 2 * NGH, nzg = p->nz > 1 ? p->nz + 2 * NGH : 1;
   for (int j = 0; j < nyg; j++)
     if (!(p->ymin[j + 1] > p->ymin[j]) || !std::isfinite(p->ymin[j + 1])) return FARGO_EINVAL;
@@ -126,6 +137,8 @@ void dims(const fargo_params *p, int &pitch, int &nyg, int &nzg) {
 int ntransported(const fargo_params *p) { return 5 + (p->nz > 1 ? 2 : 0) + (p->eos == FARGO_ADIABATIC ? 1 : 0); }
 
 inline size_t al(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t elem_bytes(const fargo_params *p) { return p->precision == FARGO_FP32_BULK ? 4 : 8; }
 
 // host tables, in the order of GeoTables
 struct HostGeo {
@@ -216,6 +229,7 @@ Layout layout(const fargo_params *p) {
   dims(p, pitch, nyg, nzg);
   size_t nc = (size_t)pitch * nyg * nzg;
   size_t nring = (size_t)p->ny * p->nz;
+  size_t eb = elem_bytes(p);
   Layout L{};
   size_t o = 0;
   L.geo = o;
@@ -237,9 +251,9 @@ Layout layout(const fargo_params *p) {
   L.sums = o;
   o += 256;
   L.v2 = o;
-  o += al(nc * 8) * ((p->nz > 1 ? 3 : 2) + (p->eos == FARGO_ADIABATIC ? 1 : 0));
+  o += al(nc * eb) * ((p->nz > 1 ? 3 : 2) + (p->eos == FARGO_ADIABATIC ? 1 : 0));
   L.T = o;
-  o += al(nc * 8) * 2 * ntransported(p);
+  o += al(nc * eb) * 2 * ntransported(p);
   L.total = o;
   return L;
 }
@@ -248,17 +262,29 @@ int hip_ok(hipError_t e) { return e == hipSuccess ? FARGO_OK : FARGO_EHIP; }
 
 // Pointers the configuration does not use are dropped, so that no kernel
 // touches a field (or a transport buffer) that does not exist.
-StateP state_of(const fargo_ctx *c, const fargo_state *s) {
-  StateP S;
-  S.rho = s->rho;
-  S.vx = s->vx;
-  S.vy = s->vy;
-  S.vz = c->m.d3 ? s->vz : nullptr;
-  S.e = c->p.eos == FARGO_ADIABATIC ? s->e : nullptr;
-  S.cs = c->p.eos == FARGO_ISOTHERMAL ? s->cs : nullptr;
-  S.pot = s->pot;
+template <typename F>
+StateT<F> state_of(const fargo_ctx *c, const fargo_state *s) {
+  StateT<F> S;
+  S.rho = (F *)s->rho;
+  S.vx = (F *)s->vx;
+  S.vy = (F *)s->vy;
+  S.vz = c->m.d3 ? (F *)s->vz : nullptr;
+  S.e = c->p.eos == FARGO_ADIABATIC ? (F *)s->e : nullptr;
+  S.cs = c->p.eos == FARGO_ISOTHERMAL ? (const F *)s->cs : nullptr;
+  S.pot = (const F *)s->pot;
   return S;
 }
+
+template <typename F>
+TSetT<F> tset(const fargo_ctx *c, void *const *slots) {
+  TSetT<F> T{};
+  for (int t = 0; t < T_MAX; t++) T.a[t] = (F *)slots[t];
+  for (int q = 0; q < c->nq; q++) T.q[q] = (F *)slots[c->tq[q]];
+  T.nq = c->nq;
+  return T;
+}
+
+bool fp32(const fargo_ctx *c) { return c->p.precision == FARGO_FP32_BULK; }
 
 int check_state(const fargo_ctx *c, const fargo_state *s) {
   if (!s || !s->rho || !s->vx || !s->vy || !s->pot) return FARGO_EINVAL;
@@ -269,7 +295,8 @@ int check_state(const fargo_ctx *c, const fargo_state *s) {
 }
 
 // boxes 2, 3, 4, 6 and the split of Eq. 29 (dt > 0: imposed)
-void timestep_phase(fargo_ctx *c, Launch &L, const StateP &S, double dt) {
+template <typename F>
+void timestep_phase(fargo_ctx *c, Launch &L, const StateT<F> &S, double dt) {
   const Mesh &m = c->m;
   if (dt > 0.0) launch_set_dt(L, c->w, dt);
   launch_bc(L, m, S.rho, S.e, S.vx, S.vy, S.vz);
@@ -407,13 +434,14 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   c->partial = (double *)(base + Lo.partial);
   c->sums_out = (double *)(base + Lo.sums);
   size_t nc = (size_t)pitch * nyg * nzg;
-  size_t fb = al(nc * 8);
+  c->esize = elem_bytes(params);
+  size_t fb = al(nc * c->esize);
   {
     size_t o = Lo.v2;
     for (int d = 0; d < 4; d++) {
       bool need = d < 2 || (d == 2 && m.d3) || (d == 3 && params->eos == FARGO_ADIABATIC);
       if (!need) continue;
-      c->v2[d] = (double *)(base + o);
+      c->v2[d] = base + o;
       o += fb;
     }
   }
@@ -421,15 +449,12 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   int slot = 0;
   for (int t = 0; t < T_MAX; t++) {
     bool need = t <= T_PYP || (m.d3 && (t == T_PZM || t == T_PZP)) || (t == T_E && params->eos == FARGO_ADIABATIC);
-    c->TA.a[t] = c->TB.a[t] = nullptr;
+    c->TA[t] = c->TB[t] = nullptr;
     if (!need) continue;
-    c->TA.a[t] = (double *)(base + Lo.T + (size_t)slot * fb);
-    c->TB.a[t] = (double *)(base + Lo.T + (size_t)(nT + slot) * fb);
+    c->TA[t] = base + Lo.T + (size_t)slot * fb;
+    c->TB[t] = base + Lo.T + (size_t)(nT + slot) * fb;
     slot++;
-    if (t != T_RHO) {
-      c->TA.q[c->TA.nq++] = c->TA.a[t];
-      c->TB.q[c->TB.nq++] = c->TB.a[t];
-    }
+    if (t != T_RHO) c->tq[c->nq++] = t;
   }
   *out = c;
   return FARGO_OK;
@@ -448,8 +473,8 @@ int fargo_cfl_dt(fargo_ctx *ctx, fargo_state *state, double *dt_host, void *stre
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   Launch L{s, &ctx->prof};
-  StateP S = state_of(ctx, state);
-  timestep_phase(ctx, L, S, 0.0);
+  if (fp32(ctx)) timestep_phase(ctx, L, state_of<float>(ctx, state), 0.0);
+  else timestep_phase(ctx, L, state_of<double>(ctx, state), 0.0);
   if (hipGetLastError() != hipSuccess) return FARGO_EHIP;
   if (!dt_host) return FARGO_OK;
   double dt = 0.0;
@@ -463,50 +488,73 @@ int fargo_cfl_dt(fargo_ctx *ctx, fargo_state *state, double *dt_host, void *stre
   return FARGO_OK;
 }
 
+} // extern "C"
+
+namespace {
+
+// One full update (Sect. 3, Fig. "flowchart") on a state of element type F.
+template <typename F>
+void step_impl(fargo_ctx *ctx, const fargo_state *state, double dt, Launch &L) {
+  const Mesh &m = ctx->m;
+  StateT<F> S = state_of<F>(ctx, state);
+  timestep_phase(ctx, L, S, dt > 0.0 ? dt : 0.0);                                  // boxes 2, 3, 4, 6
+  const double *dtp = ctx->w.dt;
+  F *v2[4] = {(F *)ctx->v2[0], (F *)ctx->v2[1], (F *)ctx->v2[2], (F *)ctx->v2[3]};
+  launch_source(L, m, S, dtp, v2[0], v2[1], v2[2], v2[3]);                        // box 7
+  StateT<F> P = S; // post-source fields: density of the state, v'' and e''
+  P.vx = v2[0];
+  P.vy = v2[1];
+  P.vz = v2[2];
+  P.e = v2[3];
+  launch_bc(L, m, P.rho, P.e, P.vx, P.vy, P.vz);                                   // box 9
+  const TSetT<F> TA = tset<F>(ctx, ctx->TA), TB = tset<F>(ctx, ctx->TB);
+  launch_sweep_y(L, m, P, TB, dtp);                                                // boxes 12a-c, Y
+  const TSetT<F> *cur = &TB;
+  if (m.d3) {
+    launch_sweep_z(L, m, (const F *)P.vz, TB, TA, dtp);                            // Z
+    cur = &TA;
+  }
+  launch_ring_x(L, m, (const F *)P.vx, *cur, S, ctx->v0, ctx->nshift, ctx->xi, dtp); // X, FARGO, 12d (v_x)
+  launch_vel(L, m, S, *cur);                                                       // 12d (v_y, v_z)
+}
+
+} // namespace
+
+extern "C" {
+
 int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream) {
   if (!ctx) return FARGO_EINVAL;
   int rc = check_state(ctx, state);
   if (rc) return rc;
   if (!(dt <= 0.0) && !std::isfinite(dt)) return FARGO_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  Launch L{s, &ctx->prof};
-  const Mesh &m = ctx->m;
-  StateP S = state_of(ctx, state);
-  timestep_phase(ctx, L, S, dt > 0.0 ? dt : 0.0);                                  // boxes 2, 3, 4, 6
-  const double *dtp = ctx->w.dt;
-  launch_source(L, m, S, dtp, ctx->v2[0], ctx->v2[1], ctx->v2[2], ctx->v2[3]);    // box 7
-  StateP P = S; // post-source fields: density of the state, v'' and e''
-  P.vx = ctx->v2[0];
-  P.vy = ctx->v2[1];
-  P.vz = ctx->v2[2];
-  P.e = ctx->v2[3];
-  launch_bc(L, m, P.rho, P.e, P.vx, P.vy, P.vz);                                   // box 9
-  launch_sweep_y(L, m, P, ctx->TB, dtp);                                           // boxes 12a-c, Y
-  const TSet *cur = &ctx->TB;
-  if (m.d3) {
-    launch_sweep_z(L, m, P.vz, ctx->TB, ctx->TA, dtp);                             // Z
-    cur = &ctx->TA;
-  }
-  launch_ring_x(L, m, P.vx, *cur, S, ctx->v0, ctx->nshift, ctx->xi, dtp);          // X, FARGO, 12d (v_x)
-  launch_vel(L, m, S, *cur);                                                       // 12d (v_y, v_z)
+  Launch L{(hipStream_t)stream, &ctx->prof};
+  if (fp32(ctx)) step_impl<float>(ctx, state, dt, L);
+  else step_impl<double>(ctx, state, dt, L);
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
 
-int fargo_shift(fargo_ctx *ctx, double *field, const int32_t *nshift, void *stream) {
+int fargo_shift(fargo_ctx *ctx, void *field, const int32_t *nshift, void *stream) {
   if (!ctx || !field || !nshift) return FARGO_EINVAL;
   if (ctx->m.nx > 8192) return FARGO_EUNSUPPORTED;
   Launch L{(hipStream_t)stream, &ctx->prof};
-  launch_shift(L, ctx->m, field, nshift);
+  if (fp32(ctx)) launch_shift(L, ctx->m, (float *)field, nshift);
+  else launch_shift(L, ctx->m, (double *)field, nshift);
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
 
-int fargo_ring_split(fargo_ctx *ctx, const double *vx, double dt, double *v0, int32_t *nshift, double *xi,
+int fargo_ring_split(fargo_ctx *ctx, const void *vx, double dt, double *v0, int32_t *nshift, double *xi,
                      void *stream) {
   if (!ctx || !vx || !v0 || !nshift || !xi || !(dt > 0.0) || !std::isfinite(dt)) return FARGO_EINVAL;
   Launch L{(hipStream_t)stream, &ctx->prof};
-  StateP S{};
-  S.vx = const_cast<double *>(vx);
-  launch_cfl(L, ctx->m, S, 0, v0, nullptr, nullptr, nullptr);
+  if (fp32(ctx)) {
+    StateT<float> S{};
+    S.vx = (float *)const_cast<void *>(vx);
+    launch_cfl(L, ctx->m, S, 0, v0, nullptr, nullptr, nullptr);
+  } else {
+    StateT<double> S{};
+    S.vx = (double *)const_cast<void *>(vx);
+    launch_cfl(L, ctx->m, S, 0, v0, nullptr, nullptr, nullptr);
+  }
   launch_split(L, ctx->m, v0, dt, nshift, xi);
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
@@ -517,8 +565,8 @@ int fargo_conserved_sums(fargo_ctx *ctx, const fargo_state *state, double out[5]
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   Launch L{s, &ctx->prof};
-  StateP S = state_of(ctx, state);
-  launch_sums(L, ctx->m, S, ctx->partial, ctx->sums_out);
+  if (fp32(ctx)) launch_sums(L, ctx->m, state_of<float>(ctx, state), ctx->partial, ctx->sums_out);
+  else launch_sums(L, ctx->m, state_of<double>(ctx, state), ctx->partial, ctx->sums_out);
   if (hipGetLastError() != hipSuccess) return FARGO_EHIP;
   if (hipMemcpyAsync(out, ctx->sums_out, 5 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return FARGO_EHIP;
   return hip_ok(hipStreamSynchronize(s));

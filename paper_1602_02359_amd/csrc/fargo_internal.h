@@ -1,6 +1,7 @@
 // Internal definitions of libfargo: mesh description (passed by value as a
 // kernel argument), device-side geometric accessors and launch helpers.
-// gfx950 only: 64-wide wavefronts, FP64 state.
+// gfx950 only: 64-wide wavefronts; the state is FP64, or FP32 in the
+// FP32-bulk mode (kernels are templates on the field type).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,6 +38,11 @@ struct Mesh {
   __host__ __device__ inline size_t idx(int i, int j, int k) const {
     return ((size_t)k * (size_t)nyg + (size_t)j) * (size_t)pitch + (size_t)i;
   }
+  // 32-bit element offset (the library requires every field to have fewer
+  // than 2^31 elements), which lets loads use an SGPR base plus one VGPR
+  __host__ __device__ inline unsigned o32(int i, int j, int k) const {
+    return ((unsigned)k * (unsigned)nyg + (unsigned)j) * (unsigned)pitch + (unsigned)i;
+  }
   __host__ __device__ inline size_t plane() const { return (size_t)nyg * (size_t)pitch; }
   __host__ __device__ inline size_t cells() const { return (size_t)nzg * plane(); }
   __device__ inline bool yper() const { return bc[0] == FARGO_BC_PERIODIC; }
@@ -68,18 +74,22 @@ struct Mesh {
   __device__ inline double Rcyl(int j, int k) const {
     return geo == FARGO_SPHERICAL ? g.ymed[j] * g.sinz[k] : g.ymed[j];
   }
-  // X-momentum factor of Tab. "momenta": Pi_x = rho * mx(v)
-  __device__ inline double mx(int j, int k, double v) const {
+  // X-momentum factor of Tab. "momenta": Pi_x = rho * mx(v); evaluated in
+  // the precision F of the field (geometric factors rounded to F)
+  template <typename F>
+  __device__ inline F mx(int j, int k, F v) const {
     if (geo == FARGO_CARTESIAN) return v;
-    double R = Rcyl(j, k);
-    return R * (v + R * omega);
+    F R = (F)Rcyl(j, k);
+    return R * (v + R * (F)omega);
   }
-  __device__ inline double vx_from(int j, int k, double m) const {
+  template <typename F>
+  __device__ inline F vx_from(int j, int k, F m) const {
     if (geo == FARGO_CARTESIAN) return m;
-    double R = Rcyl(j, k);
-    return m / R - R * omega;
+    F R = (F)Rcyl(j, k);
+    return m / R - R * (F)omega;
   }
-  __device__ inline double mz(int j, double v) const { return geo == FARGO_SPHERICAL ? g.ymed[j] * v : v; }
+  template <typename F>
+  __device__ inline F mz(int j, F v) const { return geo == FARGO_SPHERICAL ? (F)g.ymed[j] * v : v; }
 };
 
 __device__ inline int imod(int i, int n) {
@@ -90,10 +100,12 @@ __device__ inline int iwrap1(int i, int n) { // i in [-n, 2n)
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
 
-// The set of transported quantities (box 12a): rho plus nq others.
-struct TSet {
-  double *a[T_MAX];   // indexed by T_* (NULL if absent)
-  double *q[T_MAX];   // the non-density quantities, packed
+// The set of transported quantities (box 12a): rho plus nq others, stored
+// with element type R (double, or float for the FP32-bulk state).
+template <typename R>
+struct TSetT {
+  R *a[T_MAX]; // indexed by T_* (NULL if absent)
+  R *q[T_MAX]; // the non-density quantities, packed
   int nq;
 };
 
@@ -141,33 +153,45 @@ struct DevWords {
   int *err;   // error flags: 1 non-finite state, 2 bad dt
 };
 
-struct StateP {
-  double *rho, *vx, *vy, *vz, *e;
-  const double *cs, *pot;
+// Device pointers to the state (element type R); pointers the configuration
+// does not use are NULL.
+template <typename R>
+struct StateT {
+  R *rho, *vx, *vy, *vz, *e;
+  const R *cs, *pot;
 };
 
+// Each launcher is defined once for R = double and R = float.
 // boundaries (boxes 2 and 9)
-void launch_bc(Launch &L, const Mesh &m, double *rho, double *e, double *vx, double *vy, double *vz);
-// boxes 3, 6 and the split of Eq. 29
+template <typename R>
+void launch_bc(Launch &L, const Mesh &m, R *rho, R *e, R *vx, R *vy, R *vz);
+// boxes 3, 6 and the split of Eq. 29 (always FP64)
 void launch_set_dt(Launch &L, const DevWords &w, double dt);
 // per ring: v0 and (with_cfl) the minimum cell time step and maximum shear rate
-void launch_cfl(Launch &L, const Mesh &m, const StateP &s, int with_cfl, double *v0, double *ringmin,
+template <typename R>
+void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringmin,
                 double *ringshear, int *err);
 // dt from the ring slots (unless imposed), then N and xi of every ring
 void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringmin, const double *ringshear,
                      int use_given, const double *v0, int32_t *N, double *xi);
 void launch_split(Launch &L, const Mesh &m, const double *v0, double dt, int32_t *N, double *xi);
 // box 7: post-source velocities and energy into vx2, vy2, vz2, e2
-void launch_source(Launch &L, const Mesh &m, const StateP &s, const double *dt, double *vx2, double *vy2,
-                   double *vz2, double *e2);
+template <typename R>
+void launch_source(Launch &L, const Mesh &m, const StateT<R> &s, const double *dt, R *vx2, R *vy2, R *vz2, R *e2);
 // box 12
-void launch_sweep_y(Launch &L, const Mesh &m, const StateP &s, const TSet &out, const double *dt);
-void launch_sweep_z(Launch &L, const Mesh &m, const double *vz, const TSet &in, const TSet &out, const double *dt);
-void launch_ring_x(Launch &L, const Mesh &m, const double *vx2, const TSet &T, const StateP &s, const double *v0,
+template <typename R>
+void launch_sweep_y(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &out, const double *dt);
+template <typename R>
+void launch_sweep_z(Launch &L, const Mesh &m, const R *vz, const TSetT<R> &in, const TSetT<R> &out, const double *dt);
+template <typename R>
+void launch_ring_x(Launch &L, const Mesh &m, const R *vx2, const TSetT<R> &T, const StateT<R> &s, const double *v0,
                    const int32_t *N, const double *xi, const double *dt);
-void launch_vel(Launch &L, const Mesh &m, const StateP &s, const TSet &T);
+template <typename R>
+void launch_vel(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &T);
 // misc
-void launch_shift(Launch &L, const Mesh &m, double *field, const int32_t *N);
-void launch_sums(Launch &L, const Mesh &m, const StateP &s, double *partial, double *out);
+template <typename R>
+void launch_shift(Launch &L, const Mesh &m, R *field, const int32_t *N);
+template <typename R>
+void launch_sums(Launch &L, const Mesh &m, const StateT<R> &s, double *partial, double *out);
 
 } // namespace fargo

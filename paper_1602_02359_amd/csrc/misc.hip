@@ -1,6 +1,8 @@
 // Stand-alone circular shift of rings (Eq. 32) and conserved sums (mass,
 // momenta of Tab. "momenta" with the zone momentum of Eq. 19, internal
-// energy) with double-double accumulation in a fixed order.
+// energy) with double-double accumulation in a fixed order.  Both take the
+// field type F (double, or float for the FP32-bulk state); the sums are always
+// formed in FP64 from the stored values.
 #include "fargo_internal.h"
 
 namespace fargo {
@@ -8,11 +10,13 @@ namespace fargo {
 namespace {
 
 // Eq. 32 in place: one workgroup per active ring, the ring staged in LDS.
-__global__ __launch_bounds__(256) void k_shift(Mesh m, double *__restrict__ f, const int32_t *__restrict__ N) {
-  extern __shared__ double ring[];
+template <typename F>
+__global__ __launch_bounds__(256) void k_shift(Mesh m, F *__restrict__ f, const int32_t *__restrict__ N) {
+  extern __shared__ __align__(16) unsigned char ring_raw[];
+  F *ring = reinterpret_cast<F *>(ring_raw);
   int r = blockIdx.x;
   int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
-  double *row = f + m.idx(0, j, k);
+  F *row = f + m.idx(0, j, k);
   int n = m.nx;
   for (int i = threadIdx.x; i < n; i += blockDim.x) ring[i] = row[i];
   __syncthreads();
@@ -59,7 +63,8 @@ __device__ inline DD block_sum(DD v, DD *lds) {
 }
 
 // One workgroup per active ring: partial[r*10 + 2q + {0,1}] = (hi, lo) of sum q.
-__global__ __launch_bounds__(256) void k_sums(Mesh m, StateP s, double *__restrict__ partial) {
+template <typename F>
+__global__ __launch_bounds__(256) void k_sums(Mesh m, StateT<F> s, double *__restrict__ partial) {
 #pragma clang fp contract(off)
   __shared__ DD lds[4];
   int r = blockIdx.x;
@@ -71,12 +76,12 @@ __global__ __launch_bounds__(256) void k_sums(Mesh m, StateP s, double *__restri
   for (int i = threadIdx.x; i < m.nx; i += blockDim.x) {
     int ip = i + 1 == m.nx ? 0 : i + 1;
     size_t c = m.idx(i, j, k);
-    double rho = s.rho[c];
+    double rho = (double)s.rho[c];
     double t0 = rho * V;
-    double t1 = rho * 0.5 * (m.mx(j, k, s.vx[c]) + m.mx(j, k, s.vx[m.idx(ip, j, k)])) * V;
-    double t2 = rho * 0.5 * (s.vy[c] + s.vy[m.idx(i, jp, k)]) * V;
-    double t3 = m.d3 ? rho * 0.5 * (m.mz(j, s.vz[c]) + m.mz(j, s.vz[m.idx(i, j, kp)])) * V : 0.0;
-    double t4 = s.e ? s.e[c] * V : 0.0;
+    double t1 = rho * 0.5 * (m.mx(j, k, (double)s.vx[c]) + m.mx(j, k, (double)s.vx[m.idx(ip, j, k)])) * V;
+    double t2 = rho * 0.5 * ((double)s.vy[c] + (double)s.vy[m.idx(i, jp, k)]) * V;
+    double t3 = m.d3 ? rho * 0.5 * (m.mz(j, (double)s.vz[c]) + m.mz(j, (double)s.vz[m.idx(i, j, kp)])) * V : 0.0;
+    double t4 = s.e ? (double)s.e[c] * V : 0.0;
     acc[0] = dd_add(acc[0], t0);
     acc[1] = dd_add(acc[1], t1);
     acc[2] = dd_add(acc[2], t2);
@@ -106,19 +111,26 @@ __global__ __launch_bounds__(256) void k_sums_final(int nring, const double *__r
 
 } // namespace
 
-void launch_shift(Launch &L, const Mesh &m, double *field, const int32_t *N) {
+template <typename F>
+void launch_shift(Launch &L, const Mesh &m, F *field, const int32_t *N) {
   prof_begin(L, K_SHIFT);
-  k_shift<<<m.nring, 256, (size_t)m.nx * sizeof(double), L.s>>>(m, field, N);
+  k_shift<F><<<m.nring, 256, (size_t)m.nx * sizeof(F), L.s>>>(m, field, N);
   prof_end(L, K_SHIFT);
 }
 
-void launch_sums(Launch &L, const Mesh &m, const StateP &s, double *partial, double *out) {
+template <typename F>
+void launch_sums(Launch &L, const Mesh &m, const StateT<F> &s, double *partial, double *out) {
   prof_begin(L, K_SUMS);
-  k_sums<<<m.nring, 256, 0, L.s>>>(m, s, partial);
+  k_sums<F><<<m.nring, 256, 0, L.s>>>(m, s, partial);
   prof_end(L, K_SUMS);
   prof_begin(L, K_SUMS_FINAL);
   k_sums_final<<<1, 256, 0, L.s>>>(m.nring, partial, out);
   prof_end(L, K_SUMS_FINAL);
 }
+
+template void launch_shift<double>(Launch &, const Mesh &, double *, const int32_t *);
+template void launch_shift<float>(Launch &, const Mesh &, float *, const int32_t *);
+template void launch_sums<double>(Launch &, const Mesh &, const StateT<double> &, double *, double *);
+template void launch_sums<float>(Launch &, const Mesh &, const StateT<float> &, double *, double *);
 
 } // namespace fargo

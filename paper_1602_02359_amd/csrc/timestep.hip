@@ -59,8 +59,10 @@ __device__ inline double ring_bulk(const Mesh &m, const double (&v)[M], int tid,
 }
 
 // Rings in logical order (k fastest), XCD-contiguous; M zones per thread.
-template <int M>
-__global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateP s, int with_cfl, double *__restrict__ v0,
+// The state may be stored in FP32 (R = float); the time step is always formed
+// in FP64 from the stored values.
+template <int M, typename R>
+__global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_cfl, double *__restrict__ v0,
                                                   double *__restrict__ ringmin, double *__restrict__ ringshear,
                                                   int *__restrict__ err) {
 #pragma clang fp contract(off)
@@ -71,12 +73,12 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateP s, int with_cfl
   const int j = m.j0 + jj, k = m.k0 + kk;
   const int r = kk * m.ny + jj; // ring index (k - k0) * ny + (j - j0)
   const int tid = threadIdx.x, B = blockDim.x, n = m.nx;
-  const size_t base = m.idx(0, j, k);
+  const unsigned base = m.o32(0, j, k);
   double vx[M];
 #pragma unroll
   for (int mm = 0; mm < M; mm++) {
     int i = tid + B * mm;
-    vx[mm] = i < n ? s.vx[base + i] : 0.0;
+    vx[mm] = i < n ? (double)s.vx[base + i] : 0.0;
     if (i < n) V[i] = vx[mm];
   }
   const double vb_ring = ring_bulk<M>(m, vx, tid, red);
@@ -94,16 +96,16 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateP s, int with_cfl
   for (int mm = 0; mm < M; mm++) {
     int i = tid + B * mm;
     if (i >= n) continue;
-    size_t c = base + i;
+    unsigned c = base + i;
     double vxc = vx[mm], vxp = V[i + 1 == n ? 0 : i + 1];
-    double rho = s.rho[c];
+    double rho = (double)s.rho[c];
     double cw;
-    if (m.eos == FARGO_ISOTHERMAL) cw = s.cs[c];
+    if (m.eos == FARGO_ISOTHERMAL) cw = (double)s.cs[c];
     else {
-      double P = (m.gamma - 1.0) * s.e[c];
+      double P = (m.gamma - 1.0) * (double)s.e[c];
       cw = sqrt(m.gamma * P / rho);
     }
-    double vyc = s.vy[c], vyp = s.vy[c + m.pitch];
+    double vyc = (double)s.vy[c], vyp = (double)s.vy[c + m.pitch];
     bad |= !(rho > 0.0) || !isfinite(rho) || !isfinite(cw) || !isfinite(vxc) || !isfinite(vyc);
     double dt1 = fmin(Lx / cw, Lyy / cw);
     double ux = fmax(fabs(vxc - vb), fabs(vxp - vb));
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateP s, int with_cfl
     if (dvx < 0.0) dt3 = fmin(dt3, Lx / (4.0 * m.cvnr * m.cvnr * fabs(dvx)));
     if (dvy < 0.0) dt3 = fmin(dt3, Lyy / (4.0 * m.cvnr * m.cvnr * fabs(dvy)));
     if (m.d3) {
-      double vzc = s.vz[c], vzp = s.vz[c + m.plane()];
+      double vzc = (double)s.vz[c], vzp = (double)s.vz[c + (unsigned)m.plane()];
       bad |= !isfinite(vzc);
       dt1 = fmin(dt1, Lzz / cw);
       double uz = fmax(fabs(vzc), fabs(vzp));
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateP s, int with_cfl
     if (!(cell >= 0.0)) bad = 1;
     else cmin = cell < cmin ? cell : cmin;
     if (shear_on) {
-      double sh = fabs(vxc / Lx - s.vx[c + m.pitch] / dXp);
+      double sh = fabs(vxc / Lx - (double)s.vx[c + m.pitch] / dXp);
       if (sh > smax) smax = sh;
     }
   }
@@ -196,10 +198,10 @@ __global__ __launch_bounds__(256) void k_split(Mesh m, const double *__restrict_
   xi[r] = D - rn;
 }
 
-template <int M>
-void cfl_launch(Launch &L, const Mesh &m, const StateP &s, int with_cfl, double *v0, double *rmin, double *rsh,
+template <int M, typename R>
+void cfl_launch(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *rmin, double *rsh,
                 int *err) {
-  k_cfl_ring<M><<<m.nring, 256, (size_t)m.nx * sizeof(double), L.s>>>(m, s, with_cfl, v0, rmin, rsh, err);
+  k_cfl_ring<M, R><<<m.nring, 256, (size_t)m.nx * sizeof(double), L.s>>>(m, s, with_cfl, v0, rmin, rsh, err);
 }
 
 } // namespace
@@ -210,16 +212,22 @@ void launch_set_dt(Launch &L, const DevWords &w, double dt) {
   prof_end(L, K_SET_DT);
 }
 
-void launch_cfl(Launch &L, const Mesh &m, const StateP &s, int with_cfl, double *v0, double *ringmin,
+template <typename R>
+void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringmin,
                 double *ringshear, int *err) {
   prof_begin(L, K_CFL);
   int M = (m.nx + 255) / 256;
-  if (M <= 1) cfl_launch<1>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
-  else if (M == 2) cfl_launch<2>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
-  else if (M <= 4) cfl_launch<4>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
-  else cfl_launch<8>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
+  if (M <= 1) cfl_launch<1, R>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
+  else if (M == 2) cfl_launch<2, R>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
+  else if (M <= 4) cfl_launch<4, R>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
+  else cfl_launch<8, R>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
   prof_end(L, K_CFL);
 }
+
+template void launch_cfl<double>(Launch &, const Mesh &, const StateT<double> &, int, double *, double *, double *,
+                                 int *);
+template void launch_cfl<float>(Launch &, const Mesh &, const StateT<float> &, int, double *, double *, double *,
+                                int *);
 
 void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringmin, const double *ringshear,
                      int use_given, const double *v0, int32_t *N, double *xi) {

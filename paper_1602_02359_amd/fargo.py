@@ -27,6 +27,8 @@ GEOMETRY = {"cart": 0, "cyl": 1, "sph": 2}
 EOS = {"iso": 0, "adi": 1}
 BC = {"periodic": 0, "reflect": 1, "outflow": 2, "fixed": 3}
 V0_MODE = {"minmax": 0, "mean": 1}
+PRECISION = {"fp64": 0, "fp32": 1}  # fp32: FP32-bulk state, FP64 time step, split and sums
+DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
 FIELDS = ("rho", "vx", "vy", "vz", "e", "cs", "pot")
 
 
@@ -107,7 +109,7 @@ def make_params(p: Dict):
     s.v0_mode = V0_MODE[p.get("v0_mode", "minmax")]
     for i, b in enumerate(p["bc"]):
         s.bc[i] = BC[b]
-    s.precision = 0
+    s.precision = PRECISION[p.get("precision", "fp64")]
     return s, (ymin, zmin)
 
 
@@ -133,11 +135,13 @@ def _stream(stream=None):
 
 class Solver:
     """Owns a fargo context, its workspace and the device state tensors
-    (padded layout [nz_g, ny_g, pitch], float64)."""
+    (padded layout [nz_g, ny_g, pitch]; float64, or float32 when
+    params["precision"] == "fp32")."""
 
     def __init__(self, params: Dict, device: str = "cuda", workspace: bool = True):
         self.params = dict(params)
         self.device = torch.device(device)
+        self.dtype = DTYPE[self.params.get("precision", "fp64")]
         self.pitch, self.nyg, self.nzg = fargo_layout(params)
         self.shape = (self.nzg, self.nyg, self.pitch)
         self._ps, self._keep = make_params(params)
@@ -162,7 +166,8 @@ class Solver:
 
     # -- state -------------------------------------------------------------
     def upload(self, fields: Dict[str, Optional[np.ndarray]]):
-        """Copy host arrays (nz_g, ny_g, nx) into padded device tensors."""
+        """Copy host arrays (nz_g, ny_g, nx) into padded device tensors of the
+        state type (FP64 values are rounded to nearest for an FP32 state)."""
         nx = self.params["nx"]
         self.state = {}
         for n in FIELDS:
@@ -170,8 +175,8 @@ class Solver:
             if a is None:
                 self.state[n] = None
                 continue
-            t = torch.zeros(self.shape, dtype=torch.float64, device=self.device)
-            t[:, :, :nx] = torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
+            t = torch.zeros(self.shape, dtype=self.dtype, device=self.device)
+            t[:, :, :nx] = torch.from_numpy(np.ascontiguousarray(a)).to(self.device).to(self.dtype)
             self.state[n] = t
         self._bind()
 
@@ -183,7 +188,8 @@ class Solver:
     def download(self) -> Dict[str, Optional[np.ndarray]]:
         nx = self.params["nx"]
         torch.cuda.synchronize(self.device)
-        return {n: (None if t is None else t[:, :, :nx].cpu().numpy().copy()) for n, t in self.state.items()}
+        return {n: (None if t is None else t[:, :, :nx].double().cpu().numpy().copy())
+                for n, t in self.state.items()}
 
     # -- C ABI calls -------------------------------------------------------
     def fargo_step(self, dt: float = 0.0, stream=None):
@@ -200,12 +206,13 @@ class Solver:
         return out.value
 
     def fargo_shift(self, field: torch.Tensor, nshift: torch.Tensor, stream=None):
-        assert field.dtype == torch.float64 and tuple(field.shape) == self.shape and field.is_contiguous()
+        assert field.dtype == self.dtype and tuple(field.shape) == self.shape and field.is_contiguous()
         assert nshift.dtype == torch.int32 and nshift.numel() == self.params["ny"] * self.params["nz"]
         _check(_lib.fargo_shift(self._ctx, C.c_void_p(field.data_ptr()), C.c_void_p(nshift.data_ptr()),
                                 _stream(stream)), "fargo_shift")
 
     def fargo_ring_split(self, vx: torch.Tensor, dt: float, stream=None):
+        assert vx.dtype == self.dtype and tuple(vx.shape) == self.shape and vx.is_contiguous()
         nr = self.params["ny"] * self.params["nz"]
         v0 = torch.empty(nr, dtype=torch.float64, device=self.device)
         N = torch.empty(nr, dtype=torch.int32, device=self.device)

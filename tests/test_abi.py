@@ -47,3 +47,20 @@ def test_layout_and_validation_without_gpu():
     assert e.value.code == -6
     wsb = F.fargo_workspace_bytes(W.disk3d_sph().params)
     assert wsb > 16 * 1536 * 518 * 134 * 8
+
+
+def test_fp32_bulk_layout_and_precision_check():
+    import ctypes
+    from paper_1602_02359_amd import fargo as F
+    p64 = W.disk3d_sph().params
+    p32 = dict(p64, precision="fp32")
+    assert F.fargo_layout(p32) == F.fargo_layout(p64)
+    w64, w32 = F.fargo_workspace_bytes(p64), F.fargo_workspace_bytes(p32)
+    # the field buffers (post-source copies and two transport sets) halve;
+    # geometry tables and per-ring FP64 arrays do not
+    assert w32 < 0.52 * w64
+    ps, keep = F.make_params(p64)
+    ps.precision = 7
+    n = ctypes.c_size_t()
+    assert F._lib.fargo_workspace_bytes(ctypes.byref(ps), ctypes.byref(n)) == -1
+

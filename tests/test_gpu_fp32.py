@@ -1,0 +1,177 @@
+"""FP32-bulk state (precision "fp32") through the C ABI.
+
+What stays FP64 is checked exactly: the time step (formed in FP64 from the
+stored FP32 values) and each ring's v0, N and xi equal the oracle's on the
+same values upcast to FP64; circular shifts are bit-exact permutations and
+the conserved sums match the oracle's FP64 sums of the upcast state.  The
+bulk arithmetic is FP32: one step is compared with the oracle on the upcast
+input, and 100 steps with the plain FP64 GPU step from the same FP64 initial
+state, normwise with velocities scaled by the largest speed, at 1e-5 (the
+error is reported for every field).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1602_02359_amd import workloads as W
+from gpu_common import errors, owned
+
+pytestmark = pytest.mark.gpu
+
+TOL_100 = 1e-5     # FP32 bulk vs FP64 after 100 steps
+# One step: a chain of some thirty FP32 roundings (unit 6e-8), amplified by at
+# most ~50 where a gradient takes the difference of neighbouring values, and
+# scaled by the step's relative change (< 1): a few 1e-7 at most.
+TOL_ONE = 2e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _solver(prob, precision):
+    from paper_1602_02359_amd import fargo as F
+    s = F.Solver(dict(prob.params, precision=precision))
+    s.upload(prob.fields)
+    return s
+
+
+def _upcast(fields):
+    """The FP32 image of an FP64 state, as FP64 arrays (exact)."""
+    return {k: (None if v is None else v.astype(np.float32).astype(np.float64)) for k, v in fields.items()}
+
+
+def _small(name):
+    if name == "sph3d":
+        return W.disk3d_sph(nx=136, ny=19, nz=11, noise=1e-3)
+    if name == "cyl3d_planet":
+        return W.disk3d_cyl_planet(nx=150, ny=23, nz=9, noise=1e-3)
+    if name == "disk2d":
+        return W.disk2d_cyl(nx=200, ny=37, noise=1e-3)
+    if name == "cart_random":
+        return W.random_problem("cart", nx=70, ny=9, nz=7, eos="adi", seed=1)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["sph3d", "cyl3d_planet", "disk2d", "cart_random"])
+def test_fp32_one_step_vs_oracle(name):
+    prob = _small(name)
+    _say("fp32 one step", name, prob.params["nx"], prob.params["ny"], prob.params["nz"])
+    up = _upcast(prob.fields)
+    ref = {k: (None if v is None else v.copy()) for k, v in up.items()}
+    dt_ref = O.step(prob.params, ref)
+    s = _solver(prob, "fp32")
+    s.fargo_step(0.0)
+    s.fargo_check()
+    dt = s.fargo_get_dt()
+    got = s.download()
+    # box 6 runs in FP64 on the stored values: the same time step exactly
+    assert dt == dt_ref, (dt, dt_ref)
+    err = errors(prob, got, ref)
+    _say("  errors", err)
+    for k, e in err.items():
+        assert e <= TOL_ONE, (k, e)
+
+
+@pytest.mark.parametrize("name", ["sph3d", "cyl3d_planet", "disk2d"])
+def test_fp32_hundred_steps_vs_fp64(name):
+    prob = _small(name)
+    _say("fp32 vs fp64, 100 steps", name)
+    s64, s32 = _solver(prob, "fp64"), _solver(prob, "fp32")
+    for _ in range(100):
+        s64.fargo_step(0.0)
+        s32.fargo_step(0.0)
+    s64.fargo_check()
+    s32.fargo_check()
+    a, b = s32.download(), s64.download()
+    err = errors(prob, a, b)
+    _say("  errors", err, "dt", s32.fargo_get_dt(), s64.fargo_get_dt())
+    for k, e in err.items():
+        assert e <= TOL_100, (k, e)
+    assert abs(s32.fargo_get_dt() / s64.fargo_get_dt() - 1.0) < 1e-4
+
+
+@pytest.mark.parametrize("name", ["sph3d", "disk2d"])
+def test_fp32_ring_split_bit_exact(name):
+    import torch
+    prob = _small(name)
+    s = _solver(prob, "fp32")
+    vx = s.state["vx"]
+    up = s.download()["vx"]
+    dt = 0.37 * O.cfl_dt(prob.params, _upcast(prob.fields))
+    v0, N, xi = s.fargo_ring_split(vx, dt)
+    torch.cuda.synchronize()
+    rv0, rN, rxi = O.ring_split(prob.params, up, dt)
+    assert np.array_equal(N.cpu().numpy(), rN.ravel())
+    assert np.array_equal(v0.cpu().numpy(), rv0.ravel())
+    assert np.array_equal(xi.cpu().numpy(), rxi.ravel())
+
+
+def test_fp32_shift_bit_exact():
+    import torch
+    prob = W.random_problem("cyl", nx=200, ny=6, nz=5, eos="iso", seed=11, fargo=True)
+    s = _solver(prob, "fp32")
+    p = prob.params
+    rng = np.random.default_rng(5)
+    nr = p["ny"] * p["nz"]
+    N = rng.integers(-450, 450, size=nr).astype(np.int32)
+    f = s.state["rho"].clone()
+    before = f[:, :, :p["nx"]].double().cpu().numpy()
+    s.fargo_shift(f, torch.from_numpy(N).to(f.device))
+    torch.cuda.synchronize()
+    after = f[:, :, :p["nx"]].double().cpu().numpy()
+    O.shift(p, before, N.reshape(p["nz"], p["ny"]))
+    assert np.array_equal(after, before)
+
+
+@pytest.mark.parametrize("name", ["sph3d", "cyl3d_planet"])
+def test_fp32_conserved_sums(name):
+    prob = _small(name)
+    s = _solver(prob, "fp32")
+    s.fargo_cfl_dt()               # box 2 fill, as the oracle's sums expect
+    got = s.fargo_conserved_sums()
+    o, a = O.sums(prob.params, s.download())
+    for q in range(5):
+        assert abs(got[q] - o[q]) <= 1e-14 * max(a[q], 1e-300), (q, got[q], o[q])
+
+
+def test_fp32_full_size_hundred_steps():
+    """The 3D cylindrical planet disk at 2048x768x96: FP32 bulk vs the plain
+    FP64 step after 100 steps, errors formed on the device."""
+    import torch
+    prob = W.make("cyl3d_planet")
+    p = prob.params
+    _say("fp32 vs fp64 full size", p["nx"], p["ny"], p["nz"])
+    s64, s32 = _solver(prob, "fp64"), _solver(prob, "fp32")
+    prob.fields = None  # host copy no longer needed
+    for n in range(100):
+        s64.fargo_step(0.0)
+        s32.fargo_step(0.0)
+        if n % 25 == 24:
+            torch.cuda.synchronize()
+            _say("  step", n + 1)
+    s64.fargo_check()
+    s32.fargo_check()
+    nx = p["nx"]
+    vmax = max(float(s64.state[k][owned(prob, k)][..., :nx].abs().max()) for k in ("vx", "vy", "vz"))
+    err = {}
+    for k in ("rho", "vx", "vy", "vz"):
+        sl = owned(prob, k)
+        a = s32.state[k][sl][..., :nx].double()
+        b = s64.state[k][sl][..., :nx]
+        den = vmax if k.startswith("v") else float(b.abs().max())
+        err[k] = float((a - b).abs().max()) / den
+        del a
+    _say("  errors", err, "dt", s32.fargo_get_dt(), s64.fargo_get_dt())
+    for k, e in err.items():
+        assert e <= TOL_100, (k, e)

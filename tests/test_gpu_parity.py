@@ -296,3 +296,22 @@ def test_full_size_sampled(cfg):
     _say(cfg, "dt", dt, "sampled errors", worst)
     for k, e in worst.items():
         assert e <= TOL, (k, e)
+
+
+def test_disk2d_full_ten_steps():
+    """The 2D disk configuration at its full size (384 x 128) for the ten steps
+    it is specified with, each side with its own time step."""
+    prob = W.make("disk2d")
+    _say("case disk2d full, 10 steps", prob.shape)
+    ref = prob.copy_fields()
+    s = gpu_solver(prob)
+    for n in range(prob.steps):
+        dt_ref = O.step(prob.params, ref)
+        s.fargo_step(0.0)
+        dt = s.fargo_get_dt()
+        assert (dt == dt_ref) if n == 0 else abs(dt / dt_ref - 1.0) < 1e-12, (n, dt, dt_ref)
+    s.fargo_check()
+    err = errors(prob, s.download(), ref)
+    _say("disk2d 10 steps", err)
+    for k, e in err.items():
+        assert e <= 10 * TOL, (k, e)
