@@ -16,6 +16,8 @@
  *   box 6   time step (Eq. cfl2, items 1-3; Eq. 38 with orbital advection)
  *   box 7a  pressure and potential gradients, centrifugal terms (Sect. 3.3, Eq. 12)
  *   box 7b  von Neumann-Richtmyer artificial viscosity and its heating
+ *   box 7d  kinematic viscosity (App. B, Eqs. 73 and 76; cylindrical 2D),
+ *           applied after 7b and before 7c
  *   box 7c  compressional heating (time-centred, gamma-law gas)
  *   box 9   boundary fill
  *   box 12a left/right momenta (Eqs. 16-17, Tab. "momenta")
@@ -60,12 +62,14 @@ typedef struct {
   double shear_c0; /* C0 of Eq. 38; <= 0 switches the shear limit off */
   int32_t fargo, v0_mean;
   int32_t bc[4];   /* ymin, ymax, zmin, zmax sides */
+  int32_t visc;    /* 1: viscous stress (box 7d) with the static field nu */
 } orc_params;
 
 /* Arrays (nz_g, ny_g, nx), X fastest, ghosts included. */
 typedef struct {
   double *rho, *vx, *vy, *vz, *e; /* vz NULL in 2D; e NULL if isothermal */
   const double *cs, *pot;         /* static fields; cs NULL if adiabatic */
+  const double *nu;               /* static kinematic viscosity (zone centred); NULL without viscosity */
 } orc_state;
 
 /* ------------------------------------------------------------------------ */
@@ -107,6 +111,7 @@ static int check_params(const orc_params *p) {
   if (p->nz > 1 && (p->bc[2] == BC_PERIODIC) != (p->bc[3] == BC_PERIODIC)) return ORC_EINVAL;
   if (p->geometry != GEO_CART && p->bc[0] == BC_PERIODIC) return ORC_EINVAL;
   if (p->geometry == GEO_SPH && p->bc[2] == BC_PERIODIC) return ORC_EINVAL;
+  if (p->visc && (p->geometry != GEO_CYL || p->nz != 1)) return ORC_EINVAL; /* 7d: cylindrical 2D only */
   return ORC_OK;
 }
 
@@ -414,7 +419,14 @@ static double cfl_dt(const mesh_t *m, const orc_state *s, const double *v0, int 
           double dvz = s->vz[IX(i, j, k + 1)] - s->vz[c];
           if (dvz < 0.0) dt3 = fmin(dt3, Lzz / (4.0 * p->cvnr * p->cvnr * fabs(dvz)));
         }
-        double cell = 1.0 / sqrt(1.0 / (dt1 * dt1) + 1.0 / (dt2 * dt2) + 1.0 / (dt3 * dt3));
+        double inv2 = 1.0 / (dt1 * dt1) + 1.0 / (dt2 * dt2) + 1.0 / (dt3 * dt3);
+        if (p->visc) {
+          /* item 4: viscosity, Delta^2 / (4 nu), minimum over directions */
+          double Lmin = fmin(Lx, Lyy);
+          double dt4 = Lmin * Lmin / (4.0 * s->nu[c]);
+          inv2 += 1.0 / (dt4 * dt4);
+        }
+        double cell = 1.0 / sqrt(inv2);
         if (cell < mincell) mincell = cell;
         /* Eq. 38: shear between radially adjacent active zones */
         if (p->fargo && p->shear_c0 > 0.0 && j + 1 < m->jn) {
@@ -571,6 +583,71 @@ static void substep2(const mesh_t *m, orc_state *s, const double *vx1, const dou
         s->vz[c] = vz1[c] - dt * 2.0 * (qz[c] - qz[cm]) / ((s->rho[c] + s->rho[cm]) * h);
       }
     }
+}
+
+/* Box 7d: viscous stress of a kinematic viscosity nu, cylindrical 2D
+   (phi, r), in the component forms of App. B (Eq. 73) and their divergence
+   (Eq. 76).  The diagonal components sit at zone centres; tau_rphi sits on
+   the zone's lower edge in both X and Y (Fig. "stress"), where rho and nu
+   are the means of the four zones sharing it and v_phi/r is the mean of
+   v_phi/r on the two X faces it joins.  All components come from the
+   velocities after 7b (Jacobi); then v_phi (X faces of active zones) and v_r
+   (owned Y faces) are updated, with the face density of Eq. 20. */
+static void substep_visc(const mesh_t *m, orc_state *s, double dt, double *tpp, double *trr, double *trp) {
+  const double dphi = m->dx;
+  const int nx = m->nx;
+  /* zone-centred components on the active rows */
+#pragma omp parallel for schedule(static)
+  for (int j = m->j0; j < m->jn; j++) {
+    double r = m->ymed[j];
+    for (int i = 0; i < nx; i++) {
+      size_t c = IX(i, j, 0), cxp = IX(imod(i + 1, nx), j, 0), cyp = IX(i, j + 1, 0);
+      double divv = Vinv(m, j, 0) * (Sx(m, j, 0) * (s->vx[cxp] - s->vx[c]) +
+                                     (Sy(m, j + 1, 0) * s->vy[cyp] - Sy(m, j, 0) * s->vy[c]));
+      double rn = s->rho[c] * s->nu[c];
+      double ur = 0.5 * (s->vy[c] + s->vy[cyp]);
+      tpp[c] = -rn * (2.0 * ((s->vx[cxp] - s->vx[c]) / (r * dphi) + ur / r) - 2.0 / 3.0 * divv);
+      trr[c] = -rn * (2.0 * (s->vy[cyp] - s->vy[c]) / Ly(m, j) - 2.0 / 3.0 * divv);
+    }
+  }
+  /* edge component on the Y faces j0 .. jn (the edge at the lower X face) */
+#pragma omp parallel for schedule(static)
+  for (int j = m->j0; j <= m->jn; j++) {
+    for (int i = 0; i < nx; i++) {
+      int im = imod(i - 1, nx);
+      size_t c = IX(i, j, 0), cw = IX(im, j, 0), cs_ = IX(i, j - 1, 0), csw = IX(im, j - 1, 0);
+      double rho4 = 0.25 * (s->rho[c] + s->rho[cw] + s->rho[cs_] + s->rho[csw]);
+      double nu4 = 0.25 * (s->nu[c] + s->nu[cw] + s->nu[cs_] + s->nu[csw]);
+      double dvphi_dr = (s->vx[c] - s->vx[cs_]) / hy(m, j);
+      double vphi_r = 0.5 * (s->vx[c] / m->ymed[j] + s->vx[cs_] / m->ymed[j - 1]);
+      double dvr_dphi = (s->vy[c] - s->vy[cw]) / (m->ymin[j] * dphi);
+      trp[c] = -rho4 * nu4 * (dvphi_dr - vphi_r + dvr_dphi);
+    }
+  }
+  /* v_phi on the X faces of the active zones */
+#pragma omp parallel for schedule(static)
+  for (int j = m->j0; j < m->jn; j++) {
+    double r = m->ymed[j], a = m->ymin[j], b = m->ymin[j + 1];
+    for (int i = 0; i < nx; i++) {
+      int im = imod(i - 1, nx);
+      size_t c = IX(i, j, 0), cw = IX(im, j, 0), cn = IX(i, j + 1, 0);
+      double rho_f = 0.5 * (s->rho[c] + s->rho[cw]);
+      double div = (b * b * trp[cn] - a * a * trp[c]) / (r * r * Ly(m, j)) + (tpp[c] - tpp[cw]) / (r * dphi);
+      s->vx[c] -= dt * div / rho_f;
+    }
+  }
+  /* v_r on the owned Y faces */
+#pragma omp parallel for schedule(static)
+  for (int j = ylo_face(m); j < m->jn; j++) {
+    double a = m->ymin[j];
+    for (int i = 0; i < nx; i++) {
+      size_t c = IX(i, j, 0), cs_ = IX(i, j - 1, 0), ce = IX(imod(i + 1, nx), j, 0);
+      double rho_f = 0.5 * (s->rho[c] + s->rho[cs_]);
+      double div = (m->ymed[j] * trr[c] - m->ymed[j - 1] * trr[cs_]) / (a * hy(m, j)) +
+                   (trp[ce] - trp[c]) / (a * dphi) - 0.5 * (tpp[c] + tpp[cs_]) / a;
+      s->vy[c] -= dt * div / rho_f;
+    }
+  }
 }
 
 /* Box 7c, substep 3: work of the pressure forces on a gamma-law gas,
@@ -944,6 +1021,7 @@ static int state_ok(const mesh_t *m, const orc_state *s) {
   if (m->d3 && !s->vz) return 0;
   if (m->p->eos == EOS_ISO && !s->cs) return 0;
   if (m->p->eos == EOS_ADI && !s->e) return 0;
+  if (m->p->visc && !s->nu) return 0;
   return 1;
 }
 
@@ -1011,6 +1089,7 @@ int orc_step(const orc_params *p, orc_state *s, double dt_in, double *dt_out) {
     if (m->d3) memcpy(v1[2], s->vz, sizeof(double) * nc);
     substep1(m, s, P, dt, v1[0], v1[1], v1[2]);   /* box 7a */
     substep2(m, s, v1[0], v1[1], v1[2], dt, q[0], q[1], q[2]); /* box 7b */
+    if (p->visc) substep_visc(m, s, dt, q[0], q[1], P); /* box 7d (q and P reused as scratch) */
     if (p->eos == EOS_ADI) substep3(m, s, dt);    /* box 7c */
     boundary_fill(m, s);                          /* box 9 */
     momenta(m, s, &T);                            /* box 12a */

@@ -35,12 +35,12 @@ class _Params(C.Structure):
         ("eos", C.c_int32), ("gamma", C.c_double),
         ("omega", C.c_double), ("courant", C.c_double), ("cvnr", C.c_double), ("shear_c0", C.c_double),
         ("fargo", C.c_int32), ("v0_mean", C.c_int32),
-        ("bc", C.c_int32 * 4),
+        ("bc", C.c_int32 * 4), ("visc", C.c_int32),
     ]
 
 
 class _State(C.Structure):
-    _fields_ = [(n, C.POINTER(C.c_double)) for n in ("rho", "vx", "vy", "vz", "e", "cs", "pot")]
+    _fields_ = [(n, C.POINTER(C.c_double)) for n in ("rho", "vx", "vy", "vz", "e", "cs", "pot", "nu")]
 
 
 _lib = None
@@ -97,12 +97,13 @@ def _params(p: Dict):
     s.v0_mean = int(p.get("v0_mode", "minmax") == "mean")
     for i, b in enumerate(p["bc"]):
         s.bc[i] = _BC[b]
+    s.visc = int(bool(p.get("visc", False)))
     return s, (ymin, zmin)
 
 
 def _state(f: Dict):
     s = _State()
-    for n in ("rho", "vx", "vy", "vz", "e", "cs", "pot"):
+    for n in ("rho", "vx", "vy", "vz", "e", "cs", "pot", "nu"):
         a = f.get(n)
         setattr(s, n, _ptr(a))
     return s
