@@ -17,6 +17,7 @@ the same workload and reported with its normwise error against the FP64 run
 after the same number of steps from the same initial state.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -45,12 +46,49 @@ def words_per_unit(p):
     return {
         # name: (words per zone, zones per launch)
         "cfl": (2 + nvel, act),                              # rho, cs|e, velocities
-        "source": ((3 + nvel) + (nvel + adi), whole),        # rho, cs|e, pot, v -> v'', e''
+        "source": ((3 + nvel) + (nvel + adi), act),          # rho, cs|e, pot, v -> v'', e''
+        "source_ghosts": (2 * (nvel + adi), whole - act),    # v, e -> v'', e'' in ghost zones
         "sweep_y": ((1 + nvel + adi) + nT, y_rows),          # rho, v'', e'' -> T (momenta formed on the fly)
         "sweep_z": ((2 * nT + 1) if d3 else 0, act),         # T, v_z -> T
         "ring_x": ((nT + 1) + (2 + adi + 2 + (2 if d3 else 0)), act),  # T, v_x -> rho, v_x, e, Pi_y, Pi_z
         "vel_yz": ((1 + 2 + (2 if d3 else 0)) + (nvel - 1), act),      # rho, Pi_y, Pi_z -> v_y, v_z
     }
+
+
+# the source file of each kernel: a measured traffic figure is used only while
+# the file (and the shared internal header) is unchanged since the counters
+# were taken
+KERNEL_SOURCES = {"cfl": "timestep.hip", "source": "source.hip", "source_ghosts": "source.hip",
+                  "sweep_y": "transport.hip", "sweep_z": "transport.hip", "ring_x": "transport.hip",
+                  "vel_yz": "transport.hip"}
+
+
+def source_hash(kernel):
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCES[kernel], "fargo_internal.h"):
+        with open(os.path.join(ROOT, "paper_1602_02359_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, tag):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary in profiles/ (copy-calibrated), or None if there is none or the
+    kernel's source changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s.md" % tag)
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            cells = [c.strip() for c in line.strip().strip("|").split("|")]
+            if len(cells) >= 6 and cells[0] == kernel:
+                if cells[1] != source_hash(kernel):
+                    return None
+                try:
+                    return float(cells[5])
+                except ValueError:
+                    return None
+    return None
 
 
 def compulsory_bytes(p):
@@ -124,6 +162,69 @@ def cpu_baseline(prob, target_s=12.0):
         "sample": "one full step (CFL included) of %d x %d x %d zones of the same workload (rings cut "
                   "from the mesh, neighbours as fixed ghosts), %.1f s" % (p["nx"], s.params["ny"], s.params["nz"], el),
     }
+
+
+def batch_variant(steps, warmup, tune=True):
+    """The parameter sweep of 256 uneven viscous disks (N_r in 64..512,
+    N_phi = 3 N_r, alpha viscosity): the plain FP64 step called disk by disk,
+    then the FP32-bulk batch advanced by one captured graph per step with the
+    autotuned graph width and sweep chunk.  Same disks, same number of steps."""
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    from paper_1602_02359_amd import workloads as W
+    probs = W.disk_batch()
+    cells = sum(p.active_cells for p in probs)
+    print("disk batch: %d disks, %d cells" % (len(probs), cells), file=sys.stderr, flush=True)
+
+    def timed(run_one, nsteps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            run_one()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    out = {}
+    s64 = []
+    for p in probs:
+        s = F.Solver(p.params)
+        s.upload(p.fields)
+        s64.append(s)
+    step64 = lambda: [s.fargo_step(0.0) for s in s64]
+    for _ in range(warmup):
+        step64()
+    el = timed(step64, steps)
+    for s in s64:
+        s.fargo_check()
+    out["fp64_disk_by_disk"] = {"value": cells * steps / el, "ms_per_step": 1e3 * el / steps}
+    del s64
+    torch.cuda.empty_cache()
+    s32 = []
+    for p in probs:
+        s = F.Solver(dict(p.params, precision="fp32"))
+        s.upload(p.fields)
+        s32.append(s)
+    b = F.Batch(s32, lanes=8)
+    best = None
+    if tune:
+        best = b.fargo_batch_tune(lanes=(1, 4, 8, 16), chunks=(16, 32, 64), steps=3)
+    for _ in range(warmup):
+        b.fargo_batch_step()
+    el = timed(b.fargo_batch_step, steps)
+    for s in s32:
+        s.fargo_check()
+    out["fp32_batched_graph"] = {"value": cells * steps / el, "ms_per_step": 1e3 * el / steps,
+                                 "tuned": {"lanes": best[0], "chunk": best[1]} if best else None}
+    out["speedup"] = out["fp32_batched_graph"]["value"] / out["fp64_disk_by_disk"]["value"]
+    out["disks"] = len(probs)
+    out["active_cells"] = cells
+    out["unit"] = "cell-updates/s"
+    print("  fp64 disk by disk %.3e, fp32 batched graph %.3e cell-updates/s (x%.2f), tuned %s" % (
+        out["fp64_disk_by_disk"]["value"], out["fp32_batched_graph"]["value"], out["speedup"], best),
+        file=sys.stderr, flush=True)
+    del b, s32
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -205,8 +306,10 @@ def main():
     solver, r64 = run("fp64")
     value, ms, kern, dom, step_alg = r64["value"], r64["ms"], r64["kern"], r64["dom"], r64["step_alg"]
     achieved = kern[dom]["GBs"]
+    tag = "%s_%dx%dx%d_fp64" % (args.config, p["nx"], p["ny"], p["nz"])
+    traffic = measured_traffic(dom, tag)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "alg_bytes_per_launch": kern[dom]["alg_bytes"], "avg_launch_ms": kern[dom]["avg_ms"]}
 
     variants = {}
@@ -246,6 +349,8 @@ def main():
         del s32
     del solver
     torch.cuda.empty_cache()
+    if not args.no_variant:
+        variants["disk_batch"] = batch_variant(args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -111,17 +111,21 @@ typedef struct {
   int32_t v0_mode;         /* FARGO_V0_MINMAX or FARGO_V0_MEAN */
   int32_t bc[4];           /* boundary kind of the ymin, ymax, zmin, zmax sides */
   int32_t precision;       /* FARGO_FP64 or FARGO_FP32_BULK */
+  int32_t visc;            /* 1: kinematic viscosity (box 7d, App. B) from the static field nu, with
+                              item 4 of Eq. cfl2; cylindrical 2D isothermal meshes only
+                              (FARGO_EUNSUPPORTED otherwise) */
 } fargo_params;
 
 /* Device pointers to the state, each laid out as described above, with
    elements of type double (FARGO_FP64) or float (FARGO_FP32_BULK).  rho, vx,
    vy are always required; vz in 3D only (NULL in 2D); e (volumic internal
    energy) for FARGO_ADIABATIC, cs (isothermal sound speed, static) for
-   FARGO_ISOTHERMAL; pot (static potential, ghosts included) always.
-   Arrays must be aligned to their element size. */
+   FARGO_ISOTHERMAL; pot (static potential, ghosts included) always; nu
+   (static kinematic viscosity, zone centred, ghosts included) when visc is
+   set, else NULL.  Arrays must be aligned to their element size. */
 typedef struct {
   void *rho, *vx, *vy, *vz, *e;
-  const void *cs, *pot;
+  const void *cs, *pot, *nu;
 } fargo_state;
 
 typedef struct fargo_ctx fargo_ctx;
@@ -209,6 +213,33 @@ int fargo_check(fargo_ctx *ctx);
 int fargo_profile_enable(fargo_ctx *ctx, int on);
 int fargo_timings(fargo_ctx *ctx, const char **names, int64_t *counts, double *total_ms, int cap, int *n_out,
                   void *stream);
+
+/* ---- Batches of independent contexts (parameter sweeps over many disks) ----
+   A batch advances `count` contexts (any sizes and parameters, one device)
+   together.  fargo_batch_create captures one fargo_step(dt <= 0) of every
+   context into a hipGraph: the contexts are spread round-robin over `lanes`
+   streams that fork from and join into an origin stream, so that independent
+   disks run concurrently; each keeps its own device time step (box 6).  The
+   contexts, states and workspaces must outlive the batch and must not be
+   used by other calls while a batch step runs.  `states` is an array of
+   `count` states (copied).  Profiling events are not recorded inside the
+   graph. */
+typedef struct fargo_batch fargo_batch;
+int fargo_batch_create(fargo_ctx *const *ctxs, const fargo_state *states, int count, int lanes,
+                       fargo_batch **out);
+/* One step of every context: a single graph launch on `stream`. */
+int fargo_batch_step(fargo_batch *batch, void *stream);
+/* Autotuner: for every pair (lanes[a], chunks[c]) - the graph's stream count
+   and the zones per thread of the Y/Z column sweeps - re-capture the batch,
+   time `steps` graph launches with HIP events on `stream`, and keep the
+   fastest pair (written to best[0], best[1]).  The evolving fields of every
+   state are saved first and restored after each candidate (one temporary
+   device allocation), so the call leaves the states as it found them.
+   Waits for the stream. */
+int fargo_batch_tune(fargo_batch *batch, const int32_t *lanes, int nlanes, const int32_t *chunks, int nchunks,
+                     int steps, void *stream, int32_t best[2]);
+/* Release the graph and streams (waits for the device).  NULL is a no-op. */
+void fargo_batch_destroy(fargo_batch *batch);
 
 #ifdef __cplusplus
 }

@@ -15,9 +15,9 @@ using namespace fargo;
 
 namespace fargo {
 
-const char *kernel_names[K_COUNT] = {"set_dt", "bc_faces", "bc_ghosts", "cfl", "dt_final", "split",
-                                     "source",  "sweep_y",  "sweep_z",   "ring_x", "vel_yz",
-                                     "shift",   "sums",     "sums_final"};
+const char *kernel_names[K_COUNT] = {"set_dt", "bc_faces", "bc_ghosts", "cfl",    "dt_final", "split",
+                                     "source", "source_ghosts", "visc", "sweep_y", "sweep_z",  "ring_x",
+                                     "vel_yz", "shift",    "sums",      "sums_final"};
 
 struct Prof {
   bool on = false;
@@ -83,6 +83,7 @@ struct fargo_ctx {
   double *partial = nullptr, *sums_out = nullptr;
   size_t esize = 8;                                    // bytes per state element
   void *v2[4] = {nullptr, nullptr, nullptr, nullptr}; // post-source vx, vy, vz, e
+  void *v3[2] = {nullptr, nullptr};                   // after box 7d: vx, vy (viscosity only)
   // transport buffers (box 12): slot t of set A / B, and the packed order of
   // the non-density quantities
   void *TA[T_MAX] = {}, *TB[T_MAX] = {};
@@ -111,6 +112,9 @@ int check_params(const fargo_params *p) {
   if (p->geometry != FARGO_CARTESIAN && p->bc[0] == FARGO_BC_PERIODIC) return FARGO_EINVAL;
   if (p->geometry == FARGO_SPHERICAL && p->bc[2] == FARGO_BC_PERIODIC) return FARGO_EINVAL;
   if (p->precision != FARGO_FP64 && p->precision != FARGO_FP32_BULK) return FARGO_EINVAL;
+  if (p->visc != 0 && p->visc != 1) return FARGO_EINVAL;
+  if (p->visc && (p->geometry != FARGO_CYLINDRICAL || p->nz != 1 || p->eos != FARGO_ISOTHERMAL))
+    return FARGO_EUNSUPPORTED;
   if (p->nx > 2048) return FARGO_EUNSUPPORTED; // ring kernel keeps a ring per workgroup in 64 KB of LDS
   {
     // kernels address fields with 32-bit element offsets
@@ -143,6 +147,7 @@ size_t elem_bytes(const fargo_params *p) { return p->precision == FARGO_FP32_BUL
 // host tables, in the order of GeoTables
 struct HostGeo {
   std::vector<double> ymin, ymed, zmin, zmed, sinz, Ly, hy, sxj, syj, szj, invVj, sxk, syk, szk, dxlen;
+  std::vector<double> inv_dxlen, inv_hy, inv_Ly, inv_ymin, inv_ymed, cotz, inv_dzmed, inv_dz;
 };
 
 #pragma clang fp contract(off)
@@ -213,11 +218,34 @@ void make_geo(const fargo_params *p, HostGeo &G) {
       else v = G.ymed[j] * G.sinz[k] * dx;
       G.dxlen[(size_t)k * nyg + j] = v;
     }
+  // reciprocals and the cotangent of the face colatitudes, so that kernels
+  // multiply instead of dividing by geometric lengths
+  auto inv = [](const std::vector<double> &a) {
+    std::vector<double> r(a.size());
+    for (size_t t = 0; t < a.size(); t++) r[t] = 1.0 / a[t];
+    return r;
+  };
+  G.inv_dxlen = inv(G.dxlen);
+  G.inv_hy = inv(G.hy);
+  G.inv_Ly = inv(G.Ly);
+  G.inv_ymin.resize(nyg + 1);
+  for (int j = 0; j <= nyg; j++) G.inv_ymin[j] = G.ymin[j] != 0.0 ? 1.0 / G.ymin[j] : 0.0;
+  G.inv_ymed = inv(G.ymed);
+  G.cotz.resize(nzg + 1);
+  for (int k = 0; k <= nzg; k++)
+    G.cotz[k] = p->geometry == FARGO_SPHERICAL ? std::cos(G.zmin[k]) / std::sin(G.zmin[k]) : 0.0;
+  G.inv_dzmed.resize(nzg);
+  G.inv_dz.resize(nzg);
+  for (int k = 0; k < nzg; k++) {
+    G.inv_dzmed[k] = 1.0 / (k > 0 ? G.zmed[k] - G.zmed[k - 1] : G.zmin[1] - G.zmin[0]);
+    G.inv_dz[k] = 1.0 / (G.zmin[k + 1] - G.zmin[k]);
+  }
 }
 
 size_t geo_doubles(int nyg, int nzg) {
   return (size_t)(nyg + 1) + nyg + (nzg + 1) + nzg + nzg + nyg + nyg + nyg + (nyg + 1) + nyg + nyg + nzg + nzg +
-         (nzg + 1) + (size_t)nzg * nyg;
+         (nzg + 1) + (size_t)nzg * nyg +
+         (size_t)nzg * nyg + nyg + nyg + (nyg + 1) + nyg + (nzg + 1) + nzg + nzg;
 }
 
 struct Layout {
@@ -251,7 +279,7 @@ Layout layout(const fargo_params *p) {
   L.sums = o;
   o += 256;
   L.v2 = o;
-  o += al(nc * eb) * ((p->nz > 1 ? 3 : 2) + (p->eos == FARGO_ADIABATIC ? 1 : 0));
+  o += al(nc * eb) * ((p->nz > 1 ? 3 : 2) + (p->eos == FARGO_ADIABATIC ? 1 : 0) + (p->visc ? 2 : 0));
   L.T = o;
   o += al(nc * eb) * 2 * ntransported(p);
   L.total = o;
@@ -272,6 +300,7 @@ StateT<F> state_of(const fargo_ctx *c, const fargo_state *s) {
   S.e = c->p.eos == FARGO_ADIABATIC ? (F *)s->e : nullptr;
   S.cs = c->p.eos == FARGO_ISOTHERMAL ? (const F *)s->cs : nullptr;
   S.pot = (const F *)s->pot;
+  S.nu = c->p.visc ? (const F *)s->nu : nullptr;
   return S;
 }
 
@@ -291,6 +320,7 @@ int check_state(const fargo_ctx *c, const fargo_state *s) {
   if (c->m.d3 && !s->vz) return FARGO_EINVAL;
   if (c->p.eos == FARGO_ISOTHERMAL && !s->cs) return FARGO_EINVAL;
   if (c->p.eos == FARGO_ADIABATIC && !s->e) return FARGO_EINVAL;
+  if (c->p.visc && !s->nu) return FARGO_EINVAL;
   return FARGO_OK;
 }
 
@@ -382,11 +412,17 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   buf.reserve(geo_doubles(nyg, nzg));
   std::vector<size_t> off;
   for (const std::vector<double> *v : {&G.ymin, &G.ymed, &G.zmin, &G.zmed, &G.sinz, &G.Ly, &G.hy, &G.sxj, &G.syj,
-                                       &G.szj, &G.invVj, &G.sxk, &G.syk, &G.szk, &G.dxlen}) {
+                                       &G.szj, &G.invVj, &G.sxk, &G.syk, &G.szk, &G.dxlen, &G.inv_dxlen,
+                                       &G.inv_hy, &G.inv_Ly, &G.inv_ymin, &G.inv_ymed, &G.cotz, &G.inv_dzmed,
+                                       &G.inv_dz}) {
     off.push_back(buf.size());
     buf.insert(buf.end(), v->begin(), v->end());
   }
   double *gd = (double *)(base + Lo.geo);
+  if (buf.size() != geo_doubles(nyg, nzg)) { // the workspace slot is sized by geo_doubles
+    fargo_destroy(c);
+    return FARGO_EINVAL;
+  }
   if (hipMemcpy(gd, buf.data(), buf.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
     fargo_destroy(c);
     return FARGO_EHIP;
@@ -407,8 +443,10 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   m.eos = params->eos;
   m.fargo = params->fargo ? 1 : 0;
   m.v0_mean = params->v0_mode == FARGO_V0_MEAN;
+  m.visc = params->visc;
   for (int s = 0; s < 4; s++) m.bc[s] = params->bc[s];
   m.nring = params->ny * params->nz;
+  m.chunk = 64;
   m.dx = (params->xmax - params->xmin) / params->nx;
   m.gamma = params->gamma;
   m.omega = params->omega;
@@ -416,7 +454,9 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   m.cvnr = params->cvnr;
   m.shear_c0 = params->shear_c0;
   const double **tbl[] = {&m.g.ymin, &m.g.ymed, &m.g.zmin, &m.g.zmed, &m.g.sinz, &m.g.Ly, &m.g.hy, &m.g.sxj,
-                          &m.g.syj, &m.g.szj, &m.g.invVj, &m.g.sxk, &m.g.syk, &m.g.szk, &m.g.dxlen};
+                          &m.g.syj, &m.g.szj, &m.g.invVj, &m.g.sxk, &m.g.syk, &m.g.szk, &m.g.dxlen,
+                          &m.g.inv_dxlen, &m.g.inv_hy, &m.g.inv_Ly, &m.g.inv_ymin, &m.g.inv_ymed, &m.g.cotz,
+                          &m.g.inv_dzmed, &m.g.inv_dz};
   for (size_t t = 0; t < off.size(); t++) *tbl[t] = gd + off[t];
   // words and per-ring arrays
   char *wd = base + Lo.words;
@@ -443,6 +483,10 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
       if (!need) continue;
       c->v2[d] = base + o;
       o += fb;
+    }
+    if (params->visc) {
+      c->v3[0] = base + o;
+      c->v3[1] = base + o + fb;
     }
   }
   int nT = ntransported(params);
@@ -500,22 +544,28 @@ void step_impl(fargo_ctx *ctx, const fargo_state *state, double dt, Launch &L) {
   timestep_phase(ctx, L, S, dt > 0.0 ? dt : 0.0);                                  // boxes 2, 3, 4, 6
   const double *dtp = ctx->w.dt;
   F *v2[4] = {(F *)ctx->v2[0], (F *)ctx->v2[1], (F *)ctx->v2[2], (F *)ctx->v2[3]};
-  launch_source(L, m, S, dtp, v2[0], v2[1], v2[2], v2[3]);                        // box 7
+  launch_source(L, m, S, dtp, v2[0], v2[1], v2[2], v2[3]);                        // boxes 7a-7c
   StateT<F> P = S; // post-source fields: density of the state, v'' and e''
   P.vx = v2[0];
   P.vy = v2[1];
+  if (m.visc) {                                                                    // box 7d
+    launch_visc(L, m, S, v2[0], v2[1], (F *)ctx->v3[0], (F *)ctx->v3[1], dtp);
+    P.vx = (F *)ctx->v3[0];
+    P.vy = (F *)ctx->v3[1];
+  }
   P.vz = v2[2];
   P.e = v2[3];
   launch_bc(L, m, P.rho, P.e, P.vx, P.vy, P.vz);                                   // box 9
   const TSetT<F> TA = tset<F>(ctx, ctx->TA), TB = tset<F>(ctx, ctx->TB);
   launch_sweep_y(L, m, P, TB, dtp);                                                // boxes 12a-c, Y
-  const TSetT<F> *cur = &TB;
+  const TSetT<F> *cur = &TB, *other = &TA;
   if (m.d3) {
     launch_sweep_z(L, m, (const F *)P.vz, TB, TA, dtp);                            // Z
     cur = &TA;
+    other = &TB;
   }
-  launch_ring_x(L, m, (const F *)P.vx, *cur, S, ctx->v0, ctx->nshift, ctx->xi, dtp); // X, FARGO, 12d (v_x)
-  launch_vel(L, m, S, *cur);                                                       // 12d (v_y, v_z)
+  launch_ring_x(L, m, (const F *)P.vx, *cur, *other, S, ctx->v0, ctx->nshift, ctx->xi, dtp); // X, FARGO, 12d (v_x)
+  launch_vel(L, m, S, *other);                                                     // 12d (v_y, v_z)
 }
 
 } // namespace
@@ -633,6 +683,208 @@ int fargo_timings(fargo_ctx *ctx, const char **names, int64_t *counts, double *t
   }
   if (n_out) *n_out = n;
   return FARGO_OK;
+}
+
+} // extern "C"
+
+// ------------------------------------------------------------------------
+// Batches of independent contexts (many disks of uneven sizes): one step of
+// every context is captured once into a hipGraph, the disks spread over
+// `lanes` capture streams that fork from and join into one origin stream, and
+// replayed with a single graph launch per step.  Each context keeps its own
+// device time step (box 6), so nothing synchronises the host.
+// ------------------------------------------------------------------------
+struct fargo_batch {
+  std::vector<fargo_ctx *> ctx;
+  std::vector<fargo_state> st;
+  int lanes = 1;
+  hipStream_t origin = nullptr;
+  std::vector<hipStream_t> ls;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void batch_release_graph(fargo_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  for (hipStream_t s : b->ls) (void)hipStreamDestroy(s);
+  b->ls.clear();
+}
+
+// capture one step of every context; lanes streams of default priority
+int batch_capture(fargo_batch *b, int lanes) {
+  batch_release_graph(b);
+  b->lanes = lanes;
+  for (int l = 0; l < lanes; l++) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return FARGO_EHIP;
+    b->ls.push_back(s);
+  }
+  std::vector<bool> prof_on(b->ctx.size());
+  for (size_t d = 0; d < b->ctx.size(); d++) { // no event records inside the graph
+    prof_on[d] = b->ctx[d]->prof.on;
+    b->ctx[d]->prof.on = false;
+  }
+  int rc = FARGO_OK;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join(lanes, nullptr);
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) rc = FARGO_EHIP;
+  for (int l = 0; l < lanes && !rc; l++)
+    if (hipEventCreateWithFlags(&join[l], hipEventDisableTiming) != hipSuccess) rc = FARGO_EHIP;
+  bool capturing = false;
+  if (!rc && hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = FARGO_EHIP;
+  else if (!rc) capturing = true;
+  if (!rc && hipEventRecord(fork, b->origin) != hipSuccess) rc = FARGO_EHIP;
+  for (int l = 0; l < lanes && !rc; l++)
+    if (hipStreamWaitEvent(b->ls[l], fork, 0) != hipSuccess) rc = FARGO_EHIP;
+  for (size_t d = 0; d < b->ctx.size() && !rc; d++)
+    rc = fargo_step(b->ctx[d], &b->st[d], 0.0, (void *)b->ls[d % lanes]);
+  for (int l = 0; l < lanes && !rc; l++) {
+    if (hipEventRecord(join[l], b->ls[l]) != hipSuccess) rc = FARGO_EHIP;
+    else if (hipStreamWaitEvent(b->origin, join[l], 0) != hipSuccess) rc = FARGO_EHIP;
+  }
+  if (capturing) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->origin, &g);
+    if (!rc && e != hipSuccess) rc = FARGO_EHIP;
+    if (!rc) {
+      b->graph = g;
+      if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) rc = FARGO_EHIP;
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  for (hipEvent_t e : join)
+    if (e) (void)hipEventDestroy(e);
+  for (size_t d = 0; d < b->ctx.size(); d++) b->ctx[d]->prof.on = prof_on[d];
+  (void)hipGetLastError();
+  return rc;
+}
+
+size_t field_bytes(const fargo_ctx *c) { return (size_t)c->m.pitch * c->m.nyg * c->m.nzg * c->esize; }
+
+} // namespace
+
+extern "C" {
+
+int fargo_batch_create(fargo_ctx *const *ctxs, const fargo_state *states, int count, int lanes,
+                       fargo_batch **out) {
+  if (!ctxs || !states || !out || count < 1 || lanes < 1 || lanes > 64) return FARGO_EINVAL;
+  for (int d = 0; d < count; d++) {
+    if (!ctxs[d]) return FARGO_EINVAL;
+    int rc = check_state(ctxs[d], &states[d]);
+    if (rc) return rc;
+    if (ctxs[d]->dev != ctxs[0]->dev) return FARGO_EINVAL;
+  }
+  fargo_batch *b = new (std::nothrow) fargo_batch();
+  if (!b) return FARGO_ENOMEM;
+  b->ctx.assign(ctxs, ctxs + count);
+  b->st.assign(states, states + count);
+  if (hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return FARGO_EHIP;
+  }
+  int rc = batch_capture(b, lanes);
+  if (rc) {
+    fargo_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return FARGO_OK;
+}
+
+int fargo_batch_step(fargo_batch *b, void *stream) {
+  if (!b || !b->exec) return FARGO_EINVAL;
+  return hip_ok(hipGraphLaunch(b->exec, (hipStream_t)stream));
+}
+
+int fargo_batch_tune(fargo_batch *b, const int32_t *lanes, int nlanes, const int32_t *chunks, int nchunks,
+                     int steps, void *stream, int32_t *best) {
+  if (!b || !lanes || nlanes < 1 || !chunks || nchunks < 1 || steps < 1) return FARGO_EINVAL;
+  for (int t = 0; t < nlanes; t++)
+    if (lanes[t] < 1 || lanes[t] > 64) return FARGO_EINVAL;
+  for (int t = 0; t < nchunks; t++)
+    if (chunks[t] < 1) return FARGO_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return FARGO_EHIP;
+  // the evolving fields are saved and restored: tuning leaves the states as found
+  std::vector<std::pair<void *, size_t>> fields;
+  for (size_t d = 0; d < b->ctx.size(); d++) {
+    const fargo_state &st = b->st[d];
+    void *f[5] = {st.rho, st.vx, st.vy, b->ctx[d]->m.d3 ? st.vz : nullptr,
+                  b->ctx[d]->p.eos == FARGO_ADIABATIC ? st.e : nullptr};
+    for (void *p : f)
+      if (p) fields.push_back({p, field_bytes(b->ctx[d])});
+  }
+  size_t total = 0;
+  for (auto &f : fields) total += f.second;
+  void *save = nullptr;
+  if (hipMalloc(&save, total) != hipSuccess) return FARGO_ENOMEM;
+  int rc = FARGO_OK;
+  {
+    size_t o = 0;
+    for (auto &f : fields) {
+      if (hipMemcpyAsync((char *)save + o, f.first, f.second, hipMemcpyDeviceToDevice, s) != hipSuccess) rc = FARGO_EHIP;
+      o += f.second;
+    }
+  }
+  std::vector<int> chunk0(b->ctx.size());
+  for (size_t d = 0; d < b->ctx.size(); d++) chunk0[d] = b->ctx[d]->m.chunk;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = FARGO_EHIP;
+  float best_ms = 0.0f;
+  int best_l = b->lanes, best_c = chunk0[0];
+  for (int ci = 0; ci < nchunks && !rc; ci++)
+    for (int li = 0; li < nlanes && !rc; li++) {
+      for (auto *c : b->ctx) c->m.chunk = chunks[ci];
+      rc = batch_capture(b, lanes[li]);
+      if (rc) break;
+      if (hipGraphLaunch(b->exec, s) != hipSuccess) rc = FARGO_EHIP; // warm-up
+      if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = FARGO_EHIP;
+      for (int k = 0; k < steps && !rc; k++)
+        if (hipGraphLaunch(b->exec, s) != hipSuccess) rc = FARGO_EHIP;
+      if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = FARGO_EHIP;
+      float ms = 0.0f;
+      if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = FARGO_EHIP;
+      if (!rc && (best_ms == 0.0f || ms < best_ms)) {
+        best_ms = ms;
+        best_l = lanes[li];
+        best_c = chunks[ci];
+      }
+      // back to the saved state before the next candidate
+      size_t o = 0;
+      for (auto &f : fields) {
+        if (!rc && hipMemcpyAsync(f.first, (char *)save + o, f.second, hipMemcpyDeviceToDevice, s) != hipSuccess)
+          rc = FARGO_EHIP;
+        o += f.second;
+      }
+    }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = FARGO_EHIP;
+  (void)hipFree(save);
+  for (size_t d = 0; d < b->ctx.size(); d++) b->ctx[d]->m.chunk = rc ? chunk0[d] : best_c;
+  int rc2 = batch_capture(b, rc ? b->lanes : best_l);
+  if (!rc) rc = rc2;
+  if (!rc && best) {
+    best[0] = best_l;
+    best[1] = best_c;
+  }
+  return rc;
+}
+
+void fargo_batch_destroy(fargo_batch *b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  batch_release_graph(b);
+  if (b->origin) (void)hipStreamDestroy(b->origin);
+  delete b;
 }
 
 } // extern "C"

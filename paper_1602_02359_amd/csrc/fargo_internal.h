@@ -25,13 +25,17 @@ struct GeoTables {
   const double *sxj, *syj, *szj, *invVj;           // nyg, nyg+1, nyg, nyg
   const double *sxk, *syk, *szk;                   // nzg, nzg, nzg+1
   const double *dxlen;                             // nzg*nyg: azimuthal zone length
+  // reciprocals (1/dxlen, 1/hy, 1/Ly, 1/ymin, 1/ymed), cot(zmin) (spherical),
+  // 1/(zmed[k] - zmed[k-1]) and 1/(zmin[k+1] - zmin[k])
+  const double *inv_dxlen, *inv_hy, *inv_Ly, *inv_ymin, *inv_ymed, *cotz, *inv_dzmed, *inv_dz;
 };
 
 struct Mesh {
   int nx, ny, nz, pitch, nyg, nzg, j0, jn, k0, kn, d3;
-  int geo, eos, fargo, v0_mean;
+  int geo, eos, fargo, v0_mean, visc;
   int bc[4];
   int nring; // ny * nz active rings
+  int chunk; // zones per thread of the Y and Z column sweeps (a tuning parameter)
   double dx, gamma, omega, courant, cvnr, shear_c0;
   GeoTables g;
 
@@ -141,8 +145,8 @@ void prof_begin(Launch &L, int kid);
 void prof_end(Launch &L, int kid);
 
 enum KernelId {
-  K_SET_DT = 0, K_BC_FACES, K_BC_GHOSTS, K_CFL, K_DT_FINAL, K_SPLIT, K_SRC, K_SWEEP_Y, K_SWEEP_Z, K_RING_X, K_VEL,
-  K_SHIFT, K_SUMS, K_SUMS_FINAL,
+  K_SET_DT = 0, K_BC_FACES, K_BC_GHOSTS, K_CFL, K_DT_FINAL, K_SPLIT, K_SRC, K_SRC_GHOSTS, K_VISC, K_SWEEP_Y,
+  K_SWEEP_Z, K_RING_X, K_VEL, K_SHIFT, K_SUMS, K_SUMS_FINAL,
   K_COUNT
 };
 extern const char *kernel_names[K_COUNT];
@@ -158,7 +162,7 @@ struct DevWords {
 template <typename R>
 struct StateT {
   R *rho, *vx, *vy, *vz, *e;
-  const R *cs, *pot;
+  const R *cs, *pot, *nu;
 };
 
 // Each launcher is defined once for R = double and R = float.
@@ -178,14 +182,20 @@ void launch_split(Launch &L, const Mesh &m, const double *v0, double dt, int32_t
 // box 7: post-source velocities and energy into vx2, vy2, vz2, e2
 template <typename R>
 void launch_source(Launch &L, const Mesh &m, const StateT<R> &s, const double *dt, R *vx2, R *vy2, R *vz2, R *e2);
+// box 7d: viscous stress (cylindrical 2D) from vx2, vy2 into vx3, vy3
+template <typename R>
+void launch_visc(Launch &L, const Mesh &m, const StateT<R> &s, const R *vx2, const R *vy2, R *vx3, R *vy3,
+                 const double *dt);
 // box 12
 template <typename R>
 void launch_sweep_y(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &out, const double *dt);
 template <typename R>
 void launch_sweep_z(Launch &L, const Mesh &m, const R *vz, const TSetT<R> &in, const TSetT<R> &out, const double *dt);
+// X sweep, FARGO and 12d along X: reads T, writes rho, v_x, e of the state and
+// the Y/Z momenta into Tout (out of place, shifted)
 template <typename R>
-void launch_ring_x(Launch &L, const Mesh &m, const R *vx2, const TSetT<R> &T, const StateT<R> &s, const double *v0,
-                   const int32_t *N, const double *xi, const double *dt);
+void launch_ring_x(Launch &L, const Mesh &m, const R *vx2, const TSetT<R> &T, const TSetT<R> &Tout,
+                   const StateT<R> &s, const double *v0, const int32_t *N, const double *xi, const double *dt);
 template <typename R>
 void launch_vel(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &T);
 // misc

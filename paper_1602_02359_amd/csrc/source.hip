@@ -10,274 +10,316 @@
 //   7c  compressional heating of a gamma-law gas, time-centred:
 //       e <- e (1 - a)/(1 + a), a = dt (gamma - 1) div(v) / 2.
 // A zone owns its lower X, Y and Z faces (the lower Y/Z boundary face only in
-// a periodic direction).  Active zones recompute the few intermediate face
-// values their stencil needs (v' on four faces and q in three zones per
-// direction) instead of storing them.  Results go to separate arrays (v'',
-// e''), so the pass reads the state while it writes.
+// a periodic direction); faces that are not owned keep v^n.  Results go to
+// separate arrays (v'', e''), so the pass reads the state while it writes.
+//
+// Layout of the work: a workgroup takes a tile of TX x TY zones of one (X, Y)
+// plane and marches through the Z planes.  For each plane the tile and a halo
+// of two zones in X and Y are staged in LDS; the v' of every X and Y face of
+// the tile (and of the halo faces its stencil needs) is computed once and
+// kept in LDS with the reciprocal of its density sum, then each zone forms q
+// on its neighbours and its v'' and e''.  Along Z each thread keeps a sliding
+// window of its own column in registers (planes k-1 .. k+2), which also
+// supplies the tile's interior values to LDS, so each interior value is read
+// from memory once.  Geometric lengths enter through reciprocal tables.
+//
+// The field type F is double, or float for the FP32-bulk state; arithmetic is
+// carried out in F, geometric factors are rounded to F where they are used.
 #include "fargo_internal.h"
 
 namespace fargo {
 
 namespace {
 
-// The field type F is double, or float for the FP32-bulk state; arithmetic is
-// carried out in F, geometric factors are rounded to F where they are used.
-template <typename F>
-struct Src {
-  Mesh m;
-  StateT<F> s;
-  F dt;
-
-  __device__ inline F P(unsigned c) const {
-    return m.eos == FARGO_ISOTHERMAL ? s.cs[c] * s.cs[c] * s.rho[c] : (F)(m.gamma - 1.0) * s.e[c];
-  }
-  __device__ inline bool yowned(int jj) const { return jj >= m.ylo() && jj < m.jn; }
-  __device__ inline bool zowned(int kk) const { return kk >= m.zlo() && kk < m.kn; }
-};
+constexpr int TX = 64, TY = 8;          // tile; one wave per tile row
+constexpr int SX = TX + 4, SY = TY + 4; // with two halo zones on each side
+constexpr int NT = TX * TY;
 
 template <typename F>
 __device__ inline F qvisc(F c2, F rho, F dv) { return dv < F(0) ? c2 * rho * dv * dv : F(0); }
 
-// What a zone's Z stencil needs from one plane of its column.
 template <typename F>
-struct Plane {
-  F rho, P, pot, vz, vx, vxp; // vxp: v_x on the next X face (spherical centrifugal term)
+struct Lds {
+  F R[2][SY][SX];  // density (two planes in flight)
+  F P[SY][SX];     // pressure
+  F Ph[SY][SX];    // potential
+  F VX[SY][SX];    // v_x on the lower X face of each zone slot
+  F VY[SY][TX];    // v_y on the lower Y face of each zone slot
+  F VT[SY][TX];    // spherical: v_theta on the zone's two Z faces, summed
+  F AX[TY][SX];    // v'_x of X faces of the tile rows
+  F IX[TY][SX];    // 1 / ((rho_i + rho_{i-1}) dX) on those faces
+  F AY[SY][TX];    // v'_y of Y faces
+  F IY[SY][TX];    // 1 / ((rho_j + rho_{j-1}) h_y) on those faces
 };
 
-// X and Y parts of box 7 at zone (i, j, k): v''_x of face i and v''_y of face
-// j (written), and the heating and divergence contributions.  The values of
-// the five zones of each stencil are loaded once and the four face values
-// v' per direction are formed from them.
+// one zone's values in one plane
 template <typename F>
-__device__ inline void xy_part(const Src<F> &S, int i, int j, int k, unsigned c, F *__restrict__ vx2,
-                               F *__restrict__ vy2, F &heat, F &flux) {
-  const Mesh &m = S.m;
-  const StateT<F> &s = S.s;
-  const F dt = S.dt, c2 = (F)(m.cvnr * m.cvnr), om = (F)m.omega;
-  const unsigned row = c - (unsigned)i;
-  // ---- X: zones i-2 .. i+2, faces i-1 .. i+2
-  {
-    int ix[5];
-    ix[2] = i;
-    ix[1] = i == 0 ? m.nx - 1 : i - 1;
-    ix[0] = ix[1] == 0 ? m.nx - 1 : ix[1] - 1;
-    ix[3] = i + 1 == m.nx ? 0 : i + 1;
-    ix[4] = ix[3] + 1 == m.nx ? 0 : ix[3] + 1;
-    F r[5], P[5], ph[5], a[4];
-#pragma unroll
-    for (int t = 0; t < 5; t++) {
-      unsigned cc = row + (unsigned)ix[t];
-      r[t] = s.rho[cc];
-      P[t] = S.P(cc);
-      ph[t] = s.pot[cc];
-    }
-    const F dX = (F)m.DX(j, k);
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-      F gradP = F(2) * (P[t + 1] - P[t]) / ((r[t + 1] + r[t]) * dX);
-      F gradPhi = (ph[t + 1] - ph[t]) / dX;
-      a[t] = s.vx[row + (unsigned)ix[t + 1]] - dt * (gradP + gradPhi);
-    }
-    F dvx = a[2] - a[1];
-    F qx = qvisc(c2, r[2], dvx);
-    F qxm = qvisc(c2, r[1], a[1] - a[0]), qxp = qvisc(c2, r[3], a[3] - a[2]);
-    F bx1 = a[1] - dt * F(2) * (qx - qxm) / ((r[2] + r[1]) * dX);
-    F bx2 = a[2] - dt * F(2) * (qxp - qx) / ((r[3] + r[2]) * dX);
-    vx2[c] = bx1;
-    heat = qx * dvx / dX;
-    flux = (F)m.Sx(j, k) * (bx2 - bx1);
-  }
-  // ---- Y: zones jy[0..4] = below(below(j)) .. above(above(j)); faces jy[1..4]
-  {
-    int jy[5];
-    jy[2] = j;
-    jy[1] = m.jbelow(j);
-    jy[0] = m.jbelow(jy[1]);
-    jy[3] = m.jabove(j);
-    jy[4] = m.jabove(jy[3]);
-    const int ip = i + 1 == m.nx ? 0 : i + 1;
-    const int kp = m.d3 ? m.kabove(k) : k;
-    const bool sph = m.geo == FARGO_SPHERICAL, cyl = m.geo == FARGO_CYLINDRICAL;
-    const unsigned plane = (unsigned)m.plane();
-    F r[5], P[5], ph[5], vt[5], vth[5], a[4];
-#pragma unroll
-    for (int t = 0; t < 5; t++) {
-      unsigned cc = m.o32(i, jy[t], k);
-      r[t] = s.rho[cc];
-      P[t] = S.P(cc);
-      ph[t] = s.pot[cc];
-      // azimuthal velocity in the inertial frame on the two X faces of the zone
-      F R = (F)(sph ? m.g.ymed[jy[t]] * m.g.sinz[k] : m.g.ymed[jy[t]]);
-      vt[t] = (s.vx[cc] + R * om) + (s.vx[cc - (unsigned)i + (unsigned)ip] + R * om);
-      vth[t] = sph ? s.vz[cc] + s.vz[cc + (kp - k) * plane] : F(0);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-      int f = jy[t + 1];
-      unsigned cf = m.o32(i, f, k);
-      if (!S.yowned(f)) {
-        a[t] = s.vy[cf];
-        continue;
-      }
-      F h = (F)m.g.hy[f];
-      F gradP = F(2) * (P[t + 1] - P[t]) / ((r[t + 1] + r[t]) * h);
-      F gradPhi = (ph[t + 1] - ph[t]) / h;
-      F src = F(0);
-      if (cyl || sph) {
-        F v = F(0.25) * (vt[t + 1] + vt[t]);
-        src = v * v;
-        if (sph) {
-          F w = F(0.25) * (vth[t + 1] + vth[t]);
-          src += w * w;
-        }
-        src /= (F)m.g.ymin[f];
-      }
-      a[t] = s.vy[cf] - dt * (gradP + gradPhi) + dt * src;
-    }
-    F dvy = a[2] - a[1];
-    F qy = qvisc(c2, r[2], dvy);
-    F by1 = a[1], by2 = a[2]; // v^n on faces that are not owned
-    if (S.yowned(j)) {
-      F qb = qvisc(c2, r[1], a[1] - a[0]);
-      by1 = a[1] - dt * F(2) * (qy - qb) / ((r[2] + r[1]) * (F)m.g.hy[j]);
-    }
-    if (S.yowned(jy[3])) {
-      F qa = qvisc(c2, r[3], a[3] - a[2]);
-      by2 = a[2] - dt * F(2) * (qa - qy) / ((r[3] + r[2]) * (F)m.g.hy[jy[3]]);
-    }
-    vy2[c] = by1;
-    heat += qy * dvy / (F)m.g.Ly[j];
-    flux += (F)m.Sy(j + 1, k) * by2 - (F)m.Sy(j, k) * by1;
-  }
-}
+struct Zv {
+  F rho, P, pot, vz, vx, vxp; // vxp: v_x on the next X face
+};
 
-// 7c: e'' of zone c from e, the heating and the face-flux divergence sum
-template <typename F>
-__device__ inline void energy(const Src<F> &S, int j, int k, unsigned c, F heat, F flux, F *__restrict__ e2) {
-  const Mesh &m = S.m;
-  F e1 = S.s.e[c] - S.dt * heat;
-  F a = F(0.5) * S.dt * (F)(m.gamma - 1.0) * ((F)m.Vinv(j, k) * flux);
-  e2[c] = e1 * (F(1) - a) / (F(1) + a);
-}
-
-// One thread per (i, j) column marching along Z: the Z stencil of a zone
-// (planes k-2 .. k+2, in the periodic order when Z is periodic) lives in a
-// register window, so each value of the column is loaded once; the Y
-// neighbours come from the columns of co-scheduled blocks (j fastest) at the
-// same plane.  Ghost zones copy v^n and e.
-template <typename F>
-__global__ __launch_bounds__(256, 3) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
-                                                F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
-                                                F *__restrict__ e2) {
-  unsigned L = xcd_remap(blockIdx.x, gridDim.x);
-  int j = (int)(L % (unsigned)m.nyg);
-  int ib = (int)(L / (unsigned)m.nyg);
-  int i = ib * (int)blockDim.x + (int)threadIdx.x;
-  if (i >= m.nx) return;
+template <typename F, bool D3>
+__global__ __launch_bounds__(NT, 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
+                                                  F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
+                                                  F *__restrict__ e2, int nbx, int nby) {
+  __shared__ Lds<F> L;
+  const int tid = threadIdx.x, r = tid >> 6, c = tid & 63;
+  const unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int ty = (int)(Lb % (unsigned)nby), tx = (int)(Lb / (unsigned)nby);
+  const int i0 = tx * TX, jt0 = m.j0 + ty * TY;
+  const int w = min(TX, m.nx - i0), h = min(TY, m.jn - jt0);
+  const bool act = r < h && c < w;
+  const int i = i0 + c, j = jt0 + r;
   const bool adi = m.eos == FARGO_ADIABATIC;
-  auto copy = [&](int k) {
-    unsigned c = m.o32(i, j, k);
-    vx2[c] = s.vx[c];
-    vy2[c] = s.vy[c];
-    if (m.d3) vz2[c] = s.vz[c];
-    if (adi) e2[c] = s.e[c];
+  const bool sph = m.geo == FARGO_SPHERICAL, cyl = m.geo == FARGO_CYLINDRICAL;
+  const F dt = (F)*dtp, c2 = (F)(m.cvnr * m.cvnr), om = (F)m.omega, gm1 = (F)(m.gamma - 1.0);
+  const unsigned plane = (unsigned)m.plane();
+
+  // storage column of X slot sl (i0 - 2 + sl, periodic) and row of Y slot t
+  auto xcol = [&](int sl) {
+    int x = i0 - 2 + sl;
+    if (m.nx >= 2) return x < 0 ? x + m.nx : (x >= m.nx ? x - m.nx : x);
+    return 0;
   };
-  if (j < m.j0 || j >= m.jn) {
-#pragma unroll 1
-    for (int k = 0; k < m.nzg; k++) copy(k);
-    return;
-  }
-#pragma unroll 1
-  for (int k = 0; k < m.k0; k++) copy(k);
-#pragma unroll 1
-  for (int k = m.kn; k < m.nzg; k++) copy(k);
-  const Src<F> S{m, s, (F)*dtp};
-  const F dt = S.dt, c2 = (F)(m.cvnr * m.cvnr);
-  if (!m.d3) {
-    unsigned c = m.o32(i, j, 0);
-    F heat, flux;
-    xy_part(S, i, j, 0, c, vx2, vy2, heat, flux);
-    if (adi) energy(S, j, 0, c, heat, flux, e2);
-    return;
-  }
-  const int ip = i + 1 == m.nx ? 0 : i + 1;
-  const bool per = m.zper();
-  // plane p of the march, with periodic wrap over the active range if needed
-  auto pl = [&](int p) { return per ? m.k0 + (p - m.k0 + 2 * m.nz) % m.nz : p; };
-  auto load = [&](int p, Plane<F> &z) {
-    unsigned c = m.o32(i, j, p);
-    z.rho = s.rho[c];
-    z.P = S.P(c);
-    z.pot = s.pot[c];
-    z.vz = s.vz[c];
-    z.vx = s.vx[c];
-    z.vxp = s.vx[c - i + ip];
+  auto yrow = [&](int t) {
+    int y = jt0 - 2 + t;
+    if (m.yper()) y = y < m.j0 ? y + m.ny : (y >= m.jn ? y - m.ny : y);
+    return y;
   };
-  // v'_z on face p (planes below(p) = zb and p = z0), v^n if not owned
-  auto vz1 = [&](int p, const Plane<F> &zb, const Plane<F> &z0) {
-    if (!S.zowned(p)) return z0.vz;
-    F h = (F)m.hz(j, p);
-    F gradP = F(2) * (z0.P - zb.P) / ((z0.rho + zb.rho) * h);
-    F gradPhi = (z0.pot - zb.pot) / h;
+  auto yowned = [&](int f) { return f >= m.ylo() && f < m.jn; };
+  auto zowned = [&](int f) { return f >= m.zlo() && f < m.kn; };
+  auto pres = [&](unsigned o) { return adi ? gm1 * s.e[o] : s.cs[o] * s.cs[o] * s.rho[o]; };
+  auto loadz = [&](int k, Zv<F> &z) {
+    const unsigned o = m.o32(i, j, k);
+    const int ip = i + 1 == m.nx ? 0 : i + 1;
+    z.rho = s.rho[o];
+    z.P = pres(o);
+    z.pot = s.pot[o];
+    z.vz = D3 ? s.vz[o] : F(0);
+    z.vx = s.vx[o];
+    z.vxp = sph ? s.vx[o - (unsigned)i + (unsigned)ip] : F(0);
+  };
+  // v'_z on face p between planes below(p) (zb) and p (z0); v^n if not owned.
+  // iz receives 1 / ((rho + rho_below) h_z) for the viscous term.
+  auto vz1 = [&](int p, const Zv<F> &zb, const Zv<F> &z0, F &iz) {
+    iz = F(0);
+    if (!zowned(p)) return z0.vz;
+    const F ihz = sph ? (F)(m.g.inv_dzmed[p] * m.g.inv_ymed[j]) : (F)m.g.inv_dzmed[p];
+    iz = ihz / (z0.rho + zb.rho);
+    F gradP = F(2) * (z0.P - zb.P) * iz;
+    F gradPhi = (z0.pot - zb.pot) * ihz;
     F src = F(0);
-    if (m.geo == FARGO_SPHERICAL) {
-      const F om = (F)m.omega;
+    if (sph) {
       F R0 = (F)(m.g.ymed[j] * m.g.sinz[p]), R1 = (F)(m.g.ymed[j] * m.g.sinz[m.kbelow(p)]);
       F vt = F(0.25) * ((z0.vx + R0 * om) + (z0.vxp + R0 * om) + (zb.vx + R1 * om) + (zb.vxp + R1 * om));
-      double zf = m.g.zmin[p];
-      src = vt * vt * (F)(cos(zf) / sin(zf)) / (F)m.g.ymed[j];
+      src = vt * vt * (F)m.g.cotz[p] * (F)m.g.inv_ymed[j];
     }
     return z0.vz - dt * (gradP + gradPhi) + dt * src;
   };
-  // window: full records of the two newest planes (Pa = k+1, Pb = k+2), the
-  // densities of planes k-1 .. k+2 (R[0..3]) and v^n_z on faces k, k+1;
-  // v'_z on faces k-1 .. k+2 (A[0..3]); q_z in zones k-1 .. k+1 (Q[0..2])
-  const int k = m.k0;
-  Plane<F> Pa, Pb;
-  F R[4], A[4], Q[3], V0, V1;
-  load(pl(k - 2), Pa);
-  load(pl(k - 1), Pb);
-  A[0] = vz1(pl(k - 1), Pa, Pb);
-  R[0] = Pb.rho;
-  load(k, Pa);
-  A[1] = vz1(k, Pb, Pa);
-  R[1] = Pa.rho;
-  V0 = Pa.vz;
-  load(pl(k + 1), Pb);
-  A[2] = vz1(pl(k + 1), Pa, Pb);
-  R[2] = Pb.rho;
-  V1 = Pb.vz;
-  Q[0] = qvisc(c2, R[0], A[1] - A[0]);
-  Q[1] = qvisc(c2, R[1], A[2] - A[1]);
-  Pa = Pb; // plane k+1
+  const bool per = m.zper();
+  auto pl = [&](int p) { return per ? m.k0 + (p - m.k0 + 2 * m.nz) % m.nz : p; };
+
+  // Z window of the thread's column: planes k-1 (rho only), k, k+1, k+2
+  Zv<F> Z0{}, Z1{}, Z2{};
+  F Rm1 = F(0), A[4] = {}, IZ[4] = {}, Q[3] = {};
+  const int kfirst = m.k0, klast = m.kn;
+  if (act) {
+    if (D3) {
+      Zv<F> Zm2, Zm1;
+      loadz(pl(kfirst - 2), Zm2);
+      loadz(pl(kfirst - 1), Zm1);
+      A[0] = vz1(pl(kfirst - 1), Zm2, Zm1, IZ[0]);
+      Rm1 = Zm1.rho;
+      loadz(kfirst, Z0);
+      A[1] = vz1(kfirst, Zm1, Z0, IZ[1]);
+      loadz(pl(kfirst + 1), Z1);
+      A[2] = vz1(pl(kfirst + 1), Z0, Z1, IZ[2]);
+      Q[0] = qvisc(c2, Rm1, A[1] - A[0]);
+      Q[1] = qvisc(c2, Z0.rho, A[2] - A[1]);
+    } else {
+      loadz(0, Z0);
+    }
+  }
+
+  int buf = 0;
 #pragma unroll 1
-  for (int kk = m.k0; kk < m.kn; kk++) {
-    const int ka = pl(kk + 1), kaa = pl(kk + 2);
-    load(kaa, Pb);
-    A[3] = vz1(kaa, Pa, Pb);
-    R[3] = Pb.rho;
-    Q[2] = qvisc(c2, R[2], A[3] - A[2]);
-    unsigned c = m.o32(i, j, kk);
-    F heat, flux;
-    xy_part(S, i, j, kk, c, vx2, vy2, heat, flux);
-    F bz1 = V0, bz2 = V1;
-    if (S.zowned(kk)) bz1 = A[1] - dt * F(2) * (Q[1] - Q[0]) / ((R[1] + R[0]) * (F)m.hz(j, kk));
-    if (S.zowned(ka)) bz2 = A[2] - dt * F(2) * (Q[2] - Q[1]) / ((R[2] + R[1]) * (F)m.hz(j, ka));
-    vz2[c] = bz1;
-    heat += Q[1] * (A[2] - A[1]) / (F)m.Lz(j, kk);
-    flux += (F)m.Sz(j, kk + 1) * bz2 - (F)m.Sz(j, kk) * bz1;
-    if (adi) energy(S, j, kk, c, heat, flux, e2);
-    R[0] = R[1];
-    R[1] = R[2];
-    R[2] = R[3];
-    A[0] = A[1];
-    A[1] = A[2];
-    A[2] = A[3];
-    Q[0] = Q[1];
-    Q[1] = Q[2];
-    V0 = V1;
-    V1 = Pb.vz;
-    Pa = Pb;
+  for (int kk = kfirst; kk < klast; kk++) {
+    const int ka = D3 ? pl(kk + 1) : kk;
+    if (D3 && act) {
+      loadz(pl(kk + 2), Z2);
+      A[3] = vz1(pl(kk + 2), Z1, Z2, IZ[3]);
+      Q[2] = qvisc(c2, Z1.rho, A[3] - A[2]);
+    }
+    const int kp = D3 ? m.kabove(kk) : kk;
+    F(*R)[SX] = L.R[buf];
+    // ---- stage plane kk: interior from the window, halo from memory
+    if (act) {
+      R[r + 2][c + 2] = Z0.rho;
+      L.P[r + 2][c + 2] = Z0.P;
+      L.Ph[r + 2][c + 2] = Z0.pot;
+      L.VX[r + 2][c + 2] = Z0.vx;
+      if (sph) L.VT[r + 2][c] = Z0.vz + Z1.vz;
+      L.VY[r + 2][c] = s.vy[m.o32(i, j, kk)];
+    }
+    auto halo_zone = [&](int t, int sl, bool need_vy, bool need_vt) {
+      const int y = yrow(t), x = xcol(sl);
+      const unsigned o = m.o32(x, y, kk);
+      R[t][sl] = s.rho[o];
+      L.P[t][sl] = pres(o);
+      L.Ph[t][sl] = s.pot[o];
+      L.VX[t][sl] = s.vx[o];
+      if (need_vy) L.VY[t][sl - 2] = s.vy[o];
+      if (need_vt) L.VT[t][sl - 2] = s.vz[o] + s.vz[o + (unsigned)(kp - kk) * plane];
+    };
+    if (tid < 256) {
+      // Y halo rows 0, 1, h+2, h+3 over the tile's columns
+      const int q = tid >> 6, t = q < 2 ? q : h + q;
+      if (c < w) halo_zone(t, c + 2, t != 0, sph);
+    } else if (tid < 256 + 4 * TY) {
+      // X halo slots 0, 1, w+2, w+3 of the tile rows
+      const int q = tid - 256, rr = q >> 2, a = q & 3, sl = a < 2 ? a : w + a;
+      if (rr < h) halo_zone(rr + 2, sl, false, false);
+    } else if (tid < 256 + 4 * TY + 4) {
+      // v_x on the X face after the last column, in the Y halo rows
+      const int q = tid - 256 - 4 * TY, t = q < 2 ? q : h + q;
+      L.VX[t][w + 2] = s.vx[m.o32(xcol(w + 2), yrow(t), kk)];
+    }
+    __syncthreads();
+    // ---- 7a on the X and Y faces of the tile and of the halo faces needed
+    auto xface = [&](int rr, int sl) {
+      const int t = rr + 2, y = jt0 + rr;
+      const F idX = (F)m.g.inv_dxlen[(size_t)kk * m.nyg + y];
+      const F inv = idX / (R[t][sl] + R[t][sl - 1]);
+      const F gradP = F(2) * (L.P[t][sl] - L.P[t][sl - 1]) * inv;
+      const F gradPhi = (L.Ph[t][sl] - L.Ph[t][sl - 1]) * idX;
+      L.AX[rr][sl] = L.VX[t][sl] - dt * (gradP + gradPhi);
+      L.IX[rr][sl] = inv;
+    };
+    auto yface = [&](int t, int cc) {
+      const int f = yrow(t), sl = cc + 2;
+      if (!yowned(f)) {
+        L.AY[t][cc] = L.VY[t][cc];
+        L.IY[t][cc] = F(0);
+        return;
+      }
+      const F ih = (F)m.g.inv_hy[f];
+      const F inv = ih / (R[t][sl] + R[t - 1][sl]);
+      const F gradP = F(2) * (L.P[t][sl] - L.P[t - 1][sl]) * inv;
+      const F gradPhi = (L.Ph[t][sl] - L.Ph[t - 1][sl]) * ih;
+      F src = F(0);
+      if (cyl || sph) {
+        const int ya = yrow(t - 1);
+        const F Rt = (F)(sph ? m.g.ymed[f] * m.g.sinz[kk] : m.g.ymed[f]);
+        const F Ra = (F)(sph ? m.g.ymed[ya] * m.g.sinz[kk] : m.g.ymed[ya]);
+        const F vt0 = (L.VX[t][sl] + Rt * om) + (L.VX[t][sl + 1] + Rt * om);
+        const F vt1 = (L.VX[t - 1][sl] + Ra * om) + (L.VX[t - 1][sl + 1] + Ra * om);
+        const F v = F(0.25) * (vt0 + vt1);
+        src = v * v;
+        if (sph) {
+          const F wv = F(0.25) * (L.VT[t][cc] + L.VT[t - 1][cc]);
+          src += wv * wv;
+        }
+        src *= (F)m.g.inv_ymin[f];
+      }
+      L.AY[t][cc] = L.VY[t][cc] - dt * (gradP + gradPhi) + dt * src;
+      L.IY[t][cc] = inv;
+    };
+    if (act) {
+      xface(r, c + 2);
+      yface(r + 2, c);
+    }
+    if (tid < 192) {
+      const int q = tid >> 6, t = q == 0 ? 1 : h + 1 + q;
+      if (c < w) yface(t, c);
+    } else if (tid < 192 + 3 * TY) {
+      const int q = tid - 192, rr = q / 3, a = q % 3, sl = a == 0 ? 1 : w + 1 + a;
+      if (rr < h) xface(rr, sl);
+    }
+    __syncthreads();
+    // ---- 7b and 7c per zone
+    if (act) {
+      const int t = r + 2, sl = c + 2;
+      const unsigned o = m.o32(i, j, kk);
+      // X: faces sl-1 .. sl+2, zones sl-1 .. sl+1
+      const F a0 = L.AX[r][sl - 1], a1 = L.AX[r][sl], a2 = L.AX[r][sl + 1], a3 = L.AX[r][sl + 2];
+      const F r1 = R[t][sl - 1], r2 = R[t][sl], r3 = R[t][sl + 1];
+      const F dvx = a2 - a1;
+      const F qx = qvisc(c2, r2, dvx), qxm = qvisc(c2, r1, a1 - a0), qxp = qvisc(c2, r3, a3 - a2);
+      const F bx1 = a1 - dt * F(2) * (qx - qxm) * L.IX[r][sl];
+      const F bx2 = a2 - dt * F(2) * (qxp - qx) * L.IX[r][sl + 1];
+      vx2[o] = bx1;
+      F heat = qx * dvx * (F)m.g.inv_dxlen[(size_t)kk * m.nyg + j];
+      F flux = (F)m.Sx(j, kk) * (bx2 - bx1);
+      // Y: faces t-1 .. t+2, zones t-1 .. t+1
+      const F b0 = L.AY[t - 1][c], b1 = L.AY[t][c], b2 = L.AY[t + 1][c], b3 = L.AY[t + 2][c];
+      const F s1 = R[t - 1][sl], s3 = R[t + 1][sl];
+      const F dvy = b2 - b1;
+      const F qy = qvisc(c2, r2, dvy);
+      F by1 = b1, by2 = b2;
+      if (yowned(j)) by1 = b1 - dt * F(2) * (qy - qvisc(c2, s1, b1 - b0)) * L.IY[t][c];
+      if (yowned(yrow(t + 1))) by2 = b2 - dt * F(2) * (qvisc(c2, s3, b3 - b2) - qy) * L.IY[t + 1][c];
+      vy2[o] = by1;
+      heat += qy * dvy * (F)m.g.inv_Ly[j];
+      flux += (F)m.Sy(j + 1, kk) * by2 - (F)m.Sy(j, kk) * by1;
+      if (D3) {
+        F bz1 = Z0.vz, bz2 = Z1.vz;
+        if (zowned(kk)) bz1 = A[1] - dt * F(2) * (Q[1] - Q[0]) * IZ[1];
+        if (zowned(ka)) bz2 = A[2] - dt * F(2) * (Q[2] - Q[1]) * IZ[2];
+        vz2[o] = bz1;
+        const F iLz = sph ? (F)(m.g.inv_dz[kk] * m.g.inv_ymed[j]) : (F)m.g.inv_dz[kk];
+        heat += Q[1] * (A[2] - A[1]) * iLz;
+        flux += (F)m.Sz(j, kk + 1) * bz2 - (F)m.Sz(j, kk) * bz1;
+      }
+      if (adi) {
+        const F e1 = s.e[o] - dt * heat;
+        const F a = F(0.5) * dt * gm1 * ((F)m.Vinv(j, kk) * flux);
+        e2[o] = e1 * (F(1) - a) / (F(1) + a);
+      }
+      if (D3) {
+        Rm1 = Z0.rho;
+        Z0 = Z1;
+        Z1 = Z2;
+        A[0] = A[1];
+        A[1] = A[2];
+        A[2] = A[3];
+        IZ[0] = IZ[1];
+        IZ[1] = IZ[2];
+        IZ[2] = IZ[3];
+        Q[0] = Q[1];
+        Q[1] = Q[2];
+      }
+    }
+    (void)Rm1;
+    buf ^= 1;
+  }
+}
+
+// Ghost zones (Y ghost rows of every plane, and Z ghost planes of the active
+// rows) carry v^n and e into v'' and e''; one block per row.
+template <typename F>
+__global__ __launch_bounds__(256) void k_source_ghosts(Mesh m, StateT<F> s, F *__restrict__ vx2,
+                                                       F *__restrict__ vy2, F *__restrict__ vz2,
+                                                       F *__restrict__ e2) {
+  const int b = blockIdx.x, ngy = m.nyg - m.ny;
+  int j, k;
+  if (b < m.nzg * ngy) {
+    k = b / ngy;
+    const int g = b % ngy;
+    j = g < m.j0 ? g : m.jn + (g - m.j0);
+  } else {
+    const int q = b - m.nzg * ngy, ngz = m.nzg - m.nz;
+    j = m.j0 + q % m.ny;
+    const int g = q / m.ny;
+    k = g < m.k0 ? g : m.kn + (g - m.k0);
+    (void)ngz;
+  }
+  const unsigned row = m.o32(0, j, k);
+  for (int i = threadIdx.x; i < m.nx; i += blockDim.x) {
+    const unsigned o = row + (unsigned)i;
+    vx2[o] = s.vx[o];
+    vy2[o] = s.vy[o];
+    if (m.d3) vz2[o] = s.vz[o];
+    if (m.eos == FARGO_ADIABATIC) e2[o] = s.e[o];
   }
 }
 
@@ -285,12 +327,16 @@ __global__ __launch_bounds__(256, 3) void k_source(Mesh m, StateT<F> s, const do
 
 template <typename F>
 void launch_source(Launch &L, const Mesh &m, const StateT<F> &s, const double *dt, F *vx2, F *vy2, F *vz2, F *e2) {
-  int nib, bs;
-  row_blocks(m.nx, nib, bs);
-  unsigned nb = (unsigned)nib * (unsigned)m.nyg;
+  const int nbx = (m.nx + TX - 1) / TX, nby = (m.ny + TY - 1) / TY;
+  const unsigned nb = (unsigned)nbx * (unsigned)nby;
+  const unsigned ng = (unsigned)(m.nzg * (m.nyg - m.ny) + (m.d3 ? (m.nzg - m.nz) * m.ny : 0));
   prof_begin(L, K_SRC);
-  k_source<F><<<nb, bs, 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2);
+  if (m.d3) k_source<F, true><<<nb, NT, 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2, nbx, nby);
+  else k_source<F, false><<<nb, NT, 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2, nbx, nby);
   prof_end(L, K_SRC);
+  prof_begin(L, K_SRC_GHOSTS);
+  k_source_ghosts<F><<<ng, 256, 0, L.s>>>(m, s, vx2, vy2, vz2, e2);
+  prof_end(L, K_SRC_GHOSTS);
 }
 
 template void launch_source<double>(Launch &, const Mesh &, const StateT<double> &, const double *, double *, double *,

@@ -124,7 +124,14 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
       double dvz = vzp - vzc;
       if (dvz < 0.0) dt3 = fmin(dt3, Lzz / (4.0 * m.cvnr * m.cvnr * fabs(dvz)));
     }
-    double cell = 1.0 / sqrt(1.0 / (dt1 * dt1) + 1.0 / (dt2 * dt2) + 1.0 / (dt3 * dt3));
+    double inv2 = 1.0 / (dt1 * dt1) + 1.0 / (dt2 * dt2) + 1.0 / (dt3 * dt3);
+    if (m.visc) {
+      // item 4: viscosity, Delta^2 / (4 nu) with the smaller zone size
+      double Lmin = fmin(Lx, Lyy);
+      double dt4 = Lmin * Lmin / (4.0 * (double)s.nu[c]);
+      inv2 += 1.0 / (dt4 * dt4);
+    }
+    double cell = 1.0 / sqrt(inv2);
     if (!(cell >= 0.0)) bad = 1;
     else cmin = cell < cmin ? cell : cmin;
     if (shear_on) {

@@ -29,7 +29,6 @@ namespace fargo {
 
 namespace {
 
-constexpr int CHUNK = 64; // zones per thread along the sweep direction
 
 // van Leer slope per unit length from the one-sided differences and the
 // centre distances below (hm) and above (hp): 2 dl dr/(dl + dr) with
@@ -50,17 +49,26 @@ __device__ inline F vl_star(F w, F dt, F ql, F al, F Ll, F qr, F ar, F Lr) {
 template <typename F, int NQ>
 struct Zone {
   F rho, q[NQ], T[NQ]; // density, Q/rho, conserved Q
+  F w;                 // velocity on the zone's lower face in the sweep direction
 };
 
-// Column sweep over zones [a0, a1) of one column; `ld(a, Zone&)` loads zone a,
-// `geo` gives L(a) (zone width), h(f) (centre distance at face f), S(f),
-// Vi(a), w(f); `st(a, rho, T[])` stores the updated zone.
-template <typename F, int NQ, class LD, class GEO, class ST>
-__device__ inline void column_sweep(int a0, int a1, F dt, const LD &ld, const GEO &geo, const ST &st) {
+// Column sweep over zones [a0, a1) of one column.  `raw(a, RW&)` issues the
+// loads of zone a, `derive(a, const RW&, Zone&)` forms its density, Q/rho, Q
+// and lower-face velocity; `geo` gives L(a) (zone width), h(f) (centre
+// distance at face f), S(f), Vi(a); `st(a, rho, T[])` stores the updated
+// zone.  The loads of zone f + 2 are issued while zone f is being computed.
+template <typename F, int NQ, class RW, class RAW, class DER, class GEO, class ST>
+__device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const DER &derive, const GEO &geo,
+                                    const ST &st) {
   Zone<F, NQ> zm, z0, zp;
-  ld(a0 - 2, zp); // used only for the first slope
-  ld(a0 - 1, zm);
-  ld(a0, z0);
+  RW rn;
+  raw(a0 - 2, rn);
+  derive(a0 - 2, rn, zp); // used only for the first slope
+  raw(a0 - 1, rn);
+  derive(a0 - 1, rn, zm);
+  raw(a0, rn);
+  derive(a0, rn, z0);
+  raw(a0 + 1, rn);
   F sm[NQ + 1], s0[NQ + 1];
   {
     F hm = geo.h(a0 - 1), hp = geo.h(a0);
@@ -72,14 +80,16 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const LD &ld, const GE
 #pragma unroll
   for (int q = 0; q < NQ; q++) FQp[q] = F(0);
   F Lm = geo.L(a0 - 1);
+#pragma unroll 1
   for (int f = a0; f <= a1; f++) {
-    ld(f + 1, zp);
+    derive(f + 1, rn, zp);
+    if (f + 2 <= a1 + 1) raw(f + 2, rn);
     F hm = geo.h(f), hp = geo.h(f + 1);
     s0[NQ] = vl_slope(zm.rho, z0.rho, zp.rho, hm, hp);
 #pragma unroll
     for (int q = 0; q < NQ; q++) s0[q] = vl_slope(zm.q[q], z0.q[q], zp.q[q], hm, hp);
     F L0 = geo.L(f);
-    F w = geo.w(f);
+    F w = z0.w;
     F Fr = w * vl_star(w, dt, zm.rho, sm[NQ], Lm, z0.rho, s0[NQ], L0) * geo.S(f) * dt;
     F FQ[NQ];
 #pragma unroll
@@ -109,7 +119,7 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const LD &ld, const GE
 // Quantities: Pi-_x, Pi+_x, Pi-_y, Pi+_y [, Pi-_z, Pi+_z] [, e].
 // ------------------------------------------------------------------------
 template <typename F, int NQ, bool D3, bool ADI>
-__global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ rho, const F *__restrict__ vx,
+__global__ __launch_bounds__(256, 3) void k_sweep_y(Mesh m, const F *__restrict__ rho, const F *__restrict__ vx,
                                                  const F *__restrict__ vy, const F *__restrict__ vz,
                                                  const F *__restrict__ e, TSetT<F> out,
                                                  const double *__restrict__ dtp, int nchunk) {
@@ -121,54 +131,67 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
   int i = ib * (int)blockDim.x + (int)threadIdx.x;
   if (i >= m.nx) return;
   const int k = kbase + kr;
-  const int a0 = m.j0 + ch * CHUNK, a1 = min(a0 + CHUNK, m.jn);
+  const int a0 = m.j0 + ch * m.chunk, a1 = min(a0 + m.chunk, m.jn);
   const F dt = (F)*dtp;
   const int ip = i + 1 == m.nx ? 0 : i + 1;
   const unsigned pitch = m.pitch, plane = (unsigned)m.plane();
-  auto ld = [&](int a, Zone<F, NQ> &z) {
-    unsigned c = m.o32(i, a, k);
-    F r = rho[c];
-    z.rho = r;
-    z.q[0] = m.mx(a, k, vx[c]);
-    z.q[1] = m.mx(a, k, vx[c - i + ip]);
-    z.q[2] = vy[c];
-    z.q[3] = vy[c + pitch];
+  struct Raw {
+    F rho, vx0, vx1, vy0, vy1, vz0, vz1, e;
+  };
+  auto raw = [&](int a, Raw &z) {
+    const unsigned c = m.o32(i, a, k);
+    z.rho = rho[c];
+    z.vx0 = vx[c];
+    z.vx1 = vx[c - i + ip];
+    z.vy0 = vy[c];
+    z.vy1 = vy[c + pitch];
     if (D3) {
-      z.q[4] = m.mz(a, vz[c]);
-      z.q[5] = m.mz(a, vz[c + plane]);
+      z.vz0 = vz[c];
+      z.vz1 = vz[c + plane];
+    }
+    if (ADI) z.e = e[c];
+  };
+  auto derive = [&](int a, const Raw &w, Zone<F, NQ> &z) {
+    const F r = w.rho;
+    z.rho = r;
+    z.w = w.vy0;
+    z.q[0] = m.mx(a, k, w.vx0);
+    z.q[1] = m.mx(a, k, w.vx1);
+    z.q[2] = w.vy0;
+    z.q[3] = w.vy1;
+    if (D3) {
+      z.q[4] = m.mz(a, w.vz0);
+      z.q[5] = m.mz(a, w.vz1);
     }
 #pragma unroll
     for (int q = 0; q < (ADI ? NQ - 1 : NQ); q++) z.T[q] = r * z.q[q];
     if (ADI) {
-      z.T[NQ - 1] = e[c];
-      z.q[NQ - 1] = e[c] / r;
+      z.T[NQ - 1] = w.e;
+      z.q[NQ - 1] = w.e / r;
     }
   };
   struct Geo {
     const Mesh &m;
-    const F *vy;
-    unsigned base;
     int k;
     __device__ F L(int a) const { return (F)m.g.Ly[a]; }
     __device__ F h(int f) const { return (F)m.g.hy[f]; }
     __device__ F S(int f) const { return (F)m.Sy(f, k); }
     __device__ F Vi(int a) const { return (F)m.Vinv(a, k); }
-    __device__ F w(int f) const { return vy[base + (unsigned)f * (unsigned)m.pitch]; }
-  } geo{m, vy, m.o32(i, 0, k), k};
+  } geo{m, k};
   auto st = [&](int a, F r, const F (&T)[NQ]) {
     unsigned c = m.o32(i, a, k);
     out.a[T_RHO][c] = r;
 #pragma unroll
     for (int q = 0; q < NQ; q++) out.q[q][c] = T[q];
   };
-  column_sweep<F, NQ>(a0, a1, dt, ld, geo, st);
+  column_sweep<F, NQ, Raw>(a0, a1, dt, raw, derive, geo, st);
 }
 
 // ------------------------------------------------------------------------
 // Z sweep on the Y-swept quantities.
 // ------------------------------------------------------------------------
 template <typename F, int NQ>
-__global__ __launch_bounds__(256) void k_sweep_z(Mesh m, const F *__restrict__ vz, TSetT<F> in, TSetT<F> out,
+__global__ __launch_bounds__(256, 3) void k_sweep_z(Mesh m, const F *__restrict__ vz, TSetT<F> in, TSetT<F> out,
                                                  const double *__restrict__ dtp, int nchunk) {
   unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
   int jr = (int)(Lb % (unsigned)m.ny);
@@ -177,37 +200,43 @@ __global__ __launch_bounds__(256) void k_sweep_z(Mesh m, const F *__restrict__ v
   int i = ib * (int)blockDim.x + (int)threadIdx.x;
   if (i >= m.nx) return;
   const int j = m.j0 + jr;
-  const int a0 = m.k0 + ch * CHUNK, a1 = min(a0 + CHUNK, m.kn);
+  const int a0 = m.k0 + ch * m.chunk, a1 = min(a0 + m.chunk, m.kn);
   const F dt = (F)*dtp;
-  auto ld = [&](int a, Zone<F, NQ> &z) {
-    unsigned c = m.o32(i, j, a);
-    F r = in.a[T_RHO][c];
-    F ri = F(1) / r;
-    z.rho = r;
+  struct Raw {
+    F rho, w, T[NQ];
+  };
+  auto raw = [&](int a, Raw &z) {
+    const unsigned c = m.o32(i, j, a);
+    z.rho = in.a[T_RHO][c];
+    z.w = vz[c];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) z.T[q] = in.q[q][c];
+  };
+  auto derive = [&](int, const Raw &w, Zone<F, NQ> &z) {
+    const F ri = F(1) / w.rho;
+    z.rho = w.rho;
+    z.w = w.w;
 #pragma unroll
     for (int q = 0; q < NQ; q++) {
-      z.T[q] = in.q[q][c];
-      z.q[q] = z.T[q] * ri;
+      z.T[q] = w.T[q];
+      z.q[q] = w.T[q] * ri;
     }
   };
   struct Geo {
     const Mesh &m;
-    const F *vz;
-    unsigned base;
     int j;
     __device__ F L(int a) const { return (F)m.Lz(j, a); }
     __device__ F h(int f) const { return (F)m.hz(j, f); }
     __device__ F S(int f) const { return (F)m.Sz(j, f); }
     __device__ F Vi(int a) const { return (F)m.Vinv(j, a); }
-    __device__ F w(int f) const { return vz[base + (unsigned)f * (unsigned)m.plane()]; }
-  } geo{m, vz, m.o32(i, j, 0), j};
+  } geo{m, j};
   auto st = [&](int a, F r, const F (&T)[NQ]) {
     unsigned c = m.o32(i, j, a);
     out.a[T_RHO][c] = r;
 #pragma unroll
     for (int q = 0; q < NQ; q++) out.q[q][c] = T[q];
   };
-  column_sweep<F, NQ>(a0, a1, dt, ld, geo, st);
+  column_sweep<F, NQ, Raw>(a0, a1, dt, raw, derive, geo, st);
 }
 
 // ------------------------------------------------------------------------
@@ -258,108 +287,239 @@ __device__ inline F vlx_star(F q2m, F qm, F q0, F qp, F w, F cw) {
   return q0 - a * (F(1) + cw) * F(0.5);
 }
 
-// neighbour index i + d (|d| <= 2) on a ring of n zones
-__device__ inline int ringnb(int i, int d, int n) {
-  int x = i + d;
-  if (n >= 3) return x < 0 ? x + n : (x >= n ? x - n : x);
-  x %= n;
-  return x < 0 ? x + n : x;
-}
+// ------------------------------------------------------------------------
+// X: every wave owns a segment of one ring.  Lane l holds the M consecutive
+// zones z0 + M l .. z0 + M l + M - 1 of a window of 64 M zones that starts
+// HL zones before the segment and ends HR zones after it; zone neighbours
+// come from the lane's own registers or, across lanes, by wave shuffles.  The
+// halo is recomputed instead of exchanged, so no wave waits for another and
+// nothing goes through LDS.  The dependency cone of an output zone (van Leer
+// residual sweep, PPA residual, 12d along X) spans zones z-6 .. z+5.
+// Outputs are written out of place (shifted by N on store), so that the
+// segments of a ring can run in any order.
+// ------------------------------------------------------------------------
+template <typename F>
+struct RingShape;
+template <>
+struct RingShape<double> {
+  static constexpr int M = 2, HLL = 3, HRL = 3; // halo lanes on each side
+};
+template <>
+struct RingShape<float> {
+  static constexpr int M = 4, HLL = 2, HRL = 2;
+};
+
+template <typename F>
+__device__ inline F from_prev_lane(F x) { return __shfl_up(x, 1, WAVE); }
+template <typename F>
+__device__ inline F from_next_lane(F x) { return __shfl_down(x, 1, WAVE); }
+
+// a[] of the lane's M zones and its two neighbours on each side
+template <typename F, int M>
+struct Span {
+  F a[M];
+  F p2, p1, n1, n2;
+  __device__ inline void edges() {
+    p2 = from_prev_lane(a[M - 2]);
+    p1 = from_prev_lane(a[M - 1]);
+    n1 = from_next_lane(a[0]);
+    n2 = from_next_lane(a[1]);
+  }
+  __device__ inline F operator()(int x) const { // x in [-2, M + 1], static after unrolling
+    return x == -2 ? p2 : x == -1 ? p1 : x == M ? n1 : x == M + 1 ? n2 : a[x];
+  }
+};
 
 template <typename F, int M>
-__global__ __launch_bounds__(512, 4) void k_ring_x(Mesh m, const F *__restrict__ vx2, TSetT<F> T, StateT<F> s,
-                                                const double *__restrict__ v0, const int32_t *__restrict__ Nsh,
-                                                const double *__restrict__ xis, const double *__restrict__ dtp) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  F *lds = reinterpret_cast<F *>(lds_raw);
-  const int n = m.nx, B = blockDim.x, tid = threadIdx.x;
-  F *Qs = lds, *Fs = lds + n, *Es = lds + 2 * n, *Px = lds + 3 * n;
-  const int r = blockIdx.x;
+__device__ inline void next_of(const F (&a)[M], F (&out)[M]) { // value of zone z + 1
+  const F n1 = from_next_lane(a[0]);
+#pragma unroll
+  for (int m = 0; m < M; m++) out[m] = m + 1 < M ? a[m + 1] : n1;
+}
+template <typename F, int M>
+__device__ inline void prev_of(const F (&a)[M], F (&out)[M]) { // value of zone z - 1
+  const F p1 = from_prev_lane(a[M - 1]);
+#pragma unroll
+  for (int m = 0; m < M; m++) out[m] = m > 0 ? a[m - 1] : p1;
+}
+
+template <typename F>
+__global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__ vx2, TSetT<F> T, TSetT<F> Tout,
+                                                StateT<F> s, const double *__restrict__ v0,
+                                                const int32_t *__restrict__ Nsh, const double *__restrict__ xis,
+                                                const double *__restrict__ dtp, int nseg) {
+  constexpr int M = RingShape<F>::M, HLL = RingShape<F>::HLL, HRL = RingShape<F>::HRL;
+  constexpr int U = (WAVE - HLL - HRL) * M; // output zones per wave
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const long gw = (long)blk * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+  if (gw >= (long)m.nring * nseg) return;
+  const int r = (int)(gw / nseg), seg = (int)(gw % nseg);
+  const int n = m.nx;
   const int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
-  const double dtd = *dtp;
-  const F dt = (F)dtd;
-  const double dXd = m.DX(j, k), Sd = m.Sx(j, k);
-  const F S = (F)Sd, vinv = (F)m.Vinv(j, k);
+  const unsigned base = m.o32(0, j, k);
+  const double dtd = *dtp, dXd = m.DX(j, k), Sd = m.Sx(j, k);
+  const F dt = (F)dtd, S = (F)Sd, vinv = (F)m.Vinv(j, k);
   const bool fg = m.fargo != 0;
   const F vb = fg ? (F)v0[r] : F(0);
   const int N = fg ? Nsh[r] : 0;
   const int Nm = ((N % n) + n) % n; // shift on store: zone i goes to (i + Nm) mod n
   const double xid = fg ? xis[r] : 0.0;
   const F xi = (F)xid;
-  const unsigned base = m.o32(0, j, k);
   const F cdt = (F)(dtd / dXd), pfac = (F)(xid * dXd * Sd);
-  F r0[M], r1[M], rf[M], ri0[M], ri1[M], fr[M], wv[M], pxm[M], qn[M];
-#define ZONES(...)                                     \
-  _Pragma("unroll") for (int mm = 0; mm < M; mm++) {   \
-    const int i = tid + B * mm;                        \
-    if (i < n) {                                       \
-      const int im1 = ringnb(i, -1, n), ip1 = ringnb(i, 1, n); \
-      (void)im1;                                       \
-      (void)ip1;                                       \
-      __VA_ARGS__                                      \
-    }                                                  \
+  // the lane's zones and their ring indices
+  const int a0 = seg * U;                  // first output zone of the segment
+  const int zl = a0 - HLL * M + lane * M;  // first zone of the lane (window coordinates = ring coordinates)
+  const int aend = min(a0 + U, n);
+  const bool contig = zl >= 0 && zl + M <= n;
+  int iz[M];
+#pragma unroll
+  for (int q = 0; q < M; q++) {
+    int z = (zl + q) % n;
+    iz[q] = z < 0 ? z + n : z;
   }
-#define NB5(A) A[ringnb(i, -2, n)], A[im1], A[i], A[ip1], A[ringnb(i, 2, n)]
-#define OUT() (i + Nm >= n ? i + Nm - n : i + Nm)
-  // the next quantity is always loaded one quantity ahead: a barrier does not
-  // wait for global loads, so their latency hides behind the LDS phases
-  ZONES(qn[mm] = T.q[0][base + i];)
-  // density: van Leer sweep with the residual velocity
-  ZONES(r0[mm] = T.a[T_RHO][base + i]; wv[mm] = vx2[base + i] - vb; Qs[i] = r0[mm]; ri0[mm] = F(1) / r0[mm];)
-  __syncthreads();
-  ZONES(F w = wv[mm];
-        F st = vlx_star(Qs[ringnb(i, -2, n)], Qs[im1], Qs[i], Qs[ip1], w, w * cdt);
-        fr[mm] = w * st * S * dt; Fs[i] = fr[mm];)
-  __syncthreads();
-  ZONES(r1[mm] = r0[mm] - vinv * (Fs[ip1] - fr[mm]); ri1[mm] = F(1) / r1[mm]; Qs[i] = r1[mm]; rf[mm] = r1[mm];)
-  if (fg) {
-    __syncthreads();
-    ZONES(F st = ppa_star(NB5(Qs), xi); Es[xi >= F(0) ? ip1 : i] = pfac * st;)
-    __syncthreads();
-    ZONES(rf[mm] = r1[mm] - vinv * (Es[ip1] - Es[i]);)
-  }
-  // the other quantities, in the order Pi-_x, Pi+_x, Pi-_y, Pi+_y [, Pi-_z, Pi+_z] [, e]
-  for (int q = 0; q < T.nq; q++) {
-    F *Tq = T.q[q] + base;
-    F qv[M];
-    ZONES(qv[mm] = qn[mm];)
-    if (q + 1 < T.nq) {
-      const F *Tn = T.q[q + 1] + base;
-      ZONES(qn[mm] = Tn[i];)
-    }
-    __syncthreads();
-    ZONES(Qs[i] = qv[mm] * ri0[mm];)
-    __syncthreads();
-    ZONES(F w = wv[mm];
-          Fs[i] = vlx_star(Qs[ringnb(i, -2, n)], Qs[im1], Qs[i], Qs[ip1], w, w * cdt) * fr[mm];)
-    __syncthreads();
-    ZONES(qv[mm] = qv[mm] - vinv * (Fs[ip1] - Fs[i]);)
-    if (fg) {
-      ZONES(Qs[i] = qv[mm] * ri1[mm];)
-      __syncthreads();
-      ZONES(F st = ppa_star(NB5(Qs), xi); int f = xi >= F(0) ? ip1 : i; Fs[f] = st * Es[f];)
-      __syncthreads();
-      ZONES(qv[mm] = qv[mm] - vinv * (Fs[ip1] - Fs[i]);)
-    }
-    if (q == 0) {
-      ZONES(pxm[mm] = qv[mm];)
-    } else if (q == 1) {
-      ZONES(Px[i] = qv[mm];)
-    } else if (T.a[T_E] && q == T.nq - 1) {
-      ZONES(s.e[base + OUT()] = qv[mm];)
+  auto load = [&](const F *p, F (&out)[M]) {
+    if (contig) {
+      if constexpr (sizeof(F) == 8) {
+        const double2 *v = reinterpret_cast<const double2 *>(p + base + zl);
+#pragma unroll
+        for (int q = 0; q < M / 2; q++) {
+          double2 t = v[q];
+          out[2 * q] = t.x;
+          out[2 * q + 1] = t.y;
+        }
+      } else {
+        const float4 *v = reinterpret_cast<const float4 *>(p + base + zl);
+#pragma unroll
+        for (int q = 0; q < M / 4; q++) {
+          float4 t = v[q];
+          out[4 * q] = t.x;
+          out[4 * q + 1] = t.y;
+          out[4 * q + 2] = t.z;
+          out[4 * q + 3] = t.w;
+        }
+      }
     } else {
-      ZONES(Tq[OUT()] = qv[mm];)
+#pragma unroll
+      for (int q = 0; q < M; q++) out[q] = p[base + (unsigned)iz[q]];
+    }
+  };
+  auto out_at = [&](int q) { // storage index of the lane's zone q after the shift
+    int o = iz[q] + Nm;
+    return base + (unsigned)(o >= n ? o - n : o);
+  };
+  auto useful = [&](int q) { return lane >= HLL && lane < WAVE - HRL && zl + q < aend; };
+
+  // ---- density: van Leer residual sweep, then the PPA residual
+  F w[M], ri0[M], Fl[M], ri1[M], El[M], rf[M];
+  {
+    Span<F, M> R;
+    load(T.a[T_RHO], R.a);
+    load(vx2, w);
+#pragma unroll
+    for (int q = 0; q < M; q++) {
+      w[q] -= vb;
+      ri0[q] = F(1) / R.a[q];
+    }
+    R.edges();
+#pragma unroll
+    for (int q = 0; q < M; q++) {
+      const F st = vlx_star(R(q - 2), R(q - 1), R(q), R(q + 1), w[q], w[q] * cdt);
+      Fl[q] = w[q] * st * S * dt;
+    }
+    F Fh[M];
+    next_of(Fl, Fh);
+    Span<F, M> R1;
+#pragma unroll
+    for (int q = 0; q < M; q++) {
+      R1.a[q] = R.a[q] - vinv * (Fh[q] - Fl[q]);
+      ri1[q] = F(1) / R1.a[q];
+      rf[q] = R1.a[q];
+    }
+    if (fg) {
+      R1.edges();
+      F val[M];
+#pragma unroll
+      for (int q = 0; q < M; q++) val[q] = pfac * ppa_star(R1(q - 2), R1(q - 1), R1(q), R1(q + 1), R1(q + 2), xi);
+      // El: PPA mass flux through the zone's lower face (supplied by the
+      // upstream zone of that face)
+      if (xi >= F(0)) prev_of(val, El);
+      else {
+#pragma unroll
+        for (int q = 0; q < M; q++) El[q] = val[q];
+      }
+      F Eh[M];
+      next_of(El, Eh);
+#pragma unroll
+      for (int q = 0; q < M; q++) rf[q] = R1.a[q] - vinv * (Eh[q] - El[q]);
     }
   }
-  // box 12d along X (Eq. 18) on the shifted ring: face i + N takes zones i - 1, i
-  __syncthreads();
-  ZONES(Qs[i] = rf[mm];)
-  __syncthreads();
-  ZONES(F mom = (Px[im1] + pxm[mm]) / (Qs[im1] + rf[mm]); const int o = OUT();
-        s.vx[base + o] = m.vx_from(j, k, mom); s.rho[base + o] = rf[mm];)
-#undef ZONES
-#undef NB5
-#undef OUT
+  // ---- the other quantities: Pi-_y, Pi+_y [, Pi-_z, Pi+_z] [, e], then
+  // Pi-_x and Pi+_x, which 12d needs (T.q holds Pi-_x, Pi+_x first)
+  F pxm[M], pxp[M], Qn[M];
+  const int nq = T.nq;
+  auto qorder = [&](int t) { return t + 2 < nq ? t + 2 : t + 2 - nq; };
+  load(T.q[qorder(0)], Qn);
+  for (int t = 0; t < nq; t++) {
+    const int qi = qorder(t);
+    Span<F, M> Qs;
+    F Qv[M];
+#pragma unroll
+    for (int q = 0; q < M; q++) Qv[q] = Qn[q];
+    if (t + 1 < nq) load(T.q[qorder(t + 1)], Qn);
+#pragma unroll
+    for (int q = 0; q < M; q++) Qs.a[q] = Qv[q] * ri0[q];
+    Qs.edges();
+    F G[M], Gh[M];
+#pragma unroll
+    for (int q = 0; q < M; q++) G[q] = vlx_star(Qs(q - 2), Qs(q - 1), Qs(q), Qs(q + 1), w[q], w[q] * cdt) * Fl[q];
+    next_of(G, Gh);
+#pragma unroll
+    for (int q = 0; q < M; q++) Qv[q] = Qv[q] - vinv * (Gh[q] - G[q]);
+    if (fg) {
+#pragma unroll
+      for (int q = 0; q < M; q++) Qs.a[q] = Qv[q] * ri1[q];
+      Qs.edges();
+      F st[M], Hl[M], Hh[M];
+#pragma unroll
+      for (int q = 0; q < M; q++) st[q] = ppa_star(Qs(q - 2), Qs(q - 1), Qs(q), Qs(q + 1), Qs(q + 2), xi);
+      if (xi >= F(0)) {
+        prev_of(st, Hl);
+#pragma unroll
+        for (int q = 0; q < M; q++) Hl[q] *= El[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < M; q++) Hl[q] = st[q] * El[q];
+      }
+      next_of(Hl, Hh);
+#pragma unroll
+      for (int q = 0; q < M; q++) Qv[q] = Qv[q] - vinv * (Hh[q] - Hl[q]);
+    }
+    if (qi == 0) {
+#pragma unroll
+      for (int q = 0; q < M; q++) pxm[q] = Qv[q];
+    } else if (qi == 1) {
+#pragma unroll
+      for (int q = 0; q < M; q++) pxp[q] = Qv[q];
+    } else {
+      F *dst = (T.a[T_E] && qi == T.nq - 1) ? s.e : Tout.q[qi];
+#pragma unroll
+      for (int q = 0; q < M; q++)
+        if (useful(q)) dst[out_at(q)] = Qv[q];
+    }
+  }
+  // ---- box 12d along X (Eq. 18) on the shifted ring: face i + N takes zones i - 1, i
+  F pp[M], rp[M];
+  prev_of(pxp, pp);
+  prev_of(rf, rp);
+#pragma unroll
+  for (int q = 0; q < M; q++) {
+    if (!useful(q)) continue;
+    const F mom = (pp[q] + pxm[q]) / (rp[q] + rf[q]);
+    const unsigned o = out_at(q);
+    s.vx[o] = m.vx_from(j, k, mom);
+    s.rho[o] = rf[q];
+  }
 }
 
 // ------------------------------------------------------------------------
@@ -391,7 +551,7 @@ template <typename F, int NQ, bool D3, bool ADI>
 void sweep_y_launch(Launch &L, const Mesh &m, const StateT<F> &s, const TSetT<F> &out, const double *dt) {
   int nib, bs;
   row_blocks(m.nx, nib, bs);
-  int nchunk = (m.ny + CHUNK - 1) / CHUNK;
+  int nchunk = (m.ny + m.chunk - 1) / m.chunk;
   int nrows = D3 ? m.nz + 4 : 1;
   unsigned nb = (unsigned)nib * (unsigned)nchunk * (unsigned)nrows;
   k_sweep_y<F, NQ, D3, ADI><<<nb, bs, 0, L.s>>>(m, s.rho, s.vx, s.vy, s.vz, s.e, out, dt, nchunk);
@@ -401,15 +561,9 @@ template <typename F, int NQ>
 void sweep_z_launch(Launch &L, const Mesh &m, const F *vz, const TSetT<F> &in, const TSetT<F> &out, const double *dt) {
   int nib, bs;
   row_blocks(m.nx, nib, bs);
-  int nchunk = (m.nz + CHUNK - 1) / CHUNK;
+  int nchunk = (m.nz + m.chunk - 1) / m.chunk;
   unsigned nb = (unsigned)nib * (unsigned)nchunk * (unsigned)m.ny;
   k_sweep_z<F, NQ><<<nb, bs, 0, L.s>>>(m, vz, in, out, dt, nchunk);
-}
-
-template <typename F, int M>
-void ring_launch(Launch &L, const Mesh &m, int B, const F *vx2, const TSetT<F> &T, const StateT<F> &s,
-                 const double *v0, const int32_t *N, const double *xi, const double *dt) {
-  k_ring_x<F, M><<<m.nring, B, 4 * (size_t)m.nx * sizeof(F), L.s>>>(m, vx2, T, s, v0, N, xi, dt);
 }
 
 } // namespace
@@ -437,17 +591,16 @@ void launch_sweep_z(Launch &L, const Mesh &m, const F *vz, const TSetT<F> &in, c
   prof_end(L, K_SWEEP_Z);
 }
 
-// Block of B <= 512 threads with M = ceil(nx / B) zones each.
+// Waves of 64 lanes, four per block; ceil(nx / U) waves per ring.
 template <typename F>
-void launch_ring_x(Launch &L, const Mesh &m, const F *vx2, const TSetT<F> &T, const StateT<F> &s, const double *v0,
-                   const int32_t *N, const double *xi, const double *dt) {
-  int B = m.nx < 512 ? (m.nx + 63) / 64 * 64 : 512;
-  int M = (m.nx + B - 1) / B;
+void launch_ring_x(Launch &L, const Mesh &m, const F *vx2, const TSetT<F> &T, const TSetT<F> &Tout,
+                   const StateT<F> &s, const double *v0, const int32_t *N, const double *xi, const double *dt) {
+  constexpr int U = (WAVE - RingShape<F>::HLL - RingShape<F>::HRL) * RingShape<F>::M;
+  const int nseg = (m.nx + U - 1) / U;
+  const long waves = (long)m.nring * nseg;
+  const unsigned nb = (unsigned)((waves + 3) / 4);
   prof_begin(L, K_RING_X);
-  if (M == 1) ring_launch<F, 1>(L, m, B, vx2, T, s, v0, N, xi, dt);
-  else if (M == 2) ring_launch<F, 2>(L, m, B, vx2, T, s, v0, N, xi, dt);
-  else if (M == 3) ring_launch<F, 3>(L, m, B, vx2, T, s, v0, N, xi, dt);
-  else ring_launch<F, 4>(L, m, B, vx2, T, s, v0, N, xi, dt);
+  k_ring_x<F><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg);
   prof_end(L, K_RING_X);
 }
 
@@ -465,8 +618,9 @@ void launch_vel(Launch &L, const Mesh &m, const StateT<F> &s, const TSetT<F> &T)
   template void launch_sweep_y<F>(Launch &, const Mesh &, const StateT<F> &, const TSetT<F> &, const double *);   \
   template void launch_sweep_z<F>(Launch &, const Mesh &, const F *, const TSetT<F> &, const TSetT<F> &,         \
                                   const double *);                                                               \
-  template void launch_ring_x<F>(Launch &, const Mesh &, const F *, const TSetT<F> &, const StateT<F> &,         \
-                                 const double *, const int32_t *, const double *, const double *);               \
+  template void launch_ring_x<F>(Launch &, const Mesh &, const F *, const TSetT<F> &, const TSetT<F> &,         \
+                                 const StateT<F> &, const double *, const int32_t *, const double *,             \
+                                 const double *);                                                                \
   template void launch_vel<F>(Launch &, const Mesh &, const StateT<F> &, const TSetT<F> &);
 FARGO_TRANSPORT_INST(double)
 FARGO_TRANSPORT_INST(float)

@@ -1,0 +1,108 @@
+// Box 7d: kinematic viscosity, cylindrical 2D (phi, r), App. B: the stress
+// components of Eq. 73 (tau_phiphi and tau_rr at zone centres, tau_rphi on
+// the zone's lower edge in both X and Y, Fig. "stress") and their divergence
+// (Eq. 76).  Every component comes from the velocities after box 7b (Jacobi);
+// v_phi is updated on the X faces of active zones and v_r on the owned Y
+// faces, with the face density of Eq. 20; ghost zones carry v'' over.  On an
+// edge, rho and nu are the means of the four zones sharing it and v_phi / r
+// is the mean of v_phi / r on the two X faces it joins.  Each thread forms
+// the few components its two faces need; the field type F is double or float.
+#include "fargo_internal.h"
+
+namespace fargo {
+
+namespace {
+
+template <typename F>
+struct Visc {
+  Mesh m;
+  StateT<F> s;
+  const F *vx, *vy;
+
+  __device__ inline unsigned at(int i, int j) const { return m.o32(i, j, 0); }
+  __device__ inline int wrapx(int i) const { return i < 0 ? i + m.nx : (i >= m.nx ? i - m.nx : i); }
+  // tau_phiphi and tau_rr of zone (a, b)
+  __device__ inline void diag(int a, int b, F &tpp, F &trr) const {
+    const unsigned c = at(a, b), cxp = at(wrapx(a + 1), b), cyp = c + (unsigned)m.pitch;
+    const F dphi = (F)m.dx, r = (F)m.g.ymed[b];
+    const F divv = (F)m.Vinv(b, 0) * ((F)m.Sx(b, 0) * (vx[cxp] - vx[c]) +
+                                      ((F)m.Sy(b + 1, 0) * vy[cyp] - (F)m.Sy(b, 0) * vy[c]));
+    const F rn = s.rho[c] * s.nu[c];
+    const F ur = F(0.5) * (vy[c] + vy[cyp]);
+    tpp = -rn * (F(2) * ((vx[cxp] - vx[c]) / (r * dphi) + ur / r) - F(2) / F(3) * divv);
+    trr = -rn * (F(2) * (vy[cyp] - vy[c]) / (F)m.g.Ly[b] - F(2) / F(3) * divv);
+  }
+  // tau_rphi on the edge of zone (a, b) at its lower X and Y faces
+  __device__ inline F edge(int a, int b) const {
+    const int am = wrapx(a - 1);
+    const unsigned c = at(a, b), cw = at(am, b), cs_ = c - (unsigned)m.pitch, csw = cw - (unsigned)m.pitch;
+    const F rho4 = F(0.25) * (s.rho[c] + s.rho[cw] + s.rho[cs_] + s.rho[csw]);
+    const F nu4 = F(0.25) * (s.nu[c] + s.nu[cw] + s.nu[cs_] + s.nu[csw]);
+    const F dvphi_dr = (vx[c] - vx[cs_]) / (F)m.g.hy[b];
+    const F vphi_r = F(0.5) * (vx[c] / (F)m.g.ymed[b] + vx[cs_] / (F)m.g.ymed[b - 1]);
+    const F dvr_dphi = (vy[c] - vy[cw]) / ((F)m.g.ymin[b] * (F)m.dx);
+    return -rho4 * nu4 * (dvphi_dr - vphi_r + dvr_dphi);
+  }
+};
+
+template <typename F>
+__global__ __launch_bounds__(256) void k_visc(Visc<F> V, const double *__restrict__ dtp, F *__restrict__ vx3,
+                                              F *__restrict__ vy3) {
+  const Mesh &m = V.m;
+  const int nib = (m.nx + blockDim.x - 1) / blockDim.x;
+  const unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int j = (int)(Lb / (unsigned)nib);
+  const int i = (int)(Lb % (unsigned)nib) * (int)blockDim.x + (int)threadIdx.x;
+  if (i >= m.nx || j >= m.nyg) return;
+  const unsigned c = V.at(i, j);
+  if (j < m.j0 || j >= m.jn) {
+    vx3[c] = V.vx[c];
+    vy3[c] = V.vy[c];
+    return;
+  }
+  const F dt = (F)*dtp, dphi = (F)m.dx;
+  const F *rho = V.s.rho;
+  // v_phi on the X face of zone (i, j)
+  {
+    const int im = V.wrapx(i - 1);
+    F tpp0, trr0, tppw, trrw;
+    V.diag(i, j, tpp0, trr0);
+    V.diag(im, j, tppw, trrw);
+    const F a = (F)m.g.ymin[j], b = (F)m.g.ymin[j + 1], r = (F)m.g.ymed[j];
+    const F rho_f = F(0.5) * (rho[c] + rho[V.at(im, j)]);
+    const F div = (b * b * V.edge(i, j + 1) - a * a * V.edge(i, j)) / (r * r * (F)m.g.Ly[j]) + (tpp0 - tppw) / (r * dphi);
+    vx3[c] = V.vx[c] - dt * div / rho_f;
+  }
+  // v_r on the Y face of zone (i, j), if the step owns it
+  if (j >= m.ylo()) {
+    F tpp0, trr0, tpps, trrs;
+    V.diag(i, j, tpp0, trr0);
+    V.diag(i, j - 1, tpps, trrs);
+    const F a = (F)m.g.ymin[j];
+    const F rho_f = F(0.5) * (rho[c] + rho[c - (unsigned)m.pitch]);
+    const F div = ((F)m.g.ymed[j] * trr0 - (F)m.g.ymed[j - 1] * trrs) / (a * (F)m.g.hy[j]) +
+                  (V.edge(V.wrapx(i + 1), j) - V.edge(i, j)) / (a * dphi) - F(0.5) * (tpp0 + tpps) / a;
+    vy3[c] = V.vy[c] - dt * div / rho_f;
+  } else {
+    vy3[c] = V.vy[c];
+  }
+}
+
+} // namespace
+
+template <typename F>
+void launch_visc(Launch &L, const Mesh &m, const StateT<F> &s, const F *vx2, const F *vy2, F *vx3, F *vy3,
+                 const double *dt) {
+  const int bs = 256, nib = (m.nx + bs - 1) / bs;
+  const unsigned nb = (unsigned)nib * (unsigned)m.nyg;
+  prof_begin(L, K_VISC);
+  k_visc<F><<<nb, bs, 0, L.s>>>(Visc<F>{m, s, vx2, vy2}, dt, vx3, vy3);
+  prof_end(L, K_VISC);
+}
+
+template void launch_visc<double>(Launch &, const Mesh &, const StateT<double> &, const double *, const double *,
+                                  double *, double *, const double *);
+template void launch_visc<float>(Launch &, const Mesh &, const StateT<float> &, const float *, const float *,
+                                 float *, float *, const double *);
+
+} // namespace fargo

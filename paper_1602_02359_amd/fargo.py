@@ -29,7 +29,7 @@ BC = {"periodic": 0, "reflect": 1, "outflow": 2, "fixed": 3}
 V0_MODE = {"minmax": 0, "mean": 1}
 PRECISION = {"fp64": 0, "fp32": 1}  # fp32: FP32-bulk state, FP64 time step, split and sums
 DTYPE = {"fp64": torch.float64, "fp32": torch.float32}
-FIELDS = ("rho", "vx", "vy", "vz", "e", "cs", "pot")
+FIELDS = ("rho", "vx", "vy", "vz", "e", "cs", "pot", "nu")
 
 
 class fargo_params(C.Structure):
@@ -41,7 +41,7 @@ class fargo_params(C.Structure):
         ("eos", C.c_int32), ("gamma", C.c_double),
         ("omega", C.c_double), ("courant", C.c_double), ("cvnr", C.c_double), ("shear_c0", C.c_double),
         ("fargo", C.c_int32), ("v0_mode", C.c_int32),
-        ("bc", C.c_int32 * 4), ("precision", C.c_int32),
+        ("bc", C.c_int32 * 4), ("precision", C.c_int32), ("visc", C.c_int32),
     ]
 
 
@@ -71,9 +71,18 @@ _lib.fargo_profile_enable.argtypes = [C.c_void_p, C.c_int]
 _lib.fargo_timings.argtypes = [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                C.c_int, C.POINTER(C.c_int), C.c_void_p]
 
+_lib.fargo_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(fargo_state), C.c_int, C.c_int,
+                                    C.POINTER(C.c_void_p)]
+_lib.fargo_batch_step.argtypes = [C.c_void_p, C.c_void_p]
+_lib.fargo_batch_tune.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int32), C.c_int, C.c_int,
+                                  C.c_void_p, C.POINTER(C.c_int32)]
+_lib.fargo_batch_destroy.argtypes = [C.c_void_p]
+_lib.fargo_batch_destroy.restype = None
+
 EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_workspace_bytes", "fargo_init",
             "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
-            "fargo_conserved_sums", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings")
+            "fargo_conserved_sums", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
+            "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_destroy")
 
 
 class FargoError(RuntimeError):
@@ -110,6 +119,7 @@ def make_params(p: Dict):
     for i, b in enumerate(p["bc"]):
         s.bc[i] = BC[b]
     s.precision = PRECISION[p.get("precision", "fp64")]
+    s.visc = int(bool(p.get("visc", False)))
     return s, (ymin, zmin)
 
 
@@ -241,3 +251,35 @@ class Solver:
         n = C.c_int()
         _check(_lib.fargo_timings(self._ctx, names, counts, tot, cap, C.byref(n), _stream(stream)), "fargo_timings")
         return {names[i].decode(): (counts[i], tot[i]) for i in range(n.value) if counts[i] > 0}
+
+
+class Batch:
+    """Many Solvers advanced together: one captured hipGraph per step
+    (fargo_batch_*).  The solvers must stay alive and keep their state tensors
+    while the batch exists."""
+
+    def __init__(self, solvers, lanes: int = 8):
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        ctxs = (C.c_void_p * n)(*[s._ctx.value for s in self.solvers])
+        sts = (fargo_state * n)(*[s._st for s in self.solvers])
+        self._b = C.c_void_p()
+        _check(_lib.fargo_batch_create(ctxs, sts, n, int(lanes), C.byref(self._b)), "fargo_batch_create")
+
+    def __del__(self):
+        b = getattr(self, "_b", None)
+        if b is not None and b.value:
+            _lib.fargo_batch_destroy(b)
+            self._b = None
+
+    def fargo_batch_step(self, stream=None):
+        _check(_lib.fargo_batch_step(self._b, _stream(stream)), "fargo_batch_step")
+
+    def fargo_batch_tune(self, lanes=(1, 2, 4, 8, 16), chunks=(16, 32, 64), steps=3, stream=None):
+        la = (C.c_int32 * len(lanes))(*lanes)
+        ch = (C.c_int32 * len(chunks))(*chunks)
+        best = (C.c_int32 * 2)()
+        _check(_lib.fargo_batch_tune(self._b, la, len(lanes), ch, len(chunks), int(steps), _stream(stream), best),
+               "fargo_batch_tune")
+        return int(best[0]), int(best[1])
+

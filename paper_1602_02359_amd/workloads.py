@@ -169,6 +169,35 @@ def disk2d_cyl(nx=384, ny=128, rin=0.4, rout=2.5, h=0.05, seed=1, noise=1e-3,
     return Problem("disk2d_cyl", p, dict(rho=rho, vx=vx, vy=vy, vz=None, e=None, cs=cs, pot=pot), steps)
 
 
+def disk2d_visc(nx=192, ny=64, rin=0.4, rout=2.5, h=0.05, alpha=1e-3, seed=3, noise=1e-3,
+                fargo=True, steps=10) -> Problem:
+    """The 2D disk of `disk2d_cyl` with an alpha viscosity: the static field
+    nu = alpha c_s H = alpha h**2 r**0.5 (c_s = h r**-0.5, H = h r), box 7d on."""
+    pr = disk2d_cyl(nx=nx, ny=ny, rin=rin, rout=rout, h=h, seed=seed, noise=noise, fargo=fargo, steps=steps)
+    pr.params["visc"] = True
+    zc, r, xf, xc = _grid(pr.params)
+    pr.fields["nu"] = _full(pr.shape, alpha * h * h * np.sqrt(r))
+    pr.name = "disk2d_visc"
+    return pr
+
+
+def disk_batch(count=256, seed=3, nr_range=(64, 512), h_range=(0.03, 0.10), alpha_exp=(-4.0, -2.0),
+               rin=0.4, rout=2.5, noise=1e-3):
+    """The parameter sweep of uneven viscous disks: N_r uniform on nr_range,
+    N_phi = 3 N_r, aspect ratio h uniform on h_range, alpha = 10**U(alpha_exp),
+    each an isothermal `disk2d_visc` with its own noise seed (3000 + d)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for d in range(count):
+        nr = int(rng.integers(nr_range[0], nr_range[1] + 1))
+        h = float(rng.uniform(*h_range))
+        alpha = float(10.0 ** rng.uniform(*alpha_exp))
+        pr = disk2d_visc(nx=3 * nr, ny=nr, rin=rin, rout=rout, h=h, alpha=alpha, seed=3000 + d, noise=noise)
+        pr.name = "disk%03d" % d
+        out.append(pr)
+    return out
+
+
 def disk3d_sph(nx=1536, ny=512, nz=128, rin=0.4, rout=2.5, h=0.05, nh=3.0, gamma=1.4,
                seed=2, noise=1e-3, fargo=True, steps=1) -> Problem:
     """3D (phi, r, theta) adiabatic disk in hydrostatic and rotational equilibrium.

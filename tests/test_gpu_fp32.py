@@ -60,10 +60,12 @@ def _small(name):
         return W.disk2d_cyl(nx=200, ny=37, noise=1e-3)
     if name == "cart_random":
         return W.random_problem("cart", nx=70, ny=9, nz=7, eos="adi", seed=1)
+    if name == "ring_2048":  # several ring segments per wave-group, FARGO shift
+        return W.random_problem("cyl", nx=2048, ny=4, nz=1, eos="iso", seed=7, fargo=True)
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name", ["sph3d", "cyl3d_planet", "disk2d", "cart_random"])
+@pytest.mark.parametrize("name", ["sph3d", "cyl3d_planet", "disk2d", "cart_random", "ring_2048"])
 def test_fp32_one_step_vs_oracle(name):
     prob = _small(name)
     _say("fp32 one step", name, prob.params["nx"], prob.params["ny"], prob.params["nz"])

@@ -1,0 +1,152 @@
+"""Box 7d (kinematic viscosity, cylindrical 2D) and batches of uneven disks
+through the C ABI.
+
+The viscous step is compared with the FP64 oracle (time step bit-exact, state
+within 1e-12 normwise after one step); the FP32-bulk form with the FP64 step
+after 100 steps at 1e-5.  A batch step (one captured hipGraph over many disks)
+must equal the disks' own steps bit for bit, and the autotuner must leave the
+states as it found them.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1602_02359_amd import workloads as W
+from gpu_common import errors
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _solver(prob, **kw):
+    from paper_1602_02359_amd import fargo as F
+    s = F.Solver(dict(prob.params, **kw))
+    s.upload(prob.fields)
+    return s
+
+
+def _visc_disk(nx=96, ny=40, alpha=1e-2, seed=11, noise=1e-2):
+    return W.disk2d_visc(nx=nx, ny=ny, alpha=alpha, seed=seed, noise=noise)
+
+
+@pytest.mark.parametrize("shape", [(96, 40), (200, 37), (1, 50)])
+def test_visc_one_step_matches_oracle(shape):
+    prob = _visc_disk(*shape)
+    _say("visc one step", shape)
+    ref = prob.copy_fields()
+    dt_ref = O.step(prob.params, ref)
+    s = _solver(prob)
+    s.fargo_step(0.0)
+    s.fargo_check()
+    assert s.fargo_get_dt() == dt_ref
+    err = errors(prob, s.download(), ref)
+    _say("  errors", err)
+    for k, e in err.items():
+        assert e <= TOL, (k, e)
+
+
+def test_visc_several_steps_match_oracle():
+    prob = _visc_disk(128, 48, alpha=3e-2)
+    ref = prob.copy_fields()
+    s = _solver(prob)
+    for n in range(5):
+        dt_ref = O.step(prob.params, ref)
+        s.fargo_step(0.0)
+        dt = s.fargo_get_dt()
+        assert (dt == dt_ref) if n == 0 else abs(dt / dt_ref - 1.0) < 1e-12
+    s.fargo_check()
+    err = errors(prob, s.download(), ref)
+    _say("visc 5 steps", err)
+    for k, e in err.items():
+        assert e <= 10 * TOL, (k, e)
+
+
+def test_visc_fp32_hundred_steps_vs_fp64():
+    prob = _visc_disk(192, 64, alpha=1e-2, noise=1e-3)
+    s64, s32 = _solver(prob), _solver(prob, precision="fp32")
+    for _ in range(100):
+        s64.fargo_step(0.0)
+        s32.fargo_step(0.0)
+    s64.fargo_check()
+    s32.fargo_check()
+    err = errors(prob, s32.download(), s64.download())
+    _say("visc fp32 vs fp64, 100 steps", err)
+    for k, e in err.items():
+        assert e <= 1e-5, (k, e)
+
+
+def test_visc_unsupported_configurations():
+    from paper_1602_02359_amd import fargo as F
+    for prob in (W.disk3d_sph(nx=16, ny=6, nz=4), W.random_problem("cyl", nx=16, ny=6, nz=4, eos="iso"),
+                 W.random_problem("cyl", nx=16, ny=6, nz=1, eos="adi")):
+        with pytest.raises(F.FargoError) as e:
+            F.fargo_layout(dict(prob.params, visc=True))
+        assert e.value.code == -6
+
+
+def _small_batch(count, precision):
+    probs = W.disk_batch(count=count, nr_range=(16, 72), seed=5)
+    return probs, [_solver(p, precision=precision) for p in probs]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_step_equals_individual_steps(precision):
+    from paper_1602_02359_amd import fargo as F
+    probs, batch_solvers = _small_batch(7, precision)
+    _, own = _small_batch(7, precision)
+    b = F.Batch(batch_solvers, lanes=3)
+    for _ in range(4):
+        b.fargo_batch_step()
+        for s in own:
+            s.fargo_step(0.0)
+    for s in batch_solvers + own:
+        s.fargo_check()
+    for p, a, c in zip(probs, batch_solvers, own):
+        ga, gc = a.download(), c.download()
+        assert a.fargo_get_dt() == c.fargo_get_dt(), p.name
+        for k in ("rho", "vx", "vy"):
+            assert np.array_equal(ga[k], gc[k]), (p.name, k)
+    del b
+
+
+def test_batch_tune_keeps_states_and_picks_a_candidate():
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    probs, solvers = _small_batch(5, "fp32")
+    b = F.Batch(solvers, lanes=1)
+    b.fargo_batch_step()
+    before = [s.download() for s in solvers]
+    lanes, chunk = b.fargo_batch_tune(lanes=(1, 2, 4), chunks=(16, 64), steps=2)
+    assert lanes in (1, 2, 4) and chunk in (16, 64)
+    after = [s.download() for s in solvers]
+    for x, y in zip(before, after):
+        for k in ("rho", "vx", "vy"):
+            assert np.array_equal(x[k], y[k]), k
+    # the retuned batch still steps like the disks' own steps
+    _, own = _small_batch(5, "fp32")
+    for o in own:
+        o.fargo_step(0.0)
+    b.fargo_batch_step()
+    torch.cuda.synchronize()
+    for a, o in zip(solvers, own):
+        o.fargo_step(0.0)
+    for a, o in zip(solvers, own):
+        ga, go = a.download(), o.download()
+        for k in ("rho", "vx", "vy"):
+            assert np.array_equal(ga[k], go[k]), k
+    del b
