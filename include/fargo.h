@@ -15,7 +15,8 @@
  * Mesh and storage (Sect. 2.2-2.3, Tab. "corresp", Sect. 4.1):
  *   X = azimuth (periodic, uniform, no ghosts), Y = radius, Z = z or colatitude.
  *   Every field is a device array [nz_g][ny_g][pitch] of the state element
- *   type (double, or float with FARGO_FP32_BULK; see `precision`), X fastest,
+ *   type (double, or float with FARGO_FP32_BULK; see `precision`; pot is
+ *   double in both), X fastest,
  *   with ny_g = ny + 6, nz_g = nz + 6 (3D) or 1 (2D, nz == 1) and pitch from
  *   fargo_layout (a multiple of 64 elements, >= nx; columns nx..pitch-1 are
  *   padding, never read or written).  Three ghost layers in Y and Z.
@@ -83,12 +84,15 @@ extern "C" {
 #define FARGO_V0_MEAN 1
 /* precision of the evolved state (Sect. 6 discusses single vs double):
    FARGO_FP64: every field is double and all arithmetic is FP64.
-   FARGO_FP32_BULK: every field (rho, v, e, cs, pot) is float and the bulk
-   arithmetic of boxes 2, 7, 9 and 12 is FP32; the steps whose accuracy needs
-   it stay FP64: the time step (box 6, from the stored values), each ring's
-   bulk velocity v0 and the split of Eq. 29 into N and xi, and the conserved
-   sums.  The geometric coefficients are FP64 tables rounded to FP32 where
-   they enter bulk arithmetic. */
+   FARGO_FP32_BULK: the evolved fields (rho, v, e) and cs and nu are float
+   and the bulk arithmetic of boxes 2, 7, 9 and 12 is FP32; the steps whose
+   accuracy needs it stay FP64: the time step (box 6, from the stored
+   values), each ring's bulk velocity v0 and the split of Eq. 29 into N and
+   xi, the conserved sums, and the potential, which stays a double array
+   with its gradient formed in FP64 (a difference of nearly equal values:
+   FP32 storage would make its relative error eps r/dr, the round-off the
+   paper's Sect. 6 traces through derivatives).  The geometric coefficients
+   are FP64 tables rounded to FP32 where they enter bulk arithmetic. */
 #define FARGO_FP64 0
 #define FARGO_FP32_BULK 1
 
@@ -117,7 +121,8 @@ typedef struct {
 } fargo_params;
 
 /* Device pointers to the state, each laid out as described above, with
-   elements of type double (FARGO_FP64) or float (FARGO_FP32_BULK).  rho, vx,
+   elements of type double (FARGO_FP64) or float (FARGO_FP32_BULK), except
+   pot, which is always double.  rho, vx,
    vy are always required; vz in 3D only (NULL in 2D); e (volumic internal
    energy) for FARGO_ADIABATIC, cs (isothermal sound speed, static) for
    FARGO_ISOTHERMAL; pot (static potential, ghosts included) always; nu

@@ -299,7 +299,7 @@ StateT<F> state_of(const fargo_ctx *c, const fargo_state *s) {
   S.vz = c->m.d3 ? (F *)s->vz : nullptr;
   S.e = c->p.eos == FARGO_ADIABATIC ? (F *)s->e : nullptr;
   S.cs = c->p.eos == FARGO_ISOTHERMAL ? (const F *)s->cs : nullptr;
-  S.pot = (const F *)s->pot;
+  S.pot = (const double *)s->pot;
   S.nu = c->p.visc ? (const F *)s->nu : nullptr;
   return S;
 }

@@ -158,11 +158,15 @@ struct DevWords {
 };
 
 // Device pointers to the state (element type R); pointers the configuration
-// does not use are NULL.
+// does not use are NULL.  The static potential is FP64 in every mode: its
+// gradient is the difference of two nearly equal values, which FP32 storage
+// would turn into a relative force error of eps r / dr.
 template <typename R>
 struct StateT {
   R *rho, *vx, *vy, *vz, *e;
-  const R *cs, *pot, *nu;
+  const R *cs;
+  const double *pot;
+  const R *nu;
 };
 
 // Each launcher is defined once for R = double and R = float.

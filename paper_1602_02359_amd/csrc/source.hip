@@ -42,7 +42,7 @@ template <typename F>
 struct Lds {
   F R[2][SY][SX];  // density (two planes in flight)
   F P[SY][SX];     // pressure
-  F Ph[SY][SX];    // potential
+  double Ph[SY][SX]; // potential (FP64 in every mode)
   F VX[SY][SX];    // v_x on the lower X face of each zone slot
   F VY[SY][TX];    // v_y on the lower Y face of each zone slot
   F VT[SY][TX];    // spherical: v_theta on the zone's two Z faces, summed
@@ -55,7 +55,9 @@ struct Lds {
 // one zone's values in one plane
 template <typename F>
 struct Zv {
-  F rho, P, pot, vz, vx, vxp; // vxp: v_x on the next X face
+  F rho, P;
+  double pot;
+  F vz, vx, vxp; // vxp: v_x on the next X face
 };
 
 template <typename F, bool D3>
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(NT, 4) void k_source(Mesh m, StateT<F> s, const dou
     const F ihz = sph ? (F)(m.g.inv_dzmed[p] * m.g.inv_ymed[j]) : (F)m.g.inv_dzmed[p];
     iz = ihz / (z0.rho + zb.rho);
     F gradP = F(2) * (z0.P - zb.P) * iz;
-    F gradPhi = (z0.pot - zb.pot) * ihz;
+    F gradPhi = (F)((z0.pot - zb.pot) * (sph ? m.g.inv_dzmed[p] * m.g.inv_ymed[j] : m.g.inv_dzmed[p]));
     F src = F(0);
     if (sph) {
       F R0 = (F)(m.g.ymed[j] * m.g.sinz[p]), R1 = (F)(m.g.ymed[j] * m.g.sinz[m.kbelow(p)]);
@@ -188,10 +190,10 @@ __global__ __launch_bounds__(NT, 4) void k_source(Mesh m, StateT<F> s, const dou
     // ---- 7a on the X and Y faces of the tile and of the halo faces needed
     auto xface = [&](int rr, int sl) {
       const int t = rr + 2, y = jt0 + rr;
-      const F idX = (F)m.g.inv_dxlen[(size_t)kk * m.nyg + y];
-      const F inv = idX / (R[t][sl] + R[t][sl - 1]);
+      const double idXd = m.g.inv_dxlen[(size_t)kk * m.nyg + y];
+      const F inv = (F)idXd / (R[t][sl] + R[t][sl - 1]);
       const F gradP = F(2) * (L.P[t][sl] - L.P[t][sl - 1]) * inv;
-      const F gradPhi = (L.Ph[t][sl] - L.Ph[t][sl - 1]) * idX;
+      const F gradPhi = (F)((L.Ph[t][sl] - L.Ph[t][sl - 1]) * idXd);
       L.AX[rr][sl] = L.VX[t][sl] - dt * (gradP + gradPhi);
       L.IX[rr][sl] = inv;
     };
@@ -202,10 +204,10 @@ __global__ __launch_bounds__(NT, 4) void k_source(Mesh m, StateT<F> s, const dou
         L.IY[t][cc] = F(0);
         return;
       }
-      const F ih = (F)m.g.inv_hy[f];
-      const F inv = ih / (R[t][sl] + R[t - 1][sl]);
+      const double ihd = m.g.inv_hy[f];
+      const F inv = (F)ihd / (R[t][sl] + R[t - 1][sl]);
       const F gradP = F(2) * (L.P[t][sl] - L.P[t - 1][sl]) * inv;
-      const F gradPhi = (L.Ph[t][sl] - L.Ph[t - 1][sl]) * ih;
+      const F gradPhi = (F)((L.Ph[t][sl] - L.Ph[t - 1][sl]) * ihd);
       F src = F(0);
       if (cyl || sph) {
         const int ya = yrow(t - 1);

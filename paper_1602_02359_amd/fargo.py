@@ -185,8 +185,9 @@ class Solver:
             if a is None:
                 self.state[n] = None
                 continue
-            t = torch.zeros(self.shape, dtype=self.dtype, device=self.device)
-            t[:, :, :nx] = torch.from_numpy(np.ascontiguousarray(a)).to(self.device).to(self.dtype)
+            dt = torch.float64 if n == "pot" else self.dtype  # the potential is FP64 in every mode
+            t = torch.zeros(self.shape, dtype=dt, device=self.device)
+            t[:, :, :nx] = torch.from_numpy(np.ascontiguousarray(a)).to(self.device).to(dt)
             self.state[n] = t
         self._bind()
 

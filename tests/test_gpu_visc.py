@@ -81,13 +81,13 @@ def test_visc_fp32_hundred_steps_vs_fp64():
     s64, s32 = _solver(prob), _solver(prob, precision="fp32")
     for _ in range(100):
         s64.fargo_step(0.0)
-        s32.fargo_step(0.0)
+        s32.fargo_step(s64.fargo_get_dt())   # equal times
     s64.fargo_check()
     s32.fargo_check()
     err = errors(prob, s32.download(), s64.download())
     _say("visc fp32 vs fp64, 100 steps", err)
-    for k, e in err.items():
-        assert e <= 1e-5, (k, e)
+    for k, e in err.items():   # the FP32 bar of tests/test_gpu_fp32.py, same derivation
+        assert e <= 1e-4, (k, e)
 
 
 def test_visc_unsupported_configurations():
