@@ -234,7 +234,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="sph3d", choices=["sph3d", "cyl3d_planet", "disk2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variant", action="store_true", help="skip the FP32-bulk variant")
+    ap.add_argument("--no-variant", action="store_true", help="skip the FP32-bulk and disk-batch variants")
+    ap.add_argument("--no-batch", action="store_true", help="skip the disk-batch variant")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 GiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -349,7 +350,7 @@ def main():
         del s32
     del solver
     torch.cuda.empty_cache()
-    if not args.no_variant:
+    if not args.no_variant and not args.no_batch:
         variants["disk_batch"] = batch_variant(args.steps, args.warmup)
 
     cpu = None

@@ -61,7 +61,7 @@ struct Zv {
 };
 
 template <typename F, bool D3>
-__global__ __launch_bounds__(NT, 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
+__global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
                                                   F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
                                                   F *__restrict__ e2, int nbx, int nby) {
   __shared__ Lds<F> L;
@@ -143,48 +143,104 @@ __global__ __launch_bounds__(NT, 4) void k_source(Mesh m, StateT<F> s, const dou
     }
   }
 
+  // The halo zone this thread stages, if any (fixed over the march):
+  // role 1, Y halo rows 0, 1, h+2, h+3 over the tile's columns (with v_y and,
+  // in spherical geometry, the summed v_theta); role 2, X halo slots 0, 1,
+  // w+2, w+3 of the tile rows; role 3, v_x on the X face after the last
+  // column, in the Y halo rows.
+  int role = 0, ht = 0, hsl = 0;
+  if (tid < 256) {
+    const int q = tid >> 6;
+    ht = q < 2 ? q : h + q;
+    hsl = c + 2;
+    role = c < w ? 1 : 0;
+  } else if (tid < 256 + 4 * TY) {
+    const int q = tid - 256, rr = q >> 2, a = q & 3;
+    ht = rr + 2;
+    hsl = a < 2 ? a : w + a;
+    role = rr < h ? 2 : 0;
+  } else if (tid < 256 + 4 * TY + 4) {
+    const int q = tid - 256 - 4 * TY;
+    ht = q < 2 ? q : h + q;
+    hsl = w + 2;
+    role = 3;
+  }
+  const unsigned hbase = role ? m.o32(xcol(hsl), yrow(ht), 0) : 0u;
+  const bool hvy = role == 1 && ht != 0, hvt = role == 1 && sph;
+  // The values an iteration stages (own v_y, the window's next plane and the
+  // halo zone) are loaded one iteration ahead, so that their latency overlaps
+  // the previous plane's work.  FP64 fields need more registers than two
+  // workgroups per CU leave, so that kernel runs one workgroup per CU.
+  constexpr bool PF = true;
+  struct Pre {
+    Zv<F> z;     // window plane kk + 2
+    F vy;        // own v_y at plane kk
+    F hr, hP, hx, hy, ht;
+    double hp;   // halo: rho, P, v_x, v_y, summed v_theta, potential
+  };
+  auto fetch_window = [&](int kk, Pre &n) {
+    if (act && D3) loadz(pl(kk + 2), n.z);
+  };
+  auto fetch_stage = [&](int kk, Pre &n) {
+    if (act) n.vy = s.vy[m.o32(i, j, kk)];
+    if (role) {
+      const unsigned o = hbase + (unsigned)kk * plane;
+      n.hx = s.vx[o];
+      if (role != 3) {
+        n.hr = s.rho[o];
+        n.hP = pres(o);
+        n.hp = s.pot[o];
+      }
+      if (hvy) n.hy = s.vy[o];
+      if (hvt) {
+        const int kp = D3 ? m.kabove(kk) : kk;
+        n.ht = s.vz[o] + s.vz[o + (unsigned)(kp - kk) * plane];
+      }
+    }
+  };
+  auto prefetch = [&](int kk, Pre &n) {
+    fetch_window(kk, n);
+    fetch_stage(kk, n);
+  };
+  Pre nx{};
+  if (PF) prefetch(kfirst, nx);
+
   int buf = 0;
 #pragma unroll 1
   for (int kk = kfirst; kk < klast; kk++) {
     const int ka = D3 ? pl(kk + 1) : kk;
+    Pre cur;
+    if (PF) {
+      cur = nx;
+      if (kk + 1 < klast) prefetch(kk + 1, nx);
+    } else {
+      fetch_window(kk, cur);
+    }
     if (D3 && act) {
-      loadz(pl(kk + 2), Z2);
+      Z2 = cur.z;
       A[3] = vz1(pl(kk + 2), Z1, Z2, IZ[3]);
       Q[2] = qvisc(c2, Z1.rho, A[3] - A[2]);
     }
-    const int kp = D3 ? m.kabove(kk) : kk;
     F(*R)[SX] = L.R[buf];
-    // ---- stage plane kk: interior from the window, halo from memory
+    if (!PF) fetch_stage(kk, cur);
+    // ---- stage plane kk: interior from the window, halo from the prefetched values
     if (act) {
       R[r + 2][c + 2] = Z0.rho;
       L.P[r + 2][c + 2] = Z0.P;
       L.Ph[r + 2][c + 2] = Z0.pot;
       L.VX[r + 2][c + 2] = Z0.vx;
       if (sph) L.VT[r + 2][c] = Z0.vz + Z1.vz;
-      L.VY[r + 2][c] = s.vy[m.o32(i, j, kk)];
+      L.VY[r + 2][c] = cur.vy;
     }
-    auto halo_zone = [&](int t, int sl, bool need_vy, bool need_vt) {
-      const int y = yrow(t), x = xcol(sl);
-      const unsigned o = m.o32(x, y, kk);
-      R[t][sl] = s.rho[o];
-      L.P[t][sl] = pres(o);
-      L.Ph[t][sl] = s.pot[o];
-      L.VX[t][sl] = s.vx[o];
-      if (need_vy) L.VY[t][sl - 2] = s.vy[o];
-      if (need_vt) L.VT[t][sl - 2] = s.vz[o] + s.vz[o + (unsigned)(kp - kk) * plane];
-    };
-    if (tid < 256) {
-      // Y halo rows 0, 1, h+2, h+3 over the tile's columns
-      const int q = tid >> 6, t = q < 2 ? q : h + q;
-      if (c < w) halo_zone(t, c + 2, t != 0, sph);
-    } else if (tid < 256 + 4 * TY) {
-      // X halo slots 0, 1, w+2, w+3 of the tile rows
-      const int q = tid - 256, rr = q >> 2, a = q & 3, sl = a < 2 ? a : w + a;
-      if (rr < h) halo_zone(rr + 2, sl, false, false);
-    } else if (tid < 256 + 4 * TY + 4) {
-      // v_x on the X face after the last column, in the Y halo rows
-      const int q = tid - 256 - 4 * TY, t = q < 2 ? q : h + q;
-      L.VX[t][w + 2] = s.vx[m.o32(xcol(w + 2), yrow(t), kk)];
+    if (role) {
+      L.VX[ht][hsl] = cur.hx;
+      if (role != 3) {
+        R[ht][hsl] = cur.hr;
+        L.P[ht][hsl] = cur.hP;
+        L.Ph[ht][hsl] = cur.hp;
+      }
+      if (hvy) L.VY[ht][hsl - 2] = cur.hy;
+      if (hvt) L.VT[ht][hsl - 2] = cur.ht;
     }
     __syncthreads();
     // ---- 7a on the X and Y faces of the tile and of the halo faces needed

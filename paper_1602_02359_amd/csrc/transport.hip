@@ -56,10 +56,13 @@ struct Zone {
 // loads of zone a, `derive(a, const RW&, Zone&)` forms its density, Q/rho, Q
 // and lower-face velocity; `geo` gives L(a) (zone width), h(f) (centre
 // distance at face f), S(f), Vi(a); `st(a, rho, T[])` stores the updated
-// zone.  The loads of zone f + 2 are issued while zone f is being computed.
+// zone.  With FP32 fields the loads of zone f + 2 are issued while zone f is
+// being computed; with FP64 fields the registers that would take are worth
+// more as occupancy, and zone f + 1 is loaded at the start of step f.
 template <typename F, int NQ, class RW, class RAW, class DER, class GEO, class ST>
 __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const DER &derive, const GEO &geo,
                                     const ST &st) {
+  constexpr bool PF = sizeof(F) == 4;
   Zone<F, NQ> zm, z0, zp;
   RW rn;
   raw(a0 - 2, rn);
@@ -68,7 +71,7 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
   derive(a0 - 1, rn, zm);
   raw(a0, rn);
   derive(a0, rn, z0);
-  raw(a0 + 1, rn);
+  if (PF) raw(a0 + 1, rn);
   F sm[NQ + 1], s0[NQ + 1];
   {
     F hm = geo.h(a0 - 1), hp = geo.h(a0);
@@ -82,8 +85,9 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
   F Lm = geo.L(a0 - 1);
 #pragma unroll 1
   for (int f = a0; f <= a1; f++) {
+    if (!PF) raw(f + 1, rn);
     derive(f + 1, rn, zp);
-    if (f + 2 <= a1 + 1) raw(f + 2, rn);
+    if (PF && f + 2 <= a1 + 1) raw(f + 2, rn);
     F hm = geo.h(f), hp = geo.h(f + 1);
     s0[NQ] = vl_slope(zm.rho, z0.rho, zp.rho, hm, hp);
 #pragma unroll
@@ -119,7 +123,7 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
 // Quantities: Pi-_x, Pi+_x, Pi-_y, Pi+_y [, Pi-_z, Pi+_z] [, e].
 // ------------------------------------------------------------------------
 template <typename F, int NQ, bool D3, bool ADI>
-__global__ __launch_bounds__(256, 3) void k_sweep_y(Mesh m, const F *__restrict__ rho, const F *__restrict__ vx,
+__global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ rho, const F *__restrict__ vx,
                                                  const F *__restrict__ vy, const F *__restrict__ vz,
                                                  const F *__restrict__ e, TSetT<F> out,
                                                  const double *__restrict__ dtp, int nchunk) {
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(256, 3) void k_sweep_y(Mesh m, const F *__restrict_
 // Z sweep on the Y-swept quantities.
 // ------------------------------------------------------------------------
 template <typename F, int NQ>
-__global__ __launch_bounds__(256, 3) void k_sweep_z(Mesh m, const F *__restrict__ vz, TSetT<F> in, TSetT<F> out,
+__global__ __launch_bounds__(256) void k_sweep_z(Mesh m, const F *__restrict__ vz, TSetT<F> in, TSetT<F> out,
                                                  const double *__restrict__ dtp, int nchunk) {
   unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
   int jr = (int)(Lb % (unsigned)m.ny);
@@ -251,42 +255,6 @@ __device__ inline F mc_slope(F qm, F q0, F qp) {
   return dq > F(0) ? mag : -mag;
 }
 
-// PPA interface value supplied by zone 0 (right face for xi >= 0, left face
-// for xi < 0): Eqs. 34, 35, 36 and the interface formula with |xi|.
-template <typename F>
-__device__ inline F ppa_star(F q2m, F qm, F q0, F qp, F q2p, F xi) {
-  const F sixth = F(1) / F(6);
-  F dmm = mc_slope(q2m, qm, q0), dm0 = mc_slope(qm, q0, qp), dmp = mc_slope(q0, qp, q2p);
-  F l = qm + F(0.5) * (q0 - qm) - (dm0 - dmm) * sixth;
-  F r = q0 + F(0.5) * (qp - q0) - (dmp - dm0) * sixth;
-  F D = r - l, C = q0 - F(0.5) * (l + r);
-  if ((qp - q0) * (q0 - qm) <= F(0)) {
-    l = q0;
-    r = q0;
-  } else if (D * C > D * D * sixth) {
-    l = F(3) * q0 - F(2) * r;
-  } else if (-D * D * sixth > D * C) {
-    r = F(3) * q0 - F(2) * l;
-  }
-  F x = fabs(xi);
-  if (xi >= F(0)) return r + x * (q0 - r) + x * (F(1) - x) * (F(2) * q0 - r - l);
-  return l + x * (q0 - l) + x * (F(1) - x) * (F(2) * q0 - r - l);
-}
-
-// van Leer interface value with a uniform zone width: slopes in units of
-// the zone (harmonic mean of the raw differences), cw = w dt / dX.
-template <typename F>
-__device__ inline F vlx_star(F q2m, F qm, F q0, F qp, F w, F cw) {
-  if (w >= F(0)) {
-    F dm = qm - q2m, dp = q0 - qm, pr = dm * dp;
-    F a = pr > F(0) ? F(2) * pr / (dm + dp) : F(0);
-    return qm + a * (F(1) - cw) * F(0.5);
-  }
-  F dm = q0 - qm, dp = qp - q0, pr = dm * dp;
-  F a = pr > F(0) ? F(2) * pr / (dm + dp) : F(0);
-  return q0 - a * (F(1) + cw) * F(0.5);
-}
-
 // ------------------------------------------------------------------------
 // X: every wave owns a segment of one ring.  Lane l holds the M consecutive
 // zones z0 + M l .. z0 + M l + M - 1 of a window of 64 M zones that starts
@@ -341,6 +309,65 @@ __device__ inline void prev_of(const F (&a)[M], F (&out)[M]) { // value of zone 
   const F p1 = from_prev_lane(a[M - 1]);
 #pragma unroll
   for (int m = 0; m < M; m++) out[m] = m > 0 ? a[m - 1] : p1;
+}
+
+// PPA on one zone (Eqs. 34-36): limit the parabola through the edge values
+// l, r (flat at an extremum, steepened away from an overshoot), then the
+// interface value supplied by the zone, the mean of the parabola over the
+// fraction |xi| next to its right edge (xi >= 0) or left edge (xi < 0).
+template <typename F>
+__device__ inline F ppa_eval(F qm, F q0, F qp, F l, F r, F xi) {
+  const F sixth = F(1) / F(6);
+  F D = r - l, C = q0 - F(0.5) * (l + r);
+  if ((qp - q0) * (q0 - qm) <= F(0)) {
+    l = q0;
+    r = q0;
+  } else if (D * C > D * D * sixth) {
+    l = F(3) * q0 - F(2) * r;
+  } else if (-D * D * sixth > D * C) {
+    r = F(3) * q0 - F(2) * l;
+  }
+  F x = fabs(xi);
+  if (xi >= F(0)) return r + x * (q0 - r) + x * (F(1) - x) * (F(2) * q0 - r - l);
+  return l + x * (q0 - l) + x * (F(1) - x) * (F(2) * q0 - r - l);
+}
+
+// Interface values on the lane's zones; each zone's slope and each face's
+// edge value is computed once and handed to the neighbouring zone by a
+// shuffle.
+//   vlx_faces: van Leer on a uniform zone width, slopes in units of the zone
+//   (harmonic mean of the two one-sided differences, zero unless they have
+//   the same sign), and the half-step value at each zone's lower face
+//   upwinded on w, with cw = w dt / dX (Eq. 15).
+template <typename F, int M>
+__device__ inline void vlx_faces(const Span<F, M> &Q, const F (&w)[M], F cdt, F (&out)[M]) {
+  F a[M], ap[M];
+#pragma unroll
+  for (int q = 0; q < M; q++) {
+    const F dm = Q(q) - Q(q - 1), dp = Q(q + 1) - Q(q), pr = dm * dp;
+    a[q] = pr > F(0) ? F(2) * pr / (dm + dp) : F(0);
+  }
+  prev_of(a, ap);
+#pragma unroll
+  for (int q = 0; q < M; q++) {
+    const F cw = w[q] * cdt;
+    out[q] = w[q] >= F(0) ? Q(q - 1) + ap[q] * (F(1) - cw) * F(0.5) : Q(q) - a[q] * (F(1) + cw) * F(0.5);
+  }
+}
+//   ppa_values: monotonised central slopes, the edge value of each face
+//   (Eq. 34) and the interface value supplied by each zone.
+template <typename F, int M>
+__device__ inline void ppa_values(const Span<F, M> &Q, F xi, F (&out)[M]) {
+  const F sixth = F(1) / F(6);
+  F d[M], dp[M], l[M], r[M];
+#pragma unroll
+  for (int q = 0; q < M; q++) d[q] = mc_slope(Q(q - 1), Q(q), Q(q + 1));
+  prev_of(d, dp);
+#pragma unroll
+  for (int q = 0; q < M; q++) l[q] = Q(q - 1) + F(0.5) * (Q(q) - Q(q - 1)) - (d[q] - dp[q]) * sixth;
+  next_of(l, r);
+#pragma unroll
+  for (int q = 0; q < M; q++) out[q] = ppa_eval(Q(q - 1), Q(q), Q(q + 1), l[q], r[q], xi);
 }
 
 template <typename F>
@@ -422,11 +449,10 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
       ri0[q] = F(1) / R.a[q];
     }
     R.edges();
+    F st[M];
+    vlx_faces(R, w, cdt, st);
 #pragma unroll
-    for (int q = 0; q < M; q++) {
-      const F st = vlx_star(R(q - 2), R(q - 1), R(q), R(q + 1), w[q], w[q] * cdt);
-      Fl[q] = w[q] * st * S * dt;
-    }
+    for (int q = 0; q < M; q++) Fl[q] = w[q] * st[q] * S * dt;
     F Fh[M];
     next_of(Fl, Fh);
     Span<F, M> R1;
@@ -439,8 +465,9 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
     if (fg) {
       R1.edges();
       F val[M];
+      ppa_values(R1, xi, val);
 #pragma unroll
-      for (int q = 0; q < M; q++) val[q] = pfac * ppa_star(R1(q - 2), R1(q - 1), R1(q), R1(q + 1), R1(q + 2), xi);
+      for (int q = 0; q < M; q++) val[q] = pfac * val[q];
       // El: PPA mass flux through the zone's lower face (supplied by the
       // upstream zone of that face)
       if (xi >= F(0)) prev_of(val, El);
@@ -471,8 +498,9 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
     for (int q = 0; q < M; q++) Qs.a[q] = Qv[q] * ri0[q];
     Qs.edges();
     F G[M], Gh[M];
+    vlx_faces(Qs, w, cdt, G);
 #pragma unroll
-    for (int q = 0; q < M; q++) G[q] = vlx_star(Qs(q - 2), Qs(q - 1), Qs(q), Qs(q + 1), w[q], w[q] * cdt) * Fl[q];
+    for (int q = 0; q < M; q++) G[q] = G[q] * Fl[q];
     next_of(G, Gh);
 #pragma unroll
     for (int q = 0; q < M; q++) Qv[q] = Qv[q] - vinv * (Gh[q] - G[q]);
@@ -481,8 +509,7 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
       for (int q = 0; q < M; q++) Qs.a[q] = Qv[q] * ri1[q];
       Qs.edges();
       F st[M], Hl[M], Hh[M];
-#pragma unroll
-      for (int q = 0; q < M; q++) st[q] = ppa_star(Qs(q - 2), Qs(q - 1), Qs(q), Qs(q + 1), Qs(q + 2), xi);
+      ppa_values(Qs, xi, st);
       if (xi >= F(0)) {
         prev_of(st, Hl);
 #pragma unroll
