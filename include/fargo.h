@@ -161,7 +161,7 @@ void fargo_destroy(fargo_ctx *ctx);
 
 /* Boxes 2, 3, 4 and 6: fill the state's ghost layers (box 2; only ghosts and
    boundary faces are written), compute each ring's bulk velocity and the time
-   step of Eq. cfl2 (items 1-3, with the residual velocity and the shear limit
+   step of Eq. cfl2 (items 1-3, and 4 with viscosity; the residual velocity and the shear limit
    of Eq. 38 under orbital advection), minimised over active zones.  The step
    stays on the device for the next fargo_step(dt <= 0); if dt_host is not
    NULL the call waits for the stream and copies it back, returning

@@ -13,7 +13,7 @@
  *   box 2   boundary fill (ghost layers)
  *   box 3   per-ring bulk azimuthal velocity v0 (Eq. 37)
  *   box 4   pressure from the equation of state (Eqs. eos1, eos2)
- *   box 6   time step (Eq. cfl2, items 1-3; Eq. 38 with orbital advection)
+ *   box 6   time step (Eq. cfl2, items 1-4; Eq. 38 with orbital advection)
  *   box 7a  pressure and potential gradients, centrifugal terms (Sect. 3.3, Eq. 12)
  *   box 7b  von Neumann-Richtmyer artificial viscosity and its heating
  *   box 7d  kinematic viscosity (App. B, Eqs. 73 and 76; cylindrical 2D),
@@ -375,59 +375,63 @@ static inline double pressure(const mesh_t *m, const orc_state *s, size_t c) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Box 6: time step, Eq. cfl2 with items 1-3, and Eq. 38                     */
+/* Box 6: time step, Eq. cfl2 with items 1-4, and Eq. 38                     */
 /* ------------------------------------------------------------------------ */
 static double cfl_dt(const mesh_t *m, const orc_state *s, const double *v0, int *err) {
+  /* Each item of Eq. cfl2 is evaluated as its inverse, the rate 1/dt_i: the
+     minimum over directions of Delta_j / u is the maximum of u / Delta_j, and
+     the cell's step is 1/sqrt(sum of squared rates), so the smallest step of
+     the mesh is 1/sqrt of the largest sum. */
   const orc_params *p = m->p;
-  double mincell = INFINITY;
+  double maxrate2 = 0.0;
   double maxshear = 0.0;
   int bad = 0;
-#pragma omp parallel for collapse(2) schedule(static) reduction(min : mincell) reduction(max : maxshear) reduction(| : bad)
+  const double k3 = 4.0 * p->cvnr * p->cvnr;
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : maxrate2) reduction(max : maxshear) reduction(| : bad)
   for (int k = m->k0; k < m->kn; k++)
     for (int j = m->j0; j < m->jn; j++) {
       double vbulk = p->fargo ? v0[(size_t)(k - m->k0) * m->ny + (j - m->j0)] : 0.0;
       double Lx = DXlen(m, j, k), Lyy = Ly(m, j), Lzz = m->d3 ? Lz(m, j, k) : 0.0;
+      double iLx = 1.0 / Lx, iLy = 1.0 / Lyy, iLz = m->d3 ? 1.0 / Lzz : 0.0;
+      double Lmin = fmin(Lx, Lyy);
+      if (m->d3) Lmin = fmin(Lmin, Lzz);
+      double iL2 = 1.0 / (Lmin * Lmin);
       for (int i = 0; i < m->nx; i++) {
         size_t c = IX(i, j, k);
         int ip = imod(i + 1, m->nx);
         double rho = s->rho[c];
-        double cw;
-        if (p->eos == EOS_ISO) cw = s->cs[c];
-        else {
-          double P = (p->gamma - 1.0) * s->e[c];
-          cw = sqrt(p->gamma * P / rho);
-        }
-        if (!(rho > 0.0) || !isfinite(rho) || !isfinite(cw) || !isfinite(s->vx[c]) || !isfinite(s->vy[c]) ||
+        /* squared wave speed: c_s^2, or gamma P / rho */
+        double cw2;
+        if (p->eos == EOS_ISO) cw2 = s->cs[c] * s->cs[c];
+        else cw2 = p->gamma * ((p->gamma - 1.0) * s->e[c]) / rho;
+        if (!(rho > 0.0) || !isfinite(rho) || !isfinite(cw2) || !isfinite(s->vx[c]) || !isfinite(s->vy[c]) ||
             (m->d3 && !isfinite(s->vz[c])))
           bad = 1;
-        /* item 1: sound waves */
-        double dt1 = fmin(Lx / cw, Lyy / cw);
-        /* item 2: fluid motion, with the residual velocity under orbital advection */
+        /* item 1: sound waves, c_w / Delta (squared) */
+        double r1s = cw2 * iL2;
+        /* item 2: fluid motion, |V_j| / Delta_j, with the residual velocity under orbital advection */
         double ux = fmax(fabs(s->vx[c] - vbulk), fabs(s->vx[IX(ip, j, k)] - vbulk));
         double uy = fmax(fabs(s->vy[c]), fabs(s->vy[IX(i, j + 1, k)]));
-        double dt2 = fmin(Lx / ux, Lyy / uy);
-        /* item 3: artificial viscosity, on compressed directions only */
+        double r2 = fmax(ux * iLx, uy * iLy);
+        /* item 3: artificial viscosity, 4 C^2 |dv_j| / Delta_j on compressed directions */
         double dvx = s->vx[IX(ip, j, k)] - s->vx[c];
         double dvy = s->vy[IX(i, j + 1, k)] - s->vy[c];
-        double dt3 = INFINITY;
-        if (dvx < 0.0) dt3 = fmin(dt3, Lx / (4.0 * p->cvnr * p->cvnr * fabs(dvx)));
-        if (dvy < 0.0) dt3 = fmin(dt3, Lyy / (4.0 * p->cvnr * p->cvnr * fabs(dvy)));
+        double r3 = 0.0;
+        if (dvx < 0.0) r3 = fmax(r3, k3 * fabs(dvx) * iLx);
+        if (dvy < 0.0) r3 = fmax(r3, k3 * fabs(dvy) * iLy);
         if (m->d3) {
-          dt1 = fmin(dt1, Lzz / cw);
           double uz = fmax(fabs(s->vz[c]), fabs(s->vz[IX(i, j, k + 1)]));
-          dt2 = fmin(dt2, Lzz / uz);
+          r2 = fmax(r2, uz * iLz);
           double dvz = s->vz[IX(i, j, k + 1)] - s->vz[c];
-          if (dvz < 0.0) dt3 = fmin(dt3, Lzz / (4.0 * p->cvnr * p->cvnr * fabs(dvz)));
+          if (dvz < 0.0) r3 = fmax(r3, k3 * fabs(dvz) * iLz);
         }
-        double inv2 = 1.0 / (dt1 * dt1) + 1.0 / (dt2 * dt2) + 1.0 / (dt3 * dt3);
+        double rate2 = r1s + r2 * r2 + r3 * r3;
         if (p->visc) {
-          /* item 4: viscosity, Delta^2 / (4 nu), minimum over directions */
-          double Lmin = fmin(Lx, Lyy);
-          double dt4 = Lmin * Lmin / (4.0 * s->nu[c]);
-          inv2 += 1.0 / (dt4 * dt4);
+          /* item 4: viscosity, 4 nu / Delta^2 */
+          double r4 = 4.0 * s->nu[c] * iL2;
+          rate2 += r4 * r4;
         }
-        double cell = 1.0 / sqrt(inv2);
-        if (cell < mincell) mincell = cell;
+        if (rate2 > maxrate2) maxrate2 = rate2;
         /* Eq. 38: shear between radially adjacent active zones */
         if (p->fargo && p->shear_c0 > 0.0 && j + 1 < m->jn) {
           double sh = fabs(s->vx[c] / Lx - s->vx[IX(i, j + 1, k)] / DXlen(m, j + 1, k));
@@ -435,7 +439,7 @@ static double cfl_dt(const mesh_t *m, const orc_state *s, const double *v0, int 
         }
       }
     }
-  double dt = p->courant * mincell;
+  double dt = p->courant * (1.0 / sqrt(maxrate2));
   if (p->fargo && p->shear_c0 > 0.0 && maxshear > 0.0) dt = fmin(dt, p->shear_c0 / maxshear);
   if (bad) *err = ORC_ENONFINITE;
   else if (!(dt > 0.0) || !isfinite(dt)) *err = ORC_ECFL;

@@ -78,7 +78,7 @@ struct fargo_ctx {
   bool own_ws = false;
   // carved workspace
   DevWords w{};
-  double *v0 = nullptr, *xi = nullptr, *ringmin = nullptr, *ringshear = nullptr;
+  double *v0 = nullptr, *xi = nullptr, *ringrate = nullptr, *ringshear = nullptr;
   int32_t *nshift = nullptr;
   double *partial = nullptr, *sums_out = nullptr;
   size_t esize = 8;                                    // bytes per state element
@@ -249,7 +249,7 @@ size_t geo_doubles(int nyg, int nzg) {
 }
 
 struct Layout {
-  size_t geo, words, v0, xi, ringmin, ringshear, nshift, partial, sums, v2, T, total;
+  size_t geo, words, v0, xi, ringrate, ringshear, nshift, partial, sums, v2, T, total;
 };
 
 Layout layout(const fargo_params *p) {
@@ -268,7 +268,7 @@ Layout layout(const fargo_params *p) {
   o += al(nring * 8);
   L.xi = o;
   o += al(nring * 8);
-  L.ringmin = o;
+  L.ringrate = o;
   o += al(nring * 8);
   L.ringshear = o;
   o += al(nring * 8);
@@ -330,8 +330,8 @@ void timestep_phase(fargo_ctx *c, Launch &L, const StateT<F> &S, double dt) {
   const Mesh &m = c->m;
   if (dt > 0.0) launch_set_dt(L, c->w, dt);
   launch_bc(L, m, S.rho, S.e, S.vx, S.vy, S.vz);
-  launch_cfl(L, m, S, 1, c->v0, c->ringmin, c->ringshear, c->w.err);
-  launch_dt_final(L, m, c->w, c->ringmin, c->ringshear, dt > 0.0, c->v0, c->nshift, c->xi);
+  launch_cfl(L, m, S, 1, c->v0, c->ringrate, c->ringshear, c->w.err);
+  launch_dt_final(L, m, c->w, c->ringrate, c->ringshear, dt > 0.0, c->v0, c->nshift, c->xi);
 }
 
 } // namespace
@@ -468,7 +468,7 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   }
   c->v0 = (double *)(base + Lo.v0);
   c->xi = (double *)(base + Lo.xi);
-  c->ringmin = (double *)(base + Lo.ringmin);
+  c->ringrate = (double *)(base + Lo.ringrate);
   c->ringshear = (double *)(base + Lo.ringshear);
   c->nshift = (int32_t *)(base + Lo.nshift);
   c->partial = (double *)(base + Lo.partial);

@@ -175,12 +175,12 @@ template <typename R>
 void launch_bc(Launch &L, const Mesh &m, R *rho, R *e, R *vx, R *vy, R *vz);
 // boxes 3, 6 and the split of Eq. 29 (always FP64)
 void launch_set_dt(Launch &L, const DevWords &w, double dt);
-// per ring: v0 and (with_cfl) the minimum cell time step and maximum shear rate
+// per ring: v0 and (with_cfl) the largest squared rate 1/dt^2 of Eq. cfl2 and the maximum shear rate
 template <typename R>
-void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringmin,
+void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringrate,
                 double *ringshear, int *err);
 // dt from the ring slots (unless imposed), then N and xi of every ring
-void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringmin, const double *ringshear,
+void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringrate, const double *ringshear,
                      int use_given, const double *v0, int32_t *N, double *xi);
 void launch_split(Launch &L, const Mesh &m, const double *v0, double dt, int32_t *N, double *xi);
 // box 7: post-source velocities and energy into vx2, vy2, vz2, e2

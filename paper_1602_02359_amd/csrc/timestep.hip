@@ -63,7 +63,7 @@ __device__ inline double ring_bulk(const Mesh &m, const double (&v)[M], int tid,
 // in FP64 from the stored values.
 template <int M, typename R>
 __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_cfl, double *__restrict__ v0,
-                                                  double *__restrict__ ringmin, double *__restrict__ ringshear,
+                                                  double *__restrict__ ringrate, double *__restrict__ ringshear,
                                                   int *__restrict__ err) {
 #pragma clang fp contract(off)
   extern __shared__ double V[]; // the ring's v_x
@@ -86,11 +86,19 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
   if (!with_cfl) return;
   __syncthreads();
   const double vb = m.fargo ? vb_ring : 0.0;
+  // Eq. cfl2 through the inverse steps (rates u / Delta): the minimum step of
+  // a cell over directions is its maximum rate, and the smallest step is
+  // 1 / sqrt of the largest sum of squared rates (taken in k_dt_final)
   const double Lx = m.DX(j, k), Lyy = m.g.Ly[j];
   const double Lzz = m.d3 ? m.Lz(j, k) : 0.0;
+  const double iLx = 1.0 / Lx, iLy = 1.0 / Lyy, iLz = m.d3 ? 1.0 / Lzz : 0.0;
+  double Lmin = fmin(Lx, Lyy);
+  if (m.d3) Lmin = fmin(Lmin, Lzz);
+  const double iL2 = 1.0 / (Lmin * Lmin);
+  const double k3 = 4.0 * m.cvnr * m.cvnr;
   const bool shear_on = m.fargo && m.shear_c0 > 0.0 && j + 1 < m.jn;
   const double dXp = shear_on ? m.DX(j + 1, k) : 1.0;
-  double cmin = HUGE_VAL, smax = 0.0;
+  double rmax = 0.0, smax = 0.0;
   int bad = 0;
 #pragma unroll
   for (int mm = 0; mm < M; mm++) {
@@ -99,51 +107,47 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
     unsigned c = base + i;
     double vxc = vx[mm], vxp = V[i + 1 == n ? 0 : i + 1];
     double rho = (double)s.rho[c];
-    double cw;
-    if (m.eos == FARGO_ISOTHERMAL) cw = (double)s.cs[c];
-    else {
-      double P = (m.gamma - 1.0) * (double)s.e[c];
-      cw = sqrt(m.gamma * P / rho);
-    }
+    double cw2; // squared wave speed
+    if (m.eos == FARGO_ISOTHERMAL) cw2 = (double)s.cs[c] * (double)s.cs[c];
+    else cw2 = m.gamma * ((m.gamma - 1.0) * (double)s.e[c]) / rho;
     double vyc = (double)s.vy[c], vyp = (double)s.vy[c + m.pitch];
-    bad |= !(rho > 0.0) || !isfinite(rho) || !isfinite(cw) || !isfinite(vxc) || !isfinite(vyc);
-    double dt1 = fmin(Lx / cw, Lyy / cw);
+    bad |= !(rho > 0.0) || !isfinite(rho) || !isfinite(cw2) || !isfinite(vxc) || !isfinite(vyc);
+    // item 1: sound waves (squared rate); item 2: fluid motion; item 3:
+    // artificial viscosity on compressed directions
+    double r1s = cw2 * iL2;
     double ux = fmax(fabs(vxc - vb), fabs(vxp - vb));
     double uy = fmax(fabs(vyc), fabs(vyp));
-    double dt2 = fmin(Lx / ux, Lyy / uy);
+    double r2 = fmax(ux * iLx, uy * iLy);
     double dvx = vxp - vxc, dvy = vyp - vyc;
-    double dt3 = HUGE_VAL;
-    if (dvx < 0.0) dt3 = fmin(dt3, Lx / (4.0 * m.cvnr * m.cvnr * fabs(dvx)));
-    if (dvy < 0.0) dt3 = fmin(dt3, Lyy / (4.0 * m.cvnr * m.cvnr * fabs(dvy)));
+    double r3 = 0.0;
+    if (dvx < 0.0) r3 = fmax(r3, k3 * fabs(dvx) * iLx);
+    if (dvy < 0.0) r3 = fmax(r3, k3 * fabs(dvy) * iLy);
     if (m.d3) {
       double vzc = (double)s.vz[c], vzp = (double)s.vz[c + (unsigned)m.plane()];
       bad |= !isfinite(vzc);
-      dt1 = fmin(dt1, Lzz / cw);
       double uz = fmax(fabs(vzc), fabs(vzp));
-      dt2 = fmin(dt2, Lzz / uz);
+      r2 = fmax(r2, uz * iLz);
       double dvz = vzp - vzc;
-      if (dvz < 0.0) dt3 = fmin(dt3, Lzz / (4.0 * m.cvnr * m.cvnr * fabs(dvz)));
+      if (dvz < 0.0) r3 = fmax(r3, k3 * fabs(dvz) * iLz);
     }
-    double inv2 = 1.0 / (dt1 * dt1) + 1.0 / (dt2 * dt2) + 1.0 / (dt3 * dt3);
+    double rate2 = r1s + r2 * r2 + r3 * r3;
     if (m.visc) {
-      // item 4: viscosity, Delta^2 / (4 nu) with the smaller zone size
-      double Lmin = fmin(Lx, Lyy);
-      double dt4 = Lmin * Lmin / (4.0 * (double)s.nu[c]);
-      inv2 += 1.0 / (dt4 * dt4);
+      // item 4: viscosity, 4 nu / Delta^2
+      double r4 = 4.0 * (double)s.nu[c] * iL2;
+      rate2 += r4 * r4;
     }
-    double cell = 1.0 / sqrt(inv2);
-    if (!(cell >= 0.0)) bad = 1;
-    else cmin = cell < cmin ? cell : cmin;
+    if (!(rate2 >= 0.0)) bad = 1;
+    else rmax = rate2 > rmax ? rate2 : rmax;
     if (shear_on) {
       double sh = fabs(vxc / Lx - (double)s.vx[c + m.pitch] / dXp);
       if (sh > smax) smax = sh;
     }
   }
-  cmin = block_reduce(cmin, Min(), HUGE_VAL, red);
+  rmax = block_reduce(rmax, Max(), 0.0, red);
   smax = block_reduce(smax, Max(), 0.0, red);
   int anybad = __syncthreads_or(bad);
   if (tid == 0) {
-    ringmin[r] = cmin;
+    ringrate[r] = rmax; // the ring's largest squared rate
     ringshear[r] = smax;
     if (anybad) atomicOr(err, 1);
   }
@@ -152,7 +156,7 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
 // One workgroup: dt from the ring slots (or the imposed value), then the split
 // of every ring.  A non-positive or non-finite dt is flagged and replaced by 0,
 // which leaves the state unchanged.
-__global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const double *__restrict__ ringmin,
+__global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const double *__restrict__ ringrate,
                                                    const double *__restrict__ ringshear, int use_given,
                                                    const double *__restrict__ v0, int32_t *__restrict__ N,
                                                    double *__restrict__ xi) {
@@ -160,15 +164,15 @@ __global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const dou
   __shared__ double red[MAXW];
   __shared__ double dts;
   if (!use_given) {
-    double cmin = HUGE_VAL, smax = 0.0;
+    double rmax = 0.0, smax = 0.0;
     for (int r = threadIdx.x; r < m.nring; r += blockDim.x) {
-      cmin = ringmin[r] < cmin ? ringmin[r] : cmin;
+      rmax = ringrate[r] > rmax ? ringrate[r] : rmax;
       smax = ringshear[r] > smax ? ringshear[r] : smax;
     }
-    cmin = block_reduce(cmin, Min(), HUGE_VAL, red);
+    rmax = block_reduce(rmax, Max(), 0.0, red);
     smax = block_reduce(smax, Max(), 0.0, red);
     if (threadIdx.x == 0) {
-      double dt = m.courant * cmin;
+      double dt = m.courant * (1.0 / sqrt(rmax));
       if (m.fargo && m.shear_c0 > 0.0 && smax > 0.0) dt = fmin(dt, m.shear_c0 / smax);
       if (!(dt > 0.0) || !isfinite(dt)) {
         atomicOr(w.err, 2);
@@ -220,14 +224,14 @@ void launch_set_dt(Launch &L, const DevWords &w, double dt) {
 }
 
 template <typename R>
-void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringmin,
+void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringrate,
                 double *ringshear, int *err) {
   prof_begin(L, K_CFL);
   int M = (m.nx + 255) / 256;
-  if (M <= 1) cfl_launch<1, R>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
-  else if (M == 2) cfl_launch<2, R>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
-  else if (M <= 4) cfl_launch<4, R>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
-  else cfl_launch<8, R>(L, m, s, with_cfl, v0, ringmin, ringshear, err);
+  if (M <= 1) cfl_launch<1, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err);
+  else if (M == 2) cfl_launch<2, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err);
+  else if (M <= 4) cfl_launch<4, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err);
+  else cfl_launch<8, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err);
   prof_end(L, K_CFL);
 }
 
@@ -236,10 +240,10 @@ template void launch_cfl<double>(Launch &, const Mesh &, const StateT<double> &,
 template void launch_cfl<float>(Launch &, const Mesh &, const StateT<float> &, int, double *, double *, double *,
                                 int *);
 
-void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringmin, const double *ringshear,
+void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringrate, const double *ringshear,
                      int use_given, const double *v0, int32_t *N, double *xi) {
   prof_begin(L, K_DT_FINAL);
-  k_dt_final<<<1, 1024, 0, L.s>>>(m, w, ringmin, ringshear, use_given, v0, N, xi);
+  k_dt_final<<<1, 1024, 0, L.s>>>(m, w, ringrate, ringshear, use_given, v0, N, xi);
   prof_end(L, K_DT_FINAL);
 }
 
