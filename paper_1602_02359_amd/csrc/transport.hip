@@ -46,24 +46,26 @@ __device__ inline F vl_star(F w, F dt, F ql, F al, F Ll, F qr, F ar, F Lr) {
   return w >= F(0) ? ql + al * (Ll - w * dt) * F(0.5) : qr - ar * (Lr + w * dt) * F(0.5);
 }
 
-template <typename F, int NQ>
+template <typename F, int NQ, bool CT>
 struct Zone {
-  F rho, q[NQ], T[NQ]; // density, Q/rho, conserved Q
-  F w;                 // velocity on the zone's lower face in the sweep direction
+  F rho, q[NQ]; // density, Q/rho
+  F w;          // velocity on the zone's lower face in the sweep direction
+  F T[CT ? NQ : 1]; // conserved Q, when carried in the window (CT)
 };
 
 // Column sweep over zones [a0, a1) of one column.  `raw(a, RW&)` issues the
-// loads of zone a, `derive(a, const RW&, Zone&)` forms its density, Q/rho, Q
-// and lower-face velocity; `geo` gives L(a) (zone width), h(f) (centre
-// distance at face f), S(f), Vi(a); `st(a, rho, T[])` stores the updated
-// zone.  With FP32 fields the loads of zone f + 2 are issued while zone f is
+// loads of zone a, `derive(a, const RW&, Zone&)` forms its density, Q/rho and
+// lower-face velocity, `Tof(a, const Zone&, q)` gives the conserved Q of zone
+// a (carried in the window when CT, else formed again); `geo` gives L(a) (zone width), h(f)
+// (centre distance at face f), S(f), Vi(a); `st(a, rho, T[])` stores the
+// updated zone.  With FP32 fields the loads of zone f + 2 are issued while zone f is
 // being computed; with FP64 fields the registers that would take are worth
 // more as occupancy, and zone f + 1 is loaded at the start of step f.
-template <typename F, int NQ, class RW, class RAW, class DER, class GEO, class ST>
-__device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const DER &derive, const GEO &geo,
-                                    const ST &st) {
+template <typename F, int NQ, bool CT, class RW, class RAW, class DER, class TOF, class GEO, class ST>
+__device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const DER &derive, const TOF &Tof,
+                                    const GEO &geo, const ST &st) {
   constexpr bool PF = sizeof(F) == 4;
-  Zone<F, NQ> zm, z0, zp;
+  Zone<F, NQ, CT> zm, z0, zp;
   RW rn;
   raw(a0 - 2, rn);
   derive(a0 - 2, rn, zp); // used only for the first slope
@@ -102,7 +104,7 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
       F vi = geo.Vi(f - 1);
       F Tn[NQ];
 #pragma unroll
-      for (int q = 0; q < NQ; q++) Tn[q] = zm.T[q] - vi * (FQ[q] - FQp[q]);
+      for (int q = 0; q < NQ; q++) Tn[q] = Tof(f - 1, zm, q) - vi * (FQ[q] - FQp[q]);
       st(f - 1, zm.rho - vi * (Fr - Fp), Tn);
     }
     Fp = Fr;
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
     }
     if (ADI) z.e = e[c];
   };
-  auto derive = [&](int a, const Raw &w, Zone<F, NQ> &z) {
+  auto derive = [&](int a, const Raw &w, Zone<F, NQ, false> &z) {
     const F r = w.rho;
     z.rho = r;
     z.w = w.vy0;
@@ -167,12 +169,12 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
       z.q[4] = m.mz(a, w.vz0);
       z.q[5] = m.mz(a, w.vz1);
     }
-#pragma unroll
-    for (int q = 0; q < (ADI ? NQ - 1 : NQ); q++) z.T[q] = r * z.q[q];
-    if (ADI) {
-      z.T[NQ - 1] = w.e;
-      z.q[NQ - 1] = w.e / r;
-    }
+    if (ADI) z.q[NQ - 1] = w.e / r;
+  };
+  // the momenta are rho m(v) exactly as formed; e is read again (a cache hit)
+  auto Tof = [&](int a, const Zone<F, NQ, false> &z, int q) {
+    if (ADI && q == NQ - 1) return e[m.o32(i, a, k)];
+    return z.rho * z.q[q];
   };
   struct Geo {
     const Mesh &m;
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
 #pragma unroll
     for (int q = 0; q < NQ; q++) out.q[q][c] = T[q];
   };
-  column_sweep<F, NQ, Raw>(a0, a1, dt, raw, derive, geo, st);
+  column_sweep<F, NQ, false, Raw>(a0, a1, dt, raw, derive, Tof, geo, st);
 }
 
 // ------------------------------------------------------------------------
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(256) void k_sweep_z(Mesh m, const F *__restrict__ v
 #pragma unroll
     for (int q = 0; q < NQ; q++) z.T[q] = in.q[q][c];
   };
-  auto derive = [&](int, const Raw &w, Zone<F, NQ> &z) {
+  auto derive = [&](int, const Raw &w, Zone<F, NQ, true> &z) {
     const F ri = F(1) / w.rho;
     z.rho = w.rho;
     z.w = w.w;
@@ -226,6 +228,7 @@ __global__ __launch_bounds__(256) void k_sweep_z(Mesh m, const F *__restrict__ v
       z.q[q] = w.T[q] * ri;
     }
   };
+  auto Tof = [&](int, const Zone<F, NQ, true> &z, int q) { return z.T[q]; };
   struct Geo {
     const Mesh &m;
     int j;
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(256) void k_sweep_z(Mesh m, const F *__restrict__ v
 #pragma unroll
     for (int q = 0; q < NQ; q++) out.q[q][c] = T[q];
   };
-  column_sweep<F, NQ, Raw>(a0, a1, dt, raw, derive, geo, st);
+  column_sweep<F, NQ, true, Raw>(a0, a1, dt, raw, derive, Tof, geo, st);
 }
 
 // ------------------------------------------------------------------------
