@@ -40,32 +40,54 @@ __device__ inline F qvisc(F c2, F rho, F dv) { return dv < F(0) ? c2 * rho * dv 
 
 template <typename F>
 struct Lds {
-  F R[2][SY][SX];  // density (two planes in flight)
-  F P[SY][SX];     // pressure
-  double Ph[SY][SX]; // potential (FP64 in every mode)
-  F VX[SY][SX];    // v_x on the lower X face of each zone slot
-  F VY[SY][TX];    // v_y on the lower Y face of each zone slot
-  F VT[SY][TX];    // spherical: v_theta on the zone's two Z faces, summed
-  F AX[TY][SX];    // v'_x of X faces of the tile rows
-  F IX[TY][SX];    // 1 / ((rho_i + rho_{i-1}) dX) on those faces
-  F AY[SY][TX];    // v'_y of Y faces
-  F IY[SY][TX];    // 1 / ((rho_j + rho_{j-1}) h_y) on those faces
+  // staging of a plane (two planes in flight; density three)
+  F R[3][SY][SX];      // density
+  F P[2][SY][SX];      // pressure
+  double Ph[2][SY][SX]; // potential (FP64 in every mode)
+  F VX[2][SY][SX];     // v_x on the lower X face of each zone slot
+  F VY[2][SY][TX];     // v_y on the lower Y face of each zone slot
+  F VT[2][SY][TX];     // spherical: v_theta on the zone's two Z faces, summed
+  // v' of the faces of a plane (two planes in flight)
+  F AX[2][TY][SX];     // v'_x of X faces of the tile rows
+  F IX[2][TY][SX];     // 1 / ((rho_i + rho_{i-1}) dX) on those faces
+  F AY[2][SY][TX];     // v'_y of Y faces
+  F IY[2][SY][TX];     // 1 / ((rho_j + rho_{j-1}) h_y) on those faces
+  double DX[2][TY];    // 1 / dX of the tile rows, for the halo X faces
 };
+
+// An explicit register move.  The march keeps a window of plane records in
+// registers and rotates it once per plane; moving the newest record out of its
+// registers before the next plane's loads are issued lets those loads write
+// the same registers, instead of temporaries whose copy into the window would
+// wait for the loads to arrive.
+template <typename T>
+__device__ inline T vmove(T x) {
+  T y;
+  if constexpr (sizeof(T) == 8) asm("v_mov_b64 %0, %1" : "=v"(y) : "v"(x));
+  else asm("v_mov_b32 %0, %1" : "=v"(y) : "v"(x));
+  return y;
+}
 
 // one zone's values in one plane
 template <typename F>
 struct Zv {
-  F rho, P;
+  F rho, q; // q: sound speed (isothermal) or internal energy (adiabatic)
   double pot;
   F vz, vx, vxp; // vxp: v_x on the next X face
 };
 
+// A plane goes through three phases: staging into LDS (S), v' of its faces
+// (F), and the zones (Z).  The march is software-pipelined over planes: one
+// barrier interval runs Z(k), F(k+1) and S(k+2) on separate buffers, so each
+// plane costs one barrier and the three phases overlap.
 template <typename F, bool D3>
 __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
                                                   F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
                                                   F *__restrict__ e2, int nbx, int nby) {
   __shared__ Lds<F> L;
-  const int tid = threadIdx.x, r = tid >> 6, c = tid & 63;
+  // the row is the wave index: uniform, so that geometric factors of the
+  // row come through scalar loads, which do not stall behind the prefetches
+  const int tid = threadIdx.x, r = __builtin_amdgcn_readfirstlane(tid >> 6), c = tid & 63;
   const unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
   const int ty = (int)(Lb % (unsigned)nby), tx = (int)(Lb / (unsigned)nby);
   const int i0 = tx * TX, jt0 = m.j0 + ty * TY;
@@ -90,12 +112,14 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
   };
   auto yowned = [&](int f) { return f >= m.ylo() && f < m.jn; };
   auto zowned = [&](int f) { return f >= m.zlo() && f < m.kn; };
-  auto pres = [&](unsigned o) { return adi ? gm1 * s.e[o] : s.cs[o] * s.cs[o] * s.rho[o]; };
+  // Loads keep raw field values and derived ones are formed where they are
+  // used, so that a prefetched load is not waited for when it is issued.
+  auto pres = [&](F rho, F q) { return adi ? gm1 * q : q * q * rho; };
   auto loadz = [&](int k, Zv<F> &z) {
     const unsigned o = m.o32(i, j, k);
     const int ip = i + 1 == m.nx ? 0 : i + 1;
     z.rho = s.rho[o];
-    z.P = pres(o);
+    z.q = adi ? s.e[o] : s.cs[o];
     z.pot = s.pot[o];
     z.vz = D3 ? s.vz[o] : F(0);
     z.vx = s.vx[o];
@@ -106,10 +130,10 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
   auto vz1 = [&](int p, const Zv<F> &zb, const Zv<F> &z0, F &iz) {
     iz = F(0);
     if (!zowned(p)) return z0.vz;
-    const F ihz = sph ? (F)(m.g.inv_dzmed[p] * m.g.inv_ymed[j]) : (F)m.g.inv_dzmed[p];
-    iz = ihz / (z0.rho + zb.rho);
-    F gradP = F(2) * (z0.P - zb.P) * iz;
-    F gradPhi = (F)((z0.pot - zb.pot) * (sph ? m.g.inv_dzmed[p] * m.g.inv_ymed[j] : m.g.inv_dzmed[p]));
+    const double ihzd = sph ? m.g.inv_dzmed[p] * m.g.inv_ymed[j] : m.g.inv_dzmed[p];
+    iz = (F)ihzd / (z0.rho + zb.rho);
+    F gradP = F(2) * (pres(z0.rho, z0.q) - pres(zb.rho, zb.q)) * iz;
+    F gradPhi = (F)((z0.pot - zb.pot) * ihzd);
     F src = F(0);
     if (sph) {
       F R0 = (F)(m.g.ymed[j] * m.g.sinz[p]), R1 = (F)(m.g.ymed[j] * m.g.sinz[m.kbelow(p)]);
@@ -120,28 +144,6 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
   };
   const bool per = m.zper();
   auto pl = [&](int p) { return per ? m.k0 + (p - m.k0 + 2 * m.nz) % m.nz : p; };
-
-  // Z window of the thread's column: planes k-1 (rho only), k, k+1, k+2
-  Zv<F> Z0{}, Z1{}, Z2{};
-  F Rm1 = F(0), A[4] = {}, IZ[4] = {}, Q[3] = {};
-  const int kfirst = m.k0, klast = m.kn;
-  if (act) {
-    if (D3) {
-      Zv<F> Zm2, Zm1;
-      loadz(pl(kfirst - 2), Zm2);
-      loadz(pl(kfirst - 1), Zm1);
-      A[0] = vz1(pl(kfirst - 1), Zm2, Zm1, IZ[0]);
-      Rm1 = Zm1.rho;
-      loadz(kfirst, Z0);
-      A[1] = vz1(kfirst, Zm1, Z0, IZ[1]);
-      loadz(pl(kfirst + 1), Z1);
-      A[2] = vz1(pl(kfirst + 1), Z0, Z1, IZ[2]);
-      Q[0] = qvisc(c2, Rm1, A[1] - A[0]);
-      Q[1] = qvisc(c2, Z0.rho, A[2] - A[1]);
-    } else {
-      loadz(0, Z0);
-    }
-  }
 
   // The halo zone this thread stages, if any (fixed over the march):
   // role 1, Y halo rows 0, 1, h+2, h+3 over the tile's columns (with v_y and,
@@ -167,188 +169,265 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
   }
   const unsigned hbase = role ? m.o32(xcol(hsl), yrow(ht), 0) : 0u;
   const bool hvy = role == 1 && ht != 0, hvt = role == 1 && sph;
-  // The values an iteration stages (own v_y, the window's next plane and the
-  // halo zone) are loaded one iteration ahead, so that their latency overlaps
-  // the previous plane's work.  FP64 fields need more registers than two
-  // workgroups per CU leave, so that kernel runs one workgroup per CU.
-  constexpr bool PF = true;
-  struct Pre {
-    Zv<F> z;     // window plane kk + 2
-    F vy;        // own v_y at plane kk
-    F hr, hP, hx, hy, ht;
-    double hp;   // halo: rho, P, v_x, v_y, summed v_theta, potential
+  // what staging takes from memory besides the window: own v_y and the halo
+  struct Halo {
+    F vy, hr, hq, hx, hy, ht0, ht1;
+    double hp;
   };
-  auto fetch_window = [&](int kk, Pre &n) {
-    if (act && D3) loadz(pl(kk + 2), n.z);
-  };
-  auto fetch_stage = [&](int kk, Pre &n) {
+  auto load_halo = [&](int kk, Halo &n) {
     if (act) n.vy = s.vy[m.o32(i, j, kk)];
     if (role) {
       const unsigned o = hbase + (unsigned)kk * plane;
       n.hx = s.vx[o];
       if (role != 3) {
         n.hr = s.rho[o];
-        n.hP = pres(o);
+        n.hq = adi ? s.e[o] : s.cs[o];
         n.hp = s.pot[o];
       }
       if (hvy) n.hy = s.vy[o];
       if (hvt) {
         const int kp = D3 ? m.kabove(kk) : kk;
-        n.ht = s.vz[o] + s.vz[o + (unsigned)(kp - kk) * plane];
+        n.ht0 = s.vz[o];
+        n.ht1 = s.vz[o + (unsigned)(kp - kk) * plane];
       }
     }
   };
-  auto prefetch = [&](int kk, Pre &n) {
-    fetch_window(kk, n);
-    fetch_stage(kk, n);
-  };
-  Pre nx{};
-  if (PF) prefetch(kfirst, nx);
-
-  int buf = 0;
-#pragma unroll 1
-  for (int kk = kfirst; kk < klast; kk++) {
-    const int ka = D3 ? pl(kk + 1) : kk;
-    Pre cur;
-    if (PF) {
-      cur = nx;
-      if (kk + 1 < klast) prefetch(kk + 1, nx);
-    } else {
-      fetch_window(kk, cur);
-    }
-    if (D3 && act) {
-      Z2 = cur.z;
-      A[3] = vz1(pl(kk + 2), Z1, Z2, IZ[3]);
-      Q[2] = qvisc(c2, Z1.rho, A[3] - A[2]);
-    }
-    F(*R)[SX] = L.R[buf];
-    if (!PF) fetch_stage(kk, cur);
-    // ---- stage plane kk: interior from the window, halo from the prefetched values
+  // S: stage plane kk into buffers sb (and rb for the density); interior from
+  // the window record z (vt = summed v_theta of the zone), halo from hv
+  auto stage = [&](int kk, int sb, int rb, const Zv<F> &z, F vt, const Halo &hv) {
+    F(*R)[SX] = L.R[rb];
+    if (c == 0 && r < h) L.DX[sb][r] = m.g.inv_dxlen[(size_t)kk * m.nyg + jt0 + r];
     if (act) {
-      R[r + 2][c + 2] = Z0.rho;
-      L.P[r + 2][c + 2] = Z0.P;
-      L.Ph[r + 2][c + 2] = Z0.pot;
-      L.VX[r + 2][c + 2] = Z0.vx;
-      if (sph) L.VT[r + 2][c] = Z0.vz + Z1.vz;
-      L.VY[r + 2][c] = cur.vy;
+      R[r + 2][c + 2] = z.rho;
+      L.P[sb][r + 2][c + 2] = pres(z.rho, z.q);
+      L.Ph[sb][r + 2][c + 2] = z.pot;
+      L.VX[sb][r + 2][c + 2] = z.vx;
+      if (sph) L.VT[sb][r + 2][c] = vt;
+      L.VY[sb][r + 2][c] = hv.vy;
     }
     if (role) {
-      L.VX[ht][hsl] = cur.hx;
+      L.VX[sb][ht][hsl] = hv.hx;
       if (role != 3) {
-        R[ht][hsl] = cur.hr;
-        L.P[ht][hsl] = cur.hP;
-        L.Ph[ht][hsl] = cur.hp;
+        R[ht][hsl] = hv.hr;
+        L.P[sb][ht][hsl] = pres(hv.hr, hv.hq);
+        L.Ph[sb][ht][hsl] = hv.hp;
       }
-      if (hvy) L.VY[ht][hsl - 2] = cur.hy;
-      if (hvt) L.VT[ht][hsl - 2] = cur.ht;
+      if (hvy) L.VY[sb][ht][hsl - 2] = hv.hy;
+      if (hvt) L.VT[sb][ht][hsl - 2] = hv.ht0 + hv.ht1;
     }
-    __syncthreads();
-    // ---- 7a on the X and Y faces of the tile and of the halo faces needed
-    auto xface = [&](int rr, int sl) {
-      const int t = rr + 2, y = jt0 + rr;
-      const double idXd = m.g.inv_dxlen[(size_t)kk * m.nyg + y];
+  };
+  // F: 7a on the X and Y faces of plane kk (staged in sb, rb) into face buffer sb
+  auto faces = [&](int kk, int sb, int rb) {
+    F(*R)[SX] = L.R[rb];
+    auto xface = [&](int rr, int sl, double idXd) {
+      const int t = rr + 2;
       const F inv = (F)idXd / (R[t][sl] + R[t][sl - 1]);
-      const F gradP = F(2) * (L.P[t][sl] - L.P[t][sl - 1]) * inv;
-      const F gradPhi = (F)((L.Ph[t][sl] - L.Ph[t][sl - 1]) * idXd);
-      L.AX[rr][sl] = L.VX[t][sl] - dt * (gradP + gradPhi);
-      L.IX[rr][sl] = inv;
+      const F gradP = F(2) * (L.P[sb][t][sl] - L.P[sb][t][sl - 1]) * inv;
+      const F gradPhi = (F)((L.Ph[sb][t][sl] - L.Ph[sb][t][sl - 1]) * idXd);
+      L.AX[sb][rr][sl] = L.VX[sb][t][sl] - dt * (gradP + gradPhi);
+      L.IX[sb][rr][sl] = inv;
     };
     auto yface = [&](int t, int cc) {
       const int f = yrow(t), sl = cc + 2;
       if (!yowned(f)) {
-        L.AY[t][cc] = L.VY[t][cc];
-        L.IY[t][cc] = F(0);
+        L.AY[sb][t][cc] = L.VY[sb][t][cc];
+        L.IY[sb][t][cc] = F(0);
         return;
       }
       const double ihd = m.g.inv_hy[f];
       const F inv = (F)ihd / (R[t][sl] + R[t - 1][sl]);
-      const F gradP = F(2) * (L.P[t][sl] - L.P[t - 1][sl]) * inv;
-      const F gradPhi = (F)((L.Ph[t][sl] - L.Ph[t - 1][sl]) * ihd);
+      const F gradP = F(2) * (L.P[sb][t][sl] - L.P[sb][t - 1][sl]) * inv;
+      const F gradPhi = (F)((L.Ph[sb][t][sl] - L.Ph[sb][t - 1][sl]) * ihd);
       F src = F(0);
       if (cyl || sph) {
         const int ya = yrow(t - 1);
         const F Rt = (F)(sph ? m.g.ymed[f] * m.g.sinz[kk] : m.g.ymed[f]);
         const F Ra = (F)(sph ? m.g.ymed[ya] * m.g.sinz[kk] : m.g.ymed[ya]);
-        const F vt0 = (L.VX[t][sl] + Rt * om) + (L.VX[t][sl + 1] + Rt * om);
-        const F vt1 = (L.VX[t - 1][sl] + Ra * om) + (L.VX[t - 1][sl + 1] + Ra * om);
+        const F vt0 = (L.VX[sb][t][sl] + Rt * om) + (L.VX[sb][t][sl + 1] + Rt * om);
+        const F vt1 = (L.VX[sb][t - 1][sl] + Ra * om) + (L.VX[sb][t - 1][sl + 1] + Ra * om);
         const F v = F(0.25) * (vt0 + vt1);
         src = v * v;
         if (sph) {
-          const F wv = F(0.25) * (L.VT[t][cc] + L.VT[t - 1][cc]);
+          const F wv = F(0.25) * (L.VT[sb][t][cc] + L.VT[sb][t - 1][cc]);
           src += wv * wv;
         }
         src *= (F)m.g.inv_ymin[f];
       }
-      L.AY[t][cc] = L.VY[t][cc] - dt * (gradP + gradPhi) + dt * src;
-      L.IY[t][cc] = inv;
+      L.AY[sb][t][cc] = L.VY[sb][t][cc] - dt * (gradP + gradPhi) + dt * src;
+      L.IY[sb][t][cc] = inv;
     };
     if (act) {
-      xface(r, c + 2);
+      xface(r, c + 2, m.g.inv_dxlen[(size_t)kk * m.nyg + jt0 + r]);
       yface(r + 2, c);
     }
-    if (tid < 192) {
-      const int q = tid >> 6, t = q == 0 ? 1 : h + 1 + q;
+    if (r < 3) {
+      const int t = r == 0 ? 1 : h + 1 + r;
       if (c < w) yface(t, c);
     } else if (tid < 192 + 3 * TY) {
       const int q = tid - 192, rr = q / 3, a = q % 3, sl = a == 0 ? 1 : w + 1 + a;
-      if (rr < h) xface(rr, sl);
+      if (rr < h) xface(rr, sl, L.DX[sb][rr]);
     }
-    __syncthreads();
-    // ---- 7b and 7c per zone
+  };
+  // Z: 7b and 7c for the zones of plane kk (faces in sb, density in rb); zd
+  // gives the Z part: bz1/bz2 (v'' of faces kk and above(kk)), qz and dvz
+  struct ZPart {
+    F bz1, bz2, qz, dvz;
+  };
+  auto zones = [&](int kk, int sb, int rb, const ZPart &zp, F e_old) {
+    F(*R)[SX] = L.R[rb];
+    const int t = r + 2, sl = c + 2;
+    const unsigned o = m.o32(i, j, kk);
+    // X: faces sl-1 .. sl+2, zones sl-1 .. sl+1
+    const F a0 = L.AX[sb][r][sl - 1], a1 = L.AX[sb][r][sl], a2 = L.AX[sb][r][sl + 1], a3 = L.AX[sb][r][sl + 2];
+    const F r1 = R[t][sl - 1], r2 = R[t][sl], r3 = R[t][sl + 1];
+    const F dvx = a2 - a1;
+    const F qx = qvisc(c2, r2, dvx), qxm = qvisc(c2, r1, a1 - a0), qxp = qvisc(c2, r3, a3 - a2);
+    const F bx1 = a1 - dt * F(2) * (qx - qxm) * L.IX[sb][r][sl];
+    const F bx2 = a2 - dt * F(2) * (qxp - qx) * L.IX[sb][r][sl + 1];
+    vx2[o] = bx1;
+    F heat = qx * dvx * (F)m.g.inv_dxlen[(size_t)kk * m.nyg + j];
+    F flux = (F)m.Sx(j, kk) * (bx2 - bx1);
+    // Y: faces t-1 .. t+2, zones t-1 .. t+1
+    const F b0 = L.AY[sb][t - 1][c], b1 = L.AY[sb][t][c], b2 = L.AY[sb][t + 1][c], b3 = L.AY[sb][t + 2][c];
+    const F s1 = R[t - 1][sl], s3 = R[t + 1][sl];
+    const F dvy = b2 - b1;
+    const F qy = qvisc(c2, r2, dvy);
+    F by1 = b1, by2 = b2;
+    if (yowned(j)) by1 = b1 - dt * F(2) * (qy - qvisc(c2, s1, b1 - b0)) * L.IY[sb][t][c];
+    if (yowned(yrow(t + 1))) by2 = b2 - dt * F(2) * (qvisc(c2, s3, b3 - b2) - qy) * L.IY[sb][t + 1][c];
+    vy2[o] = by1;
+    heat += qy * dvy * (F)m.g.inv_Ly[j];
+    flux += (F)m.Sy(j + 1, kk) * by2 - (F)m.Sy(j, kk) * by1;
+    if (D3) {
+      vz2[o] = zp.bz1;
+      const F iLz = sph ? (F)(m.g.inv_dz[kk] * m.g.inv_ymed[j]) : (F)m.g.inv_dz[kk];
+      heat += zp.qz * zp.dvz * iLz;
+      flux += (F)m.Sz(j, kk + 1) * zp.bz2 - (F)m.Sz(j, kk) * zp.bz1;
+    }
+    if (adi) {
+      const F e1 = e_old - dt * heat;
+      const F a = F(0.5) * dt * gm1 * ((F)m.Vinv(j, kk) * flux);
+      e2[o] = e1 * (F(1) - a) / (F(1) + a);
+    }
+  };
+
+  if (!D3) {
+    // a single plane: S, F, Z in turn
+    Zv<F> z0{};
+    Halo hv{};
+    F e_old = F(0);
     if (act) {
-      const int t = r + 2, sl = c + 2;
-      const unsigned o = m.o32(i, j, kk);
-      // X: faces sl-1 .. sl+2, zones sl-1 .. sl+1
-      const F a0 = L.AX[r][sl - 1], a1 = L.AX[r][sl], a2 = L.AX[r][sl + 1], a3 = L.AX[r][sl + 2];
-      const F r1 = R[t][sl - 1], r2 = R[t][sl], r3 = R[t][sl + 1];
-      const F dvx = a2 - a1;
-      const F qx = qvisc(c2, r2, dvx), qxm = qvisc(c2, r1, a1 - a0), qxp = qvisc(c2, r3, a3 - a2);
-      const F bx1 = a1 - dt * F(2) * (qx - qxm) * L.IX[r][sl];
-      const F bx2 = a2 - dt * F(2) * (qxp - qx) * L.IX[r][sl + 1];
-      vx2[o] = bx1;
-      F heat = qx * dvx * (F)m.g.inv_dxlen[(size_t)kk * m.nyg + j];
-      F flux = (F)m.Sx(j, kk) * (bx2 - bx1);
-      // Y: faces t-1 .. t+2, zones t-1 .. t+1
-      const F b0 = L.AY[t - 1][c], b1 = L.AY[t][c], b2 = L.AY[t + 1][c], b3 = L.AY[t + 2][c];
-      const F s1 = R[t - 1][sl], s3 = R[t + 1][sl];
-      const F dvy = b2 - b1;
-      const F qy = qvisc(c2, r2, dvy);
-      F by1 = b1, by2 = b2;
-      if (yowned(j)) by1 = b1 - dt * F(2) * (qy - qvisc(c2, s1, b1 - b0)) * L.IY[t][c];
-      if (yowned(yrow(t + 1))) by2 = b2 - dt * F(2) * (qvisc(c2, s3, b3 - b2) - qy) * L.IY[t + 1][c];
-      vy2[o] = by1;
-      heat += qy * dvy * (F)m.g.inv_Ly[j];
-      flux += (F)m.Sy(j + 1, kk) * by2 - (F)m.Sy(j, kk) * by1;
-      if (D3) {
-        F bz1 = Z0.vz, bz2 = Z1.vz;
-        if (zowned(kk)) bz1 = A[1] - dt * F(2) * (Q[1] - Q[0]) * IZ[1];
-        if (zowned(ka)) bz2 = A[2] - dt * F(2) * (Q[2] - Q[1]) * IZ[2];
-        vz2[o] = bz1;
-        const F iLz = sph ? (F)(m.g.inv_dz[kk] * m.g.inv_ymed[j]) : (F)m.g.inv_dz[kk];
-        heat += Q[1] * (A[2] - A[1]) * iLz;
-        flux += (F)m.Sz(j, kk + 1) * bz2 - (F)m.Sz(j, kk) * bz1;
-      }
-      if (adi) {
-        const F e1 = s.e[o] - dt * heat;
-        const F a = F(0.5) * dt * gm1 * ((F)m.Vinv(j, kk) * flux);
-        e2[o] = e1 * (F(1) - a) / (F(1) + a);
-      }
-      if (D3) {
-        Rm1 = Z0.rho;
-        Z0 = Z1;
+      loadz(0, z0);
+      e_old = z0.q;
+    }
+    load_halo(0, hv);
+    stage(0, 0, 0, z0, F(0), hv);
+    __syncthreads();
+    faces(0, 0, 0);
+    __syncthreads();
+    if (act) zones(0, 0, 0, ZPart{}, e_old);
+    return;
+  }
+
+  // ---- 3D march over the active planes k0 .. kn-1
+  const int k0 = m.k0, kn = m.kn;
+  // Z window of the thread's column at the top of interval kk:
+  //   Z1, Z2 = records of planes kk+1, kk+2; vzk = v_z of plane kk;
+  //   A[0..2] = v'_z of faces kk .. kk+2, IZ likewise; Q[0..2] = q_z of
+  //   zones kk-1 .. kk+1
+  Zv<F> Z1{}, Z2{}, Zn{};
+  F vzk = F(0), A[3] = {}, IZ[3] = {}, Q[3] = {}, e_cur = F(0);
+  Halo hv{}, hn{};
+  if (act) {
+    Zv<F> a, b, z0;
+    F Am1, IZm1, A0, IZ0, A1, IZ1, A2, IZ2;
+    loadz(pl(k0 - 2), a);
+    loadz(pl(k0 - 1), b);
+    loadz(k0, z0);
+    loadz(pl(k0 + 1), Z1);
+    loadz(pl(k0 + 2), Z2);
+    Am1 = vz1(pl(k0 - 1), a, b, IZm1);
+    A0 = vz1(k0, b, z0, IZ0);
+    A1 = vz1(pl(k0 + 1), z0, Z1, IZ1);
+    A2 = vz1(pl(k0 + 2), Z1, Z2, IZ2);
+    (void)IZm1;
+    A[0] = A0;
+    A[1] = A1;
+    A[2] = A2;
+    IZ[0] = IZ0;
+    IZ[1] = IZ1;
+    IZ[2] = IZ2;
+    Q[0] = qvisc(c2, b.rho, A0 - Am1);
+    Q[1] = qvisc(c2, z0.rho, A1 - A0);
+    Q[2] = qvisc(c2, Z1.rho, A2 - A1);
+    vzk = z0.vz;
+    e_cur = z0.q;
+    // prologue: S(k0), then F(k0) with S(k0+1)
+    load_halo(k0, hv);
+    stage(k0, 0, 0, z0, z0.vz + Z1.vz, hv);
+  } else {
+    load_halo(k0, hv);
+    stage(k0, 0, 0, Zv<F>{}, F(0), hv);
+  }
+  __syncthreads();
+  faces(k0, 0, 0);
+  load_halo(pl(k0 + 1), hv);
+  stage(k0 + 1, 1, 1, Z1, Z1.vz + Z2.vz, hv);
+  // prefetch for interval k0: record of plane k0+3, halo of plane k0+2
+  if (act) loadz(pl(k0 + 3), Zn);
+  if (k0 + 2 < kn) load_halo(k0 + 2, hn);
+  __syncthreads();
+
+  int sb = 0, rb = 0; // buffers of plane kk
+#pragma unroll 1
+  for (int kk = k0; kk < kn; kk++) {
+    const int sb1 = sb ^ 1, rb1 = rb == 2 ? 0 : rb + 1, rb2 = rb1 == 2 ? 0 : rb1 + 1;
+    // Z(kk)
+    if (act) {
+      ZPart zp;
+      const int ka = pl(kk + 1);
+      zp.bz1 = zowned(kk) ? A[0] - dt * F(2) * (Q[1] - Q[0]) * IZ[0] : vzk;
+      zp.bz2 = zowned(ka) ? A[1] - dt * F(2) * (Q[2] - Q[1]) * IZ[1] : Z1.vz;
+      zp.qz = Q[1];
+      zp.dvz = A[1] - A[0];
+      zones(kk, sb, rb, zp, e_cur);
+    }
+    // F(kk+1), S(kk+2)
+    if (kk + 1 < kn) faces(kk + 1, sb1, rb1);
+    if (kk + 2 < kn) stage(kk + 2, sb, rb2, Z2, Z2.vz + Zn.vz, hn);
+    // advance the window and prefetch for interval kk+1
+    if (kk + 1 < kn) {
+      if (act) {
+        F A3, IZ3;
+        A3 = vz1(pl(kk + 3), Z2, Zn, IZ3);
+        const F Q3 = qvisc(c2, Z2.rho, A3 - A[2]);
+        vzk = Z1.vz;
+        e_cur = Z1.q;
         Z1 = Z2;
+        Z2.rho = vmove(Zn.rho);
+        Z2.q = vmove(Zn.q);
+        Z2.pot = vmove(Zn.pot);
+        Z2.vz = vmove(Zn.vz);
+        Z2.vx = vmove(Zn.vx);
+        Z2.vxp = sph ? vmove(Zn.vxp) : F(0);
         A[0] = A[1];
         A[1] = A[2];
-        A[2] = A[3];
+        A[2] = A3;
         IZ[0] = IZ[1];
         IZ[1] = IZ[2];
-        IZ[2] = IZ[3];
+        IZ[2] = IZ3;
         Q[0] = Q[1];
         Q[1] = Q[2];
+        Q[2] = Q3;
+        // unconditional (plane kk+4 <= kn+2 is at worst a ghost plane), so
+        // that the load writes the window register itself
+        loadz(pl(kk + 4), Zn);
       }
+      if (kk + 3 < kn) load_halo(kk + 3, hn);
     }
-    (void)Rm1;
-    buf ^= 1;
+    __syncthreads();
+    sb = sb1;
+    rb = rb1;
   }
 }
 
