@@ -30,6 +30,13 @@ struct GeoTables {
   const double *inv_dxlen, *inv_hy, *inv_Ly, *inv_ymin, *inv_ymed, *cotz, *inv_dzmed, *inv_dz;
 };
 
+// The tables do not change while kernels run.  Device code reads them
+// through the constant address space: with a wave-uniform index that is a
+// scalar load, which neither waits behind nor holds up the vector memory
+// counter of the field loads and stores around it.
+using cdouble = const __attribute__((address_space(4))) double;
+__device__ inline double gk(const double *p, size_t i) { return ((cdouble *)p)[i]; }
+
 struct Mesh {
   int nx, ny, nz, pitch, nyg, nzg, j0, jn, k0, kn, d3;
   int geo, eos, fargo, v0_mean, visc;
@@ -60,23 +67,23 @@ struct Mesh {
   __device__ inline int kabove(int k) const { return (zper() && k == kn - 1) ? k0 : k + 1; }
 
   // Tab. "geom" products (Eqs. 70, 71); face areas are of the lower face.
-  __device__ inline double Sx(int j, int k) const { return g.sxj[j] * g.sxk[k]; }
-  __device__ inline double Sy(int j, int k) const { return g.syj[j] * g.syk[k]; }
-  __device__ inline double Sz(int j, int k) const { return g.szj[j] * g.szk[k]; }
-  __device__ inline double Vinv(int j, int k) const { return g.invVj[j] / g.syk[k]; }
-  __device__ inline double Vol(int j, int k) const { return g.syk[k] / g.invVj[j]; }
-  __device__ inline double DX(int j, int k) const { return g.dxlen[(size_t)k * nyg + j]; }
+  __device__ inline double Sx(int j, int k) const { return gk(g.sxj, j) * gk(g.sxk, k); }
+  __device__ inline double Sy(int j, int k) const { return gk(g.syj, j) * gk(g.syk, k); }
+  __device__ inline double Sz(int j, int k) const { return gk(g.szj, j) * gk(g.szk, k); }
+  __device__ inline double Vinv(int j, int k) const { return gk(g.invVj, j) / gk(g.syk, k); }
+  __device__ inline double Vol(int j, int k) const { return gk(g.syk, k) / gk(g.invVj, j); }
+  __device__ inline double DX(int j, int k) const { return gk(g.dxlen, (size_t)k * nyg + j); }
   __device__ inline double Lz(int j, int k) const {
-    double d = g.zmin[k + 1] - g.zmin[k];
-    return geo == FARGO_SPHERICAL ? d * g.ymed[j] : d;
+    double d = gk(g.zmin, k + 1) - gk(g.zmin, k);
+    return geo == FARGO_SPHERICAL ? d * gk(g.ymed, j) : d;
   }
   __device__ inline double hz(int j, int k) const {
-    double d = g.zmed[k] - g.zmed[k - 1];
-    return geo == FARGO_SPHERICAL ? d * g.ymed[j] : d;
+    double d = gk(g.zmed, k) - gk(g.zmed, k - 1);
+    return geo == FARGO_SPHERICAL ? d * gk(g.ymed, j) : d;
   }
   // distance of a v_phi face centre to the rotation axis
   __device__ inline double Rcyl(int j, int k) const {
-    return geo == FARGO_SPHERICAL ? g.ymed[j] * g.sinz[k] : g.ymed[j];
+    return geo == FARGO_SPHERICAL ? gk(g.ymed, j) * gk(g.sinz, k) : gk(g.ymed, j);
   }
   // X-momentum factor of Tab. "momenta": Pi_x = rho * mx(v); evaluated in
   // the precision F of the field (geometric factors rounded to F)
@@ -93,7 +100,7 @@ struct Mesh {
     return m / R - R * (F)omega;
   }
   template <typename F>
-  __device__ inline F mz(int j, F v) const { return geo == FARGO_SPHERICAL ? (F)g.ymed[j] * v : v; }
+  __device__ inline F mz(int j, F v) const { return geo == FARGO_SPHERICAL ? (F)gk(g.ymed, j) * v : v; }
 };
 
 __device__ inline int imod(int i, int n) {

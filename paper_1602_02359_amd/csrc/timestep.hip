@@ -74,11 +74,35 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
   const int r = kk * m.ny + jj; // ring index (k - k0) * ny + (j - j0)
   const int tid = threadIdx.x, B = blockDim.x, n = m.nx;
   const unsigned base = m.o32(0, j, k);
+  const bool shear_on = with_cfl && m.fargo && m.shear_c0 > 0.0 && j + 1 < m.jn;
+  const unsigned py = (unsigned)m.pitch, pz = (unsigned)m.plane();
+  // Every load of the ring is issued before the first use (indices clamped
+  // to the ring, so no load sits behind a branch), which keeps all of them
+  // in flight together.
+  const R *qf = m.eos == FARGO_ISOTHERMAL ? s.cs : s.e;
+  R fx[M], fr[M] = {}, fq[M] = {}, fy0[M] = {}, fy1[M] = {}, fz0[M] = {}, fz1[M] = {}, fn[M] = {}, fs[M] = {};
+#pragma unroll
+  for (int mm = 0; mm < M; mm++) {
+    const unsigned c = base + (unsigned)min(tid + B * mm, n - 1);
+    fx[mm] = s.vx[c];
+    if (with_cfl) {
+      fr[mm] = s.rho[c];
+      fq[mm] = qf[c];
+      fy0[mm] = s.vy[c];
+      fy1[mm] = s.vy[c + py];
+      if (m.d3) {
+        fz0[mm] = s.vz[c];
+        fz1[mm] = s.vz[c + pz];
+      }
+      if (m.visc) fn[mm] = s.nu[c];
+      if (shear_on) fs[mm] = s.vx[c + py];
+    }
+  }
   double vx[M];
 #pragma unroll
   for (int mm = 0; mm < M; mm++) {
     int i = tid + B * mm;
-    vx[mm] = i < n ? (double)s.vx[base + i] : 0.0;
+    vx[mm] = i < n ? (double)fx[mm] : 0.0;
     if (i < n) V[i] = vx[mm];
   }
   const double vb_ring = ring_bulk<M>(m, vx, tid, red);
@@ -89,14 +113,13 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
   // Eq. cfl2 through the inverse steps (rates u / Delta): the minimum step of
   // a cell over directions is its maximum rate, and the smallest step is
   // 1 / sqrt of the largest sum of squared rates (taken in k_dt_final)
-  const double Lx = m.DX(j, k), Lyy = m.g.Ly[j];
+  const double Lx = m.DX(j, k), Lyy = gk(m.g.Ly, j);
   const double Lzz = m.d3 ? m.Lz(j, k) : 0.0;
   const double iLx = 1.0 / Lx, iLy = 1.0 / Lyy, iLz = m.d3 ? 1.0 / Lzz : 0.0;
   double Lmin = fmin(Lx, Lyy);
   if (m.d3) Lmin = fmin(Lmin, Lzz);
   const double iL2 = 1.0 / (Lmin * Lmin);
   const double k3 = 4.0 * m.cvnr * m.cvnr;
-  const bool shear_on = m.fargo && m.shear_c0 > 0.0 && j + 1 < m.jn;
   const double dXp = shear_on ? m.DX(j + 1, k) : 1.0;
   double rmax = 0.0, smax = 0.0;
   int bad = 0;
@@ -104,13 +127,12 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
   for (int mm = 0; mm < M; mm++) {
     int i = tid + B * mm;
     if (i >= n) continue;
-    unsigned c = base + i;
     double vxc = vx[mm], vxp = V[i + 1 == n ? 0 : i + 1];
-    double rho = (double)s.rho[c];
+    double rho = (double)fr[mm];
     double cw2; // squared wave speed
-    if (m.eos == FARGO_ISOTHERMAL) cw2 = (double)s.cs[c] * (double)s.cs[c];
-    else cw2 = m.gamma * ((m.gamma - 1.0) * (double)s.e[c]) / rho;
-    double vyc = (double)s.vy[c], vyp = (double)s.vy[c + m.pitch];
+    if (m.eos == FARGO_ISOTHERMAL) cw2 = (double)fq[mm] * (double)fq[mm];
+    else cw2 = m.gamma * ((m.gamma - 1.0) * (double)fq[mm]) / rho;
+    double vyc = (double)fy0[mm], vyp = (double)fy1[mm];
     bad |= !(rho > 0.0) || !isfinite(rho) || !isfinite(cw2) || !isfinite(vxc) || !isfinite(vyc);
     // item 1: sound waves (squared rate); item 2: fluid motion; item 3:
     // artificial viscosity on compressed directions
@@ -123,7 +145,7 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
     if (dvx < 0.0) r3 = fmax(r3, k3 * fabs(dvx) * iLx);
     if (dvy < 0.0) r3 = fmax(r3, k3 * fabs(dvy) * iLy);
     if (m.d3) {
-      double vzc = (double)s.vz[c], vzp = (double)s.vz[c + (unsigned)m.plane()];
+      double vzc = (double)fz0[mm], vzp = (double)fz1[mm];
       bad |= !isfinite(vzc);
       double uz = fmax(fabs(vzc), fabs(vzp));
       r2 = fmax(r2, uz * iLz);
@@ -133,13 +155,13 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
     double rate2 = r1s + r2 * r2 + r3 * r3;
     if (m.visc) {
       // item 4: viscosity, 4 nu / Delta^2
-      double r4 = 4.0 * (double)s.nu[c] * iL2;
+      double r4 = 4.0 * (double)fn[mm] * iL2;
       rate2 += r4 * r4;
     }
     if (!(rate2 >= 0.0)) bad = 1;
     else rmax = rate2 > rmax ? rate2 : rmax;
     if (shear_on) {
-      double sh = fabs(vxc / Lx - (double)s.vx[c + m.pitch] / dXp);
+      double sh = fabs(vxc / Lx - (double)fs[mm] / dXp);
       if (sh > smax) smax = sh;
     }
   }
@@ -227,11 +249,16 @@ template <typename R>
 void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringrate,
                 double *ringshear, int *err) {
   prof_begin(L, K_CFL);
-  int M = (m.nx + 255) / 256;
-  if (M <= 1) cfl_launch<1, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err);
-  else if (M == 2) cfl_launch<2, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err);
-  else if (M <= 4) cfl_launch<4, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err);
-  else cfl_launch<8, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err);
+  switch ((m.nx + 255) / 256) { // zones per thread; nx <= 2048
+  case 1: cfl_launch<1, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+  case 2: cfl_launch<2, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+  case 3: cfl_launch<3, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+  case 4: cfl_launch<4, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+  case 5: cfl_launch<5, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+  case 6: cfl_launch<6, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+  case 7: cfl_launch<7, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+  default: cfl_launch<8, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+  }
   prof_end(L, K_CFL);
 }
 

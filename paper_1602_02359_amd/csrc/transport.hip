@@ -64,7 +64,7 @@ struct Zone {
 template <typename F, int NQ, bool CT, class RW, class RAW, class DER, class TOF, class GEO, class ST>
 __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const DER &derive, const TOF &Tof,
                                     const GEO &geo, const ST &st) {
-  constexpr bool PF = sizeof(F) == 4;
+  constexpr bool PF = true;
   Zone<F, NQ, CT> zm, z0, zp;
   RW rn;
   raw(a0 - 2, rn);
@@ -179,8 +179,8 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
   struct Geo {
     const Mesh &m;
     int k;
-    __device__ F L(int a) const { return (F)m.g.Ly[a]; }
-    __device__ F h(int f) const { return (F)m.g.hy[f]; }
+    __device__ F L(int a) const { return (F)gk(m.g.Ly, a); }
+    __device__ F h(int f) const { return (F)gk(m.g.hy, f); }
     __device__ F S(int f) const { return (F)m.Sy(f, k); }
     __device__ F Vi(int a) const { return (F)m.Vinv(a, k); }
   } geo{m, k};
@@ -565,15 +565,26 @@ __global__ __launch_bounds__(256) void k_vel(Mesh m, StateT<F> s, TSetT<F> T) {
   if (i >= m.nx) return;
   int j = m.j0 + jj, k = m.k0 + kk;
   unsigned c = m.o32(i, j, k);
-  F rc = s.rho[c];
-  if (j >= m.ylo()) {
-    unsigned cm = m.o32(i, m.jbelow(j), k);
-    s.vy[c] = (T.a[T_PYP][cm] + T.a[T_PYM][c]) / (s.rho[cm] + rc);
+  const bool dy = j >= m.ylo(), dz = m.d3 && k >= m.zlo();
+  // all loads first: the stores below may alias them as far as the compiler
+  // knows, and would otherwise hold the Z loads back behind the Y store
+  F rc = s.rho[c], ry = F(0), py = F(0), my = F(0), rz = F(0), pz = F(0), mz = F(0);
+  if (dy) {
+    const unsigned cm = m.o32(i, m.jbelow(j), k);
+    ry = s.rho[cm];
+    py = T.a[T_PYP][cm];
+    my = T.a[T_PYM][c];
   }
-  if (m.d3 && k >= m.zlo()) {
-    unsigned cm = m.o32(i, j, m.kbelow(k));
-    F v = (T.a[T_PZP][cm] + T.a[T_PZM][c]) / (s.rho[cm] + rc);
-    s.vz[c] = m.geo == FARGO_SPHERICAL ? v / (F)m.g.ymed[j] : v;
+  if (dz) {
+    const unsigned cm = m.o32(i, j, m.kbelow(k));
+    rz = s.rho[cm];
+    pz = T.a[T_PZP][cm];
+    mz = T.a[T_PZM][c];
+  }
+  if (dy) s.vy[c] = (py + my) / (ry + rc);
+  if (dz) {
+    F v = (pz + mz) / (rz + rc);
+    s.vz[c] = m.geo == FARGO_SPHERICAL ? v / (F)gk(m.g.ymed, j) : v;
   }
 }
 
