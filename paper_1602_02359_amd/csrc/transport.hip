@@ -58,13 +58,11 @@ struct Zone {
 // lower-face velocity, `Tof(a, const Zone&, q)` gives the conserved Q of zone
 // a (carried in the window when CT, else formed again); `geo` gives L(a) (zone width), h(f)
 // (centre distance at face f), S(f), Vi(a); `st(a, rho, T[])` stores the
-// updated zone.  With FP32 fields the loads of zone f + 2 are issued while zone f is
-// being computed; with FP64 fields the registers that would take are worth
-// more as occupancy, and zone f + 1 is loaded at the start of step f.
+// updated zone.  The loads of zone f + 2 are issued while zone f is being
+// computed.
 template <typename F, int NQ, bool CT, class RW, class RAW, class DER, class TOF, class GEO, class ST>
 __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const DER &derive, const TOF &Tof,
                                     const GEO &geo, const ST &st) {
-  constexpr bool PF = true;
   Zone<F, NQ, CT> zm, z0, zp;
   RW rn;
   raw(a0 - 2, rn);
@@ -73,7 +71,7 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
   derive(a0 - 1, rn, zm);
   raw(a0, rn);
   derive(a0, rn, z0);
-  if (PF) raw(a0 + 1, rn);
+  raw(a0 + 1, rn);
   F sm[NQ + 1], s0[NQ + 1];
   {
     F hm = geo.h(a0 - 1), hp = geo.h(a0);
@@ -87,9 +85,8 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
   F Lm = geo.L(a0 - 1);
 #pragma unroll 1
   for (int f = a0; f <= a1; f++) {
-    if (!PF) raw(f + 1, rn);
     derive(f + 1, rn, zp);
-    if (PF && f + 2 <= a1 + 1) raw(f + 2, rn);
+    if (f + 2 <= a1 + 1) raw(f + 2, rn);
     F hm = geo.h(f), hp = geo.h(f + 1);
     s0[NQ] = vl_slope(zm.rho, z0.rho, zp.rho, hm, hp);
 #pragma unroll
@@ -280,10 +277,26 @@ struct RingShape<float> {
   static constexpr int M = 4, HLL = 2, HRL = 2;
 };
 
+// Neighbour lanes through DPP whole-wave shifts by one lane (wave_shr:1,
+// wave_shl:1): a VALU move, with no trip through the LDS crossbar.  The lane
+// at the end of the wave keeps its own value.
+template <int CTRL>
+__device__ inline int dpp_lane(int x) { return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xf, 0xf, false); }
+template <int CTRL, typename F>
+__device__ inline F dpp_move(F x) {
+  if constexpr (sizeof(F) == 8) {
+    const long long v = __double_as_longlong(x);
+    const int lo = dpp_lane<CTRL>((int)v), hi = dpp_lane<CTRL>((int)(v >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+  } else {
+    return __int_as_float(dpp_lane<CTRL>(__float_as_int(x)));
+  }
+}
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
 template <typename F>
-__device__ inline F from_prev_lane(F x) { return __shfl_up(x, 1, WAVE); }
+__device__ inline F from_prev_lane(F x) { return dpp_move<DPP_WAVE_SHR1>(x); }
 template <typename F>
-__device__ inline F from_next_lane(F x) { return __shfl_down(x, 1, WAVE); }
+__device__ inline F from_next_lane(F x) { return dpp_move<DPP_WAVE_SHL1>(x); }
 
 // a[] of the lane's M zones and its two neighbours on each side
 template <typename F, int M>
