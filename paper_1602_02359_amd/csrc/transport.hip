@@ -331,21 +331,24 @@ __device__ inline void prev_of(const F (&a)[M], F (&out)[M]) { // value of zone 
 // l, r (flat at an extremum, steepened away from an overshoot), then the
 // interface value supplied by the zone, the mean of the parabola over the
 // fraction |xi| next to its right edge (xi >= 0) or left edge (xi < 0).
+// The fraction enters through the ring constants X: x = |xi|, x (1 - x) and
+// the sign of xi, which are the same for every zone of the ring.
 template <typename F>
-__device__ inline F ppa_eval(F qm, F q0, F qp, F l, F r, F xi) {
+struct PpaX {
+  F x, x1x;
+  bool right; // xi >= 0
+};
+template <typename F>
+__device__ inline F ppa_eval(F qm, F q0, F qp, F l, F r, const PpaX<F> &X) {
   const F sixth = F(1) / F(6);
-  F D = r - l, C = q0 - F(0.5) * (l + r);
-  if ((qp - q0) * (q0 - qm) <= F(0)) {
-    l = q0;
-    r = q0;
-  } else if (D * C > D * D * sixth) {
-    l = F(3) * q0 - F(2) * r;
-  } else if (-D * D * sixth > D * C) {
-    r = F(3) * q0 - F(2) * l;
-  }
-  F x = fabs(xi);
-  if (xi >= F(0)) return r + x * (q0 - r) + x * (F(1) - x) * (F(2) * q0 - r - l);
-  return l + x * (q0 - l) + x * (F(1) - x) * (F(2) * q0 - r - l);
+  const F D = r - l, C = q0 - F(0.5) * (l + r);
+  const F DC = D * C, DD6 = D * D * sixth;
+  const bool flat = (qp - q0) * (q0 - qm) <= F(0);
+  const bool stl = !flat && DC > DD6, str = !flat && !stl && -DD6 > DC;
+  const F ln = flat ? q0 : (stl ? F(3) * q0 - F(2) * r : l);
+  const F rn = flat ? q0 : (str ? F(3) * q0 - F(2) * l : r);
+  const F ed = X.right ? rn : ln;
+  return ed + X.x * (q0 - ed) + X.x1x * (F(2) * q0 - rn - ln);
 }
 
 // Interface values on the lane's zones; each zone's slope and each face's
@@ -355,8 +358,24 @@ __device__ inline F ppa_eval(F qm, F q0, F qp, F l, F r, F xi) {
 //   (harmonic mean of the two one-sided differences, zero unless they have
 //   the same sign), and the half-step value at each zone's lower face
 //   upwinded on w, with cw = w dt / dX (Eq. 15).
+//   The upwind factors depend on the face velocity only and are formed once
+//   for all quantities: (1 - cw)/2 and (1 + cw)/2 (the halving is exact).
 template <typename F, int M>
-__device__ inline void vlx_faces(const Span<F, M> &Q, const F (&w)[M], F cdt, F (&out)[M]) {
+struct Upwind {
+  bool pos[M]; // w >= 0
+  F cl[M], cr[M];
+  __device__ inline void set(const F (&w)[M], F cdt) {
+#pragma unroll
+    for (int q = 0; q < M; q++) {
+      const F cw = w[q] * cdt;
+      pos[q] = w[q] >= F(0);
+      cl[q] = (F(1) - cw) * F(0.5);
+      cr[q] = (F(1) + cw) * F(0.5);
+    }
+  }
+};
+template <typename F, int M>
+__device__ inline void vlx_faces(const Span<F, M> &Q, const Upwind<F, M> &U, F (&out)[M]) {
   F a[M], ap[M];
 #pragma unroll
   for (int q = 0; q < M; q++) {
@@ -365,15 +384,12 @@ __device__ inline void vlx_faces(const Span<F, M> &Q, const F (&w)[M], F cdt, F 
   }
   prev_of(a, ap);
 #pragma unroll
-  for (int q = 0; q < M; q++) {
-    const F cw = w[q] * cdt;
-    out[q] = w[q] >= F(0) ? Q(q - 1) + ap[q] * (F(1) - cw) * F(0.5) : Q(q) - a[q] * (F(1) + cw) * F(0.5);
-  }
+  for (int q = 0; q < M; q++) out[q] = U.pos[q] ? Q(q - 1) + ap[q] * U.cl[q] : Q(q) - a[q] * U.cr[q];
 }
 //   ppa_values: monotonised central slopes, the edge value of each face
 //   (Eq. 34) and the interface value supplied by each zone.
 template <typename F, int M>
-__device__ inline void ppa_values(const Span<F, M> &Q, F xi, F (&out)[M]) {
+__device__ inline void ppa_values(const Span<F, M> &Q, const PpaX<F> &X, F (&out)[M]) {
   const F sixth = F(1) / F(6);
   F d[M], dp[M], l[M], r[M];
 #pragma unroll
@@ -383,11 +399,11 @@ __device__ inline void ppa_values(const Span<F, M> &Q, F xi, F (&out)[M]) {
   for (int q = 0; q < M; q++) l[q] = Q(q - 1) + F(0.5) * (Q(q) - Q(q - 1)) - (d[q] - dp[q]) * sixth;
   next_of(l, r);
 #pragma unroll
-  for (int q = 0; q < M; q++) out[q] = ppa_eval(Q(q - 1), Q(q), Q(q + 1), l[q], r[q], xi);
+  for (int q = 0; q < M; q++) out[q] = ppa_eval(Q(q - 1), Q(q), Q(q + 1), l[q], r[q], X);
 }
 
-template <typename F>
-__global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__ vx2, TSetT<F> T, TSetT<F> Tout,
+template <typename F, int NQ>
+__global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__ vx2, TSetT<F> T, TSetT<F> Tout,
                                                 StateT<F> s, const double *__restrict__ v0,
                                                 const int32_t *__restrict__ Nsh, const double *__restrict__ xis,
                                                 const double *__restrict__ dtp, int nseg) {
@@ -395,7 +411,9 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
   constexpr int U = (WAVE - HLL - HRL) * M; // output zones per wave
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x & (WAVE - 1);
-  const long gw = (long)blk * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
+  // wave-uniform (readfirstlane), so that the ring's constants come through
+  // scalar loads
+  const long gw = (long)blk * (blockDim.x / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
   if (gw >= (long)m.nring * nseg) return;
   const int r = (int)(gw / nseg), seg = (int)(gw % nseg);
   const int n = m.nx;
@@ -409,6 +427,7 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
   const int Nm = ((N % n) + n) % n; // shift on store: zone i goes to (i + Nm) mod n
   const double xid = fg ? xis[r] : 0.0;
   const F xi = (F)xid;
+  const PpaX<F> X{fabs(xi), fabs(xi) * (F(1) - fabs(xi)), xi >= F(0)};
   const F cdt = (F)(dtd / dXd), pfac = (F)(xid * dXd * Sd);
   // the lane's zones and their ring indices
   const int a0 = seg * U;                  // first output zone of the segment
@@ -453,12 +472,20 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
   };
   auto useful = [&](int q) { return lane >= HLL && lane < WAVE - HRL && zl + q < aend; };
 
+  // Every load of the window is issued here, so that all of them are in
+  // flight together: the other quantities in the order they are processed,
+  // Pi-_y, Pi+_y [, Pi-_z, Pi+_z] [, e], then Pi-_x and Pi+_x, which 12d
+  // needs (T.q holds Pi-_x, Pi+_x first).
+  constexpr auto qorder = [](int t) { return t + 2 < NQ ? t + 2 : t + 2 - NQ; };
+  F w[M], ri0[M], Fl[M], ri1[M], El[M], rf[M], Qall[NQ][M];
+  Span<F, M> R;
+  load(T.a[T_RHO], R.a);
+  load(vx2, w);
+#pragma unroll
+  for (int t = 0; t < NQ; t++) load(T.q[qorder(t)], Qall[t]);
   // ---- density: van Leer residual sweep, then the PPA residual
-  F w[M], ri0[M], Fl[M], ri1[M], El[M], rf[M];
+  Upwind<F, M> Uw;
   {
-    Span<F, M> R;
-    load(T.a[T_RHO], R.a);
-    load(vx2, w);
 #pragma unroll
     for (int q = 0; q < M; q++) {
       w[q] -= vb;
@@ -466,7 +493,8 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
     }
     R.edges();
     F st[M];
-    vlx_faces(R, w, cdt, st);
+    Uw.set(w, cdt);
+    vlx_faces(R, Uw, st);
 #pragma unroll
     for (int q = 0; q < M; q++) Fl[q] = w[q] * st[q] * S * dt;
     F Fh[M];
@@ -481,7 +509,7 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
     if (fg) {
       R1.edges();
       F val[M];
-      ppa_values(R1, xi, val);
+      ppa_values(R1, X, val);
 #pragma unroll
       for (int q = 0; q < M; q++) val[q] = pfac * val[q];
       // El: PPA mass flux through the zone's lower face (supplied by the
@@ -497,24 +525,20 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
       for (int q = 0; q < M; q++) rf[q] = R1.a[q] - vinv * (Eh[q] - El[q]);
     }
   }
-  // ---- the other quantities: Pi-_y, Pi+_y [, Pi-_z, Pi+_z] [, e], then
-  // Pi-_x and Pi+_x, which 12d needs (T.q holds Pi-_x, Pi+_x first)
-  F pxm[M], pxp[M], Qn[M];
-  const int nq = T.nq;
-  auto qorder = [&](int t) { return t + 2 < nq ? t + 2 : t + 2 - nq; };
-  load(T.q[qorder(0)], Qn);
-  for (int t = 0; t < nq; t++) {
+  // ---- the other quantities
+  F pxm[M], pxp[M];
+#pragma unroll
+  for (int t = 0; t < NQ; t++) {
     const int qi = qorder(t);
     Span<F, M> Qs;
     F Qv[M];
 #pragma unroll
-    for (int q = 0; q < M; q++) Qv[q] = Qn[q];
-    if (t + 1 < nq) load(T.q[qorder(t + 1)], Qn);
+    for (int q = 0; q < M; q++) Qv[q] = Qall[t][q];
 #pragma unroll
     for (int q = 0; q < M; q++) Qs.a[q] = Qv[q] * ri0[q];
     Qs.edges();
     F G[M], Gh[M];
-    vlx_faces(Qs, w, cdt, G);
+    vlx_faces(Qs, Uw, G);
 #pragma unroll
     for (int q = 0; q < M; q++) G[q] = G[q] * Fl[q];
     next_of(G, Gh);
@@ -525,7 +549,7 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
       for (int q = 0; q < M; q++) Qs.a[q] = Qv[q] * ri1[q];
       Qs.edges();
       F st[M], Hl[M], Hh[M];
-      ppa_values(Qs, xi, st);
+      ppa_values(Qs, X, st);
       if (xi >= F(0)) {
         prev_of(st, Hl);
 #pragma unroll
@@ -545,7 +569,7 @@ __global__ __launch_bounds__(256, 4) void k_ring_x(Mesh m, const F *__restrict__
 #pragma unroll
       for (int q = 0; q < M; q++) pxp[q] = Qv[q];
     } else {
-      F *dst = (T.a[T_E] && qi == T.nq - 1) ? s.e : Tout.q[qi];
+      F *dst = (T.a[T_E] && qi == NQ - 1) ? s.e : Tout.q[qi];
 #pragma unroll
       for (int q = 0; q < M; q++)
         if (useful(q)) dst[out_at(q)] = Qv[q];
@@ -654,7 +678,12 @@ void launch_ring_x(Launch &L, const Mesh &m, const F *vx2, const TSetT<F> &T, co
   const long waves = (long)m.nring * nseg;
   const unsigned nb = (unsigned)((waves + 3) / 4);
   prof_begin(L, K_RING_X);
-  k_ring_x<F><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg);
+  switch (T.nq) { // Pi-+_x, Pi-+_y [, Pi-+_z] [, e]
+  case 4: k_ring_x<F, 4><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg); break;
+  case 5: k_ring_x<F, 5><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg); break;
+  case 6: k_ring_x<F, 6><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg); break;
+  default: k_ring_x<F, 7><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg); break;
+  }
   prof_end(L, K_RING_X);
 }
 
