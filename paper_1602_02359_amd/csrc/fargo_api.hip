@@ -242,10 +242,10 @@ void make_geo(const fargo_params *p, HostGeo &G) {
   }
 }
 
+// the block of GeoTables: GJ_N row tables of nyg + 1 entries, GK_N plane
+// tables of nzg + 1 entries, dxlen and its reciprocal (nzg * nyg each)
 size_t geo_doubles(int nyg, int nzg) {
-  return (size_t)(nyg + 1) + nyg + (nzg + 1) + nzg + nzg + nyg + nyg + nyg + (nyg + 1) + nyg + nyg + nzg + nzg +
-         (nzg + 1) + (size_t)nzg * nyg +
-         (size_t)nzg * nyg + nyg + nyg + (nyg + 1) + nyg + (nzg + 1) + nzg + nzg;
+  return (size_t)GJ_N * (nyg + 1) + (size_t)GK_N * (nzg + 1) + 2 * (size_t)nzg * nyg;
 }
 
 struct Layout {
@@ -408,16 +408,24 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   // geometry
   HostGeo G;
   make_geo(&c->p, G);
+  // one block in the order of GeoRow, GeoPlane, then dxlen, 1/dxlen; each
+  // row (plane) table padded to nyg + 1 (nzg + 1) entries
   std::vector<double> buf;
   buf.reserve(geo_doubles(nyg, nzg));
-  std::vector<size_t> off;
-  for (const std::vector<double> *v : {&G.ymin, &G.ymed, &G.zmin, &G.zmed, &G.sinz, &G.Ly, &G.hy, &G.sxj, &G.syj,
-                                       &G.szj, &G.invVj, &G.sxk, &G.syk, &G.szk, &G.dxlen, &G.inv_dxlen,
-                                       &G.inv_hy, &G.inv_Ly, &G.inv_ymin, &G.inv_ymed, &G.cotz, &G.inv_dzmed,
-                                       &G.inv_dz}) {
-    off.push_back(buf.size());
+  const std::vector<double> *rows[GJ_N] = {&G.ymin, &G.ymed,  &G.Ly,     &G.hy,     &G.sxj,      &G.syj,
+                                          &G.szj,  &G.invVj, &G.inv_hy, &G.inv_Ly, &G.inv_ymin, &G.inv_ymed};
+  const std::vector<double> *planes[GK_N] = {&G.zmin, &G.zmed, &G.sinz, &G.sxk,      &G.syk,
+                                            &G.szk,  &G.cotz, &G.inv_dzmed, &G.inv_dz};
+  for (const std::vector<double> *v : rows) {
     buf.insert(buf.end(), v->begin(), v->end());
+    buf.resize(buf.size() + (nyg + 1) - v->size(), 0.0);
   }
+  for (const std::vector<double> *v : planes) {
+    buf.insert(buf.end(), v->begin(), v->end());
+    buf.resize(buf.size() + (nzg + 1) - v->size(), 0.0);
+  }
+  buf.insert(buf.end(), G.dxlen.begin(), G.dxlen.end());
+  buf.insert(buf.end(), G.inv_dxlen.begin(), G.inv_dxlen.end());
   double *gd = (double *)(base + Lo.geo);
   if (buf.size() != geo_doubles(nyg, nzg)) { // the workspace slot is sized by geo_doubles
     fargo_destroy(c);
@@ -453,11 +461,10 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   m.courant = params->courant;
   m.cvnr = params->cvnr;
   m.shear_c0 = params->shear_c0;
-  const double **tbl[] = {&m.g.ymin, &m.g.ymed, &m.g.zmin, &m.g.zmed, &m.g.sinz, &m.g.Ly, &m.g.hy, &m.g.sxj,
-                          &m.g.syj, &m.g.szj, &m.g.invVj, &m.g.sxk, &m.g.syk, &m.g.szk, &m.g.dxlen,
-                          &m.g.inv_dxlen, &m.g.inv_hy, &m.g.inv_Ly, &m.g.inv_ymin, &m.g.inv_ymed, &m.g.cotz,
-                          &m.g.inv_dzmed, &m.g.inv_dz};
-  for (size_t t = 0; t < off.size(); t++) *tbl[t] = gd + off[t];
+  m.g.base = gd;
+  m.g.sj = nyg + 1;
+  m.g.sk = nzg + 1;
+  m.g.n2 = nzg * nyg;
   // words and per-ring arrays
   char *wd = base + Lo.words;
   c->w.dt = (double *)wd;

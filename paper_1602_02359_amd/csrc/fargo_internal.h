@@ -17,25 +17,80 @@ constexpr int WAVE = 64;
 
 enum { T_RHO = 0, T_PXM, T_PXP, T_PYM, T_PYP, T_PZM, T_PZP, T_E, T_MAX };
 
-// Device-resident geometric tables (FP64), computed on the host at init from
-// Appendix A (Tab. "geom", Eqs. 70-71) and the face coordinates.
-struct GeoTables {
-  const double *ymin, *ymed, *zmin, *zmed, *sinz; // nyg+1, nyg, nzg+1, nzg, nzg
-  const double *Ly, *hy;                           // nyg: zone width, centre distance at face j
-  const double *sxj, *syj, *szj, *invVj;           // nyg, nyg+1, nyg, nyg
-  const double *sxk, *syk, *szk;                   // nzg, nzg, nzg+1
-  const double *dxlen;                             // nzg*nyg: azimuthal zone length
-  // reciprocals (1/dxlen, 1/hy, 1/Ly, 1/ymin, 1/ymed), cot(zmin) (spherical),
-  // 1/(zmed[k] - zmed[k-1]) and 1/(zmin[k+1] - zmin[k])
-  const double *inv_dxlen, *inv_hy, *inv_Ly, *inv_ymin, *inv_ymed, *cotz, *inv_dzmed, *inv_dz;
-};
-
 // The tables do not change while kernels run.  Device code reads them
 // through the constant address space: with a wave-uniform index that is a
 // scalar load, which neither waits behind nor holds up the vector memory
 // counter of the field loads and stores around it.
 using cdouble = const __attribute__((address_space(4))) double;
 __device__ inline double gk(const double *p, size_t i) { return ((cdouble *)p)[i]; }
+
+// Device-resident geometric tables (FP64), computed on the host at init from
+// Appendix A (Tab. "geom", Eqs. 70-71) and the face coordinates, in one block:
+// the per-row tables (sj = nyg + 1 entries apart), the per-plane tables
+// (sk = nzg + 1 entries apart), then the two per-(plane, row) tables.  A
+// kernel holds one base address and three sizes in scalar registers instead
+// of a pointer per table.
+enum GeoRow {
+  GJ_YMIN,      // face radius (nyg + 1 entries)
+  GJ_YMED,      // zone centre
+  GJ_LY,        // zone width
+  GJ_HY,        // centre distance at face j
+  GJ_SXJ,       // Tab. "geom" factors (syj: nyg + 1 entries)
+  GJ_SYJ,
+  GJ_SZJ,
+  GJ_INVVJ,
+  GJ_INV_HY,    // reciprocals
+  GJ_INV_LY,
+  GJ_INV_YMIN,  // nyg + 1 entries
+  GJ_INV_YMED,
+  GJ_N
+};
+enum GeoPlane {
+  GK_ZMIN,      // face coordinate (nzg + 1 entries)
+  GK_ZMED,
+  GK_SINZ,      // sin(zmed)
+  GK_SXK,       // Tab. "geom" factors (szk: nzg + 1 entries)
+  GK_SYK,
+  GK_SZK,
+  GK_COTZ,      // cot(zmin) in spherical geometry (nzg + 1 entries)
+  GK_INV_DZMED, // 1 / (zmed[k] - zmed[k-1])
+  GK_INV_DZ,    // 1 / (zmin[k+1] - zmin[k])
+  GK_N
+};
+struct GeoTables {
+  const double *base;
+  int sj, sk, n2; // nyg + 1, nzg + 1, nzg * nyg
+
+  __device__ inline double tj(int t, int j) const { return gk(base, (size_t)t * sj + j); }
+  __device__ inline double tk(int t, int k) const { return gk(base, (size_t)GJ_N * sj + (size_t)t * sk + k); }
+  __device__ inline double t2(int t, size_t i) const {
+    return gk(base, (size_t)GJ_N * sj + (size_t)GK_N * sk + (size_t)t * n2 + i);
+  }
+  __device__ inline double ymin(int j) const { return tj(GJ_YMIN, j); }
+  __device__ inline double ymed(int j) const { return tj(GJ_YMED, j); }
+  __device__ inline double Ly(int j) const { return tj(GJ_LY, j); }
+  __device__ inline double hy(int j) const { return tj(GJ_HY, j); }
+  __device__ inline double sxj(int j) const { return tj(GJ_SXJ, j); }
+  __device__ inline double syj(int j) const { return tj(GJ_SYJ, j); }
+  __device__ inline double szj(int j) const { return tj(GJ_SZJ, j); }
+  __device__ inline double invVj(int j) const { return tj(GJ_INVVJ, j); }
+  __device__ inline double inv_hy(int j) const { return tj(GJ_INV_HY, j); }
+  __device__ inline double inv_Ly(int j) const { return tj(GJ_INV_LY, j); }
+  __device__ inline double inv_ymin(int j) const { return tj(GJ_INV_YMIN, j); }
+  __device__ inline double inv_ymed(int j) const { return tj(GJ_INV_YMED, j); }
+  __device__ inline double zmin(int k) const { return tk(GK_ZMIN, k); }
+  __device__ inline double zmed(int k) const { return tk(GK_ZMED, k); }
+  __device__ inline double sinz(int k) const { return tk(GK_SINZ, k); }
+  __device__ inline double sxk(int k) const { return tk(GK_SXK, k); }
+  __device__ inline double syk(int k) const { return tk(GK_SYK, k); }
+  __device__ inline double szk(int k) const { return tk(GK_SZK, k); }
+  __device__ inline double cotz(int k) const { return tk(GK_COTZ, k); }
+  __device__ inline double inv_dzmed(int k) const { return tk(GK_INV_DZMED, k); }
+  __device__ inline double inv_dz(int k) const { return tk(GK_INV_DZ, k); }
+  // azimuthal zone length and its reciprocal at index k * nyg + j
+  __device__ inline double dxlen(size_t i) const { return t2(0, i); }
+  __device__ inline double inv_dxlen(size_t i) const { return t2(1, i); }
+};
 
 struct Mesh {
   int nx, ny, nz, pitch, nyg, nzg, j0, jn, k0, kn, d3;
@@ -67,23 +122,23 @@ struct Mesh {
   __device__ inline int kabove(int k) const { return (zper() && k == kn - 1) ? k0 : k + 1; }
 
   // Tab. "geom" products (Eqs. 70, 71); face areas are of the lower face.
-  __device__ inline double Sx(int j, int k) const { return gk(g.sxj, j) * gk(g.sxk, k); }
-  __device__ inline double Sy(int j, int k) const { return gk(g.syj, j) * gk(g.syk, k); }
-  __device__ inline double Sz(int j, int k) const { return gk(g.szj, j) * gk(g.szk, k); }
-  __device__ inline double Vinv(int j, int k) const { return gk(g.invVj, j) / gk(g.syk, k); }
-  __device__ inline double Vol(int j, int k) const { return gk(g.syk, k) / gk(g.invVj, j); }
-  __device__ inline double DX(int j, int k) const { return gk(g.dxlen, (size_t)k * nyg + j); }
+  __device__ inline double Sx(int j, int k) const { return g.sxj(j) * g.sxk(k); }
+  __device__ inline double Sy(int j, int k) const { return g.syj(j) * g.syk(k); }
+  __device__ inline double Sz(int j, int k) const { return g.szj(j) * g.szk(k); }
+  __device__ inline double Vinv(int j, int k) const { return g.invVj(j) / g.syk(k); }
+  __device__ inline double Vol(int j, int k) const { return g.syk(k) / g.invVj(j); }
+  __device__ inline double DX(int j, int k) const { return g.dxlen((size_t)k * nyg + j); }
   __device__ inline double Lz(int j, int k) const {
-    double d = gk(g.zmin, k + 1) - gk(g.zmin, k);
-    return geo == FARGO_SPHERICAL ? d * gk(g.ymed, j) : d;
+    double d = g.zmin(k + 1) - g.zmin(k);
+    return geo == FARGO_SPHERICAL ? d * g.ymed(j) : d;
   }
   __device__ inline double hz(int j, int k) const {
-    double d = gk(g.zmed, k) - gk(g.zmed, k - 1);
-    return geo == FARGO_SPHERICAL ? d * gk(g.ymed, j) : d;
+    double d = g.zmed(k) - g.zmed(k - 1);
+    return geo == FARGO_SPHERICAL ? d * g.ymed(j) : d;
   }
   // distance of a v_phi face centre to the rotation axis
   __device__ inline double Rcyl(int j, int k) const {
-    return geo == FARGO_SPHERICAL ? gk(g.ymed, j) * gk(g.sinz, k) : gk(g.ymed, j);
+    return geo == FARGO_SPHERICAL ? g.ymed(j) * g.sinz(k) : g.ymed(j);
   }
   // X-momentum factor of Tab. "momenta": Pi_x = rho * mx(v); evaluated in
   // the precision F of the field (geometric factors rounded to F)
@@ -100,7 +155,7 @@ struct Mesh {
     return m / R - R * (F)omega;
   }
   template <typename F>
-  __device__ inline F mz(int j, F v) const { return geo == FARGO_SPHERICAL ? (F)gk(g.ymed, j) * v : v; }
+  __device__ inline F mz(int j, F v) const { return geo == FARGO_SPHERICAL ? (F)g.ymed(j) * v : v; }
 };
 
 __device__ inline int imod(int i, int n) {

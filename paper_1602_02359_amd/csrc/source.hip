@@ -25,6 +25,8 @@
 //
 // The field type F is double, or float for the FP32-bulk state; arithmetic is
 // carried out in F, geometric factors are rounded to F where they are used.
+#include <type_traits>
+
 #include "fargo_internal.h"
 
 namespace fargo {
@@ -80,7 +82,9 @@ struct Zv {
 // (F), and the zones (Z).  The march is software-pipelined over planes: one
 // barrier interval runs Z(k), F(k+1) and S(k+2) on separate buffers, so each
 // plane costs one barrier and the three phases overlap.
-template <typename F, bool D3>
+// The geometry and the equation of state are template parameters: fewer
+// run-time conditions leave more scalar registers for the march.
+template <typename F, bool D3, int GEO, bool ADI>
 __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
                                                   F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
                                                   F *__restrict__ e2, int nbx, int nby) {
@@ -94,8 +98,8 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
   const int w = min(TX, m.nx - i0), h = min(TY, m.jn - jt0);
   const bool act = r < h && c < w;
   const int i = i0 + c, j = jt0 + r;
-  const bool adi = m.eos == FARGO_ADIABATIC;
-  const bool sph = m.geo == FARGO_SPHERICAL, cyl = m.geo == FARGO_CYLINDRICAL;
+  constexpr bool adi = ADI;
+  constexpr bool sph = GEO == FARGO_SPHERICAL, cyl = GEO == FARGO_CYLINDRICAL;
   const F dt = (F)*dtp, c2 = (F)(m.cvnr * m.cvnr), om = (F)m.omega, gm1 = (F)(m.gamma - 1.0);
   const unsigned plane = (unsigned)m.plane();
 
@@ -130,15 +134,15 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
   auto vz1 = [&](int p, const Zv<F> &zb, const Zv<F> &z0, F &iz) {
     iz = F(0);
     if (!zowned(p)) return z0.vz;
-    const double ihzd = sph ? gk(m.g.inv_dzmed, p) * gk(m.g.inv_ymed, j) : gk(m.g.inv_dzmed, p);
+    const double ihzd = sph ? m.g.inv_dzmed(p) * m.g.inv_ymed(j) : m.g.inv_dzmed(p);
     iz = (F)ihzd / (z0.rho + zb.rho);
     F gradP = F(2) * (pres(z0.rho, z0.q) - pres(zb.rho, zb.q)) * iz;
     F gradPhi = (F)((z0.pot - zb.pot) * ihzd);
     F src = F(0);
     if (sph) {
-      F R0 = (F)(gk(m.g.ymed, j) * gk(m.g.sinz, p)), R1 = (F)(gk(m.g.ymed, j) * gk(m.g.sinz, m.kbelow(p)));
+      F R0 = (F)(m.g.ymed(j) * m.g.sinz(p)), R1 = (F)(m.g.ymed(j) * m.g.sinz(m.kbelow(p)));
       F vt = F(0.25) * ((z0.vx + R0 * om) + (z0.vxp + R0 * om) + (zb.vx + R1 * om) + (zb.vxp + R1 * om));
-      src = vt * vt * (F)gk(m.g.cotz, p) * (F)gk(m.g.inv_ymed, j);
+      src = vt * vt * (F)m.g.cotz(p) * (F)m.g.inv_ymed(j);
     }
     return z0.vz - dt * (gradP + gradPhi) + dt * src;
   };
@@ -196,7 +200,7 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
   // the window record z (vt = summed v_theta of the zone), halo from hv
   auto stage = [&](int kk, int sb, int rb, const Zv<F> &z, F vt, const Halo &hv) {
     F(*R)[SX] = L.R[rb];
-    if (c == 0 && r < h) L.DX[sb][r] = gk(m.g.inv_dxlen, (size_t)kk * m.nyg + jt0 + r);
+    if (c == 0 && r < h) L.DX[sb][r] = m.g.inv_dxlen((size_t)kk * m.nyg + jt0 + r);
     if (act) {
       R[r + 2][c + 2] = z.rho;
       L.P[sb][r + 2][c + 2] = pres(z.rho, z.q);
@@ -234,15 +238,15 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
         L.IY[sb][t][cc] = F(0);
         return;
       }
-      const double ihd = gk(m.g.inv_hy, f);
+      const double ihd = m.g.inv_hy(f);
       const F inv = (F)ihd / (R[t][sl] + R[t - 1][sl]);
       const F gradP = F(2) * (L.P[sb][t][sl] - L.P[sb][t - 1][sl]) * inv;
       const F gradPhi = (F)((L.Ph[sb][t][sl] - L.Ph[sb][t - 1][sl]) * ihd);
       F src = F(0);
       if (cyl || sph) {
         const int ya = yrow(t - 1);
-        const F Rt = (F)(sph ? gk(m.g.ymed, f) * gk(m.g.sinz, kk) : gk(m.g.ymed, f));
-        const F Ra = (F)(sph ? gk(m.g.ymed, ya) * gk(m.g.sinz, kk) : gk(m.g.ymed, ya));
+        const F Rt = (F)(sph ? m.g.ymed(f) * m.g.sinz(kk) : m.g.ymed(f));
+        const F Ra = (F)(sph ? m.g.ymed(ya) * m.g.sinz(kk) : m.g.ymed(ya));
         const F vt0 = (L.VX[sb][t][sl] + Rt * om) + (L.VX[sb][t][sl + 1] + Rt * om);
         const F vt1 = (L.VX[sb][t - 1][sl] + Ra * om) + (L.VX[sb][t - 1][sl + 1] + Ra * om);
         const F v = F(0.25) * (vt0 + vt1);
@@ -251,13 +255,13 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
           const F wv = F(0.25) * (L.VT[sb][t][cc] + L.VT[sb][t - 1][cc]);
           src += wv * wv;
         }
-        src *= (F)gk(m.g.inv_ymin, f);
+        src *= (F)m.g.inv_ymin(f);
       }
       L.AY[sb][t][cc] = L.VY[sb][t][cc] - dt * (gradP + gradPhi) + dt * src;
       L.IY[sb][t][cc] = inv;
     };
     if (act) {
-      xface(r, c + 2, gk(m.g.inv_dxlen, (size_t)kk * m.nyg + jt0 + r));
+      xface(r, c + 2, m.g.inv_dxlen((size_t)kk * m.nyg + jt0 + r));
       yface(r + 2, c);
     }
     if (r < 3) {
@@ -285,7 +289,7 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
     const F bx1 = a1 - dt * F(2) * (qx - qxm) * L.IX[sb][r][sl];
     const F bx2 = a2 - dt * F(2) * (qxp - qx) * L.IX[sb][r][sl + 1];
     vx2[o] = bx1;
-    F heat = qx * dvx * (F)gk(m.g.inv_dxlen, (size_t)kk * m.nyg + j);
+    F heat = qx * dvx * (F)m.g.inv_dxlen((size_t)kk * m.nyg + j);
     F flux = (F)m.Sx(j, kk) * (bx2 - bx1);
     // Y: faces t-1 .. t+2, zones t-1 .. t+1
     const F b0 = L.AY[sb][t - 1][c], b1 = L.AY[sb][t][c], b2 = L.AY[sb][t + 1][c], b3 = L.AY[sb][t + 2][c];
@@ -296,11 +300,11 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
     if (yowned(j)) by1 = b1 - dt * F(2) * (qy - qvisc(c2, s1, b1 - b0)) * L.IY[sb][t][c];
     if (yowned(yrow(t + 1))) by2 = b2 - dt * F(2) * (qvisc(c2, s3, b3 - b2) - qy) * L.IY[sb][t + 1][c];
     vy2[o] = by1;
-    heat += qy * dvy * (F)gk(m.g.inv_Ly, j);
+    heat += qy * dvy * (F)m.g.inv_Ly(j);
     flux += (F)m.Sy(j + 1, kk) * by2 - (F)m.Sy(j, kk) * by1;
     if (D3) {
       vz2[o] = zp.bz1;
-      const F iLz = sph ? (F)(gk(m.g.inv_dz, kk) * gk(m.g.inv_ymed, j)) : (F)gk(m.g.inv_dz, kk);
+      const F iLz = sph ? (F)(m.g.inv_dz(kk) * m.g.inv_ymed(j)) : (F)m.g.inv_dz(kk);
       heat += zp.qz * zp.dvz * iLz;
       flux += (F)m.Sz(j, kk + 1) * zp.bz2 - (F)m.Sz(j, kk) * zp.bz1;
     }
@@ -468,8 +472,21 @@ void launch_source(Launch &L, const Mesh &m, const StateT<F> &s, const double *d
   const unsigned nb = (unsigned)nbx * (unsigned)nby;
   const unsigned ng = (unsigned)(m.nzg * (m.nyg - m.ny) + (m.d3 ? (m.nzg - m.nz) * m.ny : 0));
   prof_begin(L, K_SRC);
-  if (m.d3) k_source<F, true><<<nb, NT, 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2, nbx, nby);
-  else k_source<F, false><<<nb, NT, 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2, nbx, nby);
+  auto go = [&](auto d3, auto geo, auto adi) {
+    k_source<F, decltype(d3)::value, decltype(geo)::value, decltype(adi)::value>
+        <<<nb, NT, 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2, nbx, nby);
+  };
+  auto by_eos = [&](auto d3, auto geo) {
+    if (m.eos == FARGO_ADIABATIC) go(d3, geo, std::true_type{});
+    else go(d3, geo, std::false_type{});
+  };
+  auto by_geo = [&](auto d3) {
+    if (m.geo == FARGO_SPHERICAL) by_eos(d3, std::integral_constant<int, FARGO_SPHERICAL>{});
+    else if (m.geo == FARGO_CYLINDRICAL) by_eos(d3, std::integral_constant<int, FARGO_CYLINDRICAL>{});
+    else by_eos(d3, std::integral_constant<int, FARGO_CARTESIAN>{});
+  };
+  if (m.d3) by_geo(std::true_type{});
+  else by_geo(std::false_type{});
   prof_end(L, K_SRC);
   prof_begin(L, K_SRC_GHOSTS);
   k_source_ghosts<F><<<ng, 256, 0, L.s>>>(m, s, vx2, vy2, vz2, e2);

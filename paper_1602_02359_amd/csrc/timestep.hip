@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_
   // Eq. cfl2 through the inverse steps (rates u / Delta): the minimum step of
   // a cell over directions is its maximum rate, and the smallest step is
   // 1 / sqrt of the largest sum of squared rates (taken in k_dt_final)
-  const double Lx = m.DX(j, k), Lyy = gk(m.g.Ly, j);
+  const double Lx = m.DX(j, k), Lyy = m.g.Ly(j);
   const double Lzz = m.d3 ? m.Lz(j, k) : 0.0;
   const double iLx = 1.0 / Lx, iLy = 1.0 / Lyy, iLz = m.d3 ? 1.0 / Lzz : 0.0;
   double Lmin = fmin(Lx, Lyy);

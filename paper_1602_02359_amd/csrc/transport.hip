@@ -176,8 +176,8 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
   struct Geo {
     const Mesh &m;
     int k;
-    __device__ F L(int a) const { return (F)gk(m.g.Ly, a); }
-    __device__ F h(int f) const { return (F)gk(m.g.hy, f); }
+    __device__ F L(int a) const { return (F)m.g.Ly(a); }
+    __device__ F h(int f) const { return (F)m.g.hy(f); }
     __device__ F S(int f) const { return (F)m.Sy(f, k); }
     __device__ F Vi(int a) const { return (F)m.Vinv(a, k); }
   } geo{m, k};
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(256) void k_vel(Mesh m, StateT<F> s, TSetT<F> T) {
   if (dy) s.vy[c] = (py + my) / (ry + rc);
   if (dz) {
     F v = (pz + mz) / (rz + rc);
-    s.vz[c] = m.geo == FARGO_SPHERICAL ? v / (F)gk(m.g.ymed, j) : v;
+    s.vz[c] = m.geo == FARGO_SPHERICAL ? v / (F)m.g.ymed(j) : v;
   }
 }
 

@@ -24,13 +24,13 @@ struct Visc {
   // tau_phiphi and tau_rr of zone (a, b)
   __device__ inline void diag(int a, int b, F &tpp, F &trr) const {
     const unsigned c = at(a, b), cxp = at(wrapx(a + 1), b), cyp = c + (unsigned)m.pitch;
-    const F dphi = (F)m.dx, r = (F)gk(m.g.ymed, b);
+    const F dphi = (F)m.dx, r = (F)m.g.ymed(b);
     const F divv = (F)m.Vinv(b, 0) * ((F)m.Sx(b, 0) * (vx[cxp] - vx[c]) +
                                       ((F)m.Sy(b + 1, 0) * vy[cyp] - (F)m.Sy(b, 0) * vy[c]));
     const F rn = s.rho[c] * s.nu[c];
     const F ur = F(0.5) * (vy[c] + vy[cyp]);
     tpp = -rn * (F(2) * ((vx[cxp] - vx[c]) / (r * dphi) + ur / r) - F(2) / F(3) * divv);
-    trr = -rn * (F(2) * (vy[cyp] - vy[c]) / (F)gk(m.g.Ly, b) - F(2) / F(3) * divv);
+    trr = -rn * (F(2) * (vy[cyp] - vy[c]) / (F)m.g.Ly(b) - F(2) / F(3) * divv);
   }
   // tau_rphi on the edge of zone (a, b) at its lower X and Y faces
   __device__ inline F edge(int a, int b) const {
@@ -38,9 +38,9 @@ struct Visc {
     const unsigned c = at(a, b), cw = at(am, b), cs_ = c - (unsigned)m.pitch, csw = cw - (unsigned)m.pitch;
     const F rho4 = F(0.25) * (s.rho[c] + s.rho[cw] + s.rho[cs_] + s.rho[csw]);
     const F nu4 = F(0.25) * (s.nu[c] + s.nu[cw] + s.nu[cs_] + s.nu[csw]);
-    const F dvphi_dr = (vx[c] - vx[cs_]) / (F)gk(m.g.hy, b);
-    const F vphi_r = F(0.5) * (vx[c] / (F)gk(m.g.ymed, b) + vx[cs_] / (F)gk(m.g.ymed, b - 1));
-    const F dvr_dphi = (vy[c] - vy[cw]) / ((F)gk(m.g.ymin, b) * (F)m.dx);
+    const F dvphi_dr = (vx[c] - vx[cs_]) / (F)m.g.hy(b);
+    const F vphi_r = F(0.5) * (vx[c] / (F)m.g.ymed(b) + vx[cs_] / (F)m.g.ymed(b - 1));
+    const F dvr_dphi = (vy[c] - vy[cw]) / ((F)m.g.ymin(b) * (F)m.dx);
     return -rho4 * nu4 * (dvphi_dr - vphi_r + dvr_dphi);
   }
 };
@@ -68,9 +68,9 @@ __global__ __launch_bounds__(256) void k_visc(Visc<F> V, const double *__restric
     F tpp0, trr0, tppw, trrw;
     V.diag(i, j, tpp0, trr0);
     V.diag(im, j, tppw, trrw);
-    const F a = (F)gk(m.g.ymin, j), b = (F)gk(m.g.ymin, j + 1), r = (F)gk(m.g.ymed, j);
+    const F a = (F)m.g.ymin(j), b = (F)m.g.ymin(j + 1), r = (F)m.g.ymed(j);
     const F rho_f = F(0.5) * (rho[c] + rho[V.at(im, j)]);
-    const F div = (b * b * V.edge(i, j + 1) - a * a * V.edge(i, j)) / (r * r * (F)gk(m.g.Ly, j)) + (tpp0 - tppw) / (r * dphi);
+    const F div = (b * b * V.edge(i, j + 1) - a * a * V.edge(i, j)) / (r * r * (F)m.g.Ly(j)) + (tpp0 - tppw) / (r * dphi);
     vx3[c] = V.vx[c] - dt * div / rho_f;
   }
   // v_r on the Y face of zone (i, j), if the step owns it
@@ -78,9 +78,9 @@ __global__ __launch_bounds__(256) void k_visc(Visc<F> V, const double *__restric
     F tpp0, trr0, tpps, trrs;
     V.diag(i, j, tpp0, trr0);
     V.diag(i, j - 1, tpps, trrs);
-    const F a = (F)gk(m.g.ymin, j);
+    const F a = (F)m.g.ymin(j);
     const F rho_f = F(0.5) * (rho[c] + rho[c - (unsigned)m.pitch]);
-    const F div = ((F)gk(m.g.ymed, j) * trr0 - (F)gk(m.g.ymed, j - 1) * trrs) / (a * (F)gk(m.g.hy, j)) +
+    const F div = ((F)m.g.ymed(j) * trr0 - (F)m.g.ymed(j - 1) * trrs) / (a * (F)m.g.hy(j)) +
                   (V.edge(V.wrapx(i + 1), j) - V.edge(i, j)) / (a * dphi) - F(0.5) * (tpp0 + tpps) / a;
     vy3[c] = V.vy[c] - dt * div / rho_f;
   } else {
