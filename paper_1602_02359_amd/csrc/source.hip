@@ -70,6 +70,15 @@ __device__ inline T vmove(T x) {
   return y;
 }
 
+// A value the compiler is to keep in vector registers (every lane of a wave
+// holding the same value), which leaves the scalar registers to the values
+// that change along the march.
+template <typename T>
+__device__ inline T vreg(T x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
 // one zone's values in one plane
 template <typename F>
 struct Zv {
@@ -100,8 +109,15 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
   const int i = i0 + c, j = jt0 + r;
   constexpr bool adi = ADI;
   constexpr bool sph = GEO == FARGO_SPHERICAL, cyl = GEO == FARGO_CYLINDRICAL;
-  const F dt = (F)*dtp, c2 = (F)(m.cvnr * m.cvnr), om = (F)m.omega, gm1 = (F)(m.gamma - 1.0);
+  const F dt = vreg((F)*dtp), c2 = vreg((F)(m.cvnr * m.cvnr)), om = vreg((F)m.omega), gm1 = vreg((F)(m.gamma - 1.0));
   const unsigned plane = (unsigned)m.plane();
+  // geometric factors of the thread's row (the products with the plane
+  // factors are those of Mesh::Sx, Sy, Sz and Vinv); rows past the tile
+  // read the last active row
+  const int jg = min(j, m.jn - 1);
+  const double g_sxj = vreg(m.g.sxj(jg)), g_syj = vreg(m.g.syj(jg)), g_syj1 = vreg(m.g.syj(jg + 1)),
+               g_szj = vreg(m.g.szj(jg)), g_invVj = vreg(m.g.invVj(jg)), g_invLy = vreg(m.g.inv_Ly(jg)),
+               g_iymed = vreg(m.g.inv_ymed(jg)), g_ymed = vreg(m.g.ymed(jg));
 
   // storage column of X slot sl (i0 - 2 + sl, periodic) and row of Y slot t
   auto xcol = [&](int sl) {
@@ -134,15 +150,15 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
   auto vz1 = [&](int p, const Zv<F> &zb, const Zv<F> &z0, F &iz) {
     iz = F(0);
     if (!zowned(p)) return z0.vz;
-    const double ihzd = sph ? m.g.inv_dzmed(p) * m.g.inv_ymed(j) : m.g.inv_dzmed(p);
+    const double ihzd = sph ? m.g.inv_dzmed(p) * g_iymed : m.g.inv_dzmed(p);
     iz = (F)ihzd / (z0.rho + zb.rho);
     F gradP = F(2) * (pres(z0.rho, z0.q) - pres(zb.rho, zb.q)) * iz;
     F gradPhi = (F)((z0.pot - zb.pot) * ihzd);
     F src = F(0);
     if (sph) {
-      F R0 = (F)(m.g.ymed(j) * m.g.sinz(p)), R1 = (F)(m.g.ymed(j) * m.g.sinz(m.kbelow(p)));
+      F R0 = (F)(g_ymed * m.g.sinz(p)), R1 = (F)(g_ymed * m.g.sinz(m.kbelow(p)));
       F vt = F(0.25) * ((z0.vx + R0 * om) + (z0.vxp + R0 * om) + (zb.vx + R1 * om) + (zb.vxp + R1 * om));
-      src = vt * vt * (F)m.g.cotz(p) * (F)m.g.inv_ymed(j);
+      src = vt * vt * (F)m.g.cotz(p) * (F)g_iymed;
     }
     return z0.vz - dt * (gradP + gradPhi) + dt * src;
   };
@@ -290,7 +306,8 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
     const F bx2 = a2 - dt * F(2) * (qxp - qx) * L.IX[sb][r][sl + 1];
     vx2[o] = bx1;
     F heat = qx * dvx * (F)m.g.inv_dxlen((size_t)kk * m.nyg + j);
-    F flux = (F)m.Sx(j, kk) * (bx2 - bx1);
+    const double syk = m.g.syk(kk);
+    F flux = (F)(g_sxj * m.g.sxk(kk)) * (bx2 - bx1);
     // Y: faces t-1 .. t+2, zones t-1 .. t+1
     const F b0 = L.AY[sb][t - 1][c], b1 = L.AY[sb][t][c], b2 = L.AY[sb][t + 1][c], b3 = L.AY[sb][t + 2][c];
     const F s1 = R[t - 1][sl], s3 = R[t + 1][sl];
@@ -300,17 +317,17 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
     if (yowned(j)) by1 = b1 - dt * F(2) * (qy - qvisc(c2, s1, b1 - b0)) * L.IY[sb][t][c];
     if (yowned(yrow(t + 1))) by2 = b2 - dt * F(2) * (qvisc(c2, s3, b3 - b2) - qy) * L.IY[sb][t + 1][c];
     vy2[o] = by1;
-    heat += qy * dvy * (F)m.g.inv_Ly(j);
-    flux += (F)m.Sy(j + 1, kk) * by2 - (F)m.Sy(j, kk) * by1;
+    heat += qy * dvy * (F)g_invLy;
+    flux += (F)(g_syj1 * syk) * by2 - (F)(g_syj * syk) * by1;
     if (D3) {
       vz2[o] = zp.bz1;
-      const F iLz = sph ? (F)(m.g.inv_dz(kk) * m.g.inv_ymed(j)) : (F)m.g.inv_dz(kk);
+      const F iLz = sph ? (F)(m.g.inv_dz(kk) * g_iymed) : (F)m.g.inv_dz(kk);
       heat += zp.qz * zp.dvz * iLz;
-      flux += (F)m.Sz(j, kk + 1) * zp.bz2 - (F)m.Sz(j, kk) * zp.bz1;
+      flux += (F)(g_szj * m.g.szk(kk + 1)) * zp.bz2 - (F)(g_szj * m.g.szk(kk)) * zp.bz1;
     }
     if (adi) {
       const F e1 = e_old - dt * heat;
-      const F a = F(0.5) * dt * gm1 * ((F)m.Vinv(j, kk) * flux);
+      const F a = F(0.5) * dt * gm1 * ((F)(g_invVj / syk) * flux);
       e2[o] = e1 * (F(1) - a) / (F(1) + a);
     }
   };
