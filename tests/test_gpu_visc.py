@@ -3,7 +3,7 @@ through the C ABI.
 
 The viscous step is compared with the FP64 oracle (time step bit-exact, state
 within 1e-12 normwise after one step); the FP32-bulk form with the FP64 step
-after 100 steps at 1e-5.  A batch step (one captured hipGraph over many disks)
+after 100 steps at 1e-4 (the FP32 bar of tests/test_gpu_fp32.py).  A batch step (one captured hipGraph over many disks)
 must equal the disks' own steps bit for bit, and the autotuner must leave the
 states as it found them.
 """
