@@ -246,6 +246,76 @@ int fargo_batch_tune(fargo_batch *batch, const int32_t *lanes, int nlanes, const
 /* Release the graph and streams (waits for the device).  NULL is a no-op. */
 void fargo_batch_destroy(fargo_batch *batch);
 
+/* ------------------------------------------------------------------------ */
+/* Learned flux correction (an extension; the paper has no learned part)    */
+/* ------------------------------------------------------------------------ */
+/* A three-layer 3 x 3 convolutional net (4 -> 32 -> 32 -> 2 channels, ReLU
+   after the first two layers) on the active zones of a 2D cylindrical FP64
+   context predicts corrections to the mass fluxes through each zone's lower
+   X (azimuthal) and lower Y (radial) face.  They are applied as a
+   conservative flux-divergence update of the density,
+     drho_ij = -(1/V_j) [dFx_{i+1,j} - dFx_ij + dFy_{i,j+1} - dFy_ij],
+   with no correction through the two radial boundary faces, so the total mass
+   is unchanged (the telescoping argument of Sect. 3.4).  Features of a zone:
+   rho/rho_s - 1, v_y/u_s, v_x/u_s (the face velocities stored with the
+   zone) and (r - r_mid)/r_span; convolutions are periodic in X and zero
+   beyond the active radial rows.  Products run on the bfloat16 matrix cores
+   (operands rounded to nearest even, FP32 accumulation); the FP32 master
+   parameters are trained on the device with Adam (beta1 0.9, beta2 0.999,
+   eps 1e-8) on the loss mean(((drho - target)/sigma)^2).
+   Requirements: cylindrical, nz == 1, FARGO_FP64, nx a multiple of 16 and
+   nx*ny a multiple of 256 (FARGO_EUNSUPPORTED otherwise). */
+typedef struct fargo_lfc fargo_lfc;
+typedef struct {
+  double rho_s, u_s, r_mid, r_span; /* feature scales */
+  double flux_scale;                /* dF = flux_scale x net output */
+  double sigma;                     /* loss scale (> 0) */
+  double guard;                     /* apply only if rho + drho > 0 and |drho| <= guard rho in every zone */
+} fargo_lfc_params;
+/* Parameter vector (FP32): W1 [32][3][3][4], b1 [32], W2 [32][3][3][32],
+   b2 [32], W3 [2][3][3][32], b3 [2]; weights [out][ty][tx][in]. */
+#define FARGO_LFC_NPARAM 11010
+/* Device buffers of the last forward / training step, for inspection:
+   f [pixel][4], h1, h2 [pixel][32] (bfloat16 bits as uint16), o [pixel][2]
+   (float), drho [pixel] (double), g3 [pixel][4], g2, g1 [pixel][32]
+   (bfloat16 layer gradients); pixel = j nx + i over the active zones. */
+typedef struct {
+  const void *f, *h1, *h2, *o, *drho, *g3, *g2, *g1;
+} fargo_lfc_views;
+/* Bind a net to `ctx` (which must outlive it); allocates its device
+   buffers.  Parameters start at zero: set them with fargo_lfc_set_params. */
+int fargo_lfc_create(fargo_ctx *ctx, const fargo_lfc_params *p, fargo_lfc **out);
+/* Free the buffers (waits for the device).  NULL is a no-op. */
+void fargo_lfc_destroy(fargo_lfc *l);
+/* Copy n == FARGO_LFC_NPARAM host floats in (resets Adam's moments and step
+   count) or out; fargo_lfc_get_grad copies the last gradient out.  These
+   synchronize the device. */
+int fargo_lfc_set_params(fargo_lfc *l, const float *host, int32_t n);
+int fargo_lfc_get_params(fargo_lfc *l, float *host, int32_t n);
+int fargo_lfc_get_grad(fargo_lfc *l, float *host, int32_t n);
+/* The net on `state` and the density change it implies (views.drho). */
+int fargo_lfc_forward(fargo_lfc *l, const fargo_state *state, void *stream);
+/* One Adam step with learning rate lr on the loss against `target` (device,
+   double [ny][nx] over the active zones, the wanted density change). */
+int fargo_lfc_train_step(fargo_lfc *l, const fargo_state *state, const double *target, double lr,
+                         void *stream);
+/* Forward, then the guarded update of state->rho: if the guard rejects the
+   correction anywhere, the density is left as it is and the skip flag is
+   set (read with fargo_lfc_result). */
+int fargo_lfc_apply(fargo_lfc *l, fargo_state *state, void *stream);
+/* Loss of the last training step and skip flag of the last apply (waits for
+   `stream`); either pointer may be NULL. */
+int fargo_lfc_result(fargo_lfc *l, double *loss, int32_t *skipped, void *stream);
+int fargo_lfc_get_views(fargo_lfc *l, fargo_lfc_views *v);
+/* 4 x 4 conservative restriction of the active zones of a fine 2D
+   cylindrical FP64 state onto a coarse one (fine nx, ny = 4 coarse nx, ny;
+   every coarse face a fine face): density = mass / volume of the coarse
+   zone; v_x on a coarse X face = the radial-width-weighted mean of the 4 fine
+   X faces on it; v_y on a coarse Y face = the mean of the 4 fine Y faces on
+   it.  Ghost zones of the coarse state are not written. */
+int fargo_lfc_restrict(const fargo_ctx *fine, const fargo_state *fs, const fargo_ctx *coarse, fargo_state *cs,
+                       void *stream);
+
 #ifdef __cplusplus
 }
 #endif

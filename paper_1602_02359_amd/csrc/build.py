@@ -15,7 +15,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libfargo.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["fargo_api.hip", "bc.hip", "timestep.hip", "source.hip", "visc.hip", "transport.hip", "misc.hip"]
+SOURCES = ["fargo_api.hip", "bc.hip", "timestep.hip", "source.hip", "visc.hip", "transport.hip", "misc.hip", "lfc.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

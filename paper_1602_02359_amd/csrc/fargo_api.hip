@@ -895,3 +895,206 @@ void fargo_batch_destroy(fargo_batch *b) {
 }
 
 } // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned flux correction
+// ---------------------------------------------------------------------------
+struct fargo_lfc {
+  fargo_ctx *ctx = nullptr;
+  fargo_lfc_params p{};
+  LfcScales sc{};
+  LfcBufs B{};
+  int *flag = nullptr; // guard: 1 if the last apply was rejected
+  void *mem = nullptr;
+  int step = 0; // Adam steps since the parameters were set
+};
+
+namespace {
+
+bool lfc_mesh_ok(const fargo_ctx *c) {
+  const Mesh &m = c->m;
+  return c->p.geometry == FARGO_CYLINDRICAL && !m.d3 && !fp32(c) && m.nx % 16 == 0 &&
+         ((long)m.nx * m.ny) % LFC_CHUNK == 0;
+}
+
+} // namespace
+
+extern "C" {
+
+int fargo_lfc_create(fargo_ctx *ctx, const fargo_lfc_params *p, fargo_lfc **out) {
+  if (!ctx || !p || !out) return FARGO_EINVAL;
+  *out = nullptr;
+  if (!lfc_mesh_ok(ctx)) return FARGO_EUNSUPPORTED;
+  if (!(p->rho_s != 0.0) || !(p->u_s != 0.0) || !(p->r_span != 0.0) || !(p->sigma > 0.0) || !(p->guard > 0.0) ||
+      !std::isfinite(p->flux_scale))
+    return FARGO_EINVAL;
+  const long npix = (long)ctx->m.nx * ctx->m.ny, nchunk = npix / LFC_CHUNK;
+  const long nlb = (npix + 255) / 256;
+  // one allocation, carved in 256-byte aligned slots
+  size_t off = 0;
+  auto slot = [&](size_t bytes) {
+    size_t o = off;
+    off += al(bytes);
+    return o;
+  };
+  const size_t o_f = slot(npix * 4 * 2), o_h1 = slot(npix * 32 * 2), o_h2 = slot(npix * 32 * 2),
+               o_o = slot(npix * 2 * 4), o_g3 = slot(npix * 4 * 2), o_g2 = slot(npix * 32 * 2),
+               o_g1 = slot(npix * 32 * 2), o_drho = slot(npix * 8), o_gD = slot(npix * 8), o_lp = slot(nlb * 8),
+               o_loss = slot(8), o_flag = slot(4), o_w = slot(LFC_NPARAM * 4), o_mo = slot(LFC_NPARAM * 4),
+               o_ve = slot(LFC_NPARAM * 4), o_gr = slot(LFC_NPARAM * 4), o_part = slot(nchunk * 32 * 288 * 4),
+               o_dbp = slot(nchunk * 32 * 4), o_wb1 = slot(32 * 48 * 2), o_wb2 = slot(32 * 288 * 2),
+               o_wb3 = slot(16 * 288 * 2), o_wt2 = slot(32 * 288 * 2), o_wt3 = slot(32 * 48 * 2);
+  fargo_lfc *l = new fargo_lfc;
+  if (hipSetDevice(ctx->dev) != hipSuccess || hipMalloc(&l->mem, off) != hipSuccess) {
+    delete l;
+    return FARGO_ENOMEM;
+  }
+  if (hipMemset(l->mem, 0, off) != hipSuccess) {
+    fargo_lfc_destroy(l);
+    return FARGO_EHIP;
+  }
+  char *b = (char *)l->mem;
+  LfcBufs &B = l->B;
+  B.f = (unsigned short *)(b + o_f);
+  B.h1 = (unsigned short *)(b + o_h1);
+  B.h2 = (unsigned short *)(b + o_h2);
+  B.o = (float *)(b + o_o);
+  B.g3 = (unsigned short *)(b + o_g3);
+  B.g2 = (unsigned short *)(b + o_g2);
+  B.g1 = (unsigned short *)(b + o_g1);
+  B.drho = (double *)(b + o_drho);
+  B.gD = (double *)(b + o_gD);
+  B.lpart = (double *)(b + o_lp);
+  B.loss = (double *)(b + o_loss);
+  l->flag = (int *)(b + o_flag);
+  B.w = (float *)(b + o_w);
+  B.mo = (float *)(b + o_mo);
+  B.ve = (float *)(b + o_ve);
+  B.grad = (float *)(b + o_gr);
+  B.part = (float *)(b + o_part);
+  B.dbpart = (float *)(b + o_dbp);
+  B.wt.wb1 = (unsigned short *)(b + o_wb1);
+  B.wt.wb2 = (unsigned short *)(b + o_wb2);
+  B.wt.wb3 = (unsigned short *)(b + o_wb3);
+  B.wt.wt2 = (unsigned short *)(b + o_wt2);
+  B.wt.wt3 = (unsigned short *)(b + o_wt3);
+  l->ctx = ctx;
+  l->p = *p;
+  l->sc = LfcScales{p->rho_s, p->u_s, p->r_mid, p->r_span};
+  *out = l;
+  return FARGO_OK;
+}
+
+void fargo_lfc_destroy(fargo_lfc *l) {
+  if (!l) return;
+  (void)hipDeviceSynchronize();
+  if (l->mem) (void)hipFree(l->mem);
+  delete l;
+}
+
+int fargo_lfc_set_params(fargo_lfc *l, const float *host, int32_t n) {
+  if (!l || !host || n != LFC_NPARAM) return FARGO_EINVAL;
+  for (int e = 0; e < n; e++)
+    if (!std::isfinite(host[e])) return FARGO_EINVAL;
+  if (hipMemcpy(l->B.w, host, (size_t)n * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(l->B.mo, 0, (size_t)n * 4) != hipSuccess || hipMemset(l->B.ve, 0, (size_t)n * 4) != hipSuccess)
+    return FARGO_EHIP;
+  Launch L{nullptr, nullptr};
+  lfc_pack(L, l->B);
+  l->step = 0;
+  return hipDeviceSynchronize() == hipSuccess && hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+static int lfc_copy_out(const float *dev, float *host, int32_t n) {
+  if (!host || n != LFC_NPARAM) return FARGO_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return FARGO_EHIP;
+  return hipMemcpy(host, dev, (size_t)n * 4, hipMemcpyDeviceToHost) == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+int fargo_lfc_get_params(fargo_lfc *l, float *host, int32_t n) { return l ? lfc_copy_out(l->B.w, host, n) : FARGO_EINVAL; }
+
+int fargo_lfc_get_grad(fargo_lfc *l, float *host, int32_t n) {
+  return l ? lfc_copy_out(l->B.grad, host, n) : FARGO_EINVAL;
+}
+
+int fargo_lfc_forward(fargo_lfc *l, const fargo_state *state, void *stream) {
+  if (!l) return FARGO_EINVAL;
+  int rc = check_state(l->ctx, state);
+  if (rc) return rc;
+  Launch L{(hipStream_t)stream, nullptr};
+  const Mesh &m = l->ctx->m;
+  lfc_forward(L, m, (const double *)state->rho, (const double *)state->vx, (const double *)state->vy, l->sc, l->B);
+  lfc_drho(L, m, l->B, l->p.flux_scale, nullptr, l->p.sigma);
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+int fargo_lfc_train_step(fargo_lfc *l, const fargo_state *state, const double *target, double lr, void *stream) {
+  if (!l || !target || !(lr > 0.0) || !std::isfinite(lr)) return FARGO_EINVAL;
+  int rc = check_state(l->ctx, state);
+  if (rc) return rc;
+  Launch L{(hipStream_t)stream, nullptr};
+  const Mesh &m = l->ctx->m;
+  lfc_forward(L, m, (const double *)state->rho, (const double *)state->vx, (const double *)state->vy, l->sc, l->B);
+  lfc_drho(L, m, l->B, l->p.flux_scale, target, l->p.sigma);
+  lfc_backward(L, m, l->B, l->p.flux_scale);
+  l->step++;
+  const double c1 = 1.0 - std::pow(0.9, l->step), c2 = 1.0 - std::pow(0.999, l->step);
+  lfc_adam(L, l->B, (float)lr, (float)c1, (float)c2);
+  lfc_pack(L, l->B);
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+int fargo_lfc_apply(fargo_lfc *l, fargo_state *state, void *stream) {
+  int rc = fargo_lfc_forward(l, state, stream);
+  if (rc) return rc;
+  Launch L{(hipStream_t)stream, nullptr};
+  lfc_apply(L, l->ctx->m, l->B, (double *)state->rho, l->p.guard, l->flag);
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+int fargo_lfc_result(fargo_lfc *l, double *loss, int32_t *skipped, void *stream) {
+  if (!l) return FARGO_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipStreamSynchronize(s) != hipSuccess) return FARGO_EHIP;
+  if (loss && hipMemcpy(loss, l->B.loss, 8, hipMemcpyDeviceToHost) != hipSuccess) return FARGO_EHIP;
+  if (skipped) {
+    int f = 0;
+    if (hipMemcpy(&f, l->flag, 4, hipMemcpyDeviceToHost) != hipSuccess) return FARGO_EHIP;
+    *skipped = f;
+  }
+  return FARGO_OK;
+}
+
+int fargo_lfc_get_views(fargo_lfc *l, fargo_lfc_views *v) {
+  if (!l || !v) return FARGO_EINVAL;
+  v->f = l->B.f;
+  v->h1 = l->B.h1;
+  v->h2 = l->B.h2;
+  v->o = l->B.o;
+  v->drho = l->B.drho;
+  v->g3 = l->B.g3;
+  v->g2 = l->B.g2;
+  v->g1 = l->B.g1;
+  return FARGO_OK;
+}
+
+int fargo_lfc_restrict(const fargo_ctx *fine, const fargo_state *fs, const fargo_ctx *coarse, fargo_state *cs,
+                       void *stream) {
+  if (!fine || !coarse || !fs || !cs) return FARGO_EINVAL;
+  const Mesh &mf = fine->m, &mc = coarse->m;
+  for (const fargo_ctx *c : {fine, coarse})
+    if (c->p.geometry != FARGO_CYLINDRICAL || c->m.d3 || fp32(c)) return FARGO_EUNSUPPORTED;
+  if (mf.nx != 4 * mc.nx || mf.ny != 4 * mc.ny || fine->p.xmin != coarse->p.xmin || fine->p.xmax != coarse->p.xmax)
+    return FARGO_EINVAL;
+  for (int J = 0; J <= mc.ny; J++) {
+    const double yc = coarse->ymin[NGH + J], yf = fine->ymin[NGH + 4 * J];
+    if (!(std::fabs(yc - yf) <= 1e-12 * std::fabs(yc))) return FARGO_EINVAL;
+  }
+  if (!fs->rho || !fs->vx || !fs->vy || !cs->rho || !cs->vx || !cs->vy) return FARGO_EINVAL;
+  Launch L{(hipStream_t)stream, nullptr};
+  lfc_restrict(L, mf, (const double *)fs->rho, (const double *)fs->vx, (const double *)fs->vy, mc, (double *)cs->rho,
+               (double *)cs->vx, (double *)cs->vy);
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+} // extern "C"

@@ -270,4 +270,39 @@ void launch_shift(Launch &L, const Mesh &m, R *field, const int32_t *N);
 template <typename R>
 void launch_sums(Launch &L, const Mesh &m, const StateT<R> &s, double *partial, double *out);
 
+// ------------------------------------------------------------------------
+// Learned flux correction (2D cylindrical FP64 state)
+// ------------------------------------------------------------------------
+// FP32 master parameters: W1 [32][9*4], b1 [32], W2 [32][9*32], b2 [32],
+// W3 [2][9*32], b3 [2]; weights [co][tap][ci], tap = 3 ty + tx
+constexpr int LFC_OFF_W1 = 0, LFC_OFF_B1 = 1152, LFC_OFF_W2 = 1184, LFC_OFF_B2 = 10400, LFC_OFF_W3 = 10432,
+              LFC_OFF_B3 = 11008, LFC_NPARAM = 11010;
+struct LfcScales {
+  double rho_s, u_s, r_mid, r_span;
+};
+// bfloat16 weight copies: forward [rows][K padded to 16], and the transposes
+// for the input gradients [ci][tap * Cg + co]
+struct LfcWeights {
+  unsigned short *wb1, *wb2, *wb3, *wt2, *wt3; // [32][48], [32][288], [16][288], [32][288], [32][48]
+};
+struct LfcBufs {
+  unsigned short *f, *h1, *h2;      // activations [pixel][4 | 32 | 32]
+  float *o;                         // net output [pixel][2]
+  unsigned short *g3, *g2, *g1;     // layer gradients [pixel][4 | 32 | 32]
+  double *drho, *gD, *lpart, *loss; // density change, dL/d(divergence), loss partials, loss
+  float *w, *mo, *ve, *grad;        // master parameters, Adam moments, gradient [LFC_NPARAM]
+  float *part, *dbpart;             // weight-gradient partials per pixel chunk
+  LfcWeights wt;
+};
+constexpr int LFC_CHUNK = 256; // pixels per weight-gradient partial
+void lfc_forward(Launch &L, const Mesh &m, const double *rho, const double *vx, const double *vy,
+                 const LfcScales &sc, const LfcBufs &B);
+void lfc_drho(Launch &L, const Mesh &m, const LfcBufs &B, double sF, const double *target, double sigma);
+void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF);
+void lfc_adam(Launch &L, const LfcBufs &B, float lr, float c1, float c2);
+void lfc_pack(Launch &L, const LfcBufs &B);
+void lfc_apply(Launch &L, const Mesh &m, const LfcBufs &B, double *rho, double guard, int *flag);
+void lfc_restrict(Launch &L, const Mesh &mf, const double *rf, const double *vxf, const double *vyf, const Mesh &mc,
+                  double *rc, double *vxc, double *vyc);
+
 } // namespace fargo

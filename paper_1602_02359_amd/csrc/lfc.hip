@@ -1,0 +1,519 @@
+// Learned flux correction (not in the paper).  A three-layer 3 x 3
+// convolutional net on the coarse 2D (phi, r) state predicts corrections to
+// the mass fluxes through each zone's lower X and lower Y face; they enter as
+// a conservative flux-divergence update of the density, so the mass change
+// telescopes to zero over the mesh (the conservation argument of Sect. 3.4
+// applied to the added fluxes).  The net is trained on device: forward pass,
+// loss, backward pass and Adam (Kingma & Ba 2015).
+//
+// The convolutions are implicit GEMMs on the bfloat16 matrix cores
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation), one 16-row tile per wave:
+//   forward     out[p][co] = sum_k A[p][k] W[co][k],  k = tap Cin + ci,
+//               A[p][k] = act[p shifted by tap][ci]               (M = pixels)
+//   input grad  gin[p][ci] = sum_k G[p][k] Wt[ci][k], k = tap Cg + co,
+//               G[p][k] = g[p shifted back by tap][co]             (M = pixels)
+//   weight grad dW[co][k] = sum_p g[p][co] A[p][k]                 (M = Cout,
+//               reduced over pixel chunks, partial sums per chunk)
+// Operand layouts of the 16x16x16 MFMA: lane l holds row (or column) l % 16
+// and the four k values 4 (l / 16) .. 4 (l / 16) + 3; the result tile gives
+// lane l column l % 16 and rows 4 (l / 16) .. 4 (l / 16) + 3.
+//
+// Activations are channels-last bfloat16, [pixel][channel] with pixel =
+// j nx + i over the active zones (j = 0 the innermost ring), zero beyond the
+// radial rows and periodic in i; weights [co][tap][ci], tap = 3 ty + tx.
+#include "fargo_internal.h"
+
+namespace fargo {
+
+namespace {
+
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int LB = 256; // threads per block of the elementwise kernels
+
+// FP32 -> bfloat16, round to nearest even (finite values)
+__device__ inline unsigned short to_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// four consecutive bfloat16 (8-byte aligned) as an MFMA operand
+__device__ inline bf4 ld4(const unsigned short *p) {
+  const uint2 v = *reinterpret_cast<const uint2 *>(p);
+  bf4 r;
+  r[0] = (short)(v.x & 0xFFFFu);
+  r[1] = (short)(v.x >> 16);
+  r[2] = (short)(v.y & 0xFFFFu);
+  r[3] = (short)(v.y >> 16);
+  return r;
+}
+__device__ inline bf4 zero4() {
+  bf4 r;
+  r[0] = r[1] = r[2] = r[3] = 0;
+  return r;
+}
+
+// pixel reached from (y, x) by tap (ty, tx) of the forward stencil, or -1
+// outside the radial rows
+__device__ inline int tap_src(int y, int x, int ty, int tx, int ny, int nx) {
+  const int yy = y + ty - 1;
+  if (yy < 0 || yy >= ny) return -1;
+  int xx = x + tx - 1;
+  xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+  return yy * nx + xx;
+}
+// pixel whose forward tap (ty, tx) reads (y, x), or -1
+__device__ inline int tap_dst(int y, int x, int ty, int tx, int ny, int nx) {
+  const int yy = y - (ty - 1);
+  if (yy < 0 || yy >= ny) return -1;
+  int xx = x - (tx - 1);
+  xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+  return yy * nx + xx;
+}
+
+// ---------------------------------------------------------------------------
+// features (FP64 arithmetic, rounded to FP32 then to bfloat16)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(LB) void k_features(Mesh m, const double *__restrict__ rho,
+                                                 const double *__restrict__ vx, const double *__restrict__ vy,
+                                                 LfcScales sc, unsigned short *__restrict__ f) {
+#pragma clang fp contract(off)
+  const int npix = m.nx * m.ny;
+  const int p = blockIdx.x * LB + threadIdx.x;
+  if (p >= npix) return;
+  const int j = p / m.nx, i = p - j * m.nx;
+  const unsigned c = m.o32(i, j + m.j0, 0);
+  const double f0 = rho[c] / sc.rho_s - 1.0;
+  const double f1 = vy[c] / sc.u_s;
+  const double f2 = vx[c] / sc.u_s;
+  const double f3 = (m.g.ymed(j + m.j0) - sc.r_mid) / sc.r_span;
+  uint2 v;
+  v.x = (unsigned)to_bf16((float)f0) | ((unsigned)to_bf16((float)f1) << 16);
+  v.y = (unsigned)to_bf16((float)f2) | ((unsigned)to_bf16((float)f3) << 16);
+  *reinterpret_cast<uint2 *>(f + (size_t)p * 4) = v;
+}
+
+// ---------------------------------------------------------------------------
+// forward convolution: CIN -> COUT channels; KP = 9 CIN rounded up to 16,
+// the weights Wb are [16 NT][KP] bfloat16 (zero padded)
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT, bool RELU>
+__global__ __launch_bounds__(256) void k_conv_fwd(int nx, int ny, const unsigned short *__restrict__ act,
+                                                  const unsigned short *__restrict__ Wb,
+                                                  const float *__restrict__ bias, unsigned short *__restrict__ hout,
+                                                  float *__restrict__ fout) {
+  constexpr int K = 9 * CIN, KP = (K + 15) / 16 * 16, NT = (COUT + 15) / 16;
+  const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
+  const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const int pa = p0 + m; // the pixel of this lane's A row
+  const int ya = pa / nx, xa = pa - ya * nx;
+  f4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; t++) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int s = 0; s < KP / 16; s++) {
+    const int k0 = 16 * s + 4 * kq;
+    bf4 a = zero4();
+    if (k0 < K) {
+      const int tap = k0 / CIN, ci = k0 - tap * CIN;
+      const int q = tap_src(ya, xa, tap / 3, tap % 3, ny, nx);
+      if (q >= 0) a = ld4(act + (size_t)q * CIN + ci);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+      const bf4 b = ld4(Wb + (size_t)(16 * t + m) * KP + k0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; t++) {
+    const int co = 16 * t + m;
+    if (co >= COUT) continue;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const int p = p0 + 4 * kq + v;
+      float val = acc[t][v] + bias[co];
+      if (RELU) {
+        val = val > 0.f ? val : 0.f;
+        hout[(size_t)p * COUT + co] = to_bf16(val);
+      } else {
+        fout[(size_t)p * COUT + co] = val;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// density change from the net output, loss partial sums and dL/d(divergence)
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum(double v, double *lds) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); q++) s += lds[q];
+  return s; // in thread 0
+}
+
+__global__ __launch_bounds__(LB) void k_drho(Mesh m, const float *__restrict__ o, double sF,
+                                             const double *__restrict__ target, double sigma,
+                                             double *__restrict__ drho, double *__restrict__ gD,
+                                             double *__restrict__ lpart) {
+#pragma clang fp contract(off)
+  __shared__ double red[LB / 64];
+  const int nx = m.nx, ny = m.ny, npix = nx * ny;
+  const int p = blockIdx.x * LB + threadIdx.x;
+  double e2 = 0.0;
+  if (p < npix) {
+    const int j = p / nx, i = p - j * nx;
+    const int pr = j * nx + (i + 1 == nx ? 0 : i + 1), pu = p + nx;
+    const double fx0 = sF * (double)o[2 * p], fx1 = sF * (double)o[2 * pr];
+    const double fy0 = j == 0 ? 0.0 : sF * (double)o[2 * p + 1];
+    const double fy1 = j + 1 == ny ? 0.0 : sF * (double)o[2 * pu + 1];
+    const double div = (fx1 - fx0) + (fy1 - fy0);
+    const double iv = m.g.invVj(j + m.j0);
+    const double d = (-iv) * div;
+    drho[p] = d;
+    if (target) {
+      const double t = target[p];
+      const double e = (d - t) / sigma;
+      e2 = e * e;
+      const double g = 2.0 * (d - t) / ((double)npix * sigma * sigma);
+      gD[p] = (-iv) * g;
+    }
+  }
+  if (!target) return;
+  const double s = block_sum(e2, red);
+  if (threadIdx.x == 0) lpart[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(const double *__restrict__ lpart, int n, int npix,
+                                                    double *__restrict__ loss) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) s += lpart[q];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) *loss = s / (double)npix;
+}
+
+// dL/d(net output) through the adjoint of the divergence; 4 channels (the
+// last two zero) so that the input-gradient GEMM takes them in groups of 4
+__global__ __launch_bounds__(LB) void k_flux_grad(int nx, int ny, const double *__restrict__ gD, double sF,
+                                                  unsigned short *__restrict__ g3) {
+#pragma clang fp contract(off)
+  const int p = blockIdx.x * LB + threadIdx.x;
+  if (p >= nx * ny) return;
+  const int j = p / nx, i = p - j * nx;
+  const double gx = gD[j * nx + (i == 0 ? nx - 1 : i - 1)] - gD[p];
+  const double gy = j == 0 ? 0.0 : gD[p - nx] - gD[p];
+  uint2 v;
+  v.x = (unsigned)to_bf16((float)(sF * gx)) | ((unsigned)to_bf16((float)(sF * gy)) << 16);
+  v.y = 0u;
+  *reinterpret_cast<uint2 *>(g3 + (size_t)p * 4) = v;
+}
+
+// ---------------------------------------------------------------------------
+// input gradient: gin[p][ci] = [h[p][ci] > 0] sum_{tap, co} g[dst(p, tap)][co]
+// Wt[ci][tap GC + co]; GC = the gradient's channel count (a multiple of 4)
+// ---------------------------------------------------------------------------
+template <int CIN, int GC>
+__global__ __launch_bounds__(256) void k_conv_bwd_data(int nx, int ny, const unsigned short *__restrict__ g,
+                                                       const unsigned short *__restrict__ Wt,
+                                                       const unsigned short *__restrict__ h,
+                                                       unsigned short *__restrict__ gin) {
+  constexpr int K = 9 * GC, KP = (K + 15) / 16 * 16, NT = CIN / 16;
+  const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
+  const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  const int pa = p0 + m;
+  const int ya = pa / nx, xa = pa - ya * nx;
+  f4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; t++) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int s = 0; s < KP / 16; s++) {
+    const int k0 = 16 * s + 4 * kq;
+    bf4 a = zero4();
+    if (k0 < K) {
+      const int tap = k0 / GC, co = k0 - tap * GC;
+      const int q = tap_dst(ya, xa, tap / 3, tap % 3, ny, nx);
+      if (q >= 0) a = ld4(g + (size_t)q * GC + co);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+      const bf4 b = ld4(Wt + (size_t)(16 * t + m) * KP + k0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; t++) {
+    const int ci = 16 * t + m;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const size_t idx = (size_t)(p0 + 4 * kq + v) * CIN + ci;
+      const float val = from_bf16(h[idx]) > 0.f ? acc[t][v] : 0.f;
+      gin[idx] = to_bf16(val);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// weight gradient partial sums over a chunk of PC pixels, one wave per
+// (chunk, group of NG column tiles); bias gradient partials alongside
+// ---------------------------------------------------------------------------
+constexpr int PC = LFC_CHUNK;
+
+template <int CIN, int COUT, int GC, int NG>
+__global__ __launch_bounds__(256) void k_conv_bwd_w(int nx, int ny, const unsigned short *__restrict__ g,
+                                                    const unsigned short *__restrict__ act,
+                                                    float *__restrict__ part, float *__restrict__ dbpart) {
+  constexpr int K = 9 * CIN, KP = (K + 15) / 16 * 16, NTW = KP / 16, TPG = (NTW + NG - 1) / NG;
+  constexpr int MT = (COUT + 15) / 16; // row tiles of output channels
+  const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int chunk = wv / NG, grp = wv - chunk * NG;
+  const int nchunk = nx * ny / PC;
+  if (chunk >= nchunk) return;
+  f4 acc[MT][TPG];
+#pragma unroll
+  for (int r = 0; r < MT; r++)
+#pragma unroll
+    for (int t = 0; t < TPG; t++) acc[r][t] = f4{0.f, 0.f, 0.f, 0.f};
+  float db[MT];
+#pragma unroll
+  for (int r = 0; r < MT; r++) db[r] = 0.f;
+  for (int s = 0; s < PC / 16; s++) {
+    const int pb = chunk * PC + 16 * s + 4 * kq; // the lane's four pixels pb .. pb + 3
+    bf4 a[MT];
+#pragma unroll
+    for (int r = 0; r < MT; r++) {
+      a[r] = zero4();
+      const int co = 16 * r + m;
+      if (co < COUT) {
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const unsigned short x = g[(size_t)(pb + v) * GC + co];
+          a[r][v] = (short)x;
+          db[r] += from_bf16(x);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TPG; t++) {
+      const int nt = grp * TPG + t;
+      const int kk = 16 * nt + m;
+      bf4 b = zero4();
+      if (nt < NTW && kk < K) {
+        const int tap = kk / CIN, ci = kk - tap * CIN;
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int p = pb + v, y = p / nx, x = p - y * nx;
+          const int q = tap_src(y, x, tap / 3, tap % 3, ny, nx);
+          b[v] = q >= 0 ? (short)act[(size_t)q * CIN + ci] : (short)0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < MT; r++) acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r], b, acc[r][t], 0, 0, 0);
+    }
+  }
+  // result: lane holds column kk = 16 nt + m and rows co = 16 r + 4 kq + v
+#pragma unroll
+  for (int t = 0; t < TPG; t++) {
+    const int nt = grp * TPG + t;
+    const int kk = 16 * nt + m;
+    if (nt >= NTW || kk >= K) continue;
+#pragma unroll
+    for (int r = 0; r < MT; r++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int co = 16 * r + 4 * kq + v;
+        if (co < COUT) part[((size_t)chunk * COUT + co) * K + kk] = acc[r][t][v];
+      }
+  }
+  // bias: lanes m, m + 16, m + 32, m + 48 summed pixels of channel 16 r + m
+#pragma unroll
+  for (int r = 0; r < MT; r++) {
+    float d = db[r];
+    d += __shfl_xor(d, 16, 64);
+    d += __shfl_xor(d, 32, 64);
+    const int co = 16 * r + m;
+    if (grp == 0 && kq == 0 && co < COUT) dbpart[(size_t)chunk * COUT + co] = d;
+  }
+}
+
+// grad[W] = sum over chunks of the partials, grad[b] likewise (fixed order)
+__global__ __launch_bounds__(LB) void k_reduce_w(int nchunk, int cout, int K, const float *__restrict__ part,
+                                                 const float *__restrict__ dbpart, float *__restrict__ gW,
+                                                 float *__restrict__ gb) {
+  const int e = blockIdx.x * LB + threadIdx.x;
+  const int nw = cout * K;
+  if (e < nw) {
+    float s = 0.f;
+    for (int c = 0; c < nchunk; c++) s += part[(size_t)c * nw + e];
+    gW[e] = s;
+  } else if (e < nw + cout) {
+    const int co = e - nw;
+    float s = 0.f;
+    for (int c = 0; c < nchunk; c++) s += dbpart[(size_t)c * cout + co];
+    gb[co] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adam on the FP32 master parameters, and the bfloat16 copies of the weights
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(LB) void k_adam(int n, float *__restrict__ w, float *__restrict__ mo,
+                                             float *__restrict__ ve, const float *__restrict__ g, float lr,
+                                             float b1, float b2, float c1, float c2, float eps) {
+  const int e = blockIdx.x * LB + threadIdx.x;
+  if (e >= n) return;
+  const float ge = g[e];
+  const float mn = b1 * mo[e] + (1.f - b1) * ge;
+  const float vn = b2 * ve[e] + (1.f - b2) * ge * ge;
+  mo[e] = mn;
+  ve[e] = vn;
+  w[e] = w[e] - lr * (mn / c1) / (sqrtf(vn / c2) + eps);
+}
+
+// Wb_l [16 NT][KP] for the forward GEMMs; Wt2 [32][288] and Wt3 [32][48]
+// (tap-major over the 4-padded output channels) for the input gradients
+__global__ __launch_bounds__(LB) void k_pack(const float *__restrict__ w, LfcWeights b) {
+  const int e = blockIdx.x * LB + threadIdx.x;
+  const float *W1 = w + LFC_OFF_W1, *W2 = w + LFC_OFF_W2, *W3 = w + LFC_OFF_W3;
+  // forward copies
+  if (e < 32 * 48) {
+    const int co = e / 48, k = e - co * 48;
+    b.wb1[e] = k < 36 ? to_bf16(W1[co * 36 + k]) : (unsigned short)0;
+  }
+  if (e < 32 * 288) {
+    b.wb2[e] = to_bf16(W2[e]);
+    const int ci = e / 288, k = e - ci * 288, tap = k / 32, co = k - tap * 32;
+    b.wt2[e] = to_bf16(W2[co * 288 + tap * 32 + ci]);
+  }
+  if (e < 16 * 288) {
+    const int co = e / 288, k = e - co * 288;
+    b.wb3[e] = co < 2 ? to_bf16(W3[co * 288 + k]) : (unsigned short)0;
+  }
+  if (e < 32 * 48) {
+    const int ci = e / 48, k = e - ci * 48, tap = k / 4, co = k - tap * 4;
+    b.wt3[e] = (k < 36 && co < 2) ? to_bf16(W3[co * 288 + tap * 32 + ci]) : (unsigned short)0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// guard and conservative update; restriction
+// ---------------------------------------------------------------------------
+__global__ void k_flag_clear(int *flag) { *flag = 0; }
+
+__global__ __launch_bounds__(LB) void k_guard(Mesh m, const double *__restrict__ rho,
+                                              const double *__restrict__ d, double guard, int *flag) {
+#pragma clang fp contract(off)
+  const int p = blockIdx.x * LB + threadIdx.x;
+  if (p >= m.nx * m.ny) return;
+  const int j = p / m.nx, i = p - j * m.nx;
+  const double r = rho[m.o32(i, j + m.j0, 0)], dd = d[p];
+  if (!(r + dd > 0.0) || !(fabs(dd) <= guard * r)) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(LB) void k_commit(Mesh m, double *__restrict__ rho, const double *__restrict__ d,
+                                               const int *__restrict__ flag) {
+  const int p = blockIdx.x * LB + threadIdx.x;
+  if (p >= m.nx * m.ny || *flag) return;
+  const int j = p / m.nx, i = p - j * m.nx;
+  const unsigned c = m.o32(i, j + m.j0, 0);
+  rho[c] = rho[c] + d[p];
+}
+
+__global__ __launch_bounds__(LB) void k_restrict(Mesh mf, Mesh mc, const double *__restrict__ rf,
+                                                 const double *__restrict__ vxf, const double *__restrict__ vyf,
+                                                 double *__restrict__ rc, double *__restrict__ vxc,
+                                                 double *__restrict__ vyc) {
+#pragma clang fp contract(off)
+  constexpr int R = 4;
+  const int p = blockIdx.x * LB + threadIdx.x;
+  if (p >= mc.nx * mc.ny) return;
+  const int J = p / mc.nx, I = p - J * mc.nx;
+  double mass = 0.0, wsum = 0.0, vx = 0.0, drs = 0.0, vy = 0.0;
+  for (int b = 0; b < R; b++) {
+    const int jf = R * J + b + mf.j0;
+    const double ya = mf.g.ymin(jf), yb = mf.g.ymin(jf + 1);
+    const double w = 0.5 * (yb * yb - ya * ya), dr = yb - ya;
+    double s = 0.0;
+    for (int a = 0; a < R; a++) s += rf[mf.o32(R * I + a, jf, 0)] * w;
+    mass += s;
+    wsum += w;
+    vx += vxf[mf.o32(R * I, jf, 0)] * dr;
+    drs += dr;
+  }
+  for (int a = 0; a < R; a++) vy += vyf[mf.o32(R * I + a, R * J + mf.j0, 0)];
+  const unsigned c = mc.o32(I, J + mc.j0, 0);
+  rc[c] = mass / (wsum * R);
+  vxc[c] = vx / drs;
+  vyc[c] = vy / R;
+}
+
+inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+} // namespace
+
+void lfc_forward(Launch &L, const Mesh &m, const double *rho, const double *vx, const double *vy,
+                 const LfcScales &sc, const LfcBufs &B) {
+  const int npix = m.nx * m.ny;
+  k_features<<<nblk(npix, LB), LB, 0, L.s>>>(m, rho, vx, vy, sc, B.f);
+  const unsigned nb = (unsigned)(npix / 64);
+  k_conv_fwd<4, 32, true><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.f, B.wt.wb1, B.w + LFC_OFF_B1, B.h1, nullptr);
+  k_conv_fwd<32, 32, true><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h1, B.wt.wb2, B.w + LFC_OFF_B2, B.h2, nullptr);
+  k_conv_fwd<32, 2, false><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h2, B.wt.wb3, B.w + LFC_OFF_B3, nullptr, B.o);
+}
+
+void lfc_drho(Launch &L, const Mesh &m, const LfcBufs &B, double sF, const double *target, double sigma) {
+  const int npix = m.nx * m.ny;
+  const unsigned nb = nblk(npix, LB);
+  k_drho<<<nb, LB, 0, L.s>>>(m, B.o, sF, target, sigma, B.drho, B.gD, B.lpart);
+  if (target) k_loss_final<<<1, 256, 0, L.s>>>(B.lpart, (int)nb, npix, B.loss);
+}
+
+void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF) {
+  const int nx = m.nx, ny = m.ny, npix = nx * ny, nchunk = npix / PC;
+  const unsigned nb = (unsigned)(npix / 64);
+  k_flux_grad<<<nblk(npix, LB), LB, 0, L.s>>>(nx, ny, B.gD, sF, B.g3);
+  // layer 3: weights from g3 and h2, then the gradient into h2
+  k_conv_bwd_w<32, 2, 4, 6><<<nblk((long)nchunk * 6, 4), 256, 0, L.s>>>(nx, ny, B.g3, B.h2, B.part, B.dbpart);
+  k_reduce_w<<<nblk(2 * 288 + 2, LB), LB, 0, L.s>>>(nchunk, 2, 288, B.part, B.dbpart, B.grad + LFC_OFF_W3,
+                                                     B.grad + LFC_OFF_B3);
+  k_conv_bwd_data<32, 4><<<nb, 256, 0, L.s>>>(nx, ny, B.g3, B.wt.wt3, B.h2, B.g2);
+  // layer 2
+  k_conv_bwd_w<32, 32, 32, 6><<<nblk((long)nchunk * 6, 4), 256, 0, L.s>>>(nx, ny, B.g2, B.h1, B.part, B.dbpart);
+  k_reduce_w<<<nblk(32 * 288 + 32, LB), LB, 0, L.s>>>(nchunk, 32, 288, B.part, B.dbpart, B.grad + LFC_OFF_W2,
+                                                       B.grad + LFC_OFF_B2);
+  k_conv_bwd_data<32, 32><<<nb, 256, 0, L.s>>>(nx, ny, B.g2, B.wt.wt2, B.h1, B.g1);
+  // layer 1 (no gradient into the features)
+  k_conv_bwd_w<4, 32, 32, 1><<<nblk(nchunk, 4), 256, 0, L.s>>>(nx, ny, B.g1, B.f, B.part, B.dbpart);
+  k_reduce_w<<<nblk(32 * 36 + 32, LB), LB, 0, L.s>>>(nchunk, 32, 36, B.part, B.dbpart, B.grad + LFC_OFF_W1,
+                                                      B.grad + LFC_OFF_B1);
+}
+
+void lfc_adam(Launch &L, const LfcBufs &B, float lr, float c1, float c2) {
+  k_adam<<<nblk(LFC_NPARAM, LB), LB, 0, L.s>>>(LFC_NPARAM, B.w, B.mo, B.ve, B.grad, lr, 0.9f, 0.999f, c1, c2,
+                                               1e-8f);
+}
+
+void lfc_pack(Launch &L, const LfcBufs &B) { k_pack<<<nblk(32 * 288, LB), LB, 0, L.s>>>(B.w, B.wt); }
+
+void lfc_apply(Launch &L, const Mesh &m, const LfcBufs &B, double *rho, double guard, int *flag) {
+  const int npix = m.nx * m.ny;
+  k_flag_clear<<<1, 1, 0, L.s>>>(flag);
+  k_guard<<<nblk(npix, LB), LB, 0, L.s>>>(m, rho, B.drho, guard, flag);
+  k_commit<<<nblk(npix, LB), LB, 0, L.s>>>(m, rho, B.drho, flag);
+}
+
+void lfc_restrict(Launch &L, const Mesh &mf, const double *rf, const double *vxf, const double *vyf, const Mesh &mc,
+                  double *rc, double *vxc, double *vyc) {
+  k_restrict<<<nblk((long)mc.nx * mc.ny, LB), LB, 0, L.s>>>(mf, mc, rf, vxf, vyf, rc, vxc, vyc);
+}
+
+} // namespace fargo

@@ -79,10 +79,35 @@ _lib.fargo_batch_tune.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int, C.P
 _lib.fargo_batch_destroy.argtypes = [C.c_void_p]
 _lib.fargo_batch_destroy.restype = None
 
+
+class fargo_lfc_params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("rho_s", "u_s", "r_mid", "r_span", "flux_scale", "sigma", "guard")]
+
+
+class fargo_lfc_views(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("f", "h1", "h2", "o", "drho", "g3", "g2", "g1")]
+
+
+LFC_NPARAM = 11010
+_lib.fargo_lfc_create.argtypes = [C.c_void_p, C.POINTER(fargo_lfc_params), C.POINTER(C.c_void_p)]
+_lib.fargo_lfc_destroy.argtypes = [C.c_void_p]
+_lib.fargo_lfc_destroy.restype = None
+for _n in ("fargo_lfc_set_params", "fargo_lfc_get_params", "fargo_lfc_get_grad"):
+    getattr(_lib, _n).argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int32]
+_lib.fargo_lfc_forward.argtypes = [C.c_void_p, _S, C.c_void_p]
+_lib.fargo_lfc_train_step.argtypes = [C.c_void_p, _S, C.c_void_p, C.c_double, C.c_void_p]
+_lib.fargo_lfc_apply.argtypes = [C.c_void_p, _S, C.c_void_p]
+_lib.fargo_lfc_result.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]
+_lib.fargo_lfc_get_views.argtypes = [C.c_void_p, C.POINTER(fargo_lfc_views)]
+_lib.fargo_lfc_restrict.argtypes = [C.c_void_p, _S, C.c_void_p, _S, C.c_void_p]
+
 EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_workspace_bytes", "fargo_init",
             "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
             "fargo_conserved_sums", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
-            "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_destroy")
+            "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_destroy",
+            "fargo_lfc_create", "fargo_lfc_destroy", "fargo_lfc_set_params", "fargo_lfc_get_params",
+            "fargo_lfc_get_grad", "fargo_lfc_forward", "fargo_lfc_train_step", "fargo_lfc_apply",
+            "fargo_lfc_result", "fargo_lfc_get_views", "fargo_lfc_restrict")
 
 
 class FargoError(RuntimeError):
@@ -284,3 +309,89 @@ class Batch:
                "fargo_batch_tune")
         return int(best[0]), int(best[1])
 
+
+class LFC:
+    """A learned flux correction bound to a 2D cylindrical FP64 Solver
+    (fargo_lfc_*).  The solver must outlive it."""
+
+    def __init__(self, solver: Solver, rho_s: float, u_s: float, r_mid: float, r_span: float,
+                 flux_scale: float, sigma: float, guard: float = 0.5):
+        self.solver = solver
+        self._p = fargo_lfc_params(rho_s, u_s, r_mid, r_span, flux_scale, sigma, guard)
+        self._l = C.c_void_p()
+        _check(_lib.fargo_lfc_create(solver._ctx, C.byref(self._p), C.byref(self._l)), "fargo_lfc_create")
+        self.nx, self.ny = solver.params["nx"], solver.params["ny"]
+
+    def __del__(self):
+        l = getattr(self, "_l", None)
+        if l is not None and l.value:
+            _lib.fargo_lfc_destroy(l)
+            self._l = None
+
+    def _vec(self, name: str, arr=None) -> np.ndarray:
+        a = np.zeros(LFC_NPARAM, dtype=np.float32) if arr is None else np.ascontiguousarray(arr, dtype=np.float32)
+        assert a.size == LFC_NPARAM
+        _check(getattr(_lib, name)(self._l, a.ctypes.data_as(C.POINTER(C.c_float)), LFC_NPARAM), name)
+        return a
+
+    def set_params(self, flat: np.ndarray):
+        self._vec("fargo_lfc_set_params", flat)
+
+    def get_params(self) -> np.ndarray:
+        return self._vec("fargo_lfc_get_params")
+
+    def get_grad(self) -> np.ndarray:
+        return self._vec("fargo_lfc_get_grad")
+
+    def forward(self, stream=None):
+        _check(_lib.fargo_lfc_forward(self._l, C.byref(self.solver._st), _stream(stream)), "fargo_lfc_forward")
+
+    def train_step(self, target: torch.Tensor, lr: float, stream=None):
+        assert target.dtype == torch.float64 and target.is_contiguous() and target.numel() == self.nx * self.ny
+        _check(_lib.fargo_lfc_train_step(self._l, C.byref(self.solver._st), C.c_void_p(target.data_ptr()),
+                                         float(lr), _stream(stream)), "fargo_lfc_train_step")
+
+    def apply(self, stream=None):
+        _check(_lib.fargo_lfc_apply(self._l, C.byref(self.solver._st), _stream(stream)), "fargo_lfc_apply")
+
+    def result(self, stream=None):
+        loss, skipped = C.c_double(), C.c_int32()
+        _check(_lib.fargo_lfc_result(self._l, C.byref(loss), C.byref(skipped), _stream(stream)), "fargo_lfc_result")
+        return loss.value, bool(skipped.value)
+
+    def views(self) -> Dict[str, torch.Tensor]:
+        """Device buffers of the last forward or training step as tensors
+        (bfloat16 buffers as torch.bfloat16), shaped (ny, nx, channels)."""
+        v = fargo_lfc_views()
+        _check(_lib.fargo_lfc_get_views(self._l, C.byref(v)), "fargo_lfc_get_views")
+        n = self.nx * self.ny
+        dev = self.solver.device
+
+        def wrap(ptr, count, dtype):
+            # alias the library's buffer (CUDA array interface), then copy it
+            code = {torch.bfloat16: "<i2", torch.float32: "<f4", torch.float64: "<f8"}[dtype]
+            t = torch.as_tensor(_DevBuf(ptr, count, code), device=dev)
+            t = t.clone()
+            return t.view(torch.bfloat16) if dtype == torch.bfloat16 else t
+
+        out = {}
+        for name, ch, dt in (("f", 4, torch.bfloat16), ("h1", 32, torch.bfloat16), ("h2", 32, torch.bfloat16),
+                             ("o", 2, torch.float32), ("drho", 1, torch.float64), ("g3", 4, torch.bfloat16),
+                             ("g2", 32, torch.bfloat16), ("g1", 32, torch.bfloat16)):
+            t = wrap(getattr(v, name), n * ch, dt)
+            out[name] = t.view(self.ny, self.nx, ch) if ch > 1 else t.view(self.ny, self.nx)
+        return out
+
+
+class _DevBuf:
+    """A device buffer of the library seen through the CUDA array interface."""
+
+    def __init__(self, ptr: int, count: int, typestr: str):
+        self.__cuda_array_interface__ = {"shape": (count,), "typestr": typestr, "data": (int(ptr), False),
+                                         "version": 2, "strides": None}
+
+
+def lfc_restrict(fine: Solver, coarse: Solver, stream=None):
+    """4 x 4 conservative restriction of fine's active zones into coarse."""
+    _check(_lib.fargo_lfc_restrict(fine._ctx, C.byref(fine._st), coarse._ctx, C.byref(coarse._st), _stream(stream)),
+           "fargo_lfc_restrict")

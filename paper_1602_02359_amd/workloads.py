@@ -276,6 +276,34 @@ def disk3d_cyl_planet(nx=2048, ny=768, nz=96, rin=0.4, rout=2.5, h=0.05, zmax=0.
     return Problem("disk3d_cyl_planet", p, dict(rho=rho, vx=vx, vy=vy, vz=vz, e=None, cs=cs, pot=pot), steps)
 
 
+def disk2d_planet(nx=768, ny=256, rin=0.4, rout=2.5, h=0.05, q=1e-3, eps_h=0.6, omega=1.0, seed=4000,
+                  noise=1e-3, fargo=True, steps=10) -> Problem:
+    """2D (phi, r) locally isothermal disk with a fixed planet (q at r = 1) in
+    the frame co-rotating with it: Sigma = r**-0.5, c_s = h r**-0.5, the
+    planet potential of the 3D planet disk at z = 0 (softening eps_h h), and
+    v_phi**2 = (1 - 1.5 h**2)/r in the inertial frame.  Radial faces are
+    log-spaced, so the faces of an (nx, ny) mesh are every 4th face of the
+    (4 nx, 4 ny) mesh: the coarse and fine meshes of the learned flux
+    correction.  The initial state ignores the planet."""
+    p = default_params(
+        geometry="cyl", nx=nx, ny=ny, nz=1, xmin=0.0, xmax=2.0 * math.pi,
+        ymin=log_faces(rin, rout, ny), zmin=np.array([0.0, 1.0]),
+        eos="iso", omega=omega, fargo=fargo,
+        bc=("fixed", "fixed", "fixed", "fixed"),
+    )
+    shape = (1, ny + 2 * NGH, nx)
+    zc, r, xf, xc = _grid(p)
+    rho = _full(shape, r ** -0.5)
+    cs = _full(shape, h * r ** -0.5)
+    pot = _full(shape, planet_potential(r, 0.0, xc, q, eps=eps_h * h))
+    vx = _full(shape, np.sqrt((1.0 - 1.5 * h * h) / r) - omega * r)
+    vy = np.zeros(shape)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if noise:
+        _noise(rng, rho, p, noise)
+    return Problem("disk2d_planet", p, dict(rho=rho, vx=vx, vy=vy, vz=None, e=None, cs=cs, pot=pot), steps)
+
+
 # ----------------------------------------------------------------------------
 # small Cartesian test problems
 # ----------------------------------------------------------------------------
@@ -468,6 +496,9 @@ CONFIGS = {
     "sph3d": lambda **kw: disk3d_sph(**kw),
     # 3D cylindrical isothermal disk with planet, 2048 x 768 x 96, 100 steps
     "cyl3d_planet": lambda **kw: disk3d_cyl_planet(**kw),
+    # learned flux correction: coarse 768 x 256 and fine 3072 x 1024 planet disks
+    "lfc_coarse": lambda **kw: disk2d_planet(**kw),
+    "lfc_fine": lambda **kw: disk2d_planet(**dict(dict(nx=3072, ny=1024), **kw)),
 }
 
 

@@ -1,0 +1,235 @@
+"""Learned flux correction through the C ABI (fargo_lfc_*), against the
+numpy oracle (oracle/lfc.py) on the same weights and inputs.
+
+Bars.  The features are formed in FP64 and rounded the same way on both
+sides: bit-exact.  Every product takes bfloat16 operands; the GPU sums in
+FP32 (the oracle exactly), so a stored activation can land one bfloat16 unit
+(2^-8 relative) away from the oracle's where the FP32 sum sits next to a
+rounding boundary.  That happens for about one value in 10^4 (the FP32 sum
+error, ~1e-7 relative, over the bfloat16 spacing); spread over N values it
+contributes 2^-8 sqrt(flips / N) normwise, so a normwise bar of 2e-3 holds
+with a wide margin while a wrong index, tap or sign gives O(1).  The density
+change is checked against the oracle applied to the GPU's own net output
+(FP64 on both sides, 1e-14), and the Adam step against the oracle applied to
+the GPU's own gradient (FP32 against FP64, 1e-5).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lfc as L
+from paper_1602_02359_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+NG = W.NGH
+TOL_BF16 = 2e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _nerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _flat(P):
+    return np.concatenate([np.asarray(P[k], dtype=np.float32).ravel()
+                           for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def _unflat(v):
+    P, o = {}, 0
+    for n, (ci, co) in enumerate(L.LAYERS, 1):
+        w = 9 * ci * co
+        P["W%d" % n] = v[o:o + w].reshape(co, 3, 3, ci).astype(np.float64)
+        o += w
+        P["b%d" % n] = v[o:o + co].astype(np.float64)
+        o += co
+    return P
+
+
+def _geometry(p):
+    y = p["ymin"]
+    a, b = y[NG:NG + p["ny"]], y[NG + 1:NG + p["ny"] + 1]
+    dx = (p["xmax"] - p["xmin"]) / p["nx"]
+    rc = 0.5 * (a + b)
+    invV = 2.0 / ((b * b - a * a) * dx)
+    return rc, invV
+
+
+def _setup(nx=64, ny=16, seed=11, sF=None, guard=0.5):
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    prob = W.disk2d_planet(nx=nx, ny=ny, seed=4000 + seed, noise=0.05)
+    rng = np.random.default_rng(seed)
+    act = (0, slice(NG, NG + ny), slice(None))
+    prob.fields["vy"][act] = 0.02 * rng.standard_normal((ny, nx))
+    prob.fields["vx"][act] += 0.02 * rng.standard_normal((ny, nx))
+    s = F.Solver(prob.params)
+    s.upload(prob.fields)
+    rc, invV = _geometry(prob.params)
+    scales = (1.0, 0.05, 1.45, 1.05)
+    sF = sF if sF is not None else 1e-4 / float(invV.mean())
+    sigma = 1e-3
+    net = F.LFC(s, *scales, flux_scale=sF, sigma=sigma, guard=guard)
+    P = L.init_params(rng)
+    for k in ("b1", "b2", "b3"):
+        P[k] = (0.05 * rng.standard_normal(P[k].shape)).astype(np.float32)
+    P["W3"] = (P["W3"] * 10.0).astype(np.float32)
+    net.set_params(_flat(P))
+    fields = {k: prob.fields[k][act].copy() for k in ("rho", "vx", "vy")}
+    target = 1e-3 * rng.standard_normal((ny, nx))
+    return dict(s=s, net=net, P=P, rc=rc, invV=invV, scales=scales, sF=sF, sigma=sigma, fields=fields,
+                target=target, torch=torch, prob=prob)
+
+
+def test_forward_matches_oracle():
+    c = _setup()
+    net, torch = c["net"], c["torch"]
+    _say("lfc forward 64 x 16")
+    net.forward()
+    v = net.views()
+    fx = c["fields"]
+    f = L.features(fx["rho"], fx["vx"], fx["vy"], c["rc"], c["scales"])
+    assert np.array_equal(v["f"].float().cpu().numpy().astype(np.float64), f)
+    A = L.forward(f, c["P"])
+    errs = {}
+    for k in ("h1", "h2", "o"):
+        errs[k] = _nerr(v[k].float().cpu().numpy(), A[k])
+    _say("  normwise errors", errs)
+    for k, e in errs.items():
+        assert e <= TOL_BF16, (k, e)
+    # the density change from the GPU's own output: FP64 on both sides
+    o_gpu = v["o"].double().cpu().numpy()
+    d_ref = L.drho(o_gpu, c["sF"], c["invV"])
+    d_gpu = v["drho"].cpu().numpy()
+    assert _nerr(d_gpu, d_ref) <= 1e-14
+    # and it conserves mass: sum V drho = 0
+    Vs = (1.0 / c["invV"])[:, None]
+    assert abs(np.sum(d_gpu * Vs)) <= 1e-13 * np.sum(np.abs(d_gpu * Vs))
+
+
+def test_train_step_gradient_loss_and_adam():
+    c = _setup(seed=12)
+    net, torch = c["net"], c["torch"]
+    _say("lfc train step 64 x 16")
+    t_dev = torch.from_numpy(c["target"]).cuda()
+    lr = 1e-3
+    net.train_step(t_dev, lr)
+    loss, _ = net.result()
+    v = net.views()
+    grad = net.get_grad()
+    newp = net.get_params()
+    fx = c["fields"]
+    f = L.features(fx["rho"], fx["vx"], fx["vy"], c["rc"], c["scales"])
+    A = L.forward(f, c["P"])
+    Pd = {k: np.asarray(x, dtype=np.float64) for k, x in c["P"].items()}
+    G = L.backward(A, Pd, c["target"], c["sF"], c["invV"], c["sigma"])
+    d_ref = L.drho(A["o"], c["sF"], c["invV"])
+    loss_ref = L.loss(d_ref, c["target"], c["sigma"])
+    _say("  loss", loss, loss_ref)
+    assert abs(loss - loss_ref) <= TOL_BF16 * loss_ref
+    Gg = _unflat(grad)
+    errs = {k: _nerr(Gg[k], G[k]) for k in G}
+    _say("  gradient normwise errors", errs)
+    for k, e in errs.items():
+        assert e <= 5 * TOL_BF16, (k, e)
+    # the layer gradients themselves
+    g3 = v["g3"].float().cpu().numpy()
+    assert np.all(g3[..., 2:] == 0.0)
+    # Adam on the GPU's own gradient: FP32 against FP64
+    M0 = {k: np.zeros_like(x) for k, x in Pd.items()}
+    Pn, _, _ = L.adam(Pd, Gg, M0, dict(M0), 1, lr)
+    Pg = _unflat(newp)
+    for k in Pn:
+        assert np.allclose(Pg[k], Pn[k], rtol=1e-5, atol=1e-3 * lr), k
+
+
+def test_training_reduces_the_loss():
+    """Adam on one fixed sample whose target the net can represent (the
+    density change of a second, randomly drawn net on the same state): the
+    loss falls well below its start."""
+    c = _setup(seed=13)
+    net, torch = c["net"], c["torch"]
+    fx = c["fields"]
+    f = L.features(fx["rho"], fx["vx"], fx["vy"], c["rc"], c["scales"])
+    teacher = L.init_params(np.random.default_rng(99))
+    teacher["W3"] = (teacher["W3"] * 10.0).astype(np.float32)
+    target = L.drho(L.forward(f, teacher)["o"], c["sF"], c["invV"])
+    t_dev = torch.from_numpy(np.ascontiguousarray(target)).cuda()
+    losses = []
+    for n in range(300):
+        net.train_step(t_dev, 3e-3)
+        if n % 50 == 0 or n == 299:
+            losses.append(net.result()[0])
+    _say("  losses", losses)
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_apply_conserves_mass_and_guard_rejects():
+    c = _setup(seed=14)
+    s, net = c["s"], c["net"]
+    rho0 = s.state["rho"][0, NG:NG + 16, :64].clone()
+    net.apply()
+    _, skipped = net.result()
+    assert not skipped
+    d = net.views()["drho"].cpu().numpy()
+    rho1 = s.state["rho"][0, NG:NG + 16, :64].cpu().numpy()
+    assert np.array_equal(rho1, rho0.cpu().numpy() + d)
+    V = (1.0 / c["invV"])[:, None]
+    m0 = np.sum(rho0.cpu().numpy() * V)
+    assert abs(np.sum(rho1 * V) - m0) <= 1e-13 * m0
+    # a huge flux scale makes the correction exceed the guard: no change
+    c2 = _setup(seed=14, sF=1e3, guard=0.5)
+    s2, net2 = c2["s"], c2["net"]
+    before = s2.state["rho"].clone()
+    net2.apply()
+    _, skipped = net2.result()
+    assert skipped
+    assert c2["torch"].equal(before, s2.state["rho"])
+
+
+def test_restriction_matches_oracle():
+    from paper_1602_02359_amd import fargo as F
+    fine = W.disk2d_planet(nx=256, ny=64, seed=4001, noise=0.05)
+    coarse = W.disk2d_planet(nx=64, ny=16, seed=4002)
+    rng = np.random.default_rng(21)
+    act = (0, slice(NG, NG + 64), slice(None))
+    fine.fields["vy"][act] = 0.01 * rng.standard_normal((64, 256))
+    fine.fields["vx"][act] += 0.01 * rng.standard_normal((64, 256))
+    sf, sc = F.Solver(fine.params), F.Solver(coarse.params)
+    sf.upload(fine.fields)
+    sc.upload(coarse.fields)
+    ghost_before = sc.state["rho"][0, :NG].clone()
+    F.lfc_restrict(sf, sc)
+    got = sc.download()
+    fa = {k: fine.fields[k][act] for k in ("rho", "vx", "vy")}
+    yf = fine.params["ymin"][NG:NG + 65]
+    rc, vxc, vyc = L.restrict(fa["rho"], fa["vx"], fa["vy"], yf)
+    ca = (0, slice(NG, NG + 16), slice(None))
+    assert _nerr(got["rho"][ca], rc) <= 1e-14
+    assert _nerr(got["vx"][ca], vxc) <= 1e-14
+    assert _nerr(got["vy"][ca], vyc) <= 1e-14
+    assert sc.state["rho"][0, :NG].equal(ghost_before)
+
+
+def test_unsupported_meshes_are_rejected():
+    from paper_1602_02359_amd import fargo as F
+    prob = W.disk2d_planet(nx=60, ny=16)  # nx not a multiple of 16
+    s = F.Solver(prob.params)
+    s.upload(prob.fields)
+    with pytest.raises(F.FargoError):
+        F.LFC(s, 1.0, 0.05, 1.45, 1.05, flux_scale=1.0, sigma=1e-3)
