@@ -315,6 +315,12 @@ int fargo_lfc_get_views(fargo_lfc *l, fargo_lfc_views *v);
    it.  Ghost zones of the coarse state are not written. */
 int fargo_lfc_restrict(const fargo_ctx *fine, const fargo_state *fs, const fargo_ctx *coarse, fargo_state *cs,
                        void *stream);
+/* Training target over the active zones of a 2D cylindrical FP64 context:
+   target[j nx + i] = ref.rho - plain.rho (device, double [ny][nx]), the
+   density change that takes the plain coarse step to the restricted fine
+   solution. */
+int fargo_lfc_target(const fargo_ctx *ctx, const fargo_state *ref, const fargo_state *plain, double *target,
+                     void *stream);
 
 #ifdef __cplusplus
 }

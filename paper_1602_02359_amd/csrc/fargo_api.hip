@@ -115,7 +115,7 @@ int check_params(const fargo_params *p) {
   if (p->visc != 0 && p->visc != 1) return FARGO_EINVAL;
   if (p->visc && (p->geometry != FARGO_CYLINDRICAL || p->nz != 1 || p->eos != FARGO_ISOTHERMAL))
     return FARGO_EUNSUPPORTED;
-  if (p->nx > 2048) return FARGO_EUNSUPPORTED; // ring kernel keeps a ring per workgroup in 64 KB of LDS
+  if (p->nx > 4096) return FARGO_EUNSUPPORTED; // the time-step kernel holds a ring in one workgroup
   {
     // kernels address fields with 32-bit element offsets
     size_t pitch = (size_t)(p->nx + 63) / 64 * 64;
@@ -1076,6 +1076,15 @@ int fargo_lfc_get_views(fargo_lfc *l, fargo_lfc_views *v) {
   v->g2 = l->B.g2;
   v->g1 = l->B.g1;
   return FARGO_OK;
+}
+
+int fargo_lfc_target(const fargo_ctx *ctx, const fargo_state *ref, const fargo_state *plain, double *target,
+                     void *stream) {
+  if (!ctx || !ref || !plain || !target || !ref->rho || !plain->rho) return FARGO_EINVAL;
+  if (ctx->p.geometry != FARGO_CYLINDRICAL || ctx->m.d3 || fp32(ctx)) return FARGO_EUNSUPPORTED;
+  Launch L{(hipStream_t)stream, nullptr};
+  lfc_target(L, ctx->m, (const double *)ref->rho, (const double *)plain->rho, target);
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
 
 int fargo_lfc_restrict(const fargo_ctx *fine, const fargo_state *fs, const fargo_ctx *coarse, fargo_state *cs,

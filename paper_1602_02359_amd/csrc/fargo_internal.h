@@ -304,5 +304,6 @@ void lfc_pack(Launch &L, const LfcBufs &B);
 void lfc_apply(Launch &L, const Mesh &m, const LfcBufs &B, double *rho, double guard, int *flag);
 void lfc_restrict(Launch &L, const Mesh &mf, const double *rf, const double *vxf, const double *vyf, const Mesh &mc,
                   double *rc, double *vxc, double *vyc);
+void lfc_target(Launch &L, const Mesh &m, const double *ref, const double *plain, double *t);
 
 } // namespace fargo

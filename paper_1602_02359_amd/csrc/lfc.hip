@@ -456,6 +456,17 @@ __global__ __launch_bounds__(LB) void k_restrict(Mesh mf, Mesh mc, const double 
   vyc[c] = vy / R;
 }
 
+// training target: the density change that takes the plain coarse step to
+// the restricted fine solution, over the active zones
+__global__ __launch_bounds__(LB) void k_target(Mesh m, const double *__restrict__ ref,
+                                               const double *__restrict__ plain, double *__restrict__ t) {
+  const int p = blockIdx.x * LB + threadIdx.x;
+  if (p >= m.nx * m.ny) return;
+  const int j = p / m.nx, i = p - j * m.nx;
+  const unsigned c = m.o32(i, j + m.j0, 0);
+  t[p] = ref[c] - plain[c];
+}
+
 inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 } // namespace
@@ -509,6 +520,10 @@ void lfc_apply(Launch &L, const Mesh &m, const LfcBufs &B, double *rho, double g
   k_flag_clear<<<1, 1, 0, L.s>>>(flag);
   k_guard<<<nblk(npix, LB), LB, 0, L.s>>>(m, rho, B.drho, guard, flag);
   k_commit<<<nblk(npix, LB), LB, 0, L.s>>>(m, rho, B.drho, flag);
+}
+
+void lfc_target(Launch &L, const Mesh &m, const double *ref, const double *plain, double *t) {
+  k_target<<<nblk((long)m.nx * m.ny, LB), LB, 0, L.s>>>(m, ref, plain, t);
 }
 
 void lfc_restrict(Launch &L, const Mesh &mf, const double *rf, const double *vxf, const double *vyf, const Mesh &mc,

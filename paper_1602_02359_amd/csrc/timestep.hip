@@ -61,8 +61,8 @@ __device__ inline double ring_bulk(const Mesh &m, const double (&v)[M], int tid,
 // Rings in logical order (k fastest), XCD-contiguous; M zones per thread.
 // The state may be stored in FP32 (R = float); the time step is always formed
 // in FP64 from the stored values.
-template <int M, typename R>
-__global__ __launch_bounds__(256) void k_cfl_ring(Mesh m, StateT<R> s, int with_cfl, double *__restrict__ v0,
+template <int M, typename R, int NB>
+__global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_cfl, double *__restrict__ v0,
                                                   double *__restrict__ ringrate, double *__restrict__ ringshear,
                                                   int *__restrict__ err) {
 #pragma clang fp contract(off)
@@ -231,10 +231,11 @@ __global__ __launch_bounds__(256) void k_split(Mesh m, const double *__restrict_
   xi[r] = D - rn;
 }
 
-template <int M, typename R>
+// NB threads per ring: 256 up to 2048 zones, 512 up to 4096
+template <int M, typename R, int NB = 256>
 void cfl_launch(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *rmin, double *rsh,
                 int *err) {
-  k_cfl_ring<M, R><<<m.nring, 256, (size_t)m.nx * sizeof(double), L.s>>>(m, s, with_cfl, v0, rmin, rsh, err);
+  k_cfl_ring<M, R, NB><<<m.nring, NB, (size_t)m.nx * sizeof(double), L.s>>>(m, s, with_cfl, v0, rmin, rsh, err);
 }
 
 } // namespace
@@ -249,7 +250,17 @@ template <typename R>
 void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringrate,
                 double *ringshear, int *err) {
   prof_begin(L, K_CFL);
-  switch ((m.nx + 255) / 256) { // zones per thread; nx <= 2048
+  if (m.nx > 2048) { // nx <= 4096: 512 threads, 5 to 8 zones each
+    switch ((m.nx + 511) / 512) {
+    case 5: cfl_launch<5, R, 512>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+    case 6: cfl_launch<6, R, 512>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+    case 7: cfl_launch<7, R, 512>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+    default: cfl_launch<8, R, 512>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
+    }
+    prof_end(L, K_CFL);
+    return;
+  }
+  switch ((m.nx + 255) / 256) { // zones per thread
   case 1: cfl_launch<1, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
   case 2: cfl_launch<2, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
   case 3: cfl_launch<3, R>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;

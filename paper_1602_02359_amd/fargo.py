@@ -100,6 +100,7 @@ _lib.fargo_lfc_apply.argtypes = [C.c_void_p, _S, C.c_void_p]
 _lib.fargo_lfc_result.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]
 _lib.fargo_lfc_get_views.argtypes = [C.c_void_p, C.POINTER(fargo_lfc_views)]
 _lib.fargo_lfc_restrict.argtypes = [C.c_void_p, _S, C.c_void_p, _S, C.c_void_p]
+_lib.fargo_lfc_target.argtypes = [C.c_void_p, _S, _S, C.c_void_p, C.c_void_p]
 
 EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_workspace_bytes", "fargo_init",
             "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
@@ -107,7 +108,7 @@ EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_worksp
             "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_destroy",
             "fargo_lfc_create", "fargo_lfc_destroy", "fargo_lfc_set_params", "fargo_lfc_get_params",
             "fargo_lfc_get_grad", "fargo_lfc_forward", "fargo_lfc_train_step", "fargo_lfc_apply",
-            "fargo_lfc_result", "fargo_lfc_get_views", "fargo_lfc_restrict")
+            "fargo_lfc_result", "fargo_lfc_get_views", "fargo_lfc_restrict", "fargo_lfc_target")
 
 
 class FargoError(RuntimeError):
@@ -395,3 +396,11 @@ def lfc_restrict(fine: Solver, coarse: Solver, stream=None):
     """4 x 4 conservative restriction of fine's active zones into coarse."""
     _check(_lib.fargo_lfc_restrict(fine._ctx, C.byref(fine._st), coarse._ctx, C.byref(coarse._st), _stream(stream)),
            "fargo_lfc_restrict")
+
+
+def lfc_target(ref: Solver, plain: Solver, out: torch.Tensor, stream=None):
+    """out[j, i] = ref.rho - plain.rho over the active zones (same mesh)."""
+    assert out.dtype == torch.float64 and out.is_contiguous()
+    assert out.numel() == ref.params["nx"] * ref.params["ny"]
+    _check(_lib.fargo_lfc_target(ref._ctx, C.byref(ref._st), C.byref(plain._st), C.c_void_p(out.data_ptr()),
+                                 _stream(stream)), "fargo_lfc_target")

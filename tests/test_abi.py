@@ -43,7 +43,7 @@ def test_layout_and_validation_without_gpu():
             F.fargo_layout(dict(pr.params, **bad))
         assert e.value.code == -1
     with pytest.raises(F.FargoError) as e:
-        F.fargo_layout(dict(pr.params, nx=4096))
+        F.fargo_layout(dict(pr.params, nx=4097))
     assert e.value.code == -6
     wsb = F.fargo_workspace_bytes(W.disk3d_sph().params)
     assert wsb > 16 * 1536 * 518 * 134 * 8

@@ -51,6 +51,8 @@ def _cases():
     yield "sod_y_nx1", lambda: W.sod("y", n=64)
     yield "sod_z", lambda: W.sod("z", n=40)
     yield "ring_2048", lambda: W.random_problem("cyl", nx=2048, ny=4, nz=1, eos="iso", seed=7, fargo=True)
+    # rings above 2048 zones: the time-step kernel's 512-thread form
+    yield "ring_3072", lambda: W.random_problem("cyl", nx=3072, ny=4, nz=1, eos="iso", seed=9, fargo=True)
 
 
 def _with(prob, **kw):
