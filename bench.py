@@ -227,6 +227,81 @@ def batch_variant(steps, warmup, tune=True):
     return out
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
+
+
+def lfc_variant(iters=600):
+    """The learned flux correction on the planet disks (coarse 768 x 256,
+    fine 3072 x 1024): 40 samples along one fine trajectory (after 200 fine
+    spin-up steps), 32 for training and 8 held out.  Adam steps are timed with
+    per-kernel HIP events; the held-out error of the corrected coarse step
+    (|drho - target| / |target|, 1 = the plain step) before and after."""
+    import torch
+    from paper_1602_02359_amd import learned as LN
+    t0 = time.perf_counter()
+    cp, samples = LN.make_samples(40, spinup=200)
+    torch.cuda.synchronize()
+    gen = time.perf_counter() - t0
+    sc = LN.scales(cp, samples)
+    tr = LN.Trainer(cp, sc)
+    train, held = samples[:32], samples[32:]
+    before = tr.evaluate(held)
+    tr.train(train, 20, 3e-3, every=20)
+    torch.cuda.synchronize()
+    tr.feed.fargo_profile_enable(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tr.train(train, iters, 3e-3, every=iters)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    tim = tr.feed.fargo_timings()
+    tr.feed.fargo_profile_enable(False)
+    tr.train(train, iters, 1e-3, every=iters)
+    after, after_train = tr.evaluate(held), tr.evaluate(train)
+    # one guarded correction on a held-out state
+    tr.load(held[0])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(50):
+        tr.net.apply()
+    torch.cuda.synchronize()
+    apply_ms = 1e3 * (time.perf_counter() - t2) / 50
+    npix = cp.params["nx"] * cp.params["ny"]
+    # algorithmic flops of a training step (unpadded GEMM dimensions)
+    fl = {"lfc_conv_fwd": 2.0 * npix * (36 * 32 + 288 * 32 + 288 * 2),
+          "lfc_conv_bwd_w": 2.0 * npix * (36 * 32 + 288 * 32 + 288 * 2),
+          "lfc_conv_bwd_data": 2.0 * npix * (18 * 32 + 288 * 32)}
+    kern = {}
+    for name, (cnt, tot) in tim.items():
+        e = {"launches": cnt, "avg_ms": tot / cnt, "ms_per_train_step": tot / iters}
+        if name in fl:
+            e["TFLOPs"] = fl[name] * iters / (tot * 1e-3) / 1e12
+        kern[name] = e
+    dom = max((k for k in kern if "TFLOPs" in kern[k]), key=lambda k: kern[k]["ms_per_train_step"])
+    out = {
+        "workload": "learned flux correction, planet disk: coarse 768x256 (196608 zones), fine 3072x1024, "
+                    "3 conv layers 4-32-32-2, bf16 MFMA",
+        "ms_per_train_step": 1e3 * el / iters,
+        "train_steps_per_s": iters / el,
+        "ms_per_apply": apply_ms,
+        "sample_generation_s": gen,
+        "heldout_relative_error": {"before": before["relative_error"], "after": after["relative_error"]},
+        "train_relative_error_after": after_train["relative_error"],
+        "train_steps": 20 + 2 * iters,
+        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kern.items()},
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(kern[dom]["TFLOPs"], 3),
+                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": kern[dom]["TFLOPs"] / MFMA_BF16_PEAK_TFLOPS, "traffic": None},
+    }
+    print("  lfc: %.3f ms per training step, %.3f ms per apply; held-out error %.3f -> %.3f; %s %.2f TFLOP/s" % (
+        out["ms_per_train_step"], apply_ms, before["relative_error"], after["relative_error"], dom,
+        kern[dom]["TFLOPs"]), file=sys.stderr, flush=True)
+    del tr, samples
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +311,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variant", action="store_true", help="skip the FP32-bulk and disk-batch variants")
     ap.add_argument("--no-batch", action="store_true", help="skip the disk-batch variant")
+    ap.add_argument("--no-lfc", action="store_true", help="skip the learned-flux-correction variant")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 GiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -352,6 +428,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_variant and not args.no_batch:
         variants["disk_batch"] = batch_variant(args.steps, args.warmup)
+    if not args.no_variant and not args.no_lfc:
+        variants["learned_flux_correction"] = lfc_variant()
 
     cpu = None
     if not args.no_cpu_baseline:

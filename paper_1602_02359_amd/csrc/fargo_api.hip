@@ -17,7 +17,9 @@ namespace fargo {
 
 const char *kernel_names[K_COUNT] = {"set_dt", "bc_faces", "bc_ghosts", "cfl",    "dt_final", "split",
                                      "source", "source_ghosts", "visc", "sweep_y", "sweep_z",  "ring_x",
-                                     "vel_yz", "shift",    "sums",      "sums_final"};
+                                     "vel_yz", "shift",    "sums",      "sums_final",
+                                     "lfc_features", "lfc_conv_fwd", "lfc_drho", "lfc_conv_bwd_w",
+                                     "lfc_conv_bwd_data", "lfc_reduce", "lfc_adam", "lfc_apply"};
 
 struct Prof {
   bool on = false;
@@ -1021,7 +1023,7 @@ int fargo_lfc_forward(fargo_lfc *l, const fargo_state *state, void *stream) {
   if (!l) return FARGO_EINVAL;
   int rc = check_state(l->ctx, state);
   if (rc) return rc;
-  Launch L{(hipStream_t)stream, nullptr};
+  Launch L{(hipStream_t)stream, &l->ctx->prof};
   const Mesh &m = l->ctx->m;
   lfc_forward(L, m, (const double *)state->rho, (const double *)state->vx, (const double *)state->vy, l->sc, l->B);
   lfc_drho(L, m, l->B, l->p.flux_scale, nullptr, l->p.sigma);
@@ -1032,7 +1034,7 @@ int fargo_lfc_train_step(fargo_lfc *l, const fargo_state *state, const double *t
   if (!l || !target || !(lr > 0.0) || !std::isfinite(lr)) return FARGO_EINVAL;
   int rc = check_state(l->ctx, state);
   if (rc) return rc;
-  Launch L{(hipStream_t)stream, nullptr};
+  Launch L{(hipStream_t)stream, &l->ctx->prof};
   const Mesh &m = l->ctx->m;
   lfc_forward(L, m, (const double *)state->rho, (const double *)state->vx, (const double *)state->vy, l->sc, l->B);
   lfc_drho(L, m, l->B, l->p.flux_scale, target, l->p.sigma);
@@ -1047,7 +1049,7 @@ int fargo_lfc_train_step(fargo_lfc *l, const fargo_state *state, const double *t
 int fargo_lfc_apply(fargo_lfc *l, fargo_state *state, void *stream) {
   int rc = fargo_lfc_forward(l, state, stream);
   if (rc) return rc;
-  Launch L{(hipStream_t)stream, nullptr};
+  Launch L{(hipStream_t)stream, &l->ctx->prof};
   lfc_apply(L, l->ctx->m, l->B, (double *)state->rho, l->p.guard, l->flag);
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }

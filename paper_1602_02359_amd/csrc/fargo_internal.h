@@ -209,6 +209,8 @@ void prof_end(Launch &L, int kid);
 enum KernelId {
   K_SET_DT = 0, K_BC_FACES, K_BC_GHOSTS, K_CFL, K_DT_FINAL, K_SPLIT, K_SRC, K_SRC_GHOSTS, K_VISC, K_SWEEP_Y,
   K_SWEEP_Z, K_RING_X, K_VEL, K_SHIFT, K_SUMS, K_SUMS_FINAL,
+  // learned flux correction
+  K_LFC_FEATURES, K_LFC_CONV_FWD, K_LFC_DRHO, K_LFC_BWD_W, K_LFC_BWD_DATA, K_LFC_REDUCE, K_LFC_ADAM, K_LFC_APPLY,
   K_COUNT
 };
 extern const char *kernel_names[K_COUNT];

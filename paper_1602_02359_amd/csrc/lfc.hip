@@ -286,8 +286,26 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(int nx, int ny, const unsign
   float db[MT];
 #pragma unroll
   for (int r = 0; r < MT; r++) db[r] = 0.f;
+  // the lane's weight column in each of its tiles: tap and input channel
+  int tty[TPG], ttx[TPG], tci[TPG];
+  bool tok[TPG];
+#pragma unroll
+  for (int t = 0; t < TPG; t++) {
+    const int nt = grp * TPG + t, kk = 16 * nt + m;
+    tok[t] = nt < NTW && kk < K;
+    const int tap = tok[t] ? kk / CIN : 0;
+    tci[t] = tok[t] ? kk - tap * CIN : 0;
+    tty[t] = tap / 3;
+    ttx[t] = tap % 3;
+  }
   for (int s = 0; s < PC / 16; s++) {
     const int pb = chunk * PC + 16 * s + 4 * kq; // the lane's four pixels pb .. pb + 3
+    int py[4], px[4];
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      py[v] = (pb + v) / nx;
+      px[v] = pb + v - py[v] * nx;
+    }
     bf4 a[MT];
 #pragma unroll
     for (int r = 0; r < MT; r++) {
@@ -304,16 +322,12 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(int nx, int ny, const unsign
     }
 #pragma unroll
     for (int t = 0; t < TPG; t++) {
-      const int nt = grp * TPG + t;
-      const int kk = 16 * nt + m;
       bf4 b = zero4();
-      if (nt < NTW && kk < K) {
-        const int tap = kk / CIN, ci = kk - tap * CIN;
+      if (tok[t]) {
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-          const int p = pb + v, y = p / nx, x = p - y * nx;
-          const int q = tap_src(y, x, tap / 3, tap % 3, ny, nx);
-          b[v] = q >= 0 ? (short)act[(size_t)q * CIN + ci] : (short)0;
+          const int q = tap_src(py[v], px[v], tty[t], ttx[t], ny, nx);
+          b[v] = q >= 0 ? (short)act[(size_t)q * CIN + tci[t]] : (short)0;
         }
       }
 #pragma unroll
@@ -345,21 +359,30 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(int nx, int ny, const unsign
   }
 }
 
-// grad[W] = sum over chunks of the partials, grad[b] likewise (fixed order)
-__global__ __launch_bounds__(LB) void k_reduce_w(int nchunk, int cout, int K, const float *__restrict__ part,
-                                                 const float *__restrict__ dbpart, float *__restrict__ gW,
-                                                 float *__restrict__ gb) {
-  const int e = blockIdx.x * LB + threadIdx.x;
+// grad[W] = sum over chunks of the partials, grad[b] likewise.  A block takes
+// RE consecutive entries; its RG thread groups sum interleaved subsets of the
+// chunks, and the group sums are added in a fixed order (deterministic).
+constexpr int RE = 16, RG = 16;
+__global__ __launch_bounds__(RE * RG) void k_reduce_w(int nchunk, int cout, int K, const float *__restrict__ part,
+                                                      const float *__restrict__ dbpart, float *__restrict__ gW,
+                                                      float *__restrict__ gb) {
+  __shared__ float red[RG][RE];
+  const int el = threadIdx.x % RE, g = threadIdx.x / RE;
+  const int e = blockIdx.x * RE + el;
   const int nw = cout * K;
+  float s = 0.f;
   if (e < nw) {
-    float s = 0.f;
-    for (int c = 0; c < nchunk; c++) s += part[(size_t)c * nw + e];
-    gW[e] = s;
+    for (int c = g; c < nchunk; c += RG) s += part[(size_t)c * nw + e];
   } else if (e < nw + cout) {
-    const int co = e - nw;
-    float s = 0.f;
-    for (int c = 0; c < nchunk; c++) s += dbpart[(size_t)c * cout + co];
-    gb[co] = s;
+    for (int c = g; c < nchunk; c += RG) s += dbpart[(size_t)c * cout + (e - nw)];
+  }
+  red[g][el] = s;
+  __syncthreads();
+  if (g == 0 && e < nw + cout) {
+    float t = 0.f;
+    for (int q = 0; q < RG; q++) t += red[q][el];
+    if (e < nw) gW[e] = t;
+    else gb[e - nw] = t;
   }
 }
 
@@ -474,52 +497,96 @@ inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 void lfc_forward(Launch &L, const Mesh &m, const double *rho, const double *vx, const double *vy,
                  const LfcScales &sc, const LfcBufs &B) {
   const int npix = m.nx * m.ny;
+  prof_begin(L, K_LFC_FEATURES);
   k_features<<<nblk(npix, LB), LB, 0, L.s>>>(m, rho, vx, vy, sc, B.f);
+  prof_end(L, K_LFC_FEATURES);
   const unsigned nb = (unsigned)(npix / 64);
+  prof_begin(L, K_LFC_CONV_FWD);
   k_conv_fwd<4, 32, true><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.f, B.wt.wb1, B.w + LFC_OFF_B1, B.h1, nullptr);
+  prof_end(L, K_LFC_CONV_FWD);
+  prof_begin(L, K_LFC_CONV_FWD);
   k_conv_fwd<32, 32, true><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h1, B.wt.wb2, B.w + LFC_OFF_B2, B.h2, nullptr);
+  prof_end(L, K_LFC_CONV_FWD);
+  prof_begin(L, K_LFC_CONV_FWD);
   k_conv_fwd<32, 2, false><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h2, B.wt.wb3, B.w + LFC_OFF_B3, nullptr, B.o);
+  prof_end(L, K_LFC_CONV_FWD);
 }
 
 void lfc_drho(Launch &L, const Mesh &m, const LfcBufs &B, double sF, const double *target, double sigma) {
   const int npix = m.nx * m.ny;
   const unsigned nb = nblk(npix, LB);
+  prof_begin(L, K_LFC_DRHO);
   k_drho<<<nb, LB, 0, L.s>>>(m, B.o, sF, target, sigma, B.drho, B.gD, B.lpart);
-  if (target) k_loss_final<<<1, 256, 0, L.s>>>(B.lpart, (int)nb, npix, B.loss);
+  prof_end(L, K_LFC_DRHO);
+  if (target) {
+    prof_begin(L, K_LFC_DRHO);
+    k_loss_final<<<1, 256, 0, L.s>>>(B.lpart, (int)nb, npix, B.loss);
+    prof_end(L, K_LFC_DRHO);
+  }
 }
 
 void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF) {
   const int nx = m.nx, ny = m.ny, npix = nx * ny, nchunk = npix / PC;
   const unsigned nb = (unsigned)(npix / 64);
+  prof_begin(L, K_LFC_DRHO);
   k_flux_grad<<<nblk(npix, LB), LB, 0, L.s>>>(nx, ny, B.gD, sF, B.g3);
+  prof_end(L, K_LFC_DRHO);
   // layer 3: weights from g3 and h2, then the gradient into h2
+  prof_begin(L, K_LFC_BWD_W);
   k_conv_bwd_w<32, 2, 4, 6><<<nblk((long)nchunk * 6, 4), 256, 0, L.s>>>(nx, ny, B.g3, B.h2, B.part, B.dbpart);
-  k_reduce_w<<<nblk(2 * 288 + 2, LB), LB, 0, L.s>>>(nchunk, 2, 288, B.part, B.dbpart, B.grad + LFC_OFF_W3,
+  prof_end(L, K_LFC_BWD_W);
+  prof_begin(L, K_LFC_REDUCE);
+  k_reduce_w<<<nblk(2 * 288 + 2, RE), RE * RG, 0, L.s>>>(nchunk, 2, 288, B.part, B.dbpart, B.grad + LFC_OFF_W3,
                                                      B.grad + LFC_OFF_B3);
+  prof_end(L, K_LFC_REDUCE);
+  prof_begin(L, K_LFC_BWD_DATA);
   k_conv_bwd_data<32, 4><<<nb, 256, 0, L.s>>>(nx, ny, B.g3, B.wt.wt3, B.h2, B.g2);
+  prof_end(L, K_LFC_BWD_DATA);
   // layer 2
+  prof_begin(L, K_LFC_BWD_W);
   k_conv_bwd_w<32, 32, 32, 6><<<nblk((long)nchunk * 6, 4), 256, 0, L.s>>>(nx, ny, B.g2, B.h1, B.part, B.dbpart);
-  k_reduce_w<<<nblk(32 * 288 + 32, LB), LB, 0, L.s>>>(nchunk, 32, 288, B.part, B.dbpart, B.grad + LFC_OFF_W2,
+  prof_end(L, K_LFC_BWD_W);
+  prof_begin(L, K_LFC_REDUCE);
+  k_reduce_w<<<nblk(32 * 288 + 32, RE), RE * RG, 0, L.s>>>(nchunk, 32, 288, B.part, B.dbpart, B.grad + LFC_OFF_W2,
                                                        B.grad + LFC_OFF_B2);
+  prof_end(L, K_LFC_REDUCE);
+  prof_begin(L, K_LFC_BWD_DATA);
   k_conv_bwd_data<32, 32><<<nb, 256, 0, L.s>>>(nx, ny, B.g2, B.wt.wt2, B.h1, B.g1);
+  prof_end(L, K_LFC_BWD_DATA);
   // layer 1 (no gradient into the features)
+  prof_begin(L, K_LFC_BWD_W);
   k_conv_bwd_w<4, 32, 32, 1><<<nblk(nchunk, 4), 256, 0, L.s>>>(nx, ny, B.g1, B.f, B.part, B.dbpart);
-  k_reduce_w<<<nblk(32 * 36 + 32, LB), LB, 0, L.s>>>(nchunk, 32, 36, B.part, B.dbpart, B.grad + LFC_OFF_W1,
+  prof_end(L, K_LFC_BWD_W);
+  prof_begin(L, K_LFC_REDUCE);
+  k_reduce_w<<<nblk(32 * 36 + 32, RE), RE * RG, 0, L.s>>>(nchunk, 32, 36, B.part, B.dbpart, B.grad + LFC_OFF_W1,
                                                       B.grad + LFC_OFF_B1);
+  prof_end(L, K_LFC_REDUCE);
 }
 
 void lfc_adam(Launch &L, const LfcBufs &B, float lr, float c1, float c2) {
+  prof_begin(L, K_LFC_ADAM);
   k_adam<<<nblk(LFC_NPARAM, LB), LB, 0, L.s>>>(LFC_NPARAM, B.w, B.mo, B.ve, B.grad, lr, 0.9f, 0.999f, c1, c2,
                                                1e-8f);
+  prof_end(L, K_LFC_ADAM);
 }
 
-void lfc_pack(Launch &L, const LfcBufs &B) { k_pack<<<nblk(32 * 288, LB), LB, 0, L.s>>>(B.w, B.wt); }
+void lfc_pack(Launch &L, const LfcBufs &B) {
+  prof_begin(L, K_LFC_ADAM);
+  k_pack<<<nblk(32 * 288, LB), LB, 0, L.s>>>(B.w, B.wt);
+  prof_end(L, K_LFC_ADAM);
+}
 
 void lfc_apply(Launch &L, const Mesh &m, const LfcBufs &B, double *rho, double guard, int *flag) {
   const int npix = m.nx * m.ny;
+  prof_begin(L, K_LFC_APPLY);
   k_flag_clear<<<1, 1, 0, L.s>>>(flag);
+  prof_end(L, K_LFC_APPLY);
+  prof_begin(L, K_LFC_APPLY);
   k_guard<<<nblk(npix, LB), LB, 0, L.s>>>(m, rho, B.drho, guard, flag);
+  prof_end(L, K_LFC_APPLY);
+  prof_begin(L, K_LFC_APPLY);
   k_commit<<<nblk(npix, LB), LB, 0, L.s>>>(m, rho, B.drho, flag);
+  prof_end(L, K_LFC_APPLY);
 }
 
 void lfc_target(Launch &L, const Mesh &m, const double *ref, const double *plain, double *t) {
