@@ -263,7 +263,7 @@ void fargo_batch_destroy(fargo_batch *batch);
    (operands rounded to nearest even, FP32 accumulation); the FP32 master
    parameters are trained on the device with Adam (beta1 0.9, beta2 0.999,
    eps 1e-8) on the loss mean(((drho - target)/sigma)^2).
-   Requirements: cylindrical, nz == 1, FARGO_FP64, nx a multiple of 16 and
+   Requirements: cylindrical, nz == 1, FARGO_FP64, nx a multiple of 64 and
    nx*ny a multiple of 256 (FARGO_EUNSUPPORTED otherwise). */
 typedef struct fargo_lfc fargo_lfc;
 typedef struct {

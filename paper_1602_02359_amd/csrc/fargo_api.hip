@@ -915,7 +915,7 @@ namespace {
 
 bool lfc_mesh_ok(const fargo_ctx *c) {
   const Mesh &m = c->m;
-  return c->p.geometry == FARGO_CYLINDRICAL && !m.d3 && !fp32(c) && m.nx % 16 == 0 &&
+  return c->p.geometry == FARGO_CYLINDRICAL && !m.d3 && !fp32(c) && m.nx % 64 == 0 &&
          ((long)m.nx * m.ny) % LFC_CHUNK == 0;
 }
 

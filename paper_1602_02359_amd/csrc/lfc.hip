@@ -10,8 +10,8 @@
 // (v_mfma_f32_16x16x16_bf16, FP32 accumulation), one 16-row tile per wave:
 //   forward     out[p][co] = sum_k A[p][k] W[co][k],  k = tap Cin + ci,
 //               A[p][k] = act[p shifted by tap][ci]               (M = pixels)
-//   input grad  gin[p][ci] = sum_k G[p][k] Wt[ci][k], k = tap Cg + co,
-//               G[p][k] = g[p shifted back by tap][co]             (M = pixels)
+//   input grad  the adjoint convolution, a forward one with the weights
+//               transposed and their taps flipped                  (M = pixels)
 //   weight grad dW[co][k] = sum_p g[p][co] A[p][k]                 (M = Cout,
 //               reduced over pixel chunks, partial sums per chunk)
 // Operand layouts of the 16x16x16 MFMA: lane l holds row (or column) l % 16
@@ -65,15 +65,6 @@ __device__ inline int tap_src(int y, int x, int ty, int tx, int ny, int nx) {
   xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
   return yy * nx + xx;
 }
-// pixel whose forward tap (ty, tx) reads (y, x), or -1
-__device__ inline int tap_dst(int y, int x, int ty, int tx, int ny, int nx) {
-  const int yy = y - (ty - 1);
-  if (yy < 0 || yy >= ny) return -1;
-  int xx = x - (tx - 1);
-  xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-  return yy * nx + xx;
-}
-
 // ---------------------------------------------------------------------------
 // features (FP64 arithmetic, rounded to FP32 then to bfloat16)
 // ---------------------------------------------------------------------------
@@ -97,19 +88,39 @@ __global__ __launch_bounds__(LB) void k_features(Mesh m, const double *__restric
 }
 
 // ---------------------------------------------------------------------------
-// forward convolution: CIN -> COUT channels; KP = 9 CIN rounded up to 16,
-// the weights Wb are [16 NT][KP] bfloat16 (zero padded)
+// 3 x 3 convolution through LDS.  A block takes 64 pixels of one row (a wave
+// per 16 of them) and stages the three input rows they read, 66 columns wide
+// (periodic in i, zero rows outside the mesh), so that each input value is
+// read from memory once per block rather than once per tap; the MFMA A
+// operands then come from LDS.  Wb is [16 NT][KP] bfloat16, KP = 9 CIN
+// rounded up to 16.  Modes: CV_HID, out = bf16(relu(conv + b)); CV_OUT,
+// out = conv + b (FP32); CV_ADJ, the adjoint convolution (weights transposed
+// and their taps flipped), out = bf16([h > 0] conv).
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT, bool RELU>
-__global__ __launch_bounds__(256) void k_conv_fwd(int nx, int ny, const unsigned short *__restrict__ act,
-                                                  const unsigned short *__restrict__ Wb,
-                                                  const float *__restrict__ bias, unsigned short *__restrict__ hout,
-                                                  float *__restrict__ fout) {
+enum { CV_HID = 0, CV_OUT = 1, CV_ADJ = 2 };
+
+template <int CIN, int COUT, int MODE>
+__global__ __launch_bounds__(256) void k_conv(int nx, int ny, const unsigned short *__restrict__ act,
+                                              const unsigned short *__restrict__ Wb,
+                                              const float *__restrict__ bias, const unsigned short *__restrict__ h,
+                                              unsigned short *__restrict__ hout, float *__restrict__ fout) {
   constexpr int K = 9 * CIN, KP = (K + 15) / 16 * 16, NT = (COUT + 15) / 16;
-  const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
-  const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  const int pa = p0 + m; // the pixel of this lane's A row
-  const int ya = pa / nx, xa = pa - ya * nx;
+  constexpr int CP = CIN + 4, TW = 66, CH = CIN / 4; // padded pixel stride; staged columns
+  __shared__ __align__(16) unsigned short T[3][TW][CP];
+  const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, kq = lane >> 4, wv = tid >> 6;
+  const int pb = blockIdx.x * 64; // first pixel of the block: a row segment, since nx % 64 == 0
+  const int y = pb / nx, x0 = pb - y * nx;
+  for (int e = tid; e < 3 * TW * CH; e += 256) {
+    const int c4 = e % CH, col = (e / CH) % TW, ry = e / (CH * TW);
+    const int yy = y + ry - 1;
+    int xx = x0 + col - 1;
+    xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+    uint2 v = make_uint2(0u, 0u);
+    if (yy >= 0 && yy < ny) v = *reinterpret_cast<const uint2 *>(act + ((size_t)yy * nx + xx) * CIN + 4 * c4);
+    *reinterpret_cast<uint2 *>(&T[ry][col][4 * c4]) = v;
+  }
+  __syncthreads();
+  const int xl = wv * 16 + m; // the lane's A row, as a staged column offset
   f4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
@@ -119,8 +130,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(int nx, int ny, const unsigned
     bf4 a = zero4();
     if (k0 < K) {
       const int tap = k0 / CIN, ci = k0 - tap * CIN;
-      const int q = tap_src(ya, xa, tap / 3, tap % 3, ny, nx);
-      if (q >= 0) a = ld4(act + (size_t)q * CIN + ci);
+      a = ld4(&T[tap / 3][xl + tap % 3][ci]);
     }
 #pragma unroll
     for (int t = 0; t < NT; t++) {
@@ -134,13 +144,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(int nx, int ny, const unsigned
     if (co >= COUT) continue;
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      const int p = p0 + 4 * kq + v;
-      float val = acc[t][v] + bias[co];
-      if (RELU) {
-        val = val > 0.f ? val : 0.f;
-        hout[(size_t)p * COUT + co] = to_bf16(val);
+      const size_t idx = (size_t)(pb + wv * 16 + 4 * kq + v) * COUT + co;
+      if (MODE == CV_HID) {
+        const float val = acc[t][v] + bias[co];
+        hout[idx] = to_bf16(val > 0.f ? val : 0.f);
+      } else if (MODE == CV_OUT) {
+        fout[idx] = acc[t][v] + bias[co];
       } else {
-        fout[(size_t)p * COUT + co] = val;
+        hout[idx] = to_bf16(from_bf16(h[idx]) > 0.f ? acc[t][v] : 0.f);
       }
     }
   }
@@ -215,50 +226,6 @@ __global__ __launch_bounds__(LB) void k_flux_grad(int nx, int ny, const double *
   v.x = (unsigned)to_bf16((float)(sF * gx)) | ((unsigned)to_bf16((float)(sF * gy)) << 16);
   v.y = 0u;
   *reinterpret_cast<uint2 *>(g3 + (size_t)p * 4) = v;
-}
-
-// ---------------------------------------------------------------------------
-// input gradient: gin[p][ci] = [h[p][ci] > 0] sum_{tap, co} g[dst(p, tap)][co]
-// Wt[ci][tap GC + co]; GC = the gradient's channel count (a multiple of 4)
-// ---------------------------------------------------------------------------
-template <int CIN, int GC>
-__global__ __launch_bounds__(256) void k_conv_bwd_data(int nx, int ny, const unsigned short *__restrict__ g,
-                                                       const unsigned short *__restrict__ Wt,
-                                                       const unsigned short *__restrict__ h,
-                                                       unsigned short *__restrict__ gin) {
-  constexpr int K = 9 * GC, KP = (K + 15) / 16 * 16, NT = CIN / 16;
-  const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
-  const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  const int pa = p0 + m;
-  const int ya = pa / nx, xa = pa - ya * nx;
-  f4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; t++) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-  for (int s = 0; s < KP / 16; s++) {
-    const int k0 = 16 * s + 4 * kq;
-    bf4 a = zero4();
-    if (k0 < K) {
-      const int tap = k0 / GC, co = k0 - tap * GC;
-      const int q = tap_dst(ya, xa, tap / 3, tap % 3, ny, nx);
-      if (q >= 0) a = ld4(g + (size_t)q * GC + co);
-    }
-#pragma unroll
-    for (int t = 0; t < NT; t++) {
-      const bf4 b = ld4(Wt + (size_t)(16 * t + m) * KP + k0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; t++) {
-    const int ci = 16 * t + m;
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-      const size_t idx = (size_t)(p0 + 4 * kq + v) * CIN + ci;
-      const float val = from_bf16(h[idx]) > 0.f ? acc[t][v] : 0.f;
-      gin[idx] = to_bf16(val);
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -415,7 +382,7 @@ __global__ __launch_bounds__(LB) void k_pack(const float *__restrict__ w, LfcWei
   if (e < 32 * 288) {
     b.wb2[e] = to_bf16(W2[e]);
     const int ci = e / 288, k = e - ci * 288, tap = k / 32, co = k - tap * 32;
-    b.wt2[e] = to_bf16(W2[co * 288 + tap * 32 + ci]);
+    b.wt2[e] = to_bf16(W2[co * 288 + (8 - tap) * 32 + ci]); // taps flipped: the adjoint as a convolution
   }
   if (e < 16 * 288) {
     const int co = e / 288, k = e - co * 288;
@@ -423,7 +390,7 @@ __global__ __launch_bounds__(LB) void k_pack(const float *__restrict__ w, LfcWei
   }
   if (e < 32 * 48) {
     const int ci = e / 48, k = e - ci * 48, tap = k / 4, co = k - tap * 4;
-    b.wt3[e] = (k < 36 && co < 2) ? to_bf16(W3[co * 288 + tap * 32 + ci]) : (unsigned short)0;
+    b.wt3[e] = (k < 36 && co < 2) ? to_bf16(W3[co * 288 + (8 - tap) * 32 + ci]) : (unsigned short)0;
   }
 }
 
@@ -502,13 +469,13 @@ void lfc_forward(Launch &L, const Mesh &m, const double *rho, const double *vx, 
   prof_end(L, K_LFC_FEATURES);
   const unsigned nb = (unsigned)(npix / 64);
   prof_begin(L, K_LFC_CONV_FWD);
-  k_conv_fwd<4, 32, true><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.f, B.wt.wb1, B.w + LFC_OFF_B1, B.h1, nullptr);
+  k_conv<4, 32, CV_HID><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.f, B.wt.wb1, B.w + LFC_OFF_B1, nullptr, B.h1, nullptr);
   prof_end(L, K_LFC_CONV_FWD);
   prof_begin(L, K_LFC_CONV_FWD);
-  k_conv_fwd<32, 32, true><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h1, B.wt.wb2, B.w + LFC_OFF_B2, B.h2, nullptr);
+  k_conv<32, 32, CV_HID><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h1, B.wt.wb2, B.w + LFC_OFF_B2, nullptr, B.h2, nullptr);
   prof_end(L, K_LFC_CONV_FWD);
   prof_begin(L, K_LFC_CONV_FWD);
-  k_conv_fwd<32, 2, false><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h2, B.wt.wb3, B.w + LFC_OFF_B3, nullptr, B.o);
+  k_conv<32, 2, CV_OUT><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h2, B.wt.wb3, B.w + LFC_OFF_B3, nullptr, nullptr, B.o);
   prof_end(L, K_LFC_CONV_FWD);
 }
 
@@ -540,7 +507,7 @@ void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF) {
                                                      B.grad + LFC_OFF_B3);
   prof_end(L, K_LFC_REDUCE);
   prof_begin(L, K_LFC_BWD_DATA);
-  k_conv_bwd_data<32, 4><<<nb, 256, 0, L.s>>>(nx, ny, B.g3, B.wt.wt3, B.h2, B.g2);
+  k_conv<4, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g3, B.wt.wt3, nullptr, B.h2, B.g2, nullptr);
   prof_end(L, K_LFC_BWD_DATA);
   // layer 2
   prof_begin(L, K_LFC_BWD_W);
@@ -551,7 +518,7 @@ void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF) {
                                                        B.grad + LFC_OFF_B2);
   prof_end(L, K_LFC_REDUCE);
   prof_begin(L, K_LFC_BWD_DATA);
-  k_conv_bwd_data<32, 32><<<nb, 256, 0, L.s>>>(nx, ny, B.g2, B.wt.wt2, B.h1, B.g1);
+  k_conv<32, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g2, B.wt.wt2, nullptr, B.h1, B.g1, nullptr);
   prof_end(L, K_LFC_BWD_DATA);
   // layer 1 (no gradient into the features)
   prof_begin(L, K_LFC_BWD_W);

@@ -228,7 +228,7 @@ def test_restriction_matches_oracle():
 
 def test_unsupported_meshes_are_rejected():
     from paper_1602_02359_amd import fargo as F
-    prob = W.disk2d_planet(nx=60, ny=16)  # nx not a multiple of 16
+    prob = W.disk2d_planet(nx=96, ny=16)  # nx not a multiple of 64
     s = F.Solver(prob.params)
     s.upload(prob.fields)
     with pytest.raises(F.FargoError):
