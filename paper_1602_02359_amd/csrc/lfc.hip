@@ -229,100 +229,102 @@ __global__ __launch_bounds__(LB) void k_flux_grad(int nx, int ny, const double *
 }
 
 // ---------------------------------------------------------------------------
-// weight gradient partial sums over a chunk of PC pixels, one wave per
-// (chunk, group of NG column tiles); bias gradient partials alongside
+// weight gradient through LDS: dW[co][tap CIN + ci] = sum_p g[p][co]
+// act[p shifted by tap][ci] over a chunk of PC pixels (whole 64-pixel row
+// segments).  Per segment the block stages the three activation rows (as
+// the convolution does) and the layer gradient transposed to [co][pixel];
+// each wave then owns a share of the (co tile, k tile) pairs and accumulates
+// them over the chunk.  One partial sum per chunk, for the reduction below;
+// the bias gradient (the sum of g) alongside.
 // ---------------------------------------------------------------------------
 constexpr int PC = LFC_CHUNK;
 
-template <int CIN, int COUT, int GC, int NG>
-__global__ __launch_bounds__(256) void k_conv_bwd_w(int nx, int ny, const unsigned short *__restrict__ g,
-                                                    const unsigned short *__restrict__ act,
-                                                    float *__restrict__ part, float *__restrict__ dbpart) {
-  constexpr int K = 9 * CIN, KP = (K + 15) / 16 * 16, NTW = KP / 16, TPG = (NTW + NG - 1) / NG;
-  constexpr int MT = (COUT + 15) / 16; // row tiles of output channels
-  const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
-  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int chunk = wv / NG, grp = wv - chunk * NG;
-  const int nchunk = nx * ny / PC;
-  if (chunk >= nchunk) return;
-  f4 acc[MT][TPG];
+template <int CIN, int COUT, int GC>
+__global__ __launch_bounds__(256) void k_conv_w(int nx, int ny, const unsigned short *__restrict__ g,
+                                                const unsigned short *__restrict__ act, float *__restrict__ part,
+                                                float *__restrict__ dbpart) {
+  constexpr int K = 9 * CIN, KP = (K + 15) / 16 * 16, NTW = KP / 16, MT = (COUT + 15) / 16;
+  constexpr int NTILE = MT * NTW, TPW = (NTILE + 3) / 4; // tiles, and tiles per wave
+  constexpr int CP = CIN + 4, TW = 66, CH = CIN / 4, GP = 64 + 4;
+  constexpr int DBC = 32, DBS = 256 / DBC; // bias sums: channel tid % DBC, pixel subset tid / DBC
+  __shared__ __align__(16) unsigned short T[3][TW][CP];
+  __shared__ __align__(16) unsigned short Gt[MT * 16][GP];
+  __shared__ float dbr[DBS][DBC];
+  const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, kq = lane >> 4, wv = tid >> 6;
+  const int chunk = blockIdx.x;
+  f4 acc[TPW];
 #pragma unroll
-  for (int r = 0; r < MT; r++)
+  for (int t = 0; t < TPW; t++) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  // the wave's tiles: the weight column of the lane in each
+  int tmt[TPW], tty[TPW], ttx[TPW], tci[TPW];
+  bool tok[TPW];
 #pragma unroll
-    for (int t = 0; t < TPG; t++) acc[r][t] = f4{0.f, 0.f, 0.f, 0.f};
-  float db[MT];
-#pragma unroll
-  for (int r = 0; r < MT; r++) db[r] = 0.f;
-  // the lane's weight column in each of its tiles: tap and input channel
-  int tty[TPG], ttx[TPG], tci[TPG];
-  bool tok[TPG];
-#pragma unroll
-  for (int t = 0; t < TPG; t++) {
-    const int nt = grp * TPG + t, kk = 16 * nt + m;
-    tok[t] = nt < NTW && kk < K;
+  for (int t = 0; t < TPW; t++) {
+    const int tile = t * 4 + wv, mt = tile / NTW, nt = tile - mt * NTW, kk = 16 * nt + m;
+    tok[t] = tile < NTILE && kk < K;
+    tmt[t] = tile < NTILE ? mt : 0;
     const int tap = tok[t] ? kk / CIN : 0;
     tci[t] = tok[t] ? kk - tap * CIN : 0;
     tty[t] = tap / 3;
     ttx[t] = tap % 3;
   }
-  for (int s = 0; s < PC / 16; s++) {
-    const int pb = chunk * PC + 16 * s + 4 * kq; // the lane's four pixels pb .. pb + 3
-    int py[4], px[4];
+  float db = 0.f;
+  for (int seg = 0; seg < PC / 64; seg++) {
+    const int pb = chunk * PC + seg * 64;
+    const int y = pb / nx, x0 = pb - y * nx;
+    __syncthreads(); // the previous segment's reads are done
+    for (int e = tid; e < 3 * TW * CH; e += 256) {
+      const int c4 = e % CH, col = (e / CH) % TW, ry = e / (CH * TW);
+      const int yy = y + ry - 1;
+      int xx = x0 + col - 1;
+      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+      uint2 v = make_uint2(0u, 0u);
+      if (yy >= 0 && yy < ny) v = *reinterpret_cast<const uint2 *>(act + ((size_t)yy * nx + xx) * CIN + 4 * c4);
+      *reinterpret_cast<uint2 *>(&T[ry][col][4 * c4]) = v;
+    }
+    for (int e = tid; e < MT * 16 * 64; e += 256) {
+      const int px = e & 63, co = e >> 6;
+      Gt[co][px] = co < COUT ? g[(size_t)(pb + px) * GC + co] : (unsigned short)0;
+    }
+    __syncthreads();
+    {
+      const int co = tid % DBC, sub = tid / DBC;
+      if (co < COUT)
+        for (int px = sub; px < 64; px += DBS) db += from_bf16(Gt[co][px]);
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; t++) {
+      if (!tok[t] && (t * 4 + wv) >= NTILE) continue;
+#pragma unroll
+      for (int ks = 0; ks < 4; ks++) {
+        const int p4 = 16 * ks + 4 * kq; // the lane's four pixels of the segment
+        const bf4 a = ld4(&Gt[16 * tmt[t] + m][p4]);
+        bf4 b = zero4();
+        if (tok[t]) {
+#pragma unroll
+          for (int v = 0; v < 4; v++) b[v] = (short)T[tty[t]][p4 + v + ttx[t]][tci[t]];
+        }
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // result: lane holds column kk = 16 nt + m and rows co = 16 mt + 4 kq + v
+#pragma unroll
+  for (int t = 0; t < TPW; t++) {
+    if (!tok[t]) continue;
+    const int tile = t * 4 + wv, nt = tile - tmt[t] * NTW, kk = 16 * nt + m;
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      py[v] = (pb + v) / nx;
-      px[v] = pb + v - py[v] * nx;
-    }
-    bf4 a[MT];
-#pragma unroll
-    for (int r = 0; r < MT; r++) {
-      a[r] = zero4();
-      const int co = 16 * r + m;
-      if (co < COUT) {
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-          const unsigned short x = g[(size_t)(pb + v) * GC + co];
-          a[r][v] = (short)x;
-          db[r] += from_bf16(x);
-        }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < TPG; t++) {
-      bf4 b = zero4();
-      if (tok[t]) {
-#pragma unroll
-        for (int v = 0; v < 4; v++) {
-          const int q = tap_src(py[v], px[v], tty[t], ttx[t], ny, nx);
-          b[v] = q >= 0 ? (short)act[(size_t)q * CIN + tci[t]] : (short)0;
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < MT; r++) acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[r], b, acc[r][t], 0, 0, 0);
+      const int co = 16 * tmt[t] + 4 * kq + v;
+      if (co < COUT) part[((size_t)chunk * COUT + co) * K + kk] = acc[t][v];
     }
   }
-  // result: lane holds column kk = 16 nt + m and rows co = 16 r + 4 kq + v
-#pragma unroll
-  for (int t = 0; t < TPG; t++) {
-    const int nt = grp * TPG + t;
-    const int kk = 16 * nt + m;
-    if (nt >= NTW || kk >= K) continue;
-#pragma unroll
-    for (int r = 0; r < MT; r++)
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int co = 16 * r + 4 * kq + v;
-        if (co < COUT) part[((size_t)chunk * COUT + co) * K + kk] = acc[r][t][v];
-      }
-  }
-  // bias: lanes m, m + 16, m + 32, m + 48 summed pixels of channel 16 r + m
-#pragma unroll
-  for (int r = 0; r < MT; r++) {
-    float d = db[r];
-    d += __shfl_xor(d, 16, 64);
-    d += __shfl_xor(d, 32, 64);
-    const int co = 16 * r + m;
-    if (grp == 0 && kq == 0 && co < COUT) dbpart[(size_t)chunk * COUT + co] = d;
+  dbr[tid / DBC][tid % DBC] = db;
+  __syncthreads();
+  if (tid < COUT) {
+    float d = 0.f;
+    for (int q = 0; q < DBS; q++) d += dbr[q][tid];
+    dbpart[(size_t)chunk * COUT + tid] = d;
   }
 }
 
@@ -500,7 +502,7 @@ void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF) {
   prof_end(L, K_LFC_DRHO);
   // layer 3: weights from g3 and h2, then the gradient into h2
   prof_begin(L, K_LFC_BWD_W);
-  k_conv_bwd_w<32, 2, 4, 6><<<nblk((long)nchunk * 6, 4), 256, 0, L.s>>>(nx, ny, B.g3, B.h2, B.part, B.dbpart);
+  k_conv_w<32, 2, 4><<<nchunk, 256, 0, L.s>>>(nx, ny, B.g3, B.h2, B.part, B.dbpart);
   prof_end(L, K_LFC_BWD_W);
   prof_begin(L, K_LFC_REDUCE);
   k_reduce_w<<<nblk(2 * 288 + 2, RE), RE * RG, 0, L.s>>>(nchunk, 2, 288, B.part, B.dbpart, B.grad + LFC_OFF_W3,
@@ -511,7 +513,7 @@ void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF) {
   prof_end(L, K_LFC_BWD_DATA);
   // layer 2
   prof_begin(L, K_LFC_BWD_W);
-  k_conv_bwd_w<32, 32, 32, 6><<<nblk((long)nchunk * 6, 4), 256, 0, L.s>>>(nx, ny, B.g2, B.h1, B.part, B.dbpart);
+  k_conv_w<32, 32, 32><<<nchunk, 256, 0, L.s>>>(nx, ny, B.g2, B.h1, B.part, B.dbpart);
   prof_end(L, K_LFC_BWD_W);
   prof_begin(L, K_LFC_REDUCE);
   k_reduce_w<<<nblk(32 * 288 + 32, RE), RE * RG, 0, L.s>>>(nchunk, 32, 288, B.part, B.dbpart, B.grad + LFC_OFF_W2,
@@ -522,7 +524,7 @@ void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF) {
   prof_end(L, K_LFC_BWD_DATA);
   // layer 1 (no gradient into the features)
   prof_begin(L, K_LFC_BWD_W);
-  k_conv_bwd_w<4, 32, 32, 1><<<nblk(nchunk, 4), 256, 0, L.s>>>(nx, ny, B.g1, B.f, B.part, B.dbpart);
+  k_conv_w<4, 32, 32><<<nchunk, 256, 0, L.s>>>(nx, ny, B.g1, B.f, B.part, B.dbpart);
   prof_end(L, K_LFC_BWD_W);
   prof_begin(L, K_LFC_REDUCE);
   k_reduce_w<<<nblk(32 * 36 + 32, RE), RE * RG, 0, L.s>>>(nchunk, 32, 36, B.part, B.dbpart, B.grad + LFC_OFF_W1,
