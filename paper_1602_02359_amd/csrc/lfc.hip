@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) void k_conv_w(int nx, int ny, const unsigned s
 // grad[W] = sum over chunks of the partials, grad[b] likewise.  A block takes
 // RE consecutive entries; its RG thread groups sum interleaved subsets of the
 // chunks, and the group sums are added in a fixed order (deterministic).
-constexpr int RE = 16, RG = 16;
+constexpr int RE = 64, RG = 16;
 __global__ __launch_bounds__(RE * RG) void k_reduce_w(int nchunk, int cout, int K, const float *__restrict__ part,
                                                       const float *__restrict__ dbpart, float *__restrict__ gW,
                                                       float *__restrict__ gb) {
@@ -341,6 +341,7 @@ __global__ __launch_bounds__(RE * RG) void k_reduce_w(int nchunk, int cout, int 
   const int nw = cout * K;
   float s = 0.f;
   if (e < nw) {
+#pragma unroll 8
     for (int c = g; c < nchunk; c += RG) s += part[(size_t)c * nw + e];
   } else if (e < nw + cout) {
     for (int c = g; c < nchunk; c += RG) s += dbpart[(size_t)c * cout + (e - nw)];
