@@ -254,3 +254,36 @@ def test_training_pipeline_small():
     assert losses[-1] < losses[0]
     assert ev["relative_error"] < 1.0
     assert np.isfinite(eh["relative_error"])
+
+
+def test_full_size_forward_and_gradient():
+    """The 768 x 256 coarse planet disk of the benchmark: forward pass,
+    density change, loss and gradient against the oracle on the same state."""
+    c = _setup(nx=768, ny=256, seed=15)
+    net, torch = c["net"], c["torch"]
+    _say("lfc full size 768 x 256")
+    t_dev = torch.from_numpy(c["target"]).cuda()
+    net.train_step(t_dev, 1e-3)
+    loss, _ = net.result()
+    v = net.views()
+    grad = net.get_grad()
+    fx = c["fields"]
+    f = L.features(fx["rho"], fx["vx"], fx["vy"], c["rc"], c["scales"])
+    assert np.array_equal(v["f"].float().cpu().numpy().astype(np.float64), f)
+    A = L.forward(f, c["P"])
+    errs = {k: _nerr(v[k].float().cpu().numpy(), A[k]) for k in ("h1", "h2", "o")}
+    d_ref = L.drho(A["o"], c["sF"], c["invV"])
+    loss_ref = L.loss(d_ref, c["target"], c["sigma"])
+    Pd = {k: np.asarray(x, dtype=np.float64) for k, x in c["P"].items()}
+    G = L.backward(A, Pd, c["target"], c["sF"], c["invV"], c["sigma"])
+    Gg = _unflat(grad)
+    gerr = {k: _nerr(Gg[k], G[k]) for k in G}
+    _say("  forward", errs, "loss", loss, loss_ref, "gradient", gerr)
+    for k, e in errs.items():
+        assert e <= TOL_BF16, (k, e)
+    assert abs(loss - loss_ref) <= TOL_BF16 * loss_ref
+    for k, e in gerr.items():
+        assert e <= 5 * TOL_BF16, (k, e)
+    d_gpu = v["drho"].cpu().numpy()
+    Vs = (1.0 / c["invV"])[:, None]
+    assert abs(np.sum(d_gpu * Vs)) <= 1e-13 * np.sum(np.abs(d_gpu * Vs))
