@@ -230,6 +230,27 @@ def batch_variant(steps, warmup, tune=True):
 MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
 
 
+def copy_bandwidth():
+    """Bytes read plus written per second by a plain 1 GiB device copy
+    (torch's copy kernel), timed with HIP events: the bandwidth a streaming
+    kernel can reach on this GPU, for comparison with the 8 TB/s peak."""
+    import torch
+    src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(10):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 10
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * 2 ** 27 * 8 / (ms * 1e-3) / 1e9
+
+
 def lfc_variant(iters=600):
     """The learned flux correction on the planet disks (coarse 768 x 256,
     fine 3072 x 1024): 40 samples along one fine trajectory (after 200 fine
@@ -380,6 +401,8 @@ def main():
         step_alg = sum(wb * w * n for (w, n) in wpu.values())
         return solver, {"value": value, "ms": ms, "kern": kern, "dom": dom, "step_alg": step_alg}
 
+    copy_gbs = copy_bandwidth()
+    print("device copy: %.0f GB/s (read + write)" % copy_gbs, file=sys.stderr, flush=True)
     solver, r64 = run("fp64")
     value, ms, kern, dom, step_alg = r64["value"], r64["ms"], r64["kern"], r64["dom"], r64["step_alg"]
     achieved = kern[dom]["GBs"]
@@ -458,6 +481,7 @@ def main():
             "parallelism": "single GPU",
         },
         "hbm": {
+            "device_copy_GBs": copy_gbs,
             "step_alg_bytes_per_cell": step_alg / cells,
             "step_alg_GBs": value * step_alg / cells / 1e9,
             "compulsory_bytes_per_cell": compulsory_bytes(p),
