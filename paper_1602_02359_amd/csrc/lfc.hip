@@ -56,15 +56,6 @@ __device__ inline bf4 zero4() {
   return r;
 }
 
-// pixel reached from (y, x) by tap (ty, tx) of the forward stencil, or -1
-// outside the radial rows
-__device__ inline int tap_src(int y, int x, int ty, int tx, int ny, int nx) {
-  const int yy = y + ty - 1;
-  if (yy < 0 || yy >= ny) return -1;
-  int xx = x + tx - 1;
-  xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-  return yy * nx + xx;
-}
 // ---------------------------------------------------------------------------
 // features (FP64 arithmetic, rounded to FP32 then to bfloat16)
 // ---------------------------------------------------------------------------
