@@ -279,9 +279,11 @@ struct RingShape<float> {
 
 // Neighbour lanes through DPP whole-wave shifts by one lane (wave_shr:1,
 // wave_shl:1): a VALU move, with no trip through the LDS crossbar.  The lane
-// at the end of the wave keeps its own value.
+// at the end of the wave, which has no source lane, reads zero (bound_ctrl);
+// it is a halo lane, whose outputs are never stored.  Taking no old value
+// lets the move write its destination directly, without a copy first.
 template <int CTRL>
-__device__ inline int dpp_lane(int x) { return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xf, 0xf, false); }
+__device__ inline int dpp_lane(int x) { return __builtin_amdgcn_mov_dpp(x, CTRL, 0xf, 0xf, true); }
 template <int CTRL, typename F>
 __device__ inline F dpp_move(F x) {
   if constexpr (sizeof(F) == 8) {
@@ -326,6 +328,24 @@ __device__ inline void prev_of(const F (&a)[M], F (&out)[M]) { // value of zone 
 #pragma unroll
   for (int m = 0; m < M; m++) out[m] = m > 0 ? a[m - 1] : p1;
 }
+
+// Reciprocal and quotient for the ring kernel, whose FP64 form is bound by
+// its vector instruction count: the hardware reciprocal estimate refined by
+// two Newton-Raphson steps r <- r + r (1 - d r), which leaves r within about
+// one unit in the last place of 1/d (the correctly rounded division costs
+// about twice the instructions).  d must be a normal number; a zero or
+// denormal d, which the kernel only meets in discarded selects and halo
+// lanes, gives an infinite or meaningless value and no trap.  The FP32 form
+// is not bound by instructions and keeps the correctly rounded division,
+// whose unbiased rounding its 100-step error bar relies on.
+__device__ inline double ring_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+__device__ inline double ring_div(double n, double d) { return n * ring_rcp(d); }
+__device__ inline float ring_rcp(float d) { return 1.0f / d; }
+__device__ inline float ring_div(float n, float d) { return n / d; }
 
 // PPA on one zone (Eqs. 34-36): limit the parabola through the edge values
 // l, r (flat at an extremum, steepened away from an overshoot), then the
@@ -380,7 +400,7 @@ __device__ inline void vlx_faces(const Span<F, M> &Q, const Upwind<F, M> &U, F (
 #pragma unroll
   for (int q = 0; q < M; q++) {
     const F dm = Q(q) - Q(q - 1), dp = Q(q + 1) - Q(q), pr = dm * dp;
-    a[q] = pr > F(0) ? F(2) * pr / (dm + dp) : F(0);
+    a[q] = pr > F(0) ? ring_div(F(2) * pr, dm + dp) : F(0);
   }
   prev_of(a, ap);
 #pragma unroll
@@ -402,59 +422,44 @@ __device__ inline void ppa_values(const Span<F, M> &Q, const PpaX<F> &X, F (&out
   for (int q = 0; q < M; q++) out[q] = ppa_eval(Q(q - 1), Q(q), Q(q + 1), l[q], r[q], X);
 }
 
-template <typename F, int NQ>
-__global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__ vx2, TSetT<F> T, TSetT<F> Tout,
-                                                StateT<F> s, const double *__restrict__ v0,
-                                                const int32_t *__restrict__ Nsh, const double *__restrict__ xis,
-                                                const double *__restrict__ dtp, int nseg) {
-  constexpr int M = RingShape<F>::M, HLL = RingShape<F>::HLL, HRL = RingShape<F>::HRL;
-  constexpr int U = (WAVE - HLL - HRL) * M; // output zones per wave
-  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int lane = threadIdx.x & (WAVE - 1);
-  // wave-uniform (readfirstlane), so that the ring's constants come through
-  // scalar loads
-  const long gw = (long)blk * (blockDim.x / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-  if (gw >= (long)m.nring * nseg) return;
-  const int r = (int)(gw / nseg), seg = (int)(gw % nseg);
-  const int n = m.nx;
-  const int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
-  const unsigned base = m.o32(0, j, k);
-  const double dtd = *dtp, dXd = m.DX(j, k), Sd = m.Sx(j, k);
-  const F dt = (F)dtd, S = (F)Sd, vinv = (F)m.Vinv(j, k);
-  const bool fg = m.fargo != 0;
-  const F vb = fg ? (F)v0[r] : F(0);
-  const int N = fg ? Nsh[r] : 0;
-  const int Nm = ((N % n) + n) % n; // shift on store: zone i goes to (i + Nm) mod n
-  const double xid = fg ? xis[r] : 0.0;
-  const F xi = (F)xid;
-  const PpaX<F> X{fabs(xi), fabs(xi) * (F(1) - fabs(xi)), xi >= F(0)};
-  const F cdt = (F)(dtd / dXd), pfac = (F)(xid * dXd * Sd);
-  // the lane's zones and their ring indices
-  const int a0 = seg * U;                  // first output zone of the segment
-  const int zl = a0 - HLL * M + lane * M;  // first zone of the lane (window coordinates = ring coordinates)
-  const int aend = min(a0 + U, n);
-  const bool contig = zl >= 0 && zl + M <= n;
-  int iz[M];
+// The lane's place in a segment of a ring: its M zones start at window (=
+// ring) coordinate zl, iz[] are their ring indices (wrapped into [0, n)), and
+// contig tells whether they are consecutive in memory.  Only the lanes outside
+// the halo store, and only zones before the end of the segment.
+template <typename F>
+struct RingLane {
+  static constexpr int M = RingShape<F>::M, HLL = RingShape<F>::HLL, HRL = RingShape<F>::HRL;
+  static constexpr int U = (WAVE - HLL - HRL) * M; // output zones per wave
+  int n, lane, zl, aend, iz[M];
+  bool contig;
+  __device__ inline RingLane(int nx, int seg, int ln) : n(nx), lane(ln) {
+    const int a0 = seg * U;      // first output zone of the segment
+    zl = a0 - HLL * M + ln * M;  // first zone of the lane
+    aend = min(a0 + U, n);
+    contig = zl >= 0 && zl + M <= n;
 #pragma unroll
-  for (int q = 0; q < M; q++) {
-    int z = (zl + q) % n;
-    iz[q] = z < 0 ? z + n : z;
+    for (int q = 0; q < M; q++) {
+      const int z = (zl + q) % n;
+      iz[q] = z < 0 ? z + n : z;
+    }
   }
-  auto load = [&](const F *p, F (&out)[M]) {
+  __device__ inline bool useful(int q) const { return lane >= HLL && lane < WAVE - HRL && zl + q < aend; }
+  // the lane's zones of the row that starts at p
+  __device__ inline void load(const F *p, F (&out)[M]) const {
     if (contig) {
       if constexpr (sizeof(F) == 8) {
-        const double2 *v = reinterpret_cast<const double2 *>(p + base + zl);
+        const double2 *v = reinterpret_cast<const double2 *>(p + zl);
 #pragma unroll
         for (int q = 0; q < M / 2; q++) {
-          double2 t = v[q];
+          const double2 t = v[q];
           out[2 * q] = t.x;
           out[2 * q + 1] = t.y;
         }
       } else {
-        const float4 *v = reinterpret_cast<const float4 *>(p + base + zl);
+        const float4 *v = reinterpret_cast<const float4 *>(p + zl);
 #pragma unroll
         for (int q = 0; q < M / 4; q++) {
-          float4 t = v[q];
+          const float4 t = v[q];
           out[4 * q] = t.x;
           out[4 * q + 1] = t.y;
           out[4 * q + 2] = t.z;
@@ -463,37 +468,90 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < M; q++) out[q] = p[base + (unsigned)iz[q]];
+      for (int q = 0; q < M; q++) out[q] = p[iz[q]];
     }
-  };
+  }
+};
+
+// Constants of ring (j, k): time step, face area, inverse volume, the
+// shift velocity v0, the integer shift (as a store offset in [0, n)) and the
+// PPA residual xi (Eqs. 32, 33), dt/dX, the PPA flux factor xi dX S, and the
+// factors of 12d along X (Tab. "momenta": v = Pi/R - R Omega; R = 1 and
+// Omega = 0 on a Cartesian mesh).
+template <typename F>
+struct RingConst {
+  F dt, S, vinv, vb, cdt, pfac, R, iR, Rw;
+  PpaX<F> X;
+  bool fg;
+  int Nm;
+};
+template <typename F>
+__device__ inline RingConst<F> ring_const(const Mesh &m, int j, int k, int r, double dtd,
+                                          const double *__restrict__ v0, const int32_t *__restrict__ Nsh,
+                                          const double *__restrict__ xis) {
+  RingConst<F> C;
+  const int n = m.nx;
+  const double dXd = m.DX(j, k), Sd = m.Sx(j, k);
+  C.dt = (F)dtd;
+  C.S = (F)Sd;
+  C.vinv = (F)m.Vinv(j, k);
+  C.fg = m.fargo != 0;
+  C.vb = C.fg ? (F)v0[r] : F(0);
+  const int N = C.fg ? Nsh[r] : 0;
+  C.Nm = ((N % n) + n) % n; // shift on store: zone i goes to (i + Nm) mod n
+  const double xid = C.fg ? xis[r] : 0.0;
+  const F xi = (F)xid;
+  C.X = PpaX<F>{fabs(xi), fabs(xi) * (F(1) - fabs(xi)), xi >= F(0)};
+  C.cdt = (F)(dtd / dXd);
+  C.pfac = (F)(xid * dXd * Sd);
+  if (m.geo == FARGO_CARTESIAN) {
+    C.R = C.iR = F(1);
+    C.Rw = F(0);
+  } else {
+    C.R = (F)m.Rcyl(j, k);
+    C.iR = (F)(1.0 / m.Rcyl(j, k));
+    C.Rw = C.R * (F)m.omega;
+  }
+  return C;
+}
+
+// Load order of the quantities of a ring: Pi-_y, Pi+_y [, Pi-_z, Pi+_z] [, e],
+// then Pi-_x and Pi+_x, which 12d needs last (T.q holds Pi-_x, Pi+_x first).
+template <int NQ>
+__device__ constexpr int ring_qorder(int t) { return t + 2 < NQ ? t + 2 : t + 2 - NQ; }
+
+// X transport of one ring segment held in registers (Ra: density, w: v_x on
+// the lower faces, Qall[t]: quantity ring_qorder(t)), and its stores:
+// van Leer residual sweep with w - v0, PPA residual, 12d along X; every
+// output is stored shifted by N zones, out of place (Pi+-_y and Pi+-_z into
+// Tout, e and the density and v_x into the state).
+template <typename F, int NQ>
+__device__ inline void ring_update(const RingLane<F> &L, const RingConst<F> &C, unsigned base,
+                                   const F (&Ra)[RingShape<F>::M], F (&w)[RingShape<F>::M],
+                                   const F (&Qall)[NQ][RingShape<F>::M], const TSetT<F> &Tout, bool has_e,
+                                   const StateT<F> &s) {
+  constexpr int M = RingShape<F>::M;
+  const int n = L.n;
   auto out_at = [&](int q) { // storage index of the lane's zone q after the shift
-    int o = iz[q] + Nm;
+    const int o = L.iz[q] + C.Nm;
     return base + (unsigned)(o >= n ? o - n : o);
   };
-  auto useful = [&](int q) { return lane >= HLL && lane < WAVE - HRL && zl + q < aend; };
-
-  // Every load of the window is issued here, so that all of them are in
-  // flight together: the other quantities in the order they are processed,
-  // Pi-_y, Pi+_y [, Pi-_z, Pi+_z] [, e], then Pi-_x and Pi+_x, which 12d
-  // needs (T.q holds Pi-_x, Pi+_x first).
-  constexpr auto qorder = [](int t) { return t + 2 < NQ ? t + 2 : t + 2 - NQ; };
-  F w[M], ri0[M], Fl[M], ri1[M], El[M], rf[M], Qall[NQ][M];
+  const F dt = C.dt, S = C.S, vinv = C.vinv;
+  F ri0[M], Fl[M], ri1[M], El[M], rf[M];
   Span<F, M> R;
-  load(T.a[T_RHO], R.a);
-  load(vx2, w);
 #pragma unroll
-  for (int t = 0; t < NQ; t++) load(T.q[qorder(t)], Qall[t]);
+  for (int q = 0; q < M; q++) R.a[q] = Ra[q];
   // ---- density: van Leer residual sweep, then the PPA residual
   Upwind<F, M> Uw;
   {
 #pragma unroll
     for (int q = 0; q < M; q++) {
-      w[q] -= vb;
-      ri0[q] = F(1) / R.a[q];
+      w[q] -= C.vb;
+      ri0[q] = ring_rcp(R.a[q]);
     }
     R.edges();
     F st[M];
-    Uw.set(w, cdt);
+    Uw.set(w, C.cdt);
     vlx_faces(R, Uw, st);
 #pragma unroll
     for (int q = 0; q < M; q++) Fl[q] = w[q] * st[q] * S * dt;
@@ -503,18 +561,18 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
 #pragma unroll
     for (int q = 0; q < M; q++) {
       R1.a[q] = R.a[q] - vinv * (Fh[q] - Fl[q]);
-      ri1[q] = F(1) / R1.a[q];
+      ri1[q] = ring_rcp(R1.a[q]);
       rf[q] = R1.a[q];
     }
-    if (fg) {
+    if (C.fg) {
       R1.edges();
       F val[M];
-      ppa_values(R1, X, val);
+      ppa_values(R1, C.X, val);
 #pragma unroll
-      for (int q = 0; q < M; q++) val[q] = pfac * val[q];
+      for (int q = 0; q < M; q++) val[q] = C.pfac * val[q];
       // El: PPA mass flux through the zone's lower face (supplied by the
       // upstream zone of that face)
-      if (xi >= F(0)) prev_of(val, El);
+      if (C.X.right) prev_of(val, El);
       else {
 #pragma unroll
         for (int q = 0; q < M; q++) El[q] = val[q];
@@ -529,7 +587,7 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
   F pxm[M], pxp[M];
 #pragma unroll
   for (int t = 0; t < NQ; t++) {
-    const int qi = qorder(t);
+    const int qi = ring_qorder<NQ>(t);
     Span<F, M> Qs;
     F Qv[M];
 #pragma unroll
@@ -544,13 +602,13 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
     next_of(G, Gh);
 #pragma unroll
     for (int q = 0; q < M; q++) Qv[q] = Qv[q] - vinv * (Gh[q] - G[q]);
-    if (fg) {
+    if (C.fg) {
 #pragma unroll
       for (int q = 0; q < M; q++) Qs.a[q] = Qv[q] * ri1[q];
       Qs.edges();
       F st[M], Hl[M], Hh[M];
-      ppa_values(Qs, X, st);
-      if (xi >= F(0)) {
+      ppa_values(Qs, C.X, st);
+      if (C.X.right) {
         prev_of(st, Hl);
 #pragma unroll
         for (int q = 0; q < M; q++) Hl[q] *= El[q];
@@ -569,10 +627,10 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
 #pragma unroll
       for (int q = 0; q < M; q++) pxp[q] = Qv[q];
     } else {
-      F *dst = (T.a[T_E] && qi == NQ - 1) ? s.e : Tout.q[qi];
+      F *dst = (has_e && qi == NQ - 1) ? s.e : Tout.q[qi];
 #pragma unroll
       for (int q = 0; q < M; q++)
-        if (useful(q)) dst[out_at(q)] = Qv[q];
+        if (L.useful(q)) dst[out_at(q)] = Qv[q];
     }
   }
   // ---- box 12d along X (Eq. 18) on the shifted ring: face i + N takes zones i - 1, i
@@ -581,12 +639,42 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
   prev_of(rf, rp);
 #pragma unroll
   for (int q = 0; q < M; q++) {
-    if (!useful(q)) continue;
-    const F mom = (pp[q] + pxm[q]) / (rp[q] + rf[q]);
+    if (!L.useful(q)) continue;
+    const F mom = ring_div(pp[q] + pxm[q], rp[q] + rf[q]);
     const unsigned o = out_at(q);
-    s.vx[o] = m.vx_from(j, k, mom);
+    // FP64: the product with the ring's 1/R; FP32 divides, since there a
+    // rounded 1/R would bias v_x the same way at every step
+    if constexpr (sizeof(F) == 8) s.vx[o] = mom * C.iR - C.Rw;
+    else s.vx[o] = mom / C.R - C.Rw;
     s.rho[o] = rf[q];
   }
+}
+
+// X transport of every active ring (2D meshes, where there is no Z sweep).
+template <typename F, int NQ>
+__global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__ vx2, TSetT<F> T, TSetT<F> Tout,
+                                                StateT<F> s, const double *__restrict__ v0,
+                                                const int32_t *__restrict__ Nsh, const double *__restrict__ xis,
+                                                const double *__restrict__ dtp, int nseg) {
+  constexpr int M = RingShape<F>::M;
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & (WAVE - 1);
+  // wave-uniform (readfirstlane), so that the ring's constants come through
+  // scalar loads
+  const long gw = (long)blk * (blockDim.x / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  if (gw >= (long)m.nring * nseg) return;
+  const int r = (int)(gw / nseg), seg = (int)(gw % nseg);
+  const int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
+  const unsigned base = m.o32(0, j, k);
+  const RingLane<F> L(m.nx, seg, lane);
+  const RingConst<F> C = ring_const<F>(m, j, k, r, *dtp, v0, Nsh, xis);
+  // every load of the window is issued before the first use
+  F w[M], Ra[M], Qall[NQ][M];
+  L.load(T.a[T_RHO] + base, Ra);
+  L.load(vx2 + base, w);
+#pragma unroll
+  for (int t = 0; t < NQ; t++) L.load(T.q[ring_qorder<NQ>(t)] + base, Qall[t]);
+  ring_update<F, NQ>(L, C, base, Ra, w, Qall, Tout, T.a[T_E] != nullptr, s);
 }
 
 // ------------------------------------------------------------------------
