@@ -23,6 +23,8 @@
 // The field type F is double, or float for the FP32-bulk state; the arithmetic
 // of a kernel is carried out in F (per-ring constants such as dt/dX and the
 // PPA residual xi are formed in FP64 and rounded to F).
+#include <type_traits>
+
 #include "fargo_internal.h"
 
 namespace fargo {
@@ -243,10 +245,8 @@ __global__ __launch_bounds__(256) void k_sweep_z(Mesh m, const F *__restrict__ v
   column_sweep<F, NQ, true, Raw>(a0, a1, dt, raw, derive, Tof, geo, st);
 }
 
-// ------------------------------------------------------------------------
-// X: one workgroup per ring, M zones per thread (zone i = tid + B m), three
-// LDS arrays for neighbour exchange.
-// ------------------------------------------------------------------------
+// Monotonised central slope of the PPA edge values (Eq. 34): zero at an
+// extremum, else the central difference limited by twice each one-sided one.
 template <typename F>
 __device__ inline F mc_slope(F qm, F q0, F qp) {
   F dq = F(0.5) * (qp - qm);
@@ -266,15 +266,12 @@ __device__ inline F mc_slope(F qm, F q0, F qp) {
 // Outputs are written out of place (shifted by N on store), so that the
 // segments of a ring can run in any order.
 // ------------------------------------------------------------------------
+// Two zones per lane in both precisions (in FP32 four zones per lane, with
+// fewer halo lanes, measured no faster: the larger register window lowers the
+// number of waves that hide the loads).
 template <typename F>
-struct RingShape;
-template <>
-struct RingShape<double> {
+struct RingShape {
   static constexpr int M = 2, HLL = 3, HRL = 3; // halo lanes on each side
-};
-template <>
-struct RingShape<float> {
-  static constexpr int M = 4, HLL = 2, HRL = 2;
 };
 
 // Neighbour lanes through DPP whole-wave shifts by one lane (wave_shr:1,
@@ -444,27 +441,18 @@ struct RingLane {
     }
   }
   __device__ inline bool useful(int q) const { return lane >= HLL && lane < WAVE - HRL && zl + q < aend; }
-  // the lane's zones of the row that starts at p
+  // the lane's zones of the row that starts at p (two-element vector loads
+  // where they are consecutive)
   __device__ inline void load(const F *p, F (&out)[M]) const {
+    static_assert(M % 2 == 0, "pairs of zones per lane");
     if (contig) {
-      if constexpr (sizeof(F) == 8) {
-        const double2 *v = reinterpret_cast<const double2 *>(p + zl);
+      using V2 = typename std::conditional<sizeof(F) == 8, double2, float2>::type;
+      const V2 *v = reinterpret_cast<const V2 *>(p + zl);
 #pragma unroll
-        for (int q = 0; q < M / 2; q++) {
-          const double2 t = v[q];
-          out[2 * q] = t.x;
-          out[2 * q + 1] = t.y;
-        }
-      } else {
-        const float4 *v = reinterpret_cast<const float4 *>(p + zl);
-#pragma unroll
-        for (int q = 0; q < M / 4; q++) {
-          const float4 t = v[q];
-          out[4 * q] = t.x;
-          out[4 * q + 1] = t.y;
-          out[4 * q + 2] = t.z;
-          out[4 * q + 3] = t.w;
-        }
+      for (int q = 0; q < M / 2; q++) {
+        const V2 t = v[q];
+        out[2 * q] = t.x;
+        out[2 * q + 1] = t.y;
       }
     } else {
 #pragma unroll
