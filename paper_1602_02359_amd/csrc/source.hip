@@ -280,11 +280,14 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
       xface(r, c + 2, m.g.inv_dxlen((size_t)kk * m.nyg + jt0 + r));
       yface(r + 2, c);
     }
-    if (r < 3) {
-      const int t = r == 0 ? 1 : h + 1 + r;
+    // the halo faces: the last three waves take the extra Y-face rows and
+    // wave 4 the extra X faces, since waves 0-3 stage the Y-halo rows (the
+    // barrier waits for the most loaded wave)
+    if (r >= TY - 3) {
+      const int e = r - (TY - 3), t = e == 0 ? 1 : h + 1 + e;
       if (c < w) yface(t, c);
-    } else if (tid < 192 + 3 * TY) {
-      const int q = tid - 192, rr = q / 3, a = q % 3, sl = a == 0 ? 1 : w + 1 + a;
+    } else if (r == 4 && c < 3 * TY) {
+      const int rr = c / 3, a = c % 3, sl = a == 0 ? 1 : w + 1 + a;
       if (rr < h) xface(rr, sl, L.DX[sb][rr]);
     }
   };
