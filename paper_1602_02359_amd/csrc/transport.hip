@@ -326,23 +326,26 @@ __device__ inline void prev_of(const F (&a)[M], F (&out)[M]) { // value of zone 
   for (int m = 0; m < M; m++) out[m] = m > 0 ? a[m - 1] : p1;
 }
 
-// Reciprocal and quotient for the ring kernel, whose FP64 form is bound by
-// its vector instruction count: the hardware reciprocal estimate refined by
-// two Newton-Raphson steps r <- r + r (1 - d r), which leaves r within about
-// one unit in the last place of 1/d (the correctly rounded division costs
-// about twice the instructions).  d must be a normal number; a zero or
-// denormal d, which the kernel only meets in discarded selects and halo
-// lanes, gives an infinite or meaningless value and no trap.  The FP32 form
-// is not bound by instructions and keeps the correctly rounded division,
-// whose unbiased rounding its 100-step error bar relies on.
+// Reciprocal and quotient for the ring kernel, which is bound by its vector
+// instruction count: the hardware reciprocal estimate refined by
+// Newton-Raphson steps r <- r + r (1 - d r), two in FP64 and one in FP32,
+// which leaves r within about one unit in the last place of 1/d (the correctly
+// rounded division costs about twice the instructions).  The rounding of such
+// a quotient varies from zone to zone like that of a division.  d must be a
+// normal number; a zero or denormal d, which the kernel only meets in
+// discarded selects and halo lanes, gives an infinite or meaningless value and
+// no trap.
 __device__ inline double ring_rcp(double d) {
   double r = __builtin_amdgcn_rcp(d);
   r = fma(r, fma(-d, r, 1.0), r);
   return fma(r, fma(-d, r, 1.0), r);
 }
 __device__ inline double ring_div(double n, double d) { return n * ring_rcp(d); }
-__device__ inline float ring_rcp(float d) { return 1.0f / d; }
-__device__ inline float ring_div(float n, float d) { return n / d; }
+__device__ inline float ring_rcp(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return fmaf(r, fmaf(-d, r, 1.0f), r);
+}
+__device__ inline float ring_div(float n, float d) { return n * ring_rcp(d); }
 
 // PPA on one zone (Eqs. 34-36): limit the parabola through the edge values
 // l, r (flat at an extremum, steepened away from an overshoot), then the
