@@ -422,6 +422,16 @@ __device__ inline void ppa_values(const Span<F, M> &Q, const PpaX<F> &X, F (&out
   for (int q = 0; q < M; q++) out[q] = ppa_eval(Q(q - 1), Q(q), Q(q + 1), l[q], r[q], X);
 }
 
+// Element i of the row that starts at p, for 0 <= i < 2^31 / sizeof(T): a
+// uniform (scalar) row pointer plus a 32-bit byte offset, the addressing mode
+// of a global access with a scalar base, which saves the 64-bit address
+// arithmetic of every access.
+template <typename T>
+__device__ inline T *at(T *p, unsigned i) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return reinterpret_cast<T *>(reinterpret_cast<B *>(p) + i * (unsigned)sizeof(T));
+}
+
 // The lane's place in a segment of a ring: its M zones start at window (=
 // ring) coordinate zl, iz[] are their ring indices (wrapped into [0, n)), and
 // contig tells whether they are consecutive in memory.  Only the lanes outside
@@ -450,7 +460,7 @@ struct RingLane {
     static_assert(M % 2 == 0, "pairs of zones per lane");
     if (contig) {
       using V2 = typename std::conditional<sizeof(F) == 8, double2, float2>::type;
-      const V2 *v = reinterpret_cast<const V2 *>(p + zl);
+      const V2 *v = reinterpret_cast<const V2 *>(at(p, (unsigned)zl));
 #pragma unroll
       for (int q = 0; q < M / 2; q++) {
         const V2 t = v[q];
@@ -459,7 +469,7 @@ struct RingLane {
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < M; q++) out[q] = p[iz[q]];
+      for (int q = 0; q < M; q++) out[q] = *at(p, (unsigned)iz[q]);
     }
   }
 };
@@ -523,9 +533,9 @@ __device__ inline void ring_update(const RingLane<F> &L, const RingConst<F> &C, 
                                    const StateT<F> &s) {
   constexpr int M = RingShape<F>::M;
   const int n = L.n;
-  auto out_at = [&](int q) { // storage index of the lane's zone q after the shift
+  auto out_at = [&](int q) { // index in the ring of the lane's zone q after the shift
     const int o = L.iz[q] + C.Nm;
-    return base + (unsigned)(o >= n ? o - n : o);
+    return (unsigned)(o >= n ? o - n : o);
   };
   const F dt = C.dt, S = C.S, vinv = C.vinv;
   F ri0[M], Fl[M], ri1[M], El[M], rf[M];
@@ -618,10 +628,10 @@ __device__ inline void ring_update(const RingLane<F> &L, const RingConst<F> &C, 
 #pragma unroll
       for (int q = 0; q < M; q++) pxp[q] = Qv[q];
     } else {
-      F *dst = (has_e && qi == NQ - 1) ? s.e : Tout.q[qi];
+      F *dst = ((has_e && qi == NQ - 1) ? s.e : Tout.q[qi]) + base;
 #pragma unroll
       for (int q = 0; q < M; q++)
-        if (L.useful(q)) dst[out_at(q)] = Qv[q];
+        if (L.useful(q)) *at(dst, out_at(q)) = Qv[q];
     }
   }
   // ---- box 12d along X (Eq. 18) on the shifted ring: face i + N takes zones i - 1, i
@@ -635,9 +645,9 @@ __device__ inline void ring_update(const RingLane<F> &L, const RingConst<F> &C, 
     const unsigned o = out_at(q);
     // FP64: the product with the ring's 1/R; FP32 divides, since there a
     // rounded 1/R would bias v_x the same way at every step
-    if constexpr (sizeof(F) == 8) s.vx[o] = mom * C.iR - C.Rw;
-    else s.vx[o] = mom / C.R - C.Rw;
-    s.rho[o] = rf[q];
+    if constexpr (sizeof(F) == 8) *at(s.vx + base, o) = mom * C.iR - C.Rw;
+    else *at(s.vx + base, o) = mom / C.R - C.Rw;
+    *at(s.rho + base, o) = rf[q];
   }
 }
 
