@@ -4,10 +4,10 @@
 // One workgroup per active ring computes the ring's v0 and, for each of its
 // zones, the cell time step and the shear rate; the ring minimum/maximum goes
 // to a per-ring slot.  A single workgroup then reduces the slots (exact and
-// order independent: min/max), forms dt and splits every ring's displacement
-// into (N, xi).  The time step and the split use floating-point contraction
-// off and the operation order of the written definition, so that the
-// integer shift N is reproducible bit for bit.
+// order independent: min/max) and forms dt, and a kernel with a thread per
+// ring splits every ring's displacement into (N, xi).  The time step and the
+// split use floating-point contraction off and the operation order of the
+// written definition, so that the integer shift N is reproducible bit for bit.
 #include "fargo_internal.h"
 
 namespace fargo {
@@ -179,51 +179,46 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
 // of every ring.  A non-positive or non-finite dt is flagged and replaced by 0,
 // which leaves the state unchanged.
 __global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const double *__restrict__ ringrate,
-                                                   const double *__restrict__ ringshear, int use_given,
-                                                   const double *__restrict__ v0, int32_t *__restrict__ N,
-                                                   double *__restrict__ xi) {
+                                                   const double *__restrict__ ringshear) {
 #pragma clang fp contract(off)
   __shared__ double red[MAXW];
-  __shared__ double dts;
-  if (!use_given) {
-    double rmax = 0.0, smax = 0.0;
-    for (int r = threadIdx.x; r < m.nring; r += blockDim.x) {
-      rmax = ringrate[r] > rmax ? ringrate[r] : rmax;
-      smax = ringshear[r] > smax ? ringshear[r] : smax;
+  constexpr int U = 8; // loads in flight per thread
+  double rmax = 0.0, smax = 0.0;
+  for (int r0 = threadIdx.x; r0 < m.nring; r0 += U * blockDim.x) {
+    double a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int r = r0 + u * (int)blockDim.x;
+      a[u] = r < m.nring ? ringrate[r] : 0.0;
+      b[u] = r < m.nring ? ringshear[r] : 0.0;
     }
-    rmax = block_reduce(rmax, Max(), 0.0, red);
-    smax = block_reduce(smax, Max(), 0.0, red);
-    if (threadIdx.x == 0) {
-      double dt = m.courant * (1.0 / sqrt(rmax));
-      if (m.fargo && m.shear_c0 > 0.0 && smax > 0.0) dt = fmin(dt, m.shear_c0 / smax);
-      if (!(dt > 0.0) || !isfinite(dt)) {
-        atomicOr(w.err, 2);
-        dt = 0.0;
-      }
-      *w.dt = dt;
-      dts = dt;
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      rmax = a[u] > rmax ? a[u] : rmax;
+      smax = b[u] > smax ? b[u] : smax;
     }
-  } else if (threadIdx.x == 0) {
-    dts = *w.dt;
   }
-  __syncthreads();
-  if (!m.fargo) return;
-  const double dt = dts;
-  for (int r = threadIdx.x; r < m.nring; r += blockDim.x) {
-    int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
-    double D = (v0[r] * dt) / m.DX(j, k);
-    double rn = round(D);
-    N[r] = (int32_t)rn;
-    xi[r] = D - rn;
+  rmax = block_reduce(rmax, Max(), 0.0, red);
+  smax = block_reduce(smax, Max(), 0.0, red);
+  if (threadIdx.x == 0) {
+    double dt = m.courant * (1.0 / sqrt(rmax));
+    if (m.fargo && m.shear_c0 > 0.0 && smax > 0.0) dt = fmin(dt, m.shear_c0 / smax);
+    if (!(dt > 0.0) || !isfinite(dt)) {
+      atomicOr(w.err, 2);
+      dt = 0.0;
+    }
+    *w.dt = dt;
   }
 }
 
-// The split alone (stand-alone entry point): one thread per ring.
-__global__ __launch_bounds__(256) void k_split(Mesh m, const double *__restrict__ v0, double dt,
-                                               int32_t *__restrict__ N, double *__restrict__ xi) {
+// The split of Eq. 29, one thread per ring, with dt given by value or, if
+// dtp is not null, read from the device.
+__global__ __launch_bounds__(256) void k_split(Mesh m, const double *__restrict__ v0, const double *__restrict__ dtp,
+                                               double dtv, int32_t *__restrict__ N, double *__restrict__ xi) {
 #pragma clang fp contract(off)
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= m.nring) return;
+  const double dt = dtp ? *dtp : dtv;
   int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
   double D = (v0[r] * dt) / m.DX(j, k);
   double rn = round(D);
@@ -280,14 +275,21 @@ template void launch_cfl<float>(Launch &, const Mesh &, const StateT<float> &, i
 
 void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringrate, const double *ringshear,
                      int use_given, const double *v0, int32_t *N, double *xi) {
-  prof_begin(L, K_DT_FINAL);
-  k_dt_final<<<1, 1024, 0, L.s>>>(m, w, ringrate, ringshear, use_given, v0, N, xi);
-  prof_end(L, K_DT_FINAL);
+  if (!use_given) {
+    prof_begin(L, K_DT_FINAL);
+    k_dt_final<<<1, 1024, 0, L.s>>>(m, w, ringrate, ringshear);
+    prof_end(L, K_DT_FINAL);
+  }
+  if (m.fargo) {
+    prof_begin(L, K_SPLIT);
+    k_split<<<(m.nring + 255) / 256, 256, 0, L.s>>>(m, v0, w.dt, 0.0, N, xi);
+    prof_end(L, K_SPLIT);
+  }
 }
 
 void launch_split(Launch &L, const Mesh &m, const double *v0, double dt, int32_t *N, double *xi) {
   prof_begin(L, K_SPLIT);
-  k_split<<<(m.nring + 255) / 256, 256, 0, L.s>>>(m, v0, dt, N, xi);
+  k_split<<<(m.nring + 255) / 256, 256, 0, L.s>>>(m, v0, nullptr, dt, N, xi);
   prof_end(L, K_SPLIT);
 }
 
