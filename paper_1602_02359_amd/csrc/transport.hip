@@ -259,7 +259,7 @@ __device__ inline F mc_slope(F qm, F q0, F qp) {
 // X: every wave owns a segment of one ring.  Lane l holds the M consecutive
 // zones z0 + M l .. z0 + M l + M - 1 of a window of 64 M zones that starts
 // HL zones before the segment and ends HR zones after it; zone neighbours
-// come from the lane's own registers or, across lanes, by wave shuffles.  The
+// come from the lane's own registers or, across lanes, by DPP lane moves.  The
 // halo is recomputed instead of exchanged, so no wave waits for another and
 // nothing goes through LDS.  The dependency cone of an output zone (van Leer
 // residual sweep, PPA residual, 12d along X) spans zones z-6 .. z+5.
@@ -372,8 +372,8 @@ __device__ inline F ppa_eval(F qm, F q0, F qp, F l, F r, const PpaX<F> &X) {
 }
 
 // Interface values on the lane's zones; each zone's slope and each face's
-// edge value is computed once and handed to the neighbouring zone by a
-// shuffle.
+// edge value is computed once and handed to the neighbouring zone (in a
+// register, or by a DPP lane move).
 //   vlx_faces: van Leer on a uniform zone width, slopes in units of the zone
 //   (harmonic mean of the two one-sided differences, zero unless they have
 //   the same sign), and the half-step value at each zone's lower face

@@ -53,6 +53,11 @@ def _cases():
     yield "ring_2048", lambda: W.random_problem("cyl", nx=2048, ny=4, nz=1, eos="iso", seed=7, fargo=True)
     # rings above 2048 zones: the time-step kernel's 512-thread form
     yield "ring_3072", lambda: W.random_problem("cyl", nx=3072, ny=4, nz=1, eos="iso", seed=9, fargo=True)
+    # degenerate rings: a single zone (axisymmetric), and rings shorter than
+    # the stencils, whose neighbours wrap onto the zone itself
+    yield "ring_nx1_cyl", lambda: W.random_problem("cyl", nx=1, ny=9, nz=6, eos="adi", seed=12, fargo=True)
+    yield "ring_nx2_cart", lambda: W.random_problem("cart", nx=2, ny=9, nz=6, eos="adi", seed=13, fargo=True)
+    yield "ring_nx3_sph", lambda: W.random_problem("sph", nx=3, ny=9, nz=6, eos="adi", seed=14, fargo=True)
 
 
 def _with(prob, **kw):
