@@ -29,6 +29,30 @@ __device__ inline double block_reduce(double v, Op op, double id, double *lds) {
   return v; // valid in every lane
 }
 
+// Two reductions of a block at once (two barriers for both); lds holds
+// 2 * MAXW values.
+template <typename OpA, typename OpB>
+__device__ inline void block_reduce2(double &a, OpA opa, double ida, double &b, OpB opb, double idb, double *lds) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a = opa(a, __shfl_xor(a, o, 64));
+    b = opb(b, __shfl_xor(b, o, 64));
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    lds[wid] = a;
+    lds[MAXW + wid] = b;
+  }
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+  a = lane < nw ? lds[lane] : ida;
+  b = lane < nw ? lds[MAXW + lane] : idb;
+  for (int o = 32; o > 0; o >>= 1) {
+    a = opa(a, __shfl_xor(a, o, 64));
+    b = opb(b, __shfl_xor(b, o, 64));
+  }
+}
+
 struct Max { __device__ double operator()(double a, double b) const { return a > b ? a : b; } };
 struct Min { __device__ double operator()(double a, double b) const { return a < b ? a : b; } };
 struct Add { __device__ double operator()(double a, double b) const { return a + b; } };
@@ -53,8 +77,7 @@ __device__ inline double ring_bulk(const Mesh &m, const double (&v)[M], int tid,
       vmax = v[mm] > vmax ? v[mm] : vmax;
       vmin = v[mm] < vmin ? v[mm] : vmin;
     }
-  vmax = block_reduce(vmax, Max(), -HUGE_VAL, lds);
-  vmin = block_reduce(vmin, Min(), HUGE_VAL, lds);
+  block_reduce2(vmax, Max(), -HUGE_VAL, vmin, Min(), HUGE_VAL, lds);
   return 0.5 * (vmax + vmin);
 }
 
@@ -67,7 +90,7 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
                                                   int *__restrict__ err) {
 #pragma clang fp contract(off)
   extern __shared__ double V[]; // the ring's v_x
-  __shared__ double red[MAXW];
+  __shared__ double red[2 * MAXW];
   const unsigned L = xcd_remap(blockIdx.x, gridDim.x);
   const int kk = (int)(L % (unsigned)m.nz), jj = (int)(L / (unsigned)m.nz);
   const int j = m.j0 + jj, k = m.k0 + kk;
@@ -105,10 +128,10 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
     vx[mm] = i < n ? (double)fx[mm] : 0.0;
     if (i < n) V[i] = vx[mm];
   }
+  // the barriers of the reduction also make V visible to the block
   const double vb_ring = ring_bulk<M>(m, vx, tid, red);
   if (tid == 0) v0[r] = vb_ring;
   if (!with_cfl) return;
-  __syncthreads();
   const double vb = m.fargo ? vb_ring : 0.0;
   // Eq. cfl2 through the inverse steps (rates u / Delta): the minimum step of
   // a cell over directions is its maximum rate, and the smallest step is
@@ -165,8 +188,7 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
       if (sh > smax) smax = sh;
     }
   }
-  rmax = block_reduce(rmax, Max(), 0.0, red);
-  smax = block_reduce(smax, Max(), 0.0, red);
+  block_reduce2(rmax, Max(), 0.0, smax, Max(), 0.0, red);
   int anybad = __syncthreads_or(bad);
   if (tid == 0) {
     ringrate[r] = rmax; // the ring's largest squared rate
@@ -181,7 +203,7 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
 __global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const double *__restrict__ ringrate,
                                                    const double *__restrict__ ringshear) {
 #pragma clang fp contract(off)
-  __shared__ double red[MAXW];
+  __shared__ double red[2 * MAXW];
   constexpr int U = 8; // loads in flight per thread
   double rmax = 0.0, smax = 0.0;
   for (int r0 = threadIdx.x; r0 < m.nring; r0 += U * blockDim.x) {
@@ -198,8 +220,7 @@ __global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const dou
       smax = b[u] > smax ? b[u] : smax;
     }
   }
-  rmax = block_reduce(rmax, Max(), 0.0, red);
-  smax = block_reduce(smax, Max(), 0.0, red);
+  block_reduce2(rmax, Max(), 0.0, smax, Max(), 0.0, red);
   if (threadIdx.x == 0) {
     double dt = m.courant * (1.0 / sqrt(rmax));
     if (m.fargo && m.shear_c0 > 0.0 && smax > 0.0) dt = fmin(dt, m.shear_c0 / smax);
