@@ -80,8 +80,7 @@ struct fargo_ctx {
   bool own_ws = false;
   // carved workspace
   DevWords w{};
-  double *v0 = nullptr, *xi = nullptr, *ringrate = nullptr, *ringshear = nullptr;
-  int32_t *nshift = nullptr;
+  double *v0 = nullptr, *ringrate = nullptr, *ringshear = nullptr;
   double *partial = nullptr, *sums_out = nullptr;
   size_t esize = 8;                                    // bytes per state element
   void *v2[4] = {nullptr, nullptr, nullptr, nullptr}; // post-source vx, vy, vz, e
@@ -251,7 +250,7 @@ size_t geo_doubles(int nyg, int nzg) {
 }
 
 struct Layout {
-  size_t geo, words, v0, xi, ringrate, ringshear, nshift, partial, sums, v2, T, total;
+  size_t geo, words, v0, ringrate, ringshear, partial, sums, v2, T, total;
 };
 
 Layout layout(const fargo_params *p) {
@@ -268,14 +267,10 @@ Layout layout(const fargo_params *p) {
   o += 256;
   L.v0 = o;
   o += al(nring * 8);
-  L.xi = o;
-  o += al(nring * 8);
   L.ringrate = o;
   o += al(nring * 8);
   L.ringshear = o;
   o += al(nring * 8);
-  L.nshift = o;
-  o += al(nring * 4);
   L.partial = o;
   o += al(nring * 10 * 8);
   L.sums = o;
@@ -333,7 +328,7 @@ void timestep_phase(fargo_ctx *c, Launch &L, const StateT<F> &S, double dt) {
   if (dt > 0.0) launch_set_dt(L, c->w, dt);
   launch_bc(L, m, S.rho, S.e, S.vx, S.vy, S.vz);
   launch_cfl(L, m, S, 1, c->v0, c->ringrate, c->ringshear, c->w.err);
-  launch_dt_final(L, m, c->w, c->ringrate, c->ringshear, dt > 0.0, c->v0, c->nshift, c->xi);
+  launch_dt_final(L, m, c->w, c->ringrate, c->ringshear, dt > 0.0);
 }
 
 } // namespace
@@ -476,10 +471,8 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
     return FARGO_EHIP;
   }
   c->v0 = (double *)(base + Lo.v0);
-  c->xi = (double *)(base + Lo.xi);
   c->ringrate = (double *)(base + Lo.ringrate);
   c->ringshear = (double *)(base + Lo.ringshear);
-  c->nshift = (int32_t *)(base + Lo.nshift);
   c->partial = (double *)(base + Lo.partial);
   c->sums_out = (double *)(base + Lo.sums);
   size_t nc = (size_t)pitch * nyg * nzg;
@@ -573,7 +566,7 @@ void step_impl(fargo_ctx *ctx, const fargo_state *state, double dt, Launch &L) {
     cur = &TA;
     other = &TB;
   }
-  launch_ring_x(L, m, (const F *)P.vx, *cur, *other, S, ctx->v0, ctx->nshift, ctx->xi, dtp); // X, FARGO, 12d (v_x)
+  launch_ring_x(L, m, (const F *)P.vx, *cur, *other, S, ctx->v0, dtp);           // X, split, FARGO, 12d (v_x)
   launch_vel(L, m, S, *other);                                                     // 12d (v_y, v_z)
 }
 

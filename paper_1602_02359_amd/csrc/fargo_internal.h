@@ -243,9 +243,10 @@ void launch_set_dt(Launch &L, const DevWords &w, double dt);
 template <typename R>
 void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringrate,
                 double *ringshear, int *err);
-// dt from the ring slots (unless imposed), then N and xi of every ring
+// dt from the ring slots (unless imposed; the ring kernel splits each ring's
+// displacement itself)
 void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringrate, const double *ringshear,
-                     int use_given, const double *v0, int32_t *N, double *xi);
+                     int use_given);
 void launch_split(Launch &L, const Mesh &m, const double *v0, double dt, int32_t *N, double *xi);
 // box 7: post-source velocities and energy into vx2, vy2, vz2, e2
 template <typename R>
@@ -259,11 +260,11 @@ template <typename R>
 void launch_sweep_y(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &out, const double *dt);
 template <typename R>
 void launch_sweep_z(Launch &L, const Mesh &m, const R *vz, const TSetT<R> &in, const TSetT<R> &out, const double *dt);
-// X sweep, FARGO and 12d along X: reads T, writes rho, v_x, e of the state and
-// the Y/Z momenta into Tout (out of place, shifted)
+// X sweep, split of Eq. 29, FARGO and 12d along X: reads T, writes rho, v_x, e
+// of the state and the Y/Z momenta into Tout (out of place, shifted)
 template <typename R>
 void launch_ring_x(Launch &L, const Mesh &m, const R *vx2, const TSetT<R> &T, const TSetT<R> &Tout,
-                   const StateT<R> &s, const double *v0, const int32_t *N, const double *xi, const double *dt);
+                   const StateT<R> &s, const double *v0, const double *dt);
 template <typename R>
 void launch_vel(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &T);
 // misc

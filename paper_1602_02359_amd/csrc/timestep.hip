@@ -4,8 +4,9 @@
 // One workgroup per active ring computes the ring's v0 and, for each of its
 // zones, the cell time step and the shear rate; the ring minimum/maximum goes
 // to a per-ring slot.  A single workgroup then reduces the slots (exact and
-// order independent: min/max) and forms dt, and a kernel with a thread per
-// ring splits every ring's displacement into (N, xi).  The time step and the
+// order independent: min/max) and forms dt.  The split of every ring's
+// displacement into (N, xi) is taken by the ring kernel of the X transport
+// (and by k_split for the stand-alone entry point).  The time step and the
 // split use floating-point contraction off and the operation order of the
 // written definition, so that the integer shift N is reproducible bit for bit.
 #include "fargo_internal.h"
@@ -295,17 +296,11 @@ template void launch_cfl<float>(Launch &, const Mesh &, const StateT<float> &, i
                                 int *);
 
 void launch_dt_final(Launch &L, const Mesh &m, const DevWords &w, const double *ringrate, const double *ringshear,
-                     int use_given, const double *v0, int32_t *N, double *xi) {
-  if (!use_given) {
-    prof_begin(L, K_DT_FINAL);
-    k_dt_final<<<1, 1024, 0, L.s>>>(m, w, ringrate, ringshear);
-    prof_end(L, K_DT_FINAL);
-  }
-  if (m.fargo) {
-    prof_begin(L, K_SPLIT);
-    k_split<<<(m.nring + 255) / 256, 256, 0, L.s>>>(m, v0, w.dt, 0.0, N, xi);
-    prof_end(L, K_SPLIT);
-  }
+                     int use_given) {
+  if (use_given) return;
+  prof_begin(L, K_DT_FINAL);
+  k_dt_final<<<1, 1024, 0, L.s>>>(m, w, ringrate, ringshear);
+  prof_end(L, K_DT_FINAL);
 }
 
 void launch_split(Launch &L, const Mesh &m, const double *v0, double dt, int32_t *N, double *xi) {

@@ -486,10 +486,21 @@ struct RingConst {
   bool fg;
   int Nm;
 };
+// The split of Eq. 29 for one ring: D = v0 dt / dX in this operation order
+// with contraction off, N the nearest integer (ties away from zero) and
+// xi = D - N, exact; the same arithmetic as the stand-alone split and the
+// oracle, so N is reproduced bit for bit.
+__device__ inline void ring_split_at(double v0, double dt, double dX, int &N, double &xi) {
+#pragma clang fp contract(off)
+  const double D = (v0 * dt) / dX;
+  const double rn = round(D);
+  N = (int)rn;
+  xi = D - rn;
+}
+
 template <typename F>
 __device__ inline RingConst<F> ring_const(const Mesh &m, int j, int k, int r, double dtd,
-                                          const double *__restrict__ v0, const int32_t *__restrict__ Nsh,
-                                          const double *__restrict__ xis) {
+                                          const double *__restrict__ v0) {
   RingConst<F> C;
   const int n = m.nx;
   const double dXd = m.DX(j, k), Sd = m.Sx(j, k);
@@ -497,10 +508,12 @@ __device__ inline RingConst<F> ring_const(const Mesh &m, int j, int k, int r, do
   C.S = (F)Sd;
   C.vinv = (F)m.Vinv(j, k);
   C.fg = m.fargo != 0;
-  C.vb = C.fg ? (F)v0[r] : F(0);
-  const int N = C.fg ? Nsh[r] : 0;
+  const double v0d = C.fg ? v0[r] : 0.0;
+  C.vb = (F)v0d;
+  int N = 0;
+  double xid = 0.0;
+  if (C.fg) ring_split_at(v0d, dtd, dXd, N, xid);
   C.Nm = ((N % n) + n) % n; // shift on store: zone i goes to (i + Nm) mod n
-  const double xid = C.fg ? xis[r] : 0.0;
   const F xi = (F)xid;
   C.X = PpaX<F>{fabs(xi), fabs(xi) * (F(1) - fabs(xi)), xi >= F(0)};
   C.cdt = (F)(dtd / dXd);
@@ -655,7 +668,6 @@ __device__ inline void ring_update(const RingLane<F> &L, const RingConst<F> &C, 
 template <typename F, int NQ>
 __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__ vx2, TSetT<F> T, TSetT<F> Tout,
                                                 StateT<F> s, const double *__restrict__ v0,
-                                                const int32_t *__restrict__ Nsh, const double *__restrict__ xis,
                                                 const double *__restrict__ dtp, int nseg) {
   constexpr int M = RingShape<F>::M;
   const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -668,7 +680,7 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
   const int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
   const unsigned base = m.o32(0, j, k);
   const RingLane<F> L(m.nx, seg, lane);
-  const RingConst<F> C = ring_const<F>(m, j, k, r, *dtp, v0, Nsh, xis);
+  const RingConst<F> C = ring_const<F>(m, j, k, r, *dtp, v0);
   // every load of the window is issued before the first use
   F w[M], Ra[M], Qall[NQ][M];
   L.load(T.a[T_RHO] + base, Ra);
@@ -761,17 +773,17 @@ void launch_sweep_z(Launch &L, const Mesh &m, const F *vz, const TSetT<F> &in, c
 // Waves of 64 lanes, four per block; ceil(nx / U) waves per ring.
 template <typename F>
 void launch_ring_x(Launch &L, const Mesh &m, const F *vx2, const TSetT<F> &T, const TSetT<F> &Tout,
-                   const StateT<F> &s, const double *v0, const int32_t *N, const double *xi, const double *dt) {
+                   const StateT<F> &s, const double *v0, const double *dt) {
   constexpr int U = (WAVE - RingShape<F>::HLL - RingShape<F>::HRL) * RingShape<F>::M;
   const int nseg = (m.nx + U - 1) / U;
   const long waves = (long)m.nring * nseg;
   const unsigned nb = (unsigned)((waves + 3) / 4);
   prof_begin(L, K_RING_X);
   switch (T.nq) { // Pi-+_x, Pi-+_y [, Pi-+_z] [, e]
-  case 4: k_ring_x<F, 4><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg); break;
-  case 5: k_ring_x<F, 5><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg); break;
-  case 6: k_ring_x<F, 6><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg); break;
-  default: k_ring_x<F, 7><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, N, xi, dt, nseg); break;
+  case 4: k_ring_x<F, 4><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, dt, nseg); break;
+  case 5: k_ring_x<F, 5><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, dt, nseg); break;
+  case 6: k_ring_x<F, 6><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, dt, nseg); break;
+  default: k_ring_x<F, 7><<<nb, 256, 0, L.s>>>(m, vx2, T, Tout, s, v0, dt, nseg); break;
   }
   prof_end(L, K_RING_X);
 }
@@ -791,8 +803,7 @@ void launch_vel(Launch &L, const Mesh &m, const StateT<F> &s, const TSetT<F> &T)
   template void launch_sweep_z<F>(Launch &, const Mesh &, const F *, const TSetT<F> &, const TSetT<F> &,         \
                                   const double *);                                                               \
   template void launch_ring_x<F>(Launch &, const Mesh &, const F *, const TSetT<F> &, const TSetT<F> &,         \
-                                 const StateT<F> &, const double *, const int32_t *, const double *,             \
-                                 const double *);                                                                \
+                                 const StateT<F> &, const double *, const double *);                             \
   template void launch_vel<F>(Launch &, const Mesh &, const StateT<F> &, const TSetT<F> &);
 FARGO_TRANSPORT_INST(double)
 FARGO_TRANSPORT_INST(float)
