@@ -207,7 +207,7 @@ def batch_variant(steps, warmup, tune=True):
     b = F.Batch(s32, lanes=8)
     best = None
     if tune:
-        best = b.fargo_batch_tune(lanes=(1, 4, 8, 16), chunks=(16, 32, 64), steps=3)
+        best = b.fargo_batch_tune(lanes=(1, 4, 8, 16), chunks=(16, 32, 64), steps=10)
     for _ in range(warmup):
         b.fargo_batch_step()
     el = timed(b.fargo_batch_step, steps)
