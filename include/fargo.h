@@ -237,7 +237,9 @@ int fargo_batch_step(fargo_batch *batch, void *stream);
 /* Autotuner: for every pair (lanes[a], chunks[c]) - the graph's stream count
    and the zones per thread of the Y/Z column sweeps - re-capture the batch,
    time `steps` graph launches with HIP events on `stream`, and keep the
-   fastest pair (written to best[0], best[1]).  The evolving fields of every
+   fastest pair (written to best[0], best[1]) with the graph captured and
+   timed for it (a new capture of the same pair can run at another speed,
+   since its streams differ).  The evolving fields of every
    state are saved first and restored after each candidate (one temporary
    device allocation), so the call leaves the states as it found them.
    Waits for the stream. */

@@ -841,6 +841,19 @@ int fargo_batch_tune(fargo_batch *b, const int32_t *lanes, int nlanes, const int
   if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = FARGO_EHIP;
   float best_ms = 0.0f;
   int best_l = b->lanes, best_c = chunk0[0];
+  // the fastest candidate's graph is kept as timed: a graph captured again
+  // with the same width does not always run as fast (its streams differ)
+  hipGraph_t kept_graph = nullptr;
+  hipGraphExec_t kept_exec = nullptr;
+  std::vector<hipStream_t> kept_ls;
+  auto drop_kept = [&]() {
+    if (kept_exec) (void)hipGraphExecDestroy(kept_exec);
+    if (kept_graph) (void)hipGraphDestroy(kept_graph);
+    for (hipStream_t q : kept_ls) (void)hipStreamDestroy(q);
+    kept_exec = nullptr;
+    kept_graph = nullptr;
+    kept_ls.clear();
+  };
   for (int ci = 0; ci < nchunks && !rc; ci++)
     for (int li = 0; li < nlanes && !rc; li++) {
       for (auto *c : b->ctx) c->m.chunk = chunks[ci];
@@ -858,6 +871,12 @@ int fargo_batch_tune(fargo_batch *b, const int32_t *lanes, int nlanes, const int
         best_ms = ms;
         best_l = lanes[li];
         best_c = chunks[ci];
+        drop_kept();
+        kept_graph = b->graph;
+        kept_exec = b->exec;
+        kept_ls.swap(b->ls);
+        b->graph = nullptr;
+        b->exec = nullptr;
       }
       // back to the saved state before the next candidate
       size_t o = 0;
@@ -872,8 +891,19 @@ int fargo_batch_tune(fargo_batch *b, const int32_t *lanes, int nlanes, const int
   if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = FARGO_EHIP;
   (void)hipFree(save);
   for (size_t d = 0; d < b->ctx.size(); d++) b->ctx[d]->m.chunk = rc ? chunk0[d] : best_c;
-  int rc2 = batch_capture(b, rc ? b->lanes : best_l);
-  if (!rc) rc = rc2;
+  if (!rc && kept_exec) {
+    batch_release_graph(b);
+    b->graph = kept_graph;
+    b->exec = kept_exec;
+    b->ls.swap(kept_ls);
+    b->lanes = best_l;
+    kept_graph = nullptr;
+    kept_exec = nullptr;
+  } else {
+    drop_kept();
+    int rc2 = batch_capture(b, rc ? b->lanes : best_l);
+    if (!rc) rc = rc2;
+  }
   if (!rc && best) {
     best[0] = best_l;
     best[1] = best_c;
