@@ -168,11 +168,15 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
       z.q[4] = m.mz(a, w.vz0);
       z.q[5] = m.mz(a, w.vz1);
     }
-    if (ADI) z.q[NQ - 1] = w.e / r;
+    if (ADI) {
+      z.q[NQ - 1] = w.e / r;
+      z.T[0] = w.e; // the window carries no other conserved value (CT is false)
+    }
   };
-  // the momenta are rho m(v) exactly as formed; e is read again (a cache hit)
-  auto Tof = [&](int a, const Zone<F, NQ, false> &z, int q) {
-    if (ADI && q == NQ - 1) return e[m.o32(i, a, k)];
+  // the momenta are rho m(v) exactly as formed; e as loaded, carried in the
+  // window (read again three rows later, it would come from memory again)
+  auto Tof = [&](int, const Zone<F, NQ, false> &z, int q) {
+    if (ADI && q == NQ - 1) return z.T[0];
     return z.rho * z.q[q];
   };
   struct Geo {
