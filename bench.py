@@ -51,6 +51,7 @@ def words_per_unit(p):
         "sweep_y": ((1 + nvel + adi) + nT, y_rows),          # rho, v'', e'' -> T (momenta formed on the fly)
         "sweep_z": ((2 * nT + 1) if d3 else 0, act),         # T, v_z -> T
         "ring_x": ((nT + 1) + (2 + adi + 2 + (2 if d3 else 0)), act),  # T, v_x -> rho, v_x, e, Pi_y, Pi_z
+        "zx_ring": ((nT + 2 + 2 + adi + 4) if d3 else 0, act),   # Y-swept T, v_z, v_x -> rho, v_x, e, Pi_y, Pi_z
         "vel_yz": ((1 + 2 + (2 if d3 else 0)) + (nvel - 1), act),      # rho, Pi_y, Pi_z -> v_y, v_z
     }
 
@@ -60,6 +61,7 @@ def words_per_unit(p):
 # were taken
 KERNEL_SOURCES = {"cfl": "timestep.hip", "source": "source.hip", "source_ghosts": "source.hip",
                   "sweep_y": "transport.hip", "sweep_z": "transport.hip", "ring_x": "transport.hip",
+                  "zx_ring": "transport.hip",
                   "vel_yz": "transport.hip"}
 
 

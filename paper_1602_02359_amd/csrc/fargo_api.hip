@@ -9,6 +9,8 @@
 #include <new>
 #include <vector>
 
+#include <type_traits>
+
 #include "fargo_internal.h"
 
 using namespace fargo;
@@ -17,7 +19,7 @@ namespace fargo {
 
 const char *kernel_names[K_COUNT] = {"set_dt", "bc_faces", "bc_ghosts", "cfl",    "dt_final", "split",
                                      "source", "source_ghosts", "visc", "sweep_y", "sweep_z",  "ring_x",
-                                     "vel_yz", "shift",    "sums",      "sums_final",
+                                     "vel_yz", "shift",    "sums",      "sums_final", "zx_ring",
                                      "lfc_features", "lfc_conv_fwd", "lfc_drho", "lfc_conv_bwd_w",
                                      "lfc_conv_bwd_data", "lfc_reduce", "lfc_adam", "lfc_apply"};
 
@@ -561,6 +563,13 @@ void step_impl(fargo_ctx *ctx, const fargo_state *state, double dt, Launch &L) {
   const TSetT<F> TA = tset<F>(ctx, ctx->TA), TB = tset<F>(ctx, ctx->TB);
   launch_sweep_y(L, m, P, TB, dtp);                                                // boxes 12a-c, Y
   const TSetT<F> *cur = &TB, *other = &TA;
+  if constexpr (std::is_same<F, float>::value) {
+    if (m.d3) { // FP32: Z, X, split, FARGO and 12d (v_x) in one pass
+      launch_zx(L, m, (const F *)P.vx, (const F *)P.vz, TB, TA, S, ctx->v0, dtp);
+      launch_vel(L, m, S, TA);                                                     // 12d (v_y, v_z)
+      return;
+    }
+  }
   if (m.d3) {
     launch_sweep_z(L, m, (const F *)P.vz, TB, TA, dtp);                            // Z
     cur = &TA;

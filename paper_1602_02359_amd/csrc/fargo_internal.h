@@ -208,7 +208,7 @@ void prof_end(Launch &L, int kid);
 
 enum KernelId {
   K_SET_DT = 0, K_BC_FACES, K_BC_GHOSTS, K_CFL, K_DT_FINAL, K_SPLIT, K_SRC, K_SRC_GHOSTS, K_VISC, K_SWEEP_Y,
-  K_SWEEP_Z, K_RING_X, K_VEL, K_SHIFT, K_SUMS, K_SUMS_FINAL,
+  K_SWEEP_Z, K_RING_X, K_VEL, K_SHIFT, K_SUMS, K_SUMS_FINAL, K_ZX,
   // learned flux correction
   K_LFC_FEATURES, K_LFC_CONV_FWD, K_LFC_DRHO, K_LFC_BWD_W, K_LFC_BWD_DATA, K_LFC_REDUCE, K_LFC_ADAM, K_LFC_APPLY,
   K_COUNT
@@ -265,6 +265,11 @@ void launch_sweep_z(Launch &L, const Mesh &m, const R *vz, const TSetT<R> &in, c
 template <typename R>
 void launch_ring_x(Launch &L, const Mesh &m, const R *vx2, const TSetT<R> &T, const TSetT<R> &Tout,
                    const StateT<R> &s, const double *v0, const double *dt);
+// 3D: the Z sweep of the Y-swept set T fused with the X transport of
+// launch_ring_x (used for the FP32-bulk state)
+template <typename R>
+void launch_zx(Launch &L, const Mesh &m, const R *vx2, const R *vz, const TSetT<R> &T, const TSetT<R> &Tout,
+               const StateT<R> &s, const double *v0, const double *dt);
 template <typename R>
 void launch_vel(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &T);
 // misc

@@ -458,6 +458,12 @@ struct RingLane {
     }
   }
   __device__ inline bool useful(int q) const { return lane >= HLL && lane < WAVE - HRL && zl + q < aend; }
+  // the lane's zones of the row that starts at p, one load per zone and no
+  // branch on contig (for loads inside a loop)
+  __device__ inline void load_each(const F *p, F (&out)[M]) const {
+#pragma unroll
+    for (int q = 0; q < M; q++) out[q] = *at(p, (unsigned)iz[q]);
+  }
   // the lane's zones of the row that starts at p (two-element vector loads
   // where they are consecutive)
   __device__ inline void load(const F *p, F (&out)[M]) const {
@@ -694,6 +700,141 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
   ring_update<F, NQ>(L, C, base, Ra, w, Qall, Tout, T.a[T_E] != nullptr, s);
 }
 
+// Z sweep and X transport fused (3D meshes).  A wave owns one segment of the
+// rings of row j and walks up a chunk of planes.  For each of its M zones a
+// lane carries the Z column window of the sweep (three zones, the slopes and
+// the flux through the lower face), as a column sweep does; once the fluxes
+// through face k are known the Z update of plane k - 1 is complete, and it is
+// handed, in registers, to the X transport of ring (j, k - 1).  The Z-swept
+// quantities never go through memory.  The halo zones of the segment are
+// swept along Z as well, so segments stay independent.  The conserved
+// quantities handed on are formed again as rho (Q/rho).
+// Used for the FP32-bulk state, where the window and the X transport fit in
+// 168 VGPRs (three waves per SIMD); in FP64 the kernel needs about 310 (one
+// wave per SIMD) and the separate Z sweep and ring kernel are faster.
+template <typename F, int NQ>
+__global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2, const F *__restrict__ vz,
+                                            TSetT<F> T, TSetT<F> Tout, StateT<F> s, const double *__restrict__ v0,
+                                            const double *__restrict__ dtp, int nseg, int nkc) {
+  constexpr int M = RingShape<F>::M;
+  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const long gw = (long)blk * (blockDim.x / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+  if (gw >= (long)nseg * m.ny * nkc) return;
+  const int seg = (int)(gw % nseg);
+  const long rest = gw / nseg;
+  const int j = m.j0 + (int)(rest % m.ny), kc = (int)(rest / m.ny);
+  const int a0 = m.k0 + kc * m.chunk, a1 = min(a0 + m.chunk, m.kn);
+  const RingLane<F> L(m.nx, seg, lane);
+  const double dtd = *dtp;
+  const F dt = (F)dtd;
+  const bool has_e = T.a[T_E] != nullptr;
+  // a zone of the window (M columns): density, Q/rho, v_z on the lower face,
+  // v_x on the lower X face (for the X transport)
+  struct Zw {
+    F rho[M], q[NQ][M], w[M], vx[M];
+  };
+  struct Zr {
+    F rho[M], T[NQ][M], w[M], vx[M];
+  };
+  auto raw = [&](int a, Zr &z) {
+    const unsigned b = m.o32(0, j, a);
+    L.load_each(T.a[T_RHO] + b, z.rho);
+#pragma unroll
+    for (int q = 0; q < NQ; q++) L.load_each(T.q[q] + b, z.T[q]);
+    L.load_each(vz + b, z.w);
+    L.load_each(vx2 + b, z.vx);
+  };
+  auto derive = [&](const Zr &r, Zw &z) {
+#pragma unroll
+    for (int c = 0; c < M; c++) {
+      const F ri = F(1) / r.rho[c];
+      z.rho[c] = r.rho[c];
+      z.w[c] = r.w[c];
+      z.vx[c] = r.vx[c];
+#pragma unroll
+      for (int q = 0; q < NQ; q++) z.q[q][c] = r.T[q][c] * ri;
+    }
+  };
+  auto Lz = [&](int a) { return (F)m.Lz(j, a); };
+  auto hz = [&](int f) { return (F)m.hz(j, f); };
+  Zw zm, z0, zp;
+  Zr rn;
+  raw(a0 - 2, rn);
+  derive(rn, zp); // used only for the first slope
+  raw(a0 - 1, rn);
+  derive(rn, zm);
+  raw(a0, rn);
+  derive(rn, z0);
+  raw(a0 + 1, rn);
+  F sm[NQ + 1][M], s0[NQ + 1][M];
+  {
+    const F hm = hz(a0 - 1), hp = hz(a0);
+#pragma unroll
+    for (int c = 0; c < M; c++) {
+      sm[NQ][c] = vl_slope(zp.rho[c], zm.rho[c], z0.rho[c], hm, hp);
+#pragma unroll
+      for (int q = 0; q < NQ; q++) sm[q][c] = vl_slope(zp.q[q][c], zm.q[q][c], z0.q[q][c], hm, hp);
+    }
+  }
+  F Fp[M], FQp[NQ][M];
+#pragma unroll
+  for (int c = 0; c < M; c++) {
+    Fp[c] = F(0);
+#pragma unroll
+    for (int q = 0; q < NQ; q++) FQp[q][c] = F(0);
+  }
+  F Lm = Lz(a0 - 1);
+#pragma unroll 1
+  for (int f = a0; f <= a1; f++) {
+    derive(rn, zp); // zone f + 1
+    if (f + 2 <= a1 + 1) raw(f + 2, rn);
+    const F hm = hz(f), hp = hz(f + 1), L0 = Lz(f), Sf = (F)m.Sz(j, f);
+    F Fr[M], FQ[NQ][M];
+#pragma unroll
+    for (int c = 0; c < M; c++) {
+      s0[NQ][c] = vl_slope(zm.rho[c], z0.rho[c], zp.rho[c], hm, hp);
+#pragma unroll
+      for (int q = 0; q < NQ; q++) s0[q][c] = vl_slope(zm.q[q][c], z0.q[q][c], zp.q[q][c], hm, hp);
+      const F w = z0.w[c];
+      Fr[c] = w * vl_star(w, dt, zm.rho[c], sm[NQ][c], Lm, z0.rho[c], s0[NQ][c], L0) * Sf * dt;
+#pragma unroll
+      for (int q = 0; q < NQ; q++)
+        FQ[q][c] = vl_star(w, dt, zm.q[q][c], sm[q][c], Lm, z0.q[q][c], s0[q][c], L0) * Fr[c];
+    }
+    if (f > a0) {
+      // Z update of plane k = f - 1, then its ring
+      const int k = f - 1;
+      const F vi = (F)m.Vinv(j, k);
+      F Ra[M], Qall[NQ][M], w[M];
+#pragma unroll
+      for (int c = 0; c < M; c++) {
+        Ra[c] = zm.rho[c] - vi * (Fr[c] - Fp[c]);
+        w[c] = zm.vx[c];
+#pragma unroll
+        for (int t = 0; t < NQ; t++) {
+          const int q = ring_qorder<NQ>(t);
+          Qall[t][c] = zm.rho[c] * zm.q[q][c] - vi * (FQ[q][c] - FQp[q][c]);
+        }
+      }
+      const int r = (k - m.k0) * m.ny + (j - m.j0);
+      const RingConst<F> C = ring_const<F>(m, j, k, r, dtd, v0);
+      ring_update<F, NQ>(L, C, m.o32(0, j, k), Ra, w, Qall, Tout, has_e, s);
+    }
+#pragma unroll
+    for (int c = 0; c < M; c++) {
+      Fp[c] = Fr[c];
+#pragma unroll
+      for (int q = 0; q <= NQ; q++) sm[q][c] = s0[q][c];
+#pragma unroll
+      for (int q = 0; q < NQ; q++) FQp[q][c] = FQ[q][c];
+    }
+    zm = z0;
+    z0 = zp;
+    Lm = L0;
+  }
+}
+
 // ------------------------------------------------------------------------
 // 12d along Y and Z on the owned faces (Eq. 18 with Tab. "momenta").
 // ------------------------------------------------------------------------
@@ -792,6 +933,20 @@ void launch_ring_x(Launch &L, const Mesh &m, const F *vx2, const TSetT<F> &T, co
   prof_end(L, K_RING_X);
 }
 
+// Fused Z sweep and X transport: one wave per (segment, row, chunk of planes).
+template <typename F>
+void launch_zx(Launch &L, const Mesh &m, const F *vx2, const F *vz, const TSetT<F> &T, const TSetT<F> &Tout,
+               const StateT<F> &s, const double *v0, const double *dt) {
+  constexpr int U = RingLane<F>::U;
+  const int nseg = (m.nx + U - 1) / U, nkc = (m.nz + m.chunk - 1) / m.chunk;
+  const long waves = (long)nseg * m.ny * nkc;
+  const unsigned nb = (unsigned)((waves + 3) / 4);
+  prof_begin(L, K_ZX);
+  if (T.nq == 7) k_zx<F, 7><<<nb, 256, 0, L.s>>>(m, vx2, vz, T, Tout, s, v0, dt, nseg, nkc);
+  else k_zx<F, 6><<<nb, 256, 0, L.s>>>(m, vx2, vz, T, Tout, s, v0, dt, nseg, nkc);
+  prof_end(L, K_ZX);
+}
+
 template <typename F>
 void launch_vel(Launch &L, const Mesh &m, const StateT<F> &s, const TSetT<F> &T) {
   int nib, bs;
@@ -812,5 +967,7 @@ void launch_vel(Launch &L, const Mesh &m, const StateT<F> &s, const TSetT<F> &T)
 FARGO_TRANSPORT_INST(double)
 FARGO_TRANSPORT_INST(float)
 #undef FARGO_TRANSPORT_INST
+template void launch_zx<float>(Launch &, const Mesh &, const float *, const float *, const TSetT<float> &,
+                               const TSetT<float> &, const StateT<float> &, const double *, const double *);
 
 } // namespace fargo
