@@ -710,8 +710,9 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
 // swept along Z as well, so segments stay independent.  The conserved
 // quantities handed on are formed again as rho (Q/rho).
 // Used for the FP32-bulk state, where the window and the X transport fit in
-// 168 VGPRs (three waves per SIMD); in FP64 the kernel needs about 310 (one
-// wave per SIMD) and the separate Z sweep and ring kernel are faster.
+// about 160 VGPRs (three waves per SIMD); in FP64 the kernel needs about 310
+// (one wave per SIMD) and the separate Z sweep and ring kernel are faster.
+// Its quotients, in the Z part as in the X part, are those of ring_div.
 template <typename F, int NQ>
 __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2, const F *__restrict__ vz,
                                             TSetT<F> T, TSetT<F> Tout, StateT<F> s, const double *__restrict__ v0,
@@ -748,7 +749,7 @@ __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2
   auto derive = [&](const Zr &r, Zw &z) {
 #pragma unroll
     for (int c = 0; c < M; c++) {
-      const F ri = F(1) / r.rho[c];
+      const F ri = ring_rcp(r.rho[c]);
       z.rho[c] = r.rho[c];
       z.w[c] = r.w[c];
       z.vx[c] = r.vx[c];
@@ -757,6 +758,11 @@ __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2
     }
   };
   auto Lz = [&](int a) { return (F)m.Lz(j, a); };
+  // the van Leer slope of vl_slope with the quotient of ring_div
+  auto vl_slope_q = [](F qm, F q0, F qp, F hm, F hp) {
+    const F dm = q0 - qm, dp = qp - q0, pr = dm * dp;
+    return pr > F(0) ? ring_div(F(2) * pr, dm * hp + dp * hm) : F(0);
+  };
   auto hz = [&](int f) { return (F)m.hz(j, f); };
   Zw zm, z0, zp;
   Zr rn;
@@ -772,9 +778,9 @@ __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2
     const F hm = hz(a0 - 1), hp = hz(a0);
 #pragma unroll
     for (int c = 0; c < M; c++) {
-      sm[NQ][c] = vl_slope(zp.rho[c], zm.rho[c], z0.rho[c], hm, hp);
+      sm[NQ][c] = vl_slope_q(zp.rho[c], zm.rho[c], z0.rho[c], hm, hp);
 #pragma unroll
-      for (int q = 0; q < NQ; q++) sm[q][c] = vl_slope(zp.q[q][c], zm.q[q][c], z0.q[q][c], hm, hp);
+      for (int q = 0; q < NQ; q++) sm[q][c] = vl_slope_q(zp.q[q][c], zm.q[q][c], z0.q[q][c], hm, hp);
     }
   }
   F Fp[M], FQp[NQ][M];
@@ -793,9 +799,9 @@ __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2
     F Fr[M], FQ[NQ][M];
 #pragma unroll
     for (int c = 0; c < M; c++) {
-      s0[NQ][c] = vl_slope(zm.rho[c], z0.rho[c], zp.rho[c], hm, hp);
+      s0[NQ][c] = vl_slope_q(zm.rho[c], z0.rho[c], zp.rho[c], hm, hp);
 #pragma unroll
-      for (int q = 0; q < NQ; q++) s0[q][c] = vl_slope(zm.q[q][c], z0.q[q][c], zp.q[q][c], hm, hp);
+      for (int q = 0; q < NQ; q++) s0[q][c] = vl_slope_q(zm.q[q][c], z0.q[q][c], zp.q[q][c], hm, hp);
       const F w = z0.w[c];
       Fr[c] = w * vl_star(w, dt, zm.rho[c], sm[NQ][c], Lm, z0.rho[c], s0[NQ][c], L0) * Sf * dt;
 #pragma unroll
