@@ -400,7 +400,8 @@ def main():
                   ("%.0f GB/s" % entry["GBs"]) if "GBs" in entry else ""), file=sys.stderr)
         dom = max((k for k in kern if "alg_bytes" in kern[k]),
                   key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
-        step_alg = sum(wb * w * n for (w, n) in wpu.values())
+        # the kernels that ran, each as often per step as it was launched
+        step_alg = sum(e["alg_bytes"] * e["launches"] for e in kern.values() if "alg_bytes" in e) / args.steps
         return solver, {"value": value, "ms": ms, "kern": kern, "dom": dom, "step_alg": step_alg}
 
     copy_gbs = copy_bandwidth()
