@@ -84,10 +84,20 @@ def _small(name):
         return W.random_problem("cart", nx=70, ny=9, nz=7, eos="adi", seed=1)
     if name == "ring_2048":  # several ring segments per wave-group, FARGO shift
         return W.random_problem("cyl", nx=2048, ny=4, nz=1, eos="iso", seed=7, fargo=True)
+    # 3D meshes go through the fused Z/X kernel: two chunks of planes (the
+    # second ragged) and two ring segments with a ragged tail; then rings of
+    # one and three zones
+    if name == "cyl3d_chunks":
+        return W.random_problem("cyl", nx=130, ny=5, nz=70, eos="adi", seed=21, fargo=True)
+    if name == "ring_nx1_cyl3d":
+        return W.random_problem("cyl", nx=1, ny=9, nz=6, eos="adi", seed=12, fargo=True)
+    if name == "ring_nx3_sph3d":
+        return W.random_problem("sph", nx=3, ny=9, nz=6, eos="adi", seed=14, fargo=True)
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name", ["sph3d", "cyl3d_planet", "disk2d", "cart_random", "ring_2048"])
+@pytest.mark.parametrize("name", ["sph3d", "cyl3d_planet", "disk2d", "cart_random", "ring_2048", "cyl3d_chunks",
+                                  "ring_nx1_cyl3d", "ring_nx3_sph3d"])
 def test_fp32_one_step_vs_oracle(name):
     prob = _small(name)
     _say("fp32 one step", name, prob.params["nx"], prob.params["ny"], prob.params["nz"])

@@ -58,6 +58,8 @@ def _cases():
     yield "ring_nx1_cyl", lambda: W.random_problem("cyl", nx=1, ny=9, nz=6, eos="adi", seed=12, fargo=True)
     yield "ring_nx2_cart", lambda: W.random_problem("cart", nx=2, ny=9, nz=6, eos="adi", seed=13, fargo=True)
     yield "ring_nx3_sph", lambda: W.random_problem("sph", nx=3, ny=9, nz=6, eos="adi", seed=14, fargo=True)
+    # two chunks of planes in the Z sweep (the second ragged), two ring segments
+    yield "cyl3d_chunks", lambda: W.random_problem("cyl", nx=130, ny=5, nz=70, eos="adi", seed=21, fargo=True)
 
 
 def _with(prob, **kw):
