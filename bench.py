@@ -339,8 +339,8 @@ def main():
                     help="run one plain device copy of 2 GiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU hot path "
-              "(the multi-GPU slab decomposition is a design, not a measured path)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library's step runs on one device; the multi-GPU slab "
+              "decomposition is a design, not a measured path", file=sys.stderr)
         sys.exit(2)
 
     import torch
