@@ -82,7 +82,10 @@ __device__ inline double ring_bulk(const Mesh &m, const double (&v)[M], int tid,
   return 0.5 * (vmax + vmin);
 }
 
-// Rings in logical order (k fastest), XCD-contiguous; M zones per thread.
+// Rings in XCD-contiguous logical order, by tiles of 16 planes with k fastest
+// within a tile: the rings holding a ring's k + 1 and j + 1 neighbours (v_z
+// and v_y on its upper faces) were read one and 16 rings earlier, still in L2
+// except across a tile boundary.  M zones per thread.
 // The state may be stored in FP32 (R = float); the time step is always formed
 // in FP64 from the stored values.
 template <int M, typename R, int NB>
@@ -93,7 +96,10 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
   extern __shared__ double V[]; // the ring's v_x
   __shared__ double red[2 * MAXW];
   const unsigned L = xcd_remap(blockIdx.x, gridDim.x);
-  const int kk = (int)(L % (unsigned)m.nz), jj = (int)(L / (unsigned)m.nz);
+  constexpr int KT = 16;
+  const unsigned tile = L / ((unsigned)m.ny * KT), q = L % ((unsigned)m.ny * KT);
+  const int kb = (int)tile * KT, kt = min(KT, m.nz - kb);
+  const int kk = kb + (int)(q % (unsigned)kt), jj = (int)(q / (unsigned)kt);
   const int j = m.j0 + jj, k = m.k0 + kk;
   const int r = kk * m.ny + jj; // ring index (k - k0) * ny + (j - j0)
   const int tid = threadIdx.x, B = blockDim.x, n = m.nx;
