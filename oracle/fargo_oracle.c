@@ -6,8 +6,9 @@
  * benchmark's CPU-baseline leg may load this code.  It shares no code, header,
  * table or helper with the GPU library; it is written directly from the paper,
  * in the paper's order and notation, as plain loops over the mesh ("mesh
- * functions", Sect. 4.2).  Build: gcc -O2 -ffp-contract=off -fopenmp (no
- * fast-math); OpenMP only splits independent cells between threads.
+ * functions", Sect. 4.2).  Build: gcc -O3 -ffp-contract=off -fopenmp (no
+ * fast-math; -march=native for the timed CPU baseline); OpenMP only splits
+ * independent cells between threads.
  *
  * One full update (Sect. 3, Fig. "flowchart"):
  *   box 2   boundary fill (ghost layers)
@@ -377,70 +378,71 @@ static inline double pressure(const mesh_t *m, const orc_state *s, size_t c) {
 /* ------------------------------------------------------------------------ */
 /* Box 6: time step, Eq. cfl2 with items 1-4, and Eq. 38                     */
 /* ------------------------------------------------------------------------ */
+/* Eq. cfl2 as written: every item of the list is a time step Delta_j over a
+   speed, taken in each direction j of the mesh; the item's step dt_i is the
+   smallest over the directions.  A cell combines its items as
+   (sum_i dt_i^-2)^(-1/2), and the mesh step is C times the smallest cell step
+   over the active zones.  An item that does not apply, or whose speed
+   vanishes, is an infinite step and adds nothing to the sum.  Readings: the
+   speed of item 2 is the larger magnitude of the two faces bounding the cell
+   along j, with the residual velocity under orbital advection (Sect. 3.5.2);
+   item 3 acts on compressed directions only, as L / (4 C_av^2 |dv|); item 4 is
+   Delta^2 / (4 nu).  With orbital advection the shear limit of Eq. 38 is the
+   smallest C0 / |v_x(j)/dX_j - v_x(j+1)/dX_(j+1)| over radially adjacent
+   active zones, and the step is the smaller of the two. */
 static double cfl_dt(const mesh_t *m, const orc_state *s, const double *v0, int *err) {
-  /* Each item of Eq. cfl2 is evaluated as its inverse, the rate 1/dt_i: the
-     minimum over directions of Delta_j / u is the maximum of u / Delta_j, and
-     the cell's step is 1/sqrt(sum of squared rates), so the smallest step of
-     the mesh is 1/sqrt of the largest sum. */
   const orc_params *p = m->p;
-  double maxrate2 = 0.0;
-  double maxshear = 0.0;
+  double min_cell = INFINITY;  /* smallest (sum dt_i^-2)^(-1/2) */
+  double min_shear = INFINITY; /* smallest shear step of Eq. 38 */
   int bad = 0;
-  const double k3 = 4.0 * p->cvnr * p->cvnr;
-#pragma omp parallel for collapse(2) schedule(static) reduction(max : maxrate2) reduction(max : maxshear) reduction(| : bad)
+  const double c2av = p->cvnr * p->cvnr;
+  const int nd = m->d3 ? 3 : 2;
+#pragma omp parallel for collapse(2) schedule(static) reduction(min : min_cell) reduction(min : min_shear) reduction(| : bad)
   for (int k = m->k0; k < m->kn; k++)
     for (int j = m->j0; j < m->jn; j++) {
       double vbulk = p->fargo ? v0[(size_t)(k - m->k0) * m->ny + (j - m->j0)] : 0.0;
-      double Lx = DXlen(m, j, k), Lyy = Ly(m, j), Lzz = m->d3 ? Lz(m, j, k) : 0.0;
-      double iLx = 1.0 / Lx, iLy = 1.0 / Lyy, iLz = m->d3 ? 1.0 / Lzz : 0.0;
-      double Lmin = fmin(Lx, Lyy);
-      if (m->d3) Lmin = fmin(Lmin, Lzz);
-      double iL2 = 1.0 / (Lmin * Lmin);
+      double L[3] = {DXlen(m, j, k), Ly(m, j), m->d3 ? Lz(m, j, k) : 0.0};
       for (int i = 0; i < m->nx; i++) {
         size_t c = IX(i, j, k);
         int ip = imod(i + 1, m->nx);
+        /* velocities on the lower and upper faces of the cell along X, Y, Z */
+        double vlo[3] = {s->vx[c], s->vy[c], m->d3 ? s->vz[c] : 0.0};
+        double vup[3] = {s->vx[IX(ip, j, k)], s->vy[IX(i, j + 1, k)], m->d3 ? s->vz[IX(i, j, k + 1)] : 0.0};
         double rho = s->rho[c];
-        /* squared wave speed: c_s^2, or gamma P / rho */
-        double cw2;
-        if (p->eos == EOS_ISO) cw2 = s->cs[c] * s->cs[c];
-        else cw2 = p->gamma * ((p->gamma - 1.0) * s->e[c]) / rho;
-        if (!(rho > 0.0) || !isfinite(rho) || !isfinite(cw2) || !isfinite(s->vx[c]) || !isfinite(s->vy[c]) ||
-            (m->d3 && !isfinite(s->vz[c])))
+        /* sound speed: the static c_s, or sqrt(gamma P / rho) */
+        double cw = (p->eos == EOS_ISO) ? s->cs[c] : sqrt(p->gamma * ((p->gamma - 1.0) * s->e[c]) / rho);
+        if (!(rho > 0.0) || !isfinite(rho) || !isfinite(cw) || !isfinite(vlo[0]) || !isfinite(vlo[1]) ||
+            !isfinite(vlo[2]))
           bad = 1;
-        /* item 1: sound waves, c_w / Delta (squared) */
-        double r1s = cw2 * iL2;
-        /* item 2: fluid motion, |V_j| / Delta_j, with the residual velocity under orbital advection */
-        double ux = fmax(fabs(s->vx[c] - vbulk), fabs(s->vx[IX(ip, j, k)] - vbulk));
-        double uy = fmax(fabs(s->vy[c]), fabs(s->vy[IX(i, j + 1, k)]));
-        double r2 = fmax(ux * iLx, uy * iLy);
-        /* item 3: artificial viscosity, 4 C^2 |dv_j| / Delta_j on compressed directions */
-        double dvx = s->vx[IX(ip, j, k)] - s->vx[c];
-        double dvy = s->vy[IX(i, j + 1, k)] - s->vy[c];
-        double r3 = 0.0;
-        if (dvx < 0.0) r3 = fmax(r3, k3 * fabs(dvx) * iLx);
-        if (dvy < 0.0) r3 = fmax(r3, k3 * fabs(dvy) * iLy);
-        if (m->d3) {
-          double uz = fmax(fabs(s->vz[c]), fabs(s->vz[IX(i, j, k + 1)]));
-          r2 = fmax(r2, uz * iLz);
-          double dvz = s->vz[IX(i, j, k + 1)] - s->vz[c];
-          if (dvz < 0.0) r3 = fmax(r3, k3 * fabs(dvz) * iLz);
+        double dt1 = INFINITY, dt2 = INFINITY, dt3 = INFINITY, dt4 = INFINITY;
+        for (int d = 0; d < nd; d++) {
+          /* item 1: sound waves */
+          if (cw > 0.0) dt1 = fmin(dt1, L[d] / cw);
+          /* item 2: fluid motion (residual azimuthal velocity with orbital advection) */
+          double blk = d == 0 ? vbulk : 0.0;
+          double u = fmax(fabs(vlo[d] - blk), fabs(vup[d] - blk));
+          if (u > 0.0) dt2 = fmin(dt2, L[d] / u);
+          /* item 3: artificial viscosity, where the flow is compressed along d */
+          double dv = vup[d] - vlo[d];
+          if (dv < 0.0 && c2av > 0.0) dt3 = fmin(dt3, L[d] / (4.0 * c2av * fabs(dv)));
+          /* item 4: kinematic viscosity */
+          if (p->visc && s->nu[c] > 0.0) dt4 = fmin(dt4, L[d] * L[d] / (4.0 * s->nu[c]));
         }
-        double rate2 = r1s + r2 * r2 + r3 * r3;
-        if (p->visc) {
-          /* item 4: viscosity, 4 nu / Delta^2 */
-          double r4 = 4.0 * s->nu[c] * iL2;
-          rate2 += r4 * r4;
-        }
-        if (rate2 > maxrate2) maxrate2 = rate2;
-        /* Eq. 38: shear between radially adjacent active zones */
+        double sum = 1.0 / (dt1 * dt1) + 1.0 / (dt2 * dt2) + 1.0 / (dt3 * dt3) + 1.0 / (dt4 * dt4);
+        double cell = 1.0 / sqrt(sum);
+        if (cell < min_cell) min_cell = cell;
+        /* Eq. 38 between this zone and its radial neighbour j + 1, both active */
         if (p->fargo && p->shear_c0 > 0.0 && j + 1 < m->jn) {
-          double sh = fabs(s->vx[c] / Lx - s->vx[IX(i, j + 1, k)] / DXlen(m, j + 1, k));
-          if (sh > maxshear) maxshear = sh;
+          double rate = fabs(s->vx[c] / L[0] - s->vx[IX(i, j + 1, k)] / DXlen(m, j + 1, k));
+          if (rate > 0.0) {
+            double tsh = p->shear_c0 / rate;
+            if (tsh < min_shear) min_shear = tsh;
+          }
         }
       }
     }
-  double dt = p->courant * (1.0 / sqrt(maxrate2));
-  if (p->fargo && p->shear_c0 > 0.0 && maxshear > 0.0) dt = fmin(dt, p->shear_c0 / maxshear);
+  double dt = p->courant * min_cell;
+  if (p->fargo && p->shear_c0 > 0.0) dt = fmin(dt, min_shear);
   if (bad) *err = ORC_ENONFINITE;
   else if (!(dt > 0.0) || !isfinite(dt)) *err = ORC_ECFL;
   return dt;

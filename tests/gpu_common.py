@@ -1,7 +1,8 @@
 """Helpers shared by the GPU tests: running the library and the oracle on the
-same seeded inputs, the normwise error of the design notes (velocities
-normalised by the largest speed of any component), and sub-block extraction
-for sampled parity at full size."""
+same seeded inputs, the normwise errors (velocities normalised by the largest
+speed of any component, and each component by its own largest value), the
+bound between the two codes' time steps, and sub-block extraction for sampled
+parity at full size."""
 import numpy as np
 
 from paper_1602_02359_amd import workloads as W
@@ -41,6 +42,47 @@ def errors(prob, got, ref, keys=("rho", "e", "vx", "vy", "vz")):
         den = vmax if k.startswith("v") else np.abs(b[sl]).max()
         out[k] = float(num / den) if den > 0 else float(num)
     return out
+
+
+def errors_own(prob, got, ref, keys=("vx", "vy", "vz")):
+    """Per-component normwise L_inf errors of the velocities, each normalised
+    by its own largest value over what the step defines (absolute where that
+    value is zero).  Orbital and radial velocities differ by orders of
+    magnitude in a disk, so this is the stricter figure for v_y and v_z."""
+    out = {}
+    for k in keys:
+        a, b = got.get(k), ref.get(k)
+        if b is None:
+            continue
+        sl = owned(prob, k)
+        if not b[sl].size:
+            continue
+        num = np.abs(a[sl] - b[sl]).max()
+        den = np.abs(b[sl]).max()
+        out[k] = float(num / den) if den > 0 else float(num)
+    return out
+
+
+# Box 6 in the two codes.  The oracle evaluates Eq. cfl2 as written: a step
+# L/u per item and direction, the smallest over directions, dt_i^-2 summed,
+# (sum)^(-1/2), the smallest over cells, times C.  The library forms the same
+# number through rates: u/L maximised over directions, squared and summed,
+# the largest sum over cells, C/sqrt(sum).  Both take only correctly rounded
+# operations (unit u = 2^-53) on the same FP64 inputs.  Along the smallest
+# cell's path the oracle accumulates at most about 7.5u of relative error
+# (a division or square root per item, its square and reciprocal, three
+# additions, the square root, the reciprocal and C), the library about 8u
+# (a reciprocal and a product per rate, its square, three additions, the
+# square root, the division); the minimum over cells keeps a bound that every
+# cell obeys.  The shear limit of Eq. 38 is formed by the same operations in
+# the same order on both sides, so it agrees bit for bit.  Bound: twice the
+# sum, 32u relative.
+DT_REL = 32.0 * 2.0 ** -53
+
+
+def dt_close(got, ref):
+    """True if two time steps agree within the bound above."""
+    return abs(got - ref) <= DT_REL * abs(ref)
 
 
 def gpu_solver(prob):

@@ -1,8 +1,13 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-Bars: integer work (shift amounts, circular shifts) and the time step are
-bit-exact; floating-point state is within 1e-12 normwise (velocities
-normalised by the largest speed) after one step, as the target states.
+Bars: integer work (shift amounts, circular shifts) and the ring split are
+bit-exact; the time step agrees within the bound derived in gpu_common
+(32 units in the last place: the oracle writes Eq. cfl2 as printed, the
+library through rates); floating-point state is within 1e-12 normwise after
+one step, as the target states, both with velocities normalised by the
+largest speed and with each velocity component normalised by its own
+largest value.  The state is compared at the oracle's time step, imposed on
+the library, so that both take the same shift amounts.
 """
 import math
 import sys
@@ -12,7 +17,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1602_02359_amd import workloads as W
-from gpu_common import NG, errors, gpu_solver, sub_problem
+from gpu_common import NG, dt_close, errors, errors_own, gpu_solver, sub_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -77,18 +82,16 @@ def test_one_step_matches_oracle(name):
     ref = prob.copy_fields()
     dt_ref = O.step(prob.params, ref)
     s = gpu_solver(prob)
-    s.fargo_step(0.0)
+    dt_gpu = s.fargo_cfl_dt()
+    assert dt_close(dt_gpu, dt_ref), (dt_gpu, dt_ref)
+    s.fargo_step(dt_ref)
     s.fargo_check()
-    dt_gpu = s.fargo_get_dt()
     got = s.download()
-    if prob.params.get("v0_mode") == "mean":
-        # the azimuthal mean is a sum: its rounding depends on the order
-        assert abs(dt_gpu / dt_ref - 1.0) < 1e-14, (dt_gpu, dt_ref)
-    else:
-        assert dt_gpu == dt_ref, (dt_gpu, dt_ref)
-    err = errors(prob, got, ref)
-    _say(name, "dt", dt_gpu, "errors", err)
+    err, own = errors(prob, got, ref), errors_own(prob, got, ref)
+    _say(name, "dt", dt_gpu, dt_ref, "errors", err, "per component", own)
     for k, e in err.items():
+        assert e <= TOL, (k, e)
+    for k, e in own.items():
         assert e <= TOL, (k, e)
 
 
@@ -104,7 +107,7 @@ def test_several_steps_match_oracle(name):
         s.fargo_step(0.0)
         dt = s.fargo_get_dt()
         if n == 0:
-            assert dt == dt_ref
+            assert dt_close(dt, dt_ref), (dt, dt_ref)
         else:
             # the states now differ by rounding, and so may the time steps
             assert abs(dt / dt_ref - 1.0) < 1e-12, (n, dt, dt_ref)
@@ -120,7 +123,7 @@ def test_imposed_dt_and_cfl_readback():
     ref = prob.copy_fields()
     dt_ref = O.cfl_dt(prob.params, ref)
     s = gpu_solver(prob)
-    assert s.fargo_cfl_dt() == dt_ref
+    assert dt_close(s.fargo_cfl_dt(), dt_ref)
     got0 = s.download()
     for k in ("rho", "vx", "vy", "vz", "e"):  # box 2 on both sides, ghosts included
         assert np.array_equal(got0[k], ref[k]), k
@@ -280,10 +283,20 @@ def test_full_size_sampled(cfg):
     full = {k: (None if v is None else v.copy()) for k, v in f0.items()}
     dt_ref = O.cfl_dt(p, full)  # fills the ghosts of `full` (box 2)
     s = gpu_solver(prob)
+    dt = s.fargo_cfl_dt()
+    assert dt_close(dt, dt_ref), (dt, dt_ref)
+    # v0, shift amounts and residuals of every ring at the library's time
+    # step, against the oracle's split of the same velocities
+    g0, gN, gxi = s.fargo_ring_split(s.state["vx"], dt)
+    o0, oN, oxi = O.ring_split(p, full["vx"], dt)
+    torch.cuda.synchronize()
+    assert np.array_equal(g0.cpu().numpy(), o0.ravel())
+    assert np.array_equal(gN.cpu().numpy(), oN.ravel())
+    assert np.array_equal(gxi.cpu().numpy(), oxi.ravel())
+    del g0, gN, gxi
     s.fargo_step(0.0)
     s.fargo_check()
-    dt = s.fargo_get_dt()
-    assert dt == dt_ref, (dt, dt_ref)
+    assert s.fargo_get_dt() == dt  # the step's own time step, formed on the device again
     got = s.download()
     del s
     torch.cuda.empty_cache()
@@ -318,7 +331,7 @@ def test_disk2d_full_ten_steps():
         dt_ref = O.step(prob.params, ref)
         s.fargo_step(0.0)
         dt = s.fargo_get_dt()
-        assert (dt == dt_ref) if n == 0 else abs(dt / dt_ref - 1.0) < 1e-12, (n, dt, dt_ref)
+        assert dt_close(dt, dt_ref) if n == 0 else abs(dt / dt_ref - 1.0) < 1e-12, (n, dt, dt_ref)
     s.fargo_check()
     err = errors(prob, s.download(), ref)
     _say("disk2d 10 steps", err)

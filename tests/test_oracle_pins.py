@@ -400,6 +400,119 @@ def test_shear_limit_active_only_for_unresolved_scale_height():
             assert on == off
 
 
+def _cart2d(nx=4, ny=5, xlen=4.0, ylo=0.0, yhi=2.5, cs=0.01, **kw):
+    """A Cartesian 2D box at rest, isothermal, with FIXED Y sides (ghosts and
+    boundary faces as the caller writes them)."""
+    kw.setdefault("bc", ("fixed", "fixed", "reflect", "reflect"))
+    p = W.default_params(geometry="cart", nx=nx, ny=ny, nz=1, xmin=0.0, xmax=xlen,
+                         ymin=W.uniform_faces(ylo, yhi, ny), zmin=np.array([0.0, 1.0]), eos="iso", **kw)
+    pr = W._blank(p)
+    pr.fields["cs"][:] = cs
+    return pr
+
+
+def test_cfl_item2_takes_both_faces_of_a_cell():
+    """Item 2 of Eq. cfl2 with the speed of a cell read on both of its faces
+    along j (reading R11).  A 4 x 5 box (dx = 1, dy = 0.5) at rest but for the
+    boundary faces: v_y = V on the upper face of the top row (column 2) and
+    -2V on the lower face of the bottom row (column 1); the walls are FIXED, so
+    box 2 keeps both, and item 3 is off.  The bottom cell of column 1 limits:
+    its steps are 0.5/(2V) (item 2) and min(1, 0.5)/c_s (item 1), so
+    dt = C / sqrt((2V/0.5)^2 + (c_s/0.5)^2).  Without the -2V face the top
+    cell of column 2 limits, with V in place of 2V; a cell read on one face
+    only misses one of the two."""
+    V, cs = 3.0, 0.01
+    for lo, hi in ((-2 * V, V), (0.0, V), (-2 * V, 0.0)):
+        pr = _cart2d(cs=cs, cvnr=0.0)
+        f = pr.fields
+        f["vy"][0, NG, 1] = lo          # lower face of the bottom active row
+        f["vy"][0, NG + 5, 2] = hi      # upper face of the top active row
+        u = max(abs(lo), abs(hi))
+        expect = 0.44 / math.sqrt((u / 0.5) ** 2 + (cs / 0.5) ** 2)
+        dt = O.cfl_dt(pr.params, pr.copy_fields())
+        assert abs(dt / expect - 1.0) < 1e-15, (lo, hi, dt, expect)
+
+
+def test_cfl_item3_uniform_compression():
+    """Item 3 of Eq. cfl2 (reading R9: L / (4 C_av^2 |dv|) on compressed
+    directions) in a uniform compression v_y = -a y on [-2, 2], 8 rows of 0.5,
+    with c_s = 0 and FIXED walls.  Every row has dv = -a dy, so item 3 gives
+    1/(4 C_av^2 a) = 1/(8a) for C_av = sqrt(2); item 2 is largest in the two
+    end rows, where |v_y| = 2a on the wall face: 0.5/(2a).  Hence
+    dt = C / (a sqrt(4^2 + 8^2)) = C / (a sqrt(80)), and without the factor 4
+    on C_av^2 it would be C / (a sqrt(20))."""
+    a = 1.7
+    pr = _cart2d(ny=8, ylo=-2.0, yhi=2.0, cs=0.0)
+    y = pr.params["ymin"][:-1]
+    pr.fields["vy"][0, :, :] = (-a * y)[:, None]
+    dt = O.cfl_dt(pr.params, pr.copy_fields())
+    assert abs(dt / (0.44 / (a * math.sqrt(80.0))) - 1.0) < 1e-14, dt
+    # the same compression along Z in 3D (the third direction of the item)
+    p = W.default_params(geometry="cart", nx=3, ny=3, nz=8, xmin=0.0, xmax=3.0,
+                         ymin=W.uniform_faces(0.0, 3.0, 3), zmin=W.uniform_faces(-2.0, 2.0, 8), eos="iso",
+                         bc=("reflect", "reflect", "fixed", "fixed"))
+    pz = W._blank(p)
+    pz.fields["cs"][:] = 0.0
+    z = p["zmin"][:-1]
+    pz.fields["vz"][:] = (-a * z)[:, None, None]
+    dt = O.cfl_dt(p, pz.copy_fields())
+    assert abs(dt / (0.44 / (a * math.sqrt(80.0))) - 1.0) < 1e-14, dt
+
+
+def _rings(omegas, nx=16, rin=1.0, rout=2.0, cs=0.01):
+    """A cylindrical 2D disk whose ring j turns rigidly at the angular speed
+    omegas[j] (ghost rings included), with orbital advection on."""
+    ny = len(omegas) - 2 * NG
+    p = W.default_params(geometry="cyl", nx=nx, ny=ny, nz=1, xmin=0.0, xmax=2 * math.pi,
+                         ymin=W.uniform_faces(rin, rout, ny), zmin=np.array([0.0, 1.0]), eos="iso",
+                         fargo=True, bc=("fixed", "fixed", "reflect", "reflect"))
+    pr = W._blank(p)
+    pr.fields["cs"][:] = cs
+    r = W.centres(p["ymin"])
+    pr.fields["vx"][0, :, :] = (np.asarray(omegas) * r)[:, None]
+    return pr
+
+
+def test_shear_limit_eq38_compares_angular_speeds():
+    """Eq. 38 divides each ring's velocity by its own azimuthal length, so it
+    measures the difference of angular speeds.  A rigid rotation (any rate)
+    has no shear and the sound speed sets dt = C min(dr, r dphi)/c_s; rings
+    turning at 10 j (j the ring index) differ by 10 everywhere, so the shear
+    step is C0 dphi / 10 and binds.  With orbital advection the rings' own
+    rotation is removed from item 2 (uniform rings: no residual)."""
+    ny = 8
+    rigid = _rings([50.0] * (ny + 2 * NG))
+    dt = O.cfl_dt(rigid.params, rigid.copy_fields())
+    dphi = 2 * math.pi / 16
+    assert abs(dt / (0.44 * min(1.0 / ny, 1.0 * dphi) / 0.01) - 1.0) < 1e-14, dt
+    diff = _rings([10.0 * j for j in range(ny + 2 * NG)])
+    dt = O.cfl_dt(diff.params, diff.copy_fields())
+    assert abs(dt / (0.44 * dphi / 10.0) - 1.0) < 1e-13, dt
+
+
+def test_v0_mean_mode_by_brute_force():
+    """v0 as the azimuthal mean (Sect. 3.5.1, the alternative to Eq. 37), on
+    dyadic values whose sum is exact in any order, so the mean is the brute
+    force one to the last bit; then its effect on item 2 of Eq. cfl2: a ring
+    reading (0, 0, 0, V) has v0 = V/4 and a largest residual 3V/4 (against
+    V/2 for the midrange), so dt = C dx / (3V/4)."""
+    rng = np.random.default_rng(17)
+    pr = W.random_problem("cyl", nx=64, ny=5, nz=4, seed=3)
+    p = dict(pr.params, v0_mode="mean", fargo=True)
+    vx = pr.fields["vx"].copy()
+    vx[:] = rng.integers(-1024, 1024, size=vx.shape) / 256.0
+    v0, N, xi = O.ring_split(p, vx, 0.01)
+    ring = vx[NG:NG + 4, NG:NG + 5, :]
+    assert np.array_equal(v0, ring.sum(axis=2) / 64.0)
+    assert not np.array_equal(v0, 0.5 * (ring.max(axis=2) + ring.min(axis=2)))
+    V = 0.8
+    for mode, resid in (("mean", 0.75 * V), ("minmax", 0.5 * V)):
+        q = _cart2d(nx=4, ny=3, xlen=4.0, cs=0.0, cvnr=0.0, fargo=True, v0_mode=mode)
+        q.fields["vx"][0, :, 3] = V
+        dt = O.cfl_dt(q.params, q.copy_fields())
+        assert abs(dt / (0.44 * 1.0 / resid) - 1.0) < 1e-15, (mode, dt)
+
+
 # ---------------------------------------------------------------------------
 # Whole step: invariants and physics
 # ---------------------------------------------------------------------------
