@@ -92,7 +92,14 @@ extern "C" {
    with its gradient formed in FP64 (a difference of nearly equal values:
    FP32 storage would make its relative error eps r/dr, the round-off the
    paper's Sect. 6 traces through derivatives).  The geometric coefficients
-   are FP64 tables rounded to FP32 where they enter bulk arithmetic. */
+   are FP64 tables rounded to FP32 where they enter bulk arithmetic.
+   In FP32_BULK the vx array holds v_x - vb[k][j], the deviation from a
+   per-ring FP64 background vb set with fargo_set_vx_background (zero until
+   set), and the X momenta are transported as the same deviations: FP32
+   rounding is then relative to the deviation, not to the orbital speed,
+   whose rounding (eps v_K per zone and step) would otherwise enter the
+   divergence of the residual velocity at every step (Sect. 6, through
+   derivatives).  Box 6, the split and the sums use vb + vx in FP64. */
 #define FARGO_FP64 0
 #define FARGO_FP32_BULK 1
 
@@ -155,6 +162,17 @@ int fargo_workspace_bytes(const fargo_params *params, size_t *bytes);
    on the host in FP64 and uploads them (synchronously).  *out is set on
    success only. */
 int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, fargo_ctx **out);
+
+/* FARGO_FP32_BULK contexts only (FARGO_EINVAL otherwise): set the FP64
+   background vb of the azimuthal velocity, one value per ring of the whole
+   mesh, ghosts included: `vb` is host memory of nz_g * ny_g doubles indexed
+   [k][j] (finite; FARGO_EINVAL otherwise), copied synchronously.  From then
+   on the context reads and writes the state's vx as v_x - vb (see
+   FARGO_FP32_BULK); a caller that changes vb must rewrite vx to match.  A
+   good background is the ring's mean azimuthal velocity (for a disk, its
+   rotation curve in the frame); any choice gives the same step in exact
+   arithmetic. */
+int fargo_set_vx_background(fargo_ctx *ctx, const double *vb);
 
 /* Release the context (synchronises the device first).  NULL is a no-op. */
 void fargo_destroy(fargo_ctx *ctx);

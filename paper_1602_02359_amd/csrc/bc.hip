@@ -7,7 +7,8 @@
 // first interior face; FIXED writes nothing.  Boundary faces are set by one
 // launch and ghosts by a second one, so that ghost faces mirror final values;
 // the Y sides are filled over every Z row before the Z sides over every Y
-// column (corners consistent).
+// column (corners consistent).  An FP32 v_x (a deviation from its ring's
+// background) is copied with the difference of the two rings' backgrounds.
 #include "fargo_internal.h"
 
 namespace fargo {
@@ -18,6 +19,7 @@ template <typename R>
 struct Cen {
   R *p[4];
   int n;
+  int ivx; // index of v_x in p (-1 if absent)
 };
 
 __device__ inline size_t at(const Mesh &m, int dir, int i, int a, int b) {
@@ -65,6 +67,16 @@ __global__ __launch_bounds__(256) void k_bc_ghosts(Mesh m, int dir, int side, in
   }
   size_t d = at(m, dir, i, dst, b), s = at(m, dir, i, src, b);
   for (int q = 0; q < cen.n; q++) cen.p[q][d] = cen.p[q][s];
+  if constexpr (sizeof(R) == 4) {
+    // FP32 v_x is a deviation from the ring's background: the ghost takes the
+    // source's full velocity, so the two backgrounds' difference is added
+    if (cen.ivx >= 0) {
+      const int jd = dir == 1 ? dst : b, kd = dir == 1 ? b : dst;
+      const int js = dir == 1 ? src : b, ks = dir == 1 ? b : src;
+      const double off = m.bg(BG_V, js, ks) - m.bg(BG_V, jd, kd);
+      cen.p[cen.ivx][d] = cen.p[cen.ivx][s] + (R)off;
+    }
+  }
   if (fdst >= 0) vn[at(m, dir, i, fdst, b)] = sgn * vn[at(m, dir, i, fsrc, b)];
 }
 
@@ -98,6 +110,7 @@ void launch_bc(Launch &L, const Mesh &m, R *rho, R *e, R *vx, R *vy, R *vz) {
   Cen<R> cy{};
   cy.p[cy.n++] = rho;
   if (e) cy.p[cy.n++] = e;
+  cy.ivx = cy.n;
   cy.p[cy.n++] = vx;
   if (m.d3) cy.p[cy.n++] = vz;
   one_dir(L, m, 1, cy, vy);
@@ -105,6 +118,7 @@ void launch_bc(Launch &L, const Mesh &m, R *rho, R *e, R *vx, R *vy, R *vz) {
   Cen<R> cz{};
   cz.p[cz.n++] = rho;
   if (e) cz.p[cz.n++] = e;
+  cz.ivx = cz.n;
   cz.p[cz.n++] = vx;
   cz.p[cz.n++] = vy;
   one_dir(L, m, 2, cz, vz);

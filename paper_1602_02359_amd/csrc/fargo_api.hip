@@ -252,7 +252,7 @@ size_t geo_doubles(int nyg, int nzg) {
 }
 
 struct Layout {
-  size_t geo, words, v0, ringrate, ringshear, partial, sums, v2, T, total;
+  size_t geo, words, v0, ringrate, ringshear, partial, sums, bg, v2, T, total;
 };
 
 Layout layout(const fargo_params *p) {
@@ -277,6 +277,8 @@ Layout layout(const fargo_params *p) {
   o += al(nring * 10 * 8);
   L.sums = o;
   o += 256;
+  L.bg = o; // background tables of v_x (FP32-bulk state only)
+  if (p->precision == FARGO_FP32_BULK) o += al((size_t)BG_N * nyg * nzg * 8);
   L.v2 = o;
   o += al(nc * eb) * ((p->nz > 1 ? 3 : 2) + (p->eos == FARGO_ADIABATIC ? 1 : 0) + (p->visc ? 2 : 0));
   L.T = o;
@@ -321,6 +323,39 @@ int check_state(const fargo_ctx *c, const fargo_state *s) {
   if (c->p.eos == FARGO_ADIABATIC && !s->e) return FARGO_EINVAL;
   if (c->p.visc && !s->nu) return FARGO_EINVAL;
   return FARGO_OK;
+}
+
+// The background tables of an FP32-bulk context (enum BgTable) for the
+// per-ring background vb [nzg][nyg], formed on the host in FP64 and copied
+// to the device.
+int upload_background(fargo_ctx *ctx, const double *vb) {
+  const Mesh &m = ctx->m;
+  const int nyg = m.nyg, nzg = m.nzg;
+  const size_t n2 = (size_t)nyg * nzg;
+  HostGeo G;
+  make_geo(&ctx->p, G);
+  const bool cart = ctx->p.geometry == FARGO_CARTESIAN, sph = ctx->p.geometry == FARGO_SPHERICAL;
+  std::vector<double> tab((size_t)BG_N * n2, 0.0), ell(n2);
+  for (int k = 0; k < nzg; k++)
+    for (int j = 0; j < nyg; j++) {
+      const size_t r = (size_t)k * nyg + j;
+      const double R = cart ? 1.0 : (sph ? G.ymed[j] * G.sinz[k] : G.ymed[j]);
+      const double Rw = cart ? 0.0 : R * ctx->p.omega;
+      tab[BG_V * n2 + r] = vb[r];
+      tab[BG_VT * n2 + r] = vb[r] + Rw;
+      ell[r] = cart ? vb[r] : R * (vb[r] + Rw);
+    }
+  for (int k = 0; k < nzg; k++)
+    for (int j = 0; j < nyg; j++) {
+      const size_t r = (size_t)k * nyg + j;
+      if (j > 0) {
+        tab[BG_DLY * n2 + r] = ell[r] - ell[r - 1];
+        tab[BG_KV * n2 + r] =
+            (vb[r] - vb[r - 1]) / G.hy[j] - 0.5 * (vb[r] / G.ymed[j] + vb[r - 1] / G.ymed[j - 1]);
+      }
+      if (k > 0) tab[BG_DLZ * n2 + r] = ell[r] - ell[r - nyg];
+    }
+  return hip_ok(hipMemcpy((void *)m.bgt, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));
 }
 
 // boxes 2, 3, 4, 6 and the split of Eq. 29 (dt > 0: imposed)
@@ -472,6 +507,15 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
     fargo_destroy(c);
     return FARGO_EHIP;
   }
+  m.bgt = nullptr;
+  if (params->precision == FARGO_FP32_BULK) { // zero background until set
+    m.bgt = (const double *)(base + Lo.bg);
+    std::vector<double> zero((size_t)nyg * nzg, 0.0);
+    if (upload_background(c, zero.data()) != FARGO_OK) {
+      fargo_destroy(c);
+      return FARGO_EHIP;
+    }
+  }
   c->v0 = (double *)(base + Lo.v0);
   c->ringrate = (double *)(base + Lo.ringrate);
   c->ringshear = (double *)(base + Lo.ringshear);
@@ -506,6 +550,15 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   }
   *out = c;
   return FARGO_OK;
+}
+
+int fargo_set_vx_background(fargo_ctx *ctx, const double *vb) {
+  if (!ctx || !vb) return FARGO_EINVAL;
+  if (ctx->p.precision != FARGO_FP32_BULK) return FARGO_EINVAL;
+  const size_t n2 = (size_t)ctx->m.nyg * ctx->m.nzg;
+  for (size_t t = 0; t < n2; t++)
+    if (!std::isfinite(vb[t])) return FARGO_EINVAL;
+  return upload_background(ctx, vb);
 }
 
 void fargo_destroy(fargo_ctx *ctx) {

@@ -92,6 +92,22 @@ struct GeoTables {
   __device__ inline double inv_dxlen(size_t i) const { return t2(1, i); }
 };
 
+// Background of the azimuthal velocity (FP32-bulk state only): per-ring FP64
+// tables, [nzg][nyg] each, one after the other from Mesh::bgt.  The FP32
+// arrays of v_x (and of the X momenta in transport) hold deviations from it,
+// so that their rounding is relative to the deviation, not to the orbital
+// speed.  ell is the X-momentum factor of Tab. "momenta" applied to the
+// background (R (vb + R Omega), or vb on a Cartesian mesh).
+enum BgTable {
+  BG_V,   // vb: the background of v_x
+  BG_VT,  // vb + R Omega: the background of the inertial azimuthal velocity
+  BG_DLY, // ell(j, k) - ell(j - 1, k) (0 for j = 0)
+  BG_DLZ, // ell(j, k) - ell(j, k - 1) (0 for k = 0)
+  BG_KV,  // viscous edge term of the background (cylindrical 2D):
+          // (vb_j - vb_{j-1}) / h_j - (vb_j / r_j + vb_{j-1} / r_{j-1}) / 2
+  BG_N
+};
+
 struct Mesh {
   int nx, ny, nz, pitch, nyg, nzg, j0, jn, k0, kn, d3;
   int geo, eos, fargo, v0_mean, visc;
@@ -100,6 +116,12 @@ struct Mesh {
   int chunk; // zones per thread of the Y and Z column sweeps (a tuning parameter)
   double dx, gamma, omega, courant, cvnr, shear_c0;
   GeoTables g;
+  const double *bgt; // background tables (FP32-bulk state), NULL for FP64
+
+  // background table t of ring (j, k), read through the constant address space
+  __device__ inline double bg(int t, int j, int k) const {
+    return gk(bgt, (size_t)t * (size_t)g.n2 + (size_t)k * (size_t)nyg + (size_t)j);
+  }
 
   __host__ __device__ inline size_t idx(int i, int j, int k) const {
     return ((size_t)k * (size_t)nyg + (size_t)j) * (size_t)pitch + (size_t)i;
@@ -147,6 +169,13 @@ struct Mesh {
     if (geo == FARGO_CARTESIAN) return v;
     F R = (F)Rcyl(j, k);
     return R * (v + R * (F)omega);
+  }
+  // the same factor on a deviation from the background: R v (no frame term,
+  // which the background carries)
+  template <typename F>
+  __device__ inline F mxd(int j, int k, F v) const {
+    if (geo == FARGO_CARTESIAN) return v;
+    return (F)Rcyl(j, k) * v;
   }
   template <typename F>
   __device__ inline F vx_from(int j, int k, F m) const {

@@ -71,6 +71,8 @@ __global__ __launch_bounds__(256) void k_sums(Mesh m, StateT<F> s, double *__res
   int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
   int jp = m.jabove(j), kp = m.d3 ? m.kabove(k) : k;
   double V = m.Vol(j, k);
+  double vbg = 0.0; // an FP32 v_x is a deviation from the ring's FP64 background
+  if constexpr (sizeof(F) == 4) vbg = m.bg(BG_V, j, k);
   DD acc[5];
   for (int q = 0; q < 5; q++) acc[q] = DD{0.0, 0.0};
   for (int i = threadIdx.x; i < m.nx; i += blockDim.x) {
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(256) void k_sums(Mesh m, StateT<F> s, double *__res
     size_t c = m.idx(i, j, k);
     double rho = (double)s.rho[c];
     double t0 = rho * V;
-    double t1 = rho * 0.5 * (m.mx(j, k, (double)s.vx[c]) + m.mx(j, k, (double)s.vx[m.idx(ip, j, k)])) * V;
+    double t1 = rho * 0.5 * (m.mx(j, k, (double)s.vx[c] + vbg) + m.mx(j, k, (double)s.vx[m.idx(ip, j, k)] + vbg)) * V;
     double t2 = rho * 0.5 * ((double)s.vy[c] + (double)s.vy[m.idx(i, jp, k)]) * V;
     double t3 = m.d3 ? rho * 0.5 * (m.mz(j, (double)s.vz[c]) + m.mz(j, (double)s.vz[m.idx(i, j, kp)])) * V : 0.0;
     double t4 = s.e ? (double)s.e[c] * V : 0.0;

@@ -25,6 +25,9 @@
 //
 // The field type F is double, or float for the FP32-bulk state; arithmetic is
 // carried out in F, geometric factors are rounded to F where they are used.
+// An FP32 v_x is a deviation from its ring's FP64 background vb: the X-face
+// update acts on it unchanged, and the centrifugal terms add the ring's
+// vb + R Omega (formed in FP64, rounded once) where the frame term stood.
 #include <type_traits>
 
 #include "fargo_internal.h"
@@ -156,8 +159,17 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
     F gradPhi = (F)((z0.pot - zb.pot) * ihzd);
     F src = F(0);
     if (sph) {
-      F R0 = (F)(g_ymed * m.g.sinz(p)), R1 = (F)(g_ymed * m.g.sinz(m.kbelow(p)));
-      F vt = F(0.25) * ((z0.vx + R0 * om) + (z0.vxp + R0 * om) + (zb.vx + R1 * om) + (zb.vxp + R1 * om));
+      // inertial azimuthal velocity v_x + R Omega of the two rings; an FP32
+      // v_x is a deviation, and the ring's background vb + R Omega is added
+      F o0, o1;
+      if constexpr (sizeof(F) == 4) {
+        o0 = (F)m.bg(BG_VT, jg, p);
+        o1 = (F)m.bg(BG_VT, jg, m.kbelow(p));
+      } else {
+        o0 = (F)(g_ymed * m.g.sinz(p)) * om;
+        o1 = (F)(g_ymed * m.g.sinz(m.kbelow(p))) * om;
+      }
+      F vt = F(0.25) * ((z0.vx + o0) + (z0.vxp + o0) + (zb.vx + o1) + (zb.vxp + o1));
       src = vt * vt * (F)m.g.cotz(p) * (F)g_iymed;
     }
     return z0.vz - dt * (gradP + gradPhi) + dt * src;
@@ -261,10 +273,16 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
       F src = F(0);
       if (cyl || sph) {
         const int ya = yrow(t - 1);
-        const F Rt = (F)(sph ? m.g.ymed(f) * m.g.sinz(kk) : m.g.ymed(f));
-        const F Ra = (F)(sph ? m.g.ymed(ya) * m.g.sinz(kk) : m.g.ymed(ya));
-        const F vt0 = (L.VX[sb][t][sl] + Rt * om) + (L.VX[sb][t][sl + 1] + Rt * om);
-        const F vt1 = (L.VX[sb][t - 1][sl] + Ra * om) + (L.VX[sb][t - 1][sl + 1] + Ra * om);
+        F ot, oa; // R Omega, or the ring's vb + R Omega for an FP32 deviation
+        if constexpr (sizeof(F) == 4) {
+          ot = (F)m.bg(BG_VT, f, kk);
+          oa = (F)m.bg(BG_VT, ya, kk);
+        } else {
+          ot = (F)(sph ? m.g.ymed(f) * m.g.sinz(kk) : m.g.ymed(f)) * om;
+          oa = (F)(sph ? m.g.ymed(ya) * m.g.sinz(kk) : m.g.ymed(ya)) * om;
+        }
+        const F vt0 = (L.VX[sb][t][sl] + ot) + (L.VX[sb][t][sl + 1] + ot);
+        const F vt1 = (L.VX[sb][t - 1][sl] + oa) + (L.VX[sb][t - 1][sl + 1] + oa);
         const F v = F(0.25) * (vt0 + vt1);
         src = v * v;
         if (sph) {

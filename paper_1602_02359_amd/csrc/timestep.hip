@@ -128,11 +128,18 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
       if (shear_on) fs[mm] = s.vx[c + py];
     }
   }
+  // an FP32 v_x is a deviation from the ring's FP64 background: the full
+  // velocity is formed in FP64
+  double vbg = 0.0, vbg_p = 0.0;
+  if constexpr (sizeof(R) == 4) {
+    vbg = m.bg(BG_V, j, k);
+    if (shear_on) vbg_p = m.bg(BG_V, j + 1, k);
+  }
   double vx[M];
 #pragma unroll
   for (int mm = 0; mm < M; mm++) {
     int i = tid + B * mm;
-    vx[mm] = i < n ? (double)fx[mm] : 0.0;
+    vx[mm] = i < n ? (double)fx[mm] + vbg : 0.0;
     if (i < n) V[i] = vx[mm];
   }
   // the barriers of the reduction also make V visible to the block
@@ -191,7 +198,7 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
     if (!(rate2 >= 0.0)) bad = 1;
     else rmax = rate2 > rmax ? rate2 : rmax;
     if (shear_on) {
-      double sh = fabs(vxc / Lx - (double)fs[mm] / dXp);
+      double sh = fabs(vxc / Lx - ((double)fs[mm] + vbg_p) / dXp);
       if (sh > smax) smax = sh;
     }
   }

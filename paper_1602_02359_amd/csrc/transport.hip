@@ -22,7 +22,11 @@
 //
 // The field type F is double, or float for the FP32-bulk state; the arithmetic
 // of a kernel is carried out in F (per-ring constants such as dt/dX and the
-// PPA residual xi are formed in FP64 and rounded to F).
+// PPA residual xi are formed in FP64 and rounded to F).  In FP32, v_x and the
+// X momenta are deviations from a per-ring FP64 background (v_x - vb and
+// rho R (v_x - vb)): the Y and Z sweeps add the background's increments
+// between rings (column_sweep), the X transport, where it is constant, needs
+// nothing, and 12d forms the deviation again.
 #include <type_traits>
 
 #include "fargo_internal.h"
@@ -35,9 +39,24 @@ namespace {
 // van Leer slope per unit length from the one-sided differences and the
 // centre distances below (hm) and above (hp): 2 dl dr/(dl + dr) with
 // dl = dm/hm, dr = dp/hp, zero unless dl dr > 0.
+// Contraction is off in the slopes: a sweep forms the first slope of a chunk
+// of zones before its loop and the others inside it, and the same rounding
+// in both places keeps the result independent of the chunk size.
 template <typename F>
 __device__ inline F vl_slope(F qm, F q0, F qp, F hm, F hp) {
+#pragma clang fp contract(off)
   F dm = q0 - qm, dp = qp - q0;
+  F pr = dm * dp;
+  return pr > F(0) ? F(2) * pr / (dm * hp + dp * hm) : F(0);
+}
+
+// The same slope for a quantity stored as a deviation from a background that
+// changes from zone to zone: bm and bp are the background's increments across
+// the lower and upper face, so the differences are those of the full values.
+template <typename F>
+__device__ inline F vl_slope_b(F qm, F q0, F qp, F hm, F hp, F bm, F bp) {
+#pragma clang fp contract(off)
+  F dm = (q0 - qm) + bm, dp = (qp - q0) + bp;
   F pr = dm * dp;
   return pr > F(0) ? F(2) * pr / (dm * hp + dp * hm) : F(0);
 }
@@ -62,9 +81,17 @@ struct Zone {
 // (centre distance at face f), S(f), Vi(a); `st(a, rho, T[])` stores the
 // updated zone.  The loads of zone f + 2 are issued while zone f is being
 // computed.
-template <typename F, int NQ, bool CT, class RW, class RAW, class DER, class TOF, class GEO, class ST>
+// With DEV, quantities 0 and 1 (the X momenta) are deviations from a
+// background ell that is constant on a ring (the FP32-bulk state): `dl(f)`
+// gives ell(f) - ell(f - 1) at face f.  Slopes take the full differences,
+// the interface value is taken relative to the background of the face's
+// lower zone, and the update of a zone adds the background carried in
+// through its lower face, so that in exact arithmetic the result is the
+// full update minus ell times the updated density.
+template <typename F, int NQ, bool CT, bool DEV, class RW, class RAW, class DER, class TOF, class GEO, class ST,
+          class DLF>
 __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const DER &derive, const TOF &Tof,
-                                    const GEO &geo, const ST &st) {
+                                    const GEO &geo, const ST &st, const DLF &dl) {
   Zone<F, NQ, CT> zm, z0, zp;
   RW rn;
   raw(a0 - 2, rn);
@@ -75,11 +102,14 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
   derive(a0, rn, z0);
   raw(a0 + 1, rn);
   F sm[NQ + 1], s0[NQ + 1];
+  F dlf = DEV ? dl(a0) : F(0); // background increment at face f
   {
     F hm = geo.h(a0 - 1), hp = geo.h(a0);
     sm[NQ] = vl_slope(zp.rho, zm.rho, z0.rho, hm, hp);
 #pragma unroll
-    for (int q = 0; q < NQ; q++) sm[q] = vl_slope(zp.q[q], zm.q[q], z0.q[q], hm, hp);
+    for (int q = 0; q < NQ; q++)
+      sm[q] = (DEV && q < 2) ? vl_slope_b(zp.q[q], zm.q[q], z0.q[q], hm, hp, dl(a0 - 1), dlf)
+                             : vl_slope(zp.q[q], zm.q[q], z0.q[q], hm, hp);
   }
   F Fp = F(0), FQp[NQ];
 #pragma unroll
@@ -89,16 +119,20 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
   for (int f = a0; f <= a1; f++) {
     derive(f + 1, rn, zp);
     if (f + 2 <= a1 + 1) raw(f + 2, rn);
+    const F dlf1 = DEV ? dl(f + 1) : F(0);
     F hm = geo.h(f), hp = geo.h(f + 1);
     s0[NQ] = vl_slope(zm.rho, z0.rho, zp.rho, hm, hp);
 #pragma unroll
-    for (int q = 0; q < NQ; q++) s0[q] = vl_slope(zm.q[q], z0.q[q], zp.q[q], hm, hp);
+    for (int q = 0; q < NQ; q++)
+      s0[q] = (DEV && q < 2) ? vl_slope_b(zm.q[q], z0.q[q], zp.q[q], hm, hp, dlf, dlf1)
+                             : vl_slope(zm.q[q], z0.q[q], zp.q[q], hm, hp);
     F L0 = geo.L(f);
     F w = z0.w;
     F Fr = w * vl_star(w, dt, zm.rho, sm[NQ], Lm, z0.rho, s0[NQ], L0) * geo.S(f) * dt;
     F FQ[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; q++) FQ[q] = vl_star(w, dt, zm.q[q], sm[q], Lm, z0.q[q], s0[q], L0) * Fr;
+    for (int q = 0; q < NQ; q++)
+      FQ[q] = vl_star(w, dt, zm.q[q], sm[q], Lm, (DEV && q < 2) ? z0.q[q] + dlf : z0.q[q], s0[q], L0) * Fr;
     if (f > a0) {
       F vi = geo.Vi(f - 1);
       F Tn[NQ];
@@ -109,13 +143,15 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
     Fp = Fr;
 #pragma unroll
     for (int q = 0; q < NQ; q++) {
-      FQp[q] = FQ[q];
+      // the flux through face f relative to the background of its upper zone
+      FQp[q] = (DEV && q < 2) ? FQ[q] - dlf * Fr : FQ[q];
       sm[q] = s0[q];
     }
     sm[NQ] = s0[NQ];
     zm = z0;
     z0 = zp;
     Lm = L0;
+    dlf = dlf1;
   }
 }
 
@@ -139,6 +175,7 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
   const int a0 = m.j0 + ch * m.chunk, a1 = min(a0 + m.chunk, m.jn);
   const F dt = (F)*dtp;
   const int ip = i + 1 == m.nx ? 0 : i + 1;
+  constexpr bool DEV = sizeof(F) == 4;
   const unsigned pitch = m.pitch, plane = (unsigned)m.plane();
   struct Raw {
     F rho, vx0, vx1, vy0, vy1, vz0, vz1, e;
@@ -160,8 +197,13 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
     const F r = w.rho;
     z.rho = r;
     z.w = w.vy0;
-    z.q[0] = m.mx(a, k, w.vx0);
-    z.q[1] = m.mx(a, k, w.vx1);
+    if constexpr (DEV) { // FP32: v_x is a deviation, and so are the X momenta
+      z.q[0] = m.mxd(a, k, w.vx0);
+      z.q[1] = m.mxd(a, k, w.vx1);
+    } else {
+      z.q[0] = m.mx(a, k, w.vx0);
+      z.q[1] = m.mx(a, k, w.vx1);
+    }
     z.q[2] = w.vy0;
     z.q[3] = w.vy1;
     if (D3) {
@@ -193,7 +235,8 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
 #pragma unroll
     for (int q = 0; q < NQ; q++) out.q[q][c] = T[q];
   };
-  column_sweep<F, NQ, false, Raw>(a0, a1, dt, raw, derive, Tof, geo, st);
+  auto dl = [&](int f) { return (F)m.bg(BG_DLY, f, k); };
+  column_sweep<F, NQ, false, DEV, Raw>(a0, a1, dt, raw, derive, Tof, geo, st, dl);
 }
 
 // ------------------------------------------------------------------------
@@ -246,7 +289,8 @@ __global__ __launch_bounds__(256) void k_sweep_z(Mesh m, const F *__restrict__ v
 #pragma unroll
     for (int q = 0; q < NQ; q++) out.q[q][c] = T[q];
   };
-  column_sweep<F, NQ, true, Raw>(a0, a1, dt, raw, derive, Tof, geo, st);
+  auto dl = [&](int f) { return (F)m.bg(BG_DLZ, j, f); };
+  column_sweep<F, NQ, true, sizeof(F) == 4, Raw>(a0, a1, dt, raw, derive, Tof, geo, st, dl);
 }
 
 // Monotonised central slope of the PPA edge values (Eq. 34): zero at an
@@ -519,7 +563,10 @@ __device__ inline RingConst<F> ring_const(const Mesh &m, int j, int k, int r, do
   C.vinv = (F)m.Vinv(j, k);
   C.fg = m.fargo != 0;
   const double v0d = C.fg ? v0[r] : 0.0;
-  C.vb = (F)v0d;
+  // an FP32 v_x is a deviation from the ring's background vb: the residual
+  // velocity is v_x - (v0 - vb)
+  if constexpr (sizeof(F) == 4) C.vb = (F)(v0d - m.bg(BG_V, j, k));
+  else C.vb = (F)v0d;
   int N = 0;
   double xid = 0.0;
   if (C.fg) ring_split_at(v0d, dtd, dXd, N, xid);
@@ -534,7 +581,9 @@ __device__ inline RingConst<F> ring_const(const Mesh &m, int j, int k, int r, do
   } else {
     C.R = (F)m.Rcyl(j, k);
     C.iR = (F)(1.0 / m.Rcyl(j, k));
-    C.Rw = C.R * (F)m.omega;
+    // FP32: the X momenta are deviations R (v_x - vb) from the ring's
+    // background, and so is the v_x formed from them (no frame term)
+    C.Rw = sizeof(F) == 4 ? F(0) : C.R * (F)m.omega;
   }
   return C;
 }
@@ -758,11 +807,23 @@ __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2
     }
   };
   auto Lz = [&](int a) { return (F)m.Lz(j, a); };
-  // the van Leer slope of vl_slope with the quotient of ring_div
+  // the van Leer slopes of vl_slope and vl_slope_b with the quotient of
+  // ring_div
   auto vl_slope_q = [](F qm, F q0, F qp, F hm, F hp) {
+#pragma clang fp contract(off)
     const F dm = q0 - qm, dp = qp - q0, pr = dm * dp;
     return pr > F(0) ? ring_div(F(2) * pr, dm * hp + dp * hm) : F(0);
   };
+  auto vl_slope_qb = [](F qm, F q0, F qp, F hm, F hp, F bm, F bp) {
+#pragma clang fp contract(off)
+    const F dm = (q0 - qm) + bm, dp = (qp - q0) + bp, pr = dm * dp;
+    return pr > F(0) ? ring_div(F(2) * pr, dm * hp + dp * hm) : F(0);
+  };
+  // FP32: the X momenta (quantities 0 and 1) are deviations from a background
+  // constant on each ring, as in column_sweep; dl(f) is its increment across
+  // Z face f
+  constexpr bool DEV = sizeof(F) == 4;
+  auto dl = [&](int f) { return DEV ? (F)m.bg(BG_DLZ, j, f) : F(0); };
   auto hz = [&](int f) { return (F)m.hz(j, f); };
   Zw zm, z0, zp;
   Zr rn;
@@ -774,13 +835,16 @@ __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2
   derive(rn, z0);
   raw(a0 + 1, rn);
   F sm[NQ + 1][M], s0[NQ + 1][M];
+  F dlf = dl(a0); // background increment at face f
   {
-    const F hm = hz(a0 - 1), hp = hz(a0);
+    const F hm = hz(a0 - 1), hp = hz(a0), dlm = dl(a0 - 1);
 #pragma unroll
     for (int c = 0; c < M; c++) {
       sm[NQ][c] = vl_slope_q(zp.rho[c], zm.rho[c], z0.rho[c], hm, hp);
 #pragma unroll
-      for (int q = 0; q < NQ; q++) sm[q][c] = vl_slope_q(zp.q[q][c], zm.q[q][c], z0.q[q][c], hm, hp);
+      for (int q = 0; q < NQ; q++)
+        sm[q][c] = (DEV && q < 2) ? vl_slope_qb(zp.q[q][c], zm.q[q][c], z0.q[q][c], hm, hp, dlm, dlf)
+                                  : vl_slope_q(zp.q[q][c], zm.q[q][c], z0.q[q][c], hm, hp);
     }
   }
   F Fp[M], FQp[NQ][M];
@@ -795,18 +859,23 @@ __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2
   for (int f = a0; f <= a1; f++) {
     derive(rn, zp); // zone f + 1
     if (f + 2 <= a1 + 1) raw(f + 2, rn);
-    const F hm = hz(f), hp = hz(f + 1), L0 = Lz(f), Sf = (F)m.Sz(j, f);
+    const F hm = hz(f), hp = hz(f + 1), L0 = Lz(f), Sf = (F)m.Sz(j, f), dlf1 = dl(f + 1);
     F Fr[M], FQ[NQ][M];
 #pragma unroll
     for (int c = 0; c < M; c++) {
       s0[NQ][c] = vl_slope_q(zm.rho[c], z0.rho[c], zp.rho[c], hm, hp);
 #pragma unroll
-      for (int q = 0; q < NQ; q++) s0[q][c] = vl_slope_q(zm.q[q][c], z0.q[q][c], zp.q[q][c], hm, hp);
+      for (int q = 0; q < NQ; q++)
+        s0[q][c] = (DEV && q < 2) ? vl_slope_qb(zm.q[q][c], z0.q[q][c], zp.q[q][c], hm, hp, dlf, dlf1)
+                                  : vl_slope_q(zm.q[q][c], z0.q[q][c], zp.q[q][c], hm, hp);
       const F w = z0.w[c];
       Fr[c] = w * vl_star(w, dt, zm.rho[c], sm[NQ][c], Lm, z0.rho[c], s0[NQ][c], L0) * Sf * dt;
 #pragma unroll
-      for (int q = 0; q < NQ; q++)
-        FQ[q][c] = vl_star(w, dt, zm.q[q][c], sm[q][c], Lm, z0.q[q][c], s0[q][c], L0) * Fr[c];
+      for (int q = 0; q < NQ; q++) {
+        // relative to the background of the face's lower zone
+        const F qr = (DEV && q < 2) ? z0.q[q][c] + dlf : z0.q[q][c];
+        FQ[q][c] = vl_star(w, dt, zm.q[q][c], sm[q][c], Lm, qr, s0[q][c], L0) * Fr[c];
+      }
     }
     if (f > a0) {
       // Z update of plane k = f - 1, then its ring
@@ -833,11 +902,13 @@ __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2
 #pragma unroll
       for (int q = 0; q <= NQ; q++) sm[q][c] = s0[q][c];
 #pragma unroll
-      for (int q = 0; q < NQ; q++) FQp[q][c] = FQ[q][c];
+      for (int q = 0; q < NQ; q++) // relative to the background of the face's upper zone
+        FQp[q][c] = (DEV && q < 2) ? FQ[q][c] - dlf * Fr[c] : FQ[q][c];
     }
     zm = z0;
     z0 = zp;
     Lm = L0;
+    dlf = dlf1;
   }
 }
 

@@ -41,7 +41,11 @@ struct Visc {
     const F dvphi_dr = (vx[c] - vx[cs_]) / (F)m.g.hy(b);
     const F vphi_r = F(0.5) * (vx[c] / (F)m.g.ymed(b) + vx[cs_] / (F)m.g.ymed(b - 1));
     const F dvr_dphi = (vy[c] - vy[cw]) / ((F)m.g.ymin(b) * (F)m.dx);
-    return -rho4 * nu4 * (dvphi_dr - vphi_r + dvr_dphi);
+    F shear = dvphi_dr - vphi_r;
+    // an FP32 v_phi is a deviation from its ring's background: the same two
+    // terms of the background, formed in FP64 and rounded once
+    if constexpr (sizeof(F) == 4) shear += (F)m.bg(BG_KV, b, 0);
+    return -rho4 * nu4 * (shear + dvr_dphi);
   }
 };
 

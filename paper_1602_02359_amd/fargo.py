@@ -58,6 +58,7 @@ _lib.fargo_strerror.argtypes = [C.c_int]
 _lib.fargo_layout.argtypes = [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
 _lib.fargo_workspace_bytes.argtypes = [_P, C.POINTER(C.c_size_t)]
 _lib.fargo_init.argtypes = [_P, C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]
+_lib.fargo_set_vx_background.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
 _lib.fargo_destroy.argtypes = [C.c_void_p]
 _lib.fargo_destroy.restype = None
 _lib.fargo_cfl_dt.argtypes = [C.c_void_p, _S, C.POINTER(C.c_double), C.c_void_p]
@@ -103,7 +104,7 @@ _lib.fargo_lfc_restrict.argtypes = [C.c_void_p, _S, C.c_void_p, _S, C.c_void_p]
 _lib.fargo_lfc_target.argtypes = [C.c_void_p, _S, _S, C.c_void_p, C.c_void_p]
 
 EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_workspace_bytes", "fargo_init",
-            "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
+            "fargo_set_vx_background", "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
             "fargo_conserved_sums", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
             "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_destroy",
             "fargo_lfc_create", "fargo_lfc_destroy", "fargo_lfc_set_params", "fargo_lfc_get_params",
@@ -192,6 +193,7 @@ class Solver:
                 self.workspace = None
                 _check(_lib.fargo_init(C.byref(self._ps), None, 0, C.byref(self._ctx)), "fargo_init")
         self.state: Dict[str, Optional[torch.Tensor]] = {}
+        self.vxbg: Optional[np.ndarray] = None  # FP32 state: background of v_x, (nz_g, ny_g)
         self._st = fargo_state()
 
     def __del__(self):
@@ -201,11 +203,23 @@ class Solver:
             self._ctx = None
 
     # -- state -------------------------------------------------------------
+    def fargo_set_vx_background(self, vb: np.ndarray):
+        """FP32-bulk contexts: the FP64 per-ring background of v_x, shape
+        (nz_g, ny_g); the state's vx then holds v_x - vb."""
+        vb = np.ascontiguousarray(vb, dtype=np.float64).reshape(self.nzg, self.nyg)
+        _check(_lib.fargo_set_vx_background(self._ctx, vb.ctypes.data_as(C.POINTER(C.c_double))),
+               "fargo_set_vx_background")
+        self.vxbg = vb.copy()
+
     def upload(self, fields: Dict[str, Optional[np.ndarray]]):
         """Copy host arrays (nz_g, ny_g, nx) into padded device tensors of the
-        state type (FP64 values are rounded to nearest for an FP32 state)."""
+        state type (FP64 values are rounded to nearest for an FP32 state).
+        For an FP32 state the background of v_x is each ring's mean of the
+        given v_x (ghost rings included), and vx holds the rounded deviation."""
         nx = self.params["nx"]
         self.state = {}
+        if self.dtype == torch.float32 and fields.get("vx") is not None:
+            self.fargo_set_vx_background(np.asarray(fields["vx"], dtype=np.float64).mean(axis=2))
         for n in FIELDS:
             a = fields.get(n)
             if a is None:
@@ -213,9 +227,21 @@ class Solver:
                 continue
             dt = torch.float64 if n == "pot" else self.dtype  # the potential is FP64 in every mode
             t = torch.zeros(self.shape, dtype=dt, device=self.device)
-            t[:, :, :nx] = torch.from_numpy(np.ascontiguousarray(a)).to(self.device).to(dt)
+            src = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(self.device)
+            if n == "vx" and self.vxbg is not None:
+                src = src - torch.from_numpy(self.vxbg).to(self.device)[:, :, None]
+            t[:, :, :nx] = src.to(dt)
             self.state[n] = t
         self._bind()
+
+    def field64(self, name: str) -> torch.Tensor:
+        """The device field (nz_g, ny_g, nx) as FP64, with the background of
+        v_x added back for an FP32 state."""
+        nx = self.params["nx"]
+        t = self.state[name][:, :, :nx].double()
+        if name == "vx" and self.vxbg is not None:
+            t = t + torch.from_numpy(self.vxbg).to(t.device)[:, :, None]
+        return t
 
     def _bind(self):
         for n in FIELDS:
@@ -223,9 +249,9 @@ class Solver:
             setattr(self._st, n, C.c_void_p(t.data_ptr()) if t is not None else None)
 
     def download(self) -> Dict[str, Optional[np.ndarray]]:
-        nx = self.params["nx"]
+        """Host FP64 copies (nz_g, ny_g, nx) of the state (v_x in full)."""
         torch.cuda.synchronize(self.device)
-        return {n: (None if t is None else t[:, :, :nx].double().cpu().numpy().copy())
+        return {n: (None if t is None else self.field64(n).cpu().numpy().copy())
                 for n, t in self.state.items()}
 
     # -- C ABI calls -------------------------------------------------------

@@ -4,7 +4,7 @@ through the C ABI.
 The viscous step is compared with the FP64 oracle (time step within the bound
 of gpu_common, state within 1e-12 normwise after one step at the oracle's
 time step); the FP32-bulk form with the FP64 step
-after 100 steps at 1e-4 (the FP32 bar of tests/test_gpu_fp32.py).  A batch step (one captured hipGraph over many disks)
+after 100 steps at 1e-5 (the FP32 bar of tests/test_gpu_fp32.py).  A batch step (one captured hipGraph over many disks)
 must equal the disks' own steps bit for bit, and the autotuner must leave the
 states as it found them.
 """
@@ -88,10 +88,11 @@ def test_visc_fp32_hundred_steps_vs_fp64():
         s32.fargo_step(s64.fargo_get_dt())   # equal times
     s64.fargo_check()
     s32.fargo_check()
-    err = errors(prob, s32.download(), s64.download())
-    _say("visc fp32 vs fp64, 100 steps", err)
-    for k, e in err.items():   # the FP32 bar of tests/test_gpu_fp32.py, same derivation
-        assert e <= 1e-4, (k, e)
+    a, b = s32.download(), s64.download()
+    err = errors(prob, a, b)
+    _say("visc fp32 vs fp64, 100 steps", err, "per component", errors_own(prob, a, b))
+    for k, e in err.items():   # the FP32 bar of tests/test_gpu_fp32.py
+        assert e <= 1e-5, (k, e)
 
 
 def test_visc_unsupported_configurations():
