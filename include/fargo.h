@@ -220,6 +220,23 @@ int fargo_ring_split(fargo_ctx *ctx, const void *vx, double dt, double *v0, int3
    wrap.  `out` is host memory. */
 int fargo_conserved_sums(fargo_ctx *ctx, const fargo_state *state, double out[5], void *stream);
 
+/* fargo_conserved_sums for callers that cannot allocate device memory (code
+   under stream or graph capture, tight serving loops, harnesses that forbid
+   allocation): the same kernels and the same results, bit for bit, but the
+   per-ring partial sums and the five results are staged in a static device
+   array of the library (10.5 MB per device, for at most 131072 = 2^17 active
+   rings, ny * nz) instead of the context's workspace.  Nothing is allocated:
+   no hipMalloc, hipFree or allocating library call.  The array's device
+   address is looked up once per device by fargo_init, with that device
+   current; the array lives until the process ends.  Every call on one device
+   shares that device's array and keeps the last call's contents, which the
+   next call overwrites entirely (nothing needs to start at zero): calls that
+   overlap in time on one device (different streams or threads) race, and
+   must be serialised by the caller.  The current device must be the
+   context's (FARGO_EINVAL otherwise); more than 2^17 active rings give
+   FARGO_ENOMEM.  Waits for the stream; `out` is host memory. */
+int fargo_conserved_sums_noalloc(fargo_ctx *ctx, const fargo_state *state, double out[5], void *stream);
+
 /* Copy the time step last computed or imposed on the device into *dt_host
    (waits for the stream). */
 int fargo_get_dt(fargo_ctx *ctx, double *dt_host, void *stream);

@@ -416,6 +416,12 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
     delete c;
     return FARGO_EHIP;
   }
+  // the device copy of the static scratch of fargo_conserved_sums_noalloc
+  // (looked up once per device, with that device current)
+  if (static_scratch_setup(c->dev) != FARGO_OK) {
+    delete c;
+    return FARGO_EHIP;
+  }
   c->p = *params;
   int pitch, nyg, nzg;
   dims(params, pitch, nyg, nzg);
@@ -683,6 +689,26 @@ int fargo_conserved_sums(fargo_ctx *ctx, const fargo_state *state, double out[5]
   else launch_sums(L, ctx->m, state_of<double>(ctx, state), ctx->partial, ctx->sums_out);
   if (hipGetLastError() != hipSuccess) return FARGO_EHIP;
   if (hipMemcpyAsync(out, ctx->sums_out, 5 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return FARGO_EHIP;
+  return hip_ok(hipStreamSynchronize(s));
+}
+
+int fargo_conserved_sums_noalloc(fargo_ctx *ctx, const fargo_state *state, double out[5], void *stream) {
+  if (!ctx || !out) return FARGO_EINVAL;
+  int rc = check_state(ctx, state);
+  if (rc) return rc;
+  if (ctx->m.nring > SUMS_STATIC_RINGS) return FARGO_ENOMEM;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return FARGO_EHIP;
+  if (cur != ctx->dev) return FARGO_EINVAL;
+  double *scr = static_scratch(cur); // device address of this device's copy
+  if (!scr) return FARGO_EHIP;
+  double *partial = scr, *res = scr + (size_t)SUMS_STATIC_RINGS * 10;
+  hipStream_t s = (hipStream_t)stream;
+  Launch L{s, &ctx->prof};
+  if (fp32(ctx)) launch_sums(L, ctx->m, state_of<float>(ctx, state), partial, res);
+  else launch_sums(L, ctx->m, state_of<double>(ctx, state), partial, res);
+  if (hipGetLastError() != hipSuccess) return FARGO_EHIP;
+  if (hipMemcpyAsync(out, res, 5 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return FARGO_EHIP;
   return hip_ok(hipStreamSynchronize(s));
 }
 

@@ -304,6 +304,13 @@ void launch_vel(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &T)
 // misc
 template <typename R>
 void launch_shift(Launch &L, const Mesh &m, R *field, const int32_t *N);
+// Device scratch of the allocation-free sums (a file-scope device array):
+// per-device address lookup, done once per device at context creation with
+// that device current, and the address looked up (NULL before set-up).
+constexpr int SUMS_STATIC_RINGS = 1 << 17;
+constexpr int SCRATCH_MAX_DEVICES = 64;
+int static_scratch_setup(int dev);
+double *static_scratch(int dev);
 template <typename R>
 void launch_sums(Launch &L, const Mesh &m, const StateT<R> &s, double *partial, double *out);
 

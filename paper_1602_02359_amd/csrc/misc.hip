@@ -3,6 +3,8 @@
 // energy) with double-double accumulation in a fixed order.  Both take the
 // field type F (double, or float for the FP32-bulk state); the sums are always
 // formed in FP64 from the stored values.
+#include <mutex>
+
 #include "fargo_internal.h"
 
 namespace fargo {
@@ -128,6 +130,37 @@ void launch_sums(Launch &L, const Mesh &m, const StateT<F> &s, double *partial, 
   prof_begin(L, K_SUMS_FINAL);
   k_sums_final<<<1, 256, 0, L.s>>>(m.nring, partial, out);
   prof_end(L, K_SUMS_FINAL);
+}
+
+// Scratch of fargo_conserved_sums_noalloc: the per-ring double-double
+// partials (10 doubles a ring) of at most SUMS_STATIC_RINGS rings, then the
+// five results.  One copy per device, held until the process ends.  Host code
+// must not pass `scratch` itself to a kernel (in host code the name stands for
+// a host-side shadow, not the device copy): it uses the device address that
+// hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) double scratch[(size_t)SUMS_STATIC_RINGS * 10 + 8];
+
+namespace {
+std::mutex scratch_mu;
+double *scratch_dev[SCRATCH_MAX_DEVICES] = {};
+} // namespace
+
+int static_scratch_setup(int dev) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return FARGO_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_dev[dev]) return FARGO_OK;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != dev) return FARGO_EHIP;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FARGO_EHIP;
+  scratch_dev[dev] = (double *)p;
+  return FARGO_OK;
+}
+
+double *static_scratch(int dev) {
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return scratch_dev[dev];
 }
 
 template void launch_shift<double>(Launch &, const Mesh &, double *, const int32_t *);

@@ -66,6 +66,7 @@ _lib.fargo_step.argtypes = [C.c_void_p, _S, C.c_double, C.c_void_p]
 _lib.fargo_shift.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.fargo_ring_split.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.fargo_conserved_sums.argtypes = [C.c_void_p, _S, C.POINTER(C.c_double), C.c_void_p]
+_lib.fargo_conserved_sums_noalloc.argtypes = [C.c_void_p, _S, C.POINTER(C.c_double), C.c_void_p]
 _lib.fargo_get_dt.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
 _lib.fargo_check.argtypes = [C.c_void_p]
 _lib.fargo_profile_enable.argtypes = [C.c_void_p, C.c_int]
@@ -105,7 +106,7 @@ _lib.fargo_lfc_target.argtypes = [C.c_void_p, _S, _S, C.c_void_p, C.c_void_p]
 
 EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_workspace_bytes", "fargo_init",
             "fargo_set_vx_background", "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
-            "fargo_conserved_sums", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
+            "fargo_conserved_sums", "fargo_conserved_sums_noalloc", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
             "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_destroy",
             "fargo_lfc_create", "fargo_lfc_destroy", "fargo_lfc_set_params", "fargo_lfc_get_params",
             "fargo_lfc_get_grad", "fargo_lfc_forward", "fargo_lfc_train_step", "fargo_lfc_apply",
@@ -288,6 +289,12 @@ class Solver:
     def fargo_conserved_sums(self, stream=None) -> np.ndarray:
         out = (C.c_double * 5)()
         _check(_lib.fargo_conserved_sums(self._ctx, C.byref(self._st), out, _stream(stream)), "fargo_conserved_sums")
+        return np.array(list(out))
+
+    def fargo_conserved_sums_noalloc(self, stream=None) -> np.ndarray:
+        out = (C.c_double * 5)()
+        _check(_lib.fargo_conserved_sums_noalloc(self._ctx, C.byref(self._st), out, _stream(stream)),
+               "fargo_conserved_sums_noalloc")
         return np.array(list(out))
 
     def fargo_check(self):
