@@ -1,20 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the hydrodynamics step on one MI355X.
 
-Workload: the 3D spherical (phi, r, theta) adiabatic disk, 1536 x 512 x 128
-active zones, FP64, orbital advection on, time step computed on the device
-every step (the whole hot path: boundary fill, bulk velocity, CFL reduction,
-source step, transport with integer shift and PPA residual, velocities).
-Inputs are seeded and synthetic and already resident in HBM when the timed
-region starts.
+Headline workload: the 3D cylindrical (phi, r, z) isothermal disk with a
+fixed planet, 2048 x 768 x 96 active zones (151 M), FP64, orbital advection
+on, time step computed on the device every step (the whole hot path:
+boundary fill, bulk velocity, CFL reduction, source step, transport with
+integer shift and PPA residual, velocities).  Inputs are seeded and synthetic
+and already resident in HBM when the timed region starts.  The timed steps
+run with per-kernel timing off; per-kernel HIP-event means come from a
+separate pass over the same state.
 
-Prints one JSON line: cell-updates/s, ms/step, the roofline of the dominant
-kernel (algorithmic bytes per launch over its average duration from HIP
-events recorded on the launch stream during the timed steps) and the CPU
-oracle timed on a bounded sample of the same workload.  The FP32-bulk
-variant (FP32 state, FP64 time step, ring split and sums) is then timed on
-the same workload and reported with its normwise error against the FP64 run
-after the same number of steps from the same initial state.
+Prints one JSON line: cell-updates/s and ms/step of the headline, the
+roofline of its dominant kernel (algorithmic bytes per launch over its mean
+duration), the CPU oracle timed on a bounded sample of the same workload on
+one core and on all cores, and beside them:
+  - the 3D spherical adiabatic disk 1536 x 512 x 128 and the 2D disk
+    384 x 128, FP64 (same figures);
+  - the FP32-bulk state (FP64 time step, ring split and sums) on both 3D
+    disks: its rate, and its error against the FP64 run after 100 steps at
+    equal times (the FP32 run takes the FP64 run's time steps);
+  - physical time advanced per second with orbital advection on and off;
+  - the HBM ceiling of a hand-written streaming copy;
+  - the batch of 256 uneven viscous disks and the learned flux correction.
 """
 import argparse
 import hashlib
@@ -133,44 +140,99 @@ def sample_problem(prob, ny_s, nz_s):
     return W.Problem(prob.name + "_sample", sub, f, 1)
 
 
-def cpu_baseline(prob, target_s=12.0):
+def host_info():
+    """CPU model and logical CPU count of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(),
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(prob, target_s=10.0):
+    """The FP64 oracle (built with -march=native on this host, no contraction,
+    no fast-math) timed on one step of a bounded sample of the workload: whole
+    rings of the mesh, the real neighbours as fixed ghosts, scaled to about
+    target_s of work; on one thread, then on every thread OpenMP is allowed."""
     from oracle import oracle as O
+    O.use_native()
     p = prob.params
-    nz_s = 8 if p["nz"] > 1 else 1
-    ny_s = 16
-    s = sample_problem(prob, ny_s, nz_s)
-    f = s.copy_fields()
-    t0 = time.perf_counter()
-    O.step(s.params, f)
-    t_cal = time.perf_counter() - t0
-    rate = s.active_cells / t_cal
-    # scale the sample to about target_s of work, within the workload
-    want = rate * target_s
-    if p["nz"] > 1:
-        nz_s = max(4, min(p["nz"], int(want / (p["nx"] * p["ny"]))))
-        ny_s = p["ny"] if nz_s * p["nx"] * p["ny"] <= want else max(4, int(want / (p["nx"] * nz_s)))
-    else:
-        ny_s = max(4, min(p["ny"], int(want / p["nx"])))
-    s = sample_problem(prob, ny_s, nz_s)
-    f = s.copy_fields()
-    t0 = time.perf_counter()
-    O.step(s.params, f)
-    el = time.perf_counter() - t0
-    return {
-        "value": s.active_cells / el,
-        "unit": "cell-updates/s",
-        "cores": O.num_threads(),
-        "kind": "oracle",
-        "sample": "one full step (CFL included) of %d x %d x %d zones of the same workload (rings cut "
-                  "from the mesh, neighbours as fixed ghosts), %.1f s" % (p["nx"], s.params["ny"], s.params["nz"], el),
-    }
+    all_threads = O.num_threads()
+
+    def timed(ny_s, nz_s):
+        smp = sample_problem(prob, ny_s, nz_s)
+        f = smp.copy_fields()
+        t0 = time.perf_counter()
+        O.step(smp.params, f)
+        return smp, time.perf_counter() - t0
+
+    def sized(rate):
+        want = min(rate * target_s, 4e7)  # at most 40 M zones (host memory of the oracle's copy)
+        if p["nz"] > 1:
+            nz_s = max(4, min(p["nz"], int(want / (p["nx"] * p["ny"]))))
+            ny_s = p["ny"] if nz_s * p["nx"] * p["ny"] <= want else max(4, int(want / (p["nx"] * nz_s)))
+        else:
+            nz_s, ny_s = 1, max(4, min(p["ny"], int(want / p["nx"])))
+        return ny_s, nz_s
+
+    out = {}
+    for label, nth in (("one_core", 1), ("all_cores", all_threads)):
+        O.set_num_threads(nth)
+        cal, t_cal = timed(16, 8 if p["nz"] > 1 else 1)
+        smp, el = timed(*sized(cal.active_cells / t_cal))
+        out[label] = {
+            "value": smp.active_cells / el, "unit": "cell-updates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "one full step (CFL included) of %d x %d x %d zones of the same workload (whole rings, "
+                      "neighbours as fixed ghosts), %.1f s, oracle built -O3 -march=native -ffp-contract=off"
+                      % (p["nx"], smp.params["ny"], smp.params["nz"], el)}
+    O.set_num_threads(all_threads)
+    res = dict(out["all_cores"])
+    res["one_core"] = out["one_core"]
+    res["host"] = host_info()
+    return res
 
 
-def batch_variant(steps, warmup, tune=True):
+def field_errors(a, b, keys, owned):
+    """Normwise L_inf errors of solver a against solver b over the slices
+    owned(k): velocities scaled by b's largest speed; each velocity also by
+    its own largest value (own_scale)."""
+    vk = [k for k in keys if k.startswith("v")]
+    vmax = max(float(b.field64(k)[owned(k)].abs().max()) for k in vk)
+    err, own = {}, {}
+    for k in keys:
+        x, y = a.field64(k)[owned(k)], b.field64(k)[owned(k)]
+        d, ymax = float((x - y).abs().max()), float(y.abs().max())
+        err[k] = d / (vmax if k in vk else ymax)
+        if k in vk:
+            own[k] = d / ymax if ymax > 0 else d
+        del x, y
+    return err, own
+
+
+def owned_slices(p):
+    """What a step defines: active zones, and the owned Y/Z faces (interior
+    faces; the radial and vertical sides of the disks are not periodic)."""
+    d3 = p["nz"] > 1
+    ks = slice(NGH, NGH + p["nz"]) if d3 else slice(0, 1)
+    js = slice(NGH, NGH + p["ny"])
+    reg = {"vy": (ks, slice(NGH + 1, NGH + p["ny"]), slice(None)),
+           "vz": (slice(NGH + 1, NGH + p["nz"]), js, slice(None))}
+    return lambda k: reg.get(k, (ks, js, slice(None)))
+
+
+def batch_variant(steps, warmup, tune=True, err_steps=100):
     """The parameter sweep of 256 uneven viscous disks (N_r in 64..512,
-    N_phi = 3 N_r, alpha viscosity): the plain FP64 step called disk by disk,
-    then the FP32-bulk batch advanced by one captured graph per step with the
-    autotuned graph width and sweep chunk.  Same disks, same number of steps."""
+    N_phi = 3 N_r, alpha viscosity), same disks and steps in four forms: the
+    FP64 and FP32-bulk steps called disk by disk, and both advanced by one
+    captured graph per step with the autotuned graph width and sweep chunk;
+    then the FP32 disks against the FP64 ones after err_steps steps at equal
+    times (each FP32 disk takes its FP64 twin's time steps)."""
     import torch
     from paper_1602_02359_amd import fargo as F
     from paper_1602_02359_amd import workloads as W
@@ -186,46 +248,68 @@ def batch_variant(steps, warmup, tune=True):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    def solvers(precision):
+        out = []
+        for p in probs:
+            sv = F.Solver(dict(p.params, precision=precision))
+            sv.upload(p.fields)
+            out.append(sv)
+        return out
+
     out = {}
-    s64 = []
-    for p in probs:
-        s = F.Solver(p.params)
-        s.upload(p.fields)
-        s64.append(s)
-    step64 = lambda: [s.fargo_step(0.0) for s in s64]
-    for _ in range(warmup):
-        step64()
-    el = timed(step64, steps)
-    for s in s64:
-        s.fargo_check()
-    out["fp64_disk_by_disk"] = {"value": cells * steps / el, "ms_per_step": 1e3 * el / steps}
-    del s64
+    for prec in ("fp64", "fp32"):
+        ss = solvers(prec)
+        step = lambda: [sv.fargo_step(0.0) for sv in ss]
+        for _ in range(warmup):
+            step()
+        el = timed(step, steps)
+        out[prec + "_disk_by_disk"] = {"value": cells * steps / el, "ms_per_step": 1e3 * el / steps}
+        b = F.Batch(ss, lanes=8)
+        best = b.fargo_batch_tune(lanes=(1, 4, 8, 16), chunks=(16, 32, 64), steps=10) if tune else None
+        for _ in range(warmup):
+            b.fargo_batch_step()
+        el = timed(b.fargo_batch_step, steps)
+        for sv in ss:
+            sv.fargo_check()
+        out[prec + "_batched_graph"] = {"value": cells * steps / el, "ms_per_step": 1e3 * el / steps,
+                                        "tuned": {"lanes": best[0], "chunk": best[1]} if best else None}
+        print("  %s: disk by disk %.3e, batched graph %.3e cell-updates/s, tuned %s" % (
+            prec, out[prec + "_disk_by_disk"]["value"], out[prec + "_batched_graph"]["value"], best),
+            file=sys.stderr, flush=True)
+        del b, ss
+        torch.cuda.empty_cache()
+    v = lambda k: out[k]["value"]
+    out["speedup"] = {
+        "batching_fp64": v("fp64_batched_graph") / v("fp64_disk_by_disk"),
+        "batching_fp32": v("fp32_batched_graph") / v("fp32_disk_by_disk"),
+        "precision_disk_by_disk": v("fp32_disk_by_disk") / v("fp64_disk_by_disk"),
+        "fp32_batched_vs_fp64_disk_by_disk": v("fp32_batched_graph") / v("fp64_disk_by_disk"),
+    }
+    # FP32 against FP64 at equal times, disk by disk (a batch step equals the
+    # disks' own steps bit for bit)
+    worst = {}
+    for d, p in enumerate(probs):
+        a64 = F.Solver(dict(p.params, precision="fp64"))
+        a64.upload(p.fields)
+        a32 = F.Solver(dict(p.params, precision="fp32"))
+        a32.upload(p.fields)
+        for _ in range(err_steps):
+            a64.fargo_step(0.0)
+            a32.fargo_step(a64.fargo_get_dt())
+        a64.fargo_check()
+        a32.fargo_check()
+        err, _ = field_errors(a32, a64, ("rho", "vx", "vy"), owned_slices(p.params))
+        for k, e in err.items():
+            worst[k] = max(worst.get(k, 0.0), e)
+        del a64, a32
     torch.cuda.empty_cache()
-    s32 = []
-    for p in probs:
-        s = F.Solver(dict(p.params, precision="fp32"))
-        s.upload(p.fields)
-        s32.append(s)
-    b = F.Batch(s32, lanes=8)
-    best = None
-    if tune:
-        best = b.fargo_batch_tune(lanes=(1, 4, 8, 16), chunks=(16, 32, 64), steps=10)
-    for _ in range(warmup):
-        b.fargo_batch_step()
-    el = timed(b.fargo_batch_step, steps)
-    for s in s32:
-        s.fargo_check()
-    out["fp32_batched_graph"] = {"value": cells * steps / el, "ms_per_step": 1e3 * el / steps,
-                                 "tuned": {"lanes": best[0], "chunk": best[1]} if best else None}
-    out["speedup"] = out["fp32_batched_graph"]["value"] / out["fp64_disk_by_disk"]["value"]
+    out["fp32_error_vs_fp64"] = {"steps": err_steps, "equal_times": True, "max_over_disks":
+                                 {k: float("%.3g" % e) for k, e in worst.items()}}
     out["disks"] = len(probs)
     out["active_cells"] = cells
     out["unit"] = "cell-updates/s"
-    print("  fp64 disk by disk %.3e, fp32 batched graph %.3e cell-updates/s (x%.2f), tuned %s" % (
-        out["fp64_disk_by_disk"]["value"], out["fp32_batched_graph"]["value"], out["speedup"], best),
-        file=sys.stderr, flush=True)
-    del b, s32
-    torch.cuda.empty_cache()
+    print("  batch speedups %s, fp32 error %s" % (out["speedup"], out["fp32_error_vs_fp64"]),
+          file=sys.stderr, flush=True)
     return out
 
 
@@ -233,24 +317,40 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
 
 
 def copy_bandwidth():
-    """Bytes read plus written per second by a plain 1 GiB device copy
-    (torch's copy kernel), timed with HIP events: the bandwidth a streaming
-    kernel can reach on this GPU, for comparison with the 8 TB/s peak."""
+    """Bytes read plus written per second by a plain 1 GiB device copy, timed
+    with HIP events: torch's copy kernel, and the library's hand-written
+    streaming copy (16-byte vectors, four per thread per round, loads before
+    stores) at several grid sizes, the best of which is the practical HBM
+    ceiling a kernel reaches on this GPU (the vendor peak is 8 TB/s)."""
     import torch
+    from paper_1602_02359_amd import fargo as F
     src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    a.record()
-    for _ in range(10):
-        dst.copy_(src)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / 10
+    nb = 2 * src.nbytes
+
+    def rate(fn, reps=10):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return nb / (a.elapsed_time(b) / reps * 1e-3) / 1e9
+
+    out = {"torch_copy_GBs": rate(lambda: dst.copy_(src))}
+    grid = {}
+    for blocks in (1024, 2048, 4096, 8192, 16384, 32768):
+        grid[blocks] = rate(lambda: F.fargo_hbm_copy(src, dst, blocks))
+    best = max(grid, key=grid.get)
+    out["hip_stream_copy_GBs"] = grid[best]
+    out["hip_stream_copy_blocks"] = best
+    out["hip_stream_copy_by_blocks"] = {str(k): round(v, 1) for k, v in grid.items()}
+    assert torch.equal(src, dst)
     del src, dst
     torch.cuda.empty_cache()
-    return 2 * 2 ** 27 * 8 / (ms * 1e-3) / 1e9
+    return out
 
 
 def lfc_variant(iters=600):
@@ -325,16 +425,160 @@ def lfc_variant(iters=600):
     return out
 
 
+_PROBS = {}
+
+
+def problem(name):
+    """The seeded workload, generated once (its host arrays are kept)."""
+    from paper_1602_02359_amd import workloads as W
+    if name not in _PROBS:
+        _PROBS[name] = W.make(name)
+    return _PROBS[name]
+
+
+def run_workload(name, precision, steps, warmup, fargo=None, kernel_steps=5, keep=False):
+    """Upload the workload, warm up, time `steps` steps with kernel timing off,
+    then `kernel_steps` more with per-kernel HIP events on the launch stream.
+    Returns the figures (and the solver, if keep)."""
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    prob = problem(name)
+    p = dict(prob.params, precision=precision)
+    if fargo is not None:
+        p["fargo"] = bool(fargo)
+    cells = prob.active_cells
+    print("workload %s %dx%dx%d %s fargo=%s" % (name, p["nx"], p["ny"], p["nz"], precision, p["fargo"]),
+          file=sys.stderr, flush=True)
+    solver = F.Solver(p)
+    solver.upload(prob.fields)
+    for _ in range(warmup):
+        solver.fargo_step(0.0)
+    solver.fargo_check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solver.fargo_step(0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    solver.fargo_check()
+    value = cells * steps / el
+    r = {"value": value, "ms_per_step": 1e3 * el / steps, "active_cells": cells,
+         "dt_last": solver.fargo_get_dt()}
+    # per-kernel means, in a pass of their own
+    wpu = words_per_unit(p)
+    wb = 4.0 if precision == "fp32" else 8.0
+    solver.fargo_profile_enable(True)
+    for _ in range(kernel_steps):
+        solver.fargo_step(0.0)
+    timings = solver.fargo_timings()
+    solver.fargo_profile_enable(False)
+    kern = {}
+    for kname, (cnt, tot) in timings.items():
+        e = {"launches": cnt, "avg_ms": tot / cnt}
+        if kname in wpu and wpu[kname][0] > 0:
+            e["alg_bytes"] = wb * wpu[kname][0] * wpu[kname][1]
+            e["GBs"] = e["alg_bytes"] / (e["avg_ms"] * 1e-3) / 1e9
+        kern[kname] = e
+    dom = max((k for k in kern if "alg_bytes" in kern[k]), key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    step_alg = sum(e["alg_bytes"] * e["launches"] for e in kern.values() if "alg_bytes" in e) / kernel_steps
+    r.update({"kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                          for k, v in kern.items()},
+              "dominant": dom, "step_alg_bytes_per_cell": step_alg / cells,
+              "step_alg_GBs": value * step_alg / cells / 1e9})
+    tag = "%s_%dx%dx%d_%s" % (name, p["nx"], p["ny"], p["nz"], precision)
+    r["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(kern[dom]["GBs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(kern[dom]["GBs"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, tag), "alg_bytes_per_launch": kern[dom]["alg_bytes"],
+                     "avg_launch_ms": kern[dom]["avg_ms"]}
+    print("  %.3f ms/step, %.3e cell-updates/s; dominant %s %.4f ms, %.0f GB/s" % (
+        r["ms_per_step"], value, dom, kern[dom]["avg_ms"], kern[dom]["GBs"]), file=sys.stderr, flush=True)
+    for kname, e in sorted(kern.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches"]):
+        print("    %-16s %5d launches %9.4f ms avg  %s" % (kname, e["launches"], e["avg_ms"],
+              ("%.0f GB/s" % e["GBs"]) if "GBs" in e else ""), file=sys.stderr)
+    if keep:
+        return r, solver
+    del solver
+    torch.cuda.empty_cache()
+    return r, None
+
+
+def fp32_error(name, nsteps=100):
+    """FP32 bulk against FP64 after nsteps from the same FP64 initial state,
+    at equal times (the FP32 run takes the FP64 run's time steps)."""
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    prob = problem(name)
+    p = prob.params
+    a64 = F.Solver(dict(p, precision="fp64"))
+    a64.upload(prob.fields)
+    a32 = F.Solver(dict(p, precision="fp32"))
+    a32.upload(prob.fields)
+    t_sim = 0.0
+    for n in range(nsteps):
+        a64.fargo_step(0.0)
+        dt = a64.fargo_get_dt()
+        t_sim += dt
+        a32.fargo_step(dt)
+        if n % 25 == 24:
+            print("  fp32 vs fp64 %s: step %d" % (name, n + 1), file=sys.stderr, flush=True)
+    a64.fargo_check()
+    a32.fargo_check()
+    keys = ("rho", "e", "vx", "vy", "vz") if p["eos"] == "adi" else ("rho", "vx", "vy", "vz")
+    err, own = field_errors(a32, a64, keys, owned_slices(p))
+    del a64, a32
+    torch.cuda.empty_cache()
+    out = {"steps": nsteps, "equal_times": True, "time_advanced": t_sim,
+           "normwise": {k: float("%.3g" % v) for k, v in err.items()},
+           "velocity_own_scale": {k: float("%.3g" % v) for k, v in own.items()}}
+    print("  fp32 error after %d steps: %s" % (nsteps, out["normwise"]), file=sys.stderr, flush=True)
+    return out
+
+
+def physical_time_rate(name, steps, warmup, fargo):
+    """Physical time advanced per second of wall time, with orbital advection
+    on or off: the timed rate of whole steps times the mean time step of the
+    same steps (read back after the timed region)."""
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    prob = problem(name)
+    p = dict(prob.params, fargo=bool(fargo))
+    s = F.Solver(p)
+    s.upload(prob.fields)
+    for _ in range(warmup):
+        s.fargo_step(0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.fargo_step(0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    dts = []
+    for _ in range(steps):
+        s.fargo_step(0.0)
+        dts.append(s.fargo_get_dt())
+    s.fargo_check()
+    del s
+    torch.cuda.empty_cache()
+    mdt = sum(dts) / len(dts)
+    return {"ms_per_step": 1e3 * el / steps, "mean_dt": mdt, "time_per_s": mdt * steps / el}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="sph3d", choices=["sph3d", "cyl3d_planet", "disk2d"])
+    ap.add_argument("--config", default="cyl3d_planet", choices=["cyl3d_planet", "sph3d", "disk2d"])
+    ap.add_argument("--kernel-steps", type=int, default=5, help="steps of the per-kernel timing pass")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="state of the headline run (fp32: for profiling the FP32-bulk kernels)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variant", action="store_true", help="skip the FP32-bulk and disk-batch variants")
+    ap.add_argument("--no-side", action="store_true", help="skip the other two FP64 workloads")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip FP32 bulk, FARGO on/off, the disk batch and the learned correction")
     ap.add_argument("--no-batch", action="store_true", help="skip the disk-batch variant")
     ap.add_argument("--no-lfc", action="store_true", help="skip the learned-flux-correction variant")
+    ap.add_argument("--fp32-steps", type=int, default=100, help="steps of the FP32-vs-FP64 comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain device copy of 2 GiB first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -344,8 +588,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1602_02359_amd import fargo as F
-    from paper_1602_02359_amd import workloads as W
 
     if args.copy_probe:
         src = torch.ones(2 ** 28, dtype=torch.float64, device="cuda")
@@ -355,145 +597,84 @@ def main():
         print("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8), file=sys.stderr)
         del src, dst
         torch.cuda.empty_cache()
-    prob = W.make(args.config)
-    p = prob.params
-    wpu = words_per_unit(p)
-    cells = prob.active_cells
+    hbm = copy_bandwidth()
+    print("device copy: torch %.0f GB/s, hand-written %.0f GB/s (read + write)" % (
+        hbm["torch_copy_GBs"], hbm["hip_stream_copy_GBs"]), file=sys.stderr, flush=True)
 
-    def run(precision):
-        """Warm up, then time args.steps steps with per-kernel HIP events on
-        the launch stream; returns the solver (state kept) and the figures."""
-        print("workload %s %dx%dx%d %s, building state" % (args.config, p["nx"], p["ny"], p["nz"], precision),
-              file=sys.stderr, flush=True)
-        solver = F.Solver(dict(p, precision=precision))
-        solver.upload(prob.fields)
-        for _ in range(args.warmup):
-            solver.fargo_step(0.0)
-        solver.fargo_check()
-        torch.cuda.synchronize()
-        solver.fargo_profile_enable(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            solver.fargo_step(0.0)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        timings = solver.fargo_timings()
-        solver.fargo_profile_enable(False)
-        solver.fargo_check()
-        dt_last = solver.fargo_get_dt()
-        value = cells * args.steps / el
-        ms = 1e3 * el / args.steps
-        print("timed %d steps: %.3f ms/step, %.3e cell-updates/s, dt %.6g" % (args.steps, ms, value, dt_last),
-              file=sys.stderr, flush=True)
-        wb = 4.0 if precision == "fp32" else 8.0
-        kern = {}
-        for name, (cnt, tot) in timings.items():
-            avg = tot / cnt
-            entry = {"launches": cnt, "avg_ms": avg}
-            if name in wpu and wpu[name][0] > 0:
-                b = wb * wpu[name][0] * wpu[name][1]
-                entry["alg_bytes"] = b
-                entry["GBs"] = b / (avg * 1e-3) / 1e9
-            kern[name] = entry
-            print("  %-16s %6d launches  %9.4f ms avg  %s" % (name, cnt, avg,
-                  ("%.0f GB/s" % entry["GBs"]) if "GBs" in entry else ""), file=sys.stderr)
-        dom = max((k for k in kern if "alg_bytes" in kern[k]),
-                  key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
-        # the kernels that ran, each as often per step as it was launched
-        step_alg = sum(e["alg_bytes"] * e["launches"] for e in kern.values() if "alg_bytes" in e) / args.steps
-        return solver, {"value": value, "ms": ms, "kern": kern, "dom": dom, "step_alg": step_alg}
+    head, _ = run_workload(args.config, args.precision, args.steps, args.warmup, kernel_steps=args.kernel_steps)
+    p = problem(args.config).params
+    cells = problem(args.config).active_cells
+    ceiling = hbm["hip_stream_copy_GBs"]
+    hbm.update({"step_alg_bytes_per_cell": head["step_alg_bytes_per_cell"], "step_alg_GBs": head["step_alg_GBs"],
+                "step_alg_frac_of_peak": head["step_alg_GBs"] / HBM_PEAK_GBS,
+                "step_alg_frac_of_copy_ceiling": head["step_alg_GBs"] / ceiling,
+                "compulsory_bytes_per_cell": compulsory_bytes(p),
+                "effective_GBs": head["value"] * compulsory_bytes(p) / 1e9})
+    roof = head["roofline"]
+    roof["frac_of_copy_ceiling"] = round(roof["achieved"] / ceiling, 4)
 
-    copy_gbs = copy_bandwidth()
-    print("device copy: %.0f GB/s (read + write)" % copy_gbs, file=sys.stderr, flush=True)
-    solver, r64 = run("fp64")
-    value, ms, kern, dom, step_alg = r64["value"], r64["ms"], r64["kern"], r64["dom"], r64["step_alg"]
-    achieved = kern[dom]["GBs"]
-    tag = "%s_%dx%dx%d_fp64" % (args.config, p["nx"], p["ny"], p["nz"])
-    traffic = measured_traffic(dom, tag)
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "alg_bytes_per_launch": kern[dom]["alg_bytes"], "avg_launch_ms": kern[dom]["avg_ms"]}
+    side = {}
+    if not args.no_side:
+        for name in ("sph3d", "disk2d"):
+            if name == args.config:
+                continue
+            r, _ = run_workload(name, "fp64", args.steps, args.warmup, kernel_steps=args.kernel_steps)
+            side[name] = r
 
     variants = {}
     if not args.no_variant:
-        s32, r32 = run("fp32")
-        # normwise error of the FP32-bulk state against the FP64 state after
-        # the same warmup + timed steps (velocities scaled by the largest speed)
-        nx = p["nx"]
-        d3 = p["nz"] > 1
-        ks = slice(NGH, NGH + p["nz"]) if d3 else slice(0, 1)
-        js = slice(NGH, NGH + p["ny"])
-        vnames = ("vx", "vy", "vz") if d3 else ("vx", "vy")
-        vmax = max(float(solver.state[k][ks, js, :nx].abs().max()) for k in vnames)
-        err = {}
-        for k in ("rho", "e") + vnames:
-            if solver.state.get(k) is None:
-                continue
-            a = s32.state[k][ks, js, :nx].double()
-            b = solver.state[k][ks, js, :nx]
-            den = vmax if k.startswith("v") else float(b.abs().max())
-            err[k] = float((a - b).abs().max()) / den
-            del a
-        dk = r32["dom"]
-        variants["fp32_bulk"] = {
-            "value": r32["value"], "unit": "cell-updates/s", "ms_per_step": r32["ms"],
-            "speedup_vs_fp64": r32["value"] / value,
-            "error_vs_fp64": {k: float("%.3g" % v) for k, v in err.items()},
-            "steps_compared": args.warmup + args.steps,
-            "step_alg_bytes_per_cell": r32["step_alg"] / cells,
-            "dominant_kernel": {"kernel": dk, "avg_ms": r32["kern"][dk]["avg_ms"],
-                                "GBs": round(r32["kern"][dk]["GBs"], 1)},
-            "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                        for k, v in r32["kern"].items()},
-        }
-        print("  fp32 bulk: %.3e cell-updates/s (x%.2f), error vs fp64 %s" % (
-            r32["value"], r32["value"] / value, variants["fp32_bulk"]["error_vs_fp64"]), file=sys.stderr)
-        del s32
-    del solver
-    torch.cuda.empty_cache()
-    if not args.no_variant and not args.no_batch:
-        variants["disk_batch"] = batch_variant(args.steps, args.warmup)
-    if not args.no_variant and not args.no_lfc:
-        variants["learned_flux_correction"] = lfc_variant()
+        fp32 = {}
+        for name in ("cyl3d_planet", "sph3d"):
+            r, _ = run_workload(name, "fp32", args.steps, args.warmup, kernel_steps=args.kernel_steps)
+            fp64v = head["value"] if name == args.config else side.get(name, {}).get("value")
+            r["speedup_vs_fp64"] = r["value"] / fp64v if fp64v else None
+            r["error_vs_fp64"] = fp32_error(name, args.fp32_steps)
+            fp32[name] = r
+        variants["fp32_bulk"] = fp32
+        on = physical_time_rate(args.config, args.steps, args.warmup, True)
+        off = physical_time_rate(args.config, args.steps, args.warmup, False)
+        variants["physical_time_per_s"] = {"workload": args.config, "fargo_on": on, "fargo_off": off,
+                                           "gain": on["time_per_s"] / off["time_per_s"]}
+        print("  physical time per second: fargo on %.4g, off %.4g (x%.1f)" % (
+            on["time_per_s"], off["time_per_s"], on["time_per_s"] / off["time_per_s"]), file=sys.stderr, flush=True)
+        if not args.no_batch:
+            variants["disk_batch"] = batch_variant(args.steps, args.warmup)
+        if not args.no_lfc:
+            variants["learned_flux_correction"] = lfc_variant()
 
     cpu = None
     if not args.no_cpu_baseline:
         print("timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(prob)
-        print("  oracle %.3e cell-updates/s on %d threads" % (cpu["value"], cpu["cores"]), file=sys.stderr)
+        cpu = cpu_baseline(problem(args.config))
+        print("  oracle %.3e cell-updates/s on %d threads, %.3e on one" % (
+            cpu["value"], cpu["cores"], cpu["one_core"]["value"]), file=sys.stderr)
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32 bulk (f64 time step, split, sums)",
         "data": "synthetic",
         "config": {
-            "workload": "%s: %s %dx%dx%d (phi, r, %s), %s, orbital advection %s, FP64, dt on device" % (
+            "workload": "%s: %s %dx%dx%d (phi, r, %s), %s, orbital advection %s, dt on device" % (
                 args.config, p["geometry"], p["nx"], p["ny"], p["nz"], "theta" if p["geometry"] == "sph" else "z",
-                "adiabatic" if p["eos"] == "adi" else "isothermal", "on" if p["fargo"] else "off"),
+                "adiabatic" if p["eos"] == "adi" else "isothermal", "on" if p["fargo"] else "off") +
+                ("" if args.precision == "fp64" else " (FP32-bulk state)"),
             "active_cells": cells,
             "parallelism": "single GPU",
         },
-        "hbm": {
-            "device_copy_GBs": copy_gbs,
-            "step_alg_bytes_per_cell": step_alg / cells,
-            "step_alg_GBs": value * step_alg / cells / 1e9,
-            "compulsory_bytes_per_cell": compulsory_bytes(p),
-            "effective_GBs": value * compulsory_bytes(p) / 1e9,
-        },
-        "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                    for k, v in kern.items()},
+        "hbm": hbm,
+        "kernels": head["kernels"],
         "roofline": roof,
         "cpu_baseline": cpu,
+        "other_workloads_fp64": side,
         "variants": variants,
     }
     print(json.dumps(out), flush=True)

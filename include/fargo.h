@@ -237,6 +237,15 @@ int fargo_conserved_sums(fargo_ctx *ctx, const fargo_state *state, double out[5]
    FARGO_ENOMEM.  Waits for the stream; `out` is host memory. */
 int fargo_conserved_sums_noalloc(fargo_ctx *ctx, const fargo_state *state, double out[5], void *stream);
 
+/* Bandwidth probe (no part of the method): a plain streaming copy of `bytes`
+   (a multiple of 16) from src to dst, device buffers aligned to 16 bytes
+   that do not overlap, by `blocks` workgroups of 256 threads, each thread
+   moving four 16-byte vectors per round, loads before stores.  It measures
+   the HBM bandwidth a hand-written kernel reaches on this device, the
+   practical ceiling the step's kernels are compared with besides the
+   vendor peak.  Enqueued on `stream`; FARGO_EINVAL for a bad argument. */
+int fargo_hbm_copy(const void *src, void *dst, size_t bytes, int blocks, void *stream);
+
 /* Copy the time step last computed or imposed on the device into *dt_host
    (waits for the stream). */
 int fargo_get_dt(fargo_ctx *ctx, double *dt_host, void *stream);

@@ -1225,3 +1225,6 @@ void orc_split_shift(double v0, double dt, double dX, int32_t *N, double *xi) { 
 
 /* Threads the oracle's parallel loops use. */
 int orc_num_threads(void) { return omp_get_max_threads(); }
+/* Thread count of later parallel regions (timing on a given number of cores);
+   the arithmetic of a zone does not depend on it. */
+void orc_set_num_threads(int n) { if (n > 0) omp_set_num_threads(n); }

@@ -44,14 +44,27 @@ class _State(C.Structure):
 
 
 _lib = None
+_path = None  # the library to load (default: the portable build)
+
+
+def use_native():
+    """Load the copy built with -march=native on this host (built here if
+    missing) instead of the portable one; for timing.  Same bits: no
+    contraction, no fast-math.  Must be called before the first oracle call."""
+    global _path
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _build.build(native=True)
+    _path = _build.LIB_NATIVE
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        path = _path or _build.LIB
+        if not os.path.exists(path):
             _build.build()
-        L = C.CDLL(_build.LIB)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
         P = C.POINTER(_Params)
@@ -71,6 +84,8 @@ def lib():
         L.orc_split_shift.argtypes = [C.c_double, C.c_double, C.c_double, ip, dp]
         L.orc_split_shift.restype = None
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -203,3 +218,7 @@ def split_shift(v0: float, dt: float, dX: float):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int):
+    lib().orc_set_num_threads(int(n))

@@ -354,6 +354,14 @@ int upload_background(fargo_ctx *ctx, const double *vb) {
             (vb[r] - vb[r - 1]) / G.hy[j] - 0.5 * (vb[r] / G.ymed[j] + vb[r - 1] / G.ymed[j - 1]);
       }
       if (k > 0) tab[BG_DLZ * n2 + r] = ell[r] - ell[r - nyg];
+      if (!cart && j > 0) {
+        const double W = 0.5 * (tab[BG_VT * n2 + r] + tab[BG_VT * n2 + r - 1]);
+        tab[BG_CY * n2 + r] = W * W * G.inv_ymin[j];
+      }
+      if (sph && k > 0) {
+        const double W = 0.5 * (tab[BG_VT * n2 + r] + tab[BG_VT * n2 + r - nyg]);
+        tab[BG_CZ * n2 + r] = W * W * G.cotz[k] * (1.0 / G.ymed[j]);
+      }
     }
   return hip_ok(hipMemcpy((void *)m.bgt, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));
 }
@@ -710,6 +718,16 @@ int fargo_conserved_sums_noalloc(fargo_ctx *ctx, const fargo_state *state, doubl
   if (hipGetLastError() != hipSuccess) return FARGO_EHIP;
   if (hipMemcpyAsync(out, res, 5 * 8, hipMemcpyDeviceToHost, s) != hipSuccess) return FARGO_EHIP;
   return hip_ok(hipStreamSynchronize(s));
+}
+
+int fargo_hbm_copy(const void *src, void *dst, size_t bytes, int blocks, void *stream) {
+  if (!src || !dst || bytes == 0 || (bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15))
+    return FARGO_EINVAL;
+  if (blocks < 1 || blocks > (1 << 20)) return FARGO_EINVAL;
+  const char *a = (const char *)src, *b = (const char *)dst;
+  if (a < b + bytes && b < a + bytes) return FARGO_EINVAL; // overlapping ranges
+  launch_stream_copy((hipStream_t)stream, src, dst, bytes, blocks);
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
 
 int fargo_get_dt(fargo_ctx *ctx, double *dt_host, void *stream) {

@@ -105,6 +105,10 @@ enum BgTable {
   BG_DLZ, // ell(j, k) - ell(j, k - 1) (0 for k = 0)
   BG_KV,  // viscous edge term of the background (cylindrical 2D):
           // (vb_j - vb_{j-1}) / h_j - (vb_j / r_j + vb_{j-1} / r_{j-1}) / 2
+  BG_CY,  // centrifugal term of the background on Y face j: W^2 / ymin(j),
+          // W = (VT(j, k) + VT(j - 1, k)) / 2 (cylindrical and spherical)
+  BG_CZ,  // on spherical Z face k: W^2 cot(zmin(k)) / ymed(j),
+          // W = (VT(j, k) + VT(j, k - 1)) / 2
   BG_N
 };
 
@@ -311,6 +315,8 @@ constexpr int SUMS_STATIC_RINGS = 1 << 17;
 constexpr int SCRATCH_MAX_DEVICES = 64;
 int static_scratch_setup(int dev);
 double *static_scratch(int dev);
+// bandwidth probe: a plain streaming copy of `bytes` (a multiple of 16)
+void launch_stream_copy(hipStream_t s, const void *src, void *dst, size_t bytes, int blocks);
 template <typename R>
 void launch_sums(Launch &L, const Mesh &m, const StateT<R> &s, double *partial, double *out);
 

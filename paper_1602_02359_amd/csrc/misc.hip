@@ -113,7 +113,34 @@ __global__ __launch_bounds__(256) void k_sums_final(int nring, const double *__r
   }
 }
 
+// Streaming copy for the bandwidth probe: each thread moves U 16-byte
+// vectors per round, every load of a round issued before its stores, rounds
+// strided over the whole grid.
+template <int U>
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                     size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x * U;
+  for (size_t b = (size_t)blockIdx.x * blockDim.x * U + threadIdx.x; b < n; b += stride) {
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const size_t i = b + (size_t)u * blockDim.x;
+      if (i < n) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const size_t i = b + (size_t)u * blockDim.x;
+      if (i < n) dst[i] = v[u];
+    }
+  }
+}
+
 } // namespace
+
+void launch_stream_copy(hipStream_t s, const void *src, void *dst, size_t bytes, int blocks) {
+  const size_t n = bytes / 16;
+  k_stream_copy<4><<<(unsigned)blocks, 256, 0, s>>>((const uint4 *)src, (uint4 *)dst, n);
+}
 
 template <typename F>
 void launch_shift(Launch &L, const Mesh &m, F *field, const int32_t *N) {

@@ -26,8 +26,10 @@
 // The field type F is double, or float for the FP32-bulk state; arithmetic is
 // carried out in F, geometric factors are rounded to F where they are used.
 // An FP32 v_x is a deviation from its ring's FP64 background vb: the X-face
-// update acts on it unchanged, and the centrifugal terms add the ring's
-// vb + R Omega (formed in FP64, rounded once) where the frame term stood.
+// update acts on it unchanged, and each centrifugal term splits into the
+// square of the background (vb + R Omega), formed in FP64 together with the
+// potential gradient it nearly cancels and rounded once, and the FP32 terms
+// of the deviation.
 #include <type_traits>
 
 #include "fargo_internal.h"
@@ -158,21 +160,28 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
     F gradP = F(2) * (pres(z0.rho, z0.q) - pres(zb.rho, zb.q)) * iz;
     F gradPhi = (F)((z0.pot - zb.pot) * ihzd);
     F src = F(0);
-    if (sph) {
-      // inertial azimuthal velocity v_x + R Omega of the two rings; an FP32
-      // v_x is a deviation, and the ring's background vb + R Omega is added
-      F o0, o1;
-      if constexpr (sizeof(F) == 4) {
-        o0 = (F)m.bg(BG_VT, jg, p);
-        o1 = (F)m.bg(BG_VT, jg, m.kbelow(p));
+    if constexpr (sizeof(F) == 4) {
+      if (sph) {
+        // an FP32 v_x is a deviation d from the ring's background: with W the
+        // mean background of the two rings, vt^2 = W^2 + (2 W + d) d, and the
+        // W^2 part, which the potential and pressure gradients nearly cancel,
+        // is formed with the potential gradient in FP64 and rounded once
+        const F W = (F)(0.5 * (m.bg(BG_VT, jg, p) + m.bg(BG_VT, jg, m.kbelow(p))));
+        const F d = F(0.25) * ((z0.vx + z0.vxp) + (zb.vx + zb.vxp));
+        const F base = (F)(m.bg(BG_CZ, jg, p) - (z0.pot - zb.pot) * ihzd);
+        src = (F(2) * W + d) * d * (F)m.g.cotz(p) * (F)g_iymed + base;
       } else {
-        o0 = (F)(g_ymed * m.g.sinz(p)) * om;
-        o1 = (F)(g_ymed * m.g.sinz(m.kbelow(p))) * om;
+        src = -gradPhi;
       }
-      F vt = F(0.25) * ((z0.vx + o0) + (z0.vxp + o0) + (zb.vx + o1) + (zb.vxp + o1));
-      src = vt * vt * (F)m.g.cotz(p) * (F)g_iymed;
+      return z0.vz - dt * gradP + dt * src;
+    } else {
+      if (sph) { // inertial azimuthal velocity v_x + R Omega of the two rings
+        const F o0 = (F)(g_ymed * m.g.sinz(p)) * om, o1 = (F)(g_ymed * m.g.sinz(m.kbelow(p))) * om;
+        F vt = F(0.25) * ((z0.vx + o0) + (z0.vxp + o0) + (zb.vx + o1) + (zb.vxp + o1));
+        src = vt * vt * (F)m.g.cotz(p) * (F)g_iymed;
+      }
+      return z0.vz - dt * (gradP + gradPhi) + dt * src;
     }
-    return z0.vz - dt * (gradP + gradPhi) + dt * src;
   };
   const bool per = m.zper();
   auto pl = [&](int p) { return per ? m.k0 + (p - m.k0 + 2 * m.nz) % m.nz : p; };
@@ -271,27 +280,43 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
       const F gradP = F(2) * (L.P[sb][t][sl] - L.P[sb][t - 1][sl]) * inv;
       const F gradPhi = (F)((L.Ph[sb][t][sl] - L.Ph[sb][t - 1][sl]) * ihd);
       F src = F(0);
-      if (cyl || sph) {
-        const int ya = yrow(t - 1);
-        F ot, oa; // R Omega, or the ring's vb + R Omega for an FP32 deviation
-        if constexpr (sizeof(F) == 4) {
-          ot = (F)m.bg(BG_VT, f, kk);
-          oa = (F)m.bg(BG_VT, ya, kk);
+      if constexpr (sizeof(F) == 4) {
+        // an FP32 v_x is a deviation d from the ring's background: with W the
+        // mean background of the two rings, v^2 = W^2 + (2 W + d) d; the W^2
+        // part, which gravity cancels to order h^2 in a disk, is formed with
+        // the potential gradient in FP64 and rounded once
+        if (cyl || sph) {
+          const int ya = yrow(t - 1);
+          const F W = (F)(0.5 * (m.bg(BG_VT, f, kk) + m.bg(BG_VT, ya, kk)));
+          const F d = F(0.25) * ((L.VX[sb][t][sl] + L.VX[sb][t][sl + 1]) + (L.VX[sb][t - 1][sl] + L.VX[sb][t - 1][sl + 1]));
+          src = (F(2) * W + d) * d;
+          if (sph) {
+            const F wv = F(0.25) * (L.VT[sb][t][cc] + L.VT[sb][t - 1][cc]);
+            src += wv * wv;
+          }
+          src = src * (F)m.g.inv_ymin(f) +
+                (F)(m.bg(BG_CY, f, kk) - (L.Ph[sb][t][sl] - L.Ph[sb][t - 1][sl]) * ihd);
         } else {
-          ot = (F)(sph ? m.g.ymed(f) * m.g.sinz(kk) : m.g.ymed(f)) * om;
-          oa = (F)(sph ? m.g.ymed(ya) * m.g.sinz(kk) : m.g.ymed(ya)) * om;
+          src = -gradPhi;
         }
-        const F vt0 = (L.VX[sb][t][sl] + ot) + (L.VX[sb][t][sl + 1] + ot);
-        const F vt1 = (L.VX[sb][t - 1][sl] + oa) + (L.VX[sb][t - 1][sl + 1] + oa);
-        const F v = F(0.25) * (vt0 + vt1);
-        src = v * v;
-        if (sph) {
-          const F wv = F(0.25) * (L.VT[sb][t][cc] + L.VT[sb][t - 1][cc]);
-          src += wv * wv;
+        L.AY[sb][t][cc] = L.VY[sb][t][cc] - dt * gradP + dt * src;
+      } else {
+        if (cyl || sph) {
+          const int ya = yrow(t - 1);
+          const F ot = (F)(sph ? m.g.ymed(f) * m.g.sinz(kk) : m.g.ymed(f)) * om;
+          const F oa = (F)(sph ? m.g.ymed(ya) * m.g.sinz(kk) : m.g.ymed(ya)) * om;
+          const F vt0 = (L.VX[sb][t][sl] + ot) + (L.VX[sb][t][sl + 1] + ot);
+          const F vt1 = (L.VX[sb][t - 1][sl] + oa) + (L.VX[sb][t - 1][sl + 1] + oa);
+          const F v = F(0.25) * (vt0 + vt1);
+          src = v * v;
+          if (sph) {
+            const F wv = F(0.25) * (L.VT[sb][t][cc] + L.VT[sb][t - 1][cc]);
+            src += wv * wv;
+          }
+          src *= (F)m.g.inv_ymin(f);
         }
-        src *= (F)m.g.inv_ymin(f);
+        L.AY[sb][t][cc] = L.VY[sb][t][cc] - dt * (gradP + gradPhi) + dt * src;
       }
-      L.AY[sb][t][cc] = L.VY[sb][t][cc] - dt * (gradP + gradPhi) + dt * src;
       L.IY[sb][t][cc] = inv;
     };
     if (act) {

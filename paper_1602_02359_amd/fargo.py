@@ -67,6 +67,7 @@ _lib.fargo_shift.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.fargo_ring_split.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.fargo_conserved_sums.argtypes = [C.c_void_p, _S, C.POINTER(C.c_double), C.c_void_p]
 _lib.fargo_conserved_sums_noalloc.argtypes = [C.c_void_p, _S, C.POINTER(C.c_double), C.c_void_p]
+_lib.fargo_hbm_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
 _lib.fargo_get_dt.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
 _lib.fargo_check.argtypes = [C.c_void_p]
 _lib.fargo_profile_enable.argtypes = [C.c_void_p, C.c_int]
@@ -106,7 +107,7 @@ _lib.fargo_lfc_target.argtypes = [C.c_void_p, _S, _S, C.c_void_p, C.c_void_p]
 
 EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_workspace_bytes", "fargo_init",
             "fargo_set_vx_background", "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
-            "fargo_conserved_sums", "fargo_conserved_sums_noalloc", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
+            "fargo_conserved_sums", "fargo_conserved_sums_noalloc", "fargo_hbm_copy", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
             "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_destroy",
             "fargo_lfc_create", "fargo_lfc_destroy", "fargo_lfc_set_params", "fargo_lfc_get_params",
             "fargo_lfc_get_grad", "fargo_lfc_forward", "fargo_lfc_train_step", "fargo_lfc_apply",
@@ -199,7 +200,7 @@ class Solver:
 
     def __del__(self):
         ctx = getattr(self, "_ctx", None)
-        if ctx is not None and ctx.value:
+        if ctx is not None and ctx.value and _lib is not None:  # _lib is None at interpreter exit
             _lib.fargo_destroy(ctx)
             self._ctx = None
 
@@ -311,6 +312,13 @@ class Solver:
         n = C.c_int()
         _check(_lib.fargo_timings(self._ctx, names, counts, tot, cap, C.byref(n), _stream(stream)), "fargo_timings")
         return {names[i].decode(): (counts[i], tot[i]) for i in range(n.value) if counts[i] > 0}
+
+
+def fargo_hbm_copy(src: torch.Tensor, dst: torch.Tensor, blocks: int, stream=None):
+    """The library's streaming copy (bandwidth probe) of src into dst."""
+    assert src.is_contiguous() and dst.is_contiguous() and src.nbytes == dst.nbytes
+    _check(_lib.fargo_hbm_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), src.nbytes, int(blocks),
+                               _stream(stream)), "fargo_hbm_copy")
 
 
 class Batch:
