@@ -42,8 +42,10 @@ NGH = 3
 def words_per_unit(p):
     """Algorithmic words (8 bytes in FP64, 4 in FP32 bulk) moved per zone by
     each kernel of the step (each input read once, each output written once),
-    and the zones one launch processes."""
+    and the zones one launch processes.  The potential is FP64 in both modes:
+    two words of an FP32 state."""
     d3 = p["nz"] > 1
+    pw = 2 if p.get("precision") == "fp32" else 1
     adi = 1 if p["eos"] == "adi" else 0
     nT = 5 + (2 if d3 else 0) + adi
     nvel = 3 if d3 else 2
@@ -53,7 +55,7 @@ def words_per_unit(p):
     return {
         # name: (words per zone, zones per launch)
         "cfl": (2 + nvel, act),                              # rho, cs|e, velocities
-        "source": ((3 + nvel) + (nvel + adi), act),          # rho, cs|e, pot, v -> v'', e''
+        "source": ((2 + pw + nvel) + (nvel + adi), act),     # rho, cs|e, pot, v -> v'', e''
         "source_ghosts": (2 * (nvel + adi), whole - act),    # v, e -> v'', e'' in ghost zones
         "sweep_y": ((1 + nvel + adi) + nT, y_rows),          # rho, v'', e'' -> T (momenta formed on the fly)
         "sweep_z": ((2 * nT + 1) if d3 else 0, act),         # T, v_z -> T
