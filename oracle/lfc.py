@@ -142,6 +142,35 @@ def forward(f, P, rounded=True):
 
 
 # ---------------------------------------------------------------------------
+# what an FP32-accumulating implementation may return
+# ---------------------------------------------------------------------------
+
+U32 = 2.0 ** -24  # unit roundoff of FP32
+
+
+def sum_bound(depth: int, abs_sum) -> np.ndarray:
+    """Bound on the error of a sum of bfloat16 products (exact in FP32) taken
+    in FP32 with at most `depth` additions along any path to the result, at
+    up to two units of roundoff each (allowing a matrix unit's accumulation
+    to round less tightly than IEEE addition): 2 depth u sum|terms|."""
+    return 2.0 * depth * U32 * np.asarray(abs_sum, dtype=np.float64)
+
+
+def interval(z, delta, relu=False, mask=None):
+    """The values a stored bfloat16 result q(x) = bf16(fp32(x)) (after a ReLU,
+    or masked to zero where mask is False) can take when x lies within delta
+    of the exact z: q is monotone, so [q(z - delta), q(z + delta)], with
+    q(z) the oracle's own value."""
+    def q(x):
+        x = np.float32(x)
+        return bf16(np.maximum(x, np.float32(0.0)) if relu else x)
+    lo, mid, hi = q(z - delta), q(z), q(z + delta)
+    if mask is not None:
+        lo, mid, hi = (np.where(mask, a, 0.0) for a in (lo, mid, hi))
+    return lo, mid, hi
+
+
+# ---------------------------------------------------------------------------
 # fluxes, update, loss
 # ---------------------------------------------------------------------------
 

@@ -129,6 +129,37 @@ def test_batch_step_equals_individual_steps(precision):
     del b
 
 
+def test_batch_fp64_matches_oracle():
+    """Six uneven viscous disks advanced by one captured graph per step
+    (each disk with its own device time step), every disk against the oracle
+    after each of two steps: the time step within the bound of the two codes'
+    FP64 arithmetic (32 units in the last place, then 1e-12 once the states
+    differ by rounding) and the state within 1e-12 normwise.  The per-component
+    errors are printed for information: a batch cannot be given the oracle's
+    time step, and v_y, some 1e-3 of the orbital speed, carries the 1e-15
+    relative difference of the two time steps at its own scale."""
+    from paper_1602_02359_amd import fargo as F
+    probs, solvers = _small_batch(6, "fp64")
+    refs = [p.copy_fields() for p in probs]
+    b = F.Batch(solvers, lanes=3)
+    for n in range(2):
+        b.fargo_batch_step()
+        for p, sv, ref in zip(probs, solvers, refs):
+            dt_ref = O.step(p.params, ref)
+            dt = sv.fargo_get_dt()
+            if n == 0:
+                assert dt_close(dt, dt_ref), (p.name, dt, dt_ref)
+            else:
+                assert abs(dt / dt_ref - 1.0) < 1e-12, (p.name, dt, dt_ref)
+            sv.fargo_check()
+            got = sv.download()
+            err, own = errors(p, got, ref), errors_own(p, got, ref)
+            _say("batch step", n + 1, p.name, p.params["nx"], p.params["ny"], err, "per component", own)
+            for k, e in err.items():
+                assert e <= TOL, (p.name, k, e)
+    del b
+
+
 def test_batch_tune_keeps_states_and_picks_a_candidate():
     import torch
     from paper_1602_02359_amd import fargo as F

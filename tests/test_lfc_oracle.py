@@ -203,3 +203,37 @@ def test_restriction_samples_the_coarse_faces():
     assert np.allclose(vxc, np.sin(phi_c)[None, :], atol=1e-15)
     want = np.array([np.cos(phi_c + a * 2 * np.pi / (nx * R)) for a in range(R)]).mean(axis=0)
     assert np.allclose(vyc, want[None, :], atol=1e-15)
+
+
+def test_fp32_sum_bound_and_rounding_interval():
+    """The checker the GPU tests use: a sum of bfloat16 products accumulated
+    in FP32 in any order stays within sum_bound of the exact sum, and its
+    stored rounding within interval(); a conv with its taps mirrored (a
+    plausible indexing mistake) lands outside the intervals."""
+    rng = np.random.default_rng(7)
+    x = L.bf16(rng.standard_normal((6, 16, 32)))
+    w = L.bf16(0.1 * rng.standard_normal((32, 3, 3, 32)))
+    b = rng.standard_normal(32).astype(np.float32).astype(np.float64)
+    z = L.conv(x, w, b)
+    za = L.conv(np.abs(x), np.abs(w), np.abs(b))
+    d = L.sum_bound(9 * 32 + 1, za)
+    # FP32 accumulation, tap by tap and channel by channel, bias last
+    acc = np.zeros(z.shape, dtype=np.float32)
+    xp = np.zeros((8, 16, 32))
+    xp[1:-1] = x
+    for ty in range(3):
+        for tx in range(3):
+            sh = np.roll(xp[ty:ty + 6], -(tx - 1), axis=1).astype(np.float32)
+            for ci in range(32):
+                acc = acc + sh[..., ci:ci + 1] * w[:, ty, tx, ci].astype(np.float32)
+    acc = acc + b.astype(np.float32)
+    assert np.all(np.abs(acc.astype(np.float64) - z) <= d)
+    lo, mid, hi = L.interval(z, d, relu=True)
+    got = L.bf16(np.maximum(acc, np.float32(0.0)))
+    assert np.all((got >= lo) & (got <= hi))
+    assert np.count_nonzero(got != mid) <= max(8, got.size // 1000)
+    # the same layer with mirrored taps
+    bad = L.conv(x, w[:, ::-1, ::-1, :], b)
+    got_bad = L.bf16(np.maximum(np.float32(bad), np.float32(0.0)))
+    outside = np.count_nonzero((got_bad < lo) | (got_bad > hi))
+    assert outside > got.size // 2
