@@ -321,9 +321,9 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
 def copy_bandwidth():
     """Bytes read plus written per second by a plain 1 GiB device copy, timed
     with HIP events: torch's copy kernel, and the library's hand-written
-    streaming copy (16-byte vectors, four per thread per round, loads before
-    stores) at several grid sizes, the best of which is the practical HBM
-    ceiling a kernel reaches on this GPU (the vendor peak is 8 TB/s)."""
+    streaming copy (16-byte vectors, four per thread per round over a grid of
+    several sizes, or one per thread), the best of which is the practical
+    HBM ceiling a kernel reaches on this GPU (the vendor peak is 8 TB/s)."""
     import torch
     from paper_1602_02359_amd import fargo as F
     src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
@@ -343,7 +343,7 @@ def copy_bandwidth():
 
     out = {"torch_copy_GBs": rate(lambda: dst.copy_(src))}
     grid = {}
-    for blocks in (1024, 2048, 4096, 8192, 16384, 32768):
+    for blocks in (8192, 32768, 131072, 0):  # 0: one thread per 16-byte vector
         grid[blocks] = rate(lambda: F.fargo_hbm_copy(src, dst, blocks))
     best = max(grid, key=grid.get)
     out["hip_stream_copy_GBs"] = grid[best]

@@ -106,8 +106,8 @@ extern "C" {
 typedef struct {
   int32_t abi_version;     /* FARGO_ABI_VERSION */
   int32_t geometry;        /* FARGO_CARTESIAN / _CYLINDRICAL / _SPHERICAL */
-  int32_t nx, ny, nz;      /* active zones; nx >= 1, ny >= 3, nz == 1 (2D) or >= 3;
-                              spherical needs nz >= 3 */
+  int32_t nx, ny, nz;      /* active zones; 1 <= nx <= 2^22, ny >= 3, nz == 1 (2D) or >= 3;
+                              spherical needs nz >= 3; every field below 2^31 elements */
   double xmin, xmax;       /* azimuthal (X) extent; dx = (xmax - xmin)/nx */
   const double *ymin;      /* host, ny + 7 increasing face coordinates (ghosts included);
                               copied at fargo_init */
@@ -199,7 +199,9 @@ int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream);
    place, Q_i <- Q_{(i - N) mod nx}, with N = nshift[(k - k0)*ny + (j - j0)]
    read from a device array of ny*nz int32 (k0 = 3 in 3D, 0 in 2D).  The
    field has the state element type of the context.  Ghost rows are not
-   touched.  Bit-exact (a pure permutation). */
+   touched.  Bit-exact (a pure permutation).  A ring is staged in LDS: nx
+   times the element size at most 64 KiB (FARGO_EUNSUPPORTED otherwise; the
+   step's own shift has no such limit). */
 int fargo_shift(fargo_ctx *ctx, void *field, const int32_t *nshift, void *stream);
 
 /* Box 3 and the split of Eq. 29 for a given dt, on active rings: v0 (Eq. 37
@@ -240,7 +242,8 @@ int fargo_conserved_sums_noalloc(fargo_ctx *ctx, const fargo_state *state, doubl
 /* Bandwidth probe (no part of the method): a plain streaming copy of `bytes`
    (a multiple of 16) from src to dst, device buffers aligned to 16 bytes
    that do not overlap, by `blocks` workgroups of 256 threads, each thread
-   moving four 16-byte vectors per round, loads before stores.  It measures
+   moving four 16-byte vectors per round, loads before stores; blocks = 0
+   launches one thread per 16-byte vector instead.  It measures
    the HBM bandwidth a hand-written kernel reaches on this device, the
    practical ceiling the step's kernels are compared with besides the
    vendor peak.  Enqueued on `stream`; FARGO_EINVAL for a bad argument. */

@@ -118,7 +118,7 @@ int check_params(const fargo_params *p) {
   if (p->visc != 0 && p->visc != 1) return FARGO_EINVAL;
   if (p->visc && (p->geometry != FARGO_CYLINDRICAL || p->nz != 1 || p->eos != FARGO_ISOTHERMAL))
     return FARGO_EUNSUPPORTED;
-  if (p->nx > 4096) return FARGO_EUNSUPPORTED; // the time-step kernel holds a ring in one workgroup
+  if (p->nx > (1 << 22)) return FARGO_EUNSUPPORTED; // segments of a ring in one launch dimension
   {
     // kernels address fields with 32-bit element offsets
     size_t pitch = (size_t)(p->nx + 63) / 64 * 64;
@@ -140,6 +140,9 @@ void dims(const fargo_params *p, int &pitch, int &nyg, int &nzg) {
   nyg = p->ny + 2 * NGH;
   nzg = p->nz > 1 ? p->nz + 2 * NGH : 1;
 }
+
+// segments per ring of the time-step pass (1: one workgroup holds the ring)
+int cfl_segments(int nx) { return nx <= CFL_RING_MAX ? 1 : (nx + CFL_SEG - 1) / CFL_SEG; }
 
 int ntransported(const fargo_params *p) { return 5 + (p->nz > 1 ? 2 : 0) + (p->eos == FARGO_ADIABATIC ? 1 : 0); }
 
@@ -252,7 +255,7 @@ size_t geo_doubles(int nyg, int nzg) {
 }
 
 struct Layout {
-  size_t geo, words, v0, ringrate, ringshear, partial, sums, bg, v2, T, total;
+  size_t geo, words, v0, ringrate, ringshear, segmm, partial, sums, bg, v2, T, total;
 };
 
 Layout layout(const fargo_params *p) {
@@ -269,10 +272,13 @@ Layout layout(const fargo_params *p) {
   o += 256;
   L.v0 = o;
   o += al(nring * 8);
+  const size_t cseg = (size_t)cfl_segments(p->nx);
   L.ringrate = o;
-  o += al(nring * 8);
+  o += al(nring * cseg * 8);
   L.ringshear = o;
-  o += al(nring * 8);
+  o += al(nring * cseg * 8);
+  L.segmm = o;
+  if (cseg > 1) o += al(nring * cseg * 2 * 8);
   L.partial = o;
   o += al(nring * 10 * 8);
   L.sums = o;
@@ -503,6 +509,8 @@ int fargo_init(const fargo_params *params, void *workspace, size_t ws_bytes, far
   for (int s = 0; s < 4; s++) m.bc[s] = params->bc[s];
   m.nring = params->ny * params->nz;
   m.chunk = 64;
+  m.cseg = cfl_segments(params->nx);
+  m.segmm = m.cseg > 1 ? (double *)(base + Lo.segmm) : nullptr;
   m.dx = (params->xmax - params->xmin) / params->nx;
   m.gamma = params->gamma;
   m.omega = params->omega;
@@ -663,7 +671,7 @@ int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream) {
 
 int fargo_shift(fargo_ctx *ctx, void *field, const int32_t *nshift, void *stream) {
   if (!ctx || !field || !nshift) return FARGO_EINVAL;
-  if (ctx->m.nx > 8192) return FARGO_EUNSUPPORTED;
+  if ((size_t)ctx->m.nx * ctx->esize > 65536) return FARGO_EUNSUPPORTED; // the ring is staged in LDS
   Launch L{(hipStream_t)stream, &ctx->prof};
   if (fp32(ctx)) launch_shift(L, ctx->m, (float *)field, nshift);
   else launch_shift(L, ctx->m, (double *)field, nshift);
@@ -723,7 +731,7 @@ int fargo_conserved_sums_noalloc(fargo_ctx *ctx, const fargo_state *state, doubl
 int fargo_hbm_copy(const void *src, void *dst, size_t bytes, int blocks, void *stream) {
   if (!src || !dst || bytes == 0 || (bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15))
     return FARGO_EINVAL;
-  if (blocks < 1 || blocks > (1 << 20)) return FARGO_EINVAL;
+  if (blocks < 0 || blocks > (1 << 20) || bytes / 16 / 256 >= ((size_t)1 << 31)) return FARGO_EINVAL;
   const char *a = (const char *)src, *b = (const char *)dst;
   if (a < b + bytes && b < a + bytes) return FARGO_EINVAL; // overlapping ranges
   launch_stream_copy((hipStream_t)stream, src, dst, bytes, blocks);

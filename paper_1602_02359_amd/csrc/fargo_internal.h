@@ -118,6 +118,10 @@ struct Mesh {
   int bc[4];
   int nring; // ny * nz active rings
   int chunk; // zones per thread of the Y and Z column sweeps (a tuning parameter)
+  // rings longer than CFL_RING_MAX zones: the time-step pass splits each ring
+  // into cseg segments of CFL_SEG zones (1 otherwise), with per-segment slots
+  int cseg;
+  double *segmm; // per-segment extrema (or sums) of v_x, 2 per segment (cseg > 1)
   double dx, gamma, omega, courant, cvnr, shear_c0;
   GeoTables g;
   const double *bgt; // background tables (FP32-bulk state), NULL for FP64
@@ -273,6 +277,9 @@ void launch_bc(Launch &L, const Mesh &m, R *rho, R *e, R *vx, R *vy, R *vz);
 // boxes 3, 6 and the split of Eq. 29 (always FP64)
 void launch_set_dt(Launch &L, const DevWords &w, double dt);
 // per ring: v0 and (with_cfl) the largest squared rate 1/dt^2 of Eq. cfl2 and the maximum shear rate
+// (per segment of a ring when m.cseg > 1: ringrate and ringshear hold nring * cseg slots)
+constexpr int CFL_RING_MAX = 4096; // the longest ring one workgroup of the time-step kernel holds
+constexpr int CFL_SEG = 1024;      // zones of a segment of a longer ring
 template <typename R>
 void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringrate,
                 double *ringshear, int *err);

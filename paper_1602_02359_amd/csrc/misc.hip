@@ -139,7 +139,8 @@ __global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ s
 
 void launch_stream_copy(hipStream_t s, const void *src, void *dst, size_t bytes, int blocks) {
   const size_t n = bytes / 16;
-  k_stream_copy<4><<<(unsigned)blocks, 256, 0, s>>>((const uint4 *)src, (uint4 *)dst, n);
+  if (blocks > 0) k_stream_copy<4><<<(unsigned)blocks, 256, 0, s>>>((const uint4 *)src, (uint4 *)dst, n);
+  else k_stream_copy<1><<<(unsigned)((n + 255) / 256), 256, 0, s>>>((const uint4 *)src, (uint4 *)dst, n);
 }
 
 template <typename F>

@@ -82,6 +82,65 @@ __device__ inline double ring_bulk(const Mesh &m, const double (&v)[M], int tid,
   return 0.5 * (vmax + vmin);
 }
 
+// Constants of Eq. cfl2 for ring (j, k): lengths and their reciprocals.
+struct CflRing {
+  double Lx, iLx, iLy, iLz, iL2, k3, dXp;
+};
+__device__ inline CflRing cfl_ring(const Mesh &m, int j, int k, bool shear_on) {
+#pragma clang fp contract(off)
+  CflRing C;
+  const double Lyy = m.g.Ly(j), Lzz = m.d3 ? m.Lz(j, k) : 0.0;
+  C.Lx = m.DX(j, k);
+  C.iLx = 1.0 / C.Lx;
+  C.iLy = 1.0 / Lyy;
+  C.iLz = m.d3 ? 1.0 / Lzz : 0.0;
+  double Lmin = fmin(C.Lx, Lyy);
+  if (m.d3) Lmin = fmin(Lmin, Lzz);
+  C.iL2 = 1.0 / (Lmin * Lmin);
+  C.k3 = 4.0 * m.cvnr * m.cvnr;
+  C.dXp = shear_on ? m.DX(j + 1, k) : 1.0;
+  return C;
+}
+
+// Eq. cfl2 for one zone through the inverse steps (rates u / Delta): the
+// minimum step of a cell over directions is its maximum rate; returns the sum
+// of the squared rates of items 1-3 (and 4 with viscosity), and flags a
+// non-finite or non-positive state in `bad`.  q: sound speed (isothermal)
+// or internal energy; vxc, vxp: full v_x on the zone's two X faces; vb: the
+// ring's bulk velocity (0 without orbital advection).
+__device__ inline double zone_rate2(const Mesh &m, const CflRing &C, double vb, double vxc, double vxp, double rho,
+                                    double q, double vyc, double vyp, double vzc, double vzp, double nu, int &bad) {
+#pragma clang fp contract(off)
+  double cw2; // squared wave speed
+  if (m.eos == FARGO_ISOTHERMAL) cw2 = q * q;
+  else cw2 = m.gamma * ((m.gamma - 1.0) * q) / rho;
+  bad |= !(rho > 0.0) || !isfinite(rho) || !isfinite(cw2) || !isfinite(vxc) || !isfinite(vyc);
+  // item 1: sound waves (squared rate); item 2: fluid motion; item 3:
+  // artificial viscosity on compressed directions
+  const double r1s = cw2 * C.iL2;
+  const double ux = fmax(fabs(vxc - vb), fabs(vxp - vb));
+  const double uy = fmax(fabs(vyc), fabs(vyp));
+  double r2 = fmax(ux * C.iLx, uy * C.iLy);
+  const double dvx = vxp - vxc, dvy = vyp - vyc;
+  double r3 = 0.0;
+  if (dvx < 0.0) r3 = fmax(r3, C.k3 * fabs(dvx) * C.iLx);
+  if (dvy < 0.0) r3 = fmax(r3, C.k3 * fabs(dvy) * C.iLy);
+  if (m.d3) {
+    bad |= !isfinite(vzc);
+    const double uz = fmax(fabs(vzc), fabs(vzp));
+    r2 = fmax(r2, uz * C.iLz);
+    const double dvz = vzp - vzc;
+    if (dvz < 0.0) r3 = fmax(r3, C.k3 * fabs(dvz) * C.iLz);
+  }
+  double rate2 = r1s + r2 * r2 + r3 * r3;
+  if (m.visc) { // item 4: viscosity, 4 nu / Delta^2
+    const double r4 = 4.0 * nu * C.iL2;
+    rate2 += r4 * r4;
+  }
+  if (!(rate2 >= 0.0)) bad = 1;
+  return rate2;
+}
+
 // Rings in XCD-contiguous logical order, by tiles of 16 planes with k fastest
 // within a tile: the rings holding a ring's k + 1 and j + 1 neighbours (v_z
 // and v_y on its upper faces) were read one and 16 rings earlier, still in L2
@@ -147,58 +206,21 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
   if (tid == 0) v0[r] = vb_ring;
   if (!with_cfl) return;
   const double vb = m.fargo ? vb_ring : 0.0;
-  // Eq. cfl2 through the inverse steps (rates u / Delta): the minimum step of
-  // a cell over directions is its maximum rate, and the smallest step is
-  // 1 / sqrt of the largest sum of squared rates (taken in k_dt_final)
-  const double Lx = m.DX(j, k), Lyy = m.g.Ly(j);
-  const double Lzz = m.d3 ? m.Lz(j, k) : 0.0;
-  const double iLx = 1.0 / Lx, iLy = 1.0 / Lyy, iLz = m.d3 ? 1.0 / Lzz : 0.0;
-  double Lmin = fmin(Lx, Lyy);
-  if (m.d3) Lmin = fmin(Lmin, Lzz);
-  const double iL2 = 1.0 / (Lmin * Lmin);
-  const double k3 = 4.0 * m.cvnr * m.cvnr;
-  const double dXp = shear_on ? m.DX(j + 1, k) : 1.0;
+  // the smallest step is 1 / sqrt of the largest sum of squared rates (taken
+  // in k_dt_final)
+  const CflRing C = cfl_ring(m, j, k, shear_on);
   double rmax = 0.0, smax = 0.0;
   int bad = 0;
 #pragma unroll
   for (int mm = 0; mm < M; mm++) {
     int i = tid + B * mm;
     if (i >= n) continue;
-    double vxc = vx[mm], vxp = V[i + 1 == n ? 0 : i + 1];
-    double rho = (double)fr[mm];
-    double cw2; // squared wave speed
-    if (m.eos == FARGO_ISOTHERMAL) cw2 = (double)fq[mm] * (double)fq[mm];
-    else cw2 = m.gamma * ((m.gamma - 1.0) * (double)fq[mm]) / rho;
-    double vyc = (double)fy0[mm], vyp = (double)fy1[mm];
-    bad |= !(rho > 0.0) || !isfinite(rho) || !isfinite(cw2) || !isfinite(vxc) || !isfinite(vyc);
-    // item 1: sound waves (squared rate); item 2: fluid motion; item 3:
-    // artificial viscosity on compressed directions
-    double r1s = cw2 * iL2;
-    double ux = fmax(fabs(vxc - vb), fabs(vxp - vb));
-    double uy = fmax(fabs(vyc), fabs(vyp));
-    double r2 = fmax(ux * iLx, uy * iLy);
-    double dvx = vxp - vxc, dvy = vyp - vyc;
-    double r3 = 0.0;
-    if (dvx < 0.0) r3 = fmax(r3, k3 * fabs(dvx) * iLx);
-    if (dvy < 0.0) r3 = fmax(r3, k3 * fabs(dvy) * iLy);
-    if (m.d3) {
-      double vzc = (double)fz0[mm], vzp = (double)fz1[mm];
-      bad |= !isfinite(vzc);
-      double uz = fmax(fabs(vzc), fabs(vzp));
-      r2 = fmax(r2, uz * iLz);
-      double dvz = vzp - vzc;
-      if (dvz < 0.0) r3 = fmax(r3, k3 * fabs(dvz) * iLz);
-    }
-    double rate2 = r1s + r2 * r2 + r3 * r3;
-    if (m.visc) {
-      // item 4: viscosity, 4 nu / Delta^2
-      double r4 = 4.0 * (double)fn[mm] * iL2;
-      rate2 += r4 * r4;
-    }
-    if (!(rate2 >= 0.0)) bad = 1;
-    else rmax = rate2 > rmax ? rate2 : rmax;
+    const double vxc = vx[mm], vxp = V[i + 1 == n ? 0 : i + 1];
+    const double rate2 = zone_rate2(m, C, vb, vxc, vxp, (double)fr[mm], (double)fq[mm], (double)fy0[mm],
+                                    (double)fy1[mm], (double)fz0[mm], (double)fz1[mm], (double)fn[mm], bad);
+    if (rate2 >= 0.0) rmax = rate2 > rmax ? rate2 : rmax;
     if (shear_on) {
-      double sh = fabs(vxc / Lx - ((double)fs[mm] + vbg_p) / dXp);
+      double sh = fabs(vxc / C.Lx - ((double)fs[mm] + vbg_p) / C.dXp);
       if (sh > smax) smax = sh;
     }
   }
@@ -207,6 +229,118 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
   if (tid == 0) {
     ringrate[r] = rmax; // the ring's largest squared rate
     ringshear[r] = smax;
+    if (anybad) atomicOr(err, 1);
+  }
+}
+
+// Rings longer than one workgroup holds, in segments of CFL_SEG zones (256
+// threads, four zones each).  First each segment's largest and smallest
+// full v_x (or its sum, for the mean), then each segment combines its ring's
+// entries into v0 (min/max exactly as in ring_bulk; the mean as the sum of the
+// segment sums in segment order, over nx) and takes Eq. cfl2 on its zones,
+// with the v_x of the zone after its last read from memory.
+template <typename R>
+__device__ inline double full_vx(const Mesh &m, const StateT<R> &s, unsigned c, double vbg) {
+  return (double)s.vx[c] + vbg;
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_bulk_seg(Mesh m, StateT<R> s) {
+  constexpr int M = CFL_SEG / 256;
+  __shared__ double red[2 * MAXW];
+  const int r = (int)(blockIdx.x / (unsigned)m.cseg), g = (int)(blockIdx.x % (unsigned)m.cseg);
+  const int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
+  const unsigned base = m.o32(0, j, k);
+  const double vbg = sizeof(R) == 4 ? m.bg(BG_V, j, k) : 0.0;
+  const int i0 = g * CFL_SEG, i1 = min(i0 + CFL_SEG, m.nx);
+  double a = m.v0_mean ? 0.0 : -HUGE_VAL, b = HUGE_VAL;
+#pragma unroll
+  for (int mm = 0; mm < M; mm++) {
+    const int i = i0 + (int)threadIdx.x + 256 * mm;
+    if (i >= i1) continue;
+    const double v = full_vx(m, s, base + (unsigned)i, vbg);
+    if (m.v0_mean) a += v;
+    else {
+      a = v > a ? v : a;
+      b = v < b ? v : b;
+    }
+  }
+  if (m.v0_mean) {
+    a = block_reduce(a, Add(), 0.0, red);
+    b = 0.0;
+  } else {
+    block_reduce2(a, Max(), -HUGE_VAL, b, Min(), HUGE_VAL, red);
+  }
+  if (threadIdx.x == 0) {
+    m.segmm[2 * (size_t)blockIdx.x] = a;
+    m.segmm[2 * (size_t)blockIdx.x + 1] = b;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cfl_seg(Mesh m, StateT<R> s, int with_cfl, double *__restrict__ v0,
+                                                 double *__restrict__ ringrate, double *__restrict__ ringshear,
+                                                 int *__restrict__ err) {
+#pragma clang fp contract(off)
+  constexpr int M = CFL_SEG / 256;
+  __shared__ double red[2 * MAXW];
+  __shared__ double V[CFL_SEG + 1]; // the segment's full v_x and the next zone's
+  const int r = (int)(blockIdx.x / (unsigned)m.cseg), g = (int)(blockIdx.x % (unsigned)m.cseg);
+  const int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
+  const int tid = threadIdx.x, n = m.nx;
+  const unsigned base = m.o32(0, j, k);
+  const bool shear_on = with_cfl && m.fargo && m.shear_c0 > 0.0 && j + 1 < m.jn;
+  double vbg = 0.0, vbg_p = 0.0;
+  if constexpr (sizeof(R) == 4) {
+    vbg = m.bg(BG_V, j, k);
+    if (shear_on) vbg_p = m.bg(BG_V, j + 1, k);
+  }
+  // the ring's bulk velocity from its segments' entries
+  double a = m.v0_mean ? 0.0 : -HUGE_VAL, b = HUGE_VAL;
+  const double *e = m.segmm + 2 * (size_t)r * m.cseg;
+  if (m.v0_mean) {
+    if (tid == 0)
+      for (int q = 0; q < m.cseg; q++) a += e[2 * q];
+    a = block_reduce(tid == 0 ? a : 0.0, Add(), 0.0, red);
+  } else {
+    for (int q = tid; q < m.cseg; q += 256) {
+      a = e[2 * q] > a ? e[2 * q] : a;
+      b = e[2 * q + 1] < b ? e[2 * q + 1] : b;
+    }
+    block_reduce2(a, Max(), -HUGE_VAL, b, Min(), HUGE_VAL, red);
+  }
+  const double vb_ring = m.v0_mean ? a / n : 0.5 * (a + b);
+  if (g == 0 && tid == 0) v0[r] = vb_ring;
+  if (!with_cfl) return;
+  const int i0 = g * CFL_SEG, i1 = min(i0 + CFL_SEG, n);
+  for (int i = i0 + tid; i <= i1; i += 256) V[i - i0] = full_vx(m, s, base + (unsigned)(i == n ? 0 : i), vbg);
+  __syncthreads();
+  const double vb = m.fargo ? vb_ring : 0.0;
+  const CflRing C = cfl_ring(m, j, k, shear_on);
+  const unsigned py = (unsigned)m.pitch, pz = (unsigned)m.plane();
+  const R *qf = m.eos == FARGO_ISOTHERMAL ? s.cs : s.e;
+  double rmax = 0.0, smax = 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int mm = 0; mm < M; mm++) {
+    const int i = i0 + tid + 256 * mm;
+    if (i >= i1) continue;
+    const unsigned c = base + (unsigned)i;
+    const double vxc = V[i - i0], vxp = V[i - i0 + 1];
+    const double rate2 = zone_rate2(m, C, vb, vxc, vxp, (double)s.rho[c], (double)qf[c], (double)s.vy[c],
+                                    (double)s.vy[c + py], m.d3 ? (double)s.vz[c] : 0.0,
+                                    m.d3 ? (double)s.vz[c + pz] : 0.0, m.visc ? (double)s.nu[c] : 0.0, bad);
+    if (rate2 >= 0.0) rmax = rate2 > rmax ? rate2 : rmax;
+    if (shear_on) {
+      const double sh = fabs(vxc / C.Lx - ((double)s.vx[c + py] + vbg_p) / C.dXp);
+      if (sh > smax) smax = sh;
+    }
+  }
+  block_reduce2(rmax, Max(), 0.0, smax, Max(), 0.0, red);
+  const int anybad = __syncthreads_or(bad);
+  if (tid == 0) {
+    ringrate[blockIdx.x] = rmax;
+    ringshear[blockIdx.x] = smax;
     if (anybad) atomicOr(err, 1);
   }
 }
@@ -220,13 +354,14 @@ __global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const dou
   __shared__ double red[2 * MAXW];
   constexpr int U = 8; // loads in flight per thread
   double rmax = 0.0, smax = 0.0;
-  for (int r0 = threadIdx.x; r0 < m.nring; r0 += U * blockDim.x) {
+  const int nslot = m.nring * m.cseg;
+  for (int r0 = threadIdx.x; r0 < nslot; r0 += U * blockDim.x) {
     double a[U], b[U];
 #pragma unroll
     for (int u = 0; u < U; u++) {
       const int r = r0 + u * (int)blockDim.x;
-      a[u] = r < m.nring ? ringrate[r] : 0.0;
-      b[u] = r < m.nring ? ringshear[r] : 0.0;
+      a[u] = r < nslot ? ringrate[r] : 0.0;
+      b[u] = r < nslot ? ringshear[r] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; u++) {
@@ -280,6 +415,13 @@ template <typename R>
 void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, double *v0, double *ringrate,
                 double *ringshear, int *err) {
   prof_begin(L, K_CFL);
+  if (m.cseg > 1) { // rings in segments
+    const unsigned nb = (unsigned)m.nring * (unsigned)m.cseg;
+    k_bulk_seg<R><<<nb, 256, 0, L.s>>>(m, s);
+    k_cfl_seg<R><<<nb, 256, 0, L.s>>>(m, s, with_cfl, v0, ringrate, ringshear, err);
+    prof_end(L, K_CFL);
+    return;
+  }
   if (m.nx > 2048) { // nx <= 4096: 512 threads, 5 to 8 zones each
     switch ((m.nx + 511) / 512) {
     case 5: cfl_launch<5, R, 512>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;

@@ -948,21 +948,32 @@ __global__ __launch_bounds__(256) void k_vel(Mesh m, StateT<F> s, TSetT<F> T) {
   }
 }
 
+// The zones of a direction split into the fewest chunks of at most m.chunk
+// zones, of equal length (the last one shorter by less than the count), so
+// that the threads of a sweep end together.  Returns the mesh with the chunk
+// length the kernels use, and the number of chunks.
+inline Mesh balanced(const Mesh &m, int n, int &nchunk) {
+  nchunk = (n + m.chunk - 1) / m.chunk;
+  Mesh mm = m;
+  mm.chunk = (n + nchunk - 1) / nchunk;
+  return mm;
+}
+
 template <typename F, int NQ, bool D3, bool ADI>
-void sweep_y_launch(Launch &L, const Mesh &m, const StateT<F> &s, const TSetT<F> &out, const double *dt) {
-  int nib, bs;
+void sweep_y_launch(Launch &L, const Mesh &m0, const StateT<F> &s, const TSetT<F> &out, const double *dt) {
+  int nib, bs, nchunk;
+  const Mesh m = balanced(m0, m0.ny, nchunk);
   row_blocks(m.nx, nib, bs);
-  int nchunk = (m.ny + m.chunk - 1) / m.chunk;
   int nrows = D3 ? m.nz + 4 : 1;
   unsigned nb = (unsigned)nib * (unsigned)nchunk * (unsigned)nrows;
   k_sweep_y<F, NQ, D3, ADI><<<nb, bs, 0, L.s>>>(m, s.rho, s.vx, s.vy, s.vz, s.e, out, dt, nchunk);
 }
 
 template <typename F, int NQ>
-void sweep_z_launch(Launch &L, const Mesh &m, const F *vz, const TSetT<F> &in, const TSetT<F> &out, const double *dt) {
-  int nib, bs;
+void sweep_z_launch(Launch &L, const Mesh &m0, const F *vz, const TSetT<F> &in, const TSetT<F> &out, const double *dt) {
+  int nib, bs, nchunk;
+  const Mesh m = balanced(m0, m0.nz, nchunk);
   row_blocks(m.nx, nib, bs);
-  int nchunk = (m.nz + m.chunk - 1) / m.chunk;
   unsigned nb = (unsigned)nib * (unsigned)nchunk * (unsigned)m.ny;
   k_sweep_z<F, NQ><<<nb, bs, 0, L.s>>>(m, vz, in, out, dt, nchunk);
 }
@@ -1012,10 +1023,12 @@ void launch_ring_x(Launch &L, const Mesh &m, const F *vx2, const TSetT<F> &T, co
 
 // Fused Z sweep and X transport: one wave per (segment, row, chunk of planes).
 template <typename F>
-void launch_zx(Launch &L, const Mesh &m, const F *vx2, const F *vz, const TSetT<F> &T, const TSetT<F> &Tout,
+void launch_zx(Launch &L, const Mesh &m0, const F *vx2, const F *vz, const TSetT<F> &T, const TSetT<F> &Tout,
                const StateT<F> &s, const double *v0, const double *dt) {
   constexpr int U = RingLane<F>::U;
-  const int nseg = (m.nx + U - 1) / U, nkc = (m.nz + m.chunk - 1) / m.chunk;
+  int nkc;
+  const Mesh m = balanced(m0, m0.nz, nkc);
+  const int nseg = (m.nx + U - 1) / U;
   const long waves = (long)nseg * m.ny * nkc;
   const unsigned nb = (unsigned)((waves + 3) / 4);
   prof_begin(L, K_ZX);

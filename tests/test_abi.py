@@ -42,8 +42,9 @@ def test_layout_and_validation_without_gpu():
         with pytest.raises(F.FargoError) as e:
             F.fargo_layout(dict(pr.params, **bad))
         assert e.value.code == -1
+    F.fargo_layout(dict(pr.params, nx=8192))  # long rings: the time-step pass takes them in segments
     with pytest.raises(F.FargoError) as e:
-        F.fargo_layout(dict(pr.params, nx=4097))
+        F.fargo_layout(dict(pr.params, nx=(1 << 22) + 1))
     assert e.value.code == -6
     wsb = F.fargo_workspace_bytes(W.disk3d_sph().params)
     assert wsb > 16 * 1536 * 518 * 134 * 8

@@ -85,11 +85,13 @@ def _small(name):
         return W.random_problem("cyl", nx=1, ny=9, nz=6, eos="adi", seed=12, fargo=True)
     if name == "ring_nx3_sph3d":
         return W.random_problem("sph", nx=3, ny=9, nz=6, eos="adi", seed=14, fargo=True)
+    if name == "ring_5000_cyl3d":  # the time-step pass in segments of a long ring
+        return W.random_problem("cyl", nx=5000, ny=4, nz=3, eos="adi", seed=34, fargo=True)
     raise KeyError(name)
 
 
 @pytest.mark.parametrize("name", ["sph3d", "cyl3d_planet", "disk2d", "cart_random", "ring_2048", "cyl3d_chunks",
-                                  "ring_nx1_cyl3d", "ring_nx3_sph3d"])
+                                  "ring_nx1_cyl3d", "ring_nx3_sph3d", "ring_5000_cyl3d"])
 def test_fp32_one_step_vs_oracle(name):
     prob = _small(name)
     _say("fp32 one step", name, prob.params["nx"], prob.params["ny"], prob.params["nz"])

@@ -65,6 +65,13 @@ def _cases():
     yield "ring_nx3_sph", lambda: W.random_problem("sph", nx=3, ny=9, nz=6, eos="adi", seed=14, fargo=True)
     # two chunks of planes in the Z sweep (the second ragged), two ring segments
     yield "cyl3d_chunks", lambda: W.random_problem("cyl", nx=130, ny=5, nz=70, eos="adi", seed=21, fargo=True)
+    # rings longer than one workgroup of the time-step pass holds: segments of
+    # 1024 zones, the last one ragged; v0 by min/max and by the mean; 3D
+    yield "ring_8192", lambda: W.random_problem("cyl", nx=8192, ny=4, nz=1, eos="iso", seed=31, fargo=True)
+    yield "ring_5000_mean", lambda: _with(W.random_problem("cyl", nx=5000, ny=3, nz=1, eos="adi", seed=32,
+                                                           fargo=True), v0_mode="mean")
+    yield "ring_4500_sph3d", lambda: W.random_problem("sph", nx=4500, ny=4, nz=3, eos="adi", seed=33, fargo=True,
+                                                      omega=0.2)
 
 
 def _with(prob, **kw):
