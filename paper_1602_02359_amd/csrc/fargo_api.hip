@@ -121,7 +121,7 @@ int check_params(const fargo_params *p) {
   if (p->nx > (1 << 22)) return FARGO_EUNSUPPORTED; // segments of a ring in one launch dimension
   {
     // kernels address fields with 32-bit element offsets
-    size_t pitch = (size_t)(p->nx + 63) / 64 * 64;
+    size_t pitch = (size_t)(p->nx + 63) / 64 * 64 + 64;
     size_t cells = pitch * (size_t)(p->ny + 2 * NGH) * (size_t)(p->nz > 1 ? p->nz + 2 * NGH : 1);
     if (cells >= ((size_t)1 << 31)) return FARGO_EUNSUPPORTED;
   }
@@ -137,6 +137,10 @@ int check_params(const fargo_params *p) {
 
 void dims(const fargo_params *p, int &pitch, int &nyg, int &nzg) {
   pitch = (p->nx + 63) / 64 * 64;
+  // rows whose length is a multiple of 8 KiB of doubles would put the
+  // neighbours a column sweep reads on the same memory channels: one more
+  // 64-element block of padding (never read or written)
+  if (pitch % 1024 == 0) pitch += 64;
   nyg = p->ny + 2 * NGH;
   nzg = p->nz > 1 ? p->nz + 2 * NGH : 1;
 }

@@ -422,6 +422,11 @@ void launch_cfl(Launch &L, const Mesh &m, const StateT<R> &s, int with_cfl, doub
     prof_end(L, K_CFL);
     return;
   }
+  if (m.nx > 1792 && m.nx <= 2048) { // 512 threads of 4 zones
+    cfl_launch<4, R, 512>(L, m, s, with_cfl, v0, ringrate, ringshear, err);
+    prof_end(L, K_CFL);
+    return;
+  }
   if (m.nx > 2048) { // nx <= 4096: 512 threads, 5 to 8 zones each
     switch ((m.nx + 511) / 512) {
     case 5: cfl_launch<5, R, 512>(L, m, s, with_cfl, v0, ringrate, ringshear, err); break;
