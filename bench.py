@@ -364,7 +364,7 @@ def lfc_variant(iters=600):
     import torch
     from paper_1602_02359_amd import learned as LN
     t0 = time.perf_counter()
-    cp, samples = LN.make_samples(40, spinup=200)
+    cp, samples = LN.make_samples(40, spinup=200, medium=True)
     torch.cuda.synchronize()
     gen = time.perf_counter() - t0
     sc = LN.scales(cp, samples)
@@ -392,6 +392,44 @@ def lfc_variant(iters=600):
     torch.cuda.synchronize()
     apply_ms = 1e3 * (time.perf_counter() - t2) / 50
     npix = cp.params["nx"] * cp.params["ny"]
+    # against the plain FP64 solver: the coarse step with and without the
+    # correction, and the plain solver at twice the resolution (its result
+    # averaged onto the coarse mesh), on the held-out intervals
+    from paper_1602_02359_amd import fargo as F
+    from paper_1602_02359_amd import workloads as W
+
+    def step_ms(prob, nsteps=50):
+        sv = F.Solver(prob.params)
+        sv.upload(prob.fields)
+        for _ in range(3):
+            sv.fargo_step(0.0)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(nsteps):
+            sv.fargo_step(0.0)
+        torch.cuda.synchronize()
+        sv.fargo_check()
+        return 1e3 * (time.perf_counter() - t) / nsteps
+
+    med = LN.medium_error(held)
+    msteps = sum(s["medium_steps"] for s in held) / len(held)
+    cpp = cp.params
+    t_coarse = step_ms(cp)
+    t_medium = step_ms(W.disk2d_planet(nx=2 * cpp["nx"], ny=2 * cpp["ny"]))
+    equal_error = {
+        "metric": "relative error of the density after one coarse interval against the 4x-finer solution "
+                  "averaged onto the coarse mesh (1 = the plain coarse step), held-out intervals",
+        "plain_coarse": {"relative_error": 1.0, "ms_per_interval": t_coarse,
+                         "coarse_cell_updates_per_s": npix / (t_coarse * 1e-3)},
+        "corrected_coarse": {"relative_error": after["relative_error"], "ms_per_interval": t_coarse + apply_ms,
+                             "coarse_cell_updates_per_s": npix / ((t_coarse + apply_ms) * 1e-3)},
+        "plain_2x": {"relative_error": med["relative_error"], "steps_per_interval": msteps,
+                     "ms_per_interval": msteps * t_medium,
+                     "coarse_cell_updates_per_s": npix / (msteps * t_medium * 1e-3)},
+    }
+    print("  lfc equal error: corrected coarse %.3f at %.3f ms, plain 2x %.3f at %.3f ms per interval" % (
+        after["relative_error"], t_coarse + apply_ms, med["relative_error"], msteps * t_medium),
+        file=sys.stderr, flush=True)
     # algorithmic flops of a training step (unpadded GEMM dimensions)
     fl = {"lfc_conv_fwd": 2.0 * npix * (36 * 32 + 288 * 32 + 288 * 2),
           "lfc_conv_bwd_w": 2.0 * npix * (36 * 32 + 288 * 32 + 288 * 2),
@@ -412,6 +450,7 @@ def lfc_variant(iters=600):
         "sample_generation_s": gen,
         "heldout_relative_error": {"before": before["relative_error"], "after": after["relative_error"]},
         "train_relative_error_after": after_train["relative_error"],
+        "against_plain_solver": equal_error,
         "train_steps": 20 + 2 * iters,
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},

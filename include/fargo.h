@@ -356,11 +356,11 @@ int fargo_lfc_apply(fargo_lfc *l, fargo_state *state, void *stream);
    `stream`); either pointer may be NULL. */
 int fargo_lfc_result(fargo_lfc *l, double *loss, int32_t *skipped, void *stream);
 int fargo_lfc_get_views(fargo_lfc *l, fargo_lfc_views *v);
-/* 4 x 4 conservative restriction of the active zones of a fine 2D
-   cylindrical FP64 state onto a coarse one (fine nx, ny = 4 coarse nx, ny;
+/* R x R conservative restriction (R = 4, or 2) of the active zones of a fine
+   2D cylindrical FP64 state onto a coarse one (fine nx, ny = R coarse nx, ny;
    every coarse face a fine face): density = mass / volume of the coarse
-   zone; v_x on a coarse X face = the radial-width-weighted mean of the 4 fine
-   X faces on it; v_y on a coarse Y face = the mean of the 4 fine Y faces on
+   zone; v_x on a coarse X face = the radial-width-weighted mean of the R fine
+   X faces on it; v_y on a coarse Y face = the mean of the R fine Y faces on
    it.  Ghost zones of the coarse state are not written. */
 int fargo_lfc_restrict(const fargo_ctx *fine, const fargo_state *fs, const fargo_ctx *coarse, fargo_state *cs,
                        void *stream);

@@ -1236,10 +1236,12 @@ int fargo_lfc_restrict(const fargo_ctx *fine, const fargo_state *fs, const fargo
   const Mesh &mf = fine->m, &mc = coarse->m;
   for (const fargo_ctx *c : {fine, coarse})
     if (c->p.geometry != FARGO_CYLINDRICAL || c->m.d3 || fp32(c)) return FARGO_EUNSUPPORTED;
-  if (mf.nx != 4 * mc.nx || mf.ny != 4 * mc.ny || fine->p.xmin != coarse->p.xmin || fine->p.xmax != coarse->p.xmax)
+  const int R = mc.nx > 0 ? mf.nx / mc.nx : 0; // 2 or 4
+  if ((R != 2 && R != 4) || mf.nx != R * mc.nx || mf.ny != R * mc.ny || fine->p.xmin != coarse->p.xmin ||
+      fine->p.xmax != coarse->p.xmax)
     return FARGO_EINVAL;
   for (int J = 0; J <= mc.ny; J++) {
-    const double yc = coarse->ymin[NGH + J], yf = fine->ymin[NGH + 4 * J];
+    const double yc = coarse->ymin[NGH + J], yf = fine->ymin[NGH + R * J];
     if (!(std::fabs(yc - yf) <= 1e-12 * std::fabs(yc))) return FARGO_EINVAL;
   }
   if (!fs->rho || !fs->vx || !fs->vy || !cs->rho || !cs->vx || !cs->vy) return FARGO_EINVAL;

@@ -412,12 +412,11 @@ __global__ __launch_bounds__(LB) void k_commit(Mesh m, double *__restrict__ rho,
   rho[c] = rho[c] + d[p];
 }
 
-__global__ __launch_bounds__(LB) void k_restrict(Mesh mf, Mesh mc, const double *__restrict__ rf,
+__global__ __launch_bounds__(LB) void k_restrict(Mesh mf, Mesh mc, int R, const double *__restrict__ rf,
                                                  const double *__restrict__ vxf, const double *__restrict__ vyf,
                                                  double *__restrict__ rc, double *__restrict__ vxc,
                                                  double *__restrict__ vyc) {
 #pragma clang fp contract(off)
-  constexpr int R = 4;
   const int p = blockIdx.x * LB + threadIdx.x;
   if (p >= mc.nx * mc.ny) return;
   const int J = p / mc.nx, I = p - J * mc.nx;
@@ -556,7 +555,7 @@ void lfc_target(Launch &L, const Mesh &m, const double *ref, const double *plain
 
 void lfc_restrict(Launch &L, const Mesh &mf, const double *rf, const double *vxf, const double *vyf, const Mesh &mc,
                   double *rc, double *vxc, double *vyc) {
-  k_restrict<<<nblk((long)mc.nx * mc.ny, LB), LB, 0, L.s>>>(mf, mc, rf, vxf, vyf, rc, vxc, vyc);
+  k_restrict<<<nblk((long)mc.nx * mc.ny, LB), LB, 0, L.s>>>(mf, mc, mf.nx / mc.nx, rf, vxf, vyf, rc, vxc, vyc);
 }
 
 } // namespace fargo

@@ -30,10 +30,15 @@ def _copy_state(dst: F.Solver, src: F.Solver):
 
 
 def make_samples(count: int, seed: int = 4000, coarse: Dict = None, fine: Dict = None,
-                 spinup: int = 0) -> Tuple[W.Problem, List[Dict[str, torch.Tensor]]]:
+                 spinup: int = 0, medium: bool = False) -> Tuple[W.Problem, List[Dict[str, torch.Tensor]]]:
     """`count` consecutive (coarse state after the plain step, target) pairs
     along one fine trajectory.  `coarse` and `fine` are keyword arguments of
-    the planet-disk generator (the defaults are 768 x 256 and 3072 x 1024)."""
+    the planet-disk generator (the defaults are 768 x 256 and 3072 x 1024).
+    With `medium`, the plain solver at twice the coarse resolution also
+    covers each interval from the fine state averaged 2 x 2 onto its mesh, and
+    its result averaged 2 x 2 onto the coarse mesh is kept ("medium_rho",
+    with its step count "medium_steps"): the plain solver's own answer at the
+    next resolution, for comparison with the corrected coarse step."""
     cp = W.make("lfc_coarse", seed=seed, **(coarse or {}))
     fp = W.make("lfc_fine", seed=seed, **(fine or {}))
     fs = F.Solver(fp.params)
@@ -41,12 +46,21 @@ def make_samples(count: int, seed: int = 4000, coarse: Dict = None, fine: Dict =
     cin, run, ref = (F.Solver(cp.params) for _ in range(3))
     for s in (cin, run, ref):
         s.upload(cp.fields)
+    ms = mc = None
+    if medium:
+        cpp = cp.params
+        mp = W.disk2d_planet(nx=2 * cpp["nx"], ny=2 * cpp["ny"], seed=seed)
+        ms, mc = F.Solver(mp.params), F.Solver(cp.params)
+        ms.upload(mp.fields)
+        mc.upload(cp.fields)
     for _ in range(spinup):
         fs.fargo_step(0.0)
     n = cp.params["nx"] * cp.params["ny"]
     out = []
     for _ in range(count):
         F.lfc_restrict(fs, cin)
+        if ms is not None:
+            F.lfc_restrict(fs, ms)
         dt = cin.fargo_cfl_dt()
         _copy_state(run, cin)
         run.fargo_step(dt)
@@ -57,11 +71,29 @@ def make_samples(count: int, seed: int = 4000, coarse: Dict = None, fine: Dict =
         F.lfc_restrict(fs, ref)
         t = torch.empty(n, dtype=torch.float64, device=run.device)
         F.lfc_target(ref, run, t)
-        out.append({"rho": run.state["rho"].clone(), "vx": run.state["vx"].clone(), "vy": run.state["vy"].clone(),
-                    "target": t, "dt": dt})
-    for s in (fs, cin, run, ref):
+        smp = {"rho": run.state["rho"].clone(), "vx": run.state["vx"].clone(), "vy": run.state["vy"].clone(),
+               "target": t, "dt": dt}
+        if ms is not None:
+            msub = max(1, math.ceil(dt / ms.fargo_cfl_dt() * (1.0 + 1e-12)))
+            for _ in range(msub):
+                ms.fargo_step(dt / msub)
+            F.lfc_restrict(ms, mc)
+            tm = torch.empty(n, dtype=torch.float64, device=run.device)
+            F.lfc_target(mc, run, tm)  # the medium run's density change relative to the plain coarse step
+            smp["medium_drho"] = tm
+            smp["medium_steps"] = msub
+        out.append(smp)
+    for s in [fs, cin, run, ref] + ([ms, mc] if ms is not None else []):
         s.fargo_check()
     return cp, out
+
+
+def medium_error(samples) -> Dict[str, float]:
+    """Relative error of the plain solver at twice the coarse resolution in
+    the metric of Trainer.evaluate: |drho_medium - target| / |target|."""
+    rel = [float(torch.linalg.vector_norm(s["medium_drho"] - s["target"]) / torch.linalg.vector_norm(s["target"]))
+           for s in samples]
+    return {"relative_error": float(np.mean(rel)), "min": float(np.min(rel)), "max": float(np.max(rel))}
 
 
 def init_params(seed: int) -> np.ndarray:
