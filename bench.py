@@ -355,12 +355,16 @@ def copy_bandwidth():
     return out
 
 
-def lfc_variant(iters=600):
+LFC_BATCH = 8  # training samples per Adam step
+
+
+def lfc_variant(iters=600, batch=LFC_BATCH):
     """The learned flux correction on the planet disks (coarse 768 x 256,
     fine 3072 x 1024): 40 samples along one fine trajectory (after 200 fine
-    spin-up steps), 32 for training and 8 held out.  Adam steps are timed with
-    per-kernel HIP events; the held-out error of the corrected coarse step
-    (|drho - target| / |target|, 1 = the plain step) before and after."""
+    spin-up steps), 32 for training and 8 held out, `batch` samples per Adam
+    step.  Adam steps are timed with per-kernel HIP events; the held-out error
+    of the corrected coarse step (|drho - target| / |target|, 1 = the plain
+    step) before and after."""
     import torch
     from paper_1602_02359_amd import learned as LN
     t0 = time.perf_counter()
@@ -368,7 +372,7 @@ def lfc_variant(iters=600):
     torch.cuda.synchronize()
     gen = time.perf_counter() - t0
     sc = LN.scales(cp, samples)
-    tr = LN.Trainer(cp, sc)
+    tr = LN.Trainer(cp, sc, batch=batch)
     train, held = samples[:32], samples[32:]
     before = tr.evaluate(held)
     tr.train(train, 20, 3e-3, every=20)
@@ -430,10 +434,12 @@ def lfc_variant(iters=600):
     print("  lfc equal error: corrected coarse %.3f at %.3f ms, plain 2x %.3f at %.3f ms per interval" % (
         after["relative_error"], t_coarse + apply_ms, med["relative_error"], msteps * t_medium),
         file=sys.stderr, flush=True)
-    # algorithmic flops of a training step (unpadded GEMM dimensions)
-    fl = {"lfc_conv_fwd": 2.0 * npix * (36 * 32 + 288 * 32 + 288 * 2),
-          "lfc_conv_bwd_w": 2.0 * npix * (36 * 32 + 288 * 32 + 288 * 2),
-          "lfc_conv_bwd_data": 2.0 * npix * (18 * 32 + 288 * 32)}
+    # algorithmic flops of each convolution of a training step over the
+    # batch (unpadded GEMM dimensions: outputs x reduction length x 2)
+    P = float(npix * batch)
+    fl = {"lfc_fwd_l1": 2.0 * P * 32 * 36, "lfc_fwd_l2": 2.0 * P * 32 * 288, "lfc_fwd_l3": 2.0 * P * 2 * 288,
+          "lfc_adj_l3": 2.0 * P * 32 * 18, "lfc_adj_l2": 2.0 * P * 32 * 288,
+          "lfc_wgrad_l3": 2.0 * P * 2 * 288, "lfc_wgrad_l2": 2.0 * P * 32 * 288, "lfc_wgrad_l1": 2.0 * P * 32 * 36}
     kern = {}
     for name, (cnt, tot) in tim.items():
         e = {"launches": cnt, "avg_ms": tot / cnt, "ms_per_train_step": tot / iters}
@@ -443,9 +449,11 @@ def lfc_variant(iters=600):
     dom = max((k for k in kern if "TFLOPs" in kern[k]), key=lambda k: kern[k]["ms_per_train_step"])
     out = {
         "workload": "learned flux correction, planet disk: coarse 768x256 (196608 zones), fine 3072x1024, "
-                    "3 conv layers 4-32-32-2, bf16 MFMA",
+                    "3 conv layers 4-32-32-2, bf16 MFMA, %d samples per training step" % batch,
+        "batch": batch,
         "ms_per_train_step": 1e3 * el / iters,
         "train_steps_per_s": iters / el,
+        "train_samples_per_s": iters * batch / el,
         "ms_per_apply": apply_ms,
         "sample_generation_s": gen,
         "heldout_relative_error": {"before": before["relative_error"], "after": after["relative_error"]},

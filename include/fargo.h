@@ -311,28 +311,34 @@ void fargo_batch_destroy(fargo_batch *batch);
    beyond the active radial rows.  Products run on the bfloat16 matrix cores
    (operands rounded to nearest even, FP32 accumulation); the FP32 master
    parameters are trained on the device with Adam (beta1 0.9, beta2 0.999,
-   eps 1e-8) on the loss mean(((drho - target)/sigma)^2).
-   Requirements: cylindrical, nz == 1, FARGO_FP64, nx a multiple of 64 and
-   nx*ny a multiple of 256 (FARGO_EUNSUPPORTED otherwise). */
+   eps 1e-8) on the loss mean(((drho - target)/sigma)^2), the mean taken over
+   every zone of every sample of a training batch (1 to max_batch states of
+   the context's mesh per Adam step).
+   Requirements: cylindrical, nz == 1, FARGO_FP64, nx a multiple of 64
+   (FARGO_EUNSUPPORTED otherwise). */
 typedef struct fargo_lfc fargo_lfc;
 typedef struct {
   double rho_s, u_s, r_mid, r_span; /* feature scales */
   double flux_scale;                /* dF = flux_scale x net output */
   double sigma;                     /* loss scale (> 0) */
   double guard;                     /* apply only if rho + drho > 0 and |drho| <= guard rho in every zone */
+  int32_t max_batch;                /* samples per batch the buffers hold, 1..32 (0 means 1) */
 } fargo_lfc_params;
 /* Parameter vector (FP32): W1 [32][3][3][4], b1 [32], W2 [32][3][3][32],
    b2 [32], W3 [2][3][3][32], b3 [2]; weights [out][ty][tx][in]. */
 #define FARGO_LFC_NPARAM 11010
-/* Device buffers of the last forward / training step, for inspection:
-   f [pixel][4], h1, h2 [pixel][32] (bfloat16 bits as uint16), o [pixel][2]
-   (float), drho [pixel] (double), g3 [pixel][4], g2, g1 [pixel][32]
-   (bfloat16 layer gradients); pixel = j nx + i over the active zones. */
+/* Device buffers of the last forward / training batch, for inspection:
+   f [sample][pixel][4], h1, h2 [sample][pixel][32] (bfloat16 bits as
+   uint16), o [sample][pixel][2] (float), drho [sample][pixel] (double), g3
+   [sample][pixel][4], g2, g1 [sample][pixel][32] (bfloat16 layer
+   gradients); pixel = j nx + i over the active zones, samples in the order
+   they were passed. */
 typedef struct {
   const void *f, *h1, *h2, *o, *drho, *g3, *g2, *g1;
 } fargo_lfc_views;
 /* Bind a net to `ctx` (which must outlive it); allocates its device
-   buffers.  Parameters start at zero: set them with fargo_lfc_set_params. */
+   buffers, for p->max_batch samples.  Parameters start at zero: set them
+   with fargo_lfc_set_params.  FARGO_EINVAL for max_batch outside 0..32. */
 int fargo_lfc_create(fargo_ctx *ctx, const fargo_lfc_params *p, fargo_lfc **out);
 /* Free the buffers (waits for the device).  NULL is a no-op. */
 void fargo_lfc_destroy(fargo_lfc *l);
@@ -344,10 +350,19 @@ int fargo_lfc_get_params(fargo_lfc *l, float *host, int32_t n);
 int fargo_lfc_get_grad(fargo_lfc *l, float *host, int32_t n);
 /* The net on `state` and the density change it implies (views.drho). */
 int fargo_lfc_forward(fargo_lfc *l, const fargo_state *state, void *stream);
+/* The same on n states (an array, 1 <= n <= max_batch, each of the context's
+   mesh; FARGO_EINVAL otherwise), sample s in slot s of every view. */
+int fargo_lfc_forward_batch(fargo_lfc *l, const fargo_state *states, int32_t n, void *stream);
 /* One Adam step with learning rate lr on the loss against `target` (device,
    double [ny][nx] over the active zones, the wanted density change). */
 int fargo_lfc_train_step(fargo_lfc *l, const fargo_state *state, const double *target, double lr,
                          void *stream);
+/* One Adam step on a batch: n states and n targets (host array of device
+   pointers, as for train_step), the loss the mean over all n samples.  Every
+   convolution of the forward and backward pass runs once over the whole
+   batch. */
+int fargo_lfc_train_batch(fargo_lfc *l, const fargo_state *states, const double *const *targets, int32_t n,
+                          double lr, void *stream);
 /* Forward, then the guarded update of state->rho: if the guard rejects the
    correction anywhere, the density is left as it is and the skip flag is
    set (read with fargo_lfc_result). */

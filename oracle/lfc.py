@@ -26,7 +26,9 @@ innermost ring; i is periodic):
             o[..., 1] on its lower Y face; the radial boundary faces carry no
             correction (dFy of row 0 and the face above the last row are 0);
   update    drho_ij = -(1/V_j) [dFx_{i+1,j} - dFx_ij + dFy_{i,j+1} - dFy_ij];
-  loss      L = mean(((drho - t)/sigma)^2) for a target change t;
+  loss      L = mean(((drho - t)/sigma)^2) for a target change t; for a
+            batch of samples of one mesh, the mean over every zone of every
+            sample (one Adam step per batch);
   guard     the corrected density is kept only if rho + drho > 0 and
             |drho| <= g rho in every zone; else the plain step stands.
 
@@ -198,14 +200,20 @@ def loss(d, t, sigma) -> float:
     return float(np.mean(((d - t) / sigma) ** 2))
 
 
-def backward(A, P, t, sF, invV, sigma, rounded=True):
+def loss_batch(ds, ts, sigma) -> float:
+    """The loss of a batch: the mean over every zone of every sample."""
+    return float(sum(np.sum(((d - t) / sigma) ** 2) for d, t in zip(ds, ts)) / sum(d.size for d in ds))
+
+
+def backward(A, P, t, sF, invV, sigma, rounded=True, count=None):
     """Gradients of the loss in every parameter, from the activations A of
     `forward`.  The layer gradients are rounded to bfloat16 before they enter
     a product, as on the GPU; each bias gradient is the sum of its rounded
-    layer gradient."""
+    layer gradient.  `count` is the number of zones the loss averages over
+    (this sample's, by default; all samples' of a batch)."""
     q = bf16 if rounded else (lambda a: np.asarray(a, dtype=np.float64))
     d = drho(A["o"], sF, invV)
-    N = d.size
+    N = d.size if count is None else count
     g = 2.0 * (d - t) / (N * sigma * sigma)          # dL/d(drho)
     gD = -invV[:, None] * g                           # dL/d(divergence)
     gFx = np.roll(gD, 1, axis=1) - gD                 # Fx_i enters D_{i-1} (+) and D_i (-)
@@ -222,6 +230,17 @@ def backward(A, P, t, sF, invV, sigma, rounded=True):
     g1 = q(np.where(A["h1"] > 0, np.float32(dh1) if rounded else dh1, 0.0))
     G["W1"] = conv_w(g1, A["f"])
     G["b1"] = g1.sum(axis=(0, 1))
+    return G
+
+
+def backward_batch(As, P, ts, sF, invV, sigma, rounded=True):
+    """Gradients of the batch loss: each sample's gradient with the loss
+    averaged over all zones of the batch, summed over the samples."""
+    count = sum(A["o"].shape[0] * A["o"].shape[1] for A in As)
+    G = None
+    for A, t in zip(As, ts):
+        g = backward(A, P, t, sF, invV, sigma, rounded=rounded, count=count)
+        G = g if G is None else {k: G[k] + g[k] for k in G}
     return G
 
 

@@ -20,8 +20,9 @@ namespace fargo {
 const char *kernel_names[K_COUNT] = {"set_dt", "bc_faces", "bc_ghosts", "cfl",    "dt_final", "split",
                                      "source", "source_ghosts", "visc", "sweep_y", "sweep_z",  "ring_x",
                                      "vel_yz", "shift",    "sums",      "sums_final", "zx_ring",
-                                     "lfc_features", "lfc_conv_fwd", "lfc_drho", "lfc_conv_bwd_w",
-                                     "lfc_conv_bwd_data", "lfc_reduce", "lfc_adam", "lfc_apply"};
+                                     "lfc_features", "lfc_fwd_l1", "lfc_fwd_l2", "lfc_fwd_l3", "lfc_drho",
+                                     "lfc_wgrad_l3", "lfc_adj_l3", "lfc_wgrad_l2", "lfc_adj_l2",
+                                     "lfc_wgrad_l1", "lfc_reduce", "lfc_adam", "lfc_apply"};
 
 struct Prof {
   bool on = false;
@@ -1047,6 +1048,7 @@ struct fargo_lfc {
   fargo_lfc_params p{};
   LfcScales sc{};
   LfcBufs B{};
+  int maxb = 1;        // samples the buffers hold
   int *flag = nullptr; // guard: 1 if the last apply was rejected
   void *mem = nullptr;
   int step = 0; // Adam steps since the parameters were set
@@ -1056,8 +1058,21 @@ namespace {
 
 bool lfc_mesh_ok(const fargo_ctx *c) {
   const Mesh &m = c->m;
-  return c->p.geometry == FARGO_CYLINDRICAL && !m.d3 && !fp32(c) && m.nx % 64 == 0 &&
-         ((long)m.nx * m.ny) % LFC_CHUNK == 0;
+  return c->p.geometry == FARGO_CYLINDRICAL && !m.d3 && !fp32(c) && m.nx % 64 == 0;
+}
+
+// the samples' density and velocities, checked against the context
+int lfc_feed(const fargo_lfc *l, const fargo_state *states, int32_t n, LfcFeed &in) {
+  if (!states || n < 1 || n > l->maxb) return FARGO_EINVAL;
+  in = LfcFeed{};
+  for (int s = 0; s < n; s++) {
+    const int rc = check_state(l->ctx, &states[s]);
+    if (rc) return rc;
+    in.rho[s] = (const double *)states[s].rho;
+    in.vx[s] = (const double *)states[s].vx;
+    in.vy[s] = (const double *)states[s].vy;
+  }
+  return FARGO_OK;
 }
 
 } // namespace
@@ -1069,10 +1084,13 @@ int fargo_lfc_create(fargo_ctx *ctx, const fargo_lfc_params *p, fargo_lfc **out)
   *out = nullptr;
   if (!lfc_mesh_ok(ctx)) return FARGO_EUNSUPPORTED;
   if (!(p->rho_s != 0.0) || !(p->u_s != 0.0) || !(p->r_span != 0.0) || !(p->sigma > 0.0) || !(p->guard > 0.0) ||
-      !std::isfinite(p->flux_scale))
+      !std::isfinite(p->flux_scale) || p->max_batch < 0 || p->max_batch > LFC_MAXB)
     return FARGO_EINVAL;
-  const long npix = (long)ctx->m.nx * ctx->m.ny, nchunk = npix / LFC_CHUNK;
-  const long nlb = (npix + 255) / 256;
+  const int maxb = p->max_batch > 0 ? p->max_batch : 1;
+  const long npix = (long)ctx->m.nx * ctx->m.ny, ntot = npix * maxb;
+  long nwb = 0; // weight-gradient blocks, the most any batch size up to maxb takes
+  for (int n = 1; n <= maxb; n++) nwb = std::max(nwb, (long)lfc_wblocks(ctx->m.nx, ctx->m.ny, n, nullptr, nullptr));
+  const long nlb = (ntot + 255) / 256;
   // one allocation, carved in 256-byte aligned slots
   size_t off = 0;
   auto slot = [&](size_t bytes) {
@@ -1080,13 +1098,13 @@ int fargo_lfc_create(fargo_ctx *ctx, const fargo_lfc_params *p, fargo_lfc **out)
     off += al(bytes);
     return o;
   };
-  const size_t o_f = slot(npix * 4 * 2), o_h1 = slot(npix * 32 * 2), o_h2 = slot(npix * 32 * 2),
-               o_o = slot(npix * 2 * 4), o_g3 = slot(npix * 4 * 2), o_g2 = slot(npix * 32 * 2),
-               o_g1 = slot(npix * 32 * 2), o_drho = slot(npix * 8), o_gD = slot(npix * 8), o_lp = slot(nlb * 8),
+  const size_t o_f = slot(ntot * 4 * 2), o_h1 = slot(ntot * 32 * 2), o_h2 = slot(ntot * 32 * 2),
+               o_o = slot(ntot * 2 * 4), o_g3 = slot(ntot * 4 * 2), o_g2 = slot(ntot * 32 * 2),
+               o_g1 = slot(ntot * 32 * 2), o_drho = slot(ntot * 8), o_gD = slot(ntot * 8), o_lp = slot(nlb * 8),
                o_loss = slot(8), o_flag = slot(4), o_w = slot(LFC_NPARAM * 4), o_mo = slot(LFC_NPARAM * 4),
-               o_ve = slot(LFC_NPARAM * 4), o_gr = slot(LFC_NPARAM * 4), o_part = slot(nchunk * 32 * 288 * 4),
-               o_dbp = slot(nchunk * 32 * 4), o_wb1 = slot(32 * 48 * 2), o_wb2 = slot(32 * 288 * 2),
-               o_wb3 = slot(16 * 288 * 2), o_wt2 = slot(32 * 288 * 2), o_wt3 = slot(32 * 48 * 2);
+               o_ve = slot(LFC_NPARAM * 4), o_gr = slot(LFC_NPARAM * 4), o_part = slot(nwb * 32 * 288 * 4),
+               o_dbp = slot(nwb * 32 * 4), o_wp1 = slot(2048 * 2), o_wp2 = slot(9216 * 2), o_wp3 = slot(4608 * 2),
+               o_wpa3 = slot(2048 * 2), o_wpa2 = slot(9216 * 2);
   fargo_lfc *l = new fargo_lfc;
   if (hipSetDevice(ctx->dev) != hipSuccess || hipMalloc(&l->mem, off) != hipSuccess) {
     delete l;
@@ -1116,13 +1134,14 @@ int fargo_lfc_create(fargo_ctx *ctx, const fargo_lfc_params *p, fargo_lfc **out)
   B.grad = (float *)(b + o_gr);
   B.part = (float *)(b + o_part);
   B.dbpart = (float *)(b + o_dbp);
-  B.wt.wb1 = (unsigned short *)(b + o_wb1);
-  B.wt.wb2 = (unsigned short *)(b + o_wb2);
-  B.wt.wb3 = (unsigned short *)(b + o_wb3);
-  B.wt.wt2 = (unsigned short *)(b + o_wt2);
-  B.wt.wt3 = (unsigned short *)(b + o_wt3);
+  B.wt.wp1 = (unsigned short *)(b + o_wp1);
+  B.wt.wp2 = (unsigned short *)(b + o_wp2);
+  B.wt.wp3 = (unsigned short *)(b + o_wp3);
+  B.wt.wpa3 = (unsigned short *)(b + o_wpa3);
+  B.wt.wpa2 = (unsigned short *)(b + o_wpa2);
   l->ctx = ctx;
   l->p = *p;
+  l->maxb = maxb;
   l->sc = LfcScales{p->rho_s, p->u_s, p->r_mid, p->r_span};
   *out = l;
   return FARGO_OK;
@@ -1160,31 +1179,47 @@ int fargo_lfc_get_grad(fargo_lfc *l, float *host, int32_t n) {
   return l ? lfc_copy_out(l->B.grad, host, n) : FARGO_EINVAL;
 }
 
-int fargo_lfc_forward(fargo_lfc *l, const fargo_state *state, void *stream) {
+int fargo_lfc_forward_batch(fargo_lfc *l, const fargo_state *states, int32_t n, void *stream) {
   if (!l) return FARGO_EINVAL;
-  int rc = check_state(l->ctx, state);
+  LfcFeed in;
+  int rc = lfc_feed(l, states, n, in);
   if (rc) return rc;
   Launch L{(hipStream_t)stream, &l->ctx->prof};
   const Mesh &m = l->ctx->m;
-  lfc_forward(L, m, (const double *)state->rho, (const double *)state->vx, (const double *)state->vy, l->sc, l->B);
-  lfc_drho(L, m, l->B, l->p.flux_scale, nullptr, l->p.sigma);
+  lfc_forward(L, m, in, n, l->sc, l->B);
+  lfc_drho(L, m, n, l->B, l->p.flux_scale, nullptr, l->p.sigma);
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
 
-int fargo_lfc_train_step(fargo_lfc *l, const fargo_state *state, const double *target, double lr, void *stream) {
-  if (!l || !target || !(lr > 0.0) || !std::isfinite(lr)) return FARGO_EINVAL;
-  int rc = check_state(l->ctx, state);
+int fargo_lfc_forward(fargo_lfc *l, const fargo_state *state, void *stream) {
+  return fargo_lfc_forward_batch(l, state, 1, stream);
+}
+
+int fargo_lfc_train_batch(fargo_lfc *l, const fargo_state *states, const double *const *targets, int32_t n,
+                          double lr, void *stream) {
+  if (!l || !targets || !(lr > 0.0) || !std::isfinite(lr)) return FARGO_EINVAL;
+  LfcFeed in;
+  int rc = lfc_feed(l, states, n, in);
   if (rc) return rc;
+  LfcTargets tg{};
+  for (int s = 0; s < n; s++) {
+    if (!targets[s]) return FARGO_EINVAL;
+    tg.t[s] = targets[s];
+  }
   Launch L{(hipStream_t)stream, &l->ctx->prof};
   const Mesh &m = l->ctx->m;
-  lfc_forward(L, m, (const double *)state->rho, (const double *)state->vx, (const double *)state->vy, l->sc, l->B);
-  lfc_drho(L, m, l->B, l->p.flux_scale, target, l->p.sigma);
-  lfc_backward(L, m, l->B, l->p.flux_scale);
+  lfc_forward(L, m, in, n, l->sc, l->B);
+  lfc_drho(L, m, n, l->B, l->p.flux_scale, &tg, l->p.sigma);
+  lfc_backward(L, m, n, l->B, l->p.flux_scale);
   l->step++;
   const double c1 = 1.0 - std::pow(0.9, l->step), c2 = 1.0 - std::pow(0.999, l->step);
   lfc_adam(L, l->B, (float)lr, (float)c1, (float)c2);
   lfc_pack(L, l->B);
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
+int fargo_lfc_train_step(fargo_lfc *l, const fargo_state *state, const double *target, double lr, void *stream) {
+  return fargo_lfc_train_batch(l, state, &target, 1, lr, stream);
 }
 
 int fargo_lfc_apply(fargo_lfc *l, fargo_state *state, void *stream) {

@@ -247,7 +247,8 @@ enum KernelId {
   K_SET_DT = 0, K_BC_FACES, K_BC_GHOSTS, K_CFL, K_DT_FINAL, K_SPLIT, K_SRC, K_SRC_GHOSTS, K_VISC, K_SWEEP_Y,
   K_SWEEP_Z, K_RING_X, K_VEL, K_SHIFT, K_SUMS, K_SUMS_FINAL, K_ZX,
   // learned flux correction
-  K_LFC_FEATURES, K_LFC_CONV_FWD, K_LFC_DRHO, K_LFC_BWD_W, K_LFC_BWD_DATA, K_LFC_REDUCE, K_LFC_ADAM, K_LFC_APPLY,
+  K_LFC_FEATURES, K_LFC_FWD1, K_LFC_FWD2, K_LFC_FWD3, K_LFC_DRHO, K_LFC_W3, K_LFC_ADJ3, K_LFC_W2, K_LFC_ADJ2,
+  K_LFC_W1, K_LFC_REDUCE, K_LFC_ADAM, K_LFC_APPLY,
   K_COUNT
 };
 extern const char *kernel_names[K_COUNT];
@@ -337,25 +338,34 @@ constexpr int LFC_OFF_W1 = 0, LFC_OFF_B1 = 1152, LFC_OFF_W2 = 1184, LFC_OFF_B2 =
 struct LfcScales {
   double rho_s, u_s, r_mid, r_span;
 };
-// bfloat16 weight copies: forward [rows][K padded to 16], and the transposes
-// for the input gradients [ci][tap * Cg + co]
+// bfloat16 weight matrices of the five convolutions (forward L1-L3, adjoint
+// of L3 and of L2), packed as MFMA A operands (lane-major, 16 bytes a lane)
 struct LfcWeights {
-  unsigned short *wb1, *wb2, *wb3, *wt2, *wt3; // [32][48], [32][288], [16][288], [32][288], [32][48]
+  unsigned short *wp1, *wp2, *wp3, *wpa3, *wpa2; // 2048, 9216, 4608, 2048, 9216 elements
 };
 struct LfcBufs {
-  unsigned short *f, *h1, *h2;      // activations [pixel][4 | 32 | 32]
-  float *o;                         // net output [pixel][2]
-  unsigned short *g3, *g2, *g1;     // layer gradients [pixel][4 | 32 | 32]
+  unsigned short *f, *h1, *h2;      // activations [sample][pixel][4 | 32 | 32]
+  float *o;                         // net output [sample][pixel][2]
+  unsigned short *g3, *g2, *g1;     // layer gradients [sample][pixel][4 | 32 | 32]
   double *drho, *gD, *lpart, *loss; // density change, dL/d(divergence), loss partials, loss
   float *w, *mo, *ve, *grad;        // master parameters, Adam moments, gradient [LFC_NPARAM]
-  float *part, *dbpart;             // weight-gradient partials per pixel chunk
+  float *part, *dbpart;             // weight-gradient partials per block
   LfcWeights wt;
 };
-constexpr int LFC_CHUNK = 256; // pixels per weight-gradient partial
-void lfc_forward(Launch &L, const Mesh &m, const double *rho, const double *vx, const double *vy,
-                 const LfcScales &sc, const LfcBufs &B);
-void lfc_drho(Launch &L, const Mesh &m, const LfcBufs &B, double sF, const double *target, double sigma);
-void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF);
+// samples of one training or forward batch (at most LFC_MAXB), passed by value
+constexpr int LFC_MAXB = 32;
+struct LfcFeed {
+  const double *rho[LFC_MAXB], *vx[LFC_MAXB], *vy[LFC_MAXB];
+};
+struct LfcTargets {
+  const double *t[LFC_MAXB];
+};
+// blocks of the weight-gradient kernels for nsamp samples (rows per block
+// and row chunks per strip returned through rpc, nrc)
+int lfc_wblocks(int nx, int ny, int nsamp, int *rpc, int *nrc);
+void lfc_forward(Launch &L, const Mesh &m, const LfcFeed &in, int nsamp, const LfcScales &sc, const LfcBufs &B);
+void lfc_drho(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double sF, const LfcTargets *tg, double sigma);
+void lfc_backward(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double sF);
 void lfc_adam(Launch &L, const LfcBufs &B, float lr, float c1, float c2);
 void lfc_pack(Launch &L, const LfcBufs &B);
 void lfc_apply(Launch &L, const Mesh &m, const LfcBufs &B, double *rho, double guard, int *flag);

@@ -4,30 +4,34 @@
 // a conservative flux-divergence update of the density, so the mass change
 // telescopes to zero over the mesh (the conservation argument of Sect. 3.4
 // applied to the added fluxes).  The net is trained on device: forward pass,
-// loss, backward pass and Adam (Kingma & Ba 2015).
+// loss, backward pass and Adam (Kingma & Ba 2015), over a batch of samples
+// of one mesh per step.
 //
-// The convolutions are implicit GEMMs on the bfloat16 matrix cores
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation), one 16-row tile per wave:
-//   forward     out[p][co] = sum_k A[p][k] W[co][k],  k = tap Cin + ci,
-//               A[p][k] = act[p shifted by tap][ci]               (M = pixels)
+// The convolutions are implicit GEMMs on the bfloat16 matrix cores of gfx950
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation):
+//   forward     out[p][co] = sum_k W[co][k] A[k][p],  k = tap Cin + ci,
+//               A[k][p] = act[p shifted by tap][ci]       (M = Cout, N = pixels)
 //   input grad  the adjoint convolution, a forward one with the weights
-//               transposed and their taps flipped                  (M = pixels)
-//   weight grad dW[co][k] = sum_p g[p][co] A[p][k]                 (M = Cout,
-//               reduced over pixel chunks, partial sums per chunk)
-// Operand layouts of the 16x16x16 MFMA: lane l holds row (or column) l % 16
-// and the four k values 4 (l / 16) .. 4 (l / 16) + 3; the result tile gives
-// lane l column l % 16 and rows 4 (l / 16) .. 4 (l / 16) + 3.
+//               transposed and their taps flipped          (M = Cin, N = pixels)
+//   weight grad dW[co][k] = sum_p g[p][co] A[k][p]         (M = Cout, N = k,
+//               K = pixels; partial sums per block, reduced in a fixed order)
+// Operand layout of the 16 x 16 x 32 MFMA: lane l supplies row (A) or
+// column (B) l % 16 with eight k values, lane group l / 16 taking k = 8
+// (l / 16) .. 8 (l / 16) + 7 (any assignment of k to the lane groups works,
+// as long as A and B agree on it); the result gives lane l column l % 16 and
+// rows 4 (l / 16) .. 4 (l / 16) + 3.
 //
-// Activations are channels-last bfloat16, [pixel][channel] with pixel =
-// j nx + i over the active zones (j = 0 the innermost ring), zero beyond the
-// radial rows and periodic in i; weights [co][tap][ci], tap = 3 ty + tx.
+// Activations are channels-last bfloat16, [sample][pixel][channel] with
+// pixel = j nx + i over the active zones (j = 0 the innermost ring), zero
+// beyond the radial rows of each sample and periodic in i; weights
+// [co][tap][ci], tap = 3 ty + tx.
 #include "fargo_internal.h"
 
 namespace fargo {
 
 namespace {
 
-typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int LB = 256; // threads per block of the elementwise kernels
@@ -39,110 +43,140 @@ __device__ inline unsigned short to_bf16(float x) {
   return (unsigned short)(u >> 16);
 }
 __device__ inline float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ inline float lo_bf16(unsigned v) { return __uint_as_float(v << 16); }
+__device__ inline float hi_bf16(unsigned v) { return __uint_as_float(v & 0xFFFF0000u); }
+__device__ inline unsigned pack2(float a, float b) { return (unsigned)to_bf16(a) | ((unsigned)to_bf16(b) << 16); }
 
-// four consecutive bfloat16 (8-byte aligned) as an MFMA operand
-__device__ inline bf4 ld4(const unsigned short *p) {
-  const uint2 v = *reinterpret_cast<const uint2 *>(p);
-  bf4 r;
-  r[0] = (short)(v.x & 0xFFFFu);
-  r[1] = (short)(v.x >> 16);
-  r[2] = (short)(v.y & 0xFFFFu);
-  r[3] = (short)(v.y >> 16);
-  return r;
-}
-__device__ inline bf4 zero4() {
-  bf4 r;
-  r[0] = r[1] = r[2] = r[3] = 0;
-  return r;
+__device__ inline f4 mfma(uint4 a, uint4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
-// features (FP64 arithmetic, rounded to FP32 then to bfloat16)
+// features (FP64 arithmetic, rounded to FP32 then to bfloat16), all samples
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(LB) void k_features(Mesh m, const double *__restrict__ rho,
-                                                 const double *__restrict__ vx, const double *__restrict__ vy,
-                                                 LfcScales sc, unsigned short *__restrict__ f) {
+__global__ __launch_bounds__(LB) void k_features(Mesh m, LfcFeed in, int nsamp, LfcScales sc,
+                                                 unsigned short *__restrict__ f) {
 #pragma clang fp contract(off)
   const int npix = m.nx * m.ny;
-  const int p = blockIdx.x * LB + threadIdx.x;
-  if (p >= npix) return;
+  const long P = (long)blockIdx.x * LB + threadIdx.x;
+  if (P >= (long)npix * nsamp) return;
+  const int s = (int)(P / npix), p = (int)(P - (long)s * npix);
   const int j = p / m.nx, i = p - j * m.nx;
   const unsigned c = m.o32(i, j + m.j0, 0);
-  const double f0 = rho[c] / sc.rho_s - 1.0;
-  const double f1 = vy[c] / sc.u_s;
-  const double f2 = vx[c] / sc.u_s;
+  const double f0 = in.rho[s][c] / sc.rho_s - 1.0;
+  const double f1 = in.vy[s][c] / sc.u_s;
+  const double f2 = in.vx[s][c] / sc.u_s;
   const double f3 = (m.g.ymed(j + m.j0) - sc.r_mid) / sc.r_span;
   uint2 v;
   v.x = (unsigned)to_bf16((float)f0) | ((unsigned)to_bf16((float)f1) << 16);
   v.y = (unsigned)to_bf16((float)f2) | ((unsigned)to_bf16((float)f3) << 16);
-  *reinterpret_cast<uint2 *>(f + (size_t)p * 4) = v;
+  *reinterpret_cast<uint2 *>(f + (size_t)P * 4) = v;
 }
 
 // ---------------------------------------------------------------------------
-// 3 x 3 convolution through LDS.  A block takes 64 pixels of one row (a wave
-// per 16 of them) and stages the three input rows they read, 66 columns wide
-// (periodic in i, zero rows outside the mesh), so that each input value is
-// read from memory once per block rather than once per tap; the MFMA A
-// operands then come from LDS.  Wb is [16 NT][KP] bfloat16, KP = 9 CIN
-// rounded up to 16.  Modes: CV_HID, out = bf16(relu(conv + b)); CV_OUT,
-// out = conv + b (FP32); CV_ADJ, the adjoint convolution (weights transposed
-// and their taps flipped), out = bf16([h > 0] conv).
+// 3 x 3 convolution.  A block of four waves takes 64 pixels of CV_RY rows of
+// one sample and stages the rows they read, plus one above and below and one
+// column on either side (periodic in i, zero rows outside the sample), in
+// LDS once; wave w then computes columns 16 w .. 16 w + 15 of every row.
+// The weights are the MFMA A operand and stay in registers for the whole
+// block (packed per lane by k_pack); the activations are the B operand, one
+// 16-byte LDS read per lane per k step.  Modes: CV_HID, out = bf16(relu(conv
+// + b)); CV_OUT, out = conv + b (FP32, two channels); CV_ADJ, the adjoint
+// convolution, out = bf16([h > 0] conv).
 // ---------------------------------------------------------------------------
 enum { CV_HID = 0, CV_OUT = 1, CV_ADJ = 2 };
+constexpr int CV_RY = 8;
 
 template <int CIN, int COUT, int MODE>
 __global__ __launch_bounds__(256) void k_conv(int nx, int ny, const unsigned short *__restrict__ act,
-                                              const unsigned short *__restrict__ Wb,
-                                              const float *__restrict__ bias, const unsigned short *__restrict__ h,
-                                              unsigned short *__restrict__ hout, float *__restrict__ fout) {
-  constexpr int K = 9 * CIN, KP = (K + 15) / 16 * 16, NT = (COUT + 15) / 16;
-  constexpr int CP = CIN + 4, TW = 66, CH = CIN / 4; // padded pixel stride; staged columns
-  __shared__ __align__(16) unsigned short T[3][TW][CP];
-  const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, kq = lane >> 4, wv = tid >> 6;
-  const int pb = blockIdx.x * 64; // first pixel of the block: a row segment, since nx % 64 == 0
-  const int y = pb / nx, x0 = pb - y * nx;
-  for (int e = tid; e < 3 * TW * CH; e += 256) {
-    const int c4 = e % CH, col = (e / CH) % TW, ry = e / (CH * TW);
-    const int yy = y + ry - 1;
-    int xx = x0 + col - 1;
-    xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-    uint2 v = make_uint2(0u, 0u);
-    if (yy >= 0 && yy < ny) v = *reinterpret_cast<const uint2 *>(act + ((size_t)yy * nx + xx) * CIN + 4 * c4);
-    *reinterpret_cast<uint2 *>(&T[ry][col][4 * c4]) = v;
+                                              const uint4 *__restrict__ Wp, const float *__restrict__ bias,
+                                              const unsigned short *__restrict__ h, unsigned short *__restrict__ hout,
+                                              float *__restrict__ fout) {
+  constexpr int MT = (COUT + 15) / 16, KS = (9 * CIN + 31) / 32;
+  constexpr int CP = CIN == 32 ? 40 : 4; // staged pixel stride (elements): 16-byte aligned, banks spread
+  constexpr int TW = 66, NR = CV_RY + 2;
+  __shared__ __align__(16) unsigned short T[NR][TW][CP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ln = lane & 15, q = lane >> 4;
+  const int strips = nx / 64, rt = (ny + CV_RY - 1) / CV_RY;
+  const int strip = blockIdx.x % strips, rtile = (blockIdx.x / strips) % rt, s = blockIdx.x / (strips * rt);
+  const int x0 = strip * 64, y0 = rtile * CV_RY;
+  const size_t sb = (size_t)s * nx * ny; // first pixel of the sample
+  uint4 w[MT][KS];
+#pragma unroll
+  for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) w[mt][ks] = Wp[(mt * KS + ks) * 64 + lane];
+  if (CIN == 32) {
+    constexpr int NE = NR * TW * 4; // 16-byte chunks: 4 per pixel
+#pragma unroll 4
+    for (int e = tid; e < NE; e += 256) {
+      const int c8 = e & 3, col = (e >> 2) % TW, r = (e >> 2) / TW;
+      const int yy = y0 + r - 1;
+      int xx = x0 + col - 1;
+      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (yy >= 0 && yy < ny) v = *reinterpret_cast<const uint4 *>(act + (sb + (size_t)yy * nx + xx) * 32 + 8 * c8);
+      *reinterpret_cast<uint4 *>(&T[r][col][8 * c8]) = v;
+    }
+  } else {
+    constexpr int NE = NR * TW;
+    for (int e = tid; e < NE; e += 256) {
+      const int col = e % TW, r = e / TW;
+      const int yy = y0 + r - 1;
+      int xx = x0 + col - 1;
+      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+      uint2 v = make_uint2(0u, 0u);
+      if (yy >= 0 && yy < ny) v = *reinterpret_cast<const uint2 *>(act + (sb + (size_t)yy * nx + xx) * 4);
+      *reinterpret_cast<uint2 *>(&T[r][col][0]) = v;
+    }
   }
   __syncthreads();
-  const int xl = wv * 16 + m; // the lane's A row, as a staged column offset
-  f4 acc[NT];
+  const int xl = wv * 16 + ln; // the lane's pixel (B column) within the 64
+  const int nrow = min(CV_RY, ny - y0);
+  for (int r = 0; r < nrow; r += 2) {
+    f4 acc[2][MT];
 #pragma unroll
-  for (int t = 0; t < NT; t++) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-  for (int s = 0; s < KP / 16; s++) {
-    const int k0 = 16 * s + 4 * kq;
-    bf4 a = zero4();
-    if (k0 < K) {
-      const int tap = k0 / CIN, ci = k0 - tap * CIN;
-      a = ld4(&T[tap / 3][xl + tap % 3][ci]);
+    for (int rr = 0; rr < 2; rr++)
+#pragma unroll
+      for (int mt = 0; mt < MT; mt++) acc[rr][mt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+#pragma unroll
+      for (int rr = 0; rr < 2; rr++) {
+        uint4 b;
+        if (CIN == 32) { // k step = tap, lane group = 8 channels
+          b = *reinterpret_cast<const uint4 *>(&T[r + rr + ks / 3][xl + ks % 3][8 * q]);
+        } else { // k step = 8 taps of 4 channels, lane group = 2 taps
+          const int ta = 8 * ks + 2 * q, tb = ta + 1;
+          uint2 lo = make_uint2(0u, 0u), hi = make_uint2(0u, 0u);
+          if (ta < 9) lo = *reinterpret_cast<const uint2 *>(&T[r + rr + ta / 3][xl + ta % 3][0]);
+          if (tb < 9) hi = *reinterpret_cast<const uint2 *>(&T[r + rr + tb / 3][xl + tb % 3][0]);
+          b = make_uint4(lo.x, lo.y, hi.x, hi.y);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++) acc[rr][mt] = mfma(w[mt][ks], b, acc[rr][mt]);
+      }
     }
 #pragma unroll
-    for (int t = 0; t < NT; t++) {
-      const bf4 b = ld4(Wb + (size_t)(16 * t + m) * KP + k0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
-    }
-  }
+    for (int rr = 0; rr < 2; rr++) {
+      if (r + rr >= nrow) break;
+      const size_t p = sb + (size_t)(y0 + r + rr) * nx + x0 + xl;
 #pragma unroll
-  for (int t = 0; t < NT; t++) {
-    const int co = 16 * t + m;
-    if (co >= COUT) continue;
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-      const size_t idx = (size_t)(pb + wv * 16 + 4 * kq + v) * COUT + co;
-      if (MODE == CV_HID) {
-        const float val = acc[t][v] + bias[co];
-        hout[idx] = to_bf16(val > 0.f ? val : 0.f);
-      } else if (MODE == CV_OUT) {
-        fout[idx] = acc[t][v] + bias[co];
-      } else {
-        hout[idx] = to_bf16(from_bf16(h[idx]) > 0.f ? acc[t][v] : 0.f);
+      for (int mt = 0; mt < MT; mt++) {
+        const int co = 16 * mt + 4 * q;
+        const f4 a = acc[rr][mt];
+        if (MODE == CV_HID) {
+          const float v0 = fmaxf(a[0] + bias[co], 0.f), v1 = fmaxf(a[1] + bias[co + 1], 0.f);
+          const float v2 = fmaxf(a[2] + bias[co + 2], 0.f), v3 = fmaxf(a[3] + bias[co + 3], 0.f);
+          *reinterpret_cast<uint2 *>(hout + p * COUT + co) = make_uint2(pack2(v0, v1), pack2(v2, v3));
+        } else if (MODE == CV_OUT) {
+          if (q == 0) *reinterpret_cast<float2 *>(fout + p * 2) = make_float2(a[0] + bias[0], a[1] + bias[1]);
+        } else {
+          const uint2 hv = *reinterpret_cast<const uint2 *>(h + p * COUT + co);
+          const float v0 = lo_bf16(hv.x) > 0.f ? a[0] : 0.f, v1 = hi_bf16(hv.x) > 0.f ? a[1] : 0.f;
+          const float v2 = lo_bf16(hv.y) > 0.f ? a[2] : 0.f, v3 = hi_bf16(hv.y) > 0.f ? a[3] : 0.f;
+          *reinterpret_cast<uint2 *>(hout + p * COUT + co) = make_uint2(pack2(v0, v1), pack2(v2, v3));
+        }
       }
     }
   }
@@ -162,166 +196,285 @@ __device__ inline double block_sum(double v, double *lds) {
   return s; // in thread 0
 }
 
-__global__ __launch_bounds__(LB) void k_drho(Mesh m, const float *__restrict__ o, double sF,
-                                             const double *__restrict__ target, double sigma,
+__global__ __launch_bounds__(LB) void k_drho(Mesh m, int nsamp, const float *__restrict__ o, double sF,
+                                             LfcTargets tg, int with_target, double sigma,
                                              double *__restrict__ drho, double *__restrict__ gD,
                                              double *__restrict__ lpart) {
 #pragma clang fp contract(off)
   __shared__ double red[LB / 64];
   const int nx = m.nx, ny = m.ny, npix = nx * ny;
-  const int p = blockIdx.x * LB + threadIdx.x;
+  const long ntot = (long)npix * nsamp;
+  const long P = (long)blockIdx.x * LB + threadIdx.x;
   double e2 = 0.0;
-  if (p < npix) {
+  if (P < ntot) {
+    const int s = (int)(P / npix), p = (int)(P - (long)s * npix);
     const int j = p / nx, i = p - j * nx;
-    const int pr = j * nx + (i + 1 == nx ? 0 : i + 1), pu = p + nx;
-    const double fx0 = sF * (double)o[2 * p], fx1 = sF * (double)o[2 * pr];
-    const double fy0 = j == 0 ? 0.0 : sF * (double)o[2 * p + 1];
+    const long b = (long)s * npix;
+    const long pr = b + j * nx + (i + 1 == nx ? 0 : i + 1), pu = P + nx;
+    const double fx0 = sF * (double)o[2 * P], fx1 = sF * (double)o[2 * pr];
+    const double fy0 = j == 0 ? 0.0 : sF * (double)o[2 * P + 1];
     const double fy1 = j + 1 == ny ? 0.0 : sF * (double)o[2 * pu + 1];
     const double div = (fx1 - fx0) + (fy1 - fy0);
     const double iv = m.g.invVj(j + m.j0);
     const double d = (-iv) * div;
-    drho[p] = d;
-    if (target) {
-      const double t = target[p];
+    drho[P] = d;
+    if (with_target) {
+      const double t = tg.t[s][p];
       const double e = (d - t) / sigma;
       e2 = e * e;
-      const double g = 2.0 * (d - t) / ((double)npix * sigma * sigma);
-      gD[p] = (-iv) * g;
+      const double g = 2.0 * (d - t) / ((double)ntot * sigma * sigma);
+      gD[P] = (-iv) * g;
     }
   }
-  if (!target) return;
+  if (!with_target) return;
   const double s = block_sum(e2, red);
   if (threadIdx.x == 0) lpart[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void k_loss_final(const double *__restrict__ lpart, int n, int npix,
+__global__ __launch_bounds__(256) void k_loss_final(const double *__restrict__ lpart, int n, long ntot,
                                                     double *__restrict__ loss) {
   __shared__ double red[4];
   double s = 0.0;
   for (int q = threadIdx.x; q < n; q += blockDim.x) s += lpart[q];
   s = block_sum(s, red);
-  if (threadIdx.x == 0) *loss = s / (double)npix;
+  if (threadIdx.x == 0) *loss = s / (double)ntot;
 }
 
 // dL/d(net output) through the adjoint of the divergence; 4 channels (the
 // last two zero) so that the input-gradient GEMM takes them in groups of 4
-__global__ __launch_bounds__(LB) void k_flux_grad(int nx, int ny, const double *__restrict__ gD, double sF,
+__global__ __launch_bounds__(LB) void k_flux_grad(int nx, int ny, int nsamp, const double *__restrict__ gD, double sF,
                                                   unsigned short *__restrict__ g3) {
 #pragma clang fp contract(off)
-  const int p = blockIdx.x * LB + threadIdx.x;
-  if (p >= nx * ny) return;
+  const int npix = nx * ny;
+  const long P = (long)blockIdx.x * LB + threadIdx.x;
+  if (P >= (long)npix * nsamp) return;
+  const int s = (int)(P / npix), p = (int)(P - (long)s * npix);
   const int j = p / nx, i = p - j * nx;
-  const double gx = gD[j * nx + (i == 0 ? nx - 1 : i - 1)] - gD[p];
-  const double gy = j == 0 ? 0.0 : gD[p - nx] - gD[p];
+  const long b = (long)s * npix;
+  const double gx = gD[b + j * nx + (i == 0 ? nx - 1 : i - 1)] - gD[P];
+  const double gy = j == 0 ? 0.0 : gD[P - nx] - gD[P];
   uint2 v;
   v.x = (unsigned)to_bf16((float)(sF * gx)) | ((unsigned)to_bf16((float)(sF * gy)) << 16);
   v.y = 0u;
-  *reinterpret_cast<uint2 *>(g3 + (size_t)p * 4) = v;
+  *reinterpret_cast<uint2 *>(g3 + (size_t)P * 4) = v;
 }
 
 // ---------------------------------------------------------------------------
-// weight gradient through LDS: dW[co][tap CIN + ci] = sum_p g[p][co]
-// act[p shifted by tap][ci] over a chunk of PC pixels (whole 64-pixel row
-// segments).  Per segment the block stages the three activation rows (as
-// the convolution does) and the layer gradient transposed to [co][pixel];
-// each wave then owns a share of the (co tile, k tile) pairs and accumulates
-// them over the chunk.  One partial sum per chunk, for the reduction below;
-// the bias gradient (the sum of g) alongside.
+// weight gradient: dW[co][tap CIN + ci] = sum_p g[p][co] act[p shifted by
+// tap][ci] over the pixels of a block: a 64-pixel column strip of one sample
+// over a run of rows.  K of the MFMA runs over pixels, so both operands are
+// staged transposed, [channel][pixel]: the layer gradient of the current row
+// (two buffers) and the activation rows above, at and below it (a ring of
+// four, the next row loaded while the current one is computed, one barrier a
+// row).  A lane's eight pixels are consecutive; the three taps along i read
+// the same 20 bytes and shift them by 0, 2 or 4 bytes.  Six waves: for 32
+// input channels wave w takes the row offset ty = w / 2 and 16 channels, all
+// three tx; for 4 it takes one 16-wide column tile of the 36 (tap, ci) pairs
+// and one 16-wide tile of output channels.  One partial sum per block, for
+// the reduction below, and the bias gradient (the sum of g) alongside.
 // ---------------------------------------------------------------------------
-constexpr int PC = LFC_CHUNK;
+constexpr int CW_THREADS = 384;
+
+// eight consecutive bfloat16 starting `sh` elements (0..2) after a 16-byte
+// aligned LDS address
+__device__ inline uint4 run8(const unsigned short *ap, int sh) {
+  const uint4 lo = *reinterpret_cast<const uint4 *>(ap);
+  const unsigned hi = *reinterpret_cast<const unsigned *>(ap + 8);
+  const bool two = sh == 2;
+  const unsigned b = (unsigned)(sh & 1) * 2u;
+  uint4 r;
+  r.x = __builtin_amdgcn_alignbyte(two ? lo.z : lo.y, two ? lo.y : lo.x, b);
+  r.y = __builtin_amdgcn_alignbyte(two ? lo.w : lo.z, two ? lo.z : lo.y, b);
+  r.z = __builtin_amdgcn_alignbyte(two ? hi : lo.w, two ? lo.w : lo.z, b);
+  r.w = __builtin_amdgcn_alignbyte(hi, two ? hi : lo.w, b);
+  return r;
+}
 
 template <int CIN, int COUT, int GC>
-__global__ __launch_bounds__(256) void k_conv_w(int nx, int ny, const unsigned short *__restrict__ g,
-                                                const unsigned short *__restrict__ act, float *__restrict__ part,
-                                                float *__restrict__ dbpart) {
-  constexpr int K = 9 * CIN, KP = (K + 15) / 16 * 16, NTW = KP / 16, MT = (COUT + 15) / 16;
-  constexpr int NTILE = MT * NTW, TPW = (NTILE + 3) / 4; // tiles, and tiles per wave
-  constexpr int CP = CIN + 4, TW = 66, CH = CIN / 4, GP = 64 + 4;
-  constexpr int DBC = 32, DBS = 256 / DBC; // bias sums: channel tid % DBC, pixel subset tid / DBC
-  __shared__ __align__(16) unsigned short T[3][TW][CP];
-  __shared__ __align__(16) unsigned short Gt[MT * 16][GP];
-  __shared__ float dbr[DBS][DBC];
-  const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, kq = lane >> 4, wv = tid >> 6;
-  const int chunk = blockIdx.x;
-  f4 acc[TPW];
-#pragma unroll
-  for (int t = 0; t < TPW; t++) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-  // the wave's tiles: the weight column of the lane in each
-  int tmt[TPW], tty[TPW], ttx[TPW], tci[TPW];
-  bool tok[TPW];
-#pragma unroll
-  for (int t = 0; t < TPW; t++) {
-    const int tile = t * 4 + wv, mt = tile / NTW, nt = tile - mt * NTW, kk = 16 * nt + m;
-    tok[t] = tile < NTILE && kk < K;
-    tmt[t] = tile < NTILE ? mt : 0;
-    const int tap = tok[t] ? kk / CIN : 0;
-    tci[t] = tok[t] ? kk - tap * CIN : 0;
-    tty[t] = tap / 3;
-    ttx[t] = tap % 3;
-  }
-  float db = 0.f;
-  for (int seg = 0; seg < PC / 64; seg++) {
-    const int pb = chunk * PC + seg * 64;
-    const int y = pb / nx, x0 = pb - y * nx;
-    __syncthreads(); // the previous segment's reads are done
-    for (int e = tid; e < 3 * TW * CH; e += 256) {
-      const int c4 = e % CH, col = (e / CH) % TW, ry = e / (CH * TW);
-      const int yy = y + ry - 1;
+__global__ __launch_bounds__(CW_THREADS) void k_conv_w(int nx, int ny, int rpc, int nrc,
+                                                       const unsigned short *__restrict__ g,
+                                                       const unsigned short *__restrict__ act,
+                                                       float *__restrict__ part, float *__restrict__ dbpart) {
+  constexpr int MT = (COUT + 15) / 16, K = 9 * CIN;
+  constexpr int AW = 72; // staged columns (66 used): 144-byte rows
+  constexpr int NA = CIN == 32 ? 3 : 1; // accumulator tiles per M tile
+  constexpr int GE = 64 * (GC / (GC == 32 ? 8 : 4)); // layer-gradient chunks of a row
+  constexpr int AE = 66 * (CIN == 32 ? 4 : 1);      // activation chunks of a row
+  __shared__ __align__(16) unsigned short At[4][CIN][AW];
+  __shared__ __align__(16) unsigned short Gt[2][16 * MT][AW];
+  __shared__ float dbr[64][COUT == 32 ? 33 : 2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ln = lane & 15, q = lane >> 4;
+  const int strips = nx / 64;
+  const int strip = blockIdx.x % strips, rc = (blockIdx.x / strips) % nrc, s = blockIdx.x / (strips * nrc);
+  const int x0 = strip * 64, ya = rc * rpc, yb = min(ny, ya + rpc);
+  const size_t sb = (size_t)s * nx * ny;
+  // rows of the output-channel tile beyond COUT stay zero
+  if (COUT < 16 * MT)
+    for (int e = tid; e < 2 * (16 * MT - COUT) * AW; e += CW_THREADS) {
+      const int b = e / ((16 * MT - COUT) * AW), r = e % ((16 * MT - COUT) * AW);
+      Gt[b][COUT + r / AW][r % AW] = 0;
+    }
+  // staging of one activation row / one layer-gradient row, through registers
+  auto load_a = [&](int yy, uint4 &v) {
+    v = make_uint4(0u, 0u, 0u, 0u);
+    if (tid < AE && yy >= 0 && yy < ny) {
+      const int col = CIN == 32 ? tid >> 2 : tid, c8 = CIN == 32 ? tid & 3 : 0;
       int xx = x0 + col - 1;
       xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-      uint2 v = make_uint2(0u, 0u);
-      if (yy >= 0 && yy < ny) v = *reinterpret_cast<const uint2 *>(act + ((size_t)yy * nx + xx) * CIN + 4 * c4);
-      *reinterpret_cast<uint2 *>(&T[ry][col][4 * c4]) = v;
-    }
-    for (int e = tid; e < MT * 16 * 64; e += 256) {
-      const int px = e & 63, co = e >> 6;
-      Gt[co][px] = co < COUT ? g[(size_t)(pb + px) * GC + co] : (unsigned short)0;
-    }
-    __syncthreads();
-    {
-      const int co = tid % DBC, sub = tid / DBC;
-      if (co < COUT)
-        for (int px = sub; px < 64; px += DBS) db += from_bf16(Gt[co][px]);
-    }
-#pragma unroll
-    for (int t = 0; t < TPW; t++) {
-      if (!tok[t] && (t * 4 + wv) >= NTILE) continue;
-#pragma unroll
-      for (int ks = 0; ks < 4; ks++) {
-        const int p4 = 16 * ks + 4 * kq; // the lane's four pixels of the segment
-        const bf4 a = ld4(&Gt[16 * tmt[t] + m][p4]);
-        bf4 b = zero4();
-        if (tok[t]) {
-#pragma unroll
-          for (int v = 0; v < 4; v++) b[v] = (short)T[tty[t]][p4 + v + ttx[t]][tci[t]];
-        }
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      const unsigned short *src = act + (sb + (size_t)yy * nx + xx) * CIN + 8 * c8;
+      if (CIN == 32) v = *reinterpret_cast<const uint4 *>(src);
+      else {
+        const uint2 t = *reinterpret_cast<const uint2 *>(src);
+        v.x = t.x;
+        v.y = t.y;
       }
     }
-  }
-  // result: lane holds column kk = 16 nt + m and rows co = 16 mt + 4 kq + v
+  };
+  auto store_a = [&](int slot, const uint4 &v) {
+    if (tid < AE) {
+      const int col = CIN == 32 ? tid >> 2 : tid, c0 = CIN == 32 ? 8 * (tid & 3) : 0;
+      const unsigned u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-  for (int t = 0; t < TPW; t++) {
-    if (!tok[t]) continue;
-    const int tile = t * 4 + wv, nt = tile - tmt[t] * NTW, kk = 16 * nt + m;
+      for (int i = 0; i < (CIN == 32 ? 8 : 4); i++)
+        At[slot][c0 + i][col] = (unsigned short)(i & 1 ? u[i >> 1] >> 16 : u[i >> 1] & 0xFFFFu);
+    }
+  };
+  auto load_g = [&](int yy, uint4 &v) {
+    v = make_uint4(0u, 0u, 0u, 0u);
+    if (tid < GE) {
+      const int px = GC == 32 ? tid >> 2 : tid, c8 = GC == 32 ? tid & 3 : 0;
+      const unsigned short *src = g + (sb + (size_t)yy * nx + x0 + px) * GC + 8 * c8;
+      if (GC == 32) v = *reinterpret_cast<const uint4 *>(src);
+      else {
+        const uint2 t = *reinterpret_cast<const uint2 *>(src);
+        v.x = t.x;
+        v.y = t.y;
+      }
+    }
+  };
+  float db[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) db[i] = 0.f;
+  auto store_g = [&](int slot, const uint4 &v) {
+    if (tid < GE) {
+      const int px = GC == 32 ? tid >> 2 : tid, c0 = GC == 32 ? 8 * (tid & 3) : 0;
+      const unsigned u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < (GC == 32 ? 8 : COUT); i++) {
+        const unsigned short hv = (unsigned short)(i & 1 ? u[i >> 1] >> 16 : u[i >> 1] & 0xFFFFu);
+        Gt[slot][c0 + i][px] = hv;
+        db[i] += from_bf16(hv);
+      }
+    }
+  };
+  f4 acc[NA][MT];
+#pragma unroll
+  for (int a = 0; a < NA; a++)
+#pragma unroll
+    for (int mt = 0; mt < MT; mt++) acc[a][mt] = f4{0.f, 0.f, 0.f, 0.f};
+  // the wave's operands: for CIN = 32, row offset ty and channel ci; for 4,
+  // the (tap, ci) pair of its column tile and its output-channel tile
+  int ty, ci, tx = 0, mt1 = 0;
+  bool kok = true;
+  if (CIN == 32) {
+    ty = wv >> 1;
+    ci = 16 * (wv & 1) + ln;
+  } else {
+    const int kk = 16 * (wv % 3) + ln, tap = kk >> 2;
+    kok = kk < K;
+    ty = kok ? tap / 3 : 0;
+    tx = kok ? tap % 3 : 0;
+    ci = kk & 3;
+    mt1 = wv / 3;
+  }
+  // prologue: rows ya - 1, ya, ya + 1 and the layer gradient of row ya
+  {
+    uint4 v0, v1, v2, gv;
+    load_a(ya - 1, v0);
+    load_a(ya, v1);
+    load_a(ya + 1, v2);
+    load_g(ya, gv);
+    store_a(0, v0);
+    store_a(1, v1);
+    store_a(2, v2);
+    store_g(0, gv);
+  }
+  __syncthreads();
+  for (int y = ya; y < yb; y++) {
+    const int d = y - ya;
+    const bool more = y + 1 < yb;
+    uint4 av, gv;
+    if (more) {
+      load_a(y + 2, av);
+      load_g(y + 1, gv);
+    }
+    const int arow = (d + ty) & 3, gs = d & 1;
+#pragma unroll
+    for (int ks = 0; ks < 2; ks++) {
+      const int c0 = 32 * ks + 8 * q;
+      if (CIN == 32) {
+        const uint4 lo = *reinterpret_cast<const uint4 *>(&At[arow][ci][c0]);
+        const unsigned hi = *reinterpret_cast<const unsigned *>(&At[arow][ci][c0 + 8]);
+        const uint4 b1 = make_uint4(__builtin_amdgcn_alignbyte(lo.y, lo.x, 2), __builtin_amdgcn_alignbyte(lo.z, lo.y, 2),
+                                    __builtin_amdgcn_alignbyte(lo.w, lo.z, 2), __builtin_amdgcn_alignbyte(hi, lo.w, 2));
+        const uint4 b2 = make_uint4(lo.y, lo.z, lo.w, hi);
+#pragma unroll
+        for (int mt = 0; mt < MT; mt++) {
+          const uint4 a = *reinterpret_cast<const uint4 *>(&Gt[gs][16 * mt + ln][c0]);
+          acc[0][mt] = mfma(a, lo, acc[0][mt]);
+          acc[1][mt] = mfma(a, b1, acc[1][mt]);
+          acc[2][mt] = mfma(a, b2, acc[2][mt]);
+        }
+      } else {
+        uint4 b = run8(&At[arow][ci][c0], tx);
+        if (!kok) b = make_uint4(0u, 0u, 0u, 0u);
+        const uint4 a = *reinterpret_cast<const uint4 *>(&Gt[gs][16 * mt1 + ln][c0]);
+        acc[0][0] = mfma(a, b, acc[0][0]);
+      }
+    }
+    if (more) {
+      store_a((d + 3) & 3, av);
+      store_g((d + 1) & 1, gv);
+    }
+    __syncthreads();
+  }
+  // results: lane holds column ln of its tiles and rows 4 q .. 4 q + 3
+  float *pw = part + (size_t)blockIdx.x * COUT * K;
+  if (CIN == 32) {
+#pragma unroll
+    for (int a = 0; a < NA; a++)
+#pragma unroll
+      for (int mt = 0; mt < MT; mt++)
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+          const int co = 16 * mt + 4 * q + v;
+          if (co < COUT) pw[co * K + (3 * ty + a) * 32 + ci] = acc[a][mt][v];
+        }
+  } else if (kok) {
+    const int kk = 16 * (wv % 3) + ln;
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      const int co = 16 * tmt[t] + 4 * kq + v;
-      if (co < COUT) part[((size_t)chunk * COUT + co) * K + kk] = acc[t][v];
+      const int co = 16 * mt1 + 4 * q + v;
+      if (co < COUT) pw[co * K + kk] = acc[0][0][v];
     }
   }
-  dbr[tid / DBC][tid % DBC] = db;
+  // bias gradient: each staging thread summed fixed channels of one pixel
+  if (tid < GE) {
+    const int px = GC == 32 ? tid >> 2 : tid, c0 = GC == 32 ? 8 * (tid & 3) : 0;
+#pragma unroll
+    for (int i = 0; i < (GC == 32 ? 8 : COUT); i++) dbr[px][c0 + i] = db[i];
+  }
   __syncthreads();
   if (tid < COUT) {
-    float d = 0.f;
-    for (int q = 0; q < DBS; q++) d += dbr[q][tid];
-    dbpart[(size_t)chunk * COUT + tid] = d;
+    float t = 0.f;
+    for (int px = 0; px < 64; px++) t += dbr[px][tid];
+    dbpart[(size_t)blockIdx.x * COUT + tid] = t;
   }
 }
 
-// grad[W] = sum over chunks of the partials, grad[b] likewise.  A block takes
+// grad[W] = sum over blocks of the partials, grad[b] likewise.  A block takes
 // RE consecutive entries; its RG thread groups sum interleaved subsets of the
-// chunks, and the group sums are added in a fixed order (deterministic).
+// partials, and the group sums are added in a fixed order (deterministic).
 constexpr int RE = 64, RG = 16;
 __global__ __launch_bounds__(RE * RG) void k_reduce_w(int nchunk, int cout, int K, const float *__restrict__ part,
                                                       const float *__restrict__ dbpart, float *__restrict__ gW,
@@ -363,28 +516,41 @@ __global__ __launch_bounds__(LB) void k_adam(int n, float *__restrict__ w, float
   w[e] = w[e] - lr * (mn / c1) / (sqrtf(vn / c2) + eps);
 }
 
-// Wb_l [16 NT][KP] for the forward GEMMs; Wt2 [32][288] and Wt3 [32][48]
-// (tap-major over the 4-padded output channels) for the input gradients
+// bfloat16 weight matrices of the five convolutions, packed as MFMA A
+// operands: entry ((mt KS + ks) 64 + lane) 8 + e holds row 16 mt + lane % 16,
+// k = 32 ks + 8 (lane / 16) + e (zero beyond K).  Rows and k of each matrix:
+//   L1  [co][tap 4 + ci]        L2, L3  [co][tap 32 + ci]
+//   A3  [ci][tap' 4 + cg]       A2      [ci][tap' 32 + cg]
+// with the adjoint's taps flipped, tap' = 8 - tap, and cg = 2, 3 zero in A3.
+__device__ inline float lfc_wm(const float *w, int which, int row, int k) {
+  const float *W1 = w + LFC_OFF_W1, *W2 = w + LFC_OFF_W2, *W3 = w + LFC_OFF_W3;
+  switch (which) {
+  case 0: return k < 36 ? W1[row * 36 + k] : 0.f;
+  case 1: return W2[row * 288 + k];
+  case 2: return row < 2 ? W3[row * 288 + k] : 0.f;
+  case 3: {
+    if (k >= 36) return 0.f;
+    const int tap = k >> 2, cg = k & 3;
+    return cg < 2 ? W3[cg * 288 + (8 - tap) * 32 + row] : 0.f;
+  }
+  default: {
+    const int tap = k >> 5, cg = k & 31;
+    return W2[cg * 288 + (8 - tap) * 32 + row];
+  }
+  }
+}
+
 __global__ __launch_bounds__(LB) void k_pack(const float *__restrict__ w, LfcWeights b) {
   const int e = blockIdx.x * LB + threadIdx.x;
-  const float *W1 = w + LFC_OFF_W1, *W2 = w + LFC_OFF_W2, *W3 = w + LFC_OFF_W3;
-  // forward copies
-  if (e < 32 * 48) {
-    const int co = e / 48, k = e - co * 48;
-    b.wb1[e] = k < 36 ? to_bf16(W1[co * 36 + k]) : (unsigned short)0;
-  }
-  if (e < 32 * 288) {
-    b.wb2[e] = to_bf16(W2[e]);
-    const int ci = e / 288, k = e - ci * 288, tap = k / 32, co = k - tap * 32;
-    b.wt2[e] = to_bf16(W2[co * 288 + (8 - tap) * 32 + ci]); // taps flipped: the adjoint as a convolution
-  }
-  if (e < 16 * 288) {
-    const int co = e / 288, k = e - co * 288;
-    b.wb3[e] = co < 2 ? to_bf16(W3[co * 288 + k]) : (unsigned short)0;
-  }
-  if (e < 32 * 48) {
-    const int ci = e / 48, k = e - ci * 48, tap = k / 4, co = k - tap * 4;
-    b.wt3[e] = (k < 36 && co < 2) ? to_bf16(W3[co * 288 + (8 - tap) * 32 + ci]) : (unsigned short)0;
+  const int mts[5] = {2, 2, 1, 2, 2}, kss[5] = {2, 9, 9, 2, 9}, ks36[5] = {36, 288, 288, 36, 288};
+  unsigned short *dst[5] = {b.wp1, b.wp2, b.wp3, b.wpa3, b.wpa2};
+#pragma unroll
+  for (int c = 0; c < 5; c++) {
+    const int n = mts[c] * kss[c] * 512;
+    if (e >= n) continue;
+    const int el = e & 7, lane = (e >> 3) & 63, blk = e >> 9, ks = blk % kss[c], mt = blk / kss[c];
+    const int row = 16 * mt + (lane & 15), k = 32 * ks + 8 * (lane >> 4) + el;
+    dst[c][e] = k < ks36[c] ? to_bf16(lfc_wm(w, c, row, k)) : (unsigned short)0;
   }
 }
 
@@ -452,73 +618,94 @@ __global__ __launch_bounds__(LB) void k_target(Mesh m, const double *__restrict_
 
 inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-} // namespace
-
-void lfc_forward(Launch &L, const Mesh &m, const double *rho, const double *vx, const double *vy,
-                 const LfcScales &sc, const LfcBufs &B) {
-  const int npix = m.nx * m.ny;
-  prof_begin(L, K_LFC_FEATURES);
-  k_features<<<nblk(npix, LB), LB, 0, L.s>>>(m, rho, vx, vy, sc, B.f);
-  prof_end(L, K_LFC_FEATURES);
-  const unsigned nb = (unsigned)(npix / 64);
-  prof_begin(L, K_LFC_CONV_FWD);
-  k_conv<4, 32, CV_HID><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.f, B.wt.wb1, B.w + LFC_OFF_B1, nullptr, B.h1, nullptr);
-  prof_end(L, K_LFC_CONV_FWD);
-  prof_begin(L, K_LFC_CONV_FWD);
-  k_conv<32, 32, CV_HID><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h1, B.wt.wb2, B.w + LFC_OFF_B2, nullptr, B.h2, nullptr);
-  prof_end(L, K_LFC_CONV_FWD);
-  prof_begin(L, K_LFC_CONV_FWD);
-  k_conv<32, 2, CV_OUT><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h2, B.wt.wb3, B.w + LFC_OFF_B3, nullptr, nullptr, B.o);
-  prof_end(L, K_LFC_CONV_FWD);
+inline unsigned conv_blocks(const Mesh &m, int nsamp) {
+  return (unsigned)(nsamp * (m.nx / 64) * ((m.ny + CV_RY - 1) / CV_RY));
 }
 
-void lfc_drho(Launch &L, const Mesh &m, const LfcBufs &B, double sF, const double *target, double sigma) {
-  const int npix = m.nx * m.ny;
-  const unsigned nb = nblk(npix, LB);
+} // namespace
+
+// Blocks of the weight-gradient kernels: nsamp x (nx / 64) strips, each split
+// into row chunks of rpc rows so that there are about 512 blocks in all.
+int lfc_wblocks(int nx, int ny, int nsamp, int *rpc, int *nrc) {
+  const int strips = nsamp * (nx / 64);
+  int want = (512 + strips - 1) / strips;
+  want = want < 1 ? 1 : (want > ny ? ny : want);
+  const int r = (ny + want - 1) / want;
+  if (rpc) *rpc = r;
+  if (nrc) *nrc = (ny + r - 1) / r;
+  return strips * ((ny + r - 1) / r);
+}
+
+void lfc_forward(Launch &L, const Mesh &m, const LfcFeed &in, int nsamp, const LfcScales &sc, const LfcBufs &B) {
+  const long ntot = (long)m.nx * m.ny * nsamp;
+  prof_begin(L, K_LFC_FEATURES);
+  k_features<<<nblk(ntot, LB), LB, 0, L.s>>>(m, in, nsamp, sc, B.f);
+  prof_end(L, K_LFC_FEATURES);
+  const unsigned nb = conv_blocks(m, nsamp);
+  const uint4 *wp1 = (const uint4 *)B.wt.wp1, *wp2 = (const uint4 *)B.wt.wp2, *wp3 = (const uint4 *)B.wt.wp3;
+  prof_begin(L, K_LFC_FWD1);
+  k_conv<4, 32, CV_HID><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.f, wp1, B.w + LFC_OFF_B1, nullptr, B.h1, nullptr);
+  prof_end(L, K_LFC_FWD1);
+  prof_begin(L, K_LFC_FWD2);
+  k_conv<32, 32, CV_HID><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h1, wp2, B.w + LFC_OFF_B2, nullptr, B.h2, nullptr);
+  prof_end(L, K_LFC_FWD2);
+  prof_begin(L, K_LFC_FWD3);
+  k_conv<32, 2, CV_OUT><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h2, wp3, B.w + LFC_OFF_B3, nullptr, nullptr, B.o);
+  prof_end(L, K_LFC_FWD3);
+}
+
+void lfc_drho(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double sF, const LfcTargets *tg,
+              double sigma) {
+  const long ntot = (long)m.nx * m.ny * nsamp;
+  const unsigned nb = nblk(ntot, LB);
+  LfcTargets none{};
   prof_begin(L, K_LFC_DRHO);
-  k_drho<<<nb, LB, 0, L.s>>>(m, B.o, sF, target, sigma, B.drho, B.gD, B.lpart);
+  k_drho<<<nb, LB, 0, L.s>>>(m, nsamp, B.o, sF, tg ? *tg : none, tg ? 1 : 0, sigma, B.drho, B.gD, B.lpart);
   prof_end(L, K_LFC_DRHO);
-  if (target) {
+  if (tg) {
     prof_begin(L, K_LFC_DRHO);
-    k_loss_final<<<1, 256, 0, L.s>>>(B.lpart, (int)nb, npix, B.loss);
+    k_loss_final<<<1, 256, 0, L.s>>>(B.lpart, (int)nb, ntot, B.loss);
     prof_end(L, K_LFC_DRHO);
   }
 }
 
-void lfc_backward(Launch &L, const Mesh &m, const LfcBufs &B, double sF) {
-  const int nx = m.nx, ny = m.ny, npix = nx * ny, nchunk = npix / PC;
-  const unsigned nb = (unsigned)(npix / 64);
+void lfc_backward(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double sF) {
+  const int nx = m.nx, ny = m.ny;
+  const long ntot = (long)nx * ny * nsamp;
+  const unsigned nb = conv_blocks(m, nsamp);
+  int rpc = 1, nrc = 1;
+  const int nw = lfc_wblocks(nx, ny, nsamp, &rpc, &nrc);
   prof_begin(L, K_LFC_DRHO);
-  k_flux_grad<<<nblk(npix, LB), LB, 0, L.s>>>(nx, ny, B.gD, sF, B.g3);
+  k_flux_grad<<<nblk(ntot, LB), LB, 0, L.s>>>(nx, ny, nsamp, B.gD, sF, B.g3);
   prof_end(L, K_LFC_DRHO);
   // layer 3: weights from g3 and h2, then the gradient into h2
-  prof_begin(L, K_LFC_BWD_W);
-  k_conv_w<32, 2, 4><<<nchunk, 256, 0, L.s>>>(nx, ny, B.g3, B.h2, B.part, B.dbpart);
-  prof_end(L, K_LFC_BWD_W);
+  prof_begin(L, K_LFC_W3);
+  k_conv_w<32, 2, 4><<<nw, CW_THREADS, 0, L.s>>>(nx, ny, rpc, nrc, B.g3, B.h2, B.part, B.dbpart);
+  prof_end(L, K_LFC_W3);
   prof_begin(L, K_LFC_REDUCE);
-  k_reduce_w<<<nblk(2 * 288 + 2, RE), RE * RG, 0, L.s>>>(nchunk, 2, 288, B.part, B.dbpart, B.grad + LFC_OFF_W3,
+  k_reduce_w<<<nblk(2 * 288 + 2, RE), RE * RG, 0, L.s>>>(nw, 2, 288, B.part, B.dbpart, B.grad + LFC_OFF_W3,
                                                      B.grad + LFC_OFF_B3);
   prof_end(L, K_LFC_REDUCE);
-  prof_begin(L, K_LFC_BWD_DATA);
-  k_conv<4, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g3, B.wt.wt3, nullptr, B.h2, B.g2, nullptr);
-  prof_end(L, K_LFC_BWD_DATA);
+  prof_begin(L, K_LFC_ADJ3);
+  k_conv<4, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g3, (const uint4 *)B.wt.wpa3, nullptr, B.h2, B.g2, nullptr);
+  prof_end(L, K_LFC_ADJ3);
   // layer 2
-  prof_begin(L, K_LFC_BWD_W);
-  k_conv_w<32, 32, 32><<<nchunk, 256, 0, L.s>>>(nx, ny, B.g2, B.h1, B.part, B.dbpart);
-  prof_end(L, K_LFC_BWD_W);
+  prof_begin(L, K_LFC_W2);
+  k_conv_w<32, 32, 32><<<nw, CW_THREADS, 0, L.s>>>(nx, ny, rpc, nrc, B.g2, B.h1, B.part, B.dbpart);
+  prof_end(L, K_LFC_W2);
   prof_begin(L, K_LFC_REDUCE);
-  k_reduce_w<<<nblk(32 * 288 + 32, RE), RE * RG, 0, L.s>>>(nchunk, 32, 288, B.part, B.dbpart, B.grad + LFC_OFF_W2,
+  k_reduce_w<<<nblk(32 * 288 + 32, RE), RE * RG, 0, L.s>>>(nw, 32, 288, B.part, B.dbpart, B.grad + LFC_OFF_W2,
                                                        B.grad + LFC_OFF_B2);
   prof_end(L, K_LFC_REDUCE);
-  prof_begin(L, K_LFC_BWD_DATA);
-  k_conv<32, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g2, B.wt.wt2, nullptr, B.h1, B.g1, nullptr);
-  prof_end(L, K_LFC_BWD_DATA);
+  prof_begin(L, K_LFC_ADJ2);
+  k_conv<32, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g2, (const uint4 *)B.wt.wpa2, nullptr, B.h1, B.g1, nullptr);
+  prof_end(L, K_LFC_ADJ2);
   // layer 1 (no gradient into the features)
-  prof_begin(L, K_LFC_BWD_W);
-  k_conv_w<4, 32, 32><<<nchunk, 256, 0, L.s>>>(nx, ny, B.g1, B.f, B.part, B.dbpart);
-  prof_end(L, K_LFC_BWD_W);
+  prof_begin(L, K_LFC_W1);
+  k_conv_w<4, 32, 32><<<nw, CW_THREADS, 0, L.s>>>(nx, ny, rpc, nrc, B.g1, B.f, B.part, B.dbpart);
+  prof_end(L, K_LFC_W1);
   prof_begin(L, K_LFC_REDUCE);
-  k_reduce_w<<<nblk(32 * 36 + 32, RE), RE * RG, 0, L.s>>>(nchunk, 32, 36, B.part, B.dbpart, B.grad + LFC_OFF_W1,
+  k_reduce_w<<<nblk(32 * 36 + 32, RE), RE * RG, 0, L.s>>>(nw, 32, 36, B.part, B.dbpart, B.grad + LFC_OFF_W1,
                                                       B.grad + LFC_OFF_B1);
   prof_end(L, K_LFC_REDUCE);
 }
@@ -532,7 +719,7 @@ void lfc_adam(Launch &L, const LfcBufs &B, float lr, float c1, float c2) {
 
 void lfc_pack(Launch &L, const LfcBufs &B) {
   prof_begin(L, K_LFC_ADAM);
-  k_pack<<<nblk(32 * 288, LB), LB, 0, L.s>>>(B.w, B.wt);
+  k_pack<<<nblk(2 * 9 * 512, LB), LB, 0, L.s>>>(B.w, B.wt);
   prof_end(L, K_LFC_ADAM);
 }
 

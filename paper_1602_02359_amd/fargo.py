@@ -84,7 +84,8 @@ _lib.fargo_batch_destroy.restype = None
 
 
 class fargo_lfc_params(C.Structure):
-    _fields_ = [(n, C.c_double) for n in ("rho_s", "u_s", "r_mid", "r_span", "flux_scale", "sigma", "guard")]
+    _fields_ = [(n, C.c_double) for n in ("rho_s", "u_s", "r_mid", "r_span", "flux_scale", "sigma", "guard")] + \
+        [("max_batch", C.c_int32)]
 
 
 class fargo_lfc_views(C.Structure):
@@ -99,6 +100,9 @@ for _n in ("fargo_lfc_set_params", "fargo_lfc_get_params", "fargo_lfc_get_grad")
     getattr(_lib, _n).argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int32]
 _lib.fargo_lfc_forward.argtypes = [C.c_void_p, _S, C.c_void_p]
 _lib.fargo_lfc_train_step.argtypes = [C.c_void_p, _S, C.c_void_p, C.c_double, C.c_void_p]
+_lib.fargo_lfc_forward_batch.argtypes = [C.c_void_p, _S, C.c_int32, C.c_void_p]
+_lib.fargo_lfc_train_batch.argtypes = [C.c_void_p, _S, C.POINTER(C.c_void_p), C.c_int32, C.c_double, C.c_void_p]
+LFC_MAXB = 32
 _lib.fargo_lfc_apply.argtypes = [C.c_void_p, _S, C.c_void_p]
 _lib.fargo_lfc_result.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p]
 _lib.fargo_lfc_get_views.argtypes = [C.c_void_p, C.POINTER(fargo_lfc_views)]
@@ -110,7 +114,8 @@ EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_worksp
             "fargo_conserved_sums", "fargo_conserved_sums_noalloc", "fargo_hbm_copy", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
             "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_destroy",
             "fargo_lfc_create", "fargo_lfc_destroy", "fargo_lfc_set_params", "fargo_lfc_get_params",
-            "fargo_lfc_get_grad", "fargo_lfc_forward", "fargo_lfc_train_step", "fargo_lfc_apply",
+            "fargo_lfc_get_grad", "fargo_lfc_forward", "fargo_lfc_forward_batch", "fargo_lfc_train_step",
+            "fargo_lfc_train_batch", "fargo_lfc_apply",
             "fargo_lfc_result", "fargo_lfc_get_views", "fargo_lfc_restrict", "fargo_lfc_target")
 
 
@@ -354,12 +359,15 @@ class Batch:
 
 class LFC:
     """A learned flux correction bound to a 2D cylindrical FP64 Solver
-    (fargo_lfc_*).  The solver must outlive it."""
+    (fargo_lfc_*).  The solver must outlive it.  Batches (up to max_batch
+    samples) are lists of dicts holding "rho", "vx", "vy" tensors laid out as
+    the solver's own state (and "target" for training)."""
 
     def __init__(self, solver: Solver, rho_s: float, u_s: float, r_mid: float, r_span: float,
-                 flux_scale: float, sigma: float, guard: float = 0.5):
+                 flux_scale: float, sigma: float, guard: float = 0.5, max_batch: int = 1):
         self.solver = solver
-        self._p = fargo_lfc_params(rho_s, u_s, r_mid, r_span, flux_scale, sigma, guard)
+        self.max_batch = int(max_batch)
+        self._p = fargo_lfc_params(rho_s, u_s, r_mid, r_span, flux_scale, sigma, guard, self.max_batch)
         self._l = C.c_void_p()
         _check(_lib.fargo_lfc_create(solver._ctx, C.byref(self._p), C.byref(self._l)), "fargo_lfc_create")
         self.nx, self.ny = solver.params["nx"], solver.params["ny"]
@@ -393,6 +401,30 @@ class LFC:
         _check(_lib.fargo_lfc_train_step(self._l, C.byref(self.solver._st), C.c_void_p(target.data_ptr()),
                                          float(lr), _stream(stream)), "fargo_lfc_train_step")
 
+    def _states(self, samples):
+        arr = (fargo_state * len(samples))()
+        for i, smp in enumerate(samples):
+            st = arr[i]
+            for f in FIELDS:
+                setattr(st, f, getattr(self.solver._st, f))
+            for k in ("rho", "vx", "vy"):
+                t, ref = smp[k], self.solver.state[k]
+                assert t.dtype == ref.dtype and t.shape == ref.shape and t.device == ref.device and t.is_contiguous()
+                setattr(st, k, C.c_void_p(t.data_ptr()))
+        return arr
+
+    def forward_batch(self, samples, stream=None):
+        _check(_lib.fargo_lfc_forward_batch(self._l, self._states(samples), len(samples), _stream(stream)),
+               "fargo_lfc_forward_batch")
+
+    def train_batch(self, samples, lr: float, stream=None):
+        for smp in samples:
+            t = smp["target"]
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == self.nx * self.ny
+        tg = (C.c_void_p * len(samples))(*[smp["target"].data_ptr() for smp in samples])
+        _check(_lib.fargo_lfc_train_batch(self._l, self._states(samples), tg, len(samples), float(lr),
+                                          _stream(stream)), "fargo_lfc_train_batch")
+
     def apply(self, stream=None):
         _check(_lib.fargo_lfc_apply(self._l, C.byref(self.solver._st), _stream(stream)), "fargo_lfc_apply")
 
@@ -401,12 +433,14 @@ class LFC:
         _check(_lib.fargo_lfc_result(self._l, C.byref(loss), C.byref(skipped), _stream(stream)), "fargo_lfc_result")
         return loss.value, bool(skipped.value)
 
-    def views(self) -> Dict[str, torch.Tensor]:
+    def views(self, nsamp: int = 0) -> Dict[str, torch.Tensor]:
         """Device buffers of the last forward or training step as tensors
-        (bfloat16 buffers as torch.bfloat16), shaped (ny, nx, channels)."""
+        (bfloat16 buffers as torch.bfloat16), shaped (ny, nx, channels), or
+        (nsamp, ny, nx, channels) for the first nsamp samples of a batch."""
         v = fargo_lfc_views()
         _check(_lib.fargo_lfc_get_views(self._l, C.byref(v)), "fargo_lfc_get_views")
-        n = self.nx * self.ny
+        ns = max(1, nsamp)
+        n = self.nx * self.ny * ns
         dev = self.solver.device
 
         def wrap(ptr, count, dtype):
@@ -421,7 +455,8 @@ class LFC:
                              ("o", 2, torch.float32), ("drho", 1, torch.float64), ("g3", 4, torch.bfloat16),
                              ("g2", 32, torch.bfloat16), ("g1", 32, torch.bfloat16)):
             t = wrap(getattr(v, name), n * ch, dt)
-            out[name] = t.view(self.ny, self.nx, ch) if ch > 1 else t.view(self.ny, self.nx)
+            shape = ((nsamp,) if nsamp else ()) + (self.ny, self.nx) + ((ch,) if ch > 1 else ())
+            out[name] = t.view(*shape)
         return out
 
 

@@ -128,11 +128,12 @@ def scales(cp: W.Problem, samples) -> Dict[str, float]:
 class Trainer:
     """A net bound to a coarse solver whose state is loaded from samples."""
 
-    def __init__(self, cp: W.Problem, sc: Dict[str, float], seed: int = 7, guard: float = 0.5):
+    def __init__(self, cp: W.Problem, sc: Dict[str, float], seed: int = 7, guard: float = 0.5, batch: int = 1):
         self.feed = F.Solver(cp.params)
         self.feed.upload(cp.fields)
+        self.batch = int(batch)
         self.net = F.LFC(self.feed, sc["rho_s"], sc["u_s"], sc["r_mid"], sc["r_span"], sc["flux_scale"],
-                         sc["sigma"], guard)
+                         sc["sigma"], guard, max_batch=self.batch)
         self.net.set_params(init_params(seed))
 
     def load(self, s):
@@ -140,12 +141,18 @@ class Trainer:
             self.feed.state[k].copy_(s[k])
 
     def train(self, samples, iters: int, lr: float, seed: int = 0, every: int = 50) -> List[float]:
+        """iters Adam steps, each on the next `batch` samples of a fixed
+        random permutation of `samples` (cyclically)."""
         order = np.random.default_rng(seed).permutation(len(samples))
         losses = []
+        b = self.batch
         for it in range(iters):
-            s = samples[order[it % len(samples)]]
-            self.load(s)
-            self.net.train_step(s["target"], lr)
+            if b == 1:
+                s = samples[order[it % len(samples)]]
+                self.load(s)
+                self.net.train_step(s["target"], lr)
+            else:
+                self.net.train_batch([samples[order[(it * b + k) % len(samples)]] for k in range(b)], lr)
             if it % every == 0 or it == iters - 1:
                 losses.append(self.net.result()[0])
         return losses

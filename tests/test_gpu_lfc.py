@@ -95,38 +95,63 @@ def _forward_layers(v, P):
     return flips
 
 
-def _backward_layers(v, P, grad, t, sF, invV, sigma):
-    """The backward pass from the GPU's own values: g3 from the GPU's density
-    change, g2 and g1 from the GPU's g3 and g2 (masked by the GPU's h2, h1),
-    each weight and bias gradient from the GPU's layer gradient and
-    activation.  Returns the flip counts."""
+def _wdepth(nx, ny, nsamp):
+    """Longest chain of FP32 additions behind a weight or bias gradient: the
+    library's weight-gradient blocks (a 64-pixel strip of one sample over rpc
+    rows, about 512 blocks in all; the block layout of lfc_wblocks) each
+    accumulate rpc x 64 pixels (an MFMA adds 32 products per k step of 32
+    pixels, two k steps a row), the bias sums rpc values per thread and 64 in
+    the block, then the partials of the nw blocks are summed."""
+    strips = nsamp * (nx // 64)
+    want = min(max(-(-512 // strips), 1), ny)
+    rpc = -(-ny // want)
+    nw = strips * (-(-ny // rpc))
+    return rpc * 64 + nw + 64
+
+
+def _np(v, name):
+    t = v[name]
+    return t.double().cpu().numpy() if name in ("o", "drho") else t.float().cpu().numpy().astype(np.float64)
+
+
+def _backward_layers(vs, P, grad, ts, sF, invV, sigma, depth):
+    """The backward pass of a batch from the GPU's own values: for each
+    sample (views vs[s], target ts[s]) g3 from the GPU's density change (the
+    loss the mean over all zones of the batch), g2 and g1 from the GPU's g3
+    and g2 (masked by the GPU's h2, h1); each weight and bias gradient, summed
+    over the samples, from the GPU's layer gradients and activations.
+    Returns the flip counts."""
     Wb = _bw(P)
-    f = v["f"].float().cpu().numpy().astype(np.float64)
-    h1 = v["h1"].float().cpu().numpy().astype(np.float64)
-    h2 = v["h2"].float().cpu().numpy().astype(np.float64)
-    g3 = v["g3"].float().cpu().numpy().astype(np.float64)[..., :2]
-    g2 = v["g2"].float().cpu().numpy().astype(np.float64)
-    g1 = v["g1"].float().cpu().numpy().astype(np.float64)
-    d = v["drho"].cpu().numpy()
-    ny, nx = d.shape
-    # g3 = bf16(fp32(dL/dF)) from the density change: FP64 on both sides
-    gg = 2.0 * (d - t) / (d.size * sigma * sigma)
-    gD = -invV[:, None] * gg
-    gFx = np.roll(gD, 1, axis=1) - gD
-    gFy = np.zeros_like(gD)
-    gFy[1:] = gD[:-1] - gD[1:]
-    g3ref = np.stack([sF * gFx, sF * gFy], axis=-1)
-    flips = {"g3": _check_rounded("g3", g3, g3ref, 1e-15 * np.abs(g3ref))}
-    flips["g2"] = _check_rounded("g2", g2, L.conv_t(g3, Wb["W3"]),
-                                 L.sum_bound(9 * 2 + 1, L.conv_t(np.abs(g3), np.abs(Wb["W3"]))), mask=h2 > 0)
-    flips["g1"] = _check_rounded("g1", g1, L.conv_t(g2, Wb["W2"]),
-                                 L.sum_bound(9 * 32 + 1, L.conv_t(np.abs(g2), np.abs(Wb["W2"]))), mask=h1 > 0)
-    # weight and bias gradients: FP32 sums over chunks of pixels, then over chunks
-    depth = 256 + (nx * ny) // 256 + 64
+    N = sum(t.size for t in ts)
+    flips = {"g3": 0, "g2": 0, "g1": 0}
+    ref, bnd = {}, {}
+
+    def acc(k, r, d):
+        ref[k] = ref.get(k, 0.0) + r
+        bnd[k] = bnd.get(k, 0.0) + d
+
+    for v, t in zip(vs, ts):
+        f, h1, h2 = _np(v, "f"), _np(v, "h1"), _np(v, "h2")
+        g3, g2, g1 = _np(v, "g3")[..., :2], _np(v, "g2"), _np(v, "g1")
+        d = _np(v, "drho")
+        # g3 = bf16(fp32(dL/dF)) from the density change: FP64 on both sides
+        gg = 2.0 * (d - t) / (N * sigma * sigma)
+        gD = -invV[:, None] * gg
+        gFx = np.roll(gD, 1, axis=1) - gD
+        gFy = np.zeros_like(gD)
+        gFy[1:] = gD[:-1] - gD[1:]
+        g3ref = np.stack([sF * gFx, sF * gFy], axis=-1)
+        flips["g3"] += _check_rounded("g3", g3, g3ref, 1e-15 * np.abs(g3ref))
+        flips["g2"] += _check_rounded("g2", g2, L.conv_t(g3, Wb["W3"]),
+                                      L.sum_bound(9 * 2 + 1, L.conv_t(np.abs(g3), np.abs(Wb["W3"]))), mask=h2 > 0)
+        flips["g1"] += _check_rounded("g1", g1, L.conv_t(g2, Wb["W2"]),
+                                      L.sum_bound(9 * 32 + 1, L.conv_t(np.abs(g2), np.abs(Wb["W2"]))), mask=h1 > 0)
+        for n, g, x in ((3, g3, h2), (2, g2, h1), (1, g1, f)):
+            acc("W%d" % n, L.conv_w(g, x), L.conv_w(np.abs(g), np.abs(x)))
+            acc("b%d" % n, g.sum(axis=(0, 1)), np.abs(g).sum(axis=(0, 1)))
     G = _unflat(grad)
-    for n, g, x in ((3, g3, h2), (2, g2, h1), (1, g1, f)):
-        _check_sum("W%d" % n, G["W%d" % n], L.conv_w(g, x), L.sum_bound(depth, L.conv_w(np.abs(g), np.abs(x))))
-        _check_sum("b%d" % n, G["b%d" % n], g.sum(axis=(0, 1)), L.sum_bound(depth, np.abs(g).sum(axis=(0, 1))))
+    for k in ref:
+        _check_sum(k, G[k], ref[k], L.sum_bound(depth, bnd[k]))
     return flips
 
 
@@ -161,7 +186,7 @@ def _geometry(p):
     return rc, invV
 
 
-def _setup(nx=64, ny=16, seed=11, sF=None, guard=0.5):
+def _setup(nx=64, ny=16, seed=11, sF=None, guard=0.5, max_batch=1):
     import torch
     from paper_1602_02359_amd import fargo as F
     prob = W.disk2d_planet(nx=nx, ny=ny, seed=4000 + seed, noise=0.05)
@@ -175,7 +200,7 @@ def _setup(nx=64, ny=16, seed=11, sF=None, guard=0.5):
     scales = (1.0, 0.05, 1.45, 1.05)
     sF = sF if sF is not None else 1e-4 / float(invV.mean())
     sigma = 1e-3
-    net = F.LFC(s, *scales, flux_scale=sF, sigma=sigma, guard=guard)
+    net = F.LFC(s, *scales, flux_scale=sF, sigma=sigma, guard=guard, max_batch=max_batch)
     P = L.init_params(rng)
     for k in ("b1", "b2", "b3"):
         P[k] = (0.05 * rng.standard_normal(P[k].shape)).astype(np.float32)
@@ -184,7 +209,30 @@ def _setup(nx=64, ny=16, seed=11, sF=None, guard=0.5):
     fields = {k: prob.fields[k][act].copy() for k in ("rho", "vx", "vy")}
     target = 1e-3 * rng.standard_normal((ny, nx))
     return dict(s=s, net=net, P=P, rc=rc, invV=invV, scales=scales, sF=sF, sigma=sigma, fields=fields,
-                target=target, torch=torch, prob=prob)
+                target=target, torch=torch, prob=prob, nx=nx, ny=ny)
+
+
+def _samples(c, n, seed):
+    """n batch samples on the mesh of setup c: the setup's state with
+    different seeded perturbations of rho, v_x and v_y in the active zones,
+    laid out as the solver's state, and a target each."""
+    torch, s = c["torch"], c["s"]
+    nx, ny = c["nx"], c["ny"]
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        smp, fields = {}, {}
+        for name, amp in (("rho", 0.05), ("vx", 0.02), ("vy", 0.02)):
+            t = s.state[name].clone()
+            a = t[0, NG:NG + ny, :nx].cpu().numpy()
+            a = a * (1.0 + amp * rng.standard_normal(a.shape)) if name == "rho" else a + amp * rng.standard_normal(a.shape)
+            t[0, NG:NG + ny, :nx] = torch.from_numpy(a)
+            smp[name] = t
+            fields[name] = a
+        tg = 1e-3 * (k + 1) * rng.standard_normal((ny, nx))
+        smp["target"] = torch.from_numpy(np.ascontiguousarray(tg)).cuda()
+        out.append((smp, fields, tg))
+    return out
 
 
 def test_forward_matches_oracle():
@@ -225,7 +273,7 @@ def test_train_step_gradient_loss_and_adam():
     f = L.features(fx["rho"], fx["vx"], fx["vy"], c["rc"], c["scales"])
     Pd = {k: np.asarray(x, dtype=np.float64) for k, x in c["P"].items()}
     fwd = _forward_layers(v, c["P"])
-    bwd = _backward_layers(v, c["P"], grad, c["target"], c["sF"], c["invV"], c["sigma"])
+    bwd = _backward_layers([v], c["P"], grad, [c["target"]], c["sF"], c["invV"], c["sigma"], _wdepth(64, 16, 1))
     d_gpu = v["drho"].cpu().numpy()
     loss_ref = L.loss(d_gpu, c["target"], c["sigma"])
     A = L.forward(f, c["P"])
@@ -243,6 +291,71 @@ def test_train_step_gradient_loss_and_adam():
     Pg = _unflat(newp)
     for k in Pn:
         assert np.allclose(Pg[k], Pn[k], rtol=1e-5, atol=1e-3 * lr), k
+
+
+def test_forward_batch_equals_single_forwards():
+    """A batch of three states through the net in one set of launches gives,
+    sample by sample, bit for bit what the single-state forward gives."""
+    c = _setup(seed=16, max_batch=3)
+    net = c["net"]
+    smps = _samples(c, 3, 161)
+    _say("lfc forward batch of 3, 64 x 16")
+    net.forward_batch([x[0] for x in smps])
+    vb = net.views(3)
+    for k, (smp, _, _) in enumerate(smps):
+        net.forward_batch([smp])
+        v1 = net.views()
+        for name in ("f", "h1", "h2", "o", "drho"):
+            assert c["torch"].equal(vb[name][k], v1[name]), (k, name)
+
+
+@pytest.mark.parametrize("shape", [(64, 16, 3), (128, 13, 2)])
+def test_train_batch_matches_oracle(shape):
+    """One Adam step on a batch (three 64 x 16 samples; two 128 x 13, a
+    ragged row tile): every sample's features, layers and layer gradients
+    element by element, the summed weight and bias gradients within the FP32
+    sum bound, the batch loss and the Adam step."""
+    nx, ny, n = shape
+    c = _setup(nx=nx, ny=ny, seed=17, max_batch=4)
+    net, torch = c["net"], c["torch"]
+    smps = _samples(c, n, 171)
+    _say("lfc train batch of %d, %d x %d" % (n, nx, ny))
+    lr = 1e-3
+    net.train_batch([x[0] for x in smps], lr)
+    loss, _ = net.result()
+    vb = net.views(n)
+    grad, newp = net.get_grad(), net.get_params()
+    vs = [{k: vb[k][s] for k in vb} for s in range(n)]
+    flips = {}
+    for s, (_, fx, _) in enumerate(smps):
+        f = L.features(fx["rho"], fx["vx"], fx["vy"], c["rc"], c["scales"])
+        assert np.array_equal(_np(vs[s], "f"), f), s
+        for k, x in _forward_layers(vs[s], c["P"]).items():
+            flips[k] = flips.get(k, 0) + x
+        d_ref = L.drho(_np(vs[s], "o"), c["sF"], c["invV"])
+        assert np.abs(_np(vs[s], "drho") - d_ref).max() <= 1e-14 * np.abs(d_ref).max()
+    ts = [x[2] for x in smps]
+    bwd = _backward_layers(vs, c["P"], grad, ts, c["sF"], c["invV"], c["sigma"], _wdepth(nx, ny, n))
+    loss_ref = L.loss_batch([_np(v, "drho") for v in vs], ts, c["sigma"])
+    _say("  loss", loss, loss_ref, "flipped roundings", flips, bwd)
+    assert abs(loss - loss_ref) <= 1e-12 * loss_ref
+    Pd = {k: np.asarray(x, dtype=np.float64) for k, x in c["P"].items()}
+    Gg = _unflat(grad)
+    M0 = {k: np.zeros_like(x) for k, x in Pd.items()}
+    Pn, _, _ = L.adam(Pd, Gg, M0, dict(M0), 1, lr)
+    Pg = _unflat(newp)
+    for k in Pn:
+        assert np.allclose(Pg[k], Pn[k], rtol=1e-5, atol=1e-3 * lr), k
+
+
+def test_batch_size_is_checked():
+    c = _setup(seed=18, max_batch=2)
+    from paper_1602_02359_amd import fargo as F
+    smps = [x[0] for x in _samples(c, 3, 181)]
+    with pytest.raises(F.FargoError):
+        c["net"].forward_batch(smps)
+    with pytest.raises(F.FargoError):
+        c["net"].train_batch(smps, 1e-3)
 
 
 def test_training_reduces_the_loss():
@@ -358,7 +471,7 @@ def test_full_size_forward_and_gradient():
     f = L.features(fx["rho"], fx["vx"], fx["vy"], c["rc"], c["scales"])
     assert np.array_equal(v["f"].float().cpu().numpy().astype(np.float64), f)
     fwd = _forward_layers(v, c["P"])
-    bwd = _backward_layers(v, c["P"], grad, c["target"], c["sF"], c["invV"], c["sigma"])
+    bwd = _backward_layers([v], c["P"], grad, [c["target"]], c["sF"], c["invV"], c["sigma"], _wdepth(768, 256, 1))
     d_gpu = v["drho"].cpu().numpy()
     o_gpu = v["o"].double().cpu().numpy()
     d_ref = L.drho(o_gpu, c["sF"], c["invV"])

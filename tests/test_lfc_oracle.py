@@ -104,6 +104,38 @@ def test_backward_matches_finite_differences():
             assert abs(G[k][idx] - fd) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (k, idx, G[k][idx], fd)
 
 
+def test_batch_gradient_matches_finite_differences():
+    """A batch of three samples (different features and targets, one mesh):
+    the summed gradients against central differences of the batch loss, the
+    mean over every zone of every sample."""
+    P, f, t, invV = _problem()
+    rng = _rng(8)
+    fs = [f, rng.standard_normal(f.shape), rng.standard_normal(f.shape)]
+    ts = [t, 0.01 * rng.standard_normal(t.shape), 0.02 * rng.standard_normal(t.shape)]
+    sF, sigma = 0.3, 0.02
+
+    def lossP(Q):
+        return L.loss_batch([L.drho(L.forward(x, Q, rounded=False)["o"], sF, invV) for x in fs], ts, sigma)
+
+    G = L.backward_batch([L.forward(x, P, rounded=False) for x in fs], P, ts, sF, invV, sigma, rounded=False)
+    h = 1e-6
+    for k in ("W1", "W2", "W3", "b1", "b2", "b3"):
+        for _ in range(3):
+            idx = tuple(int(rng.integers(0, s)) for s in P[k].shape)
+            Qp = {kk: v.copy() for kk, v in P.items()}
+            Qm = {kk: v.copy() for kk, v in P.items()}
+            Qp[k][idx] += h
+            Qm[k][idx] -= h
+            fd = (lossP(Qp) - lossP(Qm)) / (2 * h)
+            assert abs(G[k][idx] - fd) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (k, idx, G[k][idx], fd)
+    # a batch of one is the single-sample loss and gradient
+    A = L.forward(f, P, rounded=False)
+    G1 = L.backward_batch([A], P, [t], sF, invV, sigma, rounded=False)
+    G0 = L.backward(A, P, t, sF, invV, sigma, rounded=False)
+    for k in G0:
+        assert np.array_equal(G1[k], G0[k])
+
+
 def test_flux_divergence_telescopes():
     """The added fluxes only move mass between zones: sum_j V_j sum_i drho = 0
     (periodic in i, no flux through the radial boundary faces), and a uniform
