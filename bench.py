@@ -440,13 +440,23 @@ def lfc_variant(iters=600, batch=LFC_BATCH):
     fl = {"lfc_fwd_l1": 2.0 * P * 32 * 36, "lfc_fwd_l2": 2.0 * P * 32 * 288, "lfc_fwd_l3": 2.0 * P * 2 * 288,
           "lfc_adj_l3": 2.0 * P * 32 * 18, "lfc_adj_l2": 2.0 * P * 32 * 288,
           "lfc_wgrad_l3": 2.0 * P * 2 * 288, "lfc_wgrad_l2": 2.0 * P * 32 * 288, "lfc_wgrad_l1": 2.0 * P * 32 * 36}
+    # and their algorithmic bytes (each input read once, each output written
+    # once): activations and layer gradients 2 bytes a channel, features and
+    # the last layer's gradient 4 channels, the FP32 output 8 bytes a pixel
+    by = {"lfc_fwd_l1": 8 + 64, "lfc_fwd_l2": 64 + 64, "lfc_fwd_l3": 64 + 8, "lfc_adj_l3": 8 + 64 + 64,
+          "lfc_adj_l2": 64 + 64 + 64, "lfc_wgrad_l3": 8 + 64, "lfc_wgrad_l2": 64 + 64, "lfc_wgrad_l1": 64 + 8}
     kern = {}
     for name, (cnt, tot) in tim.items():
         e = {"launches": cnt, "avg_ms": tot / cnt, "ms_per_train_step": tot / iters}
         if name in fl:
             e["TFLOPs"] = fl[name] * iters / (tot * 1e-3) / 1e12
+            e["GBs"] = P * by[name] * iters / (tot * 1e-3) / 1e9
+            e["flop_per_byte"] = fl[name] / (P * by[name])
         kern[name] = e
     dom = max((k for k in kern if "TFLOPs" in kern[k]), key=lambda k: kern[k]["ms_per_train_step"])
+    # the roof that binds: the matrix peak, or HBM bandwidth times the
+    # kernel's arithmetic intensity (the bf16 ridge is 2500 / 8 = 312 flop/byte)
+    hbm_bound = HBM_PEAK_GBS * 1e-3 * kern[dom]["flop_per_byte"] < MFMA_BF16_PEAK_TFLOPS
     out = {
         "workload": "learned flux correction, planet disk: coarse 768x256 (196608 zones), fine 3072x1024, "
                     "3 conv layers 4-32-32-2, bf16 MFMA, %d samples per training step" % batch,
@@ -462,9 +472,14 @@ def lfc_variant(iters=600, batch=LFC_BATCH):
         "train_steps": 20 + 2 * iters,
         "kernels": {k: {kk: (round(vv, 5) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
-        "roofline": {"bound": "mfma", "kernel": dom, "achieved": round(kern[dom]["TFLOPs"], 3),
-                     "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": kern[dom]["TFLOPs"] / MFMA_BF16_PEAK_TFLOPS, "traffic": None},
+        "roofline": ({"bound": "hbm", "kernel": dom, "achieved": round(kern[dom]["GBs"], 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": kern[dom]["GBs"] / HBM_PEAK_GBS, "traffic": None,
+                      "flop_per_byte": kern[dom]["flop_per_byte"], "TFLOPs": round(kern[dom]["TFLOPs"], 3),
+                      "frac_of_bf16_mfma_peak": kern[dom]["TFLOPs"] / MFMA_BF16_PEAK_TFLOPS}
+                     if hbm_bound else
+                     {"bound": "mfma", "kernel": dom, "achieved": round(kern[dom]["TFLOPs"], 3),
+                      "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                      "frac": kern[dom]["TFLOPs"] / MFMA_BF16_PEAK_TFLOPS, "traffic": None}),
     }
     print("  lfc: %.3f ms per training step, %.3f ms per apply; held-out error %.3f -> %.3f; %s %.2f TFLOP/s" % (
         out["ms_per_train_step"], apply_ms, before["relative_error"], after["relative_error"], dom,

@@ -262,32 +262,45 @@ __global__ __launch_bounds__(LB) void k_flux_grad(int nx, int ny, int nsamp, con
 // ---------------------------------------------------------------------------
 // weight gradient: dW[co][tap CIN + ci] = sum_p g[p][co] act[p shifted by
 // tap][ci] over the pixels of a block: a 64-pixel column strip of one sample
-// over a run of rows.  K of the MFMA runs over pixels, so both operands are
-// staged transposed, [channel][pixel]: the layer gradient of the current row
-// (two buffers) and the activation rows above, at and below it (a ring of
-// four, the next row loaded while the current one is computed, one barrier a
-// row).  A lane's eight pixels are consecutive; the three taps along i read
-// the same 20 bytes and shift them by 0, 2 or 4 bytes.  Six waves: for 32
-// input channels wave w takes the row offset ty = w / 2 and 16 channels, all
-// three tx; for 4 it takes one 16-wide column tile of the 36 (tap, ci) pairs
-// and one 16-wide tile of output channels.  One partial sum per block, for
-// the reduction below, and the bias gradient (the sum of g) alongside.
+// over a run of rows, taken CW_RG rows at a time.  K of the MFMA runs over
+// pixels, so both operands are staged in LDS transposed, [channel][pixel]:
+// the layer gradient of the group's rows and the activation rows from one
+// above to one below them.  A staging thread loads four consecutive pixels'
+// 16-byte channel chunks and writes each channel's four values as one 8-byte
+// store (byte permutes in registers).  The next group's global loads are
+// issued into registers before the current group is computed.  A lane's
+// eight pixels are consecutive; the three taps along i read one 24-byte
+// window and shift it by -2, 0 or +2 bytes.  Six waves: for 32 input
+// channels wave w takes the row offset ty = w / 2 and 16 channels, all three
+// tx; for 4 it takes one 16-wide column tile of the 36 (tap, ci) pairs and
+// one 16-wide tile of output channels.  One partial sum per block, for the
+// reduction below, and the bias gradient (the sum of g) alongside.
 // ---------------------------------------------------------------------------
-constexpr int CW_THREADS = 384;
+constexpr int CW_THREADS = 384, CW_RG = 4;
+constexpr int CW_AW = 80; // staged activation columns: pixel x0 - 1 + c - 7 at column c (7..72)
+constexpr int CW_GW = 72; // staged layer-gradient columns: pixel x0 + c (0..63)
 
-// eight consecutive bfloat16 starting `sh` elements (0..2) after a 16-byte
-// aligned LDS address
-__device__ inline uint4 run8(const unsigned short *ap, int sh) {
-  const uint4 lo = *reinterpret_cast<const uint4 *>(ap);
-  const unsigned hi = *reinterpret_cast<const unsigned *>(ap + 8);
-  const bool two = sh == 2;
-  const unsigned b = (unsigned)(sh & 1) * 2u;
-  uint4 r;
-  r.x = __builtin_amdgcn_alignbyte(two ? lo.z : lo.y, two ? lo.y : lo.x, b);
-  r.y = __builtin_amdgcn_alignbyte(two ? lo.w : lo.z, two ? lo.z : lo.y, b);
-  r.z = __builtin_amdgcn_alignbyte(two ? hi : lo.w, two ? lo.w : lo.z, b);
-  r.w = __builtin_amdgcn_alignbyte(hi, two ? hi : lo.w, b);
-  return r;
+// the B operand of tap column tx (0..2) from the window around LDS column c
+// (16-byte aligned): columns c - 1 + tx .. c + 6 + tx
+__device__ inline uint4 tap_run(const unsigned short *ap, int tx) {
+  const unsigned dm = *reinterpret_cast<const unsigned *>(ap - 2);
+  const uint4 d = *reinterpret_cast<const uint4 *>(ap);
+  const unsigned dp = *reinterpret_cast<const unsigned *>(ap + 8);
+  if (tx == 1) return d;
+  const bool lo = tx == 0;
+  return make_uint4(__builtin_amdgcn_alignbyte(lo ? d.x : d.y, lo ? dm : d.x, 2),
+                    __builtin_amdgcn_alignbyte(lo ? d.y : d.z, lo ? d.x : d.y, 2),
+                    __builtin_amdgcn_alignbyte(lo ? d.z : d.w, lo ? d.y : d.z, 2),
+                    __builtin_amdgcn_alignbyte(lo ? d.w : dp, lo ? d.z : d.w, 2));
+}
+
+__device__ inline unsigned dword(const uint4 &v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+
+// channel k of four pixels' chunks as four consecutive bfloat16
+__device__ inline uint2 chan4(const uint4 &p0, const uint4 &p1, const uint4 &p2, const uint4 &p3, int k) {
+  const unsigned sel = (k & 1) ? 0x07060302u : 0x05040100u;
+  return make_uint2(__builtin_amdgcn_perm(dword(p1, k >> 1), dword(p0, k >> 1), sel),
+                    __builtin_amdgcn_perm(dword(p3, k >> 1), dword(p2, k >> 1), sel));
 }
 
 template <int CIN, int COUT, int GC>
@@ -296,13 +309,21 @@ __global__ __launch_bounds__(CW_THREADS) void k_conv_w(int nx, int ny, int rpc, 
                                                        const unsigned short *__restrict__ act,
                                                        float *__restrict__ part, float *__restrict__ dbpart) {
   constexpr int MT = (COUT + 15) / 16, K = 9 * CIN;
-  constexpr int AW = 72; // staged columns (66 used): 144-byte rows
-  constexpr int NA = CIN == 32 ? 3 : 1; // accumulator tiles per M tile
-  constexpr int GE = 64 * (GC / (GC == 32 ? 8 : 4)); // layer-gradient chunks of a row
-  constexpr int AE = 66 * (CIN == 32 ? 4 : 1);      // activation chunks of a row
-  __shared__ __align__(16) unsigned short At[4][CIN][AW];
-  __shared__ __align__(16) unsigned short Gt[2][16 * MT][AW];
-  __shared__ float dbr[64][COUT == 32 ? 33 : 2];
+  constexpr int NA = CIN == 32 ? 3 : 1;  // accumulator tiles per M tile
+  constexpr int AR = CW_RG + 2;          // staged activation rows
+  constexpr int ACH = CIN == 32 ? 4 : 1; // channel chunks of 8 (or 4) per pixel
+  constexpr int GCH = GC == 32 ? 4 : 1;
+  constexpr int NAT = AR * 16 * ACH;     // activation tasks (4 pixels x one chunk) of a group
+  constexpr int NHT = AR * 2 * ACH;      // halo tasks (one pixel x one chunk)
+  constexpr int NGT = CW_RG * 16 * GCH;  // layer-gradient tasks
+  constexpr int NAL = (NAT + CW_THREADS - 1) / CW_THREADS;
+  static_assert(NHT <= CW_THREADS && NGT <= CW_THREADS, "one halo and one gradient task per thread");
+  constexpr int A_BYTES = AR * CIN * CW_AW * 2, G_BYTES = CW_RG * 16 * MT * CW_GW * 2;
+  constexpr int DB_BYTES = CW_THREADS * 8 * 4;
+  constexpr int LDS_BYTES = A_BYTES + G_BYTES > DB_BYTES ? A_BYTES + G_BYTES : DB_BYTES;
+  __shared__ __align__(16) unsigned char lds[LDS_BYTES];
+  auto At = reinterpret_cast<unsigned short(*)[CIN][CW_AW]>(lds);
+  auto Gt = reinterpret_cast<unsigned short(*)[16 * MT][CW_GW]>(lds + A_BYTES);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ln = lane & 15, q = lane >> 4;
   const int strips = nx / 64;
   const int strip = blockIdx.x % strips, rc = (blockIdx.x / strips) % nrc, s = blockIdx.x / (strips * nrc);
@@ -310,60 +331,77 @@ __global__ __launch_bounds__(CW_THREADS) void k_conv_w(int nx, int ny, int rpc, 
   const size_t sb = (size_t)s * nx * ny;
   // rows of the output-channel tile beyond COUT stay zero
   if (COUT < 16 * MT)
-    for (int e = tid; e < 2 * (16 * MT - COUT) * AW; e += CW_THREADS) {
-      const int b = e / ((16 * MT - COUT) * AW), r = e % ((16 * MT - COUT) * AW);
-      Gt[b][COUT + r / AW][r % AW] = 0;
+    for (int e = tid; e < CW_RG * (16 * MT - COUT) * CW_GW; e += CW_THREADS) {
+      const int b = e / ((16 * MT - COUT) * CW_GW), r = e % ((16 * MT - COUT) * CW_GW);
+      Gt[b][COUT + r / CW_GW][r % CW_GW] = 0;
     }
-  // staging of one activation row / one layer-gradient row, through registers
-  auto load_a = [&](int yy, uint4 &v) {
-    v = make_uint4(0u, 0u, 0u, 0u);
-    if (tid < AE && yy >= 0 && yy < ny) {
-      const int col = CIN == 32 ? tid >> 2 : tid, c8 = CIN == 32 ? tid & 3 : 0;
-      int xx = x0 + col - 1;
-      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-      const unsigned short *src = act + (sb + (size_t)yy * nx + xx) * CIN + 8 * c8;
-      if (CIN == 32) v = *reinterpret_cast<const uint4 *>(src);
-      else {
-        const uint2 t = *reinterpret_cast<const uint2 *>(src);
-        v.x = t.x;
-        v.y = t.y;
-      }
-    }
+  auto ld = [&](const unsigned short *src, int wide) -> uint4 {
+    if (wide) return *reinterpret_cast<const uint4 *>(src);
+    const uint2 t = *reinterpret_cast<const uint2 *>(src);
+    return make_uint4(t.x, t.y, 0u, 0u);
   };
-  auto store_a = [&](int slot, const uint4 &v) {
-    if (tid < AE) {
-      const int col = CIN == 32 ? tid >> 2 : tid, c0 = CIN == 32 ? 8 * (tid & 3) : 0;
-      const unsigned u[4] = {v.x, v.y, v.z, v.w};
+  // a group's global loads, into registers: activation rows y - 1 .. y + CW_RG
+  // (zero outside the sample) and layer-gradient rows y .. y + CW_RG - 1 (zero
+  // from yb on)
+  uint4 ra[NAL][4], rh, rg[4];
+  auto load = [&](int y) {
 #pragma unroll
-      for (int i = 0; i < (CIN == 32 ? 8 : 4); i++)
-        At[slot][c0 + i][col] = (unsigned short)(i & 1 ? u[i >> 1] >> 16 : u[i >> 1] & 0xFFFFu);
+    for (int i = 0; i < NAL; i++) {
+      const int t = tid + CW_THREADS * i;
+      const int r = t / (16 * ACH), w = t % (16 * ACH), m = w / ACH, c8 = w % ACH;
+      const int yy = y + r - 1;
+      const bool ok = t < NAT && yy >= 0 && yy < ny;
+      const unsigned short *src = act + (sb + (size_t)(ok ? yy : 0) * nx + x0 + 4 * m) * CIN + 8 * c8;
+#pragma unroll
+      for (int u = 0; u < 4; u++) ra[i][u] = ok ? ld(src + u * CIN, CIN == 32) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    {
+      const int r = tid / (2 * ACH), w = tid % (2 * ACH), side = w / ACH, c8 = w % ACH;
+      const int yy = y + r - 1;
+      int xx = side ? x0 + 64 : x0 - 1;
+      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+      const bool ok = tid < NHT && yy >= 0 && yy < ny;
+      rh = ok ? ld(act + (sb + (size_t)yy * nx + xx) * CIN + 8 * c8, CIN == 32) : make_uint4(0u, 0u, 0u, 0u);
+    }
+    {
+      const int r = tid / (16 * GCH), w = tid % (16 * GCH), m = w / GCH, c8 = w % GCH;
+      const bool ok = tid < NGT && y + r < yb;
+      const unsigned short *src = g + (sb + (size_t)(ok ? y + r : 0) * nx + x0 + 4 * m) * GC + 8 * c8;
+#pragma unroll
+      for (int u = 0; u < 4; u++) rg[u] = ok ? ld(src + u * GC, GC == 32) : make_uint4(0u, 0u, 0u, 0u);
     }
   };
-  auto load_g = [&](int yy, uint4 &v) {
-    v = make_uint4(0u, 0u, 0u, 0u);
-    if (tid < GE) {
-      const int px = GC == 32 ? tid >> 2 : tid, c8 = GC == 32 ? tid & 3 : 0;
-      const unsigned short *src = g + (sb + (size_t)yy * nx + x0 + px) * GC + 8 * c8;
-      if (GC == 32) v = *reinterpret_cast<const uint4 *>(src);
-      else {
-        const uint2 t = *reinterpret_cast<const uint2 *>(src);
-        v.x = t.x;
-        v.y = t.y;
-      }
-    }
-  };
+  // the registers into LDS, transposed; the bias sums of the thread's
+  // layer-gradient channels (fixed per thread)
   float db[8];
 #pragma unroll
   for (int i = 0; i < 8; i++) db[i] = 0.f;
-  auto store_g = [&](int slot, const uint4 &v) {
-    if (tid < GE) {
-      const int px = GC == 32 ? tid >> 2 : tid, c0 = GC == 32 ? 8 * (tid & 3) : 0;
-      const unsigned u[4] = {v.x, v.y, v.z, v.w};
+  auto store = [&]() {
 #pragma unroll
-      for (int i = 0; i < (GC == 32 ? 8 : COUT); i++) {
-        const unsigned short hv = (unsigned short)(i & 1 ? u[i >> 1] >> 16 : u[i >> 1] & 0xFFFFu);
-        Gt[slot][c0 + i][px] = hv;
-        db[i] += from_bf16(hv);
+    for (int i = 0; i < NAL; i++) {
+      const int t = tid + CW_THREADS * i;
+      if (t < NAT) {
+        const int r = t / (16 * ACH), w = t % (16 * ACH), m = w / ACH, c0 = 8 * (w % ACH);
+#pragma unroll
+        for (int k = 0; k < (CIN == 32 ? 8 : 4); k++)
+          *reinterpret_cast<uint2 *>(&At[r][c0 + k][8 + 4 * m]) = chan4(ra[i][0], ra[i][1], ra[i][2], ra[i][3], k);
+      }
+    }
+    if (tid < NHT) {
+      const int r = tid / (2 * ACH), w = tid % (2 * ACH), side = w / ACH, c0 = 8 * (w % ACH);
+#pragma unroll
+      for (int k = 0; k < (CIN == 32 ? 8 : 4); k++) {
+        const unsigned u = dword(rh, k >> 1);
+        At[r][c0 + k][side ? 72 : 7] = (unsigned short)(k & 1 ? u >> 16 : u & 0xFFFFu);
+      }
+    }
+    if (tid < NGT) {
+      const int r = tid / (16 * GCH), w = tid % (16 * GCH), m = w / GCH, c0 = 8 * (w % GCH);
+#pragma unroll
+      for (int k = 0; k < (GC == 32 ? 8 : COUT); k++) {
+        const uint2 v = chan4(rg[0], rg[1], rg[2], rg[3], k);
+        *reinterpret_cast<uint2 *>(&Gt[r][c0 + k][4 * m]) = v;
+        db[k] += (lo_bf16(v.x) + hi_bf16(v.x)) + (lo_bf16(v.y) + hi_bf16(v.y));
       }
     }
   };
@@ -387,54 +425,33 @@ __global__ __launch_bounds__(CW_THREADS) void k_conv_w(int nx, int ny, int rpc, 
     ci = kk & 3;
     mt1 = wv / 3;
   }
-  // prologue: rows ya - 1, ya, ya + 1 and the layer gradient of row ya
-  {
-    uint4 v0, v1, v2, gv;
-    load_a(ya - 1, v0);
-    load_a(ya, v1);
-    load_a(ya + 1, v2);
-    load_g(ya, gv);
-    store_a(0, v0);
-    store_a(1, v1);
-    store_a(2, v2);
-    store_g(0, gv);
-  }
-  __syncthreads();
-  for (int y = ya; y < yb; y++) {
-    const int d = y - ya;
-    const bool more = y + 1 < yb;
-    uint4 av, gv;
-    if (more) {
-      load_a(y + 2, av);
-      load_g(y + 1, gv);
-    }
-    const int arow = (d + ty) & 3, gs = d & 1;
+  load(ya);
+  for (int y = ya; y < yb; y += CW_RG) {
+    store();
+    __syncthreads();
+    if (y + CW_RG < yb) load(y + CW_RG);
+    const int nr = min(CW_RG, yb - y);
+    for (int rr = 0; rr < nr; rr++) {
 #pragma unroll
-    for (int ks = 0; ks < 2; ks++) {
-      const int c0 = 32 * ks + 8 * q;
-      if (CIN == 32) {
-        const uint4 lo = *reinterpret_cast<const uint4 *>(&At[arow][ci][c0]);
-        const unsigned hi = *reinterpret_cast<const unsigned *>(&At[arow][ci][c0 + 8]);
-        const uint4 b1 = make_uint4(__builtin_amdgcn_alignbyte(lo.y, lo.x, 2), __builtin_amdgcn_alignbyte(lo.z, lo.y, 2),
-                                    __builtin_amdgcn_alignbyte(lo.w, lo.z, 2), __builtin_amdgcn_alignbyte(hi, lo.w, 2));
-        const uint4 b2 = make_uint4(lo.y, lo.z, lo.w, hi);
+      for (int ks = 0; ks < 2; ks++) {
+        const int c0 = 32 * ks + 8 * q;
+        const unsigned short *ap = &At[rr + ty][ci][8 + c0];
+        if (CIN == 32) {
+          const uint4 b0 = tap_run(ap, 0), b1 = tap_run(ap, 1), b2 = tap_run(ap, 2);
 #pragma unroll
-        for (int mt = 0; mt < MT; mt++) {
-          const uint4 a = *reinterpret_cast<const uint4 *>(&Gt[gs][16 * mt + ln][c0]);
-          acc[0][mt] = mfma(a, lo, acc[0][mt]);
-          acc[1][mt] = mfma(a, b1, acc[1][mt]);
-          acc[2][mt] = mfma(a, b2, acc[2][mt]);
+          for (int mt = 0; mt < MT; mt++) {
+            const uint4 a = *reinterpret_cast<const uint4 *>(&Gt[rr][16 * mt + ln][c0]);
+            acc[0][mt] = mfma(a, b0, acc[0][mt]);
+            acc[1][mt] = mfma(a, b1, acc[1][mt]);
+            acc[2][mt] = mfma(a, b2, acc[2][mt]);
+          }
+        } else {
+          uint4 b = tap_run(ap, tx);
+          if (!kok) b = make_uint4(0u, 0u, 0u, 0u);
+          const uint4 a = *reinterpret_cast<const uint4 *>(&Gt[rr][16 * mt1 + ln][c0]);
+          acc[0][0] = mfma(a, b, acc[0][0]);
         }
-      } else {
-        uint4 b = run8(&At[arow][ci][c0], tx);
-        if (!kok) b = make_uint4(0u, 0u, 0u, 0u);
-        const uint4 a = *reinterpret_cast<const uint4 *>(&Gt[gs][16 * mt1 + ln][c0]);
-        acc[0][0] = mfma(a, b, acc[0][0]);
       }
-    }
-    if (more) {
-      store_a((d + 3) & 3, av);
-      store_g((d + 1) & 1, gv);
     }
     __syncthreads();
   }
@@ -458,16 +475,16 @@ __global__ __launch_bounds__(CW_THREADS) void k_conv_w(int nx, int ny, int rpc, 
       if (co < COUT) pw[co * K + kk] = acc[0][0][v];
     }
   }
-  // bias gradient: each staging thread summed fixed channels of one pixel
-  if (tid < GE) {
-    const int px = GC == 32 ? tid >> 2 : tid, c0 = GC == 32 ? 8 * (tid & 3) : 0;
+  // bias gradient: the threads' channel sums, added in thread order (the LDS
+  // of the staging is free after the last barrier of the loop)
+  float(*dbr)[8] = reinterpret_cast<float(*)[8]>(lds);
 #pragma unroll
-    for (int i = 0; i < (GC == 32 ? 8 : COUT); i++) dbr[px][c0 + i] = db[i];
-  }
+  for (int k = 0; k < 8; k++) dbr[tid][k] = db[k];
   __syncthreads();
   if (tid < COUT) {
+    const int c8 = GC == 32 ? tid >> 3 : 0, k = GC == 32 ? tid & 7 : tid;
     float t = 0.f;
-    for (int px = 0; px < 64; px++) t += dbr[px][tid];
+    for (int u = c8; u < NGT; u += GCH) t += dbr[u][k];
     dbpart[(size_t)blockIdx.x * COUT + tid] = t;
   }
 }
@@ -625,10 +642,11 @@ inline unsigned conv_blocks(const Mesh &m, int nsamp) {
 } // namespace
 
 // Blocks of the weight-gradient kernels: nsamp x (nx / 64) strips, each split
-// into row chunks of rpc rows so that there are about 512 blocks in all.
+// into row chunks of rpc rows, so that there are at most 512 blocks (two per
+// compute unit, all resident at once) where the strips allow.
 int lfc_wblocks(int nx, int ny, int nsamp, int *rpc, int *nrc) {
   const int strips = nsamp * (nx / 64);
-  int want = (512 + strips - 1) / strips;
+  int want = 512 / strips;
   want = want < 1 ? 1 : (want > ny ? ny : want);
   const int r = (ny + want - 1) / want;
   if (rpc) *rpc = r;

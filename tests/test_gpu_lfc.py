@@ -98,12 +98,13 @@ def _forward_layers(v, P):
 def _wdepth(nx, ny, nsamp):
     """Longest chain of FP32 additions behind a weight or bias gradient: the
     library's weight-gradient blocks (a 64-pixel strip of one sample over rpc
-    rows, about 512 blocks in all; the block layout of lfc_wblocks) each
+    rows, at most 512 blocks where the strips allow; the block layout of
+    lfc_wblocks) each
     accumulate rpc x 64 pixels (an MFMA adds 32 products per k step of 32
     pixels, two k steps a row), the bias sums rpc values per thread and 64 in
     the block, then the partials of the nw blocks are summed."""
     strips = nsamp * (nx // 64)
-    want = min(max(-(-512 // strips), 1), ny)
+    want = min(max(512 // strips, 1), ny)
     rpc = -(-ny // want)
     nw = strips * (-(-ny // rpc))
     return rpc * 64 + nw + 64
