@@ -230,11 +230,13 @@ def owned_slices(p):
 
 def batch_variant(steps, warmup, tune=True, err_steps=100):
     """The parameter sweep of 256 uneven viscous disks (N_r in 64..512,
-    N_phi = 3 N_r, alpha viscosity), same disks and steps in four forms: the
-    FP64 and FP32-bulk steps called disk by disk, and both advanced by one
-    captured graph per step with the autotuned graph width and sweep chunk;
-    then the FP32 disks against the FP64 ones after err_steps steps at equal
-    times (each FP32 disk takes its FP64 twin's time steps)."""
+    N_phi = 3 N_r, alpha viscosity), same disks and steps in six forms: the
+    FP64 and FP32-bulk steps called disk by disk; both advanced by one captured
+    graph of the disks' own steps per step (autotuned graph width and sweep
+    chunk); and both in the fused form, each kernel of the step launched once
+    over all disks (sweep chunk autotuned per size class); then the FP32 disks
+    against the FP64 ones after err_steps steps at equal times (each FP32 disk
+    takes its FP64 twin's time steps)."""
     import torch
     from paper_1602_02359_amd import fargo as F
     from paper_1602_02359_amd import workloads as W
@@ -275,17 +277,37 @@ def batch_variant(steps, warmup, tune=True, err_steps=100):
             sv.fargo_check()
         out[prec + "_batched_graph"] = {"value": cells * steps / el, "ms_per_step": 1e3 * el / steps,
                                         "tuned": {"lanes": best[0], "chunk": best[1]} if best else None}
-        print("  %s: disk by disk %.3e, batched graph %.3e cell-updates/s, tuned %s" % (
-            prec, out[prec + "_disk_by_disk"]["value"], out[prec + "_batched_graph"]["value"], best),
-            file=sys.stderr, flush=True)
+        del b
+        # fused: every kernel of the step once over all disks
+        b = F.Batch(ss, lanes=0)
+        if tune:
+            b.fargo_batch_tune(lanes=(0,), chunks=(8, 16, 32, 64), steps=10)
+        ch = b.chunks()
+        for _ in range(warmup):
+            b.fargo_batch_step()
+        el = timed(b.fargo_batch_step, steps)
+        for sv in ss:
+            sv.fargo_check()
+        by_class = {}
+        for p, c in zip(probs, ch):
+            by_class.setdefault(int(math.floor(math.log2(p.params["ny"]))), c)
+        out[prec + "_fused"] = {"value": cells * steps / el, "ms_per_step": 1e3 * el / steps,
+                                "launches_per_step": 8,
+                                "chunk_by_size_class": {"ny in [%d, %d)" % (2 ** k, 2 ** (k + 1)): c
+                                                        for k, c in sorted(by_class.items())}}
+        print("  %s: disk by disk %.3e, batched graph %.3e (tuned %s), fused %.3e cell-updates/s" % (
+            prec, out[prec + "_disk_by_disk"]["value"], out[prec + "_batched_graph"]["value"], best,
+            out[prec + "_fused"]["value"]), file=sys.stderr, flush=True)
         del b, ss
         torch.cuda.empty_cache()
     v = lambda k: out[k]["value"]
     out["speedup"] = {
-        "batching_fp64": v("fp64_batched_graph") / v("fp64_disk_by_disk"),
-        "batching_fp32": v("fp32_batched_graph") / v("fp32_disk_by_disk"),
-        "precision_disk_by_disk": v("fp32_disk_by_disk") / v("fp64_disk_by_disk"),
-        "fp32_batched_vs_fp64_disk_by_disk": v("fp32_batched_graph") / v("fp64_disk_by_disk"),
+        "fused_vs_disk_by_disk_fp64": v("fp64_fused") / v("fp64_disk_by_disk"),
+        "fused_vs_disk_by_disk_fp32": v("fp32_fused") / v("fp32_disk_by_disk"),
+        "fused_vs_graph_fp64": v("fp64_fused") / v("fp64_batched_graph"),
+        "fused_vs_graph_fp32": v("fp32_fused") / v("fp32_batched_graph"),
+        "precision_fused": v("fp32_fused") / v("fp64_fused"),
+        "fp32_fused_vs_fp64_disk_by_disk": v("fp32_fused") / v("fp64_disk_by_disk"),
     }
     # FP32 against FP64 at equal times, disk by disk (a batch step equals the
     # disks' own steps bit for bit)

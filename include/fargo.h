@@ -275,13 +275,29 @@ int fargo_timings(fargo_ctx *ctx, const char **names, int64_t *counts, double *t
    contexts, states and workspaces must outlive the batch and must not be
    used by other calls while a batch step runs.  `states` is an array of
    `count` states (copied).  Profiling events are not recorded inside the
-   graph. */
+   graph.
+   lanes == 0 selects the fused form: each kernel of the step is launched once
+   for all contexts, its workgroups mapped to (context, workgroup) through a
+   device table, so a step is seven or eight launches (captured into one
+   graph) whatever the number of disks; the results are those of fargo_step
+   context by context, bit for bit.  It requires 2D meshes (nz == 1) of one
+   configuration (precision, geometry, equation of state, viscosity, orbital
+   advection, v0 mode, boundary kinds), FIXED radial sides, and nx at most
+   1792 (FARGO_EUNSUPPORTED otherwise; lanes 1..64 take any contexts). */
 typedef struct fargo_batch fargo_batch;
 int fargo_batch_create(fargo_ctx *const *ctxs, const fargo_state *states, int count, int lanes,
                        fargo_batch **out);
 /* One step of every context: a single graph launch on `stream`. */
 int fargo_batch_step(fargo_batch *batch, void *stream);
-/* Autotuner: for every pair (lanes[a], chunks[c]) - the graph's stream count
+/* The column sweeps' zones per thread each context uses in the batch (n ==
+   count entries). */
+int fargo_batch_chunks(const fargo_batch *batch, int32_t *chunk, int n);
+/* Autotuner (the block-size tuning of Sect. 4.2, for batches).  Fused form:
+   the zones per thread of the column sweep are chosen per size class of
+   contexts (floor(log2 ny)), class after class, from chunks[], each
+   candidate timed over `steps` graph launches (lanes is ignored; best[0] =
+   0, best[1] = the last context's choice; fargo_batch_chunks gives all).
+   Other forms: for every pair (lanes[a], chunks[c]) - the graph's stream count
    and the zones per thread of the Y/Z column sweeps - re-capture the batch,
    time `steps` graph launches with HIP events on `stream`, and keep the
    fastest pair (written to best[0], best[1]) with the graph captured and

@@ -815,14 +815,28 @@ int fargo_timings(fargo_ctx *ctx, const char **names, int64_t *counts, double *t
 // replayed with a single graph launch per step.  Each context keeps its own
 // device time step (box 6), so nothing synchronises the host.
 // ------------------------------------------------------------------------
+//
+// Fused mode (lanes == 0): each kernel of the step runs once for all disks,
+// its blocks mapped to (disk, block) through a table (ManyGrid), so that a
+// step is seven or eight launches whatever the number of disks, captured into
+// one graph.  Every zone takes the arithmetic of its disk's own step, so the
+// results are those of fargo_step disk by disk, bit for bit.  It takes 2D
+// meshes of one configuration (precision, geometry, equation of state,
+// viscosity, orbital advection, v0 mode, boundary kinds) with FIXED radial
+// sides (boxes 2 and 9 then launch nothing) and rings of at most 1792 zones.
 struct fargo_batch {
   std::vector<fargo_ctx *> ctx;
   std::vector<fargo_state> st;
-  int lanes = 1;
+  int lanes = 1; // 0: fused
   hipStream_t origin = nullptr;
   std::vector<hipStream_t> ls;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // fused mode: the launches' argument blocks and tables in one allocation
+  void *fmem = nullptr;
+  ManyGrid g[8] = {};
+  int nxmax = 0;
+  std::vector<int> chunk; // per disk (the sweep's chunk length, tuned per size class)
 };
 
 namespace {
@@ -889,28 +903,159 @@ int batch_capture(fargo_batch *b, int lanes) {
 
 size_t field_bytes(const fargo_ctx *c) { return (size_t)c->m.pitch * c->m.nyg * c->m.nzg * c->esize; }
 
+// ---- fused mode ----
+enum { FU_CFL, FU_DT, FU_SRC, FU_SRCG, FU_VISC, FU_SY, FU_RX, FU_VEL, FU_N };
+
+bool fused_ok(fargo_ctx *const *c, int n) {
+  const fargo_params &p0 = c[0]->p;
+  for (int d = 0; d < n; d++) {
+    const fargo_params &p = c[d]->p;
+    const Mesh &m = c[d]->m;
+    if (m.d3 || p.precision != p0.precision || p.geometry != p0.geometry || p.eos != p0.eos ||
+        p.visc != p0.visc || p.fargo != p0.fargo || p.v0_mode != p0.v0_mode)
+      return false;
+    for (int k = 0; k < 4; k++)
+      if (p.bc[k] != p0.bc[k]) return false;
+    if (p.bc[0] != FARGO_BC_FIXED || p.bc[1] != FARGO_BC_FIXED) return false;
+    if (m.cseg != 1 || m.nx > 1792) return false;
+  }
+  return true;
+}
+
+// argument blocks and block table of one launch over all disks
+struct ManyHost {
+  size_t asz = 0;
+  std::vector<char> args;
+  std::vector<uint2> tab;
+  void *slot(size_t d) {
+    if (args.size() < (d + 1) * asz) args.resize((d + 1) * asz);
+    return args.data() + d * asz;
+  }
+  void blocks(unsigned d, unsigned nb) {
+    while (tab.size() % 8) tab.push_back(make_uint2(MANY_NONE, 0u)); // each disk from a multiple of 8
+    for (unsigned b = 0; b < nb; b++) tab.push_back(make_uint2(d, b));
+  }
+};
+
+template <typename F>
+int fused_build(fargo_batch *b) {
+  const unsigned n = (unsigned)b->ctx.size();
+  ManyHost H[FU_N];
+  // argument blocks packed at their exact size: the kernels index them so
+  H[FU_CFL].asz = cfl_args_bytes<F>();
+  H[FU_DT].asz = dt_final_args_bytes();
+  H[FU_SRC].asz = H[FU_SRCG].asz = source_args_bytes<F>();
+  H[FU_VISC].asz = visc_args_bytes<F>();
+  H[FU_SY].asz = sweep_y_args_bytes<F>();
+  H[FU_RX].asz = ring_x_args_bytes<F>();
+  H[FU_VEL].asz = vel_args_bytes<F>();
+  b->nxmax = 0;
+  for (unsigned d = 0; d < n; d++) {
+    fargo_ctx *c = b->ctx[d];
+    Mesh m = c->m;
+    m.chunk = b->chunk[d];
+    b->nxmax = std::max(b->nxmax, m.nx);
+    const StateT<F> S = state_of<F>(c, &b->st[d]);
+    const double *dtp = c->w.dt;
+    F *v2[4] = {(F *)c->v2[0], (F *)c->v2[1], (F *)c->v2[2], (F *)c->v2[3]};
+    H[FU_CFL].blocks(d, cfl_args<F>(m, S, c->v0, c->ringrate, c->ringshear, c->w.err, H[FU_CFL].slot(d)));
+    H[FU_DT].blocks(d, dt_final_args(m, c->w, c->ringrate, c->ringshear, H[FU_DT].slot(d)));
+    H[FU_SRC].blocks(d, source_args<F>(m, S, dtp, v2[0], v2[1], v2[2], v2[3], H[FU_SRC].slot(d)));
+    H[FU_SRCG].blocks(d, source_ghosts_args<F>(m, S, v2[0], v2[1], v2[2], v2[3], H[FU_SRCG].slot(d)));
+    StateT<F> P = S; // post-source fields, as in the step
+    P.vx = v2[0];
+    P.vy = v2[1];
+    if (m.visc) {
+      H[FU_VISC].blocks(d, visc_args<F>(m, S, v2[0], v2[1], (F *)c->v3[0], (F *)c->v3[1], dtp, H[FU_VISC].slot(d)));
+      P.vx = (F *)c->v3[0];
+      P.vy = (F *)c->v3[1];
+    }
+    P.vz = v2[2];
+    P.e = v2[3];
+    const TSetT<F> TA = tset<F>(c, c->TA), TB = tset<F>(c, c->TB);
+    H[FU_SY].blocks(d, sweep_y_args<F>(m, P, TB, dtp, H[FU_SY].slot(d)));
+    H[FU_RX].blocks(d, ring_x_args<F>(m, (const F *)P.vx, TB, TA, S, c->v0, dtp, H[FU_RX].slot(d)));
+    H[FU_VEL].blocks(d, vel_args<F>(m, S, TA, H[FU_VEL].slot(d)));
+  }
+  size_t total = 0;
+  for (auto &h : H) total += al(h.args.size()) + al(h.tab.size() * sizeof(uint2));
+  if (b->fmem) (void)hipFree(b->fmem);
+  b->fmem = nullptr;
+  if (hipMalloc(&b->fmem, total) != hipSuccess) return FARGO_ENOMEM;
+  char *base = (char *)b->fmem;
+  size_t o = 0;
+  for (int k = 0; k < FU_N; k++) {
+    ManyHost &h = H[k];
+    b->g[k] = ManyGrid{nullptr, nullptr, (unsigned)h.tab.size()};
+    if (h.tab.empty()) continue;
+    if (hipMemcpy(base + o, h.args.data(), h.args.size(), hipMemcpyHostToDevice) != hipSuccess) return FARGO_EHIP;
+    b->g[k].args = base + o;
+    o += al(h.args.size());
+    if (hipMemcpy(base + o, h.tab.data(), h.tab.size() * sizeof(uint2), hipMemcpyHostToDevice) != hipSuccess)
+      return FARGO_EHIP;
+    b->g[k].tab = (const uint2 *)(base + o);
+    o += al(h.tab.size() * sizeof(uint2));
+  }
+  return FARGO_OK;
+}
+
+// one step of every disk: the step's kernels, each once over all disks
+template <typename F>
+void fused_step(fargo_batch *b, Launch &L) {
+  const Mesh &m0 = b->ctx[0]->m;
+  launch_cfl_many<F>(L, b->g[FU_CFL], b->nxmax);                                  // boxes 3, 4, 6
+  launch_dt_final_many(L, b->g[FU_DT]);
+  launch_source_many<F>(L, m0, b->g[FU_SRC], b->g[FU_SRCG]);                        // boxes 7a-7c
+  if (m0.visc) launch_visc_many<F>(L, b->g[FU_VISC]);                              // box 7d
+  launch_sweep_y_many<F>(L, m0, b->g[FU_SY]);                                       // boxes 12a-c, Y
+  launch_ring_x_many<F>(L, b->ctx[0]->nq, b->g[FU_RX]);                              // X, split, FARGO, 12d
+  launch_vel_many<F>(L, b->g[FU_VEL]);                                              // 12d (v_y)
+}
+
+int fused_capture(fargo_batch *b) {
+  batch_release_graph(b);
+  int rc = fp32(b->ctx[0]) ? fused_build<float>(b) : fused_build<double>(b);
+  if (rc) return rc;
+  if (hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal) != hipSuccess) return FARGO_EHIP;
+  Launch L{b->origin, nullptr};
+  if (fp32(b->ctx[0])) fused_step<float>(b, L);
+  else fused_step<double>(b, L);
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(b->origin, &g) != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return FARGO_EHIP;
+  }
+  b->graph = g;
+  if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) return FARGO_EHIP;
+  return FARGO_OK;
+}
+
 } // namespace
 
 extern "C" {
 
 int fargo_batch_create(fargo_ctx *const *ctxs, const fargo_state *states, int count, int lanes,
                        fargo_batch **out) {
-  if (!ctxs || !states || !out || count < 1 || lanes < 1 || lanes > 64) return FARGO_EINVAL;
+  if (!ctxs || !states || !out || count < 1 || lanes < 0 || lanes > 64) return FARGO_EINVAL;
   for (int d = 0; d < count; d++) {
     if (!ctxs[d]) return FARGO_EINVAL;
     int rc = check_state(ctxs[d], &states[d]);
     if (rc) return rc;
     if (ctxs[d]->dev != ctxs[0]->dev) return FARGO_EINVAL;
   }
+  if (lanes == 0 && !fused_ok(ctxs, count)) return FARGO_EUNSUPPORTED;
   fargo_batch *b = new (std::nothrow) fargo_batch();
   if (!b) return FARGO_ENOMEM;
   b->ctx.assign(ctxs, ctxs + count);
   b->st.assign(states, states + count);
+  for (int d = 0; d < count; d++) b->chunk.push_back(ctxs[d]->m.chunk);
   if (hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking) != hipSuccess) {
     delete b;
     return FARGO_EHIP;
   }
-  int rc = batch_capture(b, lanes);
+  b->lanes = lanes;
+  int rc = lanes == 0 ? fused_capture(b) : batch_capture(b, lanes);
   if (rc) {
     fargo_batch_destroy(b);
     return rc;
@@ -924,11 +1069,20 @@ int fargo_batch_step(fargo_batch *b, void *stream) {
   return hip_ok(hipGraphLaunch(b->exec, (hipStream_t)stream));
 }
 
+int fargo_batch_chunks(const fargo_batch *b, int32_t *chunk, int n) {
+  if (!b || !chunk || n != (int)b->ctx.size()) return FARGO_EINVAL;
+  for (int d = 0; d < n; d++) chunk[d] = b->lanes == 0 ? b->chunk[d] : b->ctx[d]->m.chunk;
+  return FARGO_OK;
+}
+
 int fargo_batch_tune(fargo_batch *b, const int32_t *lanes, int nlanes, const int32_t *chunks, int nchunks,
                      int steps, void *stream, int32_t *best) {
-  if (!b || !lanes || nlanes < 1 || !chunks || nchunks < 1 || steps < 1) return FARGO_EINVAL;
-  for (int t = 0; t < nlanes; t++)
-    if (lanes[t] < 1 || lanes[t] > 64) return FARGO_EINVAL;
+  if (!b || !chunks || nchunks < 1 || steps < 1) return FARGO_EINVAL;
+  if (b->lanes != 0) { // the fused form ignores lanes
+    if (!lanes || nlanes < 1) return FARGO_EINVAL;
+    for (int t = 0; t < nlanes; t++)
+      if (lanes[t] < 1 || lanes[t] > 64) return FARGO_EINVAL;
+  }
   for (int t = 0; t < nchunks; t++)
     if (chunks[t] < 1) return FARGO_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -958,6 +1112,69 @@ int fargo_batch_tune(fargo_batch *b, const int32_t *lanes, int nlanes, const int
   for (size_t d = 0; d < b->ctx.size(); d++) chunk0[d] = b->ctx[d]->m.chunk;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = FARGO_EHIP;
+  auto restore = [&]() {
+    size_t o = 0;
+    for (auto &f : fields) {
+      if (!rc && hipMemcpyAsync(f.first, (char *)save + o, f.second, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = FARGO_EHIP;
+      o += f.second;
+    }
+  };
+  auto timed = [&](float &ms) {
+    if (hipGraphLaunch(b->exec, s) != hipSuccess) rc = FARGO_EHIP; // warm-up
+    if (!rc && hipEventRecord(e0, s) != hipSuccess) rc = FARGO_EHIP;
+    for (int k = 0; k < steps && !rc; k++)
+      if (hipGraphLaunch(b->exec, s) != hipSuccess) rc = FARGO_EHIP;
+    if (!rc && hipEventRecord(e1, s) != hipSuccess) rc = FARGO_EHIP;
+    if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = FARGO_EHIP;
+  };
+  if (b->lanes == 0) {
+    // fused: the sweep's chunk length per size class of disks (floor(log2 ny)),
+    // one class after the other, the others held at their best so far
+    std::vector<int> cls(b->ctx.size());
+    int cmin = 99, cmax = -1;
+    for (size_t d = 0; d < b->ctx.size(); d++) {
+      int c = 0;
+      while ((2 << c) <= b->ctx[d]->m.ny) c++;
+      cls[d] = c;
+      cmin = std::min(cmin, c);
+      cmax = std::max(cmax, c);
+    }
+    for (int c = cmin; c <= cmax && !rc; c++) {
+      bool any = false;
+      for (int v : cls) any |= v == c;
+      if (!any) continue;
+      float best_ms = 0.0f;
+      int best_chunk = -1;
+      for (int ci = 0; ci < nchunks && !rc; ci++) {
+        for (size_t d = 0; d < b->ctx.size(); d++)
+          if (cls[d] == c) b->chunk[d] = chunks[ci];
+        rc = fused_capture(b);
+        float ms = 0.0f;
+        if (!rc) timed(ms);
+        restore();
+        if (!rc && (best_chunk < 0 || ms < best_ms)) {
+          best_ms = ms;
+          best_chunk = chunks[ci];
+        }
+      }
+      for (size_t d = 0; d < b->ctx.size(); d++)
+        if (cls[d] == c && best_chunk > 0) b->chunk[d] = best_chunk;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = FARGO_EHIP;
+    (void)hipFree(save);
+    if (rc) b->chunk = chunk0;
+    const int rc2 = fused_capture(b);
+    if (!rc) rc = rc2;
+    if (!rc && best) {
+      best[0] = 0;
+      best[1] = b->chunk.back();
+    }
+    return rc;
+  }
   float best_ms = 0.0f;
   int best_l = b->lanes, best_c = chunk0[0];
   // the fastest candidate's graph is kept as timed: a graph captured again
@@ -1034,6 +1251,7 @@ void fargo_batch_destroy(fargo_batch *b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
   batch_release_graph(b);
+  if (b->fmem) (void)hipFree(b->fmem);
   if (b->origin) (void)hipStreamDestroy(b->origin);
   delete b;
 }

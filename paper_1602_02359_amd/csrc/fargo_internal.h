@@ -271,6 +271,40 @@ struct StateT {
   const R *nu;
 };
 
+// ------------------------------------------------------------------------
+// One launch over the blocks of several meshes (a batch of disks).  Block b
+// of the launch runs block tab[b].y of mesh tab[b].x with that mesh's
+// arguments args[tab[b].x] (the kernel's argument block, filled on the host
+// by its *_args function); tab[b].x == MANY_NONE marks a padding block, which
+// exits at once.  Every mesh's blocks start at a multiple of 8 in the launch,
+// so that the XCD-contiguous block order of a single launch carries over.
+// The kernels are the single-mesh kernels' bodies: every zone takes the same
+// arithmetic as in its own launch.
+// ------------------------------------------------------------------------
+constexpr unsigned MANY_NONE = 0xFFFFFFFFu;
+struct ManyGrid {
+  const void *args;  // device: one argument block per mesh
+  const uint2 *tab;  // device: nblk entries
+  unsigned nblk;
+};
+// the blocks and tables do not change while the kernels run: read through
+// the constant address space (scalar loads), word by word
+using cuint = const __attribute__((address_space(4))) unsigned;
+template <typename A>
+__device__ inline A many_args(const void *args, unsigned d) {
+  static_assert(sizeof(A) % 4 == 0, "argument blocks are whole words");
+  const cuint *p = (const cuint *)((const char *)args + (size_t)d * sizeof(A));
+  A a;
+  unsigned *q = reinterpret_cast<unsigned *>(&a);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(A) / 4); i++) q[i] = p[i];
+  return a;
+}
+__device__ inline uint2 many_block(const uint2 *tab) {
+  const cuint *p = (const cuint *)(tab + blockIdx.x);
+  return make_uint2(p[0], p[1]);
+}
+
 // Each launcher is defined once for R = double and R = float.
 // boundaries (boxes 2 and 9)
 template <typename R>
@@ -327,6 +361,54 @@ double *static_scratch(int dev);
 void launch_stream_copy(hipStream_t s, const void *src, void *dst, size_t bytes, int blocks);
 template <typename R>
 void launch_sums(Launch &L, const Mesh &m, const StateT<R> &s, double *partial, double *out);
+
+// Multi-mesh forms of the step's kernels on 2D meshes (see ManyGrid): for
+// each, the size of its argument block, a host function that writes one
+// mesh's block to dst and returns that mesh's block count, and the launch.
+template <typename R>
+size_t cfl_args_bytes();
+template <typename R>
+unsigned cfl_args(const Mesh &m, const StateT<R> &s, double *v0, double *ringrate, double *ringshear, int *err,
+                  void *dst);
+template <typename R>
+void launch_cfl_many(Launch &L, const ManyGrid &g, int nxmax);
+size_t dt_final_args_bytes();
+unsigned dt_final_args(const Mesh &m, const DevWords &w, const double *ringrate, const double *ringshear, void *dst);
+void launch_dt_final_many(Launch &L, const ManyGrid &g);
+template <typename F>
+size_t source_args_bytes();
+template <typename F>
+unsigned source_args(const Mesh &m, const StateT<F> &s, const double *dt, F *vx2, F *vy2, F *vz2, F *e2, void *dst);
+template <typename F>
+unsigned source_ghosts_args(const Mesh &m, const StateT<F> &s, F *vx2, F *vy2, F *vz2, F *e2, void *dst);
+template <typename F>
+void launch_source_many(Launch &L, const Mesh &m0, const ManyGrid &g, const ManyGrid &ghosts);
+template <typename F>
+size_t visc_args_bytes();
+template <typename F>
+unsigned visc_args(const Mesh &m, const StateT<F> &s, const F *vx2, const F *vy2, F *vx3, F *vy3, const double *dt,
+                   void *dst);
+template <typename F>
+void launch_visc_many(Launch &L, const ManyGrid &g);
+template <typename F>
+size_t sweep_y_args_bytes();
+template <typename F>
+unsigned sweep_y_args(const Mesh &m, const StateT<F> &s, const TSetT<F> &out, const double *dt, void *dst);
+template <typename F>
+void launch_sweep_y_many(Launch &L, const Mesh &m0, const ManyGrid &g);
+template <typename F>
+size_t ring_x_args_bytes();
+template <typename F>
+unsigned ring_x_args(const Mesh &m, const F *vx2, const TSetT<F> &T, const TSetT<F> &Tout, const StateT<F> &s,
+                     const double *v0, const double *dt, void *dst);
+template <typename F>
+void launch_ring_x_many(Launch &L, int nq, const ManyGrid &g);
+template <typename F>
+size_t vel_args_bytes();
+template <typename F>
+unsigned vel_args(const Mesh &m, const StateT<F> &s, const TSetT<F> &T, void *dst);
+template <typename F>
+void launch_vel_many(Launch &L, const ManyGrid &g);
 
 // ------------------------------------------------------------------------
 // Learned flux correction (2D cylindrical FP64 state)

@@ -99,14 +99,14 @@ struct Zv {
 // The geometry and the equation of state are template parameters: fewer
 // run-time conditions leave more scalar registers for the march.
 template <typename F, bool D3, int GEO, bool ADI>
-__global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
+__device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *__restrict__ dtp,
                                                   F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
-                                                  F *__restrict__ e2, int nbx, int nby) {
+                                                  F *__restrict__ e2, int nbx, int nby, unsigned bid_, unsigned nbk_) {
   __shared__ Lds<F> L;
   // the row is the wave index: uniform, so that geometric factors of the
   // row come through scalar loads, which do not stall behind the prefetches
   const int tid = threadIdx.x, r = __builtin_amdgcn_readfirstlane(tid >> 6), c = tid & 63;
-  const unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned Lb = xcd_remap(bid_, nbk_);
   const int ty = (int)(Lb % (unsigned)nby), tx = (int)(Lb / (unsigned)nby);
   const int i0 = tx * TX, jt0 = m.j0 + ty * TY;
   const int w = min(TX, m.nx - i0), h = min(TY, m.jn - jt0);
@@ -497,14 +497,20 @@ __global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, S
     rb = rb1;
   }
 }
+template <typename F, bool D3, int GEO, bool ADI>
+__global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
+                                                  F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
+                                                  F *__restrict__ e2, int nbx, int nby) {
+  source_body<F, D3, GEO, ADI>(m, s, dtp, vx2, vy2, vz2, e2, nbx, nby, blockIdx.x, gridDim.x);
+}
 
 // Ghost zones (Y ghost rows of every plane, and Z ghost planes of the active
 // rows) carry v^n and e into v'' and e''; one block per row.
 template <typename F>
-__global__ __launch_bounds__(256) void k_source_ghosts(Mesh m, StateT<F> s, F *__restrict__ vx2,
+__device__ __forceinline__ void source_ghosts_body(Mesh m, StateT<F> s, F *__restrict__ vx2,
                                                        F *__restrict__ vy2, F *__restrict__ vz2,
-                                                       F *__restrict__ e2) {
-  const int b = blockIdx.x, ngy = m.nyg - m.ny;
+                                                       F *__restrict__ e2, unsigned bid_, unsigned nbk_) {
+  const int b = bid_, ngy = m.nyg - m.ny;
   int j, k;
   if (b < m.nzg * ngy) {
     k = b / ngy;
@@ -525,6 +531,37 @@ __global__ __launch_bounds__(256) void k_source_ghosts(Mesh m, StateT<F> s, F *_
     if (m.d3) vz2[o] = s.vz[o];
     if (m.eos == FARGO_ADIABATIC) e2[o] = s.e[o];
   }
+}
+template <typename F>
+__global__ __launch_bounds__(256) void k_source_ghosts(Mesh m, StateT<F> s, F *__restrict__ vx2,
+                                                       F *__restrict__ vy2, F *__restrict__ vz2,
+                                                       F *__restrict__ e2) {
+  source_ghosts_body<F>(m, s, vx2, vy2, vz2, e2, blockIdx.x, gridDim.x);
+}
+
+// multi-mesh forms (ManyGrid)
+template <typename F>
+struct SourceArgs {
+  Mesh m;
+  StateT<F> s;
+  const double *dt;
+  F *vx2, *vy2, *vz2, *e2;
+  int nbx, nby;
+  unsigned nb;
+};
+template <typename F, bool D3, int GEO, bool ADI>
+__global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source_many(const void *args, const uint2 *tab) {
+  const uint2 t = many_block(tab);
+  if (t.x == MANY_NONE) return;
+  const SourceArgs<F> a = many_args<SourceArgs<F>>(args, t.x);
+  source_body<F, D3, GEO, ADI>(a.m, a.s, a.dt, a.vx2, a.vy2, a.vz2, a.e2, a.nbx, a.nby, t.y, a.nb);
+}
+template <typename F>
+__global__ __launch_bounds__(256) void k_source_ghosts_many(const void *args, const uint2 *tab) {
+  const uint2 t = many_block(tab);
+  if (t.x == MANY_NONE) return;
+  const SourceArgs<F> a = many_args<SourceArgs<F>>(args, t.x);
+  source_ghosts_body<F>(a.m, a.s, a.vx2, a.vy2, a.vz2, a.e2, t.y, a.nb);
 }
 
 } // namespace
@@ -560,5 +597,52 @@ template void launch_source<double>(Launch &, const Mesh &, const StateT<double>
                                     double *, double *);
 template void launch_source<float>(Launch &, const Mesh &, const StateT<float> &, const double *, float *, float *,
                                    float *, float *);
+
+template <typename F>
+size_t source_args_bytes() { return sizeof(SourceArgs<F>); }
+
+template <typename F>
+unsigned source_args(const Mesh &m, const StateT<F> &s, const double *dt, F *vx2, F *vy2, F *vz2, F *e2, void *dst) {
+  const int nbx = (m.nx + TX - 1) / TX, nby = (m.ny + TY - 1) / TY;
+  const unsigned nb = (unsigned)nbx * (unsigned)nby;
+  *(SourceArgs<F> *)dst = SourceArgs<F>{m, s, dt, vx2, vy2, vz2, e2, nbx, nby, nb};
+  return nb;
+}
+
+template <typename F>
+unsigned source_ghosts_args(const Mesh &m, const StateT<F> &s, F *vx2, F *vy2, F *vz2, F *e2, void *dst) {
+  const unsigned ng = (unsigned)(m.nzg * (m.nyg - m.ny) + (m.d3 ? (m.nzg - m.nz) * m.ny : 0));
+  *(SourceArgs<F> *)dst = SourceArgs<F>{m, s, nullptr, vx2, vy2, vz2, e2, 0, 0, ng};
+  return ng;
+}
+
+// 2D meshes of one geometry and equation of state (those of m0)
+template <typename F>
+void launch_source_many(Launch &L, const Mesh &m0, const ManyGrid &g, const ManyGrid &ghosts) {
+  prof_begin(L, K_SRC);
+  auto go = [&](auto geo, auto adi) {
+    k_source_many<F, false, decltype(geo)::value, decltype(adi)::value><<<g.nblk, NT, 0, L.s>>>(g.args, g.tab);
+  };
+  auto by_eos = [&](auto geo) {
+    if (m0.eos == FARGO_ADIABATIC) go(geo, std::true_type{});
+    else go(geo, std::false_type{});
+  };
+  if (m0.geo == FARGO_SPHERICAL) by_eos(std::integral_constant<int, FARGO_SPHERICAL>{});
+  else if (m0.geo == FARGO_CYLINDRICAL) by_eos(std::integral_constant<int, FARGO_CYLINDRICAL>{});
+  else by_eos(std::integral_constant<int, FARGO_CARTESIAN>{});
+  prof_end(L, K_SRC);
+  prof_begin(L, K_SRC_GHOSTS);
+  k_source_ghosts_many<F><<<ghosts.nblk, 256, 0, L.s>>>(ghosts.args, ghosts.tab);
+  prof_end(L, K_SRC_GHOSTS);
+}
+
+#define FARGO_SOURCE_MANY(F)                                                                                        \
+  template size_t source_args_bytes<F>();                                                                          \
+  template unsigned source_args<F>(const Mesh &, const StateT<F> &, const double *, F *, F *, F *, F *, void *);   \
+  template unsigned source_ghosts_args<F>(const Mesh &, const StateT<F> &, F *, F *, F *, F *, void *);            \
+  template void launch_source_many<F>(Launch &, const Mesh &, const ManyGrid &, const ManyGrid &);
+FARGO_SOURCE_MANY(double)
+FARGO_SOURCE_MANY(float)
+#undef FARGO_SOURCE_MANY
 
 } // namespace fargo

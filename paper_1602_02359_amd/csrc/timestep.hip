@@ -148,13 +148,13 @@ __device__ inline double zone_rate2(const Mesh &m, const CflRing &C, double vb, 
 // The state may be stored in FP32 (R = float); the time step is always formed
 // in FP64 from the stored values.
 template <int M, typename R, int NB>
-__global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_cfl, double *__restrict__ v0,
+__device__ __forceinline__ void cfl_ring_body(Mesh m, StateT<R> s, int with_cfl, double *__restrict__ v0,
                                                   double *__restrict__ ringrate, double *__restrict__ ringshear,
-                                                  int *__restrict__ err) {
+                                                  int *__restrict__ err, unsigned bid_, unsigned nbk_) {
 #pragma clang fp contract(off)
   extern __shared__ double V[]; // the ring's v_x
   __shared__ double red[2 * MAXW];
-  const unsigned L = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned L = xcd_remap(bid_, nbk_);
   constexpr int KT = 16;
   const unsigned tile = L / ((unsigned)m.ny * KT), q = L % ((unsigned)m.ny * KT);
   const int kb = (int)tile * KT, kt = min(KT, m.nz - kb);
@@ -231,6 +231,12 @@ __global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_c
     ringshear[r] = smax;
     if (anybad) atomicOr(err, 1);
   }
+}
+template <int M, typename R, int NB>
+__global__ __launch_bounds__(NB) void k_cfl_ring(Mesh m, StateT<R> s, int with_cfl, double *__restrict__ v0,
+                                                  double *__restrict__ ringrate, double *__restrict__ ringshear,
+                                                  int *__restrict__ err) {
+  cfl_ring_body<M, R, NB>(m, s, with_cfl, v0, ringrate, ringshear, err, blockIdx.x, gridDim.x);
 }
 
 // Rings longer than one workgroup holds, in segments of CFL_SEG zones (256
@@ -348,8 +354,8 @@ __global__ __launch_bounds__(256) void k_cfl_seg(Mesh m, StateT<R> s, int with_c
 // One workgroup: dt from the ring slots (or the imposed value), then the split
 // of every ring.  A non-positive or non-finite dt is flagged and replaced by 0,
 // which leaves the state unchanged.
-__global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const double *__restrict__ ringrate,
-                                                   const double *__restrict__ ringshear) {
+__device__ __forceinline__ void dt_final_body(const Mesh &m, const DevWords &w, const double *__restrict__ ringrate,
+                                              const double *__restrict__ ringshear) {
 #pragma clang fp contract(off)
   __shared__ double red[2 * MAXW];
   constexpr int U = 8; // loads in flight per thread
@@ -379,6 +385,38 @@ __global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const dou
     }
     *w.dt = dt;
   }
+}
+__global__ __launch_bounds__(1024) void k_dt_final(Mesh m, DevWords w, const double *__restrict__ ringrate,
+                                                   const double *__restrict__ ringshear) {
+  dt_final_body(m, w, ringrate, ringshear);
+}
+
+// multi-mesh forms (ManyGrid)
+template <typename R>
+struct CflArgs {
+  Mesh m;
+  StateT<R> s;
+  double *v0, *ringrate, *ringshear;
+  int *err;
+  unsigned nb;
+};
+template <int M, typename R>
+__global__ __launch_bounds__(256) void k_cfl_ring_many(const void *args, const uint2 *tab) {
+  const uint2 t = many_block(tab);
+  if (t.x == MANY_NONE) return;
+  const CflArgs<R> a = many_args<CflArgs<R>>(args, t.x);
+  cfl_ring_body<M, R, 256>(a.m, a.s, 1, a.v0, a.ringrate, a.ringshear, a.err, t.y, a.nb);
+}
+struct DtArgs {
+  Mesh m;
+  DevWords w;
+  const double *ringrate, *ringshear;
+};
+__global__ __launch_bounds__(1024) void k_dt_final_many(const void *args, const uint2 *tab) {
+  const uint2 t = many_block(tab);
+  if (t.x == MANY_NONE) return;
+  const DtArgs a = many_args<DtArgs>(args, t.x);
+  dt_final_body(a.m, a.w, a.ringrate, a.ringshear);
 }
 
 // The split of Eq. 29, one thread per ring, with dt given by value or, if
@@ -468,5 +506,53 @@ void launch_split(Launch &L, const Mesh &m, const double *v0, double dt, int32_t
   k_split<<<(m.nring + 255) / 256, 256, 0, L.s>>>(m, v0, nullptr, dt, N, xi);
   prof_end(L, K_SPLIT);
 }
+
+template <typename R>
+size_t cfl_args_bytes() { return sizeof(CflArgs<R>); }
+
+template <typename R>
+unsigned cfl_args(const Mesh &m, const StateT<R> &s, double *v0, double *ringrate, double *ringshear, int *err,
+                  void *dst) {
+  *(CflArgs<R> *)dst = CflArgs<R>{m, s, v0, ringrate, ringshear, err, (unsigned)m.nring};
+  return (unsigned)m.nring;
+}
+
+// rings of at most 1792 zones: 256 threads of M = ceil(nxmax / 256) zones for
+// every mesh of the launch (a shorter ring leaves some of them idle)
+template <typename R>
+void launch_cfl_many(Launch &L, const ManyGrid &g, int nxmax) {
+  prof_begin(L, K_CFL);
+  const size_t sh = (size_t)nxmax * sizeof(double);
+  switch ((nxmax + 255) / 256) {
+  case 1: k_cfl_ring_many<1, R><<<g.nblk, 256, sh, L.s>>>(g.args, g.tab); break;
+  case 2: k_cfl_ring_many<2, R><<<g.nblk, 256, sh, L.s>>>(g.args, g.tab); break;
+  case 3: k_cfl_ring_many<3, R><<<g.nblk, 256, sh, L.s>>>(g.args, g.tab); break;
+  case 4: k_cfl_ring_many<4, R><<<g.nblk, 256, sh, L.s>>>(g.args, g.tab); break;
+  case 5: k_cfl_ring_many<5, R><<<g.nblk, 256, sh, L.s>>>(g.args, g.tab); break;
+  case 6: k_cfl_ring_many<6, R><<<g.nblk, 256, sh, L.s>>>(g.args, g.tab); break;
+  default: k_cfl_ring_many<7, R><<<g.nblk, 256, sh, L.s>>>(g.args, g.tab); break;
+  }
+  prof_end(L, K_CFL);
+}
+
+size_t dt_final_args_bytes() { return sizeof(DtArgs); }
+
+unsigned dt_final_args(const Mesh &m, const DevWords &w, const double *ringrate, const double *ringshear, void *dst) {
+  *(DtArgs *)dst = DtArgs{m, w, ringrate, ringshear};
+  return 1;
+}
+
+void launch_dt_final_many(Launch &L, const ManyGrid &g) {
+  prof_begin(L, K_DT_FINAL);
+  k_dt_final_many<<<g.nblk, 1024, 0, L.s>>>(g.args, g.tab);
+  prof_end(L, K_DT_FINAL);
+}
+
+template unsigned cfl_args<double>(const Mesh &, const StateT<double> &, double *, double *, double *, int *, void *);
+template unsigned cfl_args<float>(const Mesh &, const StateT<float> &, double *, double *, double *, int *, void *);
+template size_t cfl_args_bytes<double>();
+template size_t cfl_args_bytes<float>();
+template void launch_cfl_many<double>(Launch &, const ManyGrid &, int);
+template void launch_cfl_many<float>(Launch &, const ManyGrid &, int);
 
 } // namespace fargo

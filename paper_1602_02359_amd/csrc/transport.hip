@@ -160,12 +160,12 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
 // Quantities: Pi-_x, Pi+_x, Pi-_y, Pi+_y [, Pi-_z, Pi+_z] [, e].
 // ------------------------------------------------------------------------
 template <typename F, int NQ, bool D3, bool ADI>
-__global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ rho, const F *__restrict__ vx,
+__device__ __forceinline__ void sweep_y_body(Mesh m, const F *__restrict__ rho, const F *__restrict__ vx,
                                                  const F *__restrict__ vy, const F *__restrict__ vz,
                                                  const F *__restrict__ e, TSetT<F> out,
-                                                 const double *__restrict__ dtp, int nchunk) {
+                                                 const double *__restrict__ dtp, int nchunk, unsigned bid_, unsigned nbk_) {
   const int nrows = D3 ? m.nz + 4 : 1, kbase = D3 ? m.k0 - 2 : 0;
-  unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
+  unsigned Lb = xcd_remap(bid_, nbk_);
   int kr = (int)(Lb % (unsigned)nrows);
   unsigned rest = Lb / (unsigned)nrows;
   int ch = (int)(rest % (unsigned)nchunk), ib = (int)(rest / (unsigned)nchunk);
@@ -237,6 +237,13 @@ __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ r
   };
   auto dl = [&](int f) { return (F)m.bg(BG_DLY, f, k); };
   column_sweep<F, NQ, false, DEV, Raw>(a0, a1, dt, raw, derive, Tof, geo, st, dl);
+}
+template <typename F, int NQ, bool D3, bool ADI>
+__global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ rho, const F *__restrict__ vx,
+                                                 const F *__restrict__ vy, const F *__restrict__ vz,
+                                                 const F *__restrict__ e, TSetT<F> out,
+                                                 const double *__restrict__ dtp, int nchunk) {
+  sweep_y_body<F, NQ, D3, ADI>(m, rho, vx, vy, vz, e, out, dtp, nchunk, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------------
@@ -725,11 +732,11 @@ __device__ inline void ring_update(const RingLane<F> &L, const RingConst<F> &C, 
 
 // X transport of every active ring (2D meshes, where there is no Z sweep).
 template <typename F, int NQ>
-__global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__ vx2, TSetT<F> T, TSetT<F> Tout,
+__device__ __forceinline__ void ring_x_body(Mesh m, const F *__restrict__ vx2, TSetT<F> T, TSetT<F> Tout,
                                                 StateT<F> s, const double *__restrict__ v0,
-                                                const double *__restrict__ dtp, int nseg) {
+                                                const double *__restrict__ dtp, int nseg, unsigned bid_, unsigned nbk_) {
   constexpr int M = RingShape<F>::M;
-  const unsigned blk = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned blk = xcd_remap(bid_, nbk_);
   const int lane = threadIdx.x & (WAVE - 1);
   // wave-uniform (readfirstlane), so that the ring's constants come through
   // scalar loads
@@ -747,6 +754,12 @@ __global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__
 #pragma unroll
   for (int t = 0; t < NQ; t++) L.load(T.q[ring_qorder<NQ>(t)] + base, Qall[t]);
   ring_update<F, NQ>(L, C, base, Ra, w, Qall, Tout, T.a[T_E] != nullptr, s);
+}
+template <typename F, int NQ>
+__global__ __launch_bounds__(256, 3) void k_ring_x(Mesh m, const F *__restrict__ vx2, TSetT<F> T, TSetT<F> Tout,
+                                                StateT<F> s, const double *__restrict__ v0,
+                                                const double *__restrict__ dtp, int nseg) {
+  ring_x_body<F, NQ>(m, vx2, T, Tout, s, v0, dtp, nseg, blockIdx.x, gridDim.x);
 }
 
 // Z sweep and X transport fused (3D meshes).  A wave owns one segment of the
@@ -916,8 +929,8 @@ __global__ __launch_bounds__(256, 3) void k_zx(Mesh m, const F *__restrict__ vx2
 // 12d along Y and Z on the owned faces (Eq. 18 with Tab. "momenta").
 // ------------------------------------------------------------------------
 template <typename F>
-__global__ __launch_bounds__(256) void k_vel(Mesh m, StateT<F> s, TSetT<F> T) {
-  unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void vel_body(Mesh m, StateT<F> s, TSetT<F> T, unsigned bid_, unsigned nbk_) {
+  unsigned Lb = xcd_remap(bid_, nbk_);
   int kk = (int)(Lb % (unsigned)m.nz);
   unsigned rest = Lb / (unsigned)m.nz;
   int jj = (int)(rest % (unsigned)m.ny), ib = (int)(rest / (unsigned)m.ny);
@@ -946,6 +959,10 @@ __global__ __launch_bounds__(256) void k_vel(Mesh m, StateT<F> s, TSetT<F> T) {
     F v = (pz + mz) / (rz + rc);
     s.vz[c] = m.geo == FARGO_SPHERICAL ? v / (F)m.g.ymed(j) : v;
   }
+}
+template <typename F>
+__global__ __launch_bounds__(256) void k_vel(Mesh m, StateT<F> s, TSetT<F> T) {
+  vel_body<F>(m, s, T, blockIdx.x, gridDim.x);
 }
 
 // The zones of a direction split into the fewest chunks of at most m.chunk
@@ -1040,9 +1057,9 @@ void launch_zx(Launch &L, const Mesh &m0, const F *vx2, const F *vz, const TSetT
 // The same with two consecutive zones per thread (16-byte loads and stores
 // in FP64); rows of an even number of zones.
 template <typename F>
-__global__ __launch_bounds__(256) void k_vel2(Mesh m, StateT<F> s, TSetT<F> T) {
+__device__ __forceinline__ void vel2_body(Mesh m, StateT<F> s, TSetT<F> T, unsigned bid_, unsigned nbk_) {
   using V2 = typename std::conditional<sizeof(F) == 8, double2, float2>::type;
-  unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
+  unsigned Lb = xcd_remap(bid_, nbk_);
   int kk = (int)(Lb % (unsigned)m.nz);
   unsigned rest = Lb / (unsigned)m.nz;
   int jj = (int)(rest % (unsigned)m.ny), ib = (int)(rest / (unsigned)m.ny);
@@ -1077,6 +1094,60 @@ __global__ __launch_bounds__(256) void k_vel2(Mesh m, StateT<F> s, TSetT<F> T) {
     *reinterpret_cast<V2 *>(s.vz + c) = v;
   }
 }
+template <typename F>
+__global__ __launch_bounds__(256) void k_vel2(Mesh m, StateT<F> s, TSetT<F> T) {
+  vel2_body<F>(m, s, T, blockIdx.x, gridDim.x);
+}
+
+// multi-mesh forms (ManyGrid): the sweep and 12d in blocks of one wave
+template <typename F>
+struct SweepYArgs {
+  Mesh m; // with the balanced chunk length
+  const F *rho, *vx, *vy, *vz, *e;
+  TSetT<F> out;
+  const double *dt;
+  int nchunk;
+  unsigned nb;
+};
+template <typename F, int NQ, bool D3, bool ADI>
+__global__ __launch_bounds__(256) void k_sweep_y_many(const void *args, const uint2 *tab) {
+  const uint2 t = many_block(tab);
+  if (t.x == MANY_NONE) return;
+  const SweepYArgs<F> a = many_args<SweepYArgs<F>>(args, t.x);
+  sweep_y_body<F, NQ, D3, ADI>(a.m, a.rho, a.vx, a.vy, a.vz, a.e, a.out, a.dt, a.nchunk, t.y, a.nb);
+}
+template <typename F>
+struct RingArgs {
+  Mesh m;
+  const F *vx2;
+  TSetT<F> T, Tout;
+  StateT<F> s;
+  const double *v0, *dt;
+  int nseg;
+  unsigned nb;
+};
+template <typename F, int NQ>
+__global__ __launch_bounds__(256, 3) void k_ring_x_many(const void *args, const uint2 *tab) {
+  const uint2 t = many_block(tab);
+  if (t.x == MANY_NONE) return;
+  const RingArgs<F> a = many_args<RingArgs<F>>(args, t.x);
+  ring_x_body<F, NQ>(a.m, a.vx2, a.T, a.Tout, a.s, a.v0, a.dt, a.nseg, t.y, a.nb);
+}
+template <typename F>
+struct VelArgs {
+  Mesh m;
+  StateT<F> s;
+  TSetT<F> T;
+  unsigned nb;
+};
+template <typename F>
+__global__ __launch_bounds__(256) void k_vel_many(const void *args, const uint2 *tab) {
+  const uint2 t = many_block(tab);
+  if (t.x == MANY_NONE) return;
+  const VelArgs<F> a = many_args<VelArgs<F>>(args, t.x);
+  if (a.m.nx % 2 == 0) vel2_body<F>(a.m, a.s, a.T, t.y, a.nb); // two zones per thread
+  else vel_body<F>(a.m, a.s, a.T, t.y, a.nb);
+}
 
 template <typename F>
 void launch_vel(Launch &L, const Mesh &m, const StateT<F> &s, const TSetT<F> &T) {
@@ -1093,6 +1164,85 @@ void launch_vel(Launch &L, const Mesh &m, const StateT<F> &s, const TSetT<F> &T)
   }
   prof_end(L, K_VEL);
 }
+
+// multi-mesh launches (ManyGrid) on 2D meshes: blocks of one wave for the
+// column sweep and 12d, so that narrow meshes leave few threads idle
+constexpr int MANY_BS = 64;
+
+template <typename F>
+size_t sweep_y_args_bytes() { return sizeof(SweepYArgs<F>); }
+
+template <typename F>
+unsigned sweep_y_args(const Mesh &m0, const StateT<F> &s, const TSetT<F> &out, const double *dt, void *dst) {
+  int nchunk;
+  const Mesh m = balanced(m0, m0.ny, nchunk);
+  const unsigned nb = (unsigned)((m.nx + MANY_BS - 1) / MANY_BS) * (unsigned)nchunk;
+  *(SweepYArgs<F> *)dst = SweepYArgs<F>{m, s.rho, s.vx, s.vy, s.vz, s.e, out, dt, nchunk, nb};
+  return nb;
+}
+
+template <typename F>
+void launch_sweep_y_many(Launch &L, const Mesh &m0, const ManyGrid &g) {
+  prof_begin(L, K_SWEEP_Y);
+  if (m0.eos == FARGO_ADIABATIC) k_sweep_y_many<F, 5, false, true><<<g.nblk, MANY_BS, 0, L.s>>>(g.args, g.tab);
+  else k_sweep_y_many<F, 4, false, false><<<g.nblk, MANY_BS, 0, L.s>>>(g.args, g.tab);
+  prof_end(L, K_SWEEP_Y);
+}
+
+template <typename F>
+size_t ring_x_args_bytes() { return sizeof(RingArgs<F>); }
+
+template <typename F>
+unsigned ring_x_args(const Mesh &m, const F *vx2, const TSetT<F> &T, const TSetT<F> &Tout, const StateT<F> &s,
+                     const double *v0, const double *dt, void *dst) {
+  constexpr int U = (WAVE - RingShape<F>::HLL - RingShape<F>::HRL) * RingShape<F>::M;
+  const int nseg = (m.nx + U - 1) / U;
+  const unsigned nb = (unsigned)(((long)m.nring * nseg + 3) / 4);
+  *(RingArgs<F> *)dst = RingArgs<F>{m, vx2, T, Tout, s, v0, dt, nseg, nb};
+  return nb;
+}
+
+template <typename F>
+void launch_ring_x_many(Launch &L, int nq, const ManyGrid &g) {
+  prof_begin(L, K_RING_X);
+  if (nq == 5) k_ring_x_many<F, 5><<<g.nblk, 256, 0, L.s>>>(g.args, g.tab);
+  else k_ring_x_many<F, 4><<<g.nblk, 256, 0, L.s>>>(g.args, g.tab);
+  prof_end(L, K_RING_X);
+}
+
+template <typename F>
+size_t vel_args_bytes() { return sizeof(VelArgs<F>); }
+
+// two zones per thread on rows of an even number of zones, else one
+template <typename F>
+unsigned vel_args(const Mesh &m, const StateT<F> &s, const TSetT<F> &T, void *dst) {
+  const int w = m.nx % 2 == 0 ? m.nx / 2 : m.nx;
+  const unsigned nb = (unsigned)((w + MANY_BS - 1) / MANY_BS) * (unsigned)m.ny * (unsigned)m.nz;
+  *(VelArgs<F> *)dst = VelArgs<F>{m, s, T, nb};
+  return nb;
+}
+
+template <typename F>
+void launch_vel_many(Launch &L, const ManyGrid &g) {
+  prof_begin(L, K_VEL);
+  k_vel_many<F><<<g.nblk, MANY_BS, 0, L.s>>>(g.args, g.tab);
+  prof_end(L, K_VEL);
+}
+
+#define FARGO_TRANSPORT_MANY(F)                                                                                     \
+  template size_t sweep_y_args_bytes<F>();                                                                         \
+  template unsigned sweep_y_args<F>(const Mesh &, const StateT<F> &, const TSetT<F> &, const double *, void *);    \
+  template void launch_sweep_y_many<F>(Launch &, const Mesh &, const ManyGrid &);                                  \
+  template size_t ring_x_args_bytes<F>();                                                                          \
+  template unsigned ring_x_args<F>(const Mesh &, const F *, const TSetT<F> &, const TSetT<F> &, const StateT<F> &, \
+                                   const double *, const double *, void *);                                        \
+  template void launch_ring_x_many<F>(Launch &, int, const ManyGrid &);                                            \
+  template size_t vel_args_bytes<F>();                                                                             \
+  template unsigned vel_args<F>(const Mesh &, const StateT<F> &, const TSetT<F> &, void *);                        \
+  template void launch_vel_many<F>(Launch &, const ManyGrid &);
+FARGO_TRANSPORT_MANY(double)
+FARGO_TRANSPORT_MANY(float)
+#undef FARGO_TRANSPORT_MANY
 
 #define FARGO_TRANSPORT_INST(F)                                                                                    \
   template void launch_sweep_y<F>(Launch &, const Mesh &, const StateT<F> &, const TSetT<F> &, const double *);   \

@@ -50,11 +50,11 @@ struct Visc {
 };
 
 template <typename F>
-__global__ __launch_bounds__(256) void k_visc(Visc<F> V, const double *__restrict__ dtp, F *__restrict__ vx3,
-                                              F *__restrict__ vy3) {
+__device__ __forceinline__ void visc_body(Visc<F> V, const double *__restrict__ dtp, F *__restrict__ vx3,
+                                              F *__restrict__ vy3, unsigned bid_, unsigned nbk_) {
   const Mesh &m = V.m;
   const int nib = (m.nx + blockDim.x - 1) / blockDim.x;
-  const unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned Lb = xcd_remap(bid_, nbk_);
   const int j = (int)(Lb / (unsigned)nib);
   const int i = (int)(Lb % (unsigned)nib) * (int)blockDim.x + (int)threadIdx.x;
   if (i >= m.nx || j >= m.nyg) return;
@@ -91,6 +91,27 @@ __global__ __launch_bounds__(256) void k_visc(Visc<F> V, const double *__restric
     vy3[c] = V.vy[c];
   }
 }
+template <typename F>
+__global__ __launch_bounds__(256) void k_visc(Visc<F> V, const double *__restrict__ dtp, F *__restrict__ vx3,
+                                              F *__restrict__ vy3) {
+  visc_body<F>(V, dtp, vx3, vy3, blockIdx.x, gridDim.x);
+}
+
+// multi-mesh form (ManyGrid)
+template <typename F>
+struct ViscArgs {
+  Visc<F> V;
+  const double *dt;
+  F *vx3, *vy3;
+  unsigned nb;
+};
+template <typename F>
+__global__ __launch_bounds__(256) void k_visc_many(const void *args, const uint2 *tab) {
+  const uint2 t = many_block(tab);
+  if (t.x == MANY_NONE) return;
+  const ViscArgs<F> a = many_args<ViscArgs<F>>(args, t.x);
+  visc_body<F>(a.V, a.dt, a.vx3, a.vy3, t.y, a.nb);
+}
 
 } // namespace
 
@@ -108,5 +129,33 @@ template void launch_visc<double>(Launch &, const Mesh &, const StateT<double> &
                                   double *, double *, const double *);
 template void launch_visc<float>(Launch &, const Mesh &, const StateT<float> &, const float *, const float *,
                                  float *, float *, const double *);
+
+template <typename F>
+size_t visc_args_bytes() { return sizeof(ViscArgs<F>); }
+
+template <typename F>
+unsigned visc_args(const Mesh &m, const StateT<F> &s, const F *vx2, const F *vy2, F *vx3, F *vy3, const double *dt,
+                   void *dst) {
+  const int bs = 256, nib = (m.nx + bs - 1) / bs;
+  const unsigned nb = (unsigned)nib * (unsigned)m.nyg;
+  *(ViscArgs<F> *)dst = ViscArgs<F>{Visc<F>{m, s, vx2, vy2}, dt, vx3, vy3, nb};
+  return nb;
+}
+
+template <typename F>
+void launch_visc_many(Launch &L, const ManyGrid &g) {
+  prof_begin(L, K_VISC);
+  k_visc_many<F><<<g.nblk, 256, 0, L.s>>>(g.args, g.tab);
+  prof_end(L, K_VISC);
+}
+
+#define FARGO_VISC_MANY(F)                                                                                          \
+  template size_t visc_args_bytes<F>();                                                                            \
+  template unsigned visc_args<F>(const Mesh &, const StateT<F> &, const F *, const F *, F *, F *, const double *,  \
+                                 void *);                                                                          \
+  template void launch_visc_many<F>(Launch &, const ManyGrid &);
+FARGO_VISC_MANY(double)
+FARGO_VISC_MANY(float)
+#undef FARGO_VISC_MANY
 
 } // namespace fargo

@@ -79,6 +79,7 @@ _lib.fargo_batch_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(fargo_state
 _lib.fargo_batch_step.argtypes = [C.c_void_p, C.c_void_p]
 _lib.fargo_batch_tune.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int32), C.c_int, C.c_int,
                                   C.c_void_p, C.POINTER(C.c_int32)]
+_lib.fargo_batch_chunks.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int]
 _lib.fargo_batch_destroy.argtypes = [C.c_void_p]
 _lib.fargo_batch_destroy.restype = None
 
@@ -112,7 +113,7 @@ _lib.fargo_lfc_target.argtypes = [C.c_void_p, _S, _S, C.c_void_p, C.c_void_p]
 EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_workspace_bytes", "fargo_init",
             "fargo_set_vx_background", "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
             "fargo_conserved_sums", "fargo_conserved_sums_noalloc", "fargo_hbm_copy", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
-            "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_destroy",
+            "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_chunks", "fargo_batch_destroy",
             "fargo_lfc_create", "fargo_lfc_destroy", "fargo_lfc_set_params", "fargo_lfc_get_params",
             "fargo_lfc_get_grad", "fargo_lfc_forward", "fargo_lfc_forward_batch", "fargo_lfc_train_step",
             "fargo_lfc_train_batch", "fargo_lfc_apply",
@@ -328,8 +329,10 @@ def fargo_hbm_copy(src: torch.Tensor, dst: torch.Tensor, blocks: int, stream=Non
 
 class Batch:
     """Many Solvers advanced together: one captured hipGraph per step
-    (fargo_batch_*).  The solvers must stay alive and keep their state tensors
-    while the batch exists."""
+    (fargo_batch_*).  lanes >= 1: a graph of every solver's own step over that
+    many streams; lanes = 0: the fused form, each kernel of the step launched
+    once over all solvers.  The solvers must stay alive and keep their state
+    tensors while the batch exists."""
 
     def __init__(self, solvers, lanes: int = 8):
         self.solvers = list(solvers)
@@ -355,6 +358,11 @@ class Batch:
         _check(_lib.fargo_batch_tune(self._b, la, len(lanes), ch, len(chunks), int(steps), _stream(stream), best),
                "fargo_batch_tune")
         return int(best[0]), int(best[1])
+
+    def chunks(self):
+        out = (C.c_int32 * len(self.solvers))()
+        _check(_lib.fargo_batch_chunks(self._b, out, len(self.solvers)), "fargo_batch_chunks")
+        return [int(v) for v in out]
 
 
 class LFC:

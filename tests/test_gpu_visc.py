@@ -109,12 +109,17 @@ def _small_batch(count, precision):
     return probs, [_solver(p, precision=precision) for p in probs]
 
 
+@pytest.mark.parametrize("lanes", [3, 0])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batch_step_equals_individual_steps(precision):
+def test_batch_step_equals_individual_steps(precision, lanes):
+    """A graph of the disks' own steps over three streams, and the fused form
+    (each kernel once over all disks: lanes = 0), against every disk's own
+    steps, bit for bit (odd and even ring lengths)."""
     from paper_1602_02359_amd import fargo as F
     probs, batch_solvers = _small_batch(7, precision)
     _, own = _small_batch(7, precision)
-    b = F.Batch(batch_solvers, lanes=3)
+    assert len({p.params["nx"] % 2 for p in probs}) == 2
+    b = F.Batch(batch_solvers, lanes=lanes)
     for _ in range(4):
         b.fargo_batch_step()
         for s in own:
@@ -129,7 +134,8 @@ def test_batch_step_equals_individual_steps(precision):
     del b
 
 
-def test_batch_fp64_matches_oracle():
+@pytest.mark.parametrize("lanes", [3, 0])
+def test_batch_fp64_matches_oracle(lanes):
     """Six uneven viscous disks advanced by one captured graph per step
     (each disk with its own device time step), every disk against the oracle
     after each of two steps: the time step within the bound of the two codes'
@@ -141,7 +147,7 @@ def test_batch_fp64_matches_oracle():
     from paper_1602_02359_amd import fargo as F
     probs, solvers = _small_batch(6, "fp64")
     refs = [p.copy_fields() for p in probs]
-    b = F.Batch(solvers, lanes=3)
+    b = F.Batch(solvers, lanes=lanes)
     for n in range(2):
         b.fargo_batch_step()
         for p, sv, ref in zip(probs, solvers, refs):
@@ -185,4 +191,53 @@ def test_batch_tune_keeps_states_and_picks_a_candidate():
         ga, go = a.download(), o.download()
         for k in ("rho", "vx", "vy"):
             assert np.array_equal(ga[k], go[k]), k
+    del b
+
+
+def test_fused_batch_tunes_per_size_class():
+    """The fused form's autotuner: a sweep chunk per size class of disks
+    (floor(log2 ny)) from the candidates, the states left as found, and the
+    tuned batch still steps like the disks' own steps."""
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    probs, solvers = _small_batch(6, "fp32")
+    b = F.Batch(solvers, lanes=0)
+    before = [s.download() for s in solvers]
+    lanes, chunk = b.fargo_batch_tune(lanes=(1,), chunks=(8, 64), steps=2)
+    assert lanes == 0 and chunk in (8, 64)
+    ch = b.chunks()
+    assert all(c in (8, 64) for c in ch)
+    cls = [int(np.floor(np.log2(p.params["ny"]))) for p in probs]
+    for c1, k1 in zip(ch, cls):
+        for c2, k2 in zip(ch, cls):
+            if k1 == k2:
+                assert c1 == c2
+    after = [s.download() for s in solvers]
+    for x, y in zip(before, after):
+        for k in ("rho", "vx", "vy"):
+            assert np.array_equal(x[k], y[k]), k
+    _, own = _small_batch(6, "fp32")
+    for _ in range(2):
+        b.fargo_batch_step()
+        for o in own:
+            o.fargo_step(0.0)
+    torch.cuda.synchronize()
+    for a, o in zip(solvers, own):
+        ga, go = a.download(), o.download()
+        for k in ("rho", "vx", "vy"):
+            assert np.array_equal(ga[k], go[k]), k
+    del b
+
+
+def test_fused_batch_refuses_mixed_configurations():
+    from paper_1602_02359_amd import fargo as F
+    probs = W.disk_batch(count=2, nr_range=(16, 24), seed=6)
+    mixed = [_solver(probs[0], precision="fp64"), _solver(probs[1], precision="fp32")]
+    with pytest.raises(F.FargoError) as e:
+        F.Batch(mixed, lanes=0)
+    assert e.value.code == -6
+    b = F.Batch(mixed, lanes=2)  # the graph of the disks' own steps takes them
+    b.fargo_batch_step()
+    for s in mixed:
+        s.fargo_check()
     del b
