@@ -292,7 +292,6 @@ def batch_variant(steps, warmup, tune=True, err_steps=100):
         for p, c in zip(probs, ch):
             by_class.setdefault(int(math.floor(math.log2(p.params["ny"]))), c)
         out[prec + "_fused"] = {"value": cells * steps / el, "ms_per_step": 1e3 * el / steps,
-                                "launches_per_step": 8,
                                 "chunk_by_size_class": {"ny in [%d, %d)" % (2 ** k, 2 ** (k + 1)): c
                                                         for k, c in sorted(by_class.items())}}
         print("  %s: disk by disk %.3e, batched graph %.3e (tuned %s), fused %.3e cell-updates/s" % (

@@ -835,6 +835,7 @@ struct fargo_batch {
   // fused mode: the launches' argument blocks and tables in one allocation
   void *fmem = nullptr;
   ManyGrid g[8] = {};
+  ManyGrid gcfl[8] = {}; // the time-step pass by zones per thread (ceil(nx / 256), 1..7)
   int nxmax = 0;
   std::vector<int> chunk; // per disk (the sweep's chunk length, tuned per size class)
 };
@@ -940,8 +941,9 @@ struct ManyHost {
 template <typename F>
 int fused_build(fargo_batch *b) {
   const unsigned n = (unsigned)b->ctx.size();
-  ManyHost H[FU_N];
+  ManyHost H[FU_N], HC[8];
   // argument blocks packed at their exact size: the kernels index them so
+  for (auto &h : HC) h.asz = cfl_args_bytes<F>();
   H[FU_CFL].asz = cfl_args_bytes<F>();
   H[FU_DT].asz = dt_final_args_bytes();
   H[FU_SRC].asz = H[FU_SRCG].asz = source_args_bytes<F>();
@@ -958,7 +960,10 @@ int fused_build(fargo_batch *b) {
     const StateT<F> S = state_of<F>(c, &b->st[d]);
     const double *dtp = c->w.dt;
     F *v2[4] = {(F *)c->v2[0], (F *)c->v2[1], (F *)c->v2[2], (F *)c->v2[3]};
-    H[FU_CFL].blocks(d, cfl_args<F>(m, S, c->v0, c->ringrate, c->ringshear, c->w.err, H[FU_CFL].slot(d)));
+    // the time-step pass in one launch per class of ring length (zones per
+    // thread), each with its own argument array indexed by disk
+    ManyHost &hc = HC[(m.nx + 255) / 256];
+    hc.blocks(d, cfl_args<F>(m, S, c->v0, c->ringrate, c->ringshear, c->w.err, hc.slot(d)));
     H[FU_DT].blocks(d, dt_final_args(m, c->w, c->ringrate, c->ringshear, H[FU_DT].slot(d)));
     H[FU_SRC].blocks(d, source_args<F>(m, S, dtp, v2[0], v2[1], v2[2], v2[3], H[FU_SRC].slot(d)));
     H[FU_SRCG].blocks(d, source_ghosts_args<F>(m, S, v2[0], v2[1], v2[2], v2[3], H[FU_SRCG].slot(d)));
@@ -979,22 +984,31 @@ int fused_build(fargo_batch *b) {
   }
   size_t total = 0;
   for (auto &h : H) total += al(h.args.size()) + al(h.tab.size() * sizeof(uint2));
+  for (auto &h : HC) total += al(h.args.size()) + al(h.tab.size() * sizeof(uint2));
   if (b->fmem) (void)hipFree(b->fmem);
   b->fmem = nullptr;
   if (hipMalloc(&b->fmem, total) != hipSuccess) return FARGO_ENOMEM;
   char *base = (char *)b->fmem;
   size_t o = 0;
-  for (int k = 0; k < FU_N; k++) {
-    ManyHost &h = H[k];
-    b->g[k] = ManyGrid{nullptr, nullptr, (unsigned)h.tab.size()};
-    if (h.tab.empty()) continue;
+  auto upload = [&](ManyHost &h, ManyGrid &g) {
+    g = ManyGrid{nullptr, nullptr, (unsigned)h.tab.size()};
+    if (h.tab.empty()) return FARGO_OK;
     if (hipMemcpy(base + o, h.args.data(), h.args.size(), hipMemcpyHostToDevice) != hipSuccess) return FARGO_EHIP;
-    b->g[k].args = base + o;
+    g.args = base + o;
     o += al(h.args.size());
     if (hipMemcpy(base + o, h.tab.data(), h.tab.size() * sizeof(uint2), hipMemcpyHostToDevice) != hipSuccess)
       return FARGO_EHIP;
-    b->g[k].tab = (const uint2 *)(base + o);
+    g.tab = (const uint2 *)(base + o);
     o += al(h.tab.size() * sizeof(uint2));
+    return FARGO_OK;
+  };
+  for (int k = 0; k < FU_N; k++) {
+    const int rc = upload(H[k], b->g[k]);
+    if (rc) return rc;
+  }
+  for (int k = 0; k < 8; k++) {
+    const int rc = upload(HC[k], b->gcfl[k]);
+    if (rc) return rc;
   }
   return FARGO_OK;
 }
@@ -1003,7 +1017,8 @@ int fused_build(fargo_batch *b) {
 template <typename F>
 void fused_step(fargo_batch *b, Launch &L) {
   const Mesh &m0 = b->ctx[0]->m;
-  launch_cfl_many<F>(L, b->g[FU_CFL], b->nxmax);                                  // boxes 3, 4, 6
+  for (int k = 1; k < 8; k++)                                                      // boxes 3, 4, 6
+    if (b->gcfl[k].nblk) launch_cfl_many<F>(L, b->gcfl[k], 256 * k);
   launch_dt_final_many(L, b->g[FU_DT]);
   launch_source_many<F>(L, m0, b->g[FU_SRC], b->g[FU_SRCG]);                        // boxes 7a-7c
   if (m0.visc) launch_visc_many<F>(L, b->g[FU_VISC]);                              // box 7d

@@ -61,6 +61,22 @@ struct Lds {
   F IY[2][SY][TX];     // 1 / ((rho_j + rho_{j-1}) h_y) on those faces
   double DX[2][TY];    // 1 / dX of the tile rows, for the halo X faces
 };
+// a 2D mesh has a single plane: one buffer of each (about half the LDS, so
+// that two workgroups share a compute unit)
+template <typename F>
+struct Lds2 {
+  F R[1][SY][SX];
+  F P[1][SY][SX];
+  double Ph[1][SY][SX];
+  F VX[1][SY][SX];
+  F VY[1][SY][TX];
+  F VT[1][SY][TX];
+  F AX[1][TY][SX];
+  F IX[1][TY][SX];
+  F AY[1][SY][TX];
+  F IY[1][SY][TX];
+  double DX[1][TY];
+};
 
 // An explicit register move.  The march keeps a window of plane records in
 // registers and rotates it once per plane; moving the newest record out of its
@@ -102,7 +118,7 @@ template <typename F, bool D3, int GEO, bool ADI>
 __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *__restrict__ dtp,
                                                   F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
                                                   F *__restrict__ e2, int nbx, int nby, unsigned bid_, unsigned nbk_) {
-  __shared__ Lds<F> L;
+  __shared__ typename std::conditional<D3, Lds<F>, Lds2<F>>::type L;
   // the row is the wave index: uniform, so that geometric factors of the
   // row come through scalar loads, which do not stall behind the prefetches
   const int tid = threadIdx.x, r = __builtin_amdgcn_readfirstlane(tid >> 6), c = tid & 63;
@@ -378,7 +394,7 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
     }
   };
 
-  if (!D3) {
+  if constexpr (!D3) {
     // a single plane: S, F, Z in turn
     Zv<F> z0{};
     Halo hv{};
@@ -393,9 +409,7 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
     faces(0, 0, 0);
     __syncthreads();
     if (act) zones(0, 0, 0, ZPart{}, e_old);
-    return;
-  }
-
+  } else {
   // ---- 3D march over the active planes k0 .. kn-1
   const int k0 = m.k0, kn = m.kn;
   // Z window of the thread's column at the top of interval kk:
@@ -496,9 +510,10 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
     sb = sb1;
     rb = rb1;
   }
+  }
 }
 template <typename F, bool D3, int GEO, bool ADI>
-__global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
+__global__ __launch_bounds__(NT, sizeof(F) == 8 && D3 ? 2 : 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
                                                   F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
                                                   F *__restrict__ e2, int nbx, int nby) {
   source_body<F, D3, GEO, ADI>(m, s, dtp, vx2, vy2, vz2, e2, nbx, nby, blockIdx.x, gridDim.x);
@@ -550,7 +565,7 @@ struct SourceArgs {
   unsigned nb;
 };
 template <typename F, bool D3, int GEO, bool ADI>
-__global__ __launch_bounds__(NT, sizeof(F) == 8 ? 2 : 4) void k_source_many(const void *args, const uint2 *tab) {
+__global__ __launch_bounds__(NT, sizeof(F) == 8 && D3 ? 2 : 4) void k_source_many(const void *args, const uint2 *tab) {
   const uint2 t = many_block(tab);
   if (t.x == MANY_NONE) return;
   const SourceArgs<F> a = many_args<SourceArgs<F>>(args, t.x);

@@ -66,30 +66,31 @@ __device__ __forceinline__ void visc_body(Visc<F> V, const double *__restrict__ 
   }
   const F dt = (F)*dtp, dphi = (F)m.dx;
   const F *rho = V.s.rho;
+  // every stress component the zone's two faces need, each formed once
+  // (the stores come last, so that no load waits behind them)
+  const int im = V.wrapx(i - 1);
+  const bool own_y = j >= m.ylo();
+  F tpp0, trr0, tppw, trrw, tpps = F(0), trrs = F(0);
+  V.diag(i, j, tpp0, trr0);
+  V.diag(im, j, tppw, trrw);
+  if (own_y) V.diag(i, j - 1, tpps, trrs);
+  const F e0 = V.edge(i, j), en = V.edge(i, j + 1);
+  const F ee = own_y ? V.edge(V.wrapx(i + 1), j) : F(0);
   // v_phi on the X face of zone (i, j)
-  {
-    const int im = V.wrapx(i - 1);
-    F tpp0, trr0, tppw, trrw;
-    V.diag(i, j, tpp0, trr0);
-    V.diag(im, j, tppw, trrw);
-    const F a = (F)m.g.ymin(j), b = (F)m.g.ymin(j + 1), r = (F)m.g.ymed(j);
-    const F rho_f = F(0.5) * (rho[c] + rho[V.at(im, j)]);
-    const F div = (b * b * V.edge(i, j + 1) - a * a * V.edge(i, j)) / (r * r * (F)m.g.Ly(j)) + (tpp0 - tppw) / (r * dphi);
-    vx3[c] = V.vx[c] - dt * div / rho_f;
-  }
+  const F a = (F)m.g.ymin(j), b = (F)m.g.ymin(j + 1), r = (F)m.g.ymed(j);
+  const F rx = F(0.5) * (rho[c] + rho[V.at(im, j)]);
+  const F divx = (b * b * en - a * a * e0) / (r * r * (F)m.g.Ly(j)) + (tpp0 - tppw) / (r * dphi);
+  const F vx3c = V.vx[c] - dt * divx / rx;
   // v_r on the Y face of zone (i, j), if the step owns it
-  if (j >= m.ylo()) {
-    F tpp0, trr0, tpps, trrs;
-    V.diag(i, j, tpp0, trr0);
-    V.diag(i, j - 1, tpps, trrs);
-    const F a = (F)m.g.ymin(j);
-    const F rho_f = F(0.5) * (rho[c] + rho[c - (unsigned)m.pitch]);
-    const F div = ((F)m.g.ymed(j) * trr0 - (F)m.g.ymed(j - 1) * trrs) / (a * (F)m.g.hy(j)) +
-                  (V.edge(V.wrapx(i + 1), j) - V.edge(i, j)) / (a * dphi) - F(0.5) * (tpp0 + tpps) / a;
-    vy3[c] = V.vy[c] - dt * div / rho_f;
-  } else {
-    vy3[c] = V.vy[c];
+  F vy3c = V.vy[c];
+  if (own_y) {
+    const F ry = F(0.5) * (rho[c] + rho[c - (unsigned)m.pitch]);
+    const F divy = ((F)m.g.ymed(j) * trr0 - (F)m.g.ymed(j - 1) * trrs) / (a * (F)m.g.hy(j)) +
+                   (ee - e0) / (a * dphi) - F(0.5) * (tpp0 + tpps) / a;
+    vy3c = vy3c - dt * divy / ry;
   }
+  vx3[c] = vx3c;
+  vy3[c] = vy3c;
 }
 template <typename F>
 __global__ __launch_bounds__(256) void k_visc(Visc<F> V, const double *__restrict__ dtp, F *__restrict__ vx3,
