@@ -199,9 +199,9 @@ int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream);
    place, Q_i <- Q_{(i - N) mod nx}, with N = nshift[(k - k0)*ny + (j - j0)]
    read from a device array of ny*nz int32 (k0 = 3 in 3D, 0 in 2D).  The
    field has the state element type of the context.  Ghost rows are not
-   touched.  Bit-exact (a pure permutation).  A ring is staged in LDS: nx
-   times the element size at most 64 KiB (FARGO_EUNSUPPORTED otherwise; the
-   step's own shift has no such limit). */
+   touched.  Bit-exact (a pure permutation).  A ring of at most 64 KiB is
+   staged in LDS; a longer one is shifted out of place through the context's
+   workspace (so calls on one context must not overlap a step). */
 int fargo_shift(fargo_ctx *ctx, void *field, const int32_t *nshift, void *stream);
 
 /* Box 3 and the split of Eq. 29 for a given dt, on active rings: v0 (Eq. 37

@@ -676,10 +676,11 @@ int fargo_step(fargo_ctx *ctx, fargo_state *state, double dt, void *stream) {
 
 int fargo_shift(fargo_ctx *ctx, void *field, const int32_t *nshift, void *stream) {
   if (!ctx || !field || !nshift) return FARGO_EINVAL;
-  if ((size_t)ctx->m.nx * ctx->esize > 65536) return FARGO_EUNSUPPORTED; // the ring is staged in LDS
   Launch L{(hipStream_t)stream, &ctx->prof};
-  if (fp32(ctx)) launch_shift(L, ctx->m, (float *)field, nshift);
-  else launch_shift(L, ctx->m, (double *)field, nshift);
+  // a ring staged in LDS, or (longer rings) out of place through a transport
+  // buffer of the workspace, which holds nothing between steps
+  if (fp32(ctx)) launch_shift(L, ctx->m, (float *)field, nshift, (float *)ctx->TA[T_RHO]);
+  else launch_shift(L, ctx->m, (double *)field, nshift, (double *)ctx->TA[T_RHO]);
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
 

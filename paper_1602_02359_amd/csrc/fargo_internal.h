@@ -349,7 +349,7 @@ template <typename R>
 void launch_vel(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &T);
 // misc
 template <typename R>
-void launch_shift(Launch &L, const Mesh &m, R *field, const int32_t *N);
+void launch_shift(Launch &L, const Mesh &m, R *field, const int32_t *N, R *scratch);
 // Device scratch of the allocation-free sums (a file-scope device array):
 // per-device address lookup, done once per device at context creation with
 // that device current, and the address looked up (NULL before set-up).

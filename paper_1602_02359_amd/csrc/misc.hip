@@ -31,6 +31,31 @@ __global__ __launch_bounds__(256) void k_shift(Mesh m, F *__restrict__ f, const 
   }
 }
 
+// Rings longer than the LDS holds: Eq. 32 out of place into a scratch field
+// (one row of blocks per ring), then the active rings copied back.
+template <typename F>
+__global__ __launch_bounds__(256) void k_shift_out(Mesh m, const F *__restrict__ f, F *__restrict__ t,
+                                                   const int32_t *__restrict__ N, int nib) {
+  const int r = blockIdx.x / nib, ib = blockIdx.x % nib;
+  const int i = ib * 256 + (int)threadIdx.x;
+  if (i >= m.nx) return;
+  const int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny, n = m.nx;
+  int s = N[r] % n;
+  if (s < 0) s += n;
+  int src = i - s;
+  if (src < 0) src += n;
+  const size_t row = m.idx(0, j, k);
+  t[row + i] = f[row + src];
+}
+template <typename F>
+__global__ __launch_bounds__(256) void k_shift_back(Mesh m, F *__restrict__ f, const F *__restrict__ t, int nib) {
+  const int r = blockIdx.x / nib, ib = blockIdx.x % nib;
+  const int i = ib * 256 + (int)threadIdx.x;
+  if (i >= m.nx) return;
+  const size_t o = m.idx(i, m.j0 + r % m.ny, m.k0 + r / m.ny);
+  f[o] = t[o];
+}
+
 // double-double accumulation (error-free two-sum), contraction off
 struct DD {
   double hi, lo;
@@ -144,9 +169,16 @@ void launch_stream_copy(hipStream_t s, const void *src, void *dst, size_t bytes,
 }
 
 template <typename F>
-void launch_shift(Launch &L, const Mesh &m, F *field, const int32_t *N) {
+void launch_shift(Launch &L, const Mesh &m, F *field, const int32_t *N, F *scratch) {
   prof_begin(L, K_SHIFT);
-  k_shift<F><<<m.nring, 256, (size_t)m.nx * sizeof(F), L.s>>>(m, field, N);
+  if ((size_t)m.nx * sizeof(F) <= 65536) {
+    k_shift<F><<<m.nring, 256, (size_t)m.nx * sizeof(F), L.s>>>(m, field, N);
+  } else {
+    const int nib = (m.nx + 255) / 256;
+    const unsigned nb = (unsigned)m.nring * (unsigned)nib;
+    k_shift_out<F><<<nb, 256, 0, L.s>>>(m, field, scratch, N, nib);
+    k_shift_back<F><<<nb, 256, 0, L.s>>>(m, field, scratch, nib);
+  }
   prof_end(L, K_SHIFT);
 }
 
@@ -191,8 +223,8 @@ double *static_scratch(int dev) {
   return scratch_dev[dev];
 }
 
-template void launch_shift<double>(Launch &, const Mesh &, double *, const int32_t *);
-template void launch_shift<float>(Launch &, const Mesh &, float *, const int32_t *);
+template void launch_shift<double>(Launch &, const Mesh &, double *, const int32_t *, double *);
+template void launch_shift<float>(Launch &, const Mesh &, float *, const int32_t *, float *);
 template void launch_sums<double>(Launch &, const Mesh &, const StateT<double> &, double *, double *);
 template void launch_sums<float>(Launch &, const Mesh &, const StateT<float> &, double *, double *);
 

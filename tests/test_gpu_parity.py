@@ -182,17 +182,23 @@ def test_split_ties_and_signs():
     assert oN.ravel().tolist() == [3, -3, 1]
 
 
-@pytest.mark.parametrize("nx", [1, 7, 64, 200, 2048])
-def test_shift_bit_exact(nx):
-    """Eq. 32 as a pure permutation, equal to the oracle's, ghosts untouched."""
+@pytest.mark.parametrize("nx,precision", [(1, "fp64"), (7, "fp64"), (64, "fp64"), (200, "fp64"), (2048, "fp64"),
+                                          (8192, "fp64"), (8193, "fp64"), (20000, "fp64"), (16385, "fp32")])
+def test_shift_bit_exact(nx, precision):
+    """Eq. 32 as a pure permutation, equal to the oracle's, ghosts untouched
+    (rings beyond 64 KiB through the out-of-place form)."""
     import torch
     prob = W.random_problem("cart", nx=nx, ny=5, nz=4, seed=8)
-    s = gpu_solver(prob)
+    if precision == "fp32":  # values representable in FP32, so the oracle's shift compares exactly
+        prob.fields["rho"] = prob.fields["rho"].astype(np.float32).astype(np.float64)
+    from paper_1602_02359_amd import fargo as F
+    s = F.Solver(dict(prob.params, precision=precision))
+    s.upload(prob.fields)
     rng = np.random.default_rng(nx)
     N = rng.integers(-3 * nx, 3 * nx + 1, size=(4, 5)).astype(np.int32)
     f = s.state["rho"]
     s.fargo_shift(f, torch.from_numpy(N.ravel()).to(f.device))
-    got = f[:, :, :nx].cpu().numpy()
+    got = f[:, :, :nx].double().cpu().numpy()
     ref = prob.fields["rho"].copy()
     O.shift(prob.params, ref, N)
     assert np.array_equal(got, ref)
