@@ -1336,8 +1336,7 @@ int fargo_lfc_create(fargo_ctx *ctx, const fargo_lfc_params *p, fargo_lfc **out)
                o_o = slot(ntot * 2 * 4), o_g3 = slot(ntot * 4 * 2), o_g2 = slot(ntot * 32 * 2),
                o_g1 = slot(ntot * 32 * 2), o_drho = slot(ntot * 8), o_gD = slot(ntot * 8), o_lp = slot(nlb * 8),
                o_loss = slot(8), o_flag = slot(4), o_w = slot(LFC_NPARAM * 4), o_mo = slot(LFC_NPARAM * 4),
-               o_ve = slot(LFC_NPARAM * 4), o_gr = slot(LFC_NPARAM * 4), o_part = slot(nwb * 32 * 288 * 4),
-               o_dbp = slot(nwb * 32 * 4), o_wp1 = slot(2048 * 2), o_wp2 = slot(9216 * 2), o_wp3 = slot(4608 * 2),
+               o_ve = slot(LFC_NPARAM * 4), o_gr = slot(LFC_NPARAM * 4), o_part = slot(nwb * LFC_NPARAM * 4), o_wp1 = slot(2048 * 2), o_wp2 = slot(9216 * 2), o_wp3 = slot(4608 * 2),
                o_wpa3 = slot(2048 * 2), o_wpa2 = slot(9216 * 2);
   fargo_lfc *l = new fargo_lfc;
   if (hipSetDevice(ctx->dev) != hipSuccess || hipMalloc(&l->mem, off) != hipSuccess) {
@@ -1367,7 +1366,6 @@ int fargo_lfc_create(fargo_ctx *ctx, const fargo_lfc_params *p, fargo_lfc **out)
   B.ve = (float *)(b + o_ve);
   B.grad = (float *)(b + o_gr);
   B.part = (float *)(b + o_part);
-  B.dbpart = (float *)(b + o_dbp);
   B.wt.wp1 = (unsigned short *)(b + o_wp1);
   B.wt.wp2 = (unsigned short *)(b + o_wp2);
   B.wt.wp3 = (unsigned short *)(b + o_wp3);

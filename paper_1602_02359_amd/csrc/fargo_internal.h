@@ -431,7 +431,7 @@ struct LfcBufs {
   unsigned short *g3, *g2, *g1;     // layer gradients [sample][pixel][4 | 32 | 32]
   double *drho, *gD, *lpart, *loss; // density change, dL/d(divergence), loss partials, loss
   float *w, *mo, *ve, *grad;        // master parameters, Adam moments, gradient [LFC_NPARAM]
-  float *part, *dbpart;             // weight-gradient partials per block
+  float *part;                      // weight-gradient partials, one row of LFC_NPARAM per block
   LfcWeights wt;
 };
 // samples of one training or forward batch (at most LFC_MAXB), passed by value

@@ -455,8 +455,9 @@ __global__ __launch_bounds__(CW_THREADS) void k_conv_w(int nx, int ny, int rpc, 
     }
     __syncthreads();
   }
-  // results: lane holds column ln of its tiles and rows 4 q .. 4 q + 3
-  float *pw = part + (size_t)blockIdx.x * COUT * K;
+  // results: lane holds column ln of its tiles and rows 4 q .. 4 q + 3 (one
+  // row of LFC_NPARAM partials per block, in the parameter vector's order)
+  float *pw = part + (size_t)blockIdx.x * LFC_NPARAM;
   if (CIN == 32) {
 #pragma unroll
     for (int a = 0; a < NA; a++)
@@ -485,35 +486,32 @@ __global__ __launch_bounds__(CW_THREADS) void k_conv_w(int nx, int ny, int rpc, 
     const int c8 = GC == 32 ? tid >> 3 : 0, k = GC == 32 ? tid & 7 : tid;
     float t = 0.f;
     for (int u = c8; u < NGT; u += GCH) t += dbr[u][k];
-    dbpart[(size_t)blockIdx.x * COUT + tid] = t;
+    dbpart[(size_t)blockIdx.x * LFC_NPARAM + tid] = t;
   }
 }
 
-// grad[W] = sum over blocks of the partials, grad[b] likewise.  A block takes
-// RE consecutive entries; its RG thread groups sum interleaved subsets of the
-// partials, and the group sums are added in a fixed order (deterministic).
+// The gradient of every parameter: the sum over blocks of the weight-gradient
+// kernels' partials (one row of LFC_NPARAM per block, all three layers in one
+// launch).  A block takes RE consecutive parameters; its RG thread groups sum
+// interleaved subsets of the rows, and the group sums are added in a fixed
+// order (deterministic).
 constexpr int RE = 64, RG = 16;
-__global__ __launch_bounds__(RE * RG) void k_reduce_w(int nchunk, int cout, int K, const float *__restrict__ part,
-                                                      const float *__restrict__ dbpart, float *__restrict__ gW,
-                                                      float *__restrict__ gb) {
+__global__ __launch_bounds__(RE * RG) void k_reduce_w(int nchunk, const float *__restrict__ part,
+                                                      float *__restrict__ grad) {
   __shared__ float red[RG][RE];
   const int el = threadIdx.x % RE, g = threadIdx.x / RE;
   const int e = blockIdx.x * RE + el;
-  const int nw = cout * K;
   float s = 0.f;
-  if (e < nw) {
+  if (e < LFC_NPARAM) {
 #pragma unroll 8
-    for (int c = g; c < nchunk; c += RG) s += part[(size_t)c * nw + e];
-  } else if (e < nw + cout) {
-    for (int c = g; c < nchunk; c += RG) s += dbpart[(size_t)c * cout + (e - nw)];
+    for (int c = g; c < nchunk; c += RG) s += part[(size_t)c * LFC_NPARAM + e];
   }
   red[g][el] = s;
   __syncthreads();
-  if (g == 0 && e < nw + cout) {
+  if (g == 0 && e < LFC_NPARAM) {
     float t = 0.f;
     for (int q = 0; q < RG; q++) t += red[q][el];
-    if (e < nw) gW[e] = t;
-    else gb[e - nw] = t;
+    grad[e] = t;
   }
 }
 
@@ -698,33 +696,28 @@ void lfc_backward(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double 
   prof_end(L, K_LFC_DRHO);
   // layer 3: weights from g3 and h2, then the gradient into h2
   prof_begin(L, K_LFC_W3);
-  k_conv_w<32, 2, 4><<<nw, CW_THREADS, 0, L.s>>>(nx, ny, rpc, nrc, B.g3, B.h2, B.part, B.dbpart);
+  k_conv_w<32, 2, 4><<<nw, CW_THREADS, 0, L.s>>>(nx, ny, rpc, nrc, B.g3, B.h2, B.part + LFC_OFF_W3,
+                                                 B.part + LFC_OFF_B3);
   prof_end(L, K_LFC_W3);
-  prof_begin(L, K_LFC_REDUCE);
-  k_reduce_w<<<nblk(2 * 288 + 2, RE), RE * RG, 0, L.s>>>(nw, 2, 288, B.part, B.dbpart, B.grad + LFC_OFF_W3,
-                                                     B.grad + LFC_OFF_B3);
-  prof_end(L, K_LFC_REDUCE);
   prof_begin(L, K_LFC_ADJ3);
   k_conv<4, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g3, (const uint4 *)B.wt.wpa3, nullptr, B.h2, B.g2, nullptr);
   prof_end(L, K_LFC_ADJ3);
   // layer 2
   prof_begin(L, K_LFC_W2);
-  k_conv_w<32, 32, 32><<<nw, CW_THREADS, 0, L.s>>>(nx, ny, rpc, nrc, B.g2, B.h1, B.part, B.dbpart);
+  k_conv_w<32, 32, 32><<<nw, CW_THREADS, 0, L.s>>>(nx, ny, rpc, nrc, B.g2, B.h1, B.part + LFC_OFF_W2,
+                                                   B.part + LFC_OFF_B2);
   prof_end(L, K_LFC_W2);
-  prof_begin(L, K_LFC_REDUCE);
-  k_reduce_w<<<nblk(32 * 288 + 32, RE), RE * RG, 0, L.s>>>(nw, 32, 288, B.part, B.dbpart, B.grad + LFC_OFF_W2,
-                                                       B.grad + LFC_OFF_B2);
-  prof_end(L, K_LFC_REDUCE);
   prof_begin(L, K_LFC_ADJ2);
   k_conv<32, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g2, (const uint4 *)B.wt.wpa2, nullptr, B.h1, B.g1, nullptr);
   prof_end(L, K_LFC_ADJ2);
   // layer 1 (no gradient into the features)
   prof_begin(L, K_LFC_W1);
-  k_conv_w<4, 32, 32><<<nw, CW_THREADS, 0, L.s>>>(nx, ny, rpc, nrc, B.g1, B.f, B.part, B.dbpart);
+  k_conv_w<4, 32, 32><<<nw, CW_THREADS, 0, L.s>>>(nx, ny, rpc, nrc, B.g1, B.f, B.part + LFC_OFF_W1,
+                                                  B.part + LFC_OFF_B1);
   prof_end(L, K_LFC_W1);
+  // every parameter's gradient in one reduction
   prof_begin(L, K_LFC_REDUCE);
-  k_reduce_w<<<nblk(32 * 36 + 32, RE), RE * RG, 0, L.s>>>(nw, 32, 36, B.part, B.dbpart, B.grad + LFC_OFF_W1,
-                                                      B.grad + LFC_OFF_B1);
+  k_reduce_w<<<nblk(LFC_NPARAM, RE), RE * RG, 0, L.s>>>(nw, B.part, B.grad);
   prof_end(L, K_LFC_REDUCE);
 }
 
