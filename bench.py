@@ -175,7 +175,7 @@ def cpu_baseline(prob, target_s=10.0):
         return smp, time.perf_counter() - t0
 
     def sized(rate):
-        want = min(rate * target_s, 4e7)  # at most 40 M zones (host memory of the oracle's copy)
+        want = min(rate * target_s, 1.6e8)  # at most 160 M zones (some 50 GB of host memory for the oracle)
         if p["nz"] > 1:
             nz_s = max(4, min(p["nz"], int(want / (p["nx"] * p["ny"]))))
             ny_s = p["ny"] if nz_s * p["nx"] * p["ny"] <= want else max(4, int(want / (p["nx"] * nz_s)))

@@ -633,7 +633,9 @@ void step_impl(fargo_ctx *ctx, const fargo_state *state, double dt, Launch &L) {
   P.vx = v2[0];
   P.vy = v2[1];
   if (m.visc) {                                                                    // box 7d
-    launch_visc(L, m, S, v2[0], v2[1], (F *)ctx->v3[0], (F *)ctx->v3[1], dtp);
+    // the stress components in transport set A, which holds nothing until the X sweep
+    F *const tau[3] = {(F *)ctx->TA[T_RHO], (F *)ctx->TA[T_PXM], (F *)ctx->TA[T_PXP]};
+    launch_visc(L, m, S, v2[0], v2[1], (F *)ctx->v3[0], (F *)ctx->v3[1], dtp, tau);
     P.vx = (F *)ctx->v3[0];
     P.vy = (F *)ctx->v3[1];
   }
@@ -835,7 +837,7 @@ struct fargo_batch {
   hipGraphExec_t exec = nullptr;
   // fused mode: the launches' argument blocks and tables in one allocation
   void *fmem = nullptr;
-  ManyGrid g[8] = {};
+  ManyGrid g[9] = {};
   ManyGrid gcfl[8] = {}; // the time-step pass by zones per thread (ceil(nx / 256), 1..7)
   int nxmax = 0;
   std::vector<int> chunk; // per disk (the sweep's chunk length, tuned per size class)
@@ -906,7 +908,7 @@ int batch_capture(fargo_batch *b, int lanes) {
 size_t field_bytes(const fargo_ctx *c) { return (size_t)c->m.pitch * c->m.nyg * c->m.nzg * c->esize; }
 
 // ---- fused mode ----
-enum { FU_CFL, FU_DT, FU_SRC, FU_SRCG, FU_VISC, FU_SY, FU_RX, FU_VEL, FU_N };
+enum { FU_CFL, FU_DT, FU_SRC, FU_SRCG, FU_VISC1, FU_VISC, FU_SY, FU_RX, FU_VEL, FU_N };
 
 bool fused_ok(fargo_ctx *const *c, int n) {
   const fargo_params &p0 = c[0]->p;
@@ -948,7 +950,7 @@ int fused_build(fargo_batch *b) {
   H[FU_CFL].asz = cfl_args_bytes<F>();
   H[FU_DT].asz = dt_final_args_bytes();
   H[FU_SRC].asz = H[FU_SRCG].asz = source_args_bytes<F>();
-  H[FU_VISC].asz = visc_args_bytes<F>();
+  H[FU_VISC].asz = H[FU_VISC1].asz = visc_args_bytes<F>();
   H[FU_SY].asz = sweep_y_args_bytes<F>();
   H[FU_RX].asz = ring_x_args_bytes<F>();
   H[FU_VEL].asz = vel_args_bytes<F>();
@@ -972,7 +974,12 @@ int fused_build(fargo_batch *b) {
     P.vx = v2[0];
     P.vy = v2[1];
     if (m.visc) {
-      H[FU_VISC].blocks(d, visc_args<F>(m, S, v2[0], v2[1], (F *)c->v3[0], (F *)c->v3[1], dtp, H[FU_VISC].slot(d)));
+      F *const tau[3] = {(F *)c->TA[T_RHO], (F *)c->TA[T_PXM], (F *)c->TA[T_PXP]};
+      unsigned nb1 = 0;
+      H[FU_VISC].blocks(d, visc_args<F>(m, S, v2[0], v2[1], (F *)c->v3[0], (F *)c->v3[1], dtp, tau,
+                                        H[FU_VISC].slot(d), &nb1));
+      visc_args<F>(m, S, v2[0], v2[1], (F *)c->v3[0], (F *)c->v3[1], dtp, tau, H[FU_VISC1].slot(d), &nb1);
+      H[FU_VISC1].blocks(d, nb1);
       P.vx = (F *)c->v3[0];
       P.vy = (F *)c->v3[1];
     }
@@ -1022,7 +1029,7 @@ void fused_step(fargo_batch *b, Launch &L) {
     if (b->gcfl[k].nblk) launch_cfl_many<F>(L, b->gcfl[k], 256 * k);
   launch_dt_final_many(L, b->g[FU_DT]);
   launch_source_many<F>(L, m0, b->g[FU_SRC], b->g[FU_SRCG]);                        // boxes 7a-7c
-  if (m0.visc) launch_visc_many<F>(L, b->g[FU_VISC]);                              // box 7d
+  if (m0.visc) launch_visc_many<F>(L, b->g[FU_VISC1], b->g[FU_VISC]);              // box 7d
   launch_sweep_y_many<F>(L, m0, b->g[FU_SY]);                                       // boxes 12a-c, Y
   launch_ring_x_many<F>(L, b->ctx[0]->nq, b->g[FU_RX]);                              // X, split, FARGO, 12d
   launch_vel_many<F>(L, b->g[FU_VEL]);                                              // 12d (v_y)

@@ -329,7 +329,7 @@ void launch_source(Launch &L, const Mesh &m, const StateT<R> &s, const double *d
 // box 7d: viscous stress (cylindrical 2D) from vx2, vy2 into vx3, vy3
 template <typename R>
 void launch_visc(Launch &L, const Mesh &m, const StateT<R> &s, const R *vx2, const R *vy2, R *vx3, R *vy3,
-                 const double *dt);
+                 const double *dt, R *const tau[3]);
 // box 12
 template <typename R>
 void launch_sweep_y(Launch &L, const Mesh &m, const StateT<R> &s, const TSetT<R> &out, const double *dt);
@@ -387,9 +387,9 @@ template <typename F>
 size_t visc_args_bytes();
 template <typename F>
 unsigned visc_args(const Mesh &m, const StateT<F> &s, const F *vx2, const F *vy2, F *vx3, F *vy3, const double *dt,
-                   void *dst);
+                   F *const tau[3], void *dst, unsigned *nb1);
 template <typename F>
-void launch_visc_many(Launch &L, const ManyGrid &g);
+void launch_visc_many(Launch &L, const ManyGrid &g1, const ManyGrid &g);
 template <typename F>
 size_t sweep_y_args_bytes();
 template <typename F>

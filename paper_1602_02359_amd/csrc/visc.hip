@@ -49,9 +49,34 @@ struct Visc {
   }
 };
 
+// Two passes.  1: the stress components, each formed once: tau_phiphi and
+// tau_rr of every zone in rows j0 - 1 .. jn - 1, tau_rphi of every edge in
+// rows j0 .. jn, into three scratch fields.  2: their divergence on the
+// faces (ghost zones carry v'' over).
 template <typename F>
-__device__ __forceinline__ void visc_body(Visc<F> V, const double *__restrict__ dtp, F *__restrict__ vx3,
-                                              F *__restrict__ vy3, unsigned bid_, unsigned nbk_) {
+__device__ __forceinline__ void visc_tau_body(Visc<F> V, F *__restrict__ tpp, F *__restrict__ trr,
+                                              F *__restrict__ trp, unsigned bid_, unsigned nbk_) {
+  const Mesh &m = V.m;
+  const int nib = (m.nx + blockDim.x - 1) / blockDim.x;
+  const unsigned Lb = xcd_remap(bid_, nbk_);
+  const int j = m.j0 - 1 + (int)(Lb / (unsigned)nib);
+  const int i = (int)(Lb % (unsigned)nib) * (int)blockDim.x + (int)threadIdx.x;
+  if (i >= m.nx || j > m.jn) return;
+  const unsigned c = V.at(i, j);
+  if (j < m.jn) {
+    F a, b;
+    V.diag(i, j, a, b);
+    tpp[c] = a;
+    trr[c] = b;
+  }
+  if (j >= m.j0) trp[c] = V.edge(i, j);
+}
+
+template <typename F>
+__device__ __forceinline__ void visc_div_body(Visc<F> V, const F *__restrict__ tpp, const F *__restrict__ trr,
+                                              const F *__restrict__ trp, const double *__restrict__ dtp,
+                                              F *__restrict__ vx3, F *__restrict__ vy3, unsigned bid_,
+                                              unsigned nbk_) {
   const Mesh &m = V.m;
   const int nib = (m.nx + blockDim.x - 1) / blockDim.x;
   const unsigned Lb = xcd_remap(bid_, nbk_);
@@ -66,86 +91,97 @@ __device__ __forceinline__ void visc_body(Visc<F> V, const double *__restrict__ 
   }
   const F dt = (F)*dtp, dphi = (F)m.dx;
   const F *rho = V.s.rho;
-  // every stress component the zone's two faces need, each formed once
-  // (the stores come last, so that no load waits behind them)
   const int im = V.wrapx(i - 1);
-  const bool own_y = j >= m.ylo();
-  F tpp0, trr0, tppw, trrw, tpps = F(0), trrs = F(0);
-  V.diag(i, j, tpp0, trr0);
-  V.diag(im, j, tppw, trrw);
-  if (own_y) V.diag(i, j - 1, tpps, trrs);
-  const F e0 = V.edge(i, j), en = V.edge(i, j + 1);
-  const F ee = own_y ? V.edge(V.wrapx(i + 1), j) : F(0);
+  const unsigned cw = V.at(im, j), cs_ = c - (unsigned)m.pitch;
   // v_phi on the X face of zone (i, j)
   const F a = (F)m.g.ymin(j), b = (F)m.g.ymin(j + 1), r = (F)m.g.ymed(j);
-  const F rx = F(0.5) * (rho[c] + rho[V.at(im, j)]);
-  const F divx = (b * b * en - a * a * e0) / (r * r * (F)m.g.Ly(j)) + (tpp0 - tppw) / (r * dphi);
-  const F vx3c = V.vx[c] - dt * divx / rx;
+  const F rx = F(0.5) * (rho[c] + rho[cw]);
+  const F e0 = trp[c], tpp0 = tpp[c];
+  const F divx = (b * b * trp[c + (unsigned)m.pitch] - a * a * e0) / (r * r * (F)m.g.Ly(j)) + (tpp0 - tpp[cw]) / (r * dphi);
+  vx3[c] = V.vx[c] - dt * divx / rx;
   // v_r on the Y face of zone (i, j), if the step owns it
-  F vy3c = V.vy[c];
-  if (own_y) {
-    const F ry = F(0.5) * (rho[c] + rho[c - (unsigned)m.pitch]);
-    const F divy = ((F)m.g.ymed(j) * trr0 - (F)m.g.ymed(j - 1) * trrs) / (a * (F)m.g.hy(j)) +
-                   (ee - e0) / (a * dphi) - F(0.5) * (tpp0 + tpps) / a;
-    vy3c = vy3c - dt * divy / ry;
+  if (j >= m.ylo()) {
+    const F ry = F(0.5) * (rho[c] + rho[cs_]);
+    const F divy = ((F)m.g.ymed(j) * trr[c] - (F)m.g.ymed(j - 1) * trr[cs_]) / (a * (F)m.g.hy(j)) +
+                   (trp[V.at(V.wrapx(i + 1), j)] - e0) / (a * dphi) - F(0.5) * (tpp0 + tpp[cs_]) / a;
+    vy3[c] = V.vy[c] - dt * divy / ry;
+  } else {
+    vy3[c] = V.vy[c];
   }
-  vx3[c] = vx3c;
-  vy3[c] = vy3c;
-}
-template <typename F>
-__global__ __launch_bounds__(256) void k_visc(Visc<F> V, const double *__restrict__ dtp, F *__restrict__ vx3,
-                                              F *__restrict__ vy3) {
-  visc_body<F>(V, dtp, vx3, vy3, blockIdx.x, gridDim.x);
 }
 
-// multi-mesh form (ManyGrid)
+template <typename F>
+__global__ __launch_bounds__(256) void k_visc_tau(Visc<F> V, F *__restrict__ tpp, F *__restrict__ trr,
+                                                  F *__restrict__ trp) {
+  visc_tau_body<F>(V, tpp, trr, trp, blockIdx.x, gridDim.x);
+}
+template <typename F>
+__global__ __launch_bounds__(256) void k_visc(Visc<F> V, const F *__restrict__ tpp, const F *__restrict__ trr,
+                                              const F *__restrict__ trp, const double *__restrict__ dtp,
+                                              F *__restrict__ vx3, F *__restrict__ vy3) {
+  visc_div_body<F>(V, tpp, trr, trp, dtp, vx3, vy3, blockIdx.x, gridDim.x);
+}
+
+// multi-mesh forms (ManyGrid): one argument block serves both passes
 template <typename F>
 struct ViscArgs {
   Visc<F> V;
+  F *tpp, *trr, *trp;
   const double *dt;
   F *vx3, *vy3;
-  unsigned nb;
+  unsigned nb, nb1;
 };
+template <typename F>
+__global__ __launch_bounds__(256) void k_visc_tau_many(const void *args, const uint2 *tab) {
+  const uint2 t = many_block(tab);
+  if (t.x == MANY_NONE) return;
+  const ViscArgs<F> a = many_args<ViscArgs<F>>(args, t.x);
+  visc_tau_body<F>(a.V, a.tpp, a.trr, a.trp, t.y, a.nb1);
+}
 template <typename F>
 __global__ __launch_bounds__(256) void k_visc_many(const void *args, const uint2 *tab) {
   const uint2 t = many_block(tab);
   if (t.x == MANY_NONE) return;
   const ViscArgs<F> a = many_args<ViscArgs<F>>(args, t.x);
-  visc_body<F>(a.V, a.dt, a.vx3, a.vy3, t.y, a.nb);
+  visc_div_body<F>(a.V, a.tpp, a.trr, a.trp, a.dt, a.vx3, a.vy3, t.y, a.nb);
 }
 
 } // namespace
 
 template <typename F>
 void launch_visc(Launch &L, const Mesh &m, const StateT<F> &s, const F *vx2, const F *vy2, F *vx3, F *vy3,
-                 const double *dt) {
+                 const double *dt, F *const tau[3]) {
   const int bs = 256, nib = (m.nx + bs - 1) / bs;
-  const unsigned nb = (unsigned)nib * (unsigned)m.nyg;
+  const Visc<F> V{m, s, vx2, vy2};
   prof_begin(L, K_VISC);
-  k_visc<F><<<nb, bs, 0, L.s>>>(Visc<F>{m, s, vx2, vy2}, dt, vx3, vy3);
+  k_visc_tau<F><<<(unsigned)nib * (unsigned)(m.ny + 2), bs, 0, L.s>>>(V, tau[0], tau[1], tau[2]);
+  k_visc<F><<<(unsigned)nib * (unsigned)m.nyg, bs, 0, L.s>>>(V, tau[0], tau[1], tau[2], dt, vx3, vy3);
   prof_end(L, K_VISC);
 }
 
 template void launch_visc<double>(Launch &, const Mesh &, const StateT<double> &, const double *, const double *,
-                                  double *, double *, const double *);
+                                  double *, double *, const double *, double *const[3]);
 template void launch_visc<float>(Launch &, const Mesh &, const StateT<float> &, const float *, const float *,
-                                 float *, float *, const double *);
+                                 float *, float *, const double *, float *const[3]);
 
 template <typename F>
 size_t visc_args_bytes() { return sizeof(ViscArgs<F>); }
 
+// the blocks of the second pass; those of the first through *nb1
 template <typename F>
 unsigned visc_args(const Mesh &m, const StateT<F> &s, const F *vx2, const F *vy2, F *vx3, F *vy3, const double *dt,
-                   void *dst) {
+                   F *const tau[3], void *dst, unsigned *nb1) {
   const int bs = 256, nib = (m.nx + bs - 1) / bs;
-  const unsigned nb = (unsigned)nib * (unsigned)m.nyg;
-  *(ViscArgs<F> *)dst = ViscArgs<F>{Visc<F>{m, s, vx2, vy2}, dt, vx3, vy3, nb};
+  const unsigned nb = (unsigned)nib * (unsigned)m.nyg, n1 = (unsigned)nib * (unsigned)(m.ny + 2);
+  *(ViscArgs<F> *)dst = ViscArgs<F>{Visc<F>{m, s, vx2, vy2}, tau[0], tau[1], tau[2], dt, vx3, vy3, nb, n1};
+  *nb1 = n1;
   return nb;
 }
 
 template <typename F>
-void launch_visc_many(Launch &L, const ManyGrid &g) {
+void launch_visc_many(Launch &L, const ManyGrid &g1, const ManyGrid &g) {
   prof_begin(L, K_VISC);
+  k_visc_tau_many<F><<<g1.nblk, 256, 0, L.s>>>(g1.args, g1.tab);
   k_visc_many<F><<<g.nblk, 256, 0, L.s>>>(g.args, g.tab);
   prof_end(L, K_VISC);
 }
@@ -153,8 +189,8 @@ void launch_visc_many(Launch &L, const ManyGrid &g) {
 #define FARGO_VISC_MANY(F)                                                                                          \
   template size_t visc_args_bytes<F>();                                                                            \
   template unsigned visc_args<F>(const Mesh &, const StateT<F> &, const F *, const F *, F *, F *, const double *,  \
-                                 void *);                                                                          \
-  template void launch_visc_many<F>(Launch &, const ManyGrid &);
+                                 F *const[3], void *, unsigned *);                                                 \
+  template void launch_visc_many<F>(Launch &, const ManyGrid &, const ManyGrid &);
 FARGO_VISC_MANY(double)
 FARGO_VISC_MANY(float)
 #undef FARGO_VISC_MANY
