@@ -482,3 +482,31 @@ def test_full_size_forward_and_gradient():
     assert abs(loss - loss_ref) <= 1e-12 * loss_ref
     Vs = (1.0 / c["invV"])[:, None]
     assert abs(np.sum(d_gpu * Vs)) <= 1e-13 * np.sum(np.abs(d_gpu * Vs))
+
+
+def test_full_size_train_batch_of_eight():
+    """The benchmark's training configuration: the 768 x 256 coarse planet
+    disk, eight samples per Adam step (the weight-gradient grid of that batch
+    size).  Two samples' layers element by element, and every weight and bias
+    gradient, summed over the eight samples, within the FP32 sum bound."""
+    c = _setup(nx=768, ny=256, seed=19, max_batch=8)
+    net = c["net"]
+    smps = _samples(c, 8, 191)
+    _say("lfc full size 768 x 256, batch of 8")
+    net.train_batch([x[0] for x in smps], 1e-3)
+    loss, _ = net.result()
+    vb = net.views(8)
+    grad = net.get_grad()
+    vs = [{k: vb[k][s] for k in vb} for s in range(8)]
+    flips = {}
+    for s in (0, 7):
+        fx = smps[s][1]
+        f = L.features(fx["rho"], fx["vx"], fx["vy"], c["rc"], c["scales"])
+        assert np.array_equal(_np(vs[s], "f"), f), s
+        for k, x in _forward_layers(vs[s], c["P"]).items():
+            flips[k] = flips.get(k, 0) + x
+    ts = [x[2] for x in smps]
+    bwd = _backward_layers(vs, c["P"], grad, ts, c["sF"], c["invV"], c["sigma"], _wdepth(768, 256, 8))
+    loss_ref = L.loss_batch([_np(v, "drho") for v in vs], ts, c["sigma"])
+    _say("  loss", loss, loss_ref, "flipped roundings", flips, bwd)
+    assert abs(loss - loss_ref) <= 1e-12 * loss_ref

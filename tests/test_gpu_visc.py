@@ -241,3 +241,48 @@ def test_fused_batch_refuses_mixed_configurations():
     for s in mixed:
         s.fargo_check()
     del b
+
+
+def test_fused_batch_full_size():
+    """The benchmark's batch: the 256 uneven viscous disks (N_r 64..512,
+    70.7 M zones), FP64, in the fused form with the chunk tuned per size class
+    as the benchmark does.  After two steps every disk equals its own
+    fargo_step bit for bit (a property at any size), and four sampled disks,
+    the smallest, the largest and two between, match the oracle after the
+    first step (dt within the 32-ulp bound, state within 1e-12 normwise)."""
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    probs = W.disk_batch()
+    sizes = [p.active_cells for p in probs]
+    order = np.argsort(sizes)
+    sample = [int(order[0]), int(order[len(order) // 3]), int(order[2 * len(order) // 3]), int(order[-1])]
+    refs = {d: probs[d].copy_fields() for d in sample}
+    fused = [_solver(p) for p in probs]
+    b = F.Batch(fused, lanes=0)
+    b.fargo_batch_tune(lanes=(0,), chunks=(8, 16, 32, 64), steps=2)
+    _say("fused batch of %d disks, %d zones, chunks by disk %s" % (len(probs), sum(sizes), sorted(set(b.chunks()))))
+    b.fargo_batch_step()
+    torch.cuda.synchronize()
+    for d in sample:
+        p = probs[d]
+        dt_ref = O.step(p.params, refs[d])
+        sv = fused[d]
+        dt = sv.fargo_get_dt()
+        assert dt_close(dt, dt_ref), (p.name, dt, dt_ref)
+        err = errors(p, sv.download(), refs[d])
+        _say("  %s %dx%d against the oracle: %s" % (p.name, p.params["nx"], p.params["ny"], err))
+        for k, e in err.items():
+            assert e <= TOL, (p.name, k, e)
+    b.fargo_batch_step()
+    for sv in fused:
+        sv.fargo_check()
+    for d, p in enumerate(probs):
+        own = _solver(p)
+        own.fargo_step(0.0)
+        own.fargo_step(0.0)
+        a, c = fused[d], own
+        assert a.fargo_get_dt() == c.fargo_get_dt(), p.name
+        for k in ("rho", "vx", "vy"):
+            assert torch.equal(a.state[k], c.state[k]), (p.name, k)
+        del own
+    del b
