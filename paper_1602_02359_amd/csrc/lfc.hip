@@ -88,49 +88,68 @@ enum { CV_HID = 0, CV_OUT = 1, CV_ADJ = 2 };
 constexpr int CV_RY = 8;
 
 template <int CIN, int COUT, int MODE>
-__global__ __launch_bounds__(256) void k_conv(int nx, int ny, const unsigned short *__restrict__ act,
+__global__ __launch_bounds__(256) void k_conv(int nx, int ny, int ntile, const unsigned short *__restrict__ act,
                                               const uint4 *__restrict__ Wp, const float *__restrict__ bias,
                                               const unsigned short *__restrict__ h, unsigned short *__restrict__ hout,
                                               float *__restrict__ fout) {
   constexpr int MT = (COUT + 15) / 16, KS = (9 * CIN + 31) / 32;
   constexpr int CP = CIN == 32 ? 40 : 4; // staged pixel stride (elements): 16-byte aligned, banks spread
   constexpr int TW = 66, NR = CV_RY + 2;
+  constexpr int CH = CIN == 32 ? 4 : 1;   // staged chunks per pixel (16 or 8 bytes)
+  constexpr int NE = NR * TW * CH, NL = (NE + 255) / 256;
   __shared__ __align__(16) unsigned short T[NR][TW][CP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, ln = lane & 15, q = lane >> 4;
   const int strips = nx / 64, rt = (ny + CV_RY - 1) / CV_RY;
-  const int strip = blockIdx.x % strips, rtile = (blockIdx.x / strips) % rt, s = blockIdx.x / (strips * rt);
-  const int x0 = strip * 64, y0 = rtile * CV_RY;
-  const size_t sb = (size_t)s * nx * ny; // first pixel of the sample
   uint4 w[MT][KS];
 #pragma unroll
   for (int mt = 0; mt < MT; mt++)
 #pragma unroll
     for (int ks = 0; ks < KS; ks++) w[mt][ks] = Wp[(mt * KS + ks) * 64 + lane];
-  if (CIN == 32) {
-    constexpr int NE = NR * TW * 4; // 16-byte chunks: 4 per pixel
-#pragma unroll 4
-    for (int e = tid; e < NE; e += 256) {
-      const int c8 = e & 3, col = (e >> 2) % TW, r = (e >> 2) / TW;
+  // A block takes tiles blockIdx.x, + gridDim.x, ...: the next tile's rows
+  // are loaded into registers while the current one is computed from LDS.
+  uint4 pre[NL];
+  auto fetch = [&](int tile) {
+    const int strip = tile % strips, rtile = (tile / strips) % rt, s = tile / (strips * rt);
+    const int x0 = strip * 64, y0 = rtile * CV_RY;
+    const size_t sb = (size_t)s * nx * ny;
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+      const int e = tid + 256 * l;
+      const int c8 = e % CH, col = (e / CH) % TW, r = (e / CH) / TW;
       const int yy = y0 + r - 1;
       int xx = x0 + col - 1;
       xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (yy >= 0 && yy < ny) v = *reinterpret_cast<const uint4 *>(act + (sb + (size_t)yy * nx + xx) * 32 + 8 * c8);
-      *reinterpret_cast<uint4 *>(&T[r][col][8 * c8]) = v;
+      pre[l] = make_uint4(0u, 0u, 0u, 0u);
+      if (e < NE && yy >= 0 && yy < ny) {
+        const unsigned short *src = act + (sb + (size_t)yy * nx + xx) * CIN + 8 * c8;
+        if (CIN == 32) pre[l] = *reinterpret_cast<const uint4 *>(src);
+        else {
+          const uint2 t = *reinterpret_cast<const uint2 *>(src);
+          pre[l] = make_uint4(t.x, t.y, 0u, 0u);
+        }
+      }
     }
-  } else {
-    constexpr int NE = NR * TW;
-    for (int e = tid; e < NE; e += 256) {
-      const int col = e % TW, r = e / TW;
-      const int yy = y0 + r - 1;
-      int xx = x0 + col - 1;
-      xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-      uint2 v = make_uint2(0u, 0u);
-      if (yy >= 0 && yy < ny) v = *reinterpret_cast<const uint2 *>(act + (sb + (size_t)yy * nx + xx) * 4);
-      *reinterpret_cast<uint2 *>(&T[r][col][0]) = v;
+  };
+  auto put = [&]() {
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+      const int e = tid + 256 * l;
+      if (e >= NE) continue;
+      const int c8 = e % CH, col = (e / CH) % TW, r = (e / CH) / TW;
+      if (CIN == 32) *reinterpret_cast<uint4 *>(&T[r][col][8 * c8]) = pre[l];
+      else *reinterpret_cast<uint2 *>(&T[r][col][0]) = make_uint2(pre[l].x, pre[l].y);
     }
-  }
+  };
+  int tile = blockIdx.x;
+  if (tile < ntile) fetch(tile);
+  for (; tile < ntile; tile += gridDim.x) {
+  __syncthreads(); // the previous tile's reads of T are done
+  put();
   __syncthreads();
+  if (tile + (int)gridDim.x < ntile) fetch(tile + gridDim.x);
+  const int strip = tile % strips, rtile = (tile / strips) % rt, s = tile / (strips * rt);
+  const int x0 = strip * 64, y0 = rtile * CV_RY;
+  const size_t sb = (size_t)s * nx * ny; // first pixel of the sample
   const int xl = wv * 16 + ln; // the lane's pixel (B column) within the 64
   const int nrow = min(CV_RY, ny - y0);
   for (int r = 0; r < nrow; r += 2) {
@@ -179,6 +198,7 @@ __global__ __launch_bounds__(256) void k_conv(int nx, int ny, const unsigned sho
         }
       }
     }
+  }
   }
 }
 
@@ -633,8 +653,13 @@ __global__ __launch_bounds__(LB) void k_target(Mesh m, const double *__restrict_
 
 inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
-inline unsigned conv_blocks(const Mesh &m, int nsamp) {
-  return (unsigned)(nsamp * (m.nx / 64) * ((m.ny + CV_RY - 1) / CV_RY));
+// tiles (64 pixels of CV_RY rows of one sample) of a convolution, and its
+// grid: the tiles, or as many workgroups as the compute units hold at once
+// (per unit: two of the 32-to-32-channel forms, three of the 32-to-2, five
+// of the 4-channel ones, by their registers) looping over them
+inline int conv_tiles(const Mesh &m, int nsamp) { return nsamp * (m.nx / 64) * ((m.ny + CV_RY - 1) / CV_RY); }
+inline unsigned conv_grid(int ntile, int per_cu) {
+  return (unsigned)(ntile < per_cu * 256 ? ntile : per_cu * 256);
 }
 
 } // namespace
@@ -657,16 +682,17 @@ void lfc_forward(Launch &L, const Mesh &m, const LfcFeed &in, int nsamp, const L
   prof_begin(L, K_LFC_FEATURES);
   k_features<<<nblk(ntot, LB), LB, 0, L.s>>>(m, in, nsamp, sc, B.f);
   prof_end(L, K_LFC_FEATURES);
-  const unsigned nb = conv_blocks(m, nsamp);
+  const int nt = conv_tiles(m, nsamp);
+  const unsigned nb = conv_grid(nt, 2), nb3 = conv_grid(nt, 3), nb5 = conv_grid(nt, 5);
   const uint4 *wp1 = (const uint4 *)B.wt.wp1, *wp2 = (const uint4 *)B.wt.wp2, *wp3 = (const uint4 *)B.wt.wp3;
   prof_begin(L, K_LFC_FWD1);
-  k_conv<4, 32, CV_HID><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.f, wp1, B.w + LFC_OFF_B1, nullptr, B.h1, nullptr);
+  k_conv<4, 32, CV_HID><<<nb5, 256, 0, L.s>>>(m.nx, m.ny, nt, B.f, wp1, B.w + LFC_OFF_B1, nullptr, B.h1, nullptr);
   prof_end(L, K_LFC_FWD1);
   prof_begin(L, K_LFC_FWD2);
-  k_conv<32, 32, CV_HID><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h1, wp2, B.w + LFC_OFF_B2, nullptr, B.h2, nullptr);
+  k_conv<32, 32, CV_HID><<<nb, 256, 0, L.s>>>(m.nx, m.ny, nt, B.h1, wp2, B.w + LFC_OFF_B2, nullptr, B.h2, nullptr);
   prof_end(L, K_LFC_FWD2);
   prof_begin(L, K_LFC_FWD3);
-  k_conv<32, 2, CV_OUT><<<nb, 256, 0, L.s>>>(m.nx, m.ny, B.h2, wp3, B.w + LFC_OFF_B3, nullptr, nullptr, B.o);
+  k_conv<32, 2, CV_OUT><<<nb3, 256, 0, L.s>>>(m.nx, m.ny, nt, B.h2, wp3, B.w + LFC_OFF_B3, nullptr, nullptr, B.o);
   prof_end(L, K_LFC_FWD3);
 }
 
@@ -688,7 +714,8 @@ void lfc_drho(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double sF, 
 void lfc_backward(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double sF) {
   const int nx = m.nx, ny = m.ny;
   const long ntot = (long)nx * ny * nsamp;
-  const unsigned nb = conv_blocks(m, nsamp);
+  const int nt = conv_tiles(m, nsamp);
+  const unsigned nb = conv_grid(nt, 2), nb3 = conv_grid(nt, 3), nb5 = conv_grid(nt, 5);
   int rpc = 1, nrc = 1;
   const int nw = lfc_wblocks(nx, ny, nsamp, &rpc, &nrc);
   prof_begin(L, K_LFC_DRHO);
@@ -700,7 +727,7 @@ void lfc_backward(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double 
                                                  B.part + LFC_OFF_B3);
   prof_end(L, K_LFC_W3);
   prof_begin(L, K_LFC_ADJ3);
-  k_conv<4, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g3, (const uint4 *)B.wt.wpa3, nullptr, B.h2, B.g2, nullptr);
+  k_conv<4, 32, CV_ADJ><<<nb5, 256, 0, L.s>>>(nx, ny, nt, B.g3, (const uint4 *)B.wt.wpa3, nullptr, B.h2, B.g2, nullptr);
   prof_end(L, K_LFC_ADJ3);
   // layer 2
   prof_begin(L, K_LFC_W2);
@@ -708,7 +735,7 @@ void lfc_backward(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double 
                                                    B.part + LFC_OFF_B2);
   prof_end(L, K_LFC_W2);
   prof_begin(L, K_LFC_ADJ2);
-  k_conv<32, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, B.g2, (const uint4 *)B.wt.wpa2, nullptr, B.h1, B.g1, nullptr);
+  k_conv<32, 32, CV_ADJ><<<nb, 256, 0, L.s>>>(nx, ny, nt, B.g2, (const uint4 *)B.wt.wpa2, nullptr, B.h1, B.g1, nullptr);
   prof_end(L, K_LFC_ADJ2);
   // layer 1 (no gradient into the features)
   prof_begin(L, K_LFC_W1);
