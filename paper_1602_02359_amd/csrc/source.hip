@@ -17,8 +17,8 @@
 // plane and marches through the Z planes.  For each plane the tile and a halo
 // of two zones in X and Y are staged in LDS; the v' of every X and Y face of
 // the tile (and of the halo faces its stencil needs) is computed once and
-// kept in LDS with the reciprocal of its density sum, then each zone forms q
-// on its neighbours and its v'' and e''.  Along Z each thread keeps a sliding
+// kept in LDS (with the reciprocal of its density sum where room is left),
+// then each zone forms q on its neighbours and its v'' and e''.  Along Z each thread keeps a sliding
 // window of its own column in registers (planes k-1 .. k+2), which also
 // supplies the tile's interior values to LDS, so each interior value is read
 // from memory once.  Geometric lengths enter through reciprocal tables.
@@ -38,45 +38,54 @@ namespace fargo {
 
 namespace {
 
-constexpr int TX = 64, TY = 8;          // tile; one wave per tile row
-constexpr int SX = TX + 4, SY = TY + 4; // with two halo zones on each side
-constexpr int NT = TX * TY;
+constexpr int TX = 64, SX = TX + 4; // tile width, with two halo zones on each side
+// Tile height (one wave per tile row).  The Y halo of a tile is read once per
+// tile, so taller tiles read less of it.  The FP64 3D march takes 16 rows
+// (1024 threads, at most 128 registers a thread), or 12 where the spherical or
+// adiabatic terms need more registers; FP32 marches and 2D meshes take 8
+// (two workgroups per compute unit; the FP32 march measured slower with
+// taller tiles).
+template <typename F, bool D3, int GEO, bool ADI>
+constexpr int tile_rows() {
+  if (!D3 || sizeof(F) == 4) return 8;
+  return ADI || GEO == FARGO_SPHERICAL ? 12 : 16;
+}
+template <typename F, bool D3, int GEO, bool ADI>
+constexpr int src_threads() { return 64 * tile_rows<F, D3, GEO, ADI>(); }
+// minimum waves per SIMD: one workgroup of the FP64 march per compute unit,
+// at least four waves of the others
+template <typename F, bool D3, int GEO, bool ADI>
+constexpr int src_waves() {
+  return sizeof(F) == 8 && D3 ? src_threads<F, D3, GEO, ADI>() / 256 : 4;
+}
 
 template <typename F>
 __device__ inline F qvisc(F c2, F rho, F dv) { return dv < F(0) ? c2 * rho * dv * dv : F(0); }
 
-template <typename F>
+template <typename F, int TY, int NB, bool SPH, bool KI>
 struct Lds {
-  // staging of a plane (two planes in flight; density three)
-  F R[3][SY][SX];      // density
-  F P[2][SY][SX];      // pressure
-  double Ph[2][SY][SX]; // potential (FP64 in every mode)
-  F VX[2][SY][SX];     // v_x on the lower X face of each zone slot
-  F VY[2][SY][TX];     // v_y on the lower Y face of each zone slot
-  F VT[2][SY][TX];     // spherical: v_theta on the zone's two Z faces, summed
-  // v' of the faces of a plane (two planes in flight)
-  F AX[2][TY][SX];     // v'_x of X faces of the tile rows
-  F IX[2][TY][SX];     // 1 / ((rho_i + rho_{i-1}) dX) on those faces
-  F AY[2][SY][TX];     // v'_y of Y faces
-  F IY[2][SY][TX];     // 1 / ((rho_j + rho_{j-1}) h_y) on those faces
-  double DX[2][TY];    // 1 / dX of the tile rows, for the halo X faces
+  // staging of a plane (NB planes in flight; density NB + 1 when NB > 1)
+  static constexpr int SY = TY + 4, NR = NB > 1 ? NB + 1 : 1;
+  F R[NR][SY][SX];      // density
+  F P[NB][SY][SX];      // pressure
+  double Ph[NB][SY][SX]; // potential (FP64 in every mode)
+  F VX[NB][SY][SX];     // v_x on the lower X face of each zone slot
+  F VY[NB][SY][TX];     // v_y on the lower Y face of each zone slot
+  F VT[SPH ? NB : 1][SPH ? SY : 1][SPH ? TX : 1]; // spherical: v_theta on the zone's two Z faces, summed
+  // v' of the faces of a plane (NB planes in flight)
+  F AX[NB][TY][SX];     // v'_x of X faces of the tile rows
+  F AY[NB][SY][TX];     // v'_y of Y faces
+  F IX[KI ? NB : 1][KI ? TY : 1][KI ? SX : 1]; // KI: 1 / ((rho_i + rho_{i-1}) dX) on the X faces
+  F IY[KI ? NB : 1][KI ? SY : 1][KI ? TX : 1]; // KI: 1 / ((rho_j + rho_{j-1}) h_y) on the Y faces
+  double DX[NB][TY];    // 1 / dX of the tile rows, for the halo X faces
 };
-// a 2D mesh has a single plane: one buffer of each (about half the LDS, so
-// that two workgroups share a compute unit)
-template <typename F>
-struct Lds2 {
-  F R[1][SY][SX];
-  F P[1][SY][SX];
-  double Ph[1][SY][SX];
-  F VX[1][SY][SX];
-  F VY[1][SY][TX];
-  F VT[1][SY][TX];
-  F AX[1][TY][SX];
-  F IX[1][TY][SX];
-  F AY[1][SY][TX];
-  F IY[1][SY][TX];
-  double DX[1][TY];
-};
+// (a 2D mesh has a single plane: one buffer of each, so that two workgroups
+// share a compute unit)
+constexpr size_t LDS_CU = 160 * 1024;
+// the reciprocals of the faces' density sums are kept in LDS where they fit
+// beside the rest, else formed again by the zones that use them
+template <typename F, int TY, int NB, bool SPH>
+constexpr bool keep_inv() { return sizeof(Lds<F, TY, NB, SPH, true>) <= LDS_CU; }
 
 // An explicit register move.  The march keeps a window of plane records in
 // registers and rotates it once per plane; moving the newest record out of its
@@ -118,7 +127,10 @@ template <typename F, bool D3, int GEO, bool ADI>
 __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *__restrict__ dtp,
                                                   F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
                                                   F *__restrict__ e2, int nbx, int nby, unsigned bid_, unsigned nbk_) {
-  __shared__ typename std::conditional<D3, Lds<F>, Lds2<F>>::type L;
+  constexpr int TY = tile_rows<F, D3, GEO, ADI>(), NB = D3 ? 2 : 1;
+  constexpr bool KI = keep_inv<F, TY, NB, GEO == FARGO_SPHERICAL>();
+  __shared__ Lds<F, TY, NB, GEO == FARGO_SPHERICAL, KI> L;
+  static_assert(sizeof(L) <= LDS_CU, "source step tile exceeds the LDS of a compute unit");
   // the row is the wave index: uniform, so that geometric factors of the
   // row come through scalar loads, which do not stall behind the prefetches
   const int tid = threadIdx.x, r = __builtin_amdgcn_readfirstlane(tid >> 6), c = tid & 63;
@@ -282,13 +294,13 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
       const F gradP = F(2) * (L.P[sb][t][sl] - L.P[sb][t][sl - 1]) * inv;
       const F gradPhi = (F)((L.Ph[sb][t][sl] - L.Ph[sb][t][sl - 1]) * idXd);
       L.AX[sb][rr][sl] = L.VX[sb][t][sl] - dt * (gradP + gradPhi);
-      L.IX[sb][rr][sl] = inv;
+      if constexpr (KI) L.IX[sb][rr][sl] = inv;
     };
     auto yface = [&](int t, int cc) {
       const int f = yrow(t), sl = cc + 2;
       if (!yowned(f)) {
         L.AY[sb][t][cc] = L.VY[sb][t][cc];
-        L.IY[sb][t][cc] = F(0);
+        if constexpr (KI) L.IY[sb][t][cc] = F(0);
         return;
       }
       const double ihd = m.g.inv_hy(f);
@@ -333,7 +345,7 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
         }
         L.AY[sb][t][cc] = L.VY[sb][t][cc] - dt * (gradP + gradPhi) + dt * src;
       }
-      L.IY[sb][t][cc] = inv;
+      if constexpr (KI) L.IY[sb][t][cc] = inv;
     };
     if (act) {
       xface(r, c + 2, m.g.inv_dxlen((size_t)kk * m.nyg + jt0 + r));
@@ -364,10 +376,14 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
     const F r1 = R[t][sl - 1], r2 = R[t][sl], r3 = R[t][sl + 1];
     const F dvx = a2 - a1;
     const F qx = qvisc(c2, r2, dvx), qxm = qvisc(c2, r1, a1 - a0), qxp = qvisc(c2, r3, a3 - a2);
-    const F bx1 = a1 - dt * F(2) * (qx - qxm) * L.IX[sb][r][sl];
-    const F bx2 = a2 - dt * F(2) * (qxp - qx) * L.IX[sb][r][sl + 1];
+    const double idX = m.g.inv_dxlen((size_t)kk * m.nyg + j);
+    // the reciprocals of the two X faces, as the faces' pass forms them
+    const F ix1 = KI ? L.IX[sb][r][sl] : (F)idX / (r2 + r1);
+    const F ix2 = KI ? L.IX[sb][r][sl + 1] : (F)idX / (r3 + r2);
+    const F bx1 = a1 - dt * F(2) * (qx - qxm) * ix1;
+    const F bx2 = a2 - dt * F(2) * (qxp - qx) * ix2;
     vx2[o] = bx1;
-    F heat = qx * dvx * (F)m.g.inv_dxlen((size_t)kk * m.nyg + j);
+    F heat = qx * dvx * (F)idX;
     const double syk = m.g.syk(kk);
     F flux = (F)(g_sxj * m.g.sxk(kk)) * (bx2 - bx1);
     // Y: faces t-1 .. t+2, zones t-1 .. t+1
@@ -376,8 +392,15 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
     const F dvy = b2 - b1;
     const F qy = qvisc(c2, r2, dvy);
     F by1 = b1, by2 = b2;
-    if (yowned(j)) by1 = b1 - dt * F(2) * (qy - qvisc(c2, s1, b1 - b0)) * L.IY[sb][t][c];
-    if (yowned(yrow(t + 1))) by2 = b2 - dt * F(2) * (qvisc(c2, s3, b3 - b2) - qy) * L.IY[sb][t + 1][c];
+    if (yowned(j)) {
+      const F iy = KI ? L.IY[sb][t][c] : (F)m.g.inv_hy(j) / (r2 + s1);
+      by1 = b1 - dt * F(2) * (qy - qvisc(c2, s1, b1 - b0)) * iy;
+    }
+    const int ju = yrow(t + 1);
+    if (yowned(ju)) {
+      const F iy = KI ? L.IY[sb][t + 1][c] : (F)m.g.inv_hy(ju) / (s3 + r2);
+      by2 = b2 - dt * F(2) * (qvisc(c2, s3, b3 - b2) - qy) * iy;
+    }
     vy2[o] = by1;
     heat += qy * dvy * (F)g_invLy;
     flux += (F)(g_syj1 * syk) * by2 - (F)(g_syj * syk) * by1;
@@ -513,7 +536,7 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
   }
 }
 template <typename F, bool D3, int GEO, bool ADI>
-__global__ __launch_bounds__(NT, sizeof(F) == 8 && D3 ? 2 : 4) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
+__global__ __launch_bounds__((src_threads<F, D3, GEO, ADI>()), (src_waves<F, D3, GEO, ADI>())) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
                                                   F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
                                                   F *__restrict__ e2, int nbx, int nby) {
   source_body<F, D3, GEO, ADI>(m, s, dtp, vx2, vy2, vz2, e2, nbx, nby, blockIdx.x, gridDim.x);
@@ -565,7 +588,7 @@ struct SourceArgs {
   unsigned nb;
 };
 template <typename F, bool D3, int GEO, bool ADI>
-__global__ __launch_bounds__(NT, sizeof(F) == 8 && D3 ? 2 : 4) void k_source_many(const void *args, const uint2 *tab) {
+__global__ __launch_bounds__((src_threads<F, D3, GEO, ADI>()), (src_waves<F, D3, GEO, ADI>())) void k_source_many(const void *args, const uint2 *tab) {
   const uint2 t = many_block(tab);
   if (t.x == MANY_NONE) return;
   const SourceArgs<F> a = many_args<SourceArgs<F>>(args, t.x);
@@ -579,17 +602,25 @@ __global__ __launch_bounds__(256) void k_source_ghosts_many(const void *args, co
   source_ghosts_body<F>(a.m, a.s, a.vx2, a.vy2, a.vz2, a.e2, t.y, a.nb);
 }
 
+// tile rows of the source step's launch on mesh m
+template <typename F>
+int src_rows(const Mesh &m) {
+  if (!m.d3) return tile_rows<F, false, FARGO_CARTESIAN, false>();
+  const bool tall = m.geo != FARGO_SPHERICAL && m.eos != FARGO_ADIABATIC;
+  return tall ? tile_rows<F, true, FARGO_CARTESIAN, false>() : tile_rows<F, true, FARGO_SPHERICAL, true>();
+}
+
 } // namespace
 
 template <typename F>
 void launch_source(Launch &L, const Mesh &m, const StateT<F> &s, const double *dt, F *vx2, F *vy2, F *vz2, F *e2) {
-  const int nbx = (m.nx + TX - 1) / TX, nby = (m.ny + TY - 1) / TY;
+  const int nbx = (m.nx + TX - 1) / TX, nby = (m.ny + src_rows<F>(m) - 1) / src_rows<F>(m);
   const unsigned nb = (unsigned)nbx * (unsigned)nby;
   const unsigned ng = (unsigned)(m.nzg * (m.nyg - m.ny) + (m.d3 ? (m.nzg - m.nz) * m.ny : 0));
   prof_begin(L, K_SRC);
   auto go = [&](auto d3, auto geo, auto adi) {
     k_source<F, decltype(d3)::value, decltype(geo)::value, decltype(adi)::value>
-        <<<nb, NT, 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2, nbx, nby);
+        <<<nb, src_threads<F, decltype(d3)::value, decltype(geo)::value, decltype(adi)::value>(), 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2, nbx, nby);
   };
   auto by_eos = [&](auto d3, auto geo) {
     if (m.eos == FARGO_ADIABATIC) go(d3, geo, std::true_type{});
@@ -618,7 +649,7 @@ size_t source_args_bytes() { return sizeof(SourceArgs<F>); }
 
 template <typename F>
 unsigned source_args(const Mesh &m, const StateT<F> &s, const double *dt, F *vx2, F *vy2, F *vz2, F *e2, void *dst) {
-  const int nbx = (m.nx + TX - 1) / TX, nby = (m.ny + TY - 1) / TY;
+  const int nbx = (m.nx + TX - 1) / TX, nby = (m.ny + src_rows<F>(m) - 1) / src_rows<F>(m);
   const unsigned nb = (unsigned)nbx * (unsigned)nby;
   *(SourceArgs<F> *)dst = SourceArgs<F>{m, s, dt, vx2, vy2, vz2, e2, nbx, nby, nb};
   return nb;
@@ -636,7 +667,7 @@ template <typename F>
 void launch_source_many(Launch &L, const Mesh &m0, const ManyGrid &g, const ManyGrid &ghosts) {
   prof_begin(L, K_SRC);
   auto go = [&](auto geo, auto adi) {
-    k_source_many<F, false, decltype(geo)::value, decltype(adi)::value><<<g.nblk, NT, 0, L.s>>>(g.args, g.tab);
+    k_source_many<F, false, decltype(geo)::value, decltype(adi)::value><<<g.nblk, src_threads<F, false, decltype(geo)::value, decltype(adi)::value>(), 0, L.s>>>(g.args, g.tab);
   };
   auto by_eos = [&](auto geo) {
     if (m0.eos == FARGO_ADIABATIC) go(geo, std::true_type{});
