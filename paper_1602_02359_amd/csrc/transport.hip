@@ -79,8 +79,9 @@ struct Zone {
 // lower-face velocity, `Tof(a, const Zone&, q)` gives the conserved Q of zone
 // a (carried in the window when CT, else formed again); `geo` gives L(a) (zone width), h(f)
 // (centre distance at face f), S(f), Vi(a); `st(a, rho, T[])` stores the
-// updated zone.  The loads of zone f + 2 are issued while zone f is being
-// computed.
+// updated zone.  The loads of zone f + 1 + PD are issued while zone f is
+// being computed (PD = 1 or 2 zones of loads in flight; with two, the two
+// load buffers take turns, so that no copy waits for a load).
 // With DEV, quantities 0 and 1 (the X momenta) are deviations from a
 // background ell that is constant on a ring (the FP32-bulk state): `dl(f)`
 // gives ell(f) - ell(f - 1) at face f.  Slopes take the full differences,
@@ -88,12 +89,13 @@ struct Zone {
 // lower zone, and the update of a zone adds the background carried in
 // through its lower face, so that in exact arithmetic the result is the
 // full update minus ell times the updated density.
-template <typename F, int NQ, bool CT, bool DEV, class RW, class RAW, class DER, class TOF, class GEO, class ST,
-          class DLF>
+template <typename F, int NQ, bool CT, bool DEV, class RW, int PD = 1, class RAW, class DER, class TOF, class GEO,
+          class ST, class DLF>
 __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const DER &derive, const TOF &Tof,
                                     const GEO &geo, const ST &st, const DLF &dl) {
+  static_assert(PD == 1 || PD == 2, "one or two zones of loads in flight");
   Zone<F, NQ, CT> zm, z0, zp;
-  RW rn;
+  RW rn, rn2;
   raw(a0 - 2, rn);
   derive(a0 - 2, rn, zp); // used only for the first slope
   raw(a0 - 1, rn);
@@ -101,6 +103,7 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
   raw(a0, rn);
   derive(a0, rn, z0);
   raw(a0 + 1, rn);
+  if (PD == 2 && a0 + 2 <= a1 + 1) raw(a0 + 2, rn2);
   F sm[NQ + 1], s0[NQ + 1];
   F dlf = DEV ? dl(a0) : F(0); // background increment at face f
   {
@@ -115,10 +118,11 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
 #pragma unroll
   for (int q = 0; q < NQ; q++) FQp[q] = F(0);
   F Lm = geo.L(a0 - 1);
-#pragma unroll 1
-  for (int f = a0; f <= a1; f++) {
-    derive(f + 1, rn, zp);
-    if (f + 2 <= a1 + 1) raw(f + 2, rn);
+  // face f: zone f + 1 from buffer cur, whose loads are then refilled with
+  // those of zone f + 1 + PD
+  auto face = [&](int f, RW &cur) {
+    derive(f + 1, cur, zp);
+    if (f + 1 + PD <= a1 + 1) raw(f + 1 + PD, cur);
     const F dlf1 = DEV ? dl(f + 1) : F(0);
     F hm = geo.h(f), hp = geo.h(f + 1);
     s0[NQ] = vl_slope(zm.rho, z0.rho, zp.rho, hm, hp);
@@ -152,6 +156,16 @@ __device__ inline void column_sweep(int a0, int a1, F dt, const RAW &raw, const 
     z0 = zp;
     Lm = L0;
     dlf = dlf1;
+  };
+  if constexpr (PD == 1) {
+#pragma unroll 1
+    for (int f = a0; f <= a1; f++) face(f, rn);
+  } else {
+#pragma unroll 1
+    for (int f = a0; f <= a1; f += 2) {
+      face(f, rn);
+      if (f + 1 <= a1) face(f + 1, rn2);
+    }
   }
 }
 
@@ -236,7 +250,9 @@ __device__ __forceinline__ void sweep_y_body(Mesh m, const F *__restrict__ rho, 
     for (int q = 0; q < NQ; q++) out.q[q][c] = T[q];
   };
   auto dl = [&](int f) { return (F)m.bg(BG_DLY, f, k); };
-  column_sweep<F, NQ, false, DEV, Raw>(a0, a1, dt, raw, derive, Tof, geo, st, dl);
+  // 3D: two zones of loads in flight (measured faster; the Z sweep, whose
+  // window holds the conserved values too, gains nothing from it)
+  column_sweep<F, NQ, false, DEV, Raw, D3 ? 2 : 1>(a0, a1, dt, raw, derive, Tof, geo, st, dl);
 }
 template <typename F, int NQ, bool D3, bool ADI>
 __global__ __launch_bounds__(256) void k_sweep_y(Mesh m, const F *__restrict__ rho, const F *__restrict__ vx,
