@@ -376,6 +376,39 @@ def copy_bandwidth():
     return out
 
 
+def pattern_bandwidth(nx, ny, nz, nin, nout, reps=5):
+    """Bytes read plus written per second by the library's access-pattern
+    probe with a column sweep's field counts (nin FP64 fields read, nout
+    written, nx * ny * nz each): one (x, y) column per thread walking the
+    planes, as the sweeps walk theirs, and one element per thread for
+    comparison.  The column walk's rate is the ceiling of the sweep's memory
+    access pattern with none of its arithmetic."""
+    import torch
+    from paper_1602_02359_amd import fargo as F
+    n = nx * ny * nz
+    ins = [torch.ones(n, dtype=torch.float64, device="cuda") for _ in range(nin)]
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(nout)]
+    nb = (nin + nout) * 8 * n
+
+    def rate(march):
+        F.fargo_hbm_streams(ins, outs, nx, ny, nz, march)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            F.fargo_hbm_streams(ins, outs, nx, ny, nz, march)
+        b.record()
+        torch.cuda.synchronize()
+        return nb / (a.elapsed_time(b) / reps * 1e-3) / 1e9
+
+    out = {"fields_read": nin, "fields_written": nout, "shape": [nx, ny, nz],
+           "column_march_GBs": round(rate(1), 1), "flat_GBs": round(rate(0), 1)}
+    assert bool((outs[0] == 2.0).all())
+    del ins, outs
+    torch.cuda.empty_cache()
+    return out
+
+
 LFC_BATCH = 8  # training samples per Adam step
 
 
@@ -697,6 +730,17 @@ def main():
                 "effective_GBs": head["value"] * compulsory_bytes(p) / 1e9})
     roof = head["roofline"]
     roof["frac_of_copy_ceiling"] = round(roof["achieved"] / ceiling, 4)
+    if roof["kernel"] == "sweep_z" and args.precision == "fp64":
+        # the Z sweep reads density, v_z and NQ conserved fields and writes
+        # density and the NQ fields: 2 NQ + 3 words a zone
+        nq = (round(roof["alg_bytes_per_launch"] / (cells * 8)) - 3) // 2
+        pat = pattern_bandwidth(p["nx"], p["ny"], p["nz"], nq + 2, nq + 1)
+        roof["pattern_ceiling"] = pat
+        roof["frac_of_pattern_ceiling"] = round(roof["achieved"] / pat["column_march_GBs"], 4)
+        print("access pattern of sweep_z (%d read, %d written): column walk %.0f GB/s, flat %.0f GB/s; "
+              "sweep_z at %.3f of the column walk" % (pat["fields_read"], pat["fields_written"],
+                                                     pat["column_march_GBs"], pat["flat_GBs"],
+                                                     roof["frac_of_pattern_ceiling"]), file=sys.stderr, flush=True)
 
     side = {}
     if not args.no_side:

@@ -249,6 +249,20 @@ int fargo_conserved_sums_noalloc(fargo_ctx *ctx, const fargo_state *state, doubl
    vendor peak.  Enqueued on `stream`; FARGO_EINVAL for a bad argument. */
 int fargo_hbm_copy(const void *src, void *dst, size_t bytes, int blocks, void *stream);
 
+/* Bandwidth probe of a column sweep's access pattern (no part of the
+   method): nin FP64 fields in[0..nin-1] are read and the first nout written,
+   out[q] = in[q] + in[nin - 1], each field nx * ny * nz doubles, x fastest
+   (1 <= nout <= nin <= 9; device buffers aligned to 8 bytes; no output may
+   overlap an input or another output).  march = 0: one element per thread;
+   march = 1: one (x, y) column per thread, walking its nz planes with the
+   loads of plane k + 1 issued before the stores of plane k, as the Y and Z
+   sweeps (Sect. 3.4) walk theirs.  The rate it reaches with the field counts
+   of a sweep is the ceiling of that sweep's memory access pattern, with
+   none of its arithmetic.  Enqueued on `stream`; FARGO_EINVAL for a bad
+   argument (the arrays `in` and `out` are host memory, read before return). */
+int fargo_hbm_streams(const double *const *in, int nin, double *const *out, int nout, int nx, int ny, int nz,
+                      int march, void *stream);
+
 /* Copy the time step last computed or imposed on the device into *dt_host
    (waits for the stream). */
 int fargo_get_dt(fargo_ctx *ctx, double *dt_host, void *stream);

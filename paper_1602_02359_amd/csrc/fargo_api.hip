@@ -746,6 +746,37 @@ int fargo_hbm_copy(const void *src, void *dst, size_t bytes, int blocks, void *s
   return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
 }
 
+int fargo_hbm_streams(const double *const *in, int nin, double *const *out, int nout, int nx, int ny, int nz,
+                      int march, void *stream) {
+  if (!in || !out || nin < 1 || nin > STREAMS_MAX || nout < 1 || nout > nin || nx < 1 || ny < 1 || nz < 1 ||
+      (march != 0 && march != 1))
+    return FARGO_EINVAL;
+  const size_t ncol = (size_t)nx * (size_t)ny, n = ncol * (size_t)nz;
+  if ((march ? ncol : n) / 256 >= ((size_t)1 << 31)) return FARGO_EINVAL;
+  StreamPtrs p{};
+  for (int q = 0; q < nin; q++) {
+    if (!in[q] || ((uintptr_t)in[q] & 7)) return FARGO_EINVAL;
+    p.in[q] = in[q];
+  }
+  for (int q = 0; q < nout; q++) {
+    if (!out[q] || ((uintptr_t)out[q] & 7)) return FARGO_EINVAL;
+    p.out[q] = out[q];
+  }
+  // no output may overlap another output or any input
+  auto overlap = [&](const void *a, const void *b) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + n * 8 && y < x + n * 8;
+  };
+  for (int q = 0; q < nout; q++) {
+    for (int r = 0; r < nin; r++)
+      if (overlap(p.out[q], p.in[r])) return FARGO_EINVAL;
+    for (int r = 0; r < q; r++)
+      if (overlap(p.out[q], p.out[r])) return FARGO_EINVAL;
+  }
+  launch_streams((hipStream_t)stream, p, nin, nout, ncol, nz, march);
+  return hipGetLastError() == hipSuccess ? FARGO_OK : FARGO_EHIP;
+}
+
 int fargo_get_dt(fargo_ctx *ctx, double *dt_host, void *stream) {
   if (!ctx || !dt_host) return FARGO_EINVAL;
   hipStream_t s = (hipStream_t)stream;

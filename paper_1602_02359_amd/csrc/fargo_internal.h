@@ -359,6 +359,12 @@ int static_scratch_setup(int dev);
 double *static_scratch(int dev);
 // bandwidth probe: a plain streaming copy of `bytes` (a multiple of 16)
 void launch_stream_copy(hipStream_t s, const void *src, void *dst, size_t bytes, int blocks);
+constexpr int STREAMS_MAX = 9; // fields of the access-pattern probe
+struct StreamPtrs {
+  const double *in[STREAMS_MAX];
+  double *out[STREAMS_MAX];
+};
+void launch_streams(hipStream_t s, const StreamPtrs &p, int nin, int nout, size_t ncol, int nz, int march);
 template <typename R>
 void launch_sums(Launch &L, const Mesh &m, const StateT<R> &s, double *partial, double *out);
 

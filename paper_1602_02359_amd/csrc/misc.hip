@@ -4,6 +4,7 @@
 // field type F (double, or float for the FP32-bulk state); the sums are always
 // formed in FP64 from the stored values.
 #include <mutex>
+#include <type_traits>
 
 #include "fargo_internal.h"
 
@@ -160,7 +161,67 @@ __global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ s
   }
 }
 
+// Bandwidth probe of a column sweep's access pattern: NI FP64 fields read,
+// the first nout written (out[q] = in[q] + in[NI - 1]), either one element
+// per thread (flat) or one (x, y) column per thread walking its nz planes
+// (march), the loads of plane k + 1 issued before the stores of plane k.
+template <int NI>
+__global__ __launch_bounds__(256) void k_streams_flat(StreamPtrs p, int nout, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double v[NI];
+#pragma unroll
+  for (int q = 0; q < NI; q++) v[q] = p.in[q][i];
+#pragma unroll
+  for (int q = 0; q < NI; q++)
+    if (q < nout) p.out[q][i] = v[q] + v[NI - 1];
+}
+template <int NI>
+__global__ __launch_bounds__(256) void k_streams_march(StreamPtrs p, int nout, size_t ncol, int nz) {
+  const size_t col = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= ncol) return;
+  double v[NI], w[NI] = {};
+  size_t c = col;
+#pragma unroll
+  for (int q = 0; q < NI; q++) v[q] = p.in[q][c];
+#pragma unroll 1
+  for (int k = 0; k < nz; k++) {
+    const size_t cn = c + ncol;
+    if (k + 1 < nz) {
+#pragma unroll
+      for (int q = 0; q < NI; q++) w[q] = p.in[q][cn];
+    }
+#pragma unroll
+    for (int q = 0; q < NI; q++)
+      if (q < nout) p.out[q][c] = v[q] + v[NI - 1];
+#pragma unroll
+    for (int q = 0; q < NI; q++) v[q] = w[q];
+    c = cn;
+  }
+}
+
 } // namespace
+
+void launch_streams(hipStream_t s, const StreamPtrs &p, int nin, int nout, size_t ncol, int nz, int march) {
+  const size_t n = march ? ncol : ncol * (size_t)nz;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  auto go = [&](auto ni) {
+    constexpr int NI = decltype(ni)::value;
+    if (march) k_streams_march<NI><<<nb, 256, 0, s>>>(p, nout, ncol, nz);
+    else k_streams_flat<NI><<<nb, 256, 0, s>>>(p, nout, n);
+  };
+  switch (nin) {
+  case 1: go(std::integral_constant<int, 1>{}); break;
+  case 2: go(std::integral_constant<int, 2>{}); break;
+  case 3: go(std::integral_constant<int, 3>{}); break;
+  case 4: go(std::integral_constant<int, 4>{}); break;
+  case 5: go(std::integral_constant<int, 5>{}); break;
+  case 6: go(std::integral_constant<int, 6>{}); break;
+  case 7: go(std::integral_constant<int, 7>{}); break;
+  case 8: go(std::integral_constant<int, 8>{}); break;
+  default: go(std::integral_constant<int, STREAMS_MAX>{}); break;
+  }
+}
 
 void launch_stream_copy(hipStream_t s, const void *src, void *dst, size_t bytes, int blocks) {
   const size_t n = bytes / 16;

@@ -68,6 +68,8 @@ _lib.fargo_ring_split.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p
 _lib.fargo_conserved_sums.argtypes = [C.c_void_p, _S, C.POINTER(C.c_double), C.c_void_p]
 _lib.fargo_conserved_sums_noalloc.argtypes = [C.c_void_p, _S, C.POINTER(C.c_double), C.c_void_p]
 _lib.fargo_hbm_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+_lib.fargo_hbm_streams.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_int, C.c_void_p]
 _lib.fargo_get_dt.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]
 _lib.fargo_check.argtypes = [C.c_void_p]
 _lib.fargo_profile_enable.argtypes = [C.c_void_p, C.c_int]
@@ -112,7 +114,7 @@ _lib.fargo_lfc_target.argtypes = [C.c_void_p, _S, _S, C.c_void_p, C.c_void_p]
 
 EXPORTED = ("fargo_abi_version", "fargo_strerror", "fargo_layout", "fargo_workspace_bytes", "fargo_init",
             "fargo_set_vx_background", "fargo_destroy", "fargo_cfl_dt", "fargo_step", "fargo_shift", "fargo_ring_split",
-            "fargo_conserved_sums", "fargo_conserved_sums_noalloc", "fargo_hbm_copy", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
+            "fargo_conserved_sums", "fargo_conserved_sums_noalloc", "fargo_hbm_copy", "fargo_hbm_streams", "fargo_get_dt", "fargo_check", "fargo_profile_enable", "fargo_timings",
             "fargo_batch_create", "fargo_batch_step", "fargo_batch_tune", "fargo_batch_chunks", "fargo_batch_destroy",
             "fargo_lfc_create", "fargo_lfc_destroy", "fargo_lfc_set_params", "fargo_lfc_get_params",
             "fargo_lfc_get_grad", "fargo_lfc_forward", "fargo_lfc_forward_batch", "fargo_lfc_train_step",
@@ -325,6 +327,17 @@ def fargo_hbm_copy(src: torch.Tensor, dst: torch.Tensor, blocks: int, stream=Non
     assert src.is_contiguous() and dst.is_contiguous() and src.nbytes == dst.nbytes
     _check(_lib.fargo_hbm_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), src.nbytes, int(blocks),
                                _stream(stream)), "fargo_hbm_copy")
+
+
+def fargo_hbm_streams(ins, outs, nx: int, ny: int, nz: int, march: bool, stream=None):
+    """The library's access-pattern probe: outs[q] = ins[q] + ins[-1] (FP64
+    fields of nx * ny * nz), flat or as a column march."""
+    for t in list(ins) + list(outs):
+        assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == nx * ny * nz
+    pi = (C.c_void_p * len(ins))(*[t.data_ptr() for t in ins])
+    po = (C.c_void_p * len(outs))(*[t.data_ptr() for t in outs])
+    _check(_lib.fargo_hbm_streams(pi, len(ins), po, len(outs), int(nx), int(ny), int(nz), int(bool(march)),
+                                  _stream(stream)), "fargo_hbm_streams")
 
 
 class Batch:

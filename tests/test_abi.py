@@ -65,3 +65,17 @@ def test_fp32_bulk_layout_and_precision_check():
     n = ctypes.c_size_t()
     assert F._lib.fargo_workspace_bytes(ctypes.byref(ps), ctypes.byref(n)) == -1
 
+
+
+def test_stream_probe_rejects_bad_arguments_without_gpu():
+    """fargo_hbm_streams checks its counts, sizes and pointers before it
+    launches anything."""
+    import ctypes as C
+    from paper_1602_02359_amd import fargo as F
+    lib = F._lib
+    nul = (C.c_void_p * 9)()
+    for nin, nout, nx, ny, nz, march in ((0, 1, 8, 8, 8, 0), (10, 1, 8, 8, 8, 0), (2, 3, 8, 8, 8, 0),
+                                         (2, 1, 0, 8, 8, 0), (2, 1, 8, 8, 0, 1), (2, 1, 8, 8, 8, 2),
+                                         (2, 1, 8, 8, 8, 0)):  # the last: null field pointers
+        assert lib.fargo_hbm_streams(nul, nin, nul, nout, nx, ny, nz, march, None) == -1
+    assert lib.fargo_hbm_streams(None, 1, nul, 1, 8, 8, 8, 0, None) == -1
