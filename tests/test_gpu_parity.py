@@ -350,3 +350,64 @@ def test_disk2d_full_ten_steps():
     _say("disk2d 10 steps", err)
     for k, e in err.items():
         assert e <= 10 * TOL, (k, e)
+
+
+# Meshes of several thousand rings, so that the time-step pass runs many
+# workgroups per compute unit and per XCD.  Its rings go in a logical order:
+# logical ring L is in plane tile L // (16 ny), k fastest within the tile, and
+# consecutive logical rings go to one XCD (about an eighth of them each).
+def _many_ring_cases():
+    yield "rings_cyl3d", "fp64", lambda: W.disk3d_cyl_planet(nx=256, ny=64, nz=66, noise=1e-2)
+    yield "rings_cyl3d", "fp32", lambda: W.disk3d_cyl_planet(nx=256, ny=64, nz=66, noise=1e-2)
+    yield "rings_2048", "fp64", lambda: W.random_problem("cyl", nx=2048, ny=40, nz=53, eos="iso", seed=11,
+                                                         fargo=True)
+    yield "rings_disk2d_visc", "fp64", lambda: W.disk2d_visc(nx=96, ny=4100)
+    yield "rings_sph3d_mean", "fp64", lambda: _with(W.disk3d_sph(nx=320, ny=64, nz=70, noise=1e-2), v0_mode="mean")
+
+
+def _logical_ring(L, ny, nz):
+    tile, q = divmod(L, 16 * ny)
+    kb = 16 * tile
+    kt = min(16, nz - kb)
+    return kb + q % kt, q // kt  # (k, j) counted from the first active plane and row
+
+
+@pytest.mark.parametrize("name,precision,make", list(_many_ring_cases()),
+                         ids=lambda v: v if isinstance(v, str) else "")
+def test_cfl_many_rings(name, precision, make):
+    """Every ring's v0 against the oracle (bit-exact for the min/max mode),
+    and the time step with one zone's sound speed (or energy) raised 30-fold
+    in rings at chosen places of the logical order (the first and last ring,
+    both sides of the first XCD's share, one in the middle), so that each of
+    those rings in turn sets dt: each ring's rate must come from its own
+    zones."""
+    prob = make()
+    p = dict(prob.params, precision=precision)
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    nring = ny * nz
+    r8 = (nring + 7) // 8
+    qf = "cs" if p["eos"] == "iso" else "e"
+    picks = [0, r8 - 1, r8, nring // 2 + 5, nring - 1]
+    for L in picks:
+        kk, jj = _logical_ring(L, ny, nz)
+        _say(name, precision, "ring", L, "(j, k) =", (jj, kk))
+        fields = prob.copy_fields()
+        zk = NG + kk if nz > 1 else 0
+        fields[qf][zk, NG + jj, nx // 3] *= 30.0
+        from paper_1602_02359_amd import fargo as F
+        s = F.Solver(p)
+        s.upload(fields)
+        dt = s.fargo_cfl_dt()
+        full = s.download()  # the state as the library holds it, ghosts filled
+        dt_ref = O.cfl_dt(p, full)
+        assert dt_close(dt, dt_ref), (L, dt, dt_ref)
+        if L == picks[0]:
+            import torch
+            g0, gN, gxi = s.fargo_ring_split(s.state["vx"], dt)
+            torch.cuda.synchronize()
+            v0, N, xi = O.ring_split(p, full["vx"], dt)
+            if p.get("v0_mode") == "mean":
+                assert np.allclose(g0.cpu().numpy(), v0.ravel(), rtol=1e-14, atol=1e-15)
+            else:
+                assert np.array_equal(g0.cpu().numpy(), v0.ravel())
+        s.fargo_check()
