@@ -30,27 +30,53 @@ __device__ inline double block_reduce(double v, Op op, double id, double *lds) {
   return v; // valid in every lane
 }
 
-// Two reductions of a block at once (two barriers for both); lds holds
-// 2 * MAXW values.
+// A lane move of a double by DPP (two 32-bit moves); lanes with no source
+// lane, and the rows the row mask leaves out, take id.
+template <int CTRL, int RM = 0xf>
+__device__ inline double dpp_or(double x, double id) {
+  const long long xv = __double_as_longlong(x), iv = __double_as_longlong(id);
+  const int lo = __builtin_amdgcn_update_dpp((int)iv, (int)xv, CTRL, RM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(iv >> 32), (int)(xv >> 32), CTRL, RM, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// The maximum or minimum of a wave's 64 values, in lane 63, by VALU lane
+// moves alone: shifts by 1, 2, 4 and 8 within each row of 16 lanes (lane 15
+// of a row then holds the row's result), then the broadcasts of lane 15 into
+// rows 1 and 3 and of lane 31 into rows 2 and 3.  Exact in any order, so it
+// serves min and max only.
+template <typename Op>
+__device__ inline double wave_reduce_dpp(double v, Op op, double id) {
+  constexpr int ROW_SHR = 0x110, ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+  v = op(v, dpp_or<ROW_SHR + 1>(v, id));
+  v = op(v, dpp_or<ROW_SHR + 2>(v, id));
+  v = op(v, dpp_or<ROW_SHR + 4>(v, id));
+  v = op(v, dpp_or<ROW_SHR + 8>(v, id));
+  v = op(v, dpp_or<ROW_BCAST15, 0xa>(v, id));
+  v = op(v, dpp_or<ROW_BCAST31, 0xc>(v, id));
+  return v;
+}
+
+// Two reductions of a block at once (min or max: exact in any order), with
+// two barriers for both: each wave reduces by DPP lane moves, its lane 63
+// puts the result in LDS, and every lane then reads the waves' results and
+// reduces them itself; lds holds 2 * MAXW values.
 template <typename OpA, typename OpB>
 __device__ inline void block_reduce2(double &a, OpA opa, double ida, double &b, OpB opb, double idb, double *lds) {
-  for (int o = 32; o > 0; o >>= 1) {
-    a = opa(a, __shfl_xor(a, o, 64));
-    b = opb(b, __shfl_xor(b, o, 64));
-  }
+  a = wave_reduce_dpp(a, opa, ida);
+  b = wave_reduce_dpp(b, opb, idb);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
-  if (lane == 0) {
+  if (lane == 63) {
     lds[wid] = a;
     lds[MAXW + wid] = b;
   }
   __syncthreads();
   const int nw = (blockDim.x + 63) >> 6;
-  a = lane < nw ? lds[lane] : ida;
-  b = lane < nw ? lds[MAXW + lane] : idb;
-  for (int o = 32; o > 0; o >>= 1) {
-    a = opa(a, __shfl_xor(a, o, 64));
-    b = opb(b, __shfl_xor(b, o, 64));
+  a = ida;
+  b = idb;
+  for (int w = 0; w < nw; w++) {
+    a = opa(a, lds[w]);
+    b = opb(b, lds[MAXW + w]);
   }
 }
 
