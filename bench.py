@@ -730,17 +730,29 @@ def main():
                 "effective_GBs": head["value"] * compulsory_bytes(p) / 1e9})
     roof = head["roofline"]
     roof["frac_of_copy_ceiling"] = round(roof["achieved"] / ceiling, 4)
-    if roof["kernel"] == "sweep_z" and args.precision == "fp64":
-        # the Z sweep reads density, v_z and NQ conserved fields and writes
-        # density and the NQ fields: 2 NQ + 3 words a zone
-        nq = (round(roof["alg_bytes_per_launch"] / (cells * 8)) - 3) // 2
-        pat = pattern_bandwidth(p["nx"], p["ny"], p["nz"], nq + 2, nq + 1)
-        roof["pattern_ceiling"] = pat
-        roof["frac_of_pattern_ceiling"] = round(roof["achieved"] / pat["column_march_GBs"], 4)
-        print("access pattern of sweep_z (%d read, %d written): column walk %.0f GB/s, flat %.0f GB/s; "
-              "sweep_z at %.3f of the column walk" % (pat["fields_read"], pat["fields_written"],
-                                                     pat["column_march_GBs"], pat["flat_GBs"],
-                                                     roof["frac_of_pattern_ceiling"]), file=sys.stderr, flush=True)
+    if args.precision == "fp64" and "sweep_z" in head["kernels"] and "ring_x" in head["kernels"]:
+        # the ceilings of the two largest kernels' own access patterns: the Z
+        # sweep reads density, v_z and NQ conserved fields and writes density
+        # and the NQ fields (2 NQ + 3 words a zone), one column per thread;
+        # the X transport reads density, v_x and NQ fields and writes NQ (the
+        # Y/Z momenta, e, density and v_x: 2 NQ + 2 words), consecutive zones
+        # per wave
+        kz, kx = head["kernels"]["sweep_z"], head["kernels"]["ring_x"]
+        nqz = (round(kz["alg_bytes"] / (cells * 8)) - 3) // 2
+        nqx = (round(kx["alg_bytes"] / (cells * 8)) - 2) // 2
+        pats = {"sweep_z": dict(pattern_bandwidth(p["nx"], p["ny"], p["nz"], nqz + 2, nqz + 1), walk="column"),
+                "ring_x": dict(pattern_bandwidth(p["nx"], p["ny"], p["nz"], nqx + 2, nqx), walk="flat")}
+        for name, pat in pats.items():
+            ceil_k = pat["column_march_GBs"] if pat["walk"] == "column" else pat["flat_GBs"]
+            pat["kernel_GBs"] = head["kernels"][name]["GBs"]
+            pat["kernel_frac"] = round(pat["kernel_GBs"] / ceil_k, 4)
+            print("access pattern of %s (%d read, %d written): column walk %.0f GB/s, flat %.0f GB/s; "
+                  "%s at %.3f of the %s walk" % (name, pat["fields_read"], pat["fields_written"],
+                                                  pat["column_march_GBs"], pat["flat_GBs"], name, pat["kernel_frac"],
+                                                  pat["walk"]), file=sys.stderr, flush=True)
+        roof["pattern_ceilings"] = pats
+        if roof["kernel"] in pats:
+            roof["frac_of_pattern_ceiling"] = pats[roof["kernel"]]["kernel_frac"]
 
     side = {}
     if not args.no_side:
