@@ -135,13 +135,15 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
   // row come through scalar loads, which do not stall behind the prefetches
   const int tid = threadIdx.x, r = __builtin_amdgcn_readfirstlane(tid >> 6), c = tid & 63;
   // Tiles in groups of G tile rows, Y fastest within a group.  The 16-row
-  // march takes groups of 4: the 32 workgroups an XCD runs at once then cover
-  // a patch 8 tiles wide and 4 tall, so that the X halo zones a tile reads
-  // (each a 128-byte line of its neighbour's row) are mostly a running
+  // FP64 march takes groups of 4: the 32 workgroups an XCD runs at once then
+  // cover a patch 8 tiles wide and 4 tall, so that the X halo zones a tile
+  // reads (each a 128-byte line of its neighbour's row) are mostly a running
   // neighbour's own, still in L2 (2.60 to 2.36 ms on the 2048 x 768 x 96 disk).
-  // The other tile shapes keep Y fastest over the whole mesh (G = nby), which
-  // measured as fast or faster for them.
-  const int G = TY == 16 ? 4 : nby;
+  // The FP32 march (two workgroups per compute unit) takes groups of 4 as well:
+  // 29 % fewer bytes fetched, about as fast.  The 12-row spherical march and
+  // 2D meshes keep Y fastest over the whole mesh (G = nby), which measured
+  // faster for the former.
+  const int G = TY == 16 || (D3 && sizeof(F) == 4) ? 4 : nby;
   const unsigned Lb = xcd_remap(bid_, nbk_), gsz = (unsigned)(G * nbx);
   const unsigned grp = Lb / gsz, idx = Lb % gsz, gy = (unsigned)min(G, nby - (int)grp * G);
   const int ty = (int)(grp * (unsigned)G + idx % gy), tx = (int)(idx / gy);
