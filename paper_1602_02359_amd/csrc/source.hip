@@ -18,8 +18,9 @@
 // of two zones in X and Y are staged in LDS; the v' of every X and Y face of
 // the tile (and of the halo faces its stencil needs) is computed once and
 // kept in LDS (with the reciprocal of its density sum where room is left),
-// then each zone forms q on its neighbours and its v'' and e''.  Along Z each thread keeps a sliding
-// window of its own column in registers (planes k-1 .. k+2), which also
+// then each zone forms q on its neighbours and its v'' and e''.  Along Z each
+// thread keeps a sliding window of its own column in registers (planes
+// k-1 .. k+2), which also
 // supplies the tile's interior values to LDS, so each interior value is read
 // from memory once.  Geometric lengths enter through reciprocal tables.
 //
@@ -79,8 +80,8 @@ struct Lds {
   F IY[KI ? NB : 1][KI ? SY : 1][KI ? TX : 1]; // KI: 1 / ((rho_j + rho_{j-1}) h_y) on the Y faces
   double DX[NB][TY];    // 1 / dX of the tile rows, for the halo X faces
 };
-// (a 2D mesh has a single plane: one buffer of each, so that two workgroups
-// share a compute unit)
+// (a 2D mesh has a single plane: one buffer of each, so that several
+// workgroups share a compute unit)
 constexpr size_t LDS_CU = 160 * 1024;
 // the reciprocals of the faces' density sums are kept in LDS where they fit
 // beside the rest, else formed again by the zones that use them
@@ -547,9 +548,9 @@ __device__ __forceinline__ void source_body(Mesh m, StateT<F> s, const double *_
   }
 }
 template <typename F, bool D3, int GEO, bool ADI>
-__global__ __launch_bounds__((src_threads<F, D3, GEO, ADI>()), (src_waves<F, D3, GEO, ADI>())) void k_source(Mesh m, StateT<F> s, const double *__restrict__ dtp,
-                                                  F *__restrict__ vx2, F *__restrict__ vy2, F *__restrict__ vz2,
-                                                  F *__restrict__ e2, int nbx, int nby) {
+__global__ __launch_bounds__((src_threads<F, D3, GEO, ADI>()), (src_waves<F, D3, GEO, ADI>())) void k_source(
+    Mesh m, StateT<F> s, const double *__restrict__ dtp, F *__restrict__ vx2, F *__restrict__ vy2,
+    F *__restrict__ vz2, F *__restrict__ e2, int nbx, int nby) {
   source_body<F, D3, GEO, ADI>(m, s, dtp, vx2, vy2, vz2, e2, nbx, nby, blockIdx.x, gridDim.x);
 }
 
@@ -599,7 +600,8 @@ struct SourceArgs {
   unsigned nb;
 };
 template <typename F, bool D3, int GEO, bool ADI>
-__global__ __launch_bounds__((src_threads<F, D3, GEO, ADI>()), (src_waves<F, D3, GEO, ADI>())) void k_source_many(const void *args, const uint2 *tab) {
+__global__ __launch_bounds__((src_threads<F, D3, GEO, ADI>()), (src_waves<F, D3, GEO, ADI>())) void k_source_many(
+    const void *args, const uint2 *tab) {
   const uint2 t = many_block(tab);
   if (t.x == MANY_NONE) return;
   const SourceArgs<F> a = many_args<SourceArgs<F>>(args, t.x);
@@ -630,8 +632,9 @@ void launch_source(Launch &L, const Mesh &m, const StateT<F> &s, const double *d
   const unsigned ng = (unsigned)(m.nzg * (m.nyg - m.ny) + (m.d3 ? (m.nzg - m.nz) * m.ny : 0));
   prof_begin(L, K_SRC);
   auto go = [&](auto d3, auto geo, auto adi) {
-    k_source<F, decltype(d3)::value, decltype(geo)::value, decltype(adi)::value>
-        <<<nb, src_threads<F, decltype(d3)::value, decltype(geo)::value, decltype(adi)::value>(), 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2, nbx, nby);
+    constexpr bool D3 = decltype(d3)::value, ADI = decltype(adi)::value;
+    constexpr int GEO = decltype(geo)::value;
+    k_source<F, D3, GEO, ADI><<<nb, src_threads<F, D3, GEO, ADI>(), 0, L.s>>>(m, s, dt, vx2, vy2, vz2, e2, nbx, nby);
   };
   auto by_eos = [&](auto d3, auto geo) {
     if (m.eos == FARGO_ADIABATIC) go(d3, geo, std::true_type{});
