@@ -146,13 +146,28 @@ __global__ __launch_bounds__(256) void k_conv(int nx, int ny, int ntile, const u
   __syncthreads(); // the previous tile's reads of T are done
   put();
   __syncthreads();
-  if (tile + (int)gridDim.x < ntile) fetch(tile + gridDim.x);
   const int strip = tile % strips, rtile = (tile / strips) % rt, s = tile / (strips * rt);
   const int x0 = strip * 64, y0 = rtile * CV_RY;
   const size_t sb = (size_t)s * nx * ny; // first pixel of the sample
   const int xl = wv * 16 + ln; // the lane's pixel (B column) within the 64
   const int nrow = min(CV_RY, ny - y0);
-  for (int r = 0; r < nrow; r += 2) {
+  // CV_ADJ: the ReLU mask of the tile's outputs is loaded before its
+  // products, and before the next tile's rows (the loads are waited for in
+  // issue order), so that the epilogue does not wait for memory; rows past
+  // the sample load its last row (no branch around the loads)
+  uint2 hm[MODE == CV_ADJ ? CV_RY : 1][MT];
+  if constexpr (MODE == CV_ADJ) {
+#pragma unroll
+    for (int rr = 0; rr < CV_RY; rr++) {
+      const size_t p = sb + (size_t)(y0 + min(rr, nrow - 1)) * nx + x0 + xl;
+#pragma unroll
+      for (int mt = 0; mt < MT; mt++) hm[rr][mt] = *reinterpret_cast<const uint2 *>(h + p * COUT + 16 * mt + 4 * q);
+    }
+  }
+  if (tile + (int)gridDim.x < ntile) fetch(tile + gridDim.x);
+#pragma unroll
+  for (int r = 0; r < CV_RY; r += 2) {
+    if (r >= nrow) break;
     f4 acc[2][MT];
 #pragma unroll
     for (int rr = 0; rr < 2; rr++)
@@ -191,7 +206,7 @@ __global__ __launch_bounds__(256) void k_conv(int nx, int ny, int ntile, const u
         } else if (MODE == CV_OUT) {
           if (q == 0) *reinterpret_cast<float2 *>(fout + p * 2) = make_float2(a[0] + bias[0], a[1] + bias[1]);
         } else {
-          const uint2 hv = *reinterpret_cast<const uint2 *>(h + p * COUT + co);
+          const uint2 hv = hm[MODE == CV_ADJ ? r + rr : 0][mt];
           const float v0 = lo_bf16(hv.x) > 0.f ? a[0] : 0.f, v1 = hi_bf16(hv.x) > 0.f ? a[1] : 0.f;
           const float v2 = lo_bf16(hv.y) > 0.f ? a[2] : 0.f, v3 = hi_bf16(hv.y) > 0.f ? a[3] : 0.f;
           *reinterpret_cast<uint2 *>(hout + p * COUT + co) = make_uint2(pack2(v0, v1), pack2(v2, v3));
@@ -656,7 +671,8 @@ inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 // tiles (64 pixels of CV_RY rows of one sample) of a convolution, and its
 // grid: the tiles, or as many workgroups as the compute units hold at once
 // (per unit: two of the 32-to-32-channel forms, three of the 32-to-2, five
-// of the 4-channel ones, by their registers) looping over them
+// of the 4-channel forward and four of the 4-channel adjoint, by their
+// registers) looping over them
 inline int conv_tiles(const Mesh &m, int nsamp) { return nsamp * (m.nx / 64) * ((m.ny + CV_RY - 1) / CV_RY); }
 inline unsigned conv_grid(int ntile, int per_cu) {
   return (unsigned)(ntile < per_cu * 256 ? ntile : per_cu * 256);
@@ -715,7 +731,7 @@ void lfc_backward(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double 
   const int nx = m.nx, ny = m.ny;
   const long ntot = (long)nx * ny * nsamp;
   const int nt = conv_tiles(m, nsamp);
-  const unsigned nb = conv_grid(nt, 2), nb3 = conv_grid(nt, 3), nb5 = conv_grid(nt, 5);
+  const unsigned nb = conv_grid(nt, 2), nb4 = conv_grid(nt, 4);
   int rpc = 1, nrc = 1;
   const int nw = lfc_wblocks(nx, ny, nsamp, &rpc, &nrc);
   prof_begin(L, K_LFC_DRHO);
@@ -727,7 +743,7 @@ void lfc_backward(Launch &L, const Mesh &m, int nsamp, const LfcBufs &B, double 
                                                  B.part + LFC_OFF_B3);
   prof_end(L, K_LFC_W3);
   prof_begin(L, K_LFC_ADJ3);
-  k_conv<4, 32, CV_ADJ><<<nb5, 256, 0, L.s>>>(nx, ny, nt, B.g3, (const uint4 *)B.wt.wpa3, nullptr, B.h2, B.g2, nullptr);
+  k_conv<4, 32, CV_ADJ><<<nb4, 256, 0, L.s>>>(nx, ny, nt, B.g3, (const uint4 *)B.wt.wpa3, nullptr, B.h2, B.g2, nullptr);
   prof_end(L, K_LFC_ADJ3);
   // layer 2
   prof_begin(L, K_LFC_W2);
