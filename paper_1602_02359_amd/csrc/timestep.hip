@@ -59,25 +59,33 @@ __device__ inline double wave_reduce_dpp(double v, Op op, double id) {
 // Two reductions of a block at once (min or max: exact in any order), with
 // two barriers for both: each wave reduces by DPP lane moves, its lane 63
 // puts the result in LDS, and every lane then reads the waves' results and
-// reduces them itself; lds holds 2 * MAXW values.
+// reduces them itself; lds holds 2 * MAXW values.  With `flag`, the OR of
+// every thread's *flag rides along (a wave ballot, then MAXW more values of
+// lds) and is left in *flag of every thread.
 template <typename OpA, typename OpB>
-__device__ inline void block_reduce2(double &a, OpA opa, double ida, double &b, OpB opb, double idb, double *lds) {
+__device__ inline void block_reduce2(double &a, OpA opa, double ida, double &b, OpB opb, double idb, double *lds,
+                                     int *flag = nullptr) {
   a = wave_reduce_dpp(a, opa, ida);
   b = wave_reduce_dpp(b, opb, idb);
+  const bool fw = flag && __builtin_amdgcn_ballot_w64(*flag != 0) != 0;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 63) {
     lds[wid] = a;
     lds[MAXW + wid] = b;
+    if (flag) lds[2 * MAXW + wid] = fw ? 1.0 : 0.0;
   }
   __syncthreads();
   const int nw = (blockDim.x + 63) >> 6;
   a = ida;
   b = idb;
+  int f = 0;
   for (int w = 0; w < nw; w++) {
     a = opa(a, lds[w]);
     b = opb(b, lds[MAXW + w]);
+    if (flag) f |= lds[2 * MAXW + w] != 0.0;
   }
+  if (flag) *flag = f;
 }
 
 struct Max { __device__ double operator()(double a, double b) const { return a > b ? a : b; } };
@@ -179,7 +187,7 @@ __device__ __forceinline__ void cfl_ring_body(Mesh m, StateT<R> s, int with_cfl,
                                                   int *__restrict__ err, unsigned bid_, unsigned nbk_) {
 #pragma clang fp contract(off)
   extern __shared__ double V[]; // the ring's v_x
-  __shared__ double red[2 * MAXW];
+  __shared__ double red[3 * MAXW];
   const unsigned L = xcd_remap(bid_, nbk_);
   constexpr int KT = 16;
   const unsigned tile = L / ((unsigned)m.ny * KT), q = L % ((unsigned)m.ny * KT);
@@ -250,8 +258,8 @@ __device__ __forceinline__ void cfl_ring_body(Mesh m, StateT<R> s, int with_cfl,
       if (sh > smax) smax = sh;
     }
   }
-  block_reduce2(rmax, Max(), 0.0, smax, Max(), 0.0, red);
-  int anybad = __syncthreads_or(bad);
+  int anybad = bad;
+  block_reduce2(rmax, Max(), 0.0, smax, Max(), 0.0, red, &anybad);
   if (tid == 0) {
     ringrate[r] = rmax; // the ring's largest squared rate
     ringshear[r] = smax;
@@ -315,7 +323,7 @@ __global__ __launch_bounds__(256) void k_cfl_seg(Mesh m, StateT<R> s, int with_c
                                                  int *__restrict__ err) {
 #pragma clang fp contract(off)
   constexpr int M = CFL_SEG / 256;
-  __shared__ double red[2 * MAXW];
+  __shared__ double red[3 * MAXW];
   __shared__ double V[CFL_SEG + 1]; // the segment's full v_x and the next zone's
   const int r = (int)(blockIdx.x / (unsigned)m.cseg), g = (int)(blockIdx.x % (unsigned)m.cseg);
   const int j = m.j0 + r % m.ny, k = m.k0 + r / m.ny;
@@ -368,8 +376,8 @@ __global__ __launch_bounds__(256) void k_cfl_seg(Mesh m, StateT<R> s, int with_c
       if (sh > smax) smax = sh;
     }
   }
-  block_reduce2(rmax, Max(), 0.0, smax, Max(), 0.0, red);
-  const int anybad = __syncthreads_or(bad);
+  int anybad = bad;
+  block_reduce2(rmax, Max(), 0.0, smax, Max(), 0.0, red, &anybad);
   if (tid == 0) {
     ringrate[blockIdx.x] = rmax;
     ringshear[blockIdx.x] = smax;
