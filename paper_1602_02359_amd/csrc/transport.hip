@@ -319,12 +319,14 @@ __global__ __launch_bounds__(256) void k_sweep_z(Mesh m, const F *__restrict__ v
 
 // Monotonised central slope of the PPA edge values (Eq. 34): zero at an
 // extremum, else the central difference limited by twice each one-sided one.
+// min(2 a, 2 b, |d| / 2) is formed as 2 min(a, b, |d| / 4) (exact: scaling by
+// powers of two) and takes the sign of d (d = 0 only at an extremum).
 template <typename F>
 __device__ inline F mc_slope(F qm, F q0, F qp) {
-  F dq = F(0.5) * (qp - qm);
+  const F d = qp - qm;
   if ((qp - q0) * (q0 - qm) <= F(0)) return F(0);
-  F mag = fmin(fmin(F(2) * fabs(q0 - qm), F(2) * fabs(qp - q0)), fabs(dq));
-  return dq > F(0) ? mag : -mag;
+  const F mag = F(2) * fmin(fmin(fabs(q0 - qm), fabs(qp - q0)), F(0.25) * fabs(d));
+  return copysign(mag, d);
 }
 
 // ------------------------------------------------------------------------
@@ -430,17 +432,20 @@ struct PpaX {
   F x, x1x;
   bool right; // xi >= 0
 };
+// (At an extremum both edges are q0 and the mean is q0 exactly; that case is
+// taken at the end, so the steepening selects do not test it.)
 template <typename F>
 __device__ inline F ppa_eval(F qm, F q0, F qp, F l, F r, const PpaX<F> &X) {
   const F sixth = F(1) / F(6);
   const F D = r - l, C = q0 - F(0.5) * (l + r);
   const F DC = D * C, DD6 = D * D * sixth;
   const bool flat = (qp - q0) * (q0 - qm) <= F(0);
-  const bool stl = !flat && DC > DD6, str = !flat && !stl && -DD6 > DC;
-  const F ln = flat ? q0 : (stl ? F(3) * q0 - F(2) * r : l);
-  const F rn = flat ? q0 : (str ? F(3) * q0 - F(2) * l : r);
+  const bool stl = DC > DD6, str = !stl && -DD6 > DC;
+  const F ln = stl ? F(3) * q0 - F(2) * r : l;
+  const F rn = str ? F(3) * q0 - F(2) * l : r;
   const F ed = X.right ? rn : ln;
-  return ed + X.x * (q0 - ed) + X.x1x * (F(2) * q0 - rn - ln);
+  const F v = ed + X.x * (q0 - ed) + X.x1x * (F(2) * q0 - rn - ln);
+  return flat ? q0 : v;
 }
 
 // Interface values on the lane's zones; each zone's slope and each face's
