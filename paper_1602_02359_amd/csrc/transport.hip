@@ -35,6 +35,32 @@ namespace fargo {
 
 namespace {
 
+// Reciprocal and quotient for the ring kernel, which is bound by its vector
+// instruction count: the hardware reciprocal estimate refined by
+// Newton-Raphson steps r <- r + r (1 - d r), two in FP64 and one in FP32,
+// which leaves r within about one unit in the last place of 1/d (the correctly
+// rounded division costs about twice the instructions).  The rounding of such
+// a quotient varies from zone to zone like that of a division.  d must be a
+// normal number; a zero or denormal d, which the kernel only meets in
+// discarded selects and halo lanes, gives an infinite or meaningless value and
+// no trap.
+__device__ inline double ring_rcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+__device__ inline double ring_div(double n, double d) { return n * ring_rcp(d); }
+__device__ inline float ring_rcp(float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  return fmaf(r, fmaf(-d, r, 1.0f), r);
+}
+__device__ inline float ring_div(float n, float d) { return n * ring_rcp(d); }
+// The quotient of a column sweep's van Leer slope: correctly rounded in FP64
+// (the sweeps there are bound by memory), the refined reciprocal in FP32,
+// where the Y sweep is bound by its vector instructions (as in the ring
+// kernel and the Z part of k_zx)
+__device__ inline double sweep_div(double n, double d) { return n / d; }
+__device__ inline float sweep_div(float n, float d) { return ring_div(n, d); }
 
 // van Leer slope per unit length from the one-sided differences and the
 // centre distances below (hm) and above (hp): 2 dl dr/(dl + dr) with
@@ -47,7 +73,7 @@ __device__ inline F vl_slope(F qm, F q0, F qp, F hm, F hp) {
 #pragma clang fp contract(off)
   F dm = q0 - qm, dp = qp - q0;
   F pr = dm * dp;
-  return pr > F(0) ? F(2) * pr / (dm * hp + dp * hm) : F(0);
+  return pr > F(0) ? sweep_div(F(2) * pr, dm * hp + dp * hm) : F(0);
 }
 
 // The same slope for a quantity stored as a deviation from a background that
@@ -58,7 +84,7 @@ __device__ inline F vl_slope_b(F qm, F q0, F qp, F hm, F hp, F bm, F bp) {
 #pragma clang fp contract(off)
   F dm = (q0 - qm) + bm, dp = (qp - q0) + bp;
   F pr = dm * dp;
-  return pr > F(0) ? F(2) * pr / (dm * hp + dp * hm) : F(0);
+  return pr > F(0) ? sweep_div(F(2) * pr, dm * hp + dp * hm) : F(0);
 }
 
 // half-step interface value at a face, upwinded on w (Eq. 15)
@@ -399,27 +425,6 @@ __device__ inline void prev_of(const F (&a)[M], F (&out)[M]) { // value of zone 
 #pragma unroll
   for (int m = 0; m < M; m++) out[m] = m > 0 ? a[m - 1] : p1;
 }
-
-// Reciprocal and quotient for the ring kernel, which is bound by its vector
-// instruction count: the hardware reciprocal estimate refined by
-// Newton-Raphson steps r <- r + r (1 - d r), two in FP64 and one in FP32,
-// which leaves r within about one unit in the last place of 1/d (the correctly
-// rounded division costs about twice the instructions).  The rounding of such
-// a quotient varies from zone to zone like that of a division.  d must be a
-// normal number; a zero or denormal d, which the kernel only meets in
-// discarded selects and halo lanes, gives an infinite or meaningless value and
-// no trap.
-__device__ inline double ring_rcp(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  r = fma(r, fma(-d, r, 1.0), r);
-  return fma(r, fma(-d, r, 1.0), r);
-}
-__device__ inline double ring_div(double n, double d) { return n * ring_rcp(d); }
-__device__ inline float ring_rcp(float d) {
-  const float r = __builtin_amdgcn_rcpf(d);
-  return fmaf(r, fmaf(-d, r, 1.0f), r);
-}
-__device__ inline float ring_div(float n, float d) { return n * ring_rcp(d); }
 
 // PPA on one zone (Eqs. 34-36): limit the parabola through the edge values
 // l, r (flat at an extremum, steepened away from an overshoot), then the
